@@ -1,0 +1,147 @@
+"""Pins of the oracle's finite-element pieces against facts fixed by the mathematics.
+
+Conductivity: eq. (AdmV) and its ellipticity lemma (eigenvalues g and |V|).
+Mass / stiffness: Section 3.1 (semi-disc); closed Kronecker forms on uniform
+Q1 boxes, zero row sums (Neumann problem), exact energy of linear functions.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fem
+from oracle.mesh import BoxMesh
+
+
+def _m1(n, h):
+    """1D Q1 mass: h/6 tridiag(1, 4, 1) with 2 on the two end diagonals."""
+    M = np.diag(np.full(n, 4.0)) + np.diag(np.ones(n - 1), 1) + np.diag(np.ones(n - 1), -1)
+    M[0, 0] = M[-1, -1] = 2.0
+    return M * h / 6.0
+
+
+def _k1(n, h):
+    K = np.diag(np.full(n, 2.0)) - np.diag(np.ones(n - 1), 1) - np.diag(np.ones(n - 1), -1)
+    K[0, 0] = K[-1, -1] = 1.0
+    return K / h
+
+
+def _c1(n):
+    """1D C[i, j] = int phi_i phi_j' : 1/2 (e_{i,i+1} - e_{i,i-1}), -1/2 / +1/2 at the ends."""
+    C = 0.5 * (np.diag(np.ones(n - 1), 1) - np.diag(np.ones(n - 1), -1))
+    C[0, 0] = -0.5
+    C[-1, -1] = 0.5
+    return C
+
+
+def _kron(mats):
+    """Kronecker product with axis 0 fastest: mats = [A_x, A_y, (A_z)]."""
+    out = mats[0]
+    for A in mats[1:]:
+        out = np.kron(A, out)
+    return out
+
+
+@pytest.mark.parametrize("d,n", [(2, [5, 4]), (3, [4, 3, 5])])
+def test_stiffness_row_sums_symmetry_psd(d, n):
+    mesh = BoxMesh(n)
+    theta = np.random.default_rng(1).normal(size=mesh.n_elems)
+    G = fem.conductivity_from_angle(theta, d, W.SIGMA_L, W.SIGMA_T)
+    M, K = fem.assemble(mesh, G)
+    K = K.toarray()
+    assert np.abs(K @ np.ones(mesh.n_nodes)).max() < 1e-16
+    assert np.abs(K - K.T).max() < 1e-18
+    ev = np.linalg.eigvalsh(K)
+    assert ev.min() > -1e-16 and np.sum(ev < 1e-14) == 1  # kernel = constants only
+    assert abs(M.sum() - mesh.volume) < 1e-15
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_mass_is_kronecker_of_1d_masses(d):
+    n = [5, 4, 3][:d]
+    mesh = BoxMesh(n, hi=[1.0, 0.5, 2.0][:d])
+    M = fem.assemble_mass(mesh).toarray()
+    ref = _kron([_m1(n[a], mesh.h[a]) for a in range(d)])
+    assert np.abs(M - ref).max() < 1e-16
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3, np.pi / 4, 1.2, -2.0])
+def test_stiffness_closed_form_uniform_angle_3d(theta):
+    n = [4, 5, 3]
+    mesh = BoxMesh(n, hi=[1.0, 1.5, 0.75])
+    h = mesh.h
+    G1 = fem.conductivity_from_angle(np.array([theta]), 3, W.SIGMA_L, W.SIGMA_T)[0]
+    _, K = fem.assemble(mesh, np.broadcast_to(G1, (mesh.n_elems, 3, 3)))
+    M1 = [_m1(n[a], h[a]) for a in range(3)]
+    K1 = [_k1(n[a], h[a]) for a in range(3)]
+    C1 = [_c1(n[a]) for a in range(3)]
+    ref = np.zeros((mesh.n_nodes, mesh.n_nodes))
+    # int d_q phi_j d_p phi_i : factor per axis a is K1 if a == p == q, C1^T if a == p != q,
+    # C1 if a == q != p, M1 otherwise
+    for p in range(3):
+        for q in range(3):
+            mats = []
+            for a in range(3):
+                if a == p and a == q:
+                    mats.append(K1[a])
+                elif a == p:
+                    mats.append(C1[a].T)
+                elif a == q:
+                    mats.append(C1[a])
+                else:
+                    mats.append(M1[a])
+            ref += G1[p, q] * _kron(mats)
+    assert np.abs(K.toarray() - ref).max() < 1e-17
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_energy_of_linear_functions(d):
+    """Q1 contains linear u = g.x, so u^T K u = |D| g^T G g exactly for uniform G."""
+    mesh = BoxMesh([4, 6, 3][:d], lo=[-0.5] * d, hi=[0.5, 1.0, 0.7][:d])
+    rng = np.random.default_rng(3)
+    for theta in (0.0, 0.7, 2.5):
+        G1 = fem.conductivity_from_angle(np.array([theta]), d, W.SIGMA_L, W.SIGMA_T)[0]
+        _, K = fem.assemble(mesh, np.broadcast_to(G1, (mesh.n_elems, d, d)))
+        g = rng.normal(size=d)
+        u = mesh.nodes @ g
+        assert np.isclose(u @ (K @ u), mesh.volume * g @ G1 @ g, rtol=1e-13, atol=0)
+
+
+def test_conductivity_ellipticity_lemma():
+    """eq. (AdmV): eigenvalues g (d-1 times) and |V|, eigenvector of |V| along V."""
+    rng = np.random.default_rng(4)
+    for d in (2, 3):
+        for _ in range(20):
+            V = rng.normal(size=d)
+            g = rng.uniform(0.1, 2.0)
+            G = fem.conductivity(V, g)
+            ev = np.sort(np.linalg.eigvalsh(G))
+            ref = np.sort(np.r_[np.full(d - 1, g), np.linalg.norm(V)])
+            assert np.allclose(ev, ref, rtol=1e-13, atol=0)
+            assert np.allclose(G @ V, np.linalg.norm(V) * V, rtol=1e-13)
+    # the angle form: fibre direction has eigenvalue sigma_l, its normal sigma_t
+    th = 0.83
+    G = fem.conductivity_from_angle(np.array([th]), 2, 2.0, 0.5)[0]
+    f, nrm = np.array([np.cos(th), np.sin(th)]), np.array([-np.sin(th), np.cos(th)])
+    assert np.allclose(G @ f, 2.0 * f, rtol=1e-14) and np.allclose(G @ nrm, 0.5 * nrm, rtol=1e-14)
+
+
+def test_box_load_exact():
+    mesh = BoxMesh([5, 3], hi=[1.0, 1.0])  # h = 0.25, 0.5
+    F = fem.box_load(mesh, [0.0, 0.0], [0.1, 0.3])
+    assert np.isclose(F.sum(), 0.1 * 0.3, rtol=1e-14)
+    # 1D hat integrals over [0, 0.1] with h = 0.25: node 0: 0.1 - 0.01/0.5 = 0.08, node 1: 0.02
+    # over [0, 0.3] with h = 0.5: node 0: 0.3 - 0.09 = 0.21, node 1: 0.09
+    fx = np.array([0.08, 0.02, 0, 0, 0])
+    fy = np.array([0.21, 0.09, 0.0])
+    assert np.allclose(F, np.kron(fy, fx), rtol=1e-14, atol=1e-18)
+    # a box covering the domain gives w = M 1
+    M = fem.assemble_mass(mesh)
+    assert np.allclose(fem.box_load(mesh, [-1, -1], [2, 2]), fem.node_weights(M), rtol=1e-14)
+
+
+def test_source_load_reproduces_mass_action():
+    mesh = BoxMesh([4, 3, 3])
+    M = fem.assemble_mass(mesh)
+    g = np.array([0.3, -1.0, 2.0])
+    F = fem.source_load(mesh, lambda X: X @ g + 0.5)
+    assert np.allclose(F, M @ (mesh.nodes @ g + 0.5), rtol=1e-13, atol=1e-16)

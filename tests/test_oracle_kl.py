@@ -1,0 +1,114 @@
+"""Pins of the oracle's discrete KL expansion (Section 2.3) and midpoint transfer (Section 4).
+
+* the analytic eigenvalues of the 1D exponential kernel (transcendental
+  equations of Ghanem and Spanos) are reached on a fine 1D mesh;
+* the pivoted-Cholesky route eqs. (approxEig)/(redEig) equals the dense
+  generalised eigenproblem eq. (algEig) at full rank;
+* v_i^T M v_j = lambda_i delta_ij (the identity stated after eq. (redEig));
+* sum of all eigenvalues = trace(C M);
+* the Q1 interpolant reproduces trilinear functions; the midpoint transfer of a
+  nested box hierarchy picks fine nodal values at coarse centres.
+"""
+import numpy as np
+import pytest
+import scipy.optimize as so
+
+from oracle import fem, kl
+from oracle.mesh import BoxMesh
+
+
+def _analytic_exp_eigs(std, ell, half, k):
+    c = 1.0 / ell
+    ev = []
+    for i in range(k):
+        w = so.brentq(lambda w: w * np.tan(w * half) - c, (i * np.pi + 1e-12) / half,
+                      (i * np.pi + np.pi / 2 - 1e-12) / half)
+        ev.append(2 * c * std * std / (w * w + c * c))
+        w = so.brentq(lambda w: c * np.tan(w * half) + w, (i * np.pi + np.pi / 2 + 1e-12) / half,
+                      ((i + 1) * np.pi - 1e-12) / half)
+        ev.append(2 * c * std * std / (w * w + c * c))
+    return np.sort(ev)[::-1][:k]
+
+
+def test_1d_exponential_kernel_analytic_eigenvalues():
+    mesh = BoxMesh([401])
+    M = fem.assemble_mass(mesh)
+    lam, _ = kl.kl_dense(mesh.nodes, M, 0.3, 0.2, 6)
+    ref = _analytic_exp_eigs(0.3, 0.2, 0.5, 6)
+    assert np.allclose(lam, ref, rtol=2e-4, atol=0)
+    # the pivoted-Cholesky route at full rank agrees
+    L, _ = kl.pivoted_cholesky(mesh.nodes, 0.3, 0.2, mesh.n_nodes)
+    lam2, _ = kl.kl_from_cholesky(L, M, 6)
+    assert np.allclose(lam2, lam, rtol=1e-10)
+
+
+@pytest.mark.parametrize("d,n", [(2, [7, 6]), (3, [4, 5, 4])])
+def test_cholesky_route_equals_dense_and_m_orthogonality(d, n):
+    mesh = BoxMesh(n)
+    M = fem.assemble_mass(mesh)
+    k = 8
+    lam_d, V_d = kl.kl_dense(mesh.nodes, M, 0.3, 0.3, k)
+    L, piv = kl.pivoted_cholesky(mesh.nodes, 0.3, 0.3, mesh.n_nodes)
+    C = kl.exp_cov(mesh.nodes, mesh.nodes, 0.3, 0.3)
+    assert np.abs(L @ L.T - C).max() < 1e-12  # exact factor at full rank
+    assert len(set(piv.tolist())) == len(piv)
+    lam_c, V_c = kl.kl_from_cholesky(L, M, mesh.n_nodes)
+    assert np.allclose(lam_c[:k], lam_d, rtol=1e-10)
+    # v_i^T M v_j = lambda_i delta_ij
+    G = V_c.T @ (M @ V_c)
+    assert np.abs(G - np.diag(lam_c)).max() < 1e-12 * lam_c[0]
+    # sum of all eigenvalues = trace(C M)
+    assert np.isclose(lam_c.sum(), np.sum(C * M.toarray()), rtol=1e-12)
+    # eigenspaces agree where the eigenvalues are simple (projector comparison)
+    gaps = np.abs(np.diff(lam_d)) > 1e-6 * lam_d[0]
+    for j in range(k - 1):
+        if gaps[j] and (j == 0 or gaps[j - 1]):
+            a, b = V_d[:, j] / np.sqrt(lam_d[j]), V_c[:, j] / np.sqrt(lam_c[j])
+            assert abs(abs(a @ (M @ b)) - 1.0) < 1e-8
+
+
+def test_truncated_cholesky_trace_decreases_and_stops():
+    mesh = BoxMesh([9, 9])
+    C = kl.exp_cov(mesh.nodes, mesh.nodes, 0.3, 0.2)
+    tr = np.trace(C)
+    prev = np.inf
+    for r in (2, 5, 10, 20, 40):
+        L, _ = kl.pivoted_cholesky(mesh.nodes, 0.3, 0.2, r)
+        res = tr - np.sum(L * L)
+        E = C - L @ L.T
+        assert np.linalg.eigvalsh(E).min() > -1e-12  # Schur complement stays PSD
+        assert res < prev
+        prev = res
+    L, _ = kl.pivoted_cholesky(mesh.nodes, 0.3, 0.2, 81, eps=0.05)
+    assert tr - np.sum(L * L) <= 0.05 * tr and L.shape[1] < 81
+
+
+def test_kl_modes_normalisation_and_signs():
+    mesh = BoxMesh([6, 6, 6])
+    M = fem.assemble_mass(mesh)
+    lam, psi = kl.kl_modes(mesh, M, 0.3, 0.1, 10)
+    assert np.all(np.diff(lam) <= 0)
+    assert np.abs(psi.T @ (M @ psi) - np.eye(10)).max() < 1e-12
+    for k in range(10):
+        j = int(np.argmax(np.abs(psi[:, k])))
+        assert psi[j, k] > 0
+
+
+def test_interpolation_and_midpoint_transfer():
+    fine = BoxMesh([9, 9, 9])
+    rng = np.random.default_rng(2)
+    # trilinear functions are reproduced exactly
+    c = rng.normal(size=8)
+    f = lambda X: (c[0] + c[1] * X[:, 0] + c[2] * X[:, 1] + c[3] * X[:, 2] + c[4] * X[:, 0] * X[:, 1]
+                   + c[5] * X[:, 1] * X[:, 2] + c[6] * X[:, 0] * X[:, 2] + c[7] * X[:, 0] * X[:, 1] * X[:, 2])
+    pts = rng.uniform(0, 1, (50, 3))
+    assert np.allclose(kl.interpolate(fine, f(fine.nodes), pts), f(pts), rtol=1e-13, atol=1e-13)
+    # nested coarse levels: centres are fine nodes, the transfer picks nodal values
+    vals = rng.normal(size=(fine.n_nodes, 3))
+    coarse = BoxMesh([5, 5, 5])
+    phi = kl.level_basis(fine, vals, coarse)
+    ids = fine.node_id(np.rint((coarse.centres - fine.lo) / fine.h).astype(int))
+    assert np.array_equal(phi, vals[ids])
+    # on the KL grid itself the centre value is the average of the 8 corners
+    phi_f = kl.level_basis(fine, vals, fine)
+    assert np.allclose(phi_f, vals[fine.elems].mean(axis=1), rtol=1e-14, atol=1e-15)
