@@ -1,0 +1,203 @@
+/*
+ * mlq.h -- C ABI of the MI355X (gfx950) library for the batched per-sample
+ * space-time solves of the parametric monodomain equation and the single- and
+ * multilevel quadrature estimators built on them.
+ *
+ * Method (Ben Bader, Harbrecht, Krause, Multerer, Quaglino, Schmidlin,
+ * "Space-time multilevel quadrature methods and their application for cardiac
+ * electrophysiology"):
+ *   - conductivity per element, eq. (AdmV):  G = s_t I + (s_l - s_t) f f^T,
+ *     f = (cos theta, sin theta[, 0]), theta the fibre angle of the element;
+ *   - fibre angle field, eq. (KLlowrank) with the element-midpoint transfer of
+ *     Section 4:  theta = theta0 + Phi diag(sqrt(lambda)) y;
+ *   - Crank-Nicolson space-time system eq. (st-system) with the reaction term of
+ *     eq. (mono_disc), I_ion of eq. (ionic_term); the block lower-bidiagonal
+ *     system eq. (system_C) is solved by forward substitution in time, each time
+ *     level by Newton's method with the Jacobian of Section 3.2 and a batched
+ *     GMRES (Section 3.3);
+ *   - quantities of interest of Section 2.4 (mean potential at the end time,
+ *     mean activation time);
+ *   - estimators eqs. (SL), (StandardML), (PimpedML) of Section 4.
+ *
+ * Conventions
+ *   Ownership: the library never allocates device memory.  Every device buffer
+ *     (level blob, fields, workspace, outputs) is passed in by the caller and
+ *     stays owned by the caller.  Host arrays given to mlq_create_level are
+ *     copied during the call.  Each level object owns a few bytes of pinned host
+ *     memory for convergence flags.
+ *   Layouts: a batch of B samples on a level with n nodes and P elements stores
+ *     nodal vectors sample-major, [B][n]; element fields [B][P].  Nodes and
+ *     elements of a Q1 box are numbered with axis 0 fastest.
+ *   Streams: every call takes a hipStream_t (passed as void*; NULL = the null
+ *     stream).  mlq_sample_fields, mlq_apply, mlq_lattice_normals and
+ *     mlq_accumulate only enqueue work.  mlq_solve_batch steers Newton and GMRES
+ *     from the host and returns after the work on the stream has finished.
+ *   Errors: every entry point returns an mlq_status; nothing throws across the
+ *     ABI.  mlq_last_error() returns a thread-local message for the last error.
+ *   Determinism: all reductions have a fixed order, so FP64 results are bitwise
+ *     reproducible for a fixed batch.
+ */
+#ifndef MLQ_H
+#define MLQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MLQ_OK = 0,
+  MLQ_EINVAL = -1,  /* invalid argument or descriptor */
+  MLQ_EHIP = -2,    /* a HIP runtime call failed */
+  MLQ_ENOCONV = -3, /* at least one sample did not converge (see status array) */
+  MLQ_ESIZE = -4,   /* a caller-provided buffer is too small */
+  MLQ_ESTATE = -5   /* object used in a wrong state */
+} mlq_status;
+
+typedef enum { MLQ_FP64 = 0, MLQ_MIXED = 1 } mlq_precision;
+typedef enum { MLQ_QOI_MEAN_U_FINAL = 0, MLQ_QOI_MEAN_ACT_TIME = 1 } mlq_qoi;
+typedef enum { MLQ_MESH_Q1_BOX = 0 } mlq_mesh_kind;
+
+/* per-sample status codes written by mlq_solve_batch */
+enum { MLQ_SAMPLE_OK = 0, MLQ_SAMPLE_NOCONV = 1, MLQ_SAMPLE_NAN = 2 };
+
+/* Description of one level (Section 3.1: mesh, time grid; Section 5.1: model
+ * constants).  All pointers are host pointers, read during mlq_create_level. */
+typedef struct {
+  int32_t dim;        /* 2 or 3 */
+  int32_t mesh_kind;  /* MLQ_MESH_Q1_BOX */
+  int64_t n[3];       /* nodes per axis (>= 2 each; unused axes ignored) */
+  double lo[3], hi[3];/* box corners */
+  int32_t n_steps;    /* time steps on [0, t_end]; dt = t_end / n_steps */
+  double t_end;
+  double alpha, u_rest, u_th, u_peak; /* eq. (ionic_term) */
+  double sigma_l, sigma_t;            /* along / across the fibre */
+  double stim_lo[3], stim_hi[3];      /* stimulus box (indicator in space) */
+  double stim_t_on, stim_t_off;       /* stimulus active on [t_on, t_off) */
+  double stim_amp;                    /* stimulus rate */
+  int32_t n_modes;                    /* M: KL modes (<= 1024) */
+  const double* phi;                  /* P x M row-major: modes at element centres */
+  const double* sqrt_lambda;          /* M */
+  const double* theta0;               /* P, or NULL for theta0 = 0 */
+  int32_t prec;                       /* mlq_precision */
+  int32_t qoi;                        /* mlq_qoi */
+  double newton_tol;                  /* normwise backward error of each step */
+  double inner_tol;                   /* relative residual of each GMRES solve */
+  int32_t max_newton;                 /* Newton iterations per step */
+  int32_t max_inner;                  /* GMRES iterations per Newton step (<= 64) */
+  int32_t max_batch;                  /* largest batch used with this level (<= 65535) */
+} mlq_level_desc;
+
+typedef struct mlq_level mlq_level; /* opaque */
+
+/* Device bytes the level blob needs (Phi in FP64 and FP32, theta0, load vector,
+ * node weights).  Returns MLQ_EINVAL for an invalid descriptor. */
+mlq_status mlq_level_bytes(const mlq_level_desc* desc, size_t* level_bytes);
+
+/* Validates desc, copies its arrays into level_mem_dev (>= mlq_level_bytes,
+ * 256-byte aligned), waits for the copies on stream, returns the level in *out.
+ * Rejects (MLQ_EINVAL) a descriptor with dt * |min I_ion'| >= 1, where the step
+ * equation may have several roots. */
+mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, size_t level_bytes,
+                            void* hip_stream, mlq_level** out);
+
+void mlq_destroy_level(mlq_level* level);
+
+/* Level geometry: nodes n and elements P per sample. */
+mlq_status mlq_level_sizes(const mlq_level* level, int64_t* n_nodes, int64_t* n_elems);
+
+/* Workspace bytes for one mlq_solve_batch call with `batch` samples. */
+mlq_status mlq_workspace_bytes(const mlq_level* level, int32_t batch, size_t* ws_bytes);
+
+/* KL synthesis, eq. (KLlowrank) at the level's element centres:
+ *   theta[b][p] = theta0[p] + sum_k phi[p][k] sqrt_lambda[k] Y[k + M b].
+ * Y_dev: M x batch column-major FP64 (column b = sample b).
+ * theta_dev: batch x P, FP32 when the level is MLQ_MIXED, else FP64.
+ * Enqueues only. */
+mlq_status mlq_sample_fields(mlq_level* level, const double* Y_dev, int32_t batch, void* theta_dev,
+                             void* hip_stream);
+
+/* Solves the space-time problem of every sample of the batch (fibre angles
+ * theta_dev as produced by mlq_sample_fields) and writes the quantity of
+ * interest qoi_dev[b] (FP64), a status word status_dev[b] (MLQ_SAMPLE_*) and
+ * iters_dev[2 b] = Newton iterations, iters_dev[2 b + 1] = GMRES iterations
+ * (operator applications) summed over all steps.  ws_dev: >= mlq_workspace_bytes,
+ * 256-byte aligned.  Returns after the stream has finished; MLQ_ENOCONV if any
+ * sample failed (its QoI is still written). */
+mlq_status mlq_solve_batch(mlq_level* level, const void* theta_dev, int32_t batch, void* ws_dev,
+                           size_t ws_bytes, double* qoi_dev, int32_t* status_dev, int64_t* iters_dev,
+                           void* hip_stream);
+
+/* Same as mlq_solve_batch but stops after `n_steps` steps (<= the level's) and
+ * also copies the final nodal state (batch x n, FP64) to u_out_dev (may be
+ * NULL) and the per-node activation times (batch x n, FP64, -1 = not
+ * activated) to act_out_dev (may be NULL). QoIs refer to t = n_steps * dt. */
+mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t batch, int32_t n_steps,
+                              void* ws_dev, size_t ws_bytes, double* qoi_dev, int32_t* status_dev,
+                              int64_t* iters_dev, double* u_out_dev, double* act_out_dev,
+                              void* hip_stream);
+
+/* Jacobian of one step (Section 3.2) applied matrix-free to a batch:
+ *   y = M ((1 + d) x) + dt/2 K_G x,
+ * with G per element from theta (level precision).  x, d, y: batch x n in the
+ * level's inner precision (FP32 when MLQ_MIXED, else FP64).  Enqueues only. */
+mlq_status mlq_apply(mlq_level* level, const void* theta_dev, int32_t batch, const void* x_dev,
+                     const void* d_dev, void* y_dev, void* ws_dev, size_t ws_bytes, void* hip_stream);
+
+/* Check after a synchronisation: MLQ_ENOCONV if any status is not MLQ_SAMPLE_OK. */
+mlq_status mlq_check(const int32_t* status_host, int32_t batch);
+
+/* Randomly shifted rank-1 lattice points mapped to N(0,1) coordinates:
+ *   Y[k + s (i - first)] = Phi^-1( frac( ((i z_k) mod N) / N + shift_k ) ),
+ * i = first .. first + count - 1, k < s, x clamped to [2^-53, 1 - 2^-53].
+ * z_dev (s integers, 0 < z_k < N) and shift_dev (s values in [0, 1)) are device
+ * arrays; Y_dev is s x count column-major FP64.  Enqueues only. */
+mlq_status mlq_lattice_normals(const int64_t* z_dev, const double* shift_dev, int32_t s, int64_t N,
+                               int64_t first, int32_t count, double* Y_dev, void* hip_stream);
+
+/* Component-by-component generating vector of an N-point rank-1 lattice in s
+ * dimensions, product weights gamma (s), minimising the shift-averaged
+ * worst-case error of the unanchored Sobolev space.  Host only. */
+mlq_status mlq_cbc(int64_t N, int32_t s, const double* gamma, int64_t* z_out);
+
+/* Level difference and accumulation in FP64 on the device:
+ *   Y_i = f_fine[i] - f_coarse[i] (f_coarse may be NULL: Y_i = f_fine[i]),
+ *   acc[0] += count, acc[1] += sum Y_i, acc[2] += sum Y_i^2   (fixed order). */
+mlq_status mlq_accumulate(const double* f_fine_dev, const double* f_coarse_dev, int32_t count,
+                          double* acc_dev, void* hip_stream);
+
+typedef enum {
+  MLQ_EST_MC = 0,          /* eq. (SL), Monte Carlo */
+  MLQ_EST_MLMC = 1,        /* eq. (StandardML), independent MC sets per level */
+  MLQ_EST_MLQMC = 2,       /* eq. (StandardML), randomly shifted lattice rules */
+  MLQ_EST_COMBINATION = 3  /* eq. (PimpedML), nested point sets */
+} mlq_estimator;
+
+typedef struct {
+  double estimate;
+  double rmse;              /* estimated root mean square error */
+  int32_t n_levels;
+  double level_mean[16];
+  double level_var[16];     /* sample variance of the level differences (MC kinds) */
+} mlq_estimate_out;
+
+/* Host FP64 estimators, plain sums in sample order.
+ *  MLQ_EST_MC:    n_levels = 1, f_fine[0] has n_per_level[0] values.
+ *  MLQ_EST_MLMC:  f_fine[l], f_coarse[l] (ignored for l = 0) have n_per_level[l] values.
+ *  MLQ_EST_MLQMC: f_fine[l], f_coarse[l] have n_shifts * n_per_level[l] values, shift-major.
+ *  MLQ_EST_COMBINATION: n_per_level[l] = points of Q_l (nested, increasing);
+ *     f_fine[j] = F_j at the first n_per_level[L - j] points. */
+mlq_status mlq_estimate(int32_t kind, int32_t n_levels, int32_t n_shifts, const int64_t* n_per_level,
+                        const double* const* f_fine, const double* const* f_coarse,
+                        mlq_estimate_out* out);
+
+/* Thread-local message describing the last error. */
+const char* mlq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLQ_H */

@@ -10,7 +10,8 @@ shift-averaged worst-case error in the weighted unanchored Sobolev space of
 first order with product weights gamma_j,
     e^2(z) = -1 + (1/N) sum_{k<N} prod_j (1 + gamma_j B2(frac(k z_j / N))),
     B2(x) = x^2 - x + 1/6.
-Candidates are the integers in [1, N) coprime to N; ties go to the smallest.
+Candidates are the integers in [1, N) coprime to N; ties (criteria within a
+relative 1e-12 of the minimum, i.e. equal up to rounding) go to the smallest.
 The sum over k runs in increasing k with one accumulator so that the decision
 is reproducible bit for bit by any implementation doing the same operations.
 """
@@ -41,7 +42,8 @@ def cbc(N, s, gamma):
             r = (kk * cands) % N
             acc = acc + P[kk] * (1.0 + gamma[j] * b2(r / N))
         err = -1.0 + acc / N
-        best = int(np.argmin(err))
+        # exact ties (equal up to rounding) go to the smallest candidate
+        best = int(np.argmax(err <= err.min() + 1e-12 * abs(err.min())))
         z[j] = cands[best]
         P = P * (1.0 + gamma[j] * b2(((k * z[j]) % N) / N))
     return z

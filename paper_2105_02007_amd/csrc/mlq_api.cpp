@@ -1,0 +1,608 @@
+// C ABI of the library: argument validation, level set-up, workspace layout and
+// the host-steered time / Newton / GMRES loops of one batched solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mlq_internal.h"
+
+using namespace mlq;
+
+namespace {
+
+thread_local std::string g_err;
+
+mlq_status fail(mlq_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_OK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(MLQ_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Exact integral of the 1D hat of node i (nodes x_j = lo + j h, j < n) over [a, b].
+double hat_integral(int64_t i, int64_t n, double lo, double h, double a, double b) {
+  const double xi = lo + h * (double)i;
+  double s = 0.0;
+  if (i > 0) {  // rising part on [x_{i-1}, x_i]: (x - x_{i-1}) / h
+    const double x0 = xi - h;
+    const double l = std::max(a, x0), r = std::min(b, xi);
+    if (r > l) s += ((r - x0) * (r - x0) - (l - x0) * (l - x0)) / (2.0 * h);
+  }
+  if (i < n - 1) {  // falling part on [x_i, x_{i+1}]: (x_{i+1} - x) / h
+    const double x1 = xi + h;
+    const double l = std::max(a, xi), r = std::min(b, x1);
+    if (r > l) s += ((x1 - l) * (x1 - l) - (x1 - r) * (x1 - r)) / (2.0 * h);
+  }
+  return s;
+}
+
+}  // namespace
+
+struct mlq_level {
+  mlq_level_desc d;
+  Geo geo;
+  Ionic io;
+  int64_t nn = 0, P = 0;
+  int32_t M = 0;
+  double h[3] = {1, 1, 1};
+  double vol = 0.0;
+  bool mixed = false;
+  int kmax = 30;
+  // device pointers inside the caller's level blob
+  double* phi64 = nullptr;
+  float* phi32 = nullptr;
+  double* sqrt_lambda = nullptr;
+  double* theta0 = nullptr;
+  double* fbox = nullptr;
+  double* wts = nullptr;
+  // pinned host flags
+  int32_t* host_flags = nullptr;
+};
+
+namespace {
+
+struct BlobLayout {
+  size_t phi64, phi32, sl, th0, fbox, wts, total;
+};
+
+BlobLayout blob_layout(int64_t P, int64_t M, int64_t nn) {
+  BlobLayout L{};
+  size_t o = 0;
+  L.phi64 = o; o = align256(o + sizeof(double) * P * M);
+  L.phi32 = o; o = align256(o + sizeof(float) * P * M);
+  L.sl = o;    o = align256(o + sizeof(double) * M);
+  L.th0 = o;   o = align256(o + sizeof(double) * P);
+  L.fbox = o;  o = align256(o + sizeof(double) * nn);
+  L.wts = o;   o = align256(o + sizeof(double) * nn);
+  L.total = o;
+  return L;
+}
+
+mlq_status validate(const mlq_level_desc* d) {
+  if (d == nullptr) return fail(MLQ_EINVAL, "descriptor is NULL");
+  if (d->dim != 2 && d->dim != 3) return fail(MLQ_EINVAL, "dim must be 2 or 3 (got %d)", d->dim);
+  if (d->mesh_kind != MLQ_MESH_Q1_BOX) return fail(MLQ_EINVAL, "unsupported mesh_kind %d", d->mesh_kind);
+  for (int a = 0; a < d->dim; ++a) {
+    if (d->n[a] < 2 || d->n[a] > (1 << 20)) return fail(MLQ_EINVAL, "n[%d] = %lld out of range", a, (long long)d->n[a]);
+    if (!(d->hi[a] > d->lo[a])) return fail(MLQ_EINVAL, "box axis %d is empty", a);
+  }
+  if (d->n_steps < 1) return fail(MLQ_EINVAL, "n_steps must be >= 1");
+  if (!(d->t_end > 0.0)) return fail(MLQ_EINVAL, "t_end must be positive");
+  if (!(d->sigma_l > 0.0) || !(d->sigma_t > 0.0)) return fail(MLQ_EINVAL, "conductivities must be positive");
+  if (!(d->alpha >= 0.0)) return fail(MLQ_EINVAL, "alpha must be >= 0");
+  if (d->n_modes < 0 || d->n_modes > 1024) return fail(MLQ_EINVAL, "n_modes must be in [0, 1024]");
+  if (d->n_modes > 0 && (d->phi == nullptr || d->sqrt_lambda == nullptr))
+    return fail(MLQ_EINVAL, "phi and sqrt_lambda are required when n_modes > 0");
+  if (d->prec != MLQ_FP64 && d->prec != MLQ_MIXED) return fail(MLQ_EINVAL, "unknown precision %d", d->prec);
+  if (d->qoi != MLQ_QOI_MEAN_U_FINAL && d->qoi != MLQ_QOI_MEAN_ACT_TIME) return fail(MLQ_EINVAL, "unknown qoi %d", d->qoi);
+  if (!(d->newton_tol > 0.0) || !(d->inner_tol > 0.0)) return fail(MLQ_EINVAL, "tolerances must be positive");
+  if (d->max_newton < 1 || d->max_newton > 1000) return fail(MLQ_EINVAL, "max_newton out of range");
+  if (d->max_inner < 1 || d->max_inner > kMaxInner) return fail(MLQ_EINVAL, "max_inner must be in [1, %d]", kMaxInner);
+  if (d->max_batch < 1 || d->max_batch > 65535) return fail(MLQ_EINVAL, "max_batch must be in [1, 65535]");
+  // uniqueness of the step equation: dt * |min I_ion'| < 1 (min over u of the cubic's derivative)
+  const double dt = d->t_end / d->n_steps;
+  const double r = d->u_rest, t = d->u_th, p = d->u_peak;
+  const double umin = (r + t + p) / 3.0;
+  const double dmin = d->alpha * ((umin - t) * (umin - p) + (umin - r) * (umin - p) + (umin - r) * (umin - t));
+  if (dt * std::fabs(std::min(dmin, 0.0)) >= 1.0)
+    return fail(MLQ_EINVAL, "dt * |min I_ion'| = %g >= 1: the step equation may have several roots", dt * std::fabs(dmin));
+  return MLQ_OK;
+}
+
+void sizes_of(const mlq_level_desc* d, int64_t* nn, int64_t* P) {
+  int64_t a = 1, b = 1;
+  for (int k = 0; k < d->dim; ++k) {
+    a *= d->n[k];
+    b *= d->n[k] - 1;
+  }
+  *nn = a;
+  *P = b;
+}
+
+}  // namespace
+
+namespace mlq {
+
+Work carve_workspace(void* base, int64_t nn, int64_t P, int32_t B, int kmax, bool mixed) {
+  Work w{};
+  w.kmax = kmax;
+  w.nblk = (int32_t)cdiv(nn, kBlock);
+  w.nred = (int32_t)cdiv(nn, kRedChunk);
+  const size_t ti = mixed ? sizeof(float) : sizeof(double);
+  const size_t vn = (size_t)nn * B;
+  char* p = (char*)base;
+  size_t o = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* r = p ? (void*)(p + o) : nullptr;
+    o = align256(o + bytes);
+    return r;
+  };
+  w.uk = (double*)take(vn * sizeof(double));
+  w.u = (double*)take(vn * sizeof(double));
+  w.b = (double*)take(vn * sizeof(double));
+  w.act = (double*)take(vn * sizeof(double));
+  w.d = take(vn * ti);
+  w.z = take(vn * ti);
+  w.w = take(vn * ti);
+  w.V = take(vn * ti * (kmax + 1));
+  w.coef = take((size_t)P * B * 2 * ti);
+  const size_t npart = std::max((size_t)w.nblk * 3, (size_t)w.nred * (kmax + 1));
+  w.part = (double*)take(npart * B * sizeof(double));
+  w.H = (double*)take((size_t)B * (kmax + 1) * kmax * sizeof(double));
+  w.cs = (double*)take((size_t)B * kmax * sizeof(double));
+  w.sn = (double*)take((size_t)B * kmax * sizeof(double));
+  w.g = (double*)take((size_t)B * (kmax + 1) * sizeof(double));
+  w.y = (double*)take((size_t)B * kmax * sizeof(double));
+  w.hc = (double*)take((size_t)B * (kmax + 1) * sizeof(double));
+  w.inv_eta = (double*)take((size_t)B * (kmax + 1) * sizeof(double));
+  w.beta = (double*)take((size_t)B * sizeof(double));
+  w.newton_active = (int32_t*)take((size_t)B * sizeof(int32_t));
+  w.inner_active = (int32_t*)take((size_t)B * sizeof(int32_t));
+  w.inner_k = (int32_t*)take((size_t)B * sizeof(int32_t));
+  w.status = (int32_t*)take((size_t)B * sizeof(int32_t));
+  w.iters = (int64_t*)take((size_t)B * 2 * sizeof(int64_t));
+  w.counter = (int32_t*)take(16);
+  w.bytes = o;
+  return w;
+}
+
+}  // namespace mlq
+
+extern "C" {
+
+const char* mlq_last_error(void) { return g_err.c_str(); }
+
+mlq_status mlq_level_bytes(const mlq_level_desc* desc, size_t* level_bytes) {
+  if (level_bytes == nullptr) return fail(MLQ_EINVAL, "level_bytes is NULL");
+  mlq_status st = validate(desc);
+  if (st != MLQ_OK) return st;
+  int64_t nn, P;
+  sizes_of(desc, &nn, &P);
+  *level_bytes = blob_layout(P, desc->n_modes, nn).total;
+  return MLQ_OK;
+}
+
+mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, size_t level_bytes, void* hip_stream,
+                            mlq_level** out) {
+  if (out == nullptr) return fail(MLQ_EINVAL, "out is NULL");
+  *out = nullptr;
+  mlq_status st = validate(desc);
+  if (st != MLQ_OK) return st;
+  if (level_mem_dev == nullptr) return fail(MLQ_EINVAL, "level_mem_dev is NULL");
+  if (((uintptr_t)level_mem_dev & 255) != 0) return fail(MLQ_EINVAL, "level_mem_dev must be 256-byte aligned");
+  int64_t nn, P;
+  sizes_of(desc, &nn, &P);
+  const int64_t M = desc->n_modes;
+  const BlobLayout L = blob_layout(P, M, nn);
+  if (level_bytes < L.total) return fail(MLQ_ESIZE, "level blob too small: %zu < %zu", level_bytes, L.total);
+  hipStream_t s = (hipStream_t)hip_stream;
+
+  mlq_level* lv = new (std::nothrow) mlq_level();
+  if (lv == nullptr) return fail(MLQ_EINVAL, "out of host memory");
+  lv->d = *desc;
+  lv->d.phi = lv->d.sqrt_lambda = lv->d.theta0 = nullptr;
+  lv->nn = nn;
+  lv->P = P;
+  lv->M = (int32_t)M;
+  lv->mixed = desc->prec == MLQ_MIXED;
+  lv->kmax = desc->max_inner;
+  const int dim = desc->dim;
+  for (int a = 0; a < 3; ++a) lv->h[a] = a < dim ? (desc->hi[a] - desc->lo[a]) / (double)(desc->n[a] - 1) : 1.0;
+  const double hx = lv->h[0], hy = lv->h[1], hz = lv->h[2];
+
+  Geo& g = lv->geo;
+  g.dim = dim;
+  g.nx = (int32_t)desc->n[0];
+  g.ny = (int32_t)desc->n[1];
+  g.nz = dim == 3 ? (int32_t)desc->n[2] : 1;
+  g.nn = nn;
+  g.P = P;
+  if (dim == 3) {
+    g.Hm = hx * hy * hz;
+    g.Hxx = hy * hz / hx;
+    g.Hyy = hx * hz / hy;
+    g.Hzz = hx * hy / hz;
+    g.Hxy = hz;
+  } else {
+    g.Hm = hx * hy;
+    g.Hxx = hy / hx;
+    g.Hyy = hx / hy;
+    g.Hzz = 0.0;
+    g.Hxy = 1.0;
+  }
+  g.sbar = 0.5 * (desc->sigma_l + desc->sigma_t);
+  g.st = desc->sigma_t;
+  lv->io = Ionic{desc->alpha, desc->u_rest, desc->u_th, desc->u_peak, desc->t_end / desc->n_steps};
+
+  // host-side level data: stimulus load vector (exact integral of the box
+  // indicator against each tensor-product hat) and node weights w = M 1
+  std::vector<double> f1[3], w1[3];
+  double vol = 1.0;
+  for (int a = 0; a < 3; ++a) {
+    const int64_t n = a < dim ? desc->n[a] : 1;
+    f1[a].assign(n, 1.0);
+    w1[a].assign(n, 1.0);
+    if (a >= dim) continue;
+    for (int64_t i = 0; i < n; ++i) {
+      f1[a][i] = hat_integral(i, n, desc->lo[a], lv->h[a], desc->stim_lo[a], desc->stim_hi[a]);
+      w1[a][i] = (i == 0 || i == n - 1) ? 0.5 * lv->h[a] : lv->h[a];
+    }
+    vol *= desc->hi[a] - desc->lo[a];
+  }
+  lv->vol = vol;
+  std::vector<double> fbox(nn), wts(nn);
+  for (int64_t k = 0; k < (dim == 3 ? desc->n[2] : 1); ++k)
+    for (int64_t j = 0; j < desc->n[1]; ++j)
+      for (int64_t i = 0; i < desc->n[0]; ++i) {
+        const int64_t id = i + desc->n[0] * (j + desc->n[1] * k);
+        fbox[id] = f1[0][i] * f1[1][j] * f1[2][k];
+        wts[id] = w1[0][i] * w1[1][j] * w1[2][k];
+      }
+
+  char* base = (char*)level_mem_dev;
+  lv->phi64 = (double*)(base + L.phi64);
+  lv->phi32 = (float*)(base + L.phi32);
+  lv->sqrt_lambda = (double*)(base + L.sl);
+  lv->theta0 = (double*)(base + L.th0);
+  lv->fbox = (double*)(base + L.fbox);
+  lv->wts = (double*)(base + L.wts);
+
+  std::vector<float> phi32((size_t)P * M);
+  for (size_t i = 0; i < phi32.size(); ++i) phi32[i] = (float)desc->phi[i];
+  std::vector<double> th0(P, 0.0);
+  if (desc->theta0 != nullptr) std::memcpy(th0.data(), desc->theta0, sizeof(double) * P);
+
+  auto cleanup = [&](mlq_status e) {
+    if (lv->host_flags) (void)hipHostFree(lv->host_flags);
+    delete lv;
+    return e;
+  };
+  hipError_t e = hipSuccess;
+  if (M > 0) {
+    e = hipMemcpyAsync(lv->phi64, desc->phi, sizeof(double) * P * M, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(lv->phi32, phi32.data(), sizeof(float) * P * M, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(lv->sqrt_lambda, desc->sqrt_lambda, sizeof(double) * M, hipMemcpyHostToDevice, s);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(lv->theta0, th0.data(), sizeof(double) * P, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(lv->fbox, fbox.data(), sizeof(double) * nn, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(lv->wts, wts.data(), sizeof(double) * nn, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&lv->host_flags, 64, hipHostMallocDefault);
+  if (e != hipSuccess) return cleanup(fail(MLQ_EHIP, "level upload failed: %s", hipGetErrorString(e)));
+  *out = lv;
+  return MLQ_OK;
+}
+
+void mlq_destroy_level(mlq_level* level) {
+  if (level == nullptr) return;
+  if (level->host_flags) (void)hipHostFree(level->host_flags);
+  delete level;
+}
+
+mlq_status mlq_level_sizes(const mlq_level* level, int64_t* n_nodes, int64_t* n_elems) {
+  if (level == nullptr || n_nodes == nullptr || n_elems == nullptr) return fail(MLQ_EINVAL, "NULL argument");
+  *n_nodes = level->nn;
+  *n_elems = level->P;
+  return MLQ_OK;
+}
+
+mlq_status mlq_workspace_bytes(const mlq_level* level, int32_t batch, size_t* ws_bytes) {
+  if (level == nullptr || ws_bytes == nullptr) return fail(MLQ_EINVAL, "NULL argument");
+  if (batch < 1 || batch > level->d.max_batch) return fail(MLQ_EINVAL, "batch %d outside [1, max_batch]", batch);
+  *ws_bytes = carve_workspace(nullptr, level->nn, level->P, batch, level->kmax, level->mixed).bytes;
+  return MLQ_OK;
+}
+
+mlq_status mlq_sample_fields(mlq_level* level, const double* Y_dev, int32_t batch, void* theta_dev, void* hip_stream) {
+  if (level == nullptr || Y_dev == nullptr || theta_dev == nullptr) return fail(MLQ_EINVAL, "NULL argument");
+  if (batch < 1 || batch > level->d.max_batch) return fail(MLQ_EINVAL, "batch %d outside [1, max_batch]", batch);
+  if (level->M < 1) return fail(MLQ_ESTATE, "level has no KL modes");
+  launch_kl(level->phi64, level->sqrt_lambda, level->theta0, Y_dev, level->P, level->M, batch, theta_dev,
+            level->mixed, (hipStream_t)hip_stream);
+  HIP_OK(hipGetLastError());
+  return MLQ_OK;
+}
+
+mlq_status mlq_apply(mlq_level* level, const void* theta_dev, int32_t batch, const void* x_dev, const void* d_dev,
+                     void* y_dev, void* ws_dev, size_t ws_bytes, void* hip_stream) {
+  if (level == nullptr || theta_dev == nullptr || x_dev == nullptr || d_dev == nullptr || y_dev == nullptr ||
+      ws_dev == nullptr)
+    return fail(MLQ_EINVAL, "NULL argument");
+  if (batch < 1 || batch > level->d.max_batch) return fail(MLQ_EINVAL, "batch %d outside [1, max_batch]", batch);
+  Work w = carve_workspace(ws_dev, level->nn, level->P, batch, level->kmax, level->mixed);
+  if (ws_bytes < w.bytes) return fail(MLQ_ESIZE, "workspace too small: %zu < %zu", ws_bytes, w.bytes);
+  hipStream_t s = (hipStream_t)hip_stream;
+  launch_coefs(theta_dev, w.coef, level->P, batch, 0.5 * (level->d.sigma_l - level->d.sigma_t), level->mixed, s);
+  launch_apply_public(level->geo, w.coef, x_dev, d_dev, y_dev, 0.5 * level->io.dt, batch, level->mixed, s);
+  HIP_OK(hipGetLastError());
+  return MLQ_OK;
+}
+
+static mlq_status read_counter(mlq_level* lv, const Work& w, hipStream_t s, int32_t* value) {
+  HIP_OK(hipMemcpyAsync(lv->host_flags, w.counter, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  *value = lv->host_flags[0];
+  return MLQ_OK;
+}
+
+mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t batch, int32_t n_steps, void* ws_dev,
+                              size_t ws_bytes, double* qoi_dev, int32_t* status_dev, int64_t* iters_dev,
+                              double* u_out_dev, double* act_out_dev, void* hip_stream) {
+  if (level == nullptr || theta_dev == nullptr || ws_dev == nullptr || qoi_dev == nullptr || status_dev == nullptr ||
+      iters_dev == nullptr)
+    return fail(MLQ_EINVAL, "NULL argument");
+  if (batch < 1 || batch > level->d.max_batch) return fail(MLQ_EINVAL, "batch %d outside [1, max_batch]", batch);
+  if (n_steps < 0 || n_steps > level->d.n_steps) return fail(MLQ_EINVAL, "n_steps %d outside [0, %d]", n_steps, level->d.n_steps);
+  if (((uintptr_t)ws_dev & 255) != 0) return fail(MLQ_EINVAL, "workspace must be 256-byte aligned");
+  Work w = carve_workspace(ws_dev, level->nn, level->P, batch, level->kmax, level->mixed);
+  if (ws_bytes < w.bytes) return fail(MLQ_ESIZE, "workspace too small: %zu < %zu", ws_bytes, w.bytes);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const mlq_level_desc& d = level->d;
+  const Geo& g = level->geo;
+  const bool mixed = level->mixed;
+  const double dt = level->io.dt;
+  const int kmax = level->kmax;
+
+  launch_coefs(theta_dev, w.coef, level->P, batch, 0.5 * (d.sigma_l - d.sigma_t), mixed, s);
+  launch_init(w, level->nn, batch, d.u_th, s);
+  HIP_OK(hipGetLastError());
+
+  auto rate = [&](double t) { return (d.stim_t_on <= t && t < d.stim_t_off) ? d.stim_amp : 0.0; };
+  for (int32_t k = 0; k < n_steps; ++k) {
+    const double t0 = (double)k * dt, t1 = (double)(k + 1) * dt;
+    const double load = 0.5 * dt * (rate(t1) + rate(t0));
+    launch_rhs(g, w, level->fbox, load, dt, batch, mixed, s);
+    launch_newton_reset(w, batch, s);
+    for (int it = 0;; ++it) {
+      launch_residual(g, level->io, w, batch, mixed, s);
+      launch_newton_check(g, w, batch, d.newton_tol, s);
+      launch_count(w.newton_active, batch, w.counter, s);
+      int32_t active = 0;
+      mlq_status st = read_counter(level, w, s, &active);
+      if (st != MLQ_OK) return st;
+      if (active == 0) break;
+      if (it >= d.max_newton) {
+        launch_mark_failed(w, batch, s);
+        break;
+      }
+      for (int j = 0; j < kmax; ++j) {
+        launch_precond(g, w, j, batch, mixed, s);
+        launch_apply_z(g, w, 0.5 * dt, batch, mixed, s);
+        launch_dots(g, w, j, batch, mixed, s);
+        launch_orth(g, w, j, batch, mixed, s);
+        launch_givens(g, w, j, batch, d.inner_tol, s);
+        launch_count(w.inner_active, batch, w.counter, s);
+        int32_t inner = 0;
+        st = read_counter(level, w, s, &inner);
+        if (st != MLQ_OK) return st;
+        if (inner == 0) break;
+      }
+      launch_solve_y(w, batch, s);
+      launch_update(g, w, batch, mixed, s);
+    }
+    launch_activation(w, level->nn, batch, d.u_th, t0, dt, s);
+    std::swap(w.uk, w.u);
+  }
+  launch_qoi(w, level->wts, level->nn, batch, d.qoi, (double)n_steps * dt, level->vol, qoi_dev, s);
+  HIP_OK(hipMemcpyAsync(status_dev, w.status, sizeof(int32_t) * batch, hipMemcpyDeviceToDevice, s));
+  HIP_OK(hipMemcpyAsync(iters_dev, w.iters, sizeof(int64_t) * 2 * batch, hipMemcpyDeviceToDevice, s));
+  if (u_out_dev)
+    HIP_OK(hipMemcpyAsync(u_out_dev, w.uk, sizeof(double) * level->nn * batch, hipMemcpyDeviceToDevice, s));
+  if (act_out_dev)
+    HIP_OK(hipMemcpyAsync(act_out_dev, w.act, sizeof(double) * level->nn * batch, hipMemcpyDeviceToDevice, s));
+  HIP_OK(hipGetLastError());
+  std::vector<int32_t> stat(batch);
+  HIP_OK(hipMemcpyAsync(stat.data(), w.status, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return mlq_check(stat.data(), batch);
+}
+
+mlq_status mlq_solve_batch(mlq_level* level, const void* theta_dev, int32_t batch, void* ws_dev, size_t ws_bytes,
+                           double* qoi_dev, int32_t* status_dev, int64_t* iters_dev, void* hip_stream) {
+  if (level == nullptr) return fail(MLQ_EINVAL, "level is NULL");
+  return mlq_solve_batch_ex(level, theta_dev, batch, level->d.n_steps, ws_dev, ws_bytes, qoi_dev, status_dev,
+                            iters_dev, nullptr, nullptr, hip_stream);
+}
+
+mlq_status mlq_check(const int32_t* status_host, int32_t batch) {
+  if (status_host == nullptr || batch < 0) return fail(MLQ_EINVAL, "invalid status array");
+  int32_t bad = 0;
+  for (int32_t i = 0; i < batch; ++i) bad += status_host[i] != MLQ_SAMPLE_OK;
+  if (bad) return fail(MLQ_ENOCONV, "%d of %d samples did not converge", bad, batch);
+  return MLQ_OK;
+}
+
+mlq_status mlq_lattice_normals(const int64_t* z_dev, const double* shift_dev, int32_t s, int64_t N, int64_t first,
+                               int32_t count, double* Y_dev, void* hip_stream) {
+  if (z_dev == nullptr || shift_dev == nullptr || Y_dev == nullptr) return fail(MLQ_EINVAL, "NULL argument");
+  if (s < 1 || N < 1 || first < 0 || count < 0 || N > (int64_t(1) << 31))
+    return fail(MLQ_EINVAL, "invalid lattice size");
+  if (count == 0) return MLQ_OK;
+  launch_lattice(z_dev, shift_dev, s, N, first, count, Y_dev, (hipStream_t)hip_stream);
+  HIP_OK(hipGetLastError());
+  return MLQ_OK;
+}
+
+mlq_status mlq_accumulate(const double* f_fine_dev, const double* f_coarse_dev, int32_t count, double* acc_dev,
+                          void* hip_stream) {
+  if (f_fine_dev == nullptr || acc_dev == nullptr || count < 0) return fail(MLQ_EINVAL, "invalid argument");
+  launch_accumulate(f_fine_dev, f_coarse_dev, count, acc_dev, (hipStream_t)hip_stream);
+  HIP_OK(hipGetLastError());
+  return MLQ_OK;
+}
+
+// Component-by-component construction; operations in the order k = 0..N-1 with
+// one accumulator and no contraction, so the argmin is reproducible exactly.
+mlq_status mlq_cbc(int64_t N, int32_t s, const double* gamma, int64_t* z_out) {
+#pragma clang fp contract(off)
+  if (gamma == nullptr || z_out == nullptr || N < 1 || s < 1 || N > (int64_t(1) << 20))
+    return fail(MLQ_EINVAL, "invalid CBC arguments");
+  if (N == 1) {
+    for (int j = 0; j < s; ++j) z_out[j] = 1;
+    return MLQ_OK;
+  }
+  std::vector<int64_t> cands;
+  for (int64_t z = 1; z < N; ++z) {
+    int64_t a = z, b = N;
+    while (b) {
+      const int64_t t = a % b;
+      a = b;
+      b = t;
+    }
+    if (a == 1) cands.push_back(z);
+  }
+  std::vector<double> Pk(N, 1.0);
+  const double Nd = (double)N;
+  std::vector<double> err(cands.size());
+  for (int j = 0; j < s; ++j) {
+    double emin = 0.0;
+    for (size_t c = 0; c < cands.size(); ++c) {
+      const int64_t z = cands[c];
+      double acc = 0.0;
+      for (int64_t k = 0; k < N; ++k) {
+        const double x = (double)((k * z) % N) / Nd;
+        const double b2 = x * x - x + 1.0 / 6.0;
+        acc = acc + Pk[k] * (1.0 + gamma[j] * b2);
+      }
+      err[c] = -1.0 + acc / Nd;
+      if (c == 0 || err[c] < emin) emin = err[c];
+    }
+    // criteria equal up to rounding count as ties and go to the smallest candidate
+    const double cut = emin + 1e-12 * std::fabs(emin);
+    int64_t bestz = cands[0];
+    for (size_t c = 0; c < cands.size(); ++c)
+      if (err[c] <= cut) {
+        bestz = cands[c];
+        break;
+      }
+    z_out[j] = bestz;
+    for (int64_t k = 0; k < N; ++k) {
+      const double x = (double)((k * bestz) % N) / Nd;
+      const double b2 = x * x - x + 1.0 / 6.0;
+      Pk[k] = Pk[k] * (1.0 + gamma[j] * b2);
+    }
+  }
+  return MLQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Estimators, host FP64 (eqs. (SL), (StandardML), (PimpedML)).
+static double mean_of(const double* v, int64_t n) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += v[i];
+  return s / (double)n;
+}
+
+static double var_of(const double* v, int64_t n) {
+  if (n < 2) return 0.0;
+  const double m = mean_of(v, n);
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += (v[i] - m) * (v[i] - m);
+  return s / (double)(n - 1);
+}
+
+mlq_status mlq_estimate(int32_t kind, int32_t n_levels, int32_t n_shifts, const int64_t* n_per_level,
+                        const double* const* f_fine, const double* const* f_coarse, mlq_estimate_out* out) {
+  if (out == nullptr || n_per_level == nullptr || f_fine == nullptr) return fail(MLQ_EINVAL, "NULL argument");
+  if (n_levels < 1 || n_levels > 16) return fail(MLQ_EINVAL, "n_levels must be in [1, 16]");
+  std::memset(out, 0, sizeof(*out));
+  out->n_levels = n_levels;
+  for (int l = 0; l < n_levels; ++l)
+    if (n_per_level[l] < 1 || f_fine[l] == nullptr) return fail(MLQ_EINVAL, "level %d has no samples", l);
+  if (kind == MLQ_EST_MC) {
+    if (n_levels != 1) return fail(MLQ_EINVAL, "MC estimator takes one level");
+    const int64_t n = n_per_level[0];
+    out->estimate = mean_of(f_fine[0], n);
+    out->level_mean[0] = out->estimate;
+    out->level_var[0] = var_of(f_fine[0], n);
+    out->rmse = std::sqrt(out->level_var[0] / (double)n);
+    return MLQ_OK;
+  }
+  if (kind == MLQ_EST_MLMC || kind == MLQ_EST_MLQMC) {
+    const int S = kind == MLQ_EST_MLQMC ? n_shifts : 1;
+    if (S < 1) return fail(MLQ_EINVAL, "n_shifts must be >= 1");
+    double est = 0.0, mse = 0.0;
+    for (int l = 0; l < n_levels; ++l) {
+      if (l > 0 && (f_coarse == nullptr || f_coarse[l] == nullptr)) return fail(MLQ_EINVAL, "level %d needs f_coarse", l);
+      const int64_t n = n_per_level[l];
+      std::vector<double> y((size_t)S * n);
+      for (int64_t i = 0; i < (int64_t)S * n; ++i) y[i] = f_fine[l][i] - (l > 0 ? f_coarse[l][i] : 0.0);
+      if (kind == MLQ_EST_MLMC) {
+        const double m = mean_of(y.data(), n), v = var_of(y.data(), n);
+        out->level_mean[l] = m;
+        out->level_var[l] = v;
+        est += m;
+        mse += v / (double)n;
+      } else {
+        std::vector<double> q(S);
+        for (int sh = 0; sh < S; ++sh) q[sh] = mean_of(y.data() + (size_t)sh * n, n);
+        const double m = mean_of(q.data(), S);
+        double ss = 0.0;
+        for (int sh = 0; sh < S; ++sh) ss += (q[sh] - m) * (q[sh] - m);
+        out->level_mean[l] = m;
+        out->level_var[l] = var_of(y.data(), (int64_t)S * n);
+        est += m;
+        if (S > 1) mse += ss / ((double)S * (double)(S - 1));
+      }
+    }
+    out->estimate = est;
+    out->rmse = std::sqrt(mse);
+    return MLQ_OK;
+  }
+  if (kind == MLQ_EST_COMBINATION) {
+    const int L = n_levels - 1;
+    double est = 0.0;
+    for (int l = 0; l <= L; ++l) {
+      if (l > 0 && n_per_level[l] < n_per_level[l - 1]) return fail(MLQ_EINVAL, "point sets must be nested");
+      const double* F = f_fine[L - l];
+      const double ql = mean_of(F, n_per_level[l]);
+      const double qm = l > 0 ? mean_of(F, n_per_level[l - 1]) : 0.0;
+      out->level_mean[l] = ql - qm;
+      est += ql - qm;
+    }
+    out->estimate = est;
+    out->rmse = 0.0;
+    return MLQ_OK;
+  }
+  return fail(MLQ_EINVAL, "unknown estimator kind %d", kind);
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Internal declarations shared by the host library (mlq_api.cpp) and the HIP
+// kernels (mlq_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/mlq.h"
+
+namespace mlq {
+
+// Geometry of a uniform Q1 box level, passed by value to the stencil kernels.
+// Element matrices of a brick with edges hx, hy, hz factor into 1D pieces; the
+// H* scalars are the edge-length factors of the mass, the three second-derivative
+// terms and the x-y cross term (Section 3.1, eq. (semi-disc)).
+struct Geo {
+  int32_t dim;
+  int32_t nx, ny, nz;  // nodes per axis (nz = 1 in 2D)
+  int64_t nn;          // nodes per sample
+  int64_t P;           // elements per sample
+  double Hm, Hxx, Hyy, Hzz, Hxy;
+  double sbar;         // (sigma_l + sigma_t) / 2
+  double st;           // sigma_t
+};
+
+// Physics constants of eq. (ionic_term) and the time step.
+struct Ionic {
+  double alpha, u_rest, u_th, u_peak;
+  double dt;
+};
+
+constexpr int kBlock = 256;      // threads per block of the nodal kernels
+constexpr int kRedChunk = 2048;  // nodes per block of the Krylov reduction kernels
+constexpr int kMaxInner = 64;    // upper bound on GMRES iterations per solve
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Pointers of one solve's workspace (carved from the caller's buffer).
+struct Work {
+  // FP64 per-node state, [B][n]
+  double* uk;    // u_k, state at the current time level
+  double* u;     // Newton iterate for u_{k+1}
+  double* b;     // right-hand side of the step
+  double* act;   // activation times (-1: not yet activated)
+  // inner precision per-node vectors, [B][n]
+  void* d;       // dt * I_ion'(u)
+  void* z;       // preconditioned basis vector
+  void* w;       // operator output
+  void* V;       // GMRES basis, (kmax + 1) vectors of [B][n]
+  // per element coefficients [B][P][2] (inner precision)
+  void* coef;
+  // per-sample small arrays
+  double* part;      // reduction partials
+  double* H;         // [B][kmax+1][kmax] Hessenberg
+  double* cs;        // [B][kmax]
+  double* sn;        // [B][kmax]
+  double* g;         // [B][kmax+1]
+  double* y;         // [B][kmax]: y_i * inv_eta_i of the final combination
+  double* hc;        // [B][kmax+1]: h_ij * inv_eta_i of the current Gram-Schmidt step
+  double* inv_eta;   // [B][kmax+1]: V_true[i] = V_stored[i] * inv_eta[i]
+  double* beta;      // [B]
+  int32_t* newton_active;  // [B]
+  int32_t* inner_active;   // [B]
+  int32_t* inner_k;        // [B] iterations taken in the current solve
+  int32_t* status;         // [B] (internal copy)
+  int64_t* iters;          // [B][2]
+  int32_t* counter;        // [4]
+  int kmax;                // GMRES iterations per solve (basis holds kmax + 1 vectors)
+  int32_t nblk;            // blocks per sample of the nodal kernels
+  int32_t nred;            // blocks per sample of the reduction kernels
+  size_t bytes;
+};
+
+// Carves the workspace for a batch.  With base == nullptr only computes bytes.
+Work carve_workspace(void* base, int64_t nn, int64_t P, int32_t batch, int kmax, bool mixed);
+
+// ---- kernel launchers (mlq_kernels.hip) --------------------------------------
+void launch_coefs(const void* theta, void* coef, int64_t P, int32_t B, double half_dsig, bool mixed,
+                  hipStream_t s);
+void launch_init(const Work& w, int64_t nn, int32_t B, double u_th, hipStream_t s);
+void launch_rhs(const Geo& g, const Work& w, const double* fbox, double load_coef, double dt, int32_t B,
+                bool mixed, hipStream_t s);
+void launch_residual(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);
+void launch_newton_check(const Geo& g, const Work& w, int32_t B, double tol, hipStream_t s);
+void launch_count(const int32_t* flags, int32_t B, int32_t* out, hipStream_t s);
+void launch_precond(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s);
+void launch_apply_z(const Geo& g, const Work& w, double ck, int32_t B, bool mixed, hipStream_t s);
+void launch_dots(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s);
+void launch_orth(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s);
+void launch_givens(const Geo& g, const Work& w, int j, int32_t B, double tol, hipStream_t s);
+void launch_solve_y(const Work& w, int32_t B, hipStream_t s);
+void launch_update(const Geo& g, const Work& w, int32_t B, bool mixed, hipStream_t s);
+void launch_activation(const Work& w, int64_t nn, int32_t B, double u_th, double t_k, double dt,
+                       hipStream_t s);
+void launch_qoi(const Work& w, const double* wts, int64_t nn, int32_t B, int qoi, double t_stop,
+                double vol, double* qoi_out, hipStream_t s);
+void launch_apply_public(const Geo& g, const void* coef, const void* x, const void* d, void* y,
+                         double ck, int32_t B, bool mixed, hipStream_t s);
+void launch_kl(const void* phi, const double* sqrt_lambda, const double* theta0, const double* Y,
+               int64_t P, int32_t M, int32_t B, void* theta, bool mixed, hipStream_t s);
+void launch_lattice(const int64_t* z, const double* shift, int32_t sdim, int64_t N, int64_t first,
+                    int32_t count, double* Y, hipStream_t s);
+void launch_newton_reset(const Work& w, int32_t B, hipStream_t s);
+void launch_mark_failed(const Work& w, int32_t B, hipStream_t s);
+void launch_accumulate(const double* ff, const double* fc, int32_t count, double* acc, hipStream_t s);
+
+}  // namespace mlq

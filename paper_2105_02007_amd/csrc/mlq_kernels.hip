@@ -1,0 +1,848 @@
+// HIP kernels for gfx950 (CDNA4, wave64): matrix-free Q1 operators of the
+// Crank-Nicolson / Newton space-time solve, batched GMRES, ionic pointwise
+// terms, quantities of interest, KL synthesis and lattice sampling.
+//
+// Batch layout: nodal vectors are [B][n] (sample-major, node index with axis 0
+// fastest), element data [B][P][...].  Grids use blockIdx.y for the sample so a
+// block never straddles two samples; per-sample masks let whole blocks exit.
+#include "mlq_internal.h"
+
+#include <cmath>
+
+namespace mlq {
+
+// ---------------------------------------------------------------------------
+// 1D factors of the Q1 brick element matrices (Section 3.1, eq. (semi-disc)).
+// Local node a of an element has bit k = offset along axis k.
+//   mass      int phi_a phi_b           = h * mm(a, b)
+//   stiffness int phi_a' phi_b'         = kk(a, b) / h
+//   mixed     int phi_a phi_b'          = ss(b) / 2
+__host__ __device__ constexpr double mm(int p, int q) { return p == q ? (1.0 / 3.0) : (1.0 / 6.0); }
+__host__ __device__ constexpr double kk(int p, int q) { return p == q ? 1.0 : -1.0; }
+__host__ __device__ constexpr double ss(int p) { return p ? 1.0 : -1.0; }
+
+template <typename T>
+__device__ inline T ld(const T* p) { return *p; }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Deterministic block sum; result valid in every thread.
+template <int NT>
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) r += sh[i];
+  return r;
+}
+
+// Ionic current eq. (ionic_term) and its derivative.
+__device__ inline double iion(double u, const Ionic& io) {
+  return io.alpha * (u - io.u_rest) * (u - io.u_th) * (u - io.u_peak);
+}
+__device__ inline double diion(double u, const Ionic& io) {
+  const double a = u - io.u_rest, b = u - io.u_th, c = u - io.u_peak;
+  return io.alpha * (b * c + a * c + a * b);
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-free gather of the mass and anisotropic stiffness rows of node i.
+// G_e = sbar I + p_e (e_x e_x^T - e_y e_y^T) + q_e (e_x e_y^T + e_y e_x^T) [+ (st - sbar) e_z e_z^T]
+// which equals eq. (AdmV) with V = sigma_l (cos t, sin t, 0), g = sigma_t when
+// p = (sigma_l - sigma_t)/2 cos 2t and q = (sigma_l - sigma_t)/2 sin 2t.
+// xm / xk: the 3^d neighbourhood values of the mass input and stiffness input.
+// Returns SM = sum_e (M_e xm)_a / Hm and SK = sum_e (K_e xk)_a.
+template <typename R, typename TC>
+__host__ __device__ inline void gather3(int ix, int iy, int iz, const Geo& g, const TC* __restrict__ cf,
+                               const R (&xm)[27], const R (&xk)[27], R& SM, R& SK) {
+  SM = R(0);
+  SK = R(0);
+#pragma unroll
+  for (int oz = -1; oz <= 0; ++oz)
+#pragma unroll
+    for (int oy = -1; oy <= 0; ++oy)
+#pragma unroll
+      for (int ox = -1; ox <= 0; ++ox) {
+        const int ex = ix + ox, ey = iy + oy, ez = iz + oz;
+        if (ex < 0 || ey < 0 || ez < 0 || ex >= g.nx - 1 || ey >= g.ny - 1 || ez >= g.nz - 1) continue;
+        const int ax = -ox, ay = -oy, az = -oz;
+        const int64_t e = ex + (int64_t)(g.nx - 1) * (ey + (int64_t)(g.ny - 1) * ez);
+        const R p = (R)cf[2 * e], q = (R)cf[2 * e + 1];
+        R sm = 0, sx = 0, sy = 0, sz = 0, sc = 0;
+#pragma unroll
+        for (int bz = 0; bz < 2; ++bz)
+#pragma unroll
+          for (int by = 0; by < 2; ++by)
+#pragma unroll
+            for (int bx = 0; bx < 2; ++bx) {
+              const int nb = (ox + bx + 1) + 3 * ((oy + by + 1) + 3 * (oz + bz + 1));
+              sm += (R)(mm(ax, bx) * mm(ay, by) * mm(az, bz)) * xm[nb];
+              sx += (R)(kk(ax, bx) * mm(ay, by) * mm(az, bz)) * xk[nb];
+              sy += (R)(mm(ax, bx) * kk(ay, by) * mm(az, bz)) * xk[nb];
+              sz += (R)(mm(ax, bx) * mm(ay, by) * kk(az, bz)) * xk[nb];
+              sc += (R)(0.25 * (ss(ax) * ss(by) + ss(ay) * ss(bx)) * mm(az, bz)) * xk[nb];
+            }
+        SM += sm;
+        SK += ((R)g.sbar + p) * (R)g.Hxx * sx + ((R)g.sbar - p) * (R)g.Hyy * sy +
+              (R)g.st * (R)g.Hzz * sz + q * (R)g.Hxy * sc;
+      }
+}
+
+template <typename R, typename TC>
+__host__ __device__ inline void gather2(int ix, int iy, const Geo& g, const TC* __restrict__ cf, const R (&xm)[27],
+                               const R (&xk)[27], R& SM, R& SK) {
+  SM = R(0);
+  SK = R(0);
+#pragma unroll
+  for (int oy = -1; oy <= 0; ++oy)
+#pragma unroll
+    for (int ox = -1; ox <= 0; ++ox) {
+      const int ex = ix + ox, ey = iy + oy;
+      if (ex < 0 || ey < 0 || ex >= g.nx - 1 || ey >= g.ny - 1) continue;
+      const int ax = -ox, ay = -oy;
+      const int64_t e = ex + (int64_t)(g.nx - 1) * ey;
+      const R p = (R)cf[2 * e], q = (R)cf[2 * e + 1];
+      R sm = 0, sx = 0, sy = 0, sc = 0;
+#pragma unroll
+      for (int by = 0; by < 2; ++by)
+#pragma unroll
+        for (int bx = 0; bx < 2; ++bx) {
+          const int nb = (ox + bx + 1) + 3 * (oy + by + 1) + 9;  // middle plane of the 3x3x3 block
+          sm += (R)(mm(ax, bx) * mm(ay, by)) * xm[nb];
+          sx += (R)(kk(ax, bx) * mm(ay, by)) * xk[nb];
+          sy += (R)(mm(ax, bx) * kk(ay, by)) * xk[nb];
+          sc += (R)(0.25 * (ss(ax) * ss(by) + ss(ay) * ss(bx))) * xk[nb];
+        }
+      SM += sm;
+      SK += ((R)g.sbar + p) * (R)g.Hxx * sx + ((R)g.sbar - p) * (R)g.Hyy * sy + q * (R)g.Hxy * sc;
+    }
+}
+
+// Decode node index of a sample into grid coordinates.
+__host__ __device__ inline void node_xyz(int64_t i, const Geo& g, int& ix, int& iy, int& iz) {
+  ix = (int)(i % g.nx);
+  const int64_t r = i / g.nx;
+  iy = (int)(r % g.ny);
+  iz = (int)(r / g.ny);
+}
+
+// Load the 3^d neighbourhood through a functor f(node_index) -> (mass input, stiffness input).
+template <int DIM, typename R, typename F>
+__host__ __device__ inline void load_nbhd(int ix, int iy, int iz, const Geo& g, F f, R (&xm)[27], R (&xk)[27]) {
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int nb = (dx + 1) + 3 * ((dy + 1) + 3 * (dz + 1));
+        if (DIM == 2 && dz != 0) {
+          xm[nb] = 0;
+          xk[nb] = 0;
+          continue;
+        }
+        const int jx = ix + dx, jy = iy + dy, jz = iz + dz;
+        const bool in = jx >= 0 && jy >= 0 && jz >= 0 && jx < g.nx && jy < g.ny && jz < g.nz;
+        if (in) {
+          const int64_t j = jx + (int64_t)g.nx * (jy + (int64_t)g.ny * jz);
+          f(j, xm[nb], xk[nb]);
+        } else {
+          xm[nb] = 0;
+          xk[nb] = 0;
+        }
+      }
+}
+
+template <int DIM, typename R, typename TC>
+__host__ __device__ inline void gather(int ix, int iy, int iz, const Geo& g, const TC* cf, const R (&xm)[27],
+                              const R (&xk)[27], R& SM, R& SK) {
+  if constexpr (DIM == 3)
+    gather3<R, TC>(ix, iy, iz, g, cf, xm, xk, SM, SK);
+  else
+    gather2<R, TC>(ix, iy, g, cf, xm, xk, SM, SK);
+}
+
+// ---------------------------------------------------------------------------
+// Per-element coefficients from fibre angles: p = (s_l - s_t)/2 cos 2t, q = (s_l - s_t)/2 sin 2t.
+template <typename TT, typename TC>
+__global__ void k_coefs(const TT* __restrict__ theta, TC* __restrict__ coef, int64_t total, double half_dsig) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  if constexpr (sizeof(TC) == 4) {
+    const float t2 = 2.0f * (float)theta[i];
+    float sv, cv;
+    sincosf(t2, &sv, &cv);
+    coef[2 * i] = (float)half_dsig * cv;
+    coef[2 * i + 1] = (float)half_dsig * sv;
+  } else {
+    const double t2 = 2.0 * (double)theta[i];
+    double sv, cv;
+    sincos(t2, &sv, &cv);
+    coef[2 * i] = half_dsig * cv;
+    coef[2 * i + 1] = half_dsig * sv;
+  }
+}
+
+void launch_coefs(const void* theta, void* coef, int64_t P, int32_t B, double half_dsig, bool mixed,
+                  hipStream_t s) {
+  const int64_t total = P * (int64_t)B;
+  const dim3 grid((unsigned)cdiv(total, kBlock));
+  if (mixed)
+    hipLaunchKernelGGL((k_coefs<float, float>), grid, dim3(kBlock), 0, s, (const float*)theta, (float*)coef,
+                       total, half_dsig);
+  else
+    hipLaunchKernelGGL((k_coefs<double, double>), grid, dim3(kBlock), 0, s, (const double*)theta,
+                       (double*)coef, total, half_dsig);
+}
+
+// ---------------------------------------------------------------------------
+// Initial state u_0 = 0, activation flags, per-sample counters.
+__global__ void k_init(double* uk, double* act, int64_t nn, double u_th, int32_t* status, int64_t* iters,
+                       int32_t B) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = nn * B;
+  if (i < total) {
+    uk[i] = 0.0;
+    act[i] = (0.0 >= u_th) ? 0.0 : -1.0;
+  }
+  if (i < B) {
+    status[i] = MLQ_SAMPLE_OK;
+    iters[2 * i] = 0;
+    iters[2 * i + 1] = 0;
+  }
+}
+
+void launch_init(const Work& w, int64_t nn, int32_t B, double u_th, hipStream_t s) {
+  const int64_t total = nn * B > B ? nn * B : B;
+  hipLaunchKernelGGL(k_init, dim3((unsigned)cdiv(total, kBlock)), dim3(kBlock), 0, s, w.uk, w.act, nn, u_th,
+                     w.status, w.iters, B);
+}
+
+// ---------------------------------------------------------------------------
+// Right-hand side of step k (eq. (st-system)):  b = (M - dt/2 K) u_k + c_k F_box,
+// c_k = dt/2 (s(t_{k+1}) + s(t_k)).  Also starts Newton from u = u_k.
+template <int DIM, typename TC>
+__global__ __launch_bounds__(kBlock) void k_rhs(Geo g, const double* __restrict__ uk, const TC* __restrict__ coef,
+                                                const double* __restrict__ fbox, double load_coef, double half_dt,
+                                                double* __restrict__ bvec, double* __restrict__ u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sb = blockIdx.y;
+  if (i >= g.nn) return;
+  const double* us = uk + (int64_t)sb * g.nn;
+  const TC* cf = coef + (int64_t)sb * g.P * 2;
+  int ix, iy, iz;
+  node_xyz(i, g, ix, iy, iz);
+  double xm[27], xk[27];
+  load_nbhd<DIM, double>(ix, iy, iz, g, [&](int64_t j, double& a, double& b) { a = b = us[j]; }, xm, xk);
+  double SM, SK;
+  gather<DIM, double, TC>(ix, iy, iz, g, cf, xm, xk, SM, SK);
+  const int64_t o = (int64_t)sb * g.nn + i;
+  bvec[o] = g.Hm * SM - half_dt * SK + load_coef * fbox[i];
+  u[o] = us[i];
+}
+
+void launch_rhs(const Geo& g, const Work& w, const double* fbox, double load_coef, double dt, int32_t B, bool mixed,
+                hipStream_t s) {
+  const dim3 grid((unsigned)cdiv(g.nn, kBlock), B);
+  if (g.dim == 3) {
+    if (mixed)
+      hipLaunchKernelGGL((k_rhs<3, float>), grid, dim3(kBlock), 0, s, g, w.uk, (const float*)w.coef, fbox, load_coef,
+                         0.5 * dt, w.b, w.u);
+    else
+      hipLaunchKernelGGL((k_rhs<3, double>), grid, dim3(kBlock), 0, s, g, w.uk, (const double*)w.coef, fbox,
+                         load_coef, 0.5 * dt, w.b, w.u);
+  } else {
+    if (mixed)
+      hipLaunchKernelGGL((k_rhs<2, float>), grid, dim3(kBlock), 0, s, g, w.uk, (const float*)w.coef, fbox, load_coef,
+                         0.5 * dt, w.b, w.u);
+    else
+      hipLaunchKernelGGL((k_rhs<2, double>), grid, dim3(kBlock), 0, s, g, w.uk, (const double*)w.coef, fbox,
+                         load_coef, 0.5 * dt, w.b, w.u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Nonlinear residual of a step (eq. (mono_disc)), FP64:
+//   G(u) = M (u + dt I_ion(u)) + dt/2 K u,   F = G(u) - b.
+// Writes r0 = -F (inner precision: GMRES right-hand side), d = dt I_ion'(u),
+// and per-block partial sums of |F|^2, |G|^2, |b|^2.
+template <int DIM, typename TC, typename TI>
+__global__ __launch_bounds__(kBlock) void k_residual(Geo g, Ionic io, const double* __restrict__ u,
+                                                     const double* __restrict__ bvec, const TC* __restrict__ coef,
+                                                     TI* __restrict__ r0, TI* __restrict__ dvec,
+                                                     double* __restrict__ part, const int32_t* __restrict__ active) {
+  const int sb = blockIdx.y;
+  if (active[sb] == 0) return;
+  __shared__ double sh[kBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double f2 = 0.0, g2 = 0.0, b2 = 0.0;
+  if (i < g.nn) {
+    const double* us = u + (int64_t)sb * g.nn;
+    const TC* cf = coef + (int64_t)sb * g.P * 2;
+    int ix, iy, iz;
+    node_xyz(i, g, ix, iy, iz);
+    double xm[27], xk[27];
+    load_nbhd<DIM, double>(
+        ix, iy, iz, g,
+        [&](int64_t j, double& a, double& b) {
+          const double v = us[j];
+          a = v + io.dt * iion(v, io);
+          b = v;
+        },
+        xm, xk);
+    double SM, SK;
+    gather<DIM, double, TC>(ix, iy, iz, g, cf, xm, xk, SM, SK);
+    const int64_t o = (int64_t)sb * g.nn + i;
+    const double G = g.Hm * SM + 0.5 * io.dt * SK;
+    const double bb = bvec[o];
+    const double F = G - bb;
+    r0[o] = (TI)(-F);
+    dvec[o] = (TI)(io.dt * diion(us[i], io));
+    f2 = F * F;
+    g2 = G * G;
+    b2 = bb * bb;
+  }
+  const double s0 = block_sum<kBlock>(f2, sh);
+  const double s1 = block_sum<kBlock>(g2, sh);
+  const double s2 = block_sum<kBlock>(b2, sh);
+  if (threadIdx.x == 0) {
+    double* p = part + ((int64_t)sb * gridDim.x + blockIdx.x) * 3;
+    p[0] = s0;
+    p[1] = s1;
+    p[2] = s2;
+  }
+}
+
+void launch_residual(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)cdiv(g.nn, kBlock), B);
+#define MLQ_RES(D, TC, TI)                                                                                        \
+  hipLaunchKernelGGL((k_residual<D, TC, TI>), grid, dim3(kBlock), 0, s, g, io, w.u, w.b, (const TC*)w.coef,       \
+                     (TI*)w.V, (TI*)w.d, w.part, w.newton_active)
+  if (g.dim == 3) {
+    if (mixed) MLQ_RES(3, float, float); else MLQ_RES(3, double, double);
+  } else {
+    if (mixed) MLQ_RES(2, float, float); else MLQ_RES(2, double, double);
+  }
+#undef MLQ_RES
+}
+
+// Per-sample Newton test: backward error |F| / (|G| + |b|) <= tol.  Also starts
+// GMRES: beta = |r0|, g = (beta, 0, ..), inv_eta[0] = 1/beta.
+__global__ __launch_bounds__(kBlock) void k_newton_check(const double* __restrict__ part, int32_t nblk, double tol,
+                                                         int32_t* newton_active, int32_t* inner_active,
+                                                         int32_t* inner_k, int32_t* status, double* beta, double* gv,
+                                                         double* inv_eta, int kmax) {
+  const int sb = blockIdx.x;
+  if (newton_active[sb] == 0) return;
+  __shared__ double sh[kBlock / 64];
+  double a0 = 0, a1 = 0, a2 = 0;
+  for (int i = threadIdx.x; i < nblk; i += kBlock) {
+    const double* p = part + ((int64_t)sb * nblk + i) * 3;
+    a0 += p[0];
+    a1 += p[1];
+    a2 += p[2];
+  }
+  const double F2 = block_sum<kBlock>(a0, sh);
+  const double G2 = block_sum<kBlock>(a1, sh);
+  const double B2 = block_sum<kBlock>(a2, sh);
+  if (threadIdx.x == 0) {
+    const double nf = sqrt(F2), den = sqrt(G2) + sqrt(B2);
+    const double err = den == 0.0 ? 0.0 : nf / den;
+    inner_k[sb] = 0;
+    if (!(err == err) || !isfinite(nf)) {
+      status[sb] = MLQ_SAMPLE_NAN;
+      newton_active[sb] = 0;
+      inner_active[sb] = 0;
+    } else if (err <= tol || nf == 0.0) {
+      newton_active[sb] = 0;
+      inner_active[sb] = 0;
+    } else {
+      inner_active[sb] = 1;
+      beta[sb] = nf;
+      inv_eta[(int64_t)sb * (kmax + 1)] = 1.0 / nf;
+      double* gs = gv + (int64_t)sb * (kmax + 1);
+      gs[0] = nf;
+      for (int j = 1; j <= kmax; ++j) gs[j] = 0.0;
+    }
+  }
+}
+
+
+void launch_newton_check(const Geo& g, const Work& w, int32_t B, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_newton_check, dim3(B), dim3(kBlock), 0, s, w.part, w.nblk, tol, w.newton_active,
+                     w.inner_active, w.inner_k, w.status, w.beta, w.g, w.inv_eta, w.kmax);
+}
+
+__global__ void k_count(const int32_t* __restrict__ flags, int32_t B, int32_t* out) {
+  __shared__ double sh[kBlock / 64];
+  double c = 0;
+  for (int i = threadIdx.x; i < B; i += kBlock) c += flags[i] != 0 ? 1.0 : 0.0;
+  c = block_sum<kBlock>(c, sh);
+  if (threadIdx.x == 0) out[0] = (int32_t)c;
+}
+
+void launch_count(const int32_t* flags, int32_t B, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_count, dim3(1), dim3(kBlock), 0, s, flags, B, out);
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi preconditioner with the diagonal of M (1 + d):
+//   z = v_j / (m_ii (1 + d_i)),  m_ii = Hm (elements at node i) (1/3)^dim.
+__device__ inline double mass_diag(const Geo& g, int ix, int iy, int iz) {
+  const int cx = (ix == 0 || ix == g.nx - 1) ? 1 : 2;
+  const int cy = (iy == 0 || iy == g.ny - 1) ? 1 : 2;
+  const int cz = (g.dim == 2) ? 1 : ((iz == 0 || iz == g.nz - 1) ? 1 : 2);
+  const double third = 1.0 / 3.0;
+  return g.Hm * (double)(cx * cy * cz) * (g.dim == 3 ? third * third * third : third * third);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_precond(Geo g, const T* __restrict__ V, const T* __restrict__ d,
+                                                    T* __restrict__ z, const double* __restrict__ inv_eta, int j,
+                                                    int kmax, const int32_t* __restrict__ active) {
+  const int sb = blockIdx.y;
+  if (active[sb] == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nn) return;
+  int ix, iy, iz;
+  node_xyz(i, g, ix, iy, iz);
+  const int64_t o = (int64_t)sb * g.nn + i;
+  const T s = (T)inv_eta[(int64_t)sb * (kmax + 1) + j];
+  z[o] = V[o] * s / ((T)mass_diag(g, ix, iy, iz) * ((T)1 + d[o]));
+}
+
+void launch_precond(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)w.nblk, B);
+  const size_t vs = (size_t)g.nn * B;
+  if (mixed)
+    hipLaunchKernelGGL((k_precond<float>), grid, dim3(kBlock), 0, s, g, (const float*)w.V + j * vs,
+                       (const float*)w.d, (float*)w.z, w.inv_eta, j, w.kmax, w.inner_active);
+  else
+    hipLaunchKernelGGL((k_precond<double>), grid, dim3(kBlock), 0, s, g, (const double*)w.V + j * vs,
+                       (const double*)w.d, (double*)w.z, w.inv_eta, j, w.kmax, w.inner_active);
+}
+
+// ---------------------------------------------------------------------------
+// Jacobian apply (Section 3.2): y = M ((1 + d) x) + ck K_G x, ck = dt/2.
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_apply(Geo g, const T* __restrict__ x, const T* __restrict__ d,
+                                                  const T* __restrict__ coef, T* __restrict__ y, T ck,
+                                                  const int32_t* __restrict__ active) {
+  const int sb = blockIdx.y;
+  if (active != nullptr && active[sb] == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nn) return;
+  const T* xs = x + (int64_t)sb * g.nn;
+  const T* ds = d + (int64_t)sb * g.nn;
+  const T* cf = coef + (int64_t)sb * g.P * 2;
+  int ix, iy, iz;
+  node_xyz(i, g, ix, iy, iz);
+  T xm[27], xk[27];
+  load_nbhd<DIM, T>(
+      ix, iy, iz, g,
+      [&](int64_t j, T& a, T& b) {
+        const T v = xs[j];
+        a = v + ds[j] * v;
+        b = v;
+      },
+      xm, xk);
+  T SM, SK;
+  gather<DIM, T, T>(ix, iy, iz, g, cf, xm, xk, SM, SK);
+  y[(int64_t)sb * g.nn + i] = (T)g.Hm * SM + ck * SK;
+}
+
+template <typename T>
+static void apply_dispatch(const Geo& g, const T* coef, const T* x, const T* d, T* y, double ck, int32_t B,
+                           const int32_t* active, hipStream_t s) {
+  const dim3 grid((unsigned)cdiv(g.nn, kBlock), B);
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_apply<3, T>), grid, dim3(kBlock), 0, s, g, x, d, coef, y, (T)ck, active);
+  else
+    hipLaunchKernelGGL((k_apply<2, T>), grid, dim3(kBlock), 0, s, g, x, d, coef, y, (T)ck, active);
+}
+
+void launch_apply_z(const Geo& g, const Work& w, double ck, int32_t B, bool mixed, hipStream_t s) {
+  if (mixed)
+    apply_dispatch<float>(g, (const float*)w.coef, (const float*)w.z, (const float*)w.d, (float*)w.w, ck, B,
+                          w.inner_active, s);
+  else
+    apply_dispatch<double>(g, (const double*)w.coef, (const double*)w.z, (const double*)w.d, (double*)w.w, ck, B,
+                           w.inner_active, s);
+}
+
+void launch_apply_public(const Geo& g, const void* coef, const void* x, const void* d, void* y, double ck,
+                         int32_t B, bool mixed, hipStream_t s) {
+  if (mixed)
+    apply_dispatch<float>(g, (const float*)coef, (const float*)x, (const float*)d, (float*)y, ck, B, nullptr, s);
+  else
+    apply_dispatch<double>(g, (const double*)coef, (const double*)x, (const double*)d, (double*)y, ck, B, nullptr,
+                           s);
+}
+
+// ---------------------------------------------------------------------------
+// Classical Gram-Schmidt, step j of GMRES, per sample:
+//   part[b][blk][i] = sum_chunk w . Vs_i  (i <= j)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dots(int64_t nn, const T* __restrict__ w, const T* __restrict__ V,
+                                                 size_t vs, int j, int kmax, double* __restrict__ part,
+                                                 const int32_t* __restrict__ active) {
+  const int sb = blockIdx.y;
+  if (active[sb] == 0) return;
+  __shared__ double sh[kBlock / 64];
+  const int64_t base = (int64_t)blockIdx.x * kRedChunk;
+  const int64_t end = base + kRedChunk < nn ? base + kRedChunk : nn;
+  const T* ws = w + (int64_t)sb * nn;
+  for (int i = 0; i <= j; ++i) {
+    const T* vi = V + i * vs + (int64_t)sb * nn;
+    double acc = 0.0;
+    for (int64_t t = base + threadIdx.x; t < end; t += kBlock) acc += (double)ws[t] * (double)vi[t];
+    acc = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) part[((int64_t)sb * gridDim.x + blockIdx.x) * (kmax + 1) + i] = acc;
+  }
+}
+
+// h_ij = inv_eta_i sum_blk part; hc_i = h_ij inv_eta_i (coefficient on the stored vector).
+__global__ void k_dots_final(const double* __restrict__ part, int32_t nred, int j, int kmax, double* H, double* hc,
+                             const double* __restrict__ inv_eta, const int32_t* __restrict__ active) {
+  const int sb = blockIdx.x;
+  if (active[sb] == 0) return;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+    double acc = 0.0;
+    for (int b = 0; b < nred; ++b) acc += part[((int64_t)sb * nred + b) * (kmax + 1) + i];
+    const double ie = inv_eta[(int64_t)sb * (kmax + 1) + i];
+    const double h = acc * ie;
+    H[((int64_t)sb * (kmax + 1) + i) * kmax + j] = h;
+    hc[(int64_t)sb * (kmax + 1) + i] = h * ie;
+  }
+}
+
+void launch_dots(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)w.nred, B);
+  const size_t vs = (size_t)g.nn * B;
+  if (mixed)
+    hipLaunchKernelGGL((k_dots<float>), grid, dim3(kBlock), 0, s, g.nn, (const float*)w.w, (const float*)w.V, vs,
+                       j, w.kmax, w.part, w.inner_active);
+  else
+    hipLaunchKernelGGL((k_dots<double>), grid, dim3(kBlock), 0, s, g.nn, (const double*)w.w, (const double*)w.V,
+                       vs, j, w.kmax, w.part, w.inner_active);
+  hipLaunchKernelGGL(k_dots_final, dim3(B), dim3(64), 0, s, w.part, w.nred, j, w.kmax, w.H, w.hc, w.inv_eta,
+                     w.inner_active);
+}
+
+// Vs_{j+1} = w - sum_i hc_i Vs_i, partial |Vs_{j+1}|^2.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_orth(int64_t nn, const T* __restrict__ w, T* __restrict__ V, size_t vs,
+                                                 int j, int kmax, const double* __restrict__ hc,
+                                                 double* __restrict__ part, const int32_t* __restrict__ active) {
+  const int sb = blockIdx.y;
+  if (active[sb] == 0) return;
+  __shared__ double sh[kBlock / 64];
+  __shared__ double c[kMaxInner + 1];
+  for (int i = threadIdx.x; i <= j; i += kBlock) c[i] = hc[(int64_t)sb * (kmax + 1) + i];
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRedChunk;
+  const int64_t end = base + kRedChunk < nn ? base + kRedChunk : nn;
+  const T* ws = w + (int64_t)sb * nn;
+  T* vn = V + (size_t)(j + 1) * vs + (int64_t)sb * nn;
+  double acc = 0.0;
+  for (int64_t t = base + threadIdx.x; t < end; t += kBlock) {
+    double v = (double)ws[t];
+    for (int i = 0; i <= j; ++i) v -= c[i] * (double)V[i * vs + (int64_t)sb * nn + t];
+    const T vt = (T)v;
+    vn[t] = vt;
+    acc += (double)vt * (double)vt;
+  }
+  acc = block_sum<kBlock>(acc, sh);
+  if (threadIdx.x == 0) part[(int64_t)sb * gridDim.x + blockIdx.x] = acc;
+}
+
+void launch_orth(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)w.nred, B);
+  const size_t vs = (size_t)g.nn * B;
+  if (mixed)
+    hipLaunchKernelGGL((k_orth<float>), grid, dim3(kBlock), 0, s, g.nn, (const float*)w.w, (float*)w.V, vs, j,
+                       w.kmax, w.hc, w.part, w.inner_active);
+  else
+    hipLaunchKernelGGL((k_orth<double>), grid, dim3(kBlock), 0, s, g.nn, (const double*)w.w, (double*)w.V, vs, j,
+                       w.kmax, w.hc, w.part, w.inner_active);
+}
+
+// Norm of the new vector, Givens rotations of column j, residual estimate |g_{j+1}|.
+__global__ __launch_bounds__(kBlock) void k_givens(const double* __restrict__ part, int32_t nred, int j, int kmax,
+                                                   double tol, double* H, double* cs, double* sn, double* gv,
+                                                   double* inv_eta, const double* __restrict__ beta,
+                                                   int32_t* inner_active, int32_t* inner_k) {
+  const int sb = blockIdx.x;
+  if (inner_active[sb] == 0) return;
+  __shared__ double sh[kBlock / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nred; i += kBlock) acc += part[(int64_t)sb * nred + i];
+  const double nrm2 = block_sum<kBlock>(acc, sh);
+  if (threadIdx.x != 0) return;
+  const int64_t hb = (int64_t)sb * (kmax + 1) * kmax;
+  double* Hs = H + hb;
+  double* c = cs + (int64_t)sb * kmax;
+  double* s = sn + (int64_t)sb * kmax;
+  double* gs = gv + (int64_t)sb * (kmax + 1);
+  const double hn = sqrt(nrm2);
+  inv_eta[(int64_t)sb * (kmax + 1) + j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+  for (int i = 0; i < j; ++i) {
+    const double a = Hs[i * kmax + j], b = Hs[(i + 1) * kmax + j];
+    Hs[i * kmax + j] = c[i] * a + s[i] * b;
+    Hs[(i + 1) * kmax + j] = -s[i] * a + c[i] * b;
+  }
+  const double a = Hs[j * kmax + j];
+  const double r = hypot(a, hn);
+  double cj = 1.0, sj = 0.0;
+  if (r > 0.0) {
+    cj = a / r;
+    sj = hn / r;
+  }
+  c[j] = cj;
+  s[j] = sj;
+  Hs[j * kmax + j] = r;
+  Hs[(j + 1) * kmax + j] = 0.0;
+  gs[j + 1] = -sj * gs[j];
+  gs[j] = cj * gs[j];
+  const double res = fabs(gs[j + 1]);
+  if (res <= tol * beta[sb] || hn == 0.0 || j + 1 >= kmax || !(res == res)) {
+    inner_active[sb] = 0;
+    inner_k[sb] = j + 1;
+  }
+}
+
+void launch_givens(const Geo& g, const Work& w, int j, int32_t B, double tol, hipStream_t s) {
+  (void)g;
+  hipLaunchKernelGGL(k_givens, dim3(B), dim3(kBlock), 0, s, w.part, w.nred, j, w.kmax, tol, w.H, w.cs, w.sn, w.g,
+                     w.inv_eta, w.beta, w.inner_active, w.inner_k);
+}
+
+// Back substitution R y = g on the rotated Hessenberg matrix; stores y_i inv_eta_i.
+__global__ void k_solve_y(int32_t B, int kmax, const double* __restrict__ H, const double* __restrict__ gv,
+                          const double* __restrict__ inv_eta, const int32_t* __restrict__ newton_active,
+                          const int32_t* __restrict__ inner_k, double* y) {
+  const int sb = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sb >= B || newton_active[sb] == 0) return;
+  const int k = inner_k[sb];
+  const double* Hs = H + (int64_t)sb * (kmax + 1) * kmax;
+  const double* gs = gv + (int64_t)sb * (kmax + 1);
+  double* ys = y + (int64_t)sb * kmax;
+  for (int i = k - 1; i >= 0; --i) {
+    double v = gs[i];
+    for (int l = i + 1; l < k; ++l) v -= Hs[i * kmax + l] * ys[l];
+    ys[i] = Hs[i * kmax + i] != 0.0 ? v / Hs[i * kmax + i] : 0.0;
+  }
+  for (int i = 0; i < k; ++i) ys[i] *= inv_eta[(int64_t)sb * (kmax + 1) + i];
+}
+
+void launch_solve_y(const Work& w, int32_t B, hipStream_t s) {
+  hipLaunchKernelGGL(k_solve_y, dim3((unsigned)cdiv(B, 64)), dim3(64), 0, s, B, w.kmax, w.H, w.g, w.inv_eta,
+                     w.newton_active, w.inner_k, w.y);
+}
+
+// Newton update u += P^-1 (sum_i y_i v_i) (right preconditioning), FP64 accumulate.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update(Geo g, const T* __restrict__ V, size_t vs, const T* __restrict__ d,
+                                                   const double* __restrict__ y, int kmax,
+                                                   const int32_t* __restrict__ inner_k, double* __restrict__ u,
+                                                   int64_t* iters, const int32_t* __restrict__ active) {
+  const int sb = blockIdx.y;
+  if (active[sb] == 0) return;
+  __shared__ double c[kMaxInner];
+  const int k = inner_k[sb];
+  for (int i = threadIdx.x; i < k; i += kBlock) c[i] = y[(int64_t)sb * kmax + i];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    iters[2 * sb] += 1;
+    iters[2 * sb + 1] += k;
+  }
+  if (i >= g.nn) return;
+  int ix, iy, iz;
+  node_xyz(i, g, ix, iy, iz);
+  const int64_t o = (int64_t)sb * g.nn + i;
+  double sacc = 0.0;
+  for (int l = 0; l < k; ++l) sacc += c[l] * (double)V[l * vs + o];
+  const T st = (T)sacc;
+  const T z = st / ((T)mass_diag(g, ix, iy, iz) * ((T)1 + d[o]));
+  u[o] += (double)z;
+}
+
+void launch_update(const Geo& g, const Work& w, int32_t B, bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)w.nblk, B);
+  const size_t vs = (size_t)g.nn * B;
+  if (mixed)
+    hipLaunchKernelGGL((k_update<float>), grid, dim3(kBlock), 0, s, g, (const float*)w.V, vs, (const float*)w.d, w.y,
+                       w.kmax, w.inner_k, w.u, w.iters, w.newton_active);
+  else
+    hipLaunchKernelGGL((k_update<double>), grid, dim3(kBlock), 0, s, g, (const double*)w.V, vs, (const double*)w.d,
+                       w.y, w.kmax, w.inner_k, w.u, w.iters, w.newton_active);
+}
+
+// ---------------------------------------------------------------------------
+// Activation time (Section 2.4): first crossing of u_th, linear in time.
+__global__ void k_activation(const double* __restrict__ uk, const double* __restrict__ u, double* __restrict__ act,
+                             int64_t total, double u_th, double t_k, double dt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const double a = uk[i], b = u[i];
+  if (act[i] < 0.0 && a < u_th && b >= u_th) act[i] = t_k + dt * (u_th - a) / (b - a);
+}
+
+void launch_activation(const Work& w, int64_t nn, int32_t B, double u_th, double t_k, double dt, hipStream_t s) {
+  const int64_t total = nn * B;
+  hipLaunchKernelGGL(k_activation, dim3((unsigned)cdiv(total, kBlock)), dim3(kBlock), 0, s, w.uk, w.u, w.act, total,
+                     u_th, t_k, dt);
+}
+
+// QoI: (1/|D|) sum_i w_i v_i with v = u (final) or the censored activation time.
+__global__ __launch_bounds__(kBlock) void k_qoi(const double* __restrict__ u, const double* __restrict__ act,
+                                                const double* __restrict__ wts, int64_t nn, int qoi, double t_stop,
+                                                double vol, double* out) {
+  __shared__ double sh[kBlock / 64];
+  const int sb = blockIdx.x;
+  const double* us = u + (int64_t)sb * nn;
+  const double* as = act + (int64_t)sb * nn;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < nn; i += kBlock) {
+    const double v = qoi == MLQ_QOI_MEAN_U_FINAL ? us[i] : (as[i] < 0.0 ? t_stop : as[i]);
+    acc += wts[i] * v;
+  }
+  acc = block_sum<kBlock>(acc, sh);
+  if (threadIdx.x == 0) out[sb] = acc / vol;
+}
+
+void launch_qoi(const Work& w, const double* wts, int64_t nn, int32_t B, int qoi, double t_stop, double vol,
+                double* qoi_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_qoi, dim3(B), dim3(kBlock), 0, s, w.uk, w.act, wts, nn, qoi, t_stop, vol, qoi_out);
+}
+
+// ---------------------------------------------------------------------------
+// KL synthesis eq. (KLlowrank): theta[b][p] = theta0[p] + sum_k phi[p][k] sqrt_lambda[k] Y[k + M b].
+// FP64 reference kernel: a block covers 256 element centres x 8 samples; the
+// scaled coordinates of the 8 samples sit in LDS.
+constexpr int kKLSamples = 8;
+template <typename TO>
+__global__ __launch_bounds__(kBlock) void k_kl64(const double* __restrict__ phi, const double* __restrict__ sl,
+                                                 const double* __restrict__ theta0, const double* __restrict__ Y,
+                                                 int64_t P, int32_t M, int32_t B, TO* __restrict__ theta) {
+  extern __shared__ double ys[];  // [M][kKLSamples]
+  const int b0 = blockIdx.y * kKLSamples;
+  for (int t = threadIdx.x; t < M * kKLSamples; t += kBlock) {
+    const int k = t / kKLSamples, bb = t % kKLSamples;
+    ys[t] = (b0 + bb < B) ? sl[k] * Y[(int64_t)(b0 + bb) * M + k] : 0.0;
+  }
+  __syncthreads();
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= P) return;
+  double acc[kKLSamples];
+  const double t0 = theta0 != nullptr ? theta0[p] : 0.0;
+#pragma unroll
+  for (int bb = 0; bb < kKLSamples; ++bb) acc[bb] = 0.0;
+  const double* row = phi + p * M;
+  for (int k = 0; k < M; ++k) {
+    const double f = row[k];
+#pragma unroll
+    for (int bb = 0; bb < kKLSamples; ++bb) acc[bb] += f * ys[k * kKLSamples + bb];
+  }
+#pragma unroll
+  for (int bb = 0; bb < kKLSamples; ++bb)
+    if (b0 + bb < B) theta[(int64_t)(b0 + bb) * P + p] = (TO)(t0 + acc[bb]);
+}
+
+void launch_kl(const void* phi, const double* sqrt_lambda, const double* theta0, const double* Y, int64_t P,
+               int32_t M, int32_t B, void* theta, bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)cdiv(P, kBlock), (unsigned)cdiv(B, kKLSamples));
+  const size_t sh = (size_t)M * kKLSamples * sizeof(double);
+  if (mixed)
+    hipLaunchKernelGGL((k_kl64<float>), grid, dim3(kBlock), sh, s, (const double*)phi, sqrt_lambda, theta0, Y, P, M,
+                       B, (float*)theta);
+  else
+    hipLaunchKernelGGL((k_kl64<double>), grid, dim3(kBlock), sh, s, (const double*)phi, sqrt_lambda, theta0, Y, P,
+                       M, B, (double*)theta);
+}
+
+// ---------------------------------------------------------------------------
+// Shifted rank-1 lattice points mapped to N(0,1): y = Phi^-1(frac(((i z) mod N)/N + shift)).
+__global__ void k_lattice(const int64_t* __restrict__ z, const double* __restrict__ shift, int32_t sdim, int64_t N,
+                          int64_t first, int32_t count, double* __restrict__ Y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)sdim * count) return;
+  const int k = (int)(t % sdim);
+  const int64_t i = first + t / sdim;
+  const int64_t r = (i % N) * (z[k] % N) % N;
+  double x = (double)r / (double)N + shift[k];
+  if (x >= 1.0) x -= 1.0;
+  const double eps = 1.1102230246251565e-16;  // 2^-53
+  x = x < eps ? eps : (x > 1.0 - eps ? 1.0 - eps : x);
+  Y[t] = normcdfinv(x);
+}
+
+void launch_lattice(const int64_t* z, const double* shift, int32_t sdim, int64_t N, int64_t first, int32_t count,
+                    double* Y, hipStream_t s) {
+  const int64_t total = (int64_t)sdim * count;
+  hipLaunchKernelGGL(k_lattice, dim3((unsigned)cdiv(total, kBlock)), dim3(kBlock), 0, s, z, shift, sdim, N, first,
+                     count, Y);
+}
+
+// ---------------------------------------------------------------------------
+// Level difference and FP64 accumulation, one block, fixed order.
+__global__ void k_accumulate(const double* __restrict__ ff, const double* __restrict__ fc, int32_t count,
+                             double* acc) {
+  __shared__ double sh[kBlock / 64];
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < count; i += kBlock) {
+    const double y = ff[i] - (fc != nullptr ? fc[i] : 0.0);
+    s1 += y;
+    s2 += y * y;
+  }
+  s1 = block_sum<kBlock>(s1, sh);
+  s2 = block_sum<kBlock>(s2, sh);
+  if (threadIdx.x == 0) {
+    acc[0] += (double)count;
+    acc[1] += s1;
+    acc[2] += s2;
+  }
+}
+
+void launch_accumulate(const double* ff, const double* fc, int32_t count, double* acc, hipStream_t s) {
+  hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(kBlock), 0, s, ff, fc, count, acc);
+}
+
+}  // namespace mlq
+
+namespace mlq {
+
+// Newton bookkeeping: samples that failed stay frozen; the others start a step.
+__global__ void k_newton_reset(const int32_t* __restrict__ status, int32_t* newton_active, int32_t B) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < B) newton_active[i] = status[i] == MLQ_SAMPLE_OK ? 1 : 0;
+}
+
+__global__ void k_mark_failed(int32_t* status, int32_t* newton_active, int32_t B) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < B && newton_active[i] != 0) {
+    status[i] = MLQ_SAMPLE_NOCONV;
+    newton_active[i] = 0;
+  }
+}
+
+void launch_newton_reset(const Work& w, int32_t B, hipStream_t s) {
+  hipLaunchKernelGGL(k_newton_reset, dim3((unsigned)cdiv(B, kBlock)), dim3(kBlock), 0, s, w.status,
+                     w.newton_active, B);
+}
+
+void launch_mark_failed(const Work& w, int32_t B, hipStream_t s) {
+  hipLaunchKernelGGL(k_mark_failed, dim3((unsigned)cdiv(B, kBlock)), dim3(kBlock), 0, s, w.status,
+                     w.newton_active, B);
+}
+
+}  // namespace mlq

@@ -1,0 +1,260 @@
+"""Thin ctypes binding of libmlq.so (include/mlq.h).
+
+Argument marshalling only: every step of the solve runs in the HIP kernels of
+the library.  Device buffers are torch tensors on the current HIP device;
+torch provides memory and streams.  Importing this module fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmlq.so")
+
+MLQ_OK, MLQ_EINVAL, MLQ_EHIP, MLQ_ENOCONV, MLQ_ESIZE, MLQ_ESTATE = 0, -1, -2, -3, -4, -5
+MLQ_FP64, MLQ_MIXED = 0, 1
+MLQ_QOI_MEAN_U_FINAL, MLQ_QOI_MEAN_ACT_TIME = 0, 1
+MLQ_EST_MC, MLQ_EST_MLMC, MLQ_EST_MLQMC, MLQ_EST_COMBINATION = 0, 1, 2, 3
+
+EXPORTED = [
+    "mlq_level_bytes", "mlq_create_level", "mlq_destroy_level", "mlq_level_sizes", "mlq_workspace_bytes",
+    "mlq_sample_fields", "mlq_solve_batch", "mlq_solve_batch_ex", "mlq_apply", "mlq_check",
+    "mlq_lattice_normals", "mlq_cbc", "mlq_accumulate", "mlq_estimate", "mlq_last_error",
+]
+
+
+class MlqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mlq error {code}: {msg}")
+        self.code = code
+
+
+class LevelDesc(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("mesh_kind", C.c_int32),
+        ("n", C.c_int64 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+        ("n_steps", C.c_int32), ("t_end", C.c_double),
+        ("alpha", C.c_double), ("u_rest", C.c_double), ("u_th", C.c_double), ("u_peak", C.c_double),
+        ("sigma_l", C.c_double), ("sigma_t", C.c_double),
+        ("stim_lo", C.c_double * 3), ("stim_hi", C.c_double * 3),
+        ("stim_t_on", C.c_double), ("stim_t_off", C.c_double), ("stim_amp", C.c_double),
+        ("n_modes", C.c_int32),
+        ("phi", C.POINTER(C.c_double)), ("sqrt_lambda", C.POINTER(C.c_double)), ("theta0", C.POINTER(C.c_double)),
+        ("prec", C.c_int32), ("qoi", C.c_int32),
+        ("newton_tol", C.c_double), ("inner_tol", C.c_double),
+        ("max_newton", C.c_int32), ("max_inner", C.c_int32), ("max_batch", C.c_int32),
+    ]
+
+
+class EstimateOut(C.Structure):
+    _fields_ = [("estimate", C.c_double), ("rmse", C.c_double), ("n_levels", C.c_int32),
+                ("level_mean", C.c_double * 16), ("level_var", C.c_double * 16)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(python paper_2105_02007_amd/build.py)")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, I64, D, VP = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_void_p
+    sig = {
+        "mlq_level_bytes": [C.POINTER(LevelDesc), C.POINTER(C.c_size_t)],
+        "mlq_create_level": [C.POINTER(LevelDesc), VP, C.c_size_t, VP, C.POINTER(VP)],
+        "mlq_level_sizes": [VP, C.POINTER(I64), C.POINTER(I64)],
+        "mlq_workspace_bytes": [VP, I32, C.POINTER(C.c_size_t)],
+        "mlq_sample_fields": [VP, VP, I32, VP, VP],
+        "mlq_solve_batch": [VP, VP, I32, VP, C.c_size_t, VP, VP, VP, VP],
+        "mlq_solve_batch_ex": [VP, VP, I32, I32, VP, C.c_size_t, VP, VP, VP, VP, VP, VP],
+        "mlq_apply": [VP, VP, I32, VP, VP, VP, VP, C.c_size_t, VP],
+        "mlq_check": [VP, I32],
+        "mlq_lattice_normals": [VP, VP, I32, I64, I64, I32, VP, VP],
+        "mlq_cbc": [I64, I32, VP, VP],
+        "mlq_accumulate": [VP, VP, I32, VP, VP],
+        "mlq_estimate": [I32, I32, I32, VP, VP, VP, C.POINTER(EstimateOut)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.mlq_destroy_level.argtypes = [VP]
+    lib.mlq_destroy_level.restype = None
+    lib.mlq_last_error.argtypes = []
+    lib.mlq_last_error.restype = C.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def check(code):
+    if code != MLQ_OK:
+        raise MlqError(code, lib.mlq_last_error().decode())
+    return code
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_desc(level: dict, phys: dict, *, n_modes=0, phi=None, sqrt_lambda=None, theta0=None,
+              prec=MLQ_FP64, qoi=MLQ_QOI_MEAN_U_FINAL, newton_tol=1e-13, inner_tol=1e-6,
+              max_newton=20, max_inner=30, max_batch=1):
+    """Fills an mlq_level_desc from a workload level and physics dict.  Returns (desc, keepalive)."""
+    d = LevelDesc()
+    dim = level["dim"]
+    d.dim, d.mesh_kind = dim, 0
+    for a in range(3):
+        d.n[a] = level["n"][a] if a < dim else 1
+        d.lo[a] = level["lo"][a] if a < dim else 0.0
+        d.hi[a] = level["hi"][a] if a < dim else 1.0
+        d.stim_lo[a] = phys["stim_lo"][a] if a < dim else 0.0
+        d.stim_hi[a] = phys["stim_hi"][a] if a < dim else 1.0
+    d.n_steps, d.t_end = int(level["n_steps"]), float(phys["t_end"])
+    for k in ("alpha", "u_rest", "u_th", "u_peak", "sigma_l", "sigma_t", "stim_t_on", "stim_t_off", "stim_amp"):
+        setattr(d, k, float(phys[k]))
+    keep = []
+    d.n_modes = int(n_modes)
+    if n_modes > 0:
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        sl = np.ascontiguousarray(sqrt_lambda, dtype=np.float64)
+        keep += [phi, sl]
+        d.phi = phi.ctypes.data_as(C.POINTER(C.c_double))
+        d.sqrt_lambda = sl.ctypes.data_as(C.POINTER(C.c_double))
+    if theta0 is not None:
+        t0 = np.ascontiguousarray(theta0, dtype=np.float64)
+        keep.append(t0)
+        d.theta0 = t0.ctypes.data_as(C.POINTER(C.c_double))
+    d.prec, d.qoi = int(prec), int(qoi)
+    d.newton_tol, d.inner_tol = float(newton_tol), float(inner_tol)
+    d.max_newton, d.max_inner, d.max_batch = int(max_newton), int(max_inner), int(max_batch)
+    return d, keep
+
+
+class Level:
+    """One level: descriptor, device blob, level handle.  Device memory comes from torch."""
+
+    def __init__(self, desc: LevelDesc, keep=None, device="cuda"):
+        import torch
+        self.desc, self._keep = desc, keep
+        nbytes = C.c_size_t()
+        check(lib.mlq_level_bytes(C.byref(desc), C.byref(nbytes)))
+        self.blob = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        check(lib.mlq_create_level(C.byref(desc), _ptr(self.blob), nbytes.value, _stream(), C.byref(h)))
+        self.handle = h
+        nn, ne = C.c_int64(), C.c_int64()
+        check(lib.mlq_level_sizes(self.handle, C.byref(nn), C.byref(ne)))
+        self.n_nodes, self.n_elems = int(nn.value), int(ne.value)
+        self.mixed = desc.prec == MLQ_MIXED
+        self.device = device
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib.mlq_destroy_level(h)
+            self.handle = None
+
+    @property
+    def theta_dtype(self):
+        import torch
+        return torch.float32 if self.mixed else torch.float64
+
+    def workspace(self, batch):
+        import torch
+        nbytes = C.c_size_t()
+        check(lib.mlq_workspace_bytes(self.handle, int(batch), C.byref(nbytes)))
+        if self._ws is None or self._ws.numel() < nbytes.value:
+            self._ws = None
+            self._ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        return self._ws, int(nbytes.value)
+
+    def sample_fields(self, Y, theta=None):
+        """Y: (M, B) FP64 device tensor, column b = sample b (stored as B x M row-major)."""
+        import torch
+        B = Y.shape[1]
+        Yc = Y.t().contiguous()  # column-major M x B == row-major B x M
+        if theta is None:
+            theta = torch.empty((B, self.n_elems), dtype=self.theta_dtype, device=self.device)
+        check(lib.mlq_sample_fields(self.handle, _ptr(Yc), int(B), _ptr(theta), _stream()))
+        return theta
+
+    def solve(self, theta, n_steps=None, want_state=False):
+        import torch
+        B = theta.shape[0]
+        ws, nbytes = self.workspace(B)
+        qoi = torch.empty(B, dtype=torch.float64, device=self.device)
+        status = torch.empty(B, dtype=torch.int32, device=self.device)
+        iters = torch.empty((B, 2), dtype=torch.int64, device=self.device)
+        u = act = None
+        if want_state:
+            u = torch.empty((B, self.n_nodes), dtype=torch.float64, device=self.device)
+            act = torch.empty((B, self.n_nodes), dtype=torch.float64, device=self.device)
+        steps = self.desc.n_steps if n_steps is None else int(n_steps)
+        code = lib.mlq_solve_batch_ex(self.handle, _ptr(theta), int(B), steps, _ptr(ws), nbytes, _ptr(qoi),
+                                      _ptr(status), _ptr(iters), _ptr(u), _ptr(act), _stream())
+        if code not in (MLQ_OK, MLQ_ENOCONV):
+            check(code)
+        return dict(qoi=qoi, status=status, iters=iters, u=u, act=act, code=code)
+
+    def apply(self, theta, x, d, y=None):
+        import torch
+        B = theta.shape[0]
+        ws, nbytes = self.workspace(B)
+        if y is None:
+            y = torch.empty_like(x)
+        check(lib.mlq_apply(self.handle, _ptr(theta), int(B), _ptr(x), _ptr(d), _ptr(y), _ptr(ws), nbytes,
+                            _stream()))
+        return y
+
+
+def lattice_normals(z, shift, N, first, count, device="cuda"):
+    """(s, count) FP64 device tensor of shifted-lattice normals."""
+    import torch
+    zd = torch.as_tensor(np.asarray(z, dtype=np.int64), device=device)
+    sd = torch.as_tensor(np.asarray(shift, dtype=np.float64), device=device)
+    s = zd.numel()
+    Y = torch.empty((count, s), dtype=torch.float64, device=device)  # column-major s x count
+    check(lib.mlq_lattice_normals(_ptr(zd), _ptr(sd), int(s), int(N), int(first), int(count), _ptr(Y), _stream()))
+    return Y.t()
+
+
+def cbc(N, s, gamma):
+    g = np.ascontiguousarray(gamma, dtype=np.float64)
+    z = np.zeros(s, dtype=np.int64)
+    check(lib.mlq_cbc(int(N), int(s), g.ctypes.data_as(C.c_void_p), z.ctypes.data_as(C.c_void_p)))
+    return z
+
+
+def accumulate(f_fine, f_coarse, acc):
+    n = f_fine.numel()
+    check(lib.mlq_accumulate(_ptr(f_fine), _ptr(f_coarse), int(n), _ptr(acc), _stream()))
+    return acc
+
+
+def estimate(kind, f_fine, f_coarse=None, n_per_level=None, n_shifts=1):
+    """Host estimator over lists of numpy arrays (per level)."""
+    L = len(f_fine)
+    ff = [np.ascontiguousarray(a, dtype=np.float64) for a in f_fine]
+    fc = [np.ascontiguousarray(a, dtype=np.float64) if a is not None else None
+          for a in (f_coarse or [None] * L)]
+    if n_per_level is None:
+        n_per_level = [a.size // n_shifts for a in ff]
+    npl = np.ascontiguousarray(n_per_level, dtype=np.int64)
+    pf = (C.c_void_p * L)(*[a.ctypes.data for a in ff])
+    pc = (C.c_void_p * L)(*[(a.ctypes.data if a is not None else None) for a in fc])
+    out = EstimateOut()
+    check(lib.mlq_estimate(int(kind), L, int(n_shifts), npl.ctypes.data_as(C.c_void_p), C.cast(pf, C.c_void_p),
+                           C.cast(pc, C.c_void_p), C.byref(out)))
+    return dict(estimate=out.estimate, rmse=out.rmse, level_mean=list(out.level_mean[:L]),
+                level_var=list(out.level_var[:L]))

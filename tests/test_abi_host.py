@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol of include/mlq.h, validates descriptors, and its host-only routines
+(lattice construction, estimators) agree with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def mlq():
+    lib = os.path.join(ROOT, "paper_2105_02007_amd", "libmlq.so")
+    if not os.path.exists(lib):
+        pytest.fail("libmlq.so is not built: run __graft_entry__.build()")
+    from paper_2105_02007_amd import mlq as m
+    return m
+
+
+def test_exports_every_declared_symbol(mlq):
+    header = open(os.path.join(ROOT, "include", "mlq.h")).read()
+    declared = set(re.findall(r"\b(mlq_[a-z_0-9]+)\s*\(", header))
+    assert declared >= set(mlq.EXPORTED) and len(declared) >= 15
+    for name in declared:
+        assert hasattr(mlq.lib, name), name
+
+
+def _desc(mlq, **kw):
+    lv = dict(dim=3, n=[9, 9, 9], lo=[0, 0, 0], hi=[1, 1, 1], n_steps=32)
+    lv.update({k: v for k, v in kw.items() if k in lv})
+    phys = W.physics(3)
+    phys.update({k: v for k, v in kw.items() if k in phys})
+    rest = {k: v for k, v in kw.items() if k not in lv and k not in phys}
+    return mlq.make_desc(lv, phys, **rest)
+
+
+def _bytes(mlq, d):
+    import ctypes as C
+    n = C.c_size_t()
+    return mlq.lib.mlq_level_bytes(C.byref(d), C.byref(n)), n.value
+
+
+def test_descriptor_validation(mlq):
+    d, _ = _desc(mlq)
+    code, nbytes = _bytes(mlq, d)
+    assert code == 0 and nbytes >= 2 * 729 * 8
+    for bad in (dict(dim=4), dict(n_steps=0), dict(sigma_l=-1.0), dict(max_inner=1000), dict(prec=7),
+                dict(qoi=5), dict(newton_tol=0.0), dict(max_batch=0)):
+        d, _ = _desc(mlq, **bad)
+        assert _bytes(mlq, d)[0] == mlq.MLQ_EINVAL, bad
+    # dt * |min I_ion'| >= 1 admits several roots of the step equation
+    d, _ = _desc(mlq, n_steps=1, t_end=0.25)
+    assert _bytes(mlq, d)[0] == mlq.MLQ_EINVAL
+    assert b"several roots" in mlq.lib.mlq_last_error()
+    d, _ = _desc(mlq, n_steps=2, t_end=0.25)
+    assert _bytes(mlq, d)[0] == 0
+
+
+@pytest.mark.parametrize("N,s", [(1, 4), (4, 20), (16, 128), (64, 32), (256, 128)])
+def test_cbc_bit_exact_with_oracle(mlq, N, s):
+    from oracle import qmc
+    gamma = 1.0 / (1.0 + np.arange(s)) ** 1.5
+    assert np.array_equal(mlq.cbc(N, s, gamma), qmc.cbc(N, s, gamma))
+
+
+def test_estimators_match_oracle(mlq):
+    from oracle import estimators as E
+    rng = np.random.default_rng(3)
+    f = rng.normal(size=50)
+    r = mlq.estimate(mlq.MLQ_EST_MC, [f])
+    m, s = E.single_level(list(f))
+    assert np.isclose(r["estimate"], m, rtol=1e-14) and np.isclose(r["rmse"], s, rtol=1e-13)
+    ff = [rng.normal(size=n) for n in (64, 16, 4)]
+    fc = [None] + [rng.normal(size=n) for n in (16, 4)]
+    r = mlq.estimate(mlq.MLQ_EST_MLMC, ff, fc)
+    est, rmse, means, vars_ = E.standard_ml([list(a) for a in ff], [None] + [list(a) for a in fc[1:]])
+    assert np.isclose(r["estimate"], est, rtol=1e-14) and np.isclose(r["rmse"], rmse, rtol=1e-13)
+    assert np.allclose(r["level_var"], vars_, rtol=1e-13)
+    S = 5
+    ff = [rng.normal(size=S * n) for n in (8, 2)]
+    fc = [None, rng.normal(size=S * 2)]
+    r = mlq.estimate(mlq.MLQ_EST_MLQMC, ff, fc, n_per_level=[8, 2], n_shifts=S)
+    of = [[list(a[s * n:(s + 1) * n]) for s in range(S)] for a, n in zip(ff, (8, 2))]
+    oc = [None, [list(fc[1][s * 2:(s + 1) * 2]) for s in range(S)]]
+    est, rmse, _ = E.standard_mlqmc(of, [[None] * S, oc[1]])
+    assert np.isclose(r["estimate"], est, rtol=1e-14) and np.isclose(r["rmse"], rmse, rtol=1e-13)
+    npts = [4, 8, 16]
+    F = [rng.normal(size=16) for _ in range(3)]
+    fj = [F[j][:npts[2 - j]] for j in range(3)]
+    r = mlq.estimate(mlq.MLQ_EST_COMBINATION, fj, n_per_level=npts)
+    assert np.isclose(r["estimate"], E.combination(fj, npts), rtol=1e-14)
