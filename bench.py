@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Throughput of the batched space-time solves on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic input: the
+configured estimator end to end (sample points, KL synthesis, Crank-Nicolson /
+Newton / GMRES solves on every level and the coarse partner level, QoIs,
+level differences, estimator).  The KL basis and level set-up are one-time
+set-up outside the timed region; Monte Carlo normals are inputs and are
+resident in HBM before timing starts.
+
+Prints one JSON line (rank 0).  Metric: space-time DOF x inner iterations per
+second = sum over samples, steps and Newton iterations of n_l * (GMRES
+iterations), over wall time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "space-time DOF·iters/s per GPU + MLQMC time-to-RMSE, mixed vs FP64"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per node-sample of the Jacobian apply: x, d, y and the two
+# element coefficients (one element per node), in the inner precision
+APPLY_BYTES = {0: 5 * 8, 1: 5 * 4}
+
+WORKLOAD_TEXT = {
+    "c1": "2D unit square Q1 33x33, 64 steps, 16-mode KL (l=0.2, s=0.3 rad), 16 MC samples, mean u(T), FP64",
+    "c2": "3D unit cube Q1 9^3..65^3 nested, 32..256 steps, 64-mode KL (l=0.1, s=0.3 rad) on 65^3, "
+          "MLMC 2048/512/128/32 samples, mean activation time, FP64",
+    "c3": "3D unit cube Q1 129^3, 512 steps, 128-mode KL, 64 rank-1 lattice points x 1 shift, "
+          "mean activation time, FP32 inner + FP64 Newton residual",
+    "c4": "3D unit cube Q1 9^3..129^3 nested, 32..512 steps, 128-mode KL, MLQMC 16 shifts x 256/64/16/4/1, "
+          "mean activation time",
+}
+
+
+def cpu_baseline(cfg, budget_s):
+    """The oracle on a bounded sample of the same workload (level 0 and 1 samples of its first two levels)."""
+    import numpy as np
+
+    import workloads as W
+    from oracle import run
+    meshes = run.level_meshes(cfg)
+    B = run.kl_basis(cfg, meshes, max_rank=2 * cfg["kl"]["n_modes"])
+    M = cfg["kl"]["n_modes"]
+    phys = cfg["physics"]
+    dof_iters, st_dof, n_solves = 0.0, 0.0, 0
+    t0 = time.perf_counter()
+    plan = []
+    for l in range(min(2, len(meshes))):
+        plan += [(l, i) for i in range(8 if l == 0 else 1)]
+    done = []
+    for l, i in plan:
+        if time.perf_counter() - t0 > budget_s:
+            break
+        Y = W.mc_normals(cfg["seed"], l, i + 1, M)[:, i:i + 1]
+        th = run.sample_theta(B["phi"][l], B["sqrt_lam"], Y)[0]
+        out = run.solve_theta(meshes[l], th, phys, cfg["levels"][l]["n_steps"])
+        n = meshes[l].n_nodes
+        dof_iters += n * out["lin_iters"]
+        st_dof += n * cfg["levels"][l]["n_steps"]
+        n_solves += 1
+        done.append(l)
+    el = time.perf_counter() - t0
+    counts = {l: done.count(l) for l in sorted(set(done))}
+    desc = ", ".join(f"{c} sample(s) of level {l} ({'x'.join(map(str, cfg['levels'][l]['n']))} nodes, "
+                     f"{cfg['levels'][l]['n_steps']} steps)" for l, c in counts.items())
+    return dict(value=dof_iters / el, unit="DOF·iters/s", cores=1, kind="oracle",
+                sample=f"{desc}; single process; a direct sparse solve counts as one iteration, "
+                       f"GMRES iterations otherwise; KL set-up excluded; {el:.1f} s",
+                st_dof_per_s=st_dof / el, seconds=el)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--prec", choices=["fp64", "mixed"], default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--breakdown", action="store_true", help="extra untimed pass timing every kernel class")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(samples would shard across GPUs with one all-reduce of the estimator sums).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2105_02007_amd import mlq
+    from paper_2105_02007_amd.driver import ConfigRunner
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = "cuda:0"
+    cfg = W.config(args.config)
+    prec = cfg["prec"] if args.prec is None else (W.PREC_FP64 if args.prec == "fp64" else W.PREC_MIXED)
+    t_setup = time.perf_counter()
+    runner = ConfigRunner(cfg, prec=prec, device=dev)
+    t_setup = time.perf_counter() - t_setup
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    log(f"set-up done in {t_setup:.1f} s (KL rank {runner.kl_rank})")
+    runner.log = log
+    samp = cfg["sampling"]
+    M = cfg["kl"]["n_modes"]
+    kind = samp["kind"]
+    if kind in ("mc", "mlmc"):
+        Ys = [torch.as_tensor(W.mc_normals(cfg["seed"], l, n, M), device=dev)
+              for l, n in enumerate(samp["n_per_level"])]
+        if kind == "mc":
+            step = lambda: runner.run_mc(Ys[0])
+        else:
+            step = lambda: runner.run_mlmc(Ys)
+    else:
+        S = samp.get("n_shifts", 1)
+        shifts = [W.lattice_shifts(cfg["seed"], l, S, M) for l in range(len(cfg["levels"]))]
+        step = lambda: runner.run_mlqmc(shifts)
+
+    for i in range(args.warmup):
+        step()
+        log(f"warmup {i} done")
+    for L in runner.levels:
+        L.timing_enable(("apply",))
+        L.timing_read(reset=True)
+    runner.reset_counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = None
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    dof_iters, st_dof = runner.dof_iters, runner.st_dof
+
+    # dominant kernel: the Jacobian apply of the finest level (most of the bytes)
+    apply_ms = apply_units = 0.0
+    apply_launches = 0
+    per_level = []
+    for l, L in enumerate(runner.levels):
+        t = L.timing_read(reset=True)["apply"]
+        apply_ms += t["ms"]
+        apply_units += t["units"]
+        apply_launches += t["launches"]
+        per_level.append(dict(level=l, nodes=L.n_nodes, apply_ms=round(t["ms"], 3), apply_launches=t["launches"]))
+        L.timing_enable(())
+    bpu = APPLY_BYTES[prec]
+    achieved = (apply_units * bpu) / (apply_ms * 1e-3) / 1e9 if apply_ms > 0 else 0.0
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    kernel="k_apply (Jacobian apply)", bytes_per_node_sample=bpu,
+                    avg_launch_us=round(1e3 * apply_ms / max(apply_launches, 1), 2),
+                    launches=apply_launches)
+
+    breakdown = None
+    if args.breakdown:
+        for L in runner.levels:
+            L.timing_enable(tuple(mlq.KERNEL_CLASSES))
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - tb
+        tot = {}
+        for L in runner.levels:
+            for c, v in L.timing_read(reset=True).items():
+                tot[c] = tot.get(c, 0.0) + v["ms"]
+            L.timing_enable(())
+        breakdown = dict(wall_ms=round(tb * 1e3, 1), kernel_ms={c: round(v, 2) for c, v in tot.items()})
+
+    line = {
+        "metric": METRIC, "value": dof_iters / el, "unit": "DOF·iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == W.PREC_FP64 else "f32+f64",
+        "data": "synthetic (seeded KL fibre-angle fields, MC normals / rank-1 lattice points)",
+        "config": {"workload": f"{args.config}: {WORKLOAD_TEXT[args.config]}", "levels": len(cfg["levels"]),
+                   "samples_per_level": samp["n_per_level"], "n_shifts": samp.get("n_shifts", 1),
+                   "parallelism": "single GPU, samples batched per level"},
+        "st_dof_per_s": st_dof / el,
+        "estimate": res["estimate"], "rmse_est": res["rmse"],
+        "level_means": res["level_mean"],
+        "kl": {"rank": runner.kl_rank, "trace_resid": runner.kl_resid},
+        "setup_s": round(t_setup, 2),
+        "roofline": roofline,
+        "apply_per_level": per_level,
+    }
+    if breakdown:
+        line["breakdown"] = breakdown
+    runner.log = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -64,7 +64,8 @@ typedef enum { MLQ_MESH_Q1_BOX = 0 } mlq_mesh_kind;
 enum { MLQ_SAMPLE_OK = 0, MLQ_SAMPLE_NOCONV = 1, MLQ_SAMPLE_NAN = 2 };
 
 /* Description of one level (Section 3.1: mesh, time grid; Section 5.1: model
- * constants).  All pointers are host pointers, read during mlq_create_level. */
+ * constants).  The arrays are read during mlq_create_level; they are host
+ * pointers unless arrays_on_device is 1. */
 typedef struct {
   int32_t dim;        /* 2 or 3 */
   int32_t mesh_kind;  /* MLQ_MESH_Q1_BOX */
@@ -88,6 +89,7 @@ typedef struct {
   int32_t max_newton;                 /* Newton iterations per step */
   int32_t max_inner;                  /* GMRES iterations per Newton step (<= 64) */
   int32_t max_batch;                  /* largest batch used with this level (<= 65535) */
+  int32_t arrays_on_device;           /* 1: phi, sqrt_lambda, theta0 are device pointers */
 } mlq_level_desc;
 
 typedef struct mlq_level mlq_level; /* opaque */
@@ -192,6 +194,68 @@ typedef struct {
 mlq_status mlq_estimate(int32_t kind, int32_t n_levels, int32_t n_shifts, const int64_t* n_per_level,
                         const double* const* f_fine, const double* const* f_coarse,
                         mlq_estimate_out* out);
+
+/* ---- KL basis set-up (Section 2.3; element-midpoint transfer of Section 4) ----
+ * Covariance C(x, x') = std_dev^2 exp(-|x - x'|_2 / corr_len) on the nodes of a
+ * uniform Q1 box (normally the finest level).  eq. (algEig) is reduced by a
+ * pivoted Cholesky factor C ~ L L^T (largest remaining diagonal first, lowest
+ * index on ties; stops at rank max_rank, or once the rank is >= n_modes and
+ * trace(C - L L^T) <= eps trace(C)) to eq. (redEig), L^T M L v~ = lambda v~. */
+typedef struct {
+  int32_t dim;          /* 2 or 3 */
+  int64_t n[3];         /* nodes per axis of the KL grid */
+  double lo[3], hi[3];
+  double std_dev;       /* s */
+  double corr_len;      /* l */
+  int32_t n_modes;      /* M <= 1024 */
+  int32_t max_rank;     /* n_modes <= max_rank <= min(4096, nodes) */
+  double eps;           /* relative trace tolerance of the pivoted Cholesky */
+} mlq_kl_desc;
+
+/* Device workspace bytes of mlq_kl_modes (dominated by two n x max_rank FP64 arrays). */
+mlq_status mlq_kl_workspace_bytes(const mlq_kl_desc* kd, size_t* ws_bytes);
+
+/* Largest n_modes eigenpairs: lambda_host (M, descending) and the M-orthonormal
+ * modes psi_dev (n x M column-major FP64 device array, psi_k^T M psi_k = 1, entry of
+ * largest magnitude positive).  rank_out: Cholesky rank used; resid_out:
+ * trace(C - L L^T) / trace(C).  Synchronises the stream. */
+mlq_status mlq_kl_modes(const mlq_kl_desc* kd, void* ws_dev, size_t ws_bytes, double* lambda_host,
+                        double* psi_dev, int32_t* rank_out, double* resid_out, void* hip_stream);
+
+/* Element-midpoint transfer: phi_dev (P x M row-major FP64, device) = the Q1
+ * interpolant of the KL-grid modes at the element centres of the Q1 box level
+ * (level_n nodes per axis on [level_lo, level_hi]).  Enqueues only. */
+mlq_status mlq_kl_transfer(const mlq_kl_desc* kd, const double* psi_dev, const int64_t* level_n,
+                           const double* level_lo, const double* level_hi, double* phi_dev, void* hip_stream);
+
+/* ---- kernel timing (HIP events on the solve's stream) ----
+ * Kernel classes of mlq_solve_batch; `units` counts node-samples processed. */
+enum {
+  MLQ_K_APPLY = 0,    /* Jacobian apply inside GMRES */
+  MLQ_K_RESIDUAL = 1, /* nonlinear residual + ionic terms */
+  MLQ_K_RHS = 2,      /* right-hand side of a step */
+  MLQ_K_PRECOND = 3,  /* preconditioner */
+  MLQ_K_DOTS = 4,     /* Gram-Schmidt projections (+ their final sums) */
+  MLQ_K_ORTH = 5,     /* Gram-Schmidt update + norm */
+  MLQ_K_SMALL = 6,    /* per-sample scalar kernels (checks, Givens, counts) */
+  MLQ_K_UPDATE = 7,   /* Newton update */
+  MLQ_K_QOI = 8,      /* activation tracking and QoI reductions */
+  MLQ_K_CLASSES = 9
+};
+
+typedef struct {
+  double ms[16];        /* summed kernel time per class */
+  int64_t launches[16]; /* launches per class */
+  double units[16];     /* node-samples processed per class */
+} mlq_timing;
+
+/* Times the kernel classes whose bit is set in kernel_mask (0 turns timing off)
+ * during later mlq_solve_batch calls on this level.  Each timed launch is
+ * bracketed by two events on the solve's stream. */
+mlq_status mlq_timing_enable(mlq_level* level, uint32_t kernel_mask);
+
+/* Reads (and with reset != 0 clears) the accumulated timings of the level. */
+mlq_status mlq_timing_read(mlq_level* level, mlq_timing* out, int32_t reset);
 
 /* Thread-local message describing the last error. */
 const char* mlq_last_error(void);

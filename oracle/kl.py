@@ -14,7 +14,8 @@ Readings (where the paper leaves a choice):
 * kernel C(x, x') = s^2 exp(-|x - x'|_2 / l) (exponential, Euclidean distance);
 * y_k standard normal (the workloads draw Gaussian coordinates);
 * pivoted Cholesky stops when trace(C - L L^T) <= eps trace(C) or at rank r_max;
-* sign of each mode: its entry of largest magnitude is positive (first on ties);
+* sign of each mode: its first entry of largest magnitude is positive (entries
+  within a relative 1e-9 of the maximum count as ties);
 * fine -> coarse transfer (Section 4, element midpoint rule): a level-l element
   takes the value of the finest-mesh nodal interpolant at its centre.
 """
@@ -55,9 +56,16 @@ def pivoted_cholesky(nodes, std, corr_len, max_rank, eps=0.0):
 
 
 def fix_signs(V):
+    """Make the first entry of (numerically) largest magnitude of each column positive.
+
+    Symmetric meshes produce modes whose extreme entries come in +/- pairs of
+    equal magnitude; entries within a relative 1e-9 of the maximum count as tied
+    and the lowest index decides.
+    """
     V = V.copy()
     for k in range(V.shape[1]):
-        j = int(np.argmax(np.abs(V[:, k])))
+        a = np.abs(V[:, k])
+        j = int(np.argmax(a >= a.max() * (1.0 - 1e-9)))
         if V[j, k] < 0:
             V[:, k] = -V[:, k]
     return V

@@ -49,6 +49,7 @@ class Problem:
         self.F_box = fem.box_load(mesh, p["stim_lo"], p["stim_hi"])
         self.source = source  # optional callable t -> load vector (manufactured solutions)
         self.w = fem.node_weights(self.M)
+        self.lin_iters = 0  # linear-solver iterations (a direct solve counts as one)
 
     def load(self, t):
         F = stim_rate(t, self.p) * self.F_box
@@ -69,10 +70,16 @@ class Problem:
     def linsolve(self, J, r):
         n = r.shape[0]
         if n <= DIRECT_MAX_NODES:
+            self.lin_iters += 1
             return spla.splu(J).solve(r)
         dinv = 1.0 / J.diagonal()
         pre = spla.LinearOperator(J.shape, matvec=lambda v: dinv * v)
-        x, _ = spla.gmres(J, r, M=pre, rtol=1e-14, atol=0.0, restart=200, maxiter=5)
+
+        def count(_):
+            self.lin_iters += 1
+
+        x, _ = spla.gmres(J, r, M=pre, rtol=1e-14, atol=0.0, restart=200, maxiter=5, callback=count,
+                          callback_type="pr_norm")
         return x  # Newton's own residual test decides convergence
 
 
@@ -127,7 +134,7 @@ def solve(mesh: BoxMesh, G, p, n_steps, tol=1e-13, source=None, keep_all=False, 
     out = dict(u=u_k, act=act, act_censored=act_c, dt=dt, t_stop=t_stop,
                mean_u_final=float(prob.w @ u_k) / vol,
                mean_act=float(prob.w @ act_c) / vol,
-               newton_iters=np.array(newton_its), w=prob.w)
+               newton_iters=np.array(newton_its), lin_iters=prob.lin_iters, w=prob.w)
     if keep_all:
         out["history"] = np.array(history)
     return out

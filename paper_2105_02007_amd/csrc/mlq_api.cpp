@@ -73,19 +73,80 @@ struct mlq_level {
   double* theta0 = nullptr;
   double* fbox = nullptr;
   double* wts = nullptr;
+  void* tri = nullptr;  // 1 / pivots of tridiag(1, 4, 1) per axis, [3][nmax], inner precision
+  int nmax = 0;
   // pinned host flags
   int32_t* host_flags = nullptr;
+  // kernel timing
+  uint32_t tmask = 0;
+  mlq_timing tim{};
+  struct Pending {
+    int cls;
+    double units;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> free_events;
 };
 
 namespace {
 
+hipEvent_t take_event(mlq_level* lv) {
+  if (!lv->free_events.empty()) {
+    hipEvent_t e = lv->free_events.back();
+    lv->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events when its class is timed.
+template <typename F>
+void timed(mlq_level* lv, int cls, double units, hipStream_t s, F&& launch) {
+  if (!(lv->tmask & (1u << cls))) {
+    launch();
+    return;
+  }
+  hipEvent_t a = take_event(lv), b = take_event(lv);
+  if (a == nullptr || b == nullptr) {
+    launch();
+    return;
+  }
+  (void)hipEventRecord(a, s);
+  launch();
+  (void)hipEventRecord(b, s);
+  lv->pending.push_back({cls, units, a, b});
+}
+
+// After a stream synchronisation: fold finished event pairs into the totals.
+void harvest(mlq_level* lv) {
+  for (auto& p : lv->pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      lv->tim.ms[p.cls] += ms;
+      lv->tim.launches[p.cls] += 1;
+      lv->tim.units[p.cls] += p.units;
+    }
+    lv->free_events.push_back(p.a);
+    lv->free_events.push_back(p.b);
+  }
+  lv->pending.clear();
+}
+
+}  // namespace
+
+namespace {
+
 struct BlobLayout {
-  size_t phi64, phi32, sl, th0, fbox, wts, total;
+  size_t phi64, phi32, sl, th0, fbox, wts, tri, total;
 };
 
-BlobLayout blob_layout(int64_t P, int64_t M, int64_t nn) {
+BlobLayout blob_layout(int64_t P, int64_t M, int64_t nn, int64_t nmax) {
   BlobLayout L{};
   size_t o = 0;
+  L.tri = o;   o = align256(o + sizeof(double) * 3 * nmax);
   L.phi64 = o; o = align256(o + sizeof(double) * P * M);
   L.phi32 = o; o = align256(o + sizeof(float) * P * M);
   L.sl = o;    o = align256(o + sizeof(double) * M);
@@ -196,7 +257,7 @@ mlq_status mlq_level_bytes(const mlq_level_desc* desc, size_t* level_bytes) {
   if (st != MLQ_OK) return st;
   int64_t nn, P;
   sizes_of(desc, &nn, &P);
-  *level_bytes = blob_layout(P, desc->n_modes, nn).total;
+  *level_bytes = blob_layout(P, desc->n_modes, nn, std::max({desc->n[0], desc->n[1], desc->n[2]})).total;
   return MLQ_OK;
 }
 
@@ -211,7 +272,8 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   int64_t nn, P;
   sizes_of(desc, &nn, &P);
   const int64_t M = desc->n_modes;
-  const BlobLayout L = blob_layout(P, M, nn);
+  const int64_t nmax = std::max({desc->n[0], desc->n[1], desc->n[2]});
+  const BlobLayout L = blob_layout(P, M, nn, nmax);
   if (level_bytes < L.total) return fail(MLQ_ESIZE, "level blob too small: %zu < %zu", level_bytes, L.total);
   hipStream_t s = (hipStream_t)hip_stream;
 
@@ -284,11 +346,42 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   lv->theta0 = (double*)(base + L.th0);
   lv->fbox = (double*)(base + L.fbox);
   lv->wts = (double*)(base + L.wts);
-
-  std::vector<float> phi32((size_t)P * M);
-  for (size_t i = 0; i < phi32.size(); ++i) phi32[i] = (float)desc->phi[i];
-  std::vector<double> th0(P, 0.0);
-  if (desc->theta0 != nullptr) std::memcpy(th0.data(), desc->theta0, sizeof(double) * P);
+  lv->tri = (void*)(base + L.tri);
+  lv->nmax = (int)nmax;
+  // preconditioner tables: pivots of tridiag(1, 4, 1) with 2 at both ends, per axis
+  std::vector<double> tri64(3 * nmax, 0.0);
+  std::vector<float> tri32(3 * nmax, 0.0f);
+  for (int a = 0; a < 3; ++a) {
+    const int64_t n = a < dim ? desc->n[a] : 1;
+    double prev = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      const double diag = (i == 0 || i == n - 1) ? 2.0 : 4.0;
+      const double piv = diag - (i > 0 ? prev : 0.0);
+      prev = 1.0 / piv;
+      tri64[a * nmax + i] = prev;
+      tri32[a * nmax + i] = (float)prev;
+    }
+  }
+  // LDS planes of the preconditioner: x-y and x-z planes of one sample
+  {
+    const size_t ti = lv->mixed ? sizeof(float) : sizeof(double);
+    const size_t plane = ti * (size_t)desc->n[0] * (size_t)std::max(desc->n[1], dim == 3 ? desc->n[2] : 1);
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      delete lv;
+      return fail(MLQ_EHIP, "cannot query the device");
+    }
+    const size_t lim = std::max(prop.sharedMemPerBlock, prop.sharedMemPerBlockOptin);
+    if (plane > lim) {
+      delete lv;
+      return fail(MLQ_EINVAL, "a grid plane (%zu bytes) exceeds the LDS of one workgroup (%zu bytes)", plane, lim);
+    }
+    if (prepare_minv_kernels(plane) != hipSuccess) {
+      delete lv;
+      return fail(MLQ_EHIP, "cannot raise the LDS limit of the preconditioner kernels to %zu bytes", plane);
+    }
+  }
 
   auto cleanup = [&](mlq_status e) {
     if (lv->host_flags) (void)hipHostFree(lv->host_flags);
@@ -296,12 +389,39 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
     return e;
   };
   hipError_t e = hipSuccess;
-  if (M > 0) {
-    e = hipMemcpyAsync(lv->phi64, desc->phi, sizeof(double) * P * M, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(lv->phi32, phi32.data(), sizeof(float) * P * M, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(lv->sqrt_lambda, desc->sqrt_lambda, sizeof(double) * M, hipMemcpyHostToDevice, s);
+  std::vector<float> phi32;
+  std::vector<double> th0;
+  if (desc->arrays_on_device) {
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+    if (M > 0) {
+      e = hipMemcpyAsync(lv->phi64, desc->phi, sizeof(double) * P * M, k, s);
+      if (e == hipSuccess) launch_cast_f32(lv->phi64, lv->phi32, P * M, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(lv->sqrt_lambda, desc->sqrt_lambda, sizeof(double) * M, k, s);
+    }
+    if (e == hipSuccess) {
+      if (desc->theta0 != nullptr)
+        e = hipMemcpyAsync(lv->theta0, desc->theta0, sizeof(double) * P, k, s);
+      else
+        e = hipMemsetAsync(lv->theta0, 0, sizeof(double) * P, s);
+    }
+  } else {
+    phi32.resize((size_t)P * M);
+    for (size_t i = 0; i < phi32.size(); ++i) phi32[i] = (float)desc->phi[i];
+    th0.assign(P, 0.0);
+    if (desc->theta0 != nullptr) std::memcpy(th0.data(), desc->theta0, sizeof(double) * P);
+    if (M > 0) {
+      e = hipMemcpyAsync(lv->phi64, desc->phi, sizeof(double) * P * M, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(lv->phi32, phi32.data(), sizeof(float) * P * M, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(lv->sqrt_lambda, desc->sqrt_lambda, sizeof(double) * M, hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(lv->theta0, th0.data(), sizeof(double) * P, hipMemcpyHostToDevice, s);
   }
-  if (e == hipSuccess) e = hipMemcpyAsync(lv->theta0, th0.data(), sizeof(double) * P, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    if (lv->mixed)
+      e = hipMemcpyAsync(lv->tri, tri32.data(), sizeof(float) * 3 * nmax, hipMemcpyHostToDevice, s);
+    else
+      e = hipMemcpyAsync(lv->tri, tri64.data(), sizeof(double) * 3 * nmax, hipMemcpyHostToDevice, s);
+  }
   if (e == hipSuccess) e = hipMemcpyAsync(lv->fbox, fbox.data(), sizeof(double) * nn, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(lv->wts, wts.data(), sizeof(double) * nn, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -313,8 +433,26 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
 
 void mlq_destroy_level(mlq_level* level) {
   if (level == nullptr) return;
+  for (auto& p : level->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : level->free_events) (void)hipEventDestroy(e);
   if (level->host_flags) (void)hipHostFree(level->host_flags);
   delete level;
+}
+
+mlq_status mlq_timing_enable(mlq_level* level, uint32_t kernel_mask) {
+  if (level == nullptr) return fail(MLQ_EINVAL, "level is NULL");
+  level->tmask = kernel_mask;
+  return MLQ_OK;
+}
+
+mlq_status mlq_timing_read(mlq_level* level, mlq_timing* out, int32_t reset) {
+  if (level == nullptr || out == nullptr) return fail(MLQ_EINVAL, "NULL argument");
+  *out = level->tim;
+  if (reset) level->tim = mlq_timing{};
+  return MLQ_OK;
 }
 
 mlq_status mlq_level_sizes(const mlq_level* level, int64_t* n_nodes, int64_t* n_elems) {
@@ -360,6 +498,7 @@ static mlq_status read_counter(mlq_level* lv, const Work& w, hipStream_t s, int3
   HIP_OK(hipMemcpyAsync(lv->host_flags, w.counter, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   *value = lv->host_flags[0];
+  harvest(lv);
   return MLQ_OK;
 }
 
@@ -386,16 +525,19 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
   HIP_OK(hipGetLastError());
 
   auto rate = [&](double t) { return (d.stim_t_on <= t && t < d.stim_t_off) ? d.stim_amp : 0.0; };
+  const double nn = (double)level->nn;
   for (int32_t k = 0; k < n_steps; ++k) {
     const double t0 = (double)k * dt, t1 = (double)(k + 1) * dt;
     const double load = 0.5 * dt * (rate(t1) + rate(t0));
-    launch_rhs(g, w, level->fbox, load, dt, batch, mixed, s);
+    timed(level, MLQ_K_RHS, nn * batch, s, [&] { launch_rhs(g, w, level->fbox, load, dt, batch, mixed, s); });
     launch_newton_reset(w, batch, s);
+    int32_t active = batch;
     for (int it = 0;; ++it) {
-      launch_residual(g, level->io, w, batch, mixed, s);
-      launch_newton_check(g, w, batch, d.newton_tol, s);
-      launch_count(w.newton_active, batch, w.counter, s);
-      int32_t active = 0;
+      timed(level, MLQ_K_RESIDUAL, nn * active, s, [&] { launch_residual(g, level->io, w, batch, mixed, s); });
+      timed(level, MLQ_K_SMALL, 0.0, s, [&] {
+        launch_newton_check(g, w, batch, d.newton_tol, s);
+        launch_count(w.newton_active, batch, w.counter, s);
+      });
       mlq_status st = read_counter(level, w, s, &active);
       if (st != MLQ_OK) return st;
       if (active == 0) break;
@@ -403,22 +545,28 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
         launch_mark_failed(w, batch, s);
         break;
       }
+      int32_t inner = active;
       for (int j = 0; j < kmax; ++j) {
-        launch_precond(g, w, j, batch, mixed, s);
-        launch_apply_z(g, w, 0.5 * dt, batch, mixed, s);
-        launch_dots(g, w, j, batch, mixed, s);
-        launch_orth(g, w, j, batch, mixed, s);
-        launch_givens(g, w, j, batch, d.inner_tol, s);
-        launch_count(w.inner_active, batch, w.counter, s);
-        int32_t inner = 0;
+        const double units = nn * inner;
+        timed(level, MLQ_K_PRECOND, units, s,
+              [&] { launch_minv_basis(g, w, level->tri, level->nmax, j, batch, mixed, s); });
+        timed(level, MLQ_K_APPLY, units, s, [&] { launch_apply_pk(g, w, j, 0.5 * dt, batch, mixed, s); });
+        timed(level, MLQ_K_DOTS, units, s, [&] { launch_dots(g, w, j, batch, mixed, s); });
+        timed(level, MLQ_K_ORTH, units, s, [&] { launch_orth(g, w, j, batch, mixed, s); });
+        timed(level, MLQ_K_SMALL, 0.0, s, [&] {
+          launch_givens(g, w, j, batch, d.inner_tol, s);
+          launch_count(w.inner_active, batch, w.counter, s);
+        });
         st = read_counter(level, w, s, &inner);
         if (st != MLQ_OK) return st;
         if (inner == 0) break;
       }
-      launch_solve_y(w, batch, s);
-      launch_update(g, w, batch, mixed, s);
+      timed(level, MLQ_K_UPDATE, nn * active, s, [&] {
+        launch_solve_y(w, batch, s);
+        launch_update_pm(g, w, level->tri, level->nmax, batch, mixed, s);
+      });
     }
-    launch_activation(w, level->nn, batch, d.u_th, t0, dt, s);
+    timed(level, MLQ_K_QOI, nn * batch, s, [&] { launch_activation(w, level->nn, batch, d.u_th, t0, dt, s); });
     std::swap(w.uk, w.u);
   }
   launch_qoi(w, level->wts, level->nn, batch, d.qoi, (double)n_steps * dt, level->vol, qoi_dev, s);
@@ -432,6 +580,7 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
   std::vector<int32_t> stat(batch);
   HIP_OK(hipMemcpyAsync(stat.data(), w.status, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
+  harvest(level);
   return mlq_check(stat.data(), batch);
 }
 
@@ -603,6 +752,38 @@ mlq_status mlq_estimate(int32_t kind, int32_t n_levels, int32_t n_shifts, const 
     return MLQ_OK;
   }
   return fail(MLQ_EINVAL, "unknown estimator kind %d", kind);
+}
+
+// ---------------------------------------------------------------------------
+// KL set-up
+mlq_status mlq_kl_workspace_bytes(const mlq_kl_desc* kd, size_t* ws_bytes) {
+  if (ws_bytes == nullptr || kl_validate(kd) != MLQ_OK) return fail(MLQ_EINVAL, "invalid KL descriptor");
+  *ws_bytes = kl_workspace_bytes(kd);
+  return MLQ_OK;
+}
+
+mlq_status mlq_kl_modes(const mlq_kl_desc* kd, void* ws_dev, size_t ws_bytes, double* lambda_host, double* psi_dev,
+                        int32_t* rank_out, double* resid_out, void* hip_stream) {
+  if (kl_validate(kd) != MLQ_OK) return fail(MLQ_EINVAL, "invalid KL descriptor");
+  if (ws_dev == nullptr || lambda_host == nullptr || psi_dev == nullptr) return fail(MLQ_EINVAL, "NULL argument");
+  if (ws_bytes < kl_workspace_bytes(kd)) return fail(MLQ_ESIZE, "KL workspace too small");
+  if (((uintptr_t)ws_dev & 255) != 0) return fail(MLQ_EINVAL, "workspace must be 256-byte aligned");
+  std::string err;
+  mlq_status st = kl_modes(kd, ws_dev, lambda_host, psi_dev, rank_out, resid_out, (hipStream_t)hip_stream, err);
+  if (st != MLQ_OK) return fail(st, "%s", err.c_str());
+  return MLQ_OK;
+}
+
+mlq_status mlq_kl_transfer(const mlq_kl_desc* kd, const double* psi_dev, const int64_t* level_n,
+                           const double* level_lo, const double* level_hi, double* phi_dev, void* hip_stream) {
+  if (kl_validate(kd) != MLQ_OK) return fail(MLQ_EINVAL, "invalid KL descriptor");
+  if (psi_dev == nullptr || level_n == nullptr || level_lo == nullptr || level_hi == nullptr || phi_dev == nullptr)
+    return fail(MLQ_EINVAL, "NULL argument");
+  for (int a = 0; a < kd->dim; ++a)
+    if (level_n[a] < 2 || !(level_hi[a] > level_lo[a])) return fail(MLQ_EINVAL, "invalid level box");
+  mlq_status st = kl_transfer(kd, psi_dev, level_n, level_lo, level_hi, phi_dev, (hipStream_t)hip_stream);
+  if (st != MLQ_OK) return fail(st, "transfer launch failed");
+  return MLQ_OK;
 }
 
 }  // extern "C"

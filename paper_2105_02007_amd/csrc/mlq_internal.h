@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 #include "../../include/mlq.h"
 
@@ -104,5 +105,19 @@ void launch_lattice(const int64_t* z, const double* shift, int32_t sdim, int64_t
 void launch_newton_reset(const Work& w, int32_t B, hipStream_t s);
 void launch_mark_failed(const Work& w, int32_t B, hipStream_t s);
 void launch_accumulate(const double* ff, const double* fc, int32_t count, double* acc, hipStream_t s);
+
+// KL set-up (mlq_kl.hip)
+mlq_status kl_validate(const mlq_kl_desc* kd);
+size_t kl_workspace_bytes(const mlq_kl_desc* kd);
+mlq_status kl_modes(const mlq_kl_desc* kd, void* ws, double* lambda_host, double* psi_dev, int32_t* rank_out,
+                    double* resid_out, hipStream_t s, std::string& err);
+mlq_status kl_transfer(const mlq_kl_desc* kd, const double* psi_dev, const int64_t* level_n, const double* level_lo,
+                       const double* level_hi, double* phi_dev, hipStream_t s);
+void launch_minv_basis(const Geo& g, const Work& w, const void* tri, int nmax, int j, int32_t B, bool mixed,
+                       hipStream_t s);
+void launch_apply_pk(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s);
+void launch_update_pm(const Geo& g, const Work& w, const void* tri, int nmax, int32_t B, bool mixed, hipStream_t s);
+hipError_t prepare_minv_kernels(size_t bytes);
+void launch_cast_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
 }  // namespace mlq

@@ -628,10 +628,12 @@ void launch_givens(const Geo& g, const Work& w, int j, int32_t B, double tol, hi
 // Back substitution R y = g on the rotated Hessenberg matrix; stores y_i inv_eta_i.
 __global__ void k_solve_y(int32_t B, int kmax, const double* __restrict__ H, const double* __restrict__ gv,
                           const double* __restrict__ inv_eta, const int32_t* __restrict__ newton_active,
-                          const int32_t* __restrict__ inner_k, double* y) {
+                          const int32_t* __restrict__ inner_k, double* y, int64_t* iters) {
   const int sb = blockIdx.x * blockDim.x + threadIdx.x;
   if (sb >= B || newton_active[sb] == 0) return;
   const int k = inner_k[sb];
+  iters[2 * sb] += 1;
+  iters[2 * sb + 1] += k;
   const double* Hs = H + (int64_t)sb * (kmax + 1) * kmax;
   const double* gs = gv + (int64_t)sb * (kmax + 1);
   double* ys = y + (int64_t)sb * kmax;
@@ -645,7 +647,7 @@ __global__ void k_solve_y(int32_t B, int kmax, const double* __restrict__ H, con
 
 void launch_solve_y(const Work& w, int32_t B, hipStream_t s) {
   hipLaunchKernelGGL(k_solve_y, dim3((unsigned)cdiv(B, 64)), dim3(64), 0, s, B, w.kmax, w.H, w.g, w.inv_eta,
-                     w.newton_active, w.inner_k, w.y);
+                     w.newton_active, w.inner_k, w.y, w.iters);
 }
 
 // Newton update u += P^-1 (sum_i y_i v_i) (right preconditioning), FP64 accumulate.
@@ -661,10 +663,7 @@ __global__ __launch_bounds__(kBlock) void k_update(Geo g, const T* __restrict__ 
   for (int i = threadIdx.x; i < k; i += kBlock) c[i] = y[(int64_t)sb * kmax + i];
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    iters[2 * sb] += 1;
-    iters[2 * sb + 1] += k;
-  }
+  (void)iters;
   if (i >= g.nn) return;
   int ix, iy, iz;
   node_xyz(i, g, ix, iy, iz);
@@ -843,6 +842,257 @@ void launch_newton_reset(const Work& w, int32_t B, hipStream_t s) {
 void launch_mark_failed(const Work& w, int32_t B, hipStream_t s) {
   hipLaunchKernelGGL(k_mark_failed, dim3((unsigned)cdiv(B, kBlock)), dim3(kBlock), 0, s, w.status,
                      w.newton_active, B);
+}
+
+}  // namespace mlq
+
+namespace mlq {
+
+__global__ void k_cast_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
+void launch_cast_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_cast_f32, dim3((unsigned)cdiv(n, kBlock)), dim3(kBlock), 0, s, src, dst, n);
+}
+
+}  // namespace mlq
+
+namespace mlq {
+
+// ---------------------------------------------------------------------------
+// Preconditioner P = M (I + D): exact inverse of the consistent Q1 mass, which is
+// the Kronecker product of 1D masses M_a = h_a/6 tridiag(1, 4, 1) (2 on the end
+// diagonals), followed by the pointwise division by (1 + d).  With right
+// preconditioning the mass part of J P^-1 is the identity, so the Krylov
+// operator is v -> v + dt/2 K P^-1 v.
+//
+// Thomas elimination of tridiag(1, 4, 1) (2 at the ends) along a strided line;
+// iv[i] = 1 / (pivot i) is precomputed per axis.
+template <typename T>
+__device__ inline void thomas_line(T* a, int n, int stride, const T* __restrict__ iv) {
+  T prev = a[0] * iv[0];
+  a[0] = prev;
+  for (int i = 1; i < n; ++i) {
+    prev = (a[i * stride] - prev) * iv[i];
+    a[i * stride] = prev;
+  }
+  T nxt = prev;
+  for (int i = n - 2; i >= 0; --i) {
+    nxt = a[i * stride] - iv[i] * nxt;
+    a[i * stride] = nxt;
+  }
+}
+
+enum { kOutPlain = 0, kOutDivD = 1, kOutAddU = 2 };
+
+// x and y sweeps of one z-plane of one sample in LDS.  Input scaled by
+// c6 * inv_eta[j] (c6 = prod 6/h_a) when inv_eta != nullptr, by c6 otherwise.
+template <typename T, int OUT>
+__global__ __launch_bounds__(kBlock) void k_minv_xy(Geo g, const T* __restrict__ in, T* __restrict__ out,
+                                                    const double* __restrict__ inv_eta, int j, int kmax, double c6,
+                                                    const T* __restrict__ ivx, const T* __restrict__ ivy,
+                                                    const T* __restrict__ d, double* __restrict__ u,
+                                                    const int32_t* __restrict__ active) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sh = reinterpret_cast<T*>(smem_raw);
+  const int sb = blockIdx.y;
+  if (active[sb] == 0) return;
+  const int nx = g.nx, ny = g.ny, np = nx * ny;
+  const int64_t base = (int64_t)sb * g.nn + (int64_t)blockIdx.x * np;
+  const T s = (T)(c6 * (inv_eta != nullptr ? inv_eta[(int64_t)sb * (kmax + 1) + j] : 1.0));
+  for (int t = threadIdx.x; t < np; t += kBlock) sh[t] = in[base + t] * s;
+  __syncthreads();
+  for (int r = threadIdx.x; r < ny; r += kBlock) thomas_line(sh + r * nx, nx, 1, ivx);
+  __syncthreads();
+  for (int c = threadIdx.x; c < nx; c += kBlock) thomas_line(sh + c, ny, nx, ivy);
+  __syncthreads();
+  for (int t = threadIdx.x; t < np; t += kBlock) {
+    T v = sh[t];
+    if (OUT == kOutPlain) {
+      out[base + t] = v;
+    } else {
+      v = v / ((T)1 + d[base + t]);
+      if (OUT == kOutDivD)
+        out[base + t] = v;
+      else
+        u[base + t] += (double)v;
+    }
+  }
+}
+
+// z sweeps of one x-z plane (fixed y) of one sample in LDS, then the division by (1 + d).
+template <typename T, int OUT>
+__global__ __launch_bounds__(kBlock) void k_minv_z(Geo g, const T* __restrict__ in, T* __restrict__ out,
+                                                   const T* __restrict__ ivz, const T* __restrict__ d,
+                                                   double* __restrict__ u, const int32_t* __restrict__ active) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sh = reinterpret_cast<T*>(smem_raw);
+  const int sb = blockIdx.y;
+  if (active[sb] == 0) return;
+  const int nx = g.nx, nz = g.nz;
+  const int64_t plane = (int64_t)g.nx * g.ny;
+  const int64_t base = (int64_t)sb * g.nn + (int64_t)blockIdx.x * nx;
+  const int np = nx * nz;
+  for (int t = threadIdx.x; t < np; t += kBlock) sh[t] = in[base + (int64_t)(t / nx) * plane + (t % nx)];
+  __syncthreads();
+  for (int c = threadIdx.x; c < nx; c += kBlock) thomas_line(sh + c, nz, nx, ivz);
+  __syncthreads();
+  for (int t = threadIdx.x; t < np; t += kBlock) {
+    const int64_t o = base + (int64_t)(t / nx) * plane + (t % nx);
+    const T v = sh[t] / ((T)1 + d[o]);
+    if (OUT == kOutDivD)
+      out[o] = v;
+    else
+      u[o] += (double)v;
+  }
+}
+
+// z <- P^-1 (scale * src); with add_u the result is added to u instead (FP64).
+template <typename T>
+static void minv_dispatch(const Geo& g, const T* src, T* tmp, T* dst, const double* inv_eta, int j, int kmax,
+                          const T* tri, int nmax, const T* d, double* u, bool add_u, const int32_t* active,
+                          int32_t B, hipStream_t s) {
+  const T* ivx = tri;
+  const T* ivy = tri + nmax;
+  const T* ivz = tri + 2 * nmax;
+  if (g.dim == 2) {
+    const double c6 = 36.0 / g.Hm;
+    const size_t sh = sizeof(T) * (size_t)g.nx * g.ny;
+    if (add_u)
+      hipLaunchKernelGGL((k_minv_xy<T, kOutAddU>), dim3(1, B), dim3(kBlock), sh, s, g, src, dst, inv_eta, j, kmax, c6,
+                         ivx, ivy, d, u, active);
+    else
+      hipLaunchKernelGGL((k_minv_xy<T, kOutDivD>), dim3(1, B), dim3(kBlock), sh, s, g, src, dst, inv_eta, j, kmax, c6,
+                         ivx, ivy, d, u, active);
+    return;
+  }
+  const double c6 = 216.0 / g.Hm;
+  const size_t shxy = sizeof(T) * (size_t)g.nx * g.ny;
+  const size_t shxz = sizeof(T) * (size_t)g.nx * g.nz;
+  hipLaunchKernelGGL((k_minv_xy<T, kOutPlain>), dim3(g.nz, B), dim3(kBlock), shxy, s, g, src, tmp, inv_eta, j, kmax,
+                     c6, ivx, ivy, d, u, active);
+  if (add_u)
+    hipLaunchKernelGGL((k_minv_z<T, kOutAddU>), dim3(g.ny, B), dim3(kBlock), shxz, s, g, tmp, dst, ivz, d, u, active);
+  else
+    hipLaunchKernelGGL((k_minv_z<T, kOutDivD>), dim3(g.ny, B), dim3(kBlock), shxz, s, g, tmp, dst, ivz, d, u, active);
+}
+
+// GMRES preconditioner step: z = P^-1 v_j (v_j = stored basis vector times inv_eta_j); w is scratch.
+void launch_minv_basis(const Geo& g, const Work& w, const void* tri, int nmax, int j, int32_t B, bool mixed,
+                       hipStream_t s) {
+  const size_t vs = (size_t)g.nn * B;
+  if (mixed)
+    minv_dispatch<float>(g, (const float*)w.V + j * vs, (float*)w.w, (float*)w.z, w.inv_eta, j, w.kmax,
+                         (const float*)tri, nmax, (const float*)w.d, nullptr, false, w.inner_active, B, s);
+  else
+    minv_dispatch<double>(g, (const double*)w.V + j * vs, (double*)w.w, (double*)w.z, w.inv_eta, j, w.kmax,
+                          (const double*)tri, nmax, (const double*)w.d, nullptr, false, w.inner_active, B, s);
+}
+
+// Preconditioned operator: w = v_j + dt/2 K_G z  (the mass part of J P^-1 is the identity).
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_apply_pk(Geo g, const T* __restrict__ z, const T* __restrict__ vj,
+                                                     const double* __restrict__ inv_eta, int j, int kmax,
+                                                     const T* __restrict__ coef, T* __restrict__ w, T ck,
+                                                     const int32_t* __restrict__ active) {
+  const int sb = blockIdx.y;
+  if (active[sb] == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nn) return;
+  const T* zs = z + (int64_t)sb * g.nn;
+  const T* cf = coef + (int64_t)sb * g.P * 2;
+  int ix, iy, iz;
+  node_xyz(i, g, ix, iy, iz);
+  T xm[27], xk[27];
+  load_nbhd<DIM, T>(
+      ix, iy, iz, g,
+      [&](int64_t jj, T& a, T& b) {
+        a = 0;
+        b = zs[jj];
+      },
+      xm, xk);
+  T SM, SK;
+  gather<DIM, T, T>(ix, iy, iz, g, cf, xm, xk, SM, SK);
+  const int64_t o = (int64_t)sb * g.nn + i;
+  const T sj = (T)inv_eta[(int64_t)sb * (kmax + 1) + j];
+  w[o] = vj[o] * sj + ck * SK;
+}
+
+void launch_apply_pk(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)w.nblk, B);
+  const size_t vs = (size_t)g.nn * B;
+#define MLQ_APK(D, T)                                                                                         \
+  hipLaunchKernelGGL((k_apply_pk<D, T>), grid, dim3(kBlock), 0, s, g, (const T*)w.z, (const T*)w.V + j * vs, \
+                     w.inv_eta, j, w.kmax, (const T*)w.coef, (T*)w.w, (T)ck, w.inner_active)
+  if (g.dim == 3) {
+    if (mixed) MLQ_APK(3, float); else MLQ_APK(3, double);
+  } else {
+    if (mixed) MLQ_APK(2, float); else MLQ_APK(2, double);
+  }
+#undef MLQ_APK
+}
+
+// Newton update, right preconditioning: u += P^-1 (sum_l y_l v_l).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_combine_basis(int64_t nn, const T* __restrict__ V, size_t vs,
+                                                          const double* __restrict__ y, int kmax,
+                                                          const int32_t* __restrict__ inner_k, T* __restrict__ out,
+                                                          const int32_t* __restrict__ active) {
+  const int sb = blockIdx.y;
+  if (active[sb] == 0) return;
+  __shared__ double c[kMaxInner];
+  const int k = inner_k[sb];
+  for (int i = threadIdx.x; i < k; i += kBlock) c[i] = y[(int64_t)sb * kmax + i];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  const int64_t o = (int64_t)sb * nn + i;
+  double acc = 0.0;
+  for (int l = 0; l < k; ++l) acc += c[l] * (double)V[l * vs + o];
+  out[o] = (T)acc;
+}
+
+void launch_update_pm(const Geo& g, const Work& w, const void* tri, int nmax, int32_t B, bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)w.nblk, B);
+  const size_t vs = (size_t)g.nn * B;
+  if (mixed) {
+    hipLaunchKernelGGL((k_combine_basis<float>), grid, dim3(kBlock), 0, s, g.nn, (const float*)w.V, vs, w.y, w.kmax,
+                       w.inner_k, (float*)w.w, w.newton_active);
+    minv_dispatch<float>(g, (const float*)w.w, (float*)w.z, (float*)w.z, nullptr, 0, w.kmax, (const float*)tri, nmax,
+                         (const float*)w.d, w.u, true, w.newton_active, B, s);
+  } else {
+    hipLaunchKernelGGL((k_combine_basis<double>), grid, dim3(kBlock), 0, s, g.nn, (const double*)w.V, vs, w.y,
+                       w.kmax, w.inner_k, (double*)w.w, w.newton_active);
+    minv_dispatch<double>(g, (const double*)w.w, (double*)w.z, (double*)w.z, nullptr, 0, w.kmax, (const double*)tri,
+                          nmax, (const double*)w.d, w.u, true, w.newton_active, B, s);
+  }
+}
+
+}  // namespace mlq
+
+namespace mlq {
+
+// Large planes need more than the default 64 KB of dynamic LDS per workgroup.
+hipError_t prepare_minv_kernels(size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  const int b = (int)bytes;
+  hipError_t e = hipSuccess;
+#define MLQ_ATTR(K)                                                                                    \
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)(K), hipFuncAttributeMaxDynamicSharedMemorySize, b)
+  MLQ_ATTR((k_minv_xy<double, kOutPlain>));
+  MLQ_ATTR((k_minv_xy<double, kOutDivD>));
+  MLQ_ATTR((k_minv_xy<double, kOutAddU>));
+  MLQ_ATTR((k_minv_z<double, kOutDivD>));
+  MLQ_ATTR((k_minv_z<double, kOutAddU>));
+  MLQ_ATTR((k_minv_xy<float, kOutPlain>));
+  MLQ_ATTR((k_minv_xy<float, kOutDivD>));
+  MLQ_ATTR((k_minv_xy<float, kOutAddU>));
+  MLQ_ATTR((k_minv_z<float, kOutDivD>));
+  MLQ_ATTR((k_minv_z<float, kOutAddU>));
+#undef MLQ_ATTR
+  return e;
 }
 
 }  // namespace mlq

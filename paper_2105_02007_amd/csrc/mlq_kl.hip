@@ -1,0 +1,518 @@
+// Discrete Karhunen-Loeve basis of the fibre-angle field (Section 2.3) on the
+// nodes of a uniform Q1 box, and its element-midpoint transfer to the element
+// centres of a level (Section 4).
+//
+//   eq. (algEig)    M C M v = lambda M v,     C_ij = s^2 exp(-|x_i - x_j|_2 / l)
+//   C ~ L L^T       pivoted Cholesky (largest remaining diagonal, lowest index on
+//                   ties; columns of C evaluated on the fly on the GPU)
+//   eq. (redEig)    L^T M L v~ = lambda v~ (R x R, cyclic Jacobi on the host)
+//   v = L v~        v_i^T M v_j = lambda_i delta_ij;  psi = v / sqrt(lambda)
+//
+// Sign of each mode: its first entry of largest magnitude is positive (entries
+// within a relative 1e-9 of the maximum count as ties).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mlq_internal.h"
+
+namespace mlq {
+
+namespace {
+
+constexpr int kT = 256;
+
+struct Box {
+  int32_t dim;
+  int64_t n[3];
+  double lo[3], h[3];
+  int64_t nn;
+};
+
+__host__ __device__ inline void box_xyz(const Box& b, int64_t i, double x[3]) {
+  const int64_t ix = i % b.n[0];
+  const int64_t r = i / b.n[0];
+  const int64_t iy = r % b.n[1];
+  const int64_t iz = r / b.n[1];
+  x[0] = b.lo[0] + b.h[0] * (double)ix;
+  x[1] = b.lo[1] + b.h[1] * (double)iy;
+  x[2] = b.dim == 3 ? b.lo[2] + b.h[2] * (double)iz : 0.0;
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Block-level (max value, lowest index) and sum of d; partials per block.
+__global__ __launch_bounds__(kT) void k_argmax_sum(const double* __restrict__ d, int64_t n, int use_abs,
+                                                   double* __restrict__ pv, int64_t* __restrict__ pi,
+                                                   double* __restrict__ ps) {
+  __shared__ double sv[kT];
+  __shared__ int64_t si[kT];
+  __shared__ double ss[kT];
+  const int64_t base = (int64_t)blockIdx.x * kT * 16;
+  double bv = -1.0, sum = 0.0;
+  int64_t bi = -1;
+  for (int k = 0; k < 16; ++k) {
+    const int64_t i = base + (int64_t)k * kT + threadIdx.x;
+    if (i < n) {
+      const double v = use_abs ? fabs(d[i]) : d[i];
+      sum += d[i];
+      if (bi < 0 || v > bv) {
+        bv = v;
+        bi = i;
+      }
+    }
+  }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  ss[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double v2 = sv[threadIdx.x + o];
+      const int64_t i2 = si[threadIdx.x + o];
+      if (i2 >= 0 && (si[threadIdx.x] < 0 || v2 > sv[threadIdx.x] || (v2 == sv[threadIdx.x] && i2 < si[threadIdx.x]))) {
+        sv[threadIdx.x] = v2;
+        si[threadIdx.x] = i2;
+      }
+      ss[threadIdx.x] += ss[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    pv[blockIdx.x] = sv[0];
+    pi[blockIdx.x] = si[0];
+    ps[blockIdx.x] = ss[0];
+  }
+}
+
+// Final reduction over block partials (one block).  out: [0] = max, [1] = sum; idx_out = argmax.
+__global__ __launch_bounds__(kT) void k_argmax_final(const double* __restrict__ pv, const int64_t* __restrict__ pi,
+                                                     const double* __restrict__ ps, int nb, double* out,
+                                                     int64_t* idx_out) {
+  __shared__ double sv[kT];
+  __shared__ int64_t si[kT];
+  __shared__ double ss[kT];
+  double bv = -1.0, sum = 0.0;
+  int64_t bi = -1;
+  for (int b = threadIdx.x; b < nb; b += kT) {
+    sum += ps[b];
+    if (pi[b] >= 0 && (bi < 0 || pv[b] > bv || (pv[b] == bv && pi[b] < bi))) {
+      bv = pv[b];
+      bi = pi[b];
+    }
+  }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  ss[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double v2 = sv[threadIdx.x + o];
+      const int64_t i2 = si[threadIdx.x + o];
+      if (i2 >= 0 && (si[threadIdx.x] < 0 || v2 > sv[threadIdx.x] || (v2 == sv[threadIdx.x] && i2 < si[threadIdx.x]))) {
+        sv[threadIdx.x] = v2;
+        si[threadIdx.x] = i2;
+      }
+      ss[threadIdx.x] += ss[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sv[0];
+    out[1] = ss[0];
+    idx_out[0] = si[0];
+  }
+}
+
+// Column r of the pivoted Cholesky factor (column-major L, n rows):
+//   L[:, r] = (C[:, p] - L[:, :r] L[p, :r]^T) / sqrt(d_p),  d -= L[:, r]^2,  d_p = 0.
+__global__ __launch_bounds__(kT) void k_chol_col(Box b, double* __restrict__ L, double* __restrict__ d, int r,
+                                                 const int64_t* __restrict__ pivp, const double* __restrict__ stat,
+                                                 double s2, double inv_len) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= b.nn) return;
+  const int64_t p = pivp[0];
+  const double dp = stat[0];
+  double xi[3], xp[3];
+  box_xyz(b, i, xi);
+  box_xyz(b, p, xp);
+  const double dx = xi[0] - xp[0], dy = xi[1] - xp[1], dz = xi[2] - xp[2];
+  double c = s2 * exp(-sqrt(dx * dx + dy * dy + dz * dz) * inv_len);
+  for (int j = 0; j < r; ++j) c -= L[(int64_t)j * b.nn + i] * L[(int64_t)j * b.nn + p];
+  const double l = c / sqrt(dp);
+  L[(int64_t)r * b.nn + i] = l;
+  d[i] = (i == p) ? 0.0 : d[i] - l * l;
+}
+
+// Mass matrix (tensor-product Q1) applied to every column: grid (blocks, columns).
+__global__ __launch_bounds__(kT) void k_mass_cols(Box b, const double* __restrict__ X, double* __restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= b.nn) return;
+  const int64_t c = blockIdx.y;
+  const double* x = X + c * b.nn;
+  const int64_t ix = i % b.n[0], r = i / b.n[0], iy = r % b.n[1], iz = r / b.n[1];
+  // separable stencil: (M1 (x) M1 (x) M1), M1 = h/6 tridiag(1, 4, 1), halved diagonal at the ends
+  double acc = 0.0;
+  const int zlo = b.dim == 3 ? -1 : 0, zhi = b.dim == 3 ? 1 : 0;
+  for (int oz = zlo; oz <= zhi; ++oz) {
+    const int64_t jz = iz + oz;
+    if (jz < 0 || jz >= b.n[2]) continue;
+    double wz = 1.0;
+    if (b.dim == 3) wz = oz != 0 ? b.h[2] / 6.0 : ((iz == 0 || iz == b.n[2] - 1) ? 2.0 : 4.0) * b.h[2] / 6.0;
+    for (int oy = -1; oy <= 1; ++oy) {
+      const int64_t jy = iy + oy;
+      if (jy < 0 || jy >= b.n[1]) continue;
+      const double wy = oy != 0 ? b.h[1] / 6.0 : ((iy == 0 || iy == b.n[1] - 1) ? 2.0 : 4.0) * b.h[1] / 6.0;
+      for (int ox = -1; ox <= 1; ++ox) {
+        const int64_t jx = ix + ox;
+        if (jx < 0 || jx >= b.n[0]) continue;
+        const double wx = ox != 0 ? b.h[0] / 6.0 : ((ix == 0 || ix == b.n[0] - 1) ? 2.0 : 4.0) * b.h[0] / 6.0;
+        acc += wx * wy * wz * x[jx + b.n[0] * (jy + b.n[1] * jz)];
+      }
+    }
+  }
+  Y[c * b.nn + i] = acc;
+}
+
+// Split-K Gram matrix: part[chunk][a][c] = sum_{rows in chunk} A[:, a] B[:, c] (A, B column-major, n rows).
+constexpr int kGT = 16;       // tile edge
+constexpr int kGChunk = 8192; // rows per chunk
+__global__ __launch_bounds__(kGT * kGT) void k_gram(const double* __restrict__ A, const double* __restrict__ Bm,
+                                                    int64_t n, int R, double* __restrict__ part) {
+  __shared__ double sa[64][kGT + 1];
+  __shared__ double sb[64][kGT + 1];
+  const int ta = threadIdx.x % kGT, tc = threadIdx.x / kGT;
+  const int a = blockIdx.x * kGT + ta, c = blockIdx.y * kGT + tc;
+  const int64_t r0 = (int64_t)blockIdx.z * kGChunk;
+  const int64_t r1 = r0 + kGChunk < n ? r0 + kGChunk : n;
+  double acc = 0.0;
+  for (int64_t rb = r0; rb < r1; rb += 64) {
+    // load 64 rows x 16 columns of A (tile columns blockIdx.x) and of B (tile columns blockIdx.y)
+    for (int t = threadIdx.x; t < 64 * kGT; t += kGT * kGT) {
+      const int row = t % 64, col = t / 64;
+      const int64_t gr = rb + row;
+      const int ca = blockIdx.x * kGT + col, cb = blockIdx.y * kGT + col;
+      sa[row][col] = (gr < r1 && ca < R) ? A[(int64_t)ca * n + gr] : 0.0;
+      sb[row][col] = (gr < r1 && cb < R) ? Bm[(int64_t)cb * n + gr] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int row = 0; row < 64; ++row) acc += sa[row][ta] * sb[row][tc];
+    __syncthreads();
+  }
+  if (a < R && c < R) part[((int64_t)blockIdx.z * R + a) * R + c] = acc;
+}
+
+__global__ void k_gram_sum(const double* __restrict__ part, int nchunk, int R, double* S) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)R * R) return;
+  double s = 0.0;
+  for (int k = 0; k < nchunk; ++k) s += part[(int64_t)k * R * R + t];
+  S[t] = s;
+}
+
+// psi[:, k] = L W[:, k] (column-major, n rows; W is R x M row-major in LDS chunks).
+__global__ __launch_bounds__(kT) void k_combine(const double* __restrict__ L, int64_t n, int R,
+                                                const double* __restrict__ W, int M, double* __restrict__ psi) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int k = blockIdx.y;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < R; ++j) acc += L[(int64_t)j * n + i] * W[(int64_t)j * M + k];
+  psi[(int64_t)k * n + i] = acc;
+}
+
+// Sign convention: the first entry of largest magnitude is positive; entries
+// within a relative 1e-9 of the maximum count as ties (symmetric meshes give
+// +/- pairs of equal magnitude).  One block per column.
+__global__ __launch_bounds__(kT) void k_sign_fix(double* psi, int64_t n) {
+  __shared__ double sv[kT];
+  __shared__ int64_t si[kT];
+  double* col = psi + (int64_t)blockIdx.x * n;
+  double bv = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kT) bv = fmax(bv, fabs(col[i]));
+  sv[threadIdx.x] = bv;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sv[threadIdx.x] = fmax(sv[threadIdx.x], sv[threadIdx.x + o]);
+    __syncthreads();
+  }
+  const double cut = sv[0] * (1.0 - 1e-9);
+  int64_t first = -1;
+  for (int64_t i = threadIdx.x; i < n; i += kT)
+    if (fabs(col[i]) >= cut) {
+      first = i;
+      break;
+    }
+  si[threadIdx.x] = first;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const int64_t a = si[threadIdx.x], b = si[threadIdx.x + o];
+      si[threadIdx.x] = (a < 0) ? b : ((b < 0) ? a : (a < b ? a : b));
+    }
+    __syncthreads();
+  }
+  const bool flip = si[0] >= 0 && col[si[0]] < 0.0;
+  __syncthreads();
+  if (flip)
+    for (int64_t i = threadIdx.x; i < n; i += kT) col[i] = -col[i];
+}
+
+// Element-midpoint transfer: phi[p][k] = Q1 interpolant of psi[:, k] (KL grid) at centre p of the level.
+__global__ __launch_bounds__(kT) void k_transfer(Box kb, Box lb, const double* __restrict__ psi, int M,
+                                                 double* __restrict__ phi, int64_t P) {
+  const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (t >= P * M) return;
+  const int64_t p = t / M;
+  const int k = (int)(t % M);
+  const int64_t nex = lb.n[0] - 1, ney = lb.n[1] - 1;
+  const int64_t ex = p % nex, r = p / nex, ey = r % ney, ez = r / ney;
+  const int64_t e[3] = {ex, ey, ez};
+  int64_t cell[3] = {0, 0, 0};
+  double xi[3] = {0, 0, 0};
+  for (int a = 0; a < kb.dim; ++a) {
+    const double c = lb.lo[a] + ((double)e[a] + 0.5) * lb.h[a];
+    const double rel = (c - kb.lo[a]) / kb.h[a];
+    int64_t ci = (int64_t)floor(rel);
+    ci = ci < 0 ? 0 : (ci > kb.n[a] - 2 ? kb.n[a] - 2 : ci);
+    cell[a] = ci;
+    xi[a] = rel - (double)ci;
+  }
+  const double* col = psi + (int64_t)k * kb.nn;
+  double acc = 0.0;
+  const int nloc = kb.dim == 3 ? 8 : 4;
+  for (int a = 0; a < nloc; ++a) {
+    double w = 1.0;
+    int64_t id = 0, stride = 1;
+    for (int ax = 0; ax < kb.dim; ++ax) {
+      const int off = (a >> ax) & 1;
+      w *= off ? xi[ax] : 1.0 - xi[ax];
+      id += (cell[ax] + off) * stride;
+      stride *= kb.n[ax];
+    }
+    acc += w * col[id];
+  }
+  phi[p * M + k] = acc;
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric R x R matrix (row-major, in place).
+// On return A's diagonal holds the eigenvalues and V (row-major) the eigenvectors as columns.
+void jacobi_eig(std::vector<double>& A, std::vector<double>& V, int R) {
+  V.assign((size_t)R * R, 0.0);
+  for (int i = 0; i < R; ++i) V[(size_t)i * R + i] = 1.0;
+  auto a = [&](int i, int j) -> double& { return A[(size_t)i * R + j]; };
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < R; ++i) {
+      diag += a(i, i) * a(i, i);
+      for (int j = i + 1; j < R; ++j) off += a(i, j) * a(i, j);
+    }
+    if (off <= 1e-30 * diag || off == 0.0) break;
+    for (int p = 0; p < R - 1; ++p)
+      for (int q = p + 1; q < R; ++q) {
+        const double apq = a(p, q);
+        if (std::fabs(apq) <= 1e-300) continue;
+        // rotation annihilating a_pq (symmetric Schur decomposition of the 2x2 block)
+        const double tau = (a(q, q) - a(p, p)) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+        for (int k = 0; k < R; ++k) {  // columns p, q
+          const double akp = a(k, p), akq = a(k, q);
+          a(k, p) = c * akp - s * akq;
+          a(k, q) = s * akp + c * akq;
+        }
+        for (int k = 0; k < R; ++k) {  // rows p, q
+          const double apk = a(p, k), aqk = a(q, k);
+          a(p, k) = c * apk - s * aqk;
+          a(q, k) = s * apk + c * aqk;
+        }
+        for (int k = 0; k < R; ++k) {
+          const double vkp = V[(size_t)k * R + p], vkq = V[(size_t)k * R + q];
+          V[(size_t)k * R + p] = c * vkp - s * vkq;
+          V[(size_t)k * R + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+}
+
+Box make_box(const mlq_kl_desc* kd) {
+  Box b{};
+  b.dim = kd->dim;
+  b.nn = 1;
+  for (int a = 0; a < 3; ++a) {
+    b.n[a] = a < kd->dim ? kd->n[a] : 1;
+    b.lo[a] = a < kd->dim ? kd->lo[a] : 0.0;
+    b.h[a] = a < kd->dim ? (kd->hi[a] - kd->lo[a]) / (double)(kd->n[a] - 1) : 1.0;
+    b.nn *= b.n[a];
+  }
+  return b;
+}
+
+inline size_t al(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct KlWork {
+  double *L, *ML, *d, *pv, *ps, *stat, *part, *S, *W;
+  int64_t *pi, *idx;
+  size_t bytes;
+};
+
+KlWork kl_carve(void* base, int64_t n, int R, int M) {
+  KlWork w{};
+  char* p = (char*)base;
+  size_t o = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* r = p ? (void*)(p + o) : nullptr;
+    o = al(o + bytes);
+    return r;
+  };
+  const int64_t nb = cdiv(n, kT * 16);
+  const int64_t nchunk = cdiv(n, kGChunk);
+  w.L = (double*)take(sizeof(double) * n * R);
+  w.ML = (double*)take(sizeof(double) * n * R);
+  w.d = (double*)take(sizeof(double) * n);
+  w.pv = (double*)take(sizeof(double) * nb);
+  w.ps = (double*)take(sizeof(double) * nb);
+  w.pi = (int64_t*)take(sizeof(int64_t) * nb);
+  w.stat = (double*)take(sizeof(double) * 4);
+  w.idx = (int64_t*)take(sizeof(int64_t) * 4);
+  w.part = (double*)take(sizeof(double) * nchunk * R * R);
+  w.S = (double*)take(sizeof(double) * R * R);
+  w.W = (double*)take(sizeof(double) * R * M);
+  w.bytes = o;
+  return w;
+}
+
+}  // namespace
+
+mlq_status kl_validate(const mlq_kl_desc* kd) {
+  if (kd == nullptr) return MLQ_EINVAL;
+  if (kd->dim != 2 && kd->dim != 3) return MLQ_EINVAL;
+  int64_t n = 1;
+  for (int a = 0; a < kd->dim; ++a) {
+    if (kd->n[a] < 2 || !(kd->hi[a] > kd->lo[a])) return MLQ_EINVAL;
+    n *= kd->n[a];
+  }
+  if (kd->n_modes < 1 || kd->n_modes > 1024) return MLQ_EINVAL;
+  if (kd->max_rank < kd->n_modes || kd->max_rank > 4096 || kd->max_rank > n) return MLQ_EINVAL;
+  if (!(kd->std_dev > 0.0) || !(kd->corr_len > 0.0) || !(kd->eps >= 0.0)) return MLQ_EINVAL;
+  return MLQ_OK;
+}
+
+size_t kl_workspace_bytes(const mlq_kl_desc* kd) {
+  const Box b = make_box(kd);
+  return kl_carve(nullptr, b.nn, kd->max_rank, kd->n_modes).bytes;
+}
+
+// Returns MLQ_OK or MLQ_EHIP; error text in err.
+mlq_status kl_modes(const mlq_kl_desc* kd, void* ws, double* lambda_host, double* psi_dev, int32_t* rank_out,
+                    double* resid_out, hipStream_t s, std::string& err) {
+  const Box b = make_box(kd);
+  const int64_t n = b.nn;
+  const int Rmax = kd->max_rank, M = kd->n_modes;
+  KlWork w = kl_carve(ws, n, Rmax, M);
+  const int64_t nb = cdiv(n, kT * 16);
+  const double s2 = kd->std_dev * kd->std_dev;
+  const double tr0 = s2 * (double)n;
+  auto chk = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+      err = std::string(what) + ": " + hipGetErrorString(e);
+      return false;
+    }
+    return true;
+  };
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)cdiv(n, kT)), dim3(kT), 0, s, w.d, n, s2);
+  double hstat[2];
+  int rank = 0;
+  double resid = tr0;
+  for (int r = 0; r < Rmax; ++r) {
+    hipLaunchKernelGGL(k_argmax_sum, dim3((unsigned)nb), dim3(kT), 0, s, w.d, n, 0, w.pv, w.pi, w.ps);
+    hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(kT), 0, s, w.pv, w.pi, w.ps, (int)nb, w.stat, w.idx);
+    if (!chk(hipMemcpyAsync(hstat, w.stat, sizeof(hstat), hipMemcpyDeviceToHost, s), "copy")) return MLQ_EHIP;
+    if (!chk(hipStreamSynchronize(s), "sync")) return MLQ_EHIP;
+    resid = hstat[1];
+    if (hstat[0] <= 0.0) break;                            // exact low rank reached
+    if (r >= M && resid <= kd->eps * tr0) break;           // truncation criterion
+    hipLaunchKernelGGL(k_chol_col, dim3((unsigned)cdiv(n, kT)), dim3(kT), 0, s, b, w.L, w.d, r, w.idx, w.stat, s2,
+                       1.0 / kd->corr_len);
+    rank = r + 1;
+  }
+  if (rank < M) {
+    err = "covariance has numerical rank below n_modes";
+    return MLQ_EINVAL;
+  }
+  if (rank == Rmax) {  // residual after the last column
+    hipLaunchKernelGGL(k_argmax_sum, dim3((unsigned)nb), dim3(kT), 0, s, w.d, n, 0, w.pv, w.pi, w.ps);
+    hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(kT), 0, s, w.pv, w.pi, w.ps, (int)nb, w.stat, w.idx);
+    if (!chk(hipMemcpyAsync(hstat, w.stat, sizeof(hstat), hipMemcpyDeviceToHost, s), "copy")) return MLQ_EHIP;
+    if (!chk(hipStreamSynchronize(s), "sync")) return MLQ_EHIP;
+    resid = hstat[1];
+  }
+  const int R = rank;
+  // reduced eigenproblem eq. (redEig): S = L^T M L
+  hipLaunchKernelGGL(k_mass_cols, dim3((unsigned)cdiv(n, kT), R), dim3(kT), 0, s, b, w.L, w.ML);
+  const int nchunk = (int)cdiv(n, kGChunk);
+  hipLaunchKernelGGL(k_gram, dim3((unsigned)cdiv(R, kGT), (unsigned)cdiv(R, kGT), nchunk), dim3(kGT * kGT), 0, s,
+                     w.L, w.ML, n, R, w.part);
+  hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)cdiv((int64_t)R * R, kT)), dim3(kT), 0, s, w.part, nchunk, R, w.S);
+  std::vector<double> S((size_t)R * R), V;
+  if (!chk(hipMemcpyAsync(S.data(), w.S, sizeof(double) * R * R, hipMemcpyDeviceToHost, s), "copy S")) return MLQ_EHIP;
+  if (!chk(hipStreamSynchronize(s), "sync")) return MLQ_EHIP;
+  for (int i = 0; i < R; ++i)
+    for (int j = i + 1; j < R; ++j) {
+      const double v = 0.5 * (S[(size_t)i * R + j] + S[(size_t)j * R + i]);
+      S[(size_t)i * R + j] = S[(size_t)j * R + i] = v;
+    }
+  jacobi_eig(S, V, R);
+  std::vector<int> order(R);
+  for (int i = 0; i < R; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return S[(size_t)x * R + x] > S[(size_t)y * R + y]; });
+  std::vector<double> W((size_t)R * M);
+  for (int k = 0; k < M; ++k) {
+    const double lam = S[(size_t)order[k] * R + order[k]];
+    if (!(lam > 0.0)) {
+      err = "non-positive KL eigenvalue among the requested modes";
+      return MLQ_EINVAL;
+    }
+    lambda_host[k] = lam;
+    const double inv = 1.0 / std::sqrt(lam);
+    for (int j = 0; j < R; ++j) W[(size_t)j * M + k] = V[(size_t)j * R + order[k]] * inv;
+  }
+  if (!chk(hipMemcpyAsync(w.W, W.data(), sizeof(double) * R * M, hipMemcpyHostToDevice, s), "copy W")) return MLQ_EHIP;
+  hipLaunchKernelGGL(k_combine, dim3((unsigned)cdiv(n, kT), M), dim3(kT), 0, s, w.L, n, R, w.W, M, psi_dev);
+  hipLaunchKernelGGL(k_sign_fix, dim3(M), dim3(kT), 0, s, psi_dev, n);
+  if (!chk(hipGetLastError(), "launch")) return MLQ_EHIP;
+  if (!chk(hipStreamSynchronize(s), "sync")) return MLQ_EHIP;
+  if (rank_out) *rank_out = R;
+  if (resid_out) *resid_out = resid / tr0;
+  return MLQ_OK;
+}
+
+mlq_status kl_transfer(const mlq_kl_desc* kd, const double* psi_dev, const int64_t* level_n, const double* level_lo,
+                       const double* level_hi, double* phi_dev, hipStream_t s) {
+  const Box kb = make_box(kd);
+  Box lb{};
+  lb.dim = kd->dim;
+  lb.nn = 1;
+  int64_t P = 1;
+  for (int a = 0; a < 3; ++a) {
+    lb.n[a] = a < kd->dim ? level_n[a] : 2;
+    lb.lo[a] = a < kd->dim ? level_lo[a] : 0.0;
+    lb.h[a] = a < kd->dim ? (level_hi[a] - level_lo[a]) / (double)(level_n[a] - 1) : 1.0;
+    lb.nn *= lb.n[a];
+    if (a < kd->dim) P *= level_n[a] - 1;
+  }
+  const int M = kd->n_modes;
+  hipLaunchKernelGGL(k_transfer, dim3((unsigned)cdiv(P * M, kT)), dim3(kT), 0, s, kb, lb, psi_dev, M, phi_dev, P);
+  return hipGetLastError() == hipSuccess ? MLQ_OK : MLQ_EHIP;
+}
+
+}  // namespace mlq

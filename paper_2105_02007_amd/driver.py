@@ -1,0 +1,119 @@
+"""Workload driver: sets a configuration up and runs its estimator through the C ABI.
+
+Host orchestration only (which level, which batch, in which order); the KL
+basis, field synthesis, solves, lattice points, level differences and
+estimators all run in libmlq (HIP kernels, or its host C++ for the estimator
+sums).  Random numbers of Monte Carlo sampling (standard normals) and the
+random shifts of lattice rules are inputs, passed in by the caller.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import mlq
+
+EST_OF = {"mc": mlq.MLQ_EST_MC, "qmc": mlq.MLQ_EST_MLQMC, "mlmc": mlq.MLQ_EST_MLMC, "mlqmc": mlq.MLQ_EST_MLQMC}
+
+
+class ConfigRunner:
+    """Levels of one workload with their KL bases (Section 2.3) on one device."""
+
+    def __init__(self, cfg: dict, prec: int | None = None, device="cuda", newton_tol=None, inner_tol=None,
+                 max_inner=30, kl_rank_factor=2, kl_eps=1e-2):
+        self.cfg = cfg
+        self.device = device
+        self.prec = cfg["prec"] if prec is None else prec
+        self.phys = cfg["physics"]
+        kcfg = cfg["kl"]
+        M = kcfg["n_modes"]
+        kl_level = cfg["levels"][kcfg["grid_level"]]
+        self.kd = mlq.kl_desc(cfg["dim"], kl_level["n"], kl_level["lo"], kl_level["hi"], kcfg["std"],
+                              kcfg["corr_len"], M, max_rank=kl_rank_factor * M, eps=kl_eps)
+        lam, psi, self.kl_rank, self.kl_resid = mlq.kl_modes(self.kd, device=device)
+        self.lam = lam
+        sl = torch.as_tensor(np.sqrt(lam), dtype=torch.float64, device=device)
+        self.levels = []
+        samp = cfg["sampling"]
+        n_shifts = samp.get("n_shifts", 1)
+        for l, lv in enumerate(cfg["levels"]):
+            # the largest batch a level sees: its own samples and, as the coarse side, level l+1's
+            nb = samp["n_per_level"][l] * n_shifts
+            if l + 1 < len(cfg["levels"]):
+                nb = max(nb, samp["n_per_level"][l + 1] * n_shifts)
+            phi = mlq.kl_transfer(self.kd, psi, lv, device=device)
+            desc, keep = mlq.make_desc(
+                lv, self.phys, n_modes=M, phi=phi, sqrt_lambda=sl, prec=self.prec, qoi=cfg["qoi"],
+                newton_tol=newton_tol if newton_tol is not None else (1e-13 if self.prec == mlq.MLQ_FP64 else 1e-10),
+                inner_tol=inner_tol if inner_tol is not None else (1e-6 if self.prec == mlq.MLQ_FP64 else 1e-5),
+                max_inner=max_inner, max_batch=nb)
+            L = mlq.Level(desc, keep, device=device)
+            L._keep = None  # arrays were copied into the level blob
+            self.levels.append(L)
+            del phi
+        del psi
+        torch.cuda.synchronize()
+        self.dof_iters = 0.0
+        self.st_dof = 0.0
+        self.log = None  # optional callable(str) for progress lines
+
+    def reset_counters(self):
+        self.dof_iters = 0.0
+        self.st_dof = 0.0
+
+    def solve(self, l: int, Y: torch.Tensor):
+        """QoIs (device FP64) of the samples Y (M x B, device FP64) on level l."""
+        L = self.levels[l]
+        theta = L.sample_fields(Y)
+        out = L.solve(theta)
+        if out["code"] != mlq.MLQ_OK:
+            st = out["status"].cpu().numpy()
+            raise mlq.MlqError(out["code"], f"{int((st != 0).sum())} samples failed on level {l}")
+        it = out["iters"]
+        B = Y.shape[1]
+        self.dof_iters += float(L.n_nodes) * float(it[:, 1].sum().item())
+        self.st_dof += float(L.n_nodes) * float(L.desc.n_steps) * B
+        if self.log is not None:
+            self.log(f"level {l}: {B} samples x {L.n_nodes} nodes x {L.desc.n_steps} steps solved")
+        return out["qoi"]
+
+    # ---- estimators -----------------------------------------------------
+    def run_mlmc(self, Ys):
+        """eq. (StandardML) with independent MC sets: Ys[l] = (M x N_l) device normals."""
+        ff, fc = [], []
+        for l, Y in enumerate(Ys):
+            ff.append(self.solve(l, Y))
+            fc.append(self.solve(l - 1, Y) if l > 0 else None)
+        return self._estimate(mlq.MLQ_EST_MLMC, ff, fc, [Y.shape[1] for Y in Ys], 1)
+
+    def run_mc(self, Y, level=0):
+        f = self.solve(level, Y)
+        return self._estimate(mlq.MLQ_EST_MC, [f], None, [Y.shape[1]], 1)
+
+    def lattice_points(self, l, shifts):
+        """Shifted lattice normals for level l: (M x S*N_l) device tensor, shift-major."""
+        N = self.cfg["sampling"]["n_per_level"][l]
+        M = self.kd.n_modes
+        gamma = self.lam / self.lam[0]
+        z = mlq.cbc(N, M, gamma)
+        cols = [mlq.lattice_normals(z, shifts[s], N, 0, N, device=self.device) for s in range(shifts.shape[0])]
+        return torch.cat(cols, dim=1)
+
+    def run_mlqmc(self, shifts_per_level, levels=None):
+        """eq. (StandardML) with randomly shifted lattice rules (shift-major sample order)."""
+        levels = range(len(self.levels)) if levels is None else levels
+        ff, fc, npl = [], [], []
+        S = shifts_per_level[0].shape[0]
+        for l in levels:
+            Y = self.lattice_points(l, shifts_per_level[l])
+            ff.append(self.solve(l, Y))
+            fc.append(self.solve(l - 1, Y) if l > 0 else None)
+            npl.append(Y.shape[1] // S)
+        return self._estimate(mlq.MLQ_EST_MLQMC, ff, fc, npl, S)
+
+    def _estimate(self, kind, ff, fc, npl, S):
+        ffh = [f.cpu().numpy() for f in ff]
+        fch = [c.cpu().numpy() if c is not None else None for c in (fc or [None] * len(ff))]
+        res = mlq.estimate(kind, ffh, fch, n_per_level=npl, n_shifts=S)
+        res["f_fine"], res["f_coarse"] = ffh, fch
+        return res

@@ -24,7 +24,9 @@ EXPORTED = [
     "mlq_level_bytes", "mlq_create_level", "mlq_destroy_level", "mlq_level_sizes", "mlq_workspace_bytes",
     "mlq_sample_fields", "mlq_solve_batch", "mlq_solve_batch_ex", "mlq_apply", "mlq_check",
     "mlq_lattice_normals", "mlq_cbc", "mlq_accumulate", "mlq_estimate", "mlq_last_error",
+    "mlq_kl_workspace_bytes", "mlq_kl_modes", "mlq_kl_transfer", "mlq_timing_enable", "mlq_timing_read",
 ]
+KERNEL_CLASSES = ["apply", "residual", "rhs", "precond", "dots", "orth", "small", "update", "qoi"]
 
 
 class MlqError(RuntimeError):
@@ -47,7 +49,20 @@ class LevelDesc(C.Structure):
         ("prec", C.c_int32), ("qoi", C.c_int32),
         ("newton_tol", C.c_double), ("inner_tol", C.c_double),
         ("max_newton", C.c_int32), ("max_inner", C.c_int32), ("max_batch", C.c_int32),
+        ("arrays_on_device", C.c_int32),
     ]
+
+
+class KlDesc(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("n", C.c_int64 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+        ("std_dev", C.c_double), ("corr_len", C.c_double),
+        ("n_modes", C.c_int32), ("max_rank", C.c_int32), ("eps", C.c_double),
+    ]
+
+
+class Timing(C.Structure):
+    _fields_ = [("ms", C.c_double * 16), ("launches", C.c_int64 * 16), ("units", C.c_double * 16)]
 
 
 class EstimateOut(C.Structure):
@@ -75,6 +90,11 @@ def _load():
         "mlq_cbc": [I64, I32, VP, VP],
         "mlq_accumulate": [VP, VP, I32, VP, VP],
         "mlq_estimate": [I32, I32, I32, VP, VP, VP, C.POINTER(EstimateOut)],
+        "mlq_kl_workspace_bytes": [C.POINTER(KlDesc), C.POINTER(C.c_size_t)],
+        "mlq_kl_modes": [C.POINTER(KlDesc), VP, C.c_size_t, VP, VP, VP, VP, VP],
+        "mlq_kl_transfer": [C.POINTER(KlDesc), VP, VP, VP, VP, VP, VP],
+        "mlq_timing_enable": [VP, C.c_uint32],
+        "mlq_timing_read": [VP, C.POINTER(Timing), I32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -124,16 +144,25 @@ def make_desc(level: dict, phys: dict, *, n_modes=0, phi=None, sqrt_lambda=None,
         setattr(d, k, float(phys[k]))
     keep = []
     d.n_modes = int(n_modes)
-    if n_modes > 0:
-        phi = np.ascontiguousarray(phi, dtype=np.float64)
-        sl = np.ascontiguousarray(sqrt_lambda, dtype=np.float64)
-        keep += [phi, sl]
-        d.phi = phi.ctypes.data_as(C.POINTER(C.c_double))
-        d.sqrt_lambda = sl.ctypes.data_as(C.POINTER(C.c_double))
-    if theta0 is not None:
-        t0 = np.ascontiguousarray(theta0, dtype=np.float64)
-        keep.append(t0)
-        d.theta0 = t0.ctypes.data_as(C.POINTER(C.c_double))
+    on_dev = n_modes > 0 and hasattr(phi, "data_ptr")
+    d.arrays_on_device = 1 if on_dev else 0
+    if on_dev:  # torch device tensors
+        keep += [phi, sqrt_lambda, theta0]
+        d.phi = C.cast(C.c_void_p(phi.data_ptr()), C.POINTER(C.c_double))
+        d.sqrt_lambda = C.cast(C.c_void_p(sqrt_lambda.data_ptr()), C.POINTER(C.c_double))
+        if theta0 is not None:
+            d.theta0 = C.cast(C.c_void_p(theta0.data_ptr()), C.POINTER(C.c_double))
+    else:
+        if n_modes > 0:
+            phi = np.ascontiguousarray(phi, dtype=np.float64)
+            sl = np.ascontiguousarray(sqrt_lambda, dtype=np.float64)
+            keep += [phi, sl]
+            d.phi = phi.ctypes.data_as(C.POINTER(C.c_double))
+            d.sqrt_lambda = sl.ctypes.data_as(C.POINTER(C.c_double))
+        if theta0 is not None:
+            t0 = np.ascontiguousarray(theta0, dtype=np.float64)
+            keep.append(t0)
+            d.theta0 = t0.ctypes.data_as(C.POINTER(C.c_double))
     d.prec, d.qoi = int(prec), int(qoi)
     d.newton_tol, d.inner_tol = float(newton_tol), float(inner_tol)
     d.max_newton, d.max_inner, d.max_batch = int(max_newton), int(max_inner), int(max_batch)
@@ -207,6 +236,18 @@ class Level:
             check(code)
         return dict(qoi=qoi, status=status, iters=iters, u=u, act=act, code=code)
 
+    def timing_enable(self, classes=("apply",)):
+        mask = 0
+        for c in classes:
+            mask |= 1 << KERNEL_CLASSES.index(c)
+        check(lib.mlq_timing_enable(self.handle, mask))
+
+    def timing_read(self, reset=True):
+        t = Timing()
+        check(lib.mlq_timing_read(self.handle, C.byref(t), 1 if reset else 0))
+        return {c: dict(ms=t.ms[i], launches=int(t.launches[i]), units=t.units[i])
+                for i, c in enumerate(KERNEL_CLASSES)}
+
     def apply(self, theta, x, d, y=None):
         import torch
         B = theta.shape[0]
@@ -258,3 +299,49 @@ def estimate(kind, f_fine, f_coarse=None, n_per_level=None, n_shifts=1):
                            C.cast(pc, C.c_void_p), C.byref(out)))
     return dict(estimate=out.estimate, rmse=out.rmse, level_mean=list(out.level_mean[:L]),
                 level_var=list(out.level_var[:L]))
+
+
+def kl_desc(dim, n, lo, hi, std_dev, corr_len, n_modes, max_rank=None, eps=1e-2):
+    d = KlDesc()
+    d.dim = int(dim)
+    for a in range(3):
+        d.n[a] = int(n[a]) if a < dim else 1
+        d.lo[a] = float(lo[a]) if a < dim else 0.0
+        d.hi[a] = float(hi[a]) if a < dim else 1.0
+    d.std_dev, d.corr_len = float(std_dev), float(corr_len)
+    d.n_modes = int(n_modes)
+    d.max_rank = int(max_rank if max_rank is not None else 2 * n_modes)
+    d.eps = float(eps)
+    return d
+
+
+def kl_modes(kd: KlDesc, device="cuda"):
+    """Returns (lambda (M,) numpy, psi (M, n) device tensor [row k = mode k], rank, relative residual)."""
+    import torch
+    nbytes = C.c_size_t()
+    check(lib.mlq_kl_workspace_bytes(C.byref(kd), C.byref(nbytes)))
+    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+    n = 1
+    for a in range(kd.dim):
+        n *= kd.n[a]
+    psi = torch.empty((kd.n_modes, n), dtype=torch.float64, device=device)  # column-major n x M
+    lam = np.zeros(kd.n_modes)
+    rank, resid = C.c_int32(), C.c_double()
+    check(lib.mlq_kl_modes(C.byref(kd), _ptr(ws), nbytes.value, lam.ctypes.data_as(C.c_void_p), _ptr(psi),
+                           C.byref(rank), C.byref(resid), _stream()))
+    del ws
+    return lam, psi, int(rank.value), float(resid.value)
+
+
+def kl_transfer(kd: KlDesc, psi, level: dict, device="cuda"):
+    """Phi_l (P x M, device FP64) at the element centres of a Q1 box level."""
+    import torch
+    dim = kd.dim
+    n = np.array([level["n"][a] if a < dim else 2 for a in range(3)], dtype=np.int64)
+    lo = np.array([level["lo"][a] if a < dim else 0.0 for a in range(3)], dtype=np.float64)
+    hi = np.array([level["hi"][a] if a < dim else 1.0 for a in range(3)], dtype=np.float64)
+    P = int(np.prod(n[:dim] - 1))
+    phi = torch.empty((P, kd.n_modes), dtype=torch.float64, device=device)
+    check(lib.mlq_kl_transfer(C.byref(kd), _ptr(psi), n.ctypes.data_as(C.c_void_p), lo.ctypes.data_as(C.c_void_p),
+                              hi.ctypes.data_as(C.c_void_p), _ptr(phi), _stream()))
+    return phi

@@ -123,6 +123,9 @@ def test_solve_fp64_3d_activation(env):
         assert np.array_equal(ra < 0, act[b] < 0)
         on = ra >= 0
         assert np.abs(act[b][on] - ra[on]).max(initial=0.0) <= 1e-10 * r["t_stop"]
+    # the mass-inverse preconditioner keeps GMRES short (mass-dominated Jacobian)
+    it = out["iters"].cpu().numpy()
+    assert (it[:, 1] / it[:, 0]).max() < 12, it
 
 
 def test_solve_fp64_ragged_3d_truncated(env):
@@ -210,3 +213,51 @@ def test_accumulate_matches_host(env):
     assert a[0] == 1010
     assert abs(a[1] - (y.sum() + ff[:10].sum())) < 1e-12
     assert abs(a[2] - ((y * y).sum() + (ff[:10] ** 2).sum())) < 1e-10
+
+
+@pytest.mark.parametrize("dim,n", [(3, [7, 6, 5]), (2, [12, 9])])
+def test_kl_modes_match_oracle_full_rank(env, dim, n):
+    torch, mlq = env
+    from oracle import fem, kl
+    from oracle.mesh import BoxMesh
+    mesh = BoxMesh(n)
+    M = fem.assemble_mass(mesh)
+    k = 8
+    lam_ref, V_ref = kl.kl_dense(mesh.nodes, M, 0.3, 0.2, k)
+    kd = mlq.kl_desc(dim, n, [0.0] * dim, [1.0] * dim, 0.3, 0.2, k, max_rank=mesh.n_nodes, eps=0.0)
+    lam, psi, rank, resid = mlq.kl_modes(kd)
+    assert rank == mesh.n_nodes and resid < 1e-12
+    assert np.allclose(lam, lam_ref, rtol=1e-10, atol=0)
+    P = psi.cpu().numpy().T  # (n, k)
+    assert np.abs(P.T @ (M @ P) - np.eye(k)).max() < 1e-10
+    gaps = np.abs(np.diff(lam_ref)) > 1e-6 * lam_ref[0]
+    for j in range(k - 1):
+        if gaps[j] and (j == 0 or gaps[j - 1]):  # simple eigenvalue: same mode and sign
+            ref = V_ref[:, j] / np.sqrt(lam_ref[j])
+            assert np.abs(P[:, j] - ref).max() < 1e-8 * np.abs(ref).max()
+
+
+def test_kl_truncated_and_transfer_match_oracle(env):
+    torch, mlq = env
+    from oracle import fem, kl
+    from oracle.mesh import BoxMesh
+    fine = BoxMesh([17, 17, 17])
+    M = fem.assemble_mass(fine)
+    k, R = 12, 40
+    L, _ = kl.pivoted_cholesky(fine.nodes, 0.3, 0.1, R)
+    lam_ref, V_ref = kl.kl_from_cholesky(L, M, k)
+    kd = mlq.kl_desc(3, [17] * 3, [0.0] * 3, [1.0] * 3, 0.3, 0.1, k, max_rank=R, eps=0.0)
+    lam, psi, rank, resid = mlq.kl_modes(kd)
+    assert rank == R
+    assert np.allclose(lam, lam_ref, rtol=1e-9, atol=0)
+    tr = 0.09 * fine.n_nodes
+    assert abs(resid - (tr - np.sum(L * L)) / tr) < 1e-10
+    # midpoint transfer of the oracle's own modes to a nested coarse level and to the KL grid itself
+    psi_ref = V_ref / np.sqrt(lam_ref)
+    psi_d = torch.as_tensor(np.ascontiguousarray(psi_ref.T), device="cuda")
+    for nc in (5, 9, 17):
+        coarse = BoxMesh([nc] * 3)
+        lv = dict(dim=3, n=[nc] * 3, lo=[0.0] * 3, hi=[1.0] * 3)
+        phi = mlq.kl_transfer(kd, psi_d, lv).cpu().numpy()
+        ref = kl.level_basis(fine, psi_ref, coarse)
+        assert np.abs(phi - ref).max() <= 1e-14 * np.abs(ref).max()
