@@ -202,11 +202,13 @@ void sizes_of(const mlq_level_desc* d, int64_t* nn, int64_t* P) {
 
 namespace mlq {
 
-Work carve_workspace(void* base, int64_t nn, int64_t P, int32_t B, int kmax, bool mixed) {
+Work carve_workspace(void* base, const Geo& geo, int32_t B, int kmax, bool mixed) {
   Work w{};
+  const int64_t nn = geo.nn, P = geo.P;
   w.kmax = kmax;
   w.nblk = (int32_t)cdiv(nn, kBlock);
   w.nred = (int32_t)cdiv(nn, kRedChunk);
+  w.nres = geo.dim == 3 ? stencil3_blocks(geo) : w.nblk;
   const size_t ti = mixed ? sizeof(float) : sizeof(double);
   const size_t vn = (size_t)nn * B;
   char* p = (char*)base;
@@ -225,8 +227,9 @@ Work carve_workspace(void* base, int64_t nn, int64_t P, int32_t B, int kmax, boo
   w.w = take(vn * ti);
   w.V = take(vn * ti * (kmax + 1));
   w.coef = take((size_t)P * B * 2 * ti);
-  const size_t npart = std::max((size_t)w.nblk * 3, (size_t)w.nred * (kmax + 1));
+  const size_t npart = std::max((size_t)std::max(w.nblk, w.nres) * 3, (size_t)w.nred * (kmax + 1));
   w.part = (double*)take(npart * B * sizeof(double));
+  w.dpart = (double*)take((size_t)w.nred * (kmax + 1) * B * sizeof(double));
   w.H = (double*)take((size_t)B * (kmax + 1) * kmax * sizeof(double));
   w.cs = (double*)take((size_t)B * kmax * sizeof(double));
   w.sn = (double*)take((size_t)B * kmax * sizeof(double));
@@ -310,6 +313,9 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
     g.Hzz = 0.0;
     g.Hxy = 1.0;
   }
+  g.Hx = hx;
+  g.Hy = hy;
+  g.Hz = hz;
   g.sbar = 0.5 * (desc->sigma_l + desc->sigma_t);
   g.st = desc->sigma_t;
   lv->io = Ionic{desc->alpha, desc->u_rest, desc->u_th, desc->u_peak, desc->t_end / desc->n_steps};
@@ -465,7 +471,7 @@ mlq_status mlq_level_sizes(const mlq_level* level, int64_t* n_nodes, int64_t* n_
 mlq_status mlq_workspace_bytes(const mlq_level* level, int32_t batch, size_t* ws_bytes) {
   if (level == nullptr || ws_bytes == nullptr) return fail(MLQ_EINVAL, "NULL argument");
   if (batch < 1 || batch > level->d.max_batch) return fail(MLQ_EINVAL, "batch %d outside [1, max_batch]", batch);
-  *ws_bytes = carve_workspace(nullptr, level->nn, level->P, batch, level->kmax, level->mixed).bytes;
+  *ws_bytes = carve_workspace(nullptr, level->geo, batch, level->kmax, level->mixed).bytes;
   return MLQ_OK;
 }
 
@@ -485,11 +491,14 @@ mlq_status mlq_apply(mlq_level* level, const void* theta_dev, int32_t batch, con
       ws_dev == nullptr)
     return fail(MLQ_EINVAL, "NULL argument");
   if (batch < 1 || batch > level->d.max_batch) return fail(MLQ_EINVAL, "batch %d outside [1, max_batch]", batch);
-  Work w = carve_workspace(ws_dev, level->nn, level->P, batch, level->kmax, level->mixed);
+  Work w = carve_workspace(ws_dev, level->geo, batch, level->kmax, level->mixed);
   if (ws_bytes < w.bytes) return fail(MLQ_ESIZE, "workspace too small: %zu < %zu", ws_bytes, w.bytes);
   hipStream_t s = (hipStream_t)hip_stream;
   launch_coefs(theta_dev, w.coef, level->P, batch, 0.5 * (level->d.sigma_l - level->d.sigma_t), level->mixed, s);
-  launch_apply_public(level->geo, w.coef, x_dev, d_dev, y_dev, 0.5 * level->io.dt, batch, level->mixed, s);
+  if (level->geo.dim == 3)
+    launch_apply_full3(level->geo, w.coef, x_dev, d_dev, y_dev, 0.5 * level->io.dt, batch, level->mixed, s);
+  else
+    launch_apply_public(level->geo, w.coef, x_dev, d_dev, y_dev, 0.5 * level->io.dt, batch, level->mixed, s);
   HIP_OK(hipGetLastError());
   return MLQ_OK;
 }
@@ -511,7 +520,7 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
   if (batch < 1 || batch > level->d.max_batch) return fail(MLQ_EINVAL, "batch %d outside [1, max_batch]", batch);
   if (n_steps < 0 || n_steps > level->d.n_steps) return fail(MLQ_EINVAL, "n_steps %d outside [0, %d]", n_steps, level->d.n_steps);
   if (((uintptr_t)ws_dev & 255) != 0) return fail(MLQ_EINVAL, "workspace must be 256-byte aligned");
-  Work w = carve_workspace(ws_dev, level->nn, level->P, batch, level->kmax, level->mixed);
+  Work w = carve_workspace(ws_dev, level->geo, batch, level->kmax, level->mixed);
   if (ws_bytes < w.bytes) return fail(MLQ_ESIZE, "workspace too small: %zu < %zu", ws_bytes, w.bytes);
   hipStream_t s = (hipStream_t)hip_stream;
   const mlq_level_desc& d = level->d;
@@ -529,11 +538,21 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
   for (int32_t k = 0; k < n_steps; ++k) {
     const double t0 = (double)k * dt, t1 = (double)(k + 1) * dt;
     const double load = 0.5 * dt * (rate(t1) + rate(t0));
-    timed(level, MLQ_K_RHS, nn * batch, s, [&] { launch_rhs(g, w, level->fbox, load, dt, batch, mixed, s); });
+    timed(level, MLQ_K_RHS, nn * batch, s, [&] {
+      if (g.dim == 3)
+        launch_rhs3(g, w, level->fbox, load, dt, batch, mixed, s);
+      else
+        launch_rhs(g, w, level->fbox, load, dt, batch, mixed, s);
+    });
     launch_newton_reset(w, batch, s);
     int32_t active = batch;
     for (int it = 0;; ++it) {
-      timed(level, MLQ_K_RESIDUAL, nn * active, s, [&] { launch_residual(g, level->io, w, batch, mixed, s); });
+      timed(level, MLQ_K_RESIDUAL, nn * active, s, [&] {
+        if (g.dim == 3)
+          launch_residual3(g, level->io, w, batch, mixed, s);
+        else
+          launch_residual(g, level->io, w, batch, mixed, s);
+      });
       timed(level, MLQ_K_SMALL, 0.0, s, [&] {
         launch_newton_check(g, w, batch, d.newton_tol, s);
         launch_count(w.newton_active, batch, w.counter, s);
@@ -550,7 +569,12 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
         const double units = nn * inner;
         timed(level, MLQ_K_PRECOND, units, s,
               [&] { launch_minv_basis(g, w, level->tri, level->nmax, j, batch, mixed, s); });
-        timed(level, MLQ_K_APPLY, units, s, [&] { launch_apply_pk(g, w, j, 0.5 * dt, batch, mixed, s); });
+        timed(level, MLQ_K_APPLY, units, s, [&] {
+          if (g.dim == 3)
+            launch_apply_pk3(g, w, j, 0.5 * dt, batch, mixed, s);
+          else
+            launch_apply_pk(g, w, j, 0.5 * dt, batch, mixed, s);
+        });
         timed(level, MLQ_K_DOTS, units, s, [&] { launch_dots(g, w, j, batch, mixed, s); });
         timed(level, MLQ_K_ORTH, units, s, [&] { launch_orth(g, w, j, batch, mixed, s); });
         timed(level, MLQ_K_SMALL, 0.0, s, [&] {

@@ -21,6 +21,7 @@ struct Geo {
   int64_t nn;          // nodes per sample
   int64_t P;           // elements per sample
   double Hm, Hxx, Hyy, Hzz, Hxy;
+  double Hx, Hy, Hz;   // edge lengths
   double sbar;         // (sigma_l + sigma_t) / 2
   double st;           // sigma_t
 };
@@ -52,7 +53,8 @@ struct Work {
   // per element coefficients [B][P][2] (inner precision)
   void* coef;
   // per-sample small arrays
-  double* part;      // reduction partials
+  double* part;      // reduction partials (residual norms, Gram-Schmidt norms)
+  double* dpart;     // Gram-Schmidt projection partials [B][kmax+1][nred]
   double* H;         // [B][kmax+1][kmax] Hessenberg
   double* cs;        // [B][kmax]
   double* sn;        // [B][kmax]
@@ -70,11 +72,12 @@ struct Work {
   int kmax;                // GMRES iterations per solve (basis holds kmax + 1 vectors)
   int32_t nblk;            // blocks per sample of the nodal kernels
   int32_t nred;            // blocks per sample of the reduction kernels
+  int32_t nres;            // blocks per sample of the residual kernel (partial norms)
   size_t bytes;
 };
 
 // Carves the workspace for a batch.  With base == nullptr only computes bytes.
-Work carve_workspace(void* base, int64_t nn, int64_t P, int32_t batch, int kmax, bool mixed);
+Work carve_workspace(void* base, const Geo& g, int32_t batch, int kmax, bool mixed);
 
 // ---- kernel launchers (mlq_kernels.hip) --------------------------------------
 void launch_coefs(const void* theta, void* coef, int64_t P, int32_t B, double half_dsig, bool mixed,
@@ -118,6 +121,13 @@ void launch_minv_basis(const Geo& g, const Work& w, const void* tri, int nmax, i
 void launch_apply_pk(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s);
 void launch_update_pm(const Geo& g, const Work& w, const void* tri, int nmax, int32_t B, bool mixed, hipStream_t s);
 hipError_t prepare_minv_kernels(size_t bytes);
+int32_t stencil3_blocks(const Geo& g);
+void launch_apply_pk3(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s);
+void launch_apply_full3(const Geo& g, const void* coef, const void* x, const void* d, void* y, double ck, int32_t B,
+                        bool mixed, hipStream_t s);
+void launch_residual3(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);
+void launch_rhs3(const Geo& g, const Work& w, const double* fbox, double load_coef, double dt, int32_t B, bool mixed,
+                 hipStream_t s);
 void launch_cast_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
 }  // namespace mlq

@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_newton_check(const double* __restric
 
 
 void launch_newton_check(const Geo& g, const Work& w, int32_t B, double tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_newton_check, dim3(B), dim3(kBlock), 0, s, w.part, w.nblk, tol, w.newton_active,
+  hipLaunchKernelGGL(k_newton_check, dim3(B), dim3(kBlock), 0, s, w.part, w.nres, tol, w.newton_active,
                      w.inner_active, w.inner_k, w.status, w.beta, w.g, w.inv_eta, w.kmax);
 }
 
@@ -505,22 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_dots(int64_t nn, const T* __restrict
     double acc = 0.0;
     for (int64_t t = base + threadIdx.x; t < end; t += kBlock) acc += (double)ws[t] * (double)vi[t];
     acc = block_sum<kBlock>(acc, sh);
-    if (threadIdx.x == 0) part[((int64_t)sb * gridDim.x + blockIdx.x) * (kmax + 1) + i] = acc;
-  }
-}
-
-// h_ij = inv_eta_i sum_blk part; hc_i = h_ij inv_eta_i (coefficient on the stored vector).
-__global__ void k_dots_final(const double* __restrict__ part, int32_t nred, int j, int kmax, double* H, double* hc,
-                             const double* __restrict__ inv_eta, const int32_t* __restrict__ active) {
-  const int sb = blockIdx.x;
-  if (active[sb] == 0) return;
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-    double acc = 0.0;
-    for (int b = 0; b < nred; ++b) acc += part[((int64_t)sb * nred + b) * (kmax + 1) + i];
-    const double ie = inv_eta[(int64_t)sb * (kmax + 1) + i];
-    const double h = acc * ie;
-    H[((int64_t)sb * (kmax + 1) + i) * kmax + j] = h;
-    hc[(int64_t)sb * (kmax + 1) + i] = h * ie;
+    if (threadIdx.x == 0) part[((int64_t)sb * (kmax + 1) + i) * gridDim.x + blockIdx.x] = acc;
   }
 }
 
@@ -529,24 +514,38 @@ void launch_dots(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipS
   const size_t vs = (size_t)g.nn * B;
   if (mixed)
     hipLaunchKernelGGL((k_dots<float>), grid, dim3(kBlock), 0, s, g.nn, (const float*)w.w, (const float*)w.V, vs,
-                       j, w.kmax, w.part, w.inner_active);
+                       j, w.kmax, w.dpart, w.inner_active);
   else
     hipLaunchKernelGGL((k_dots<double>), grid, dim3(kBlock), 0, s, g.nn, (const double*)w.w, (const double*)w.V,
-                       vs, j, w.kmax, w.part, w.inner_active);
-  hipLaunchKernelGGL(k_dots_final, dim3(B), dim3(64), 0, s, w.part, w.nred, j, w.kmax, w.H, w.hc, w.inv_eta,
-                     w.inner_active);
+                       vs, j, w.kmax, w.dpart, w.inner_active);
 }
 
-// Vs_{j+1} = w - sum_i hc_i Vs_i, partial |Vs_{j+1}|^2.
+// Vs_{j+1} = w - sum_i hc_i Vs_i, partial |Vs_{j+1}|^2.  Each block first sums the
+// projection partials of k_dots (one wave per coefficient, fixed order):
+// h_ij = inv_eta_i sum_blk part, hc_i = h_ij inv_eta_i; block 0 stores column j of H.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_orth(int64_t nn, const T* __restrict__ w, T* __restrict__ V, size_t vs,
-                                                 int j, int kmax, const double* __restrict__ hc,
+                                                 int j, int kmax, const double* __restrict__ dpart,
+                                                 const double* __restrict__ inv_eta, double* __restrict__ H,
                                                  double* __restrict__ part, const int32_t* __restrict__ active) {
   const int sb = blockIdx.y;
   if (active[sb] == 0) return;
   __shared__ double sh[kBlock / 64];
   __shared__ double c[kMaxInner + 1];
-  for (int i = threadIdx.x; i <= j; i += kBlock) c[i] = hc[(int64_t)sb * (kmax + 1) + i];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nred = gridDim.x;
+  for (int i = wid; i <= j; i += kBlock / 64) {
+    const double* pi = dpart + ((int64_t)sb * (kmax + 1) + i) * nred;
+    double a = 0.0;
+    for (int b = lane; b < nred; b += 64) a += pi[b];
+    a = wave_sum(a);
+    if (lane == 0) {
+      const double ie = inv_eta[(int64_t)sb * (kmax + 1) + i];
+      const double h = a * ie;
+      c[i] = h * ie;
+      if (blockIdx.x == 0) H[((int64_t)sb * (kmax + 1) + i) * kmax + j] = h;
+    }
+  }
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kRedChunk;
   const int64_t end = base + kRedChunk < nn ? base + kRedChunk : nn;
@@ -569,10 +568,10 @@ void launch_orth(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipS
   const size_t vs = (size_t)g.nn * B;
   if (mixed)
     hipLaunchKernelGGL((k_orth<float>), grid, dim3(kBlock), 0, s, g.nn, (const float*)w.w, (float*)w.V, vs, j,
-                       w.kmax, w.hc, w.part, w.inner_active);
+                       w.kmax, w.dpart, w.inv_eta, w.H, w.part, w.inner_active);
   else
     hipLaunchKernelGGL((k_orth<double>), grid, dim3(kBlock), 0, s, g.nn, (const double*)w.w, (double*)w.V, vs, j,
-                       w.kmax, w.hc, w.part, w.inner_active);
+                       w.kmax, w.dpart, w.inv_eta, w.H, w.part, w.inner_active);
 }
 
 // Norm of the new vector, Givens rotations of column j, residual estimate |g_{j+1}|.
@@ -885,11 +884,39 @@ __device__ inline void thomas_line(T* a, int n, int stride, const T* __restrict_
   }
 }
 
+// Same elimination with the line length known at compile time (fully unrolled,
+// so the LDS loads of later entries are issued ahead of the recurrence).
+template <int N, typename T>
+__device__ inline void thomas_fixed(T* a, int stride, const T* __restrict__ iv) {
+  T v[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = a[i * stride];
+  T prev = v[0] * iv[0];
+  v[0] = prev;
+#pragma unroll
+  for (int i = 1; i < N; ++i) {
+    prev = (v[i] - prev) * iv[i];
+    v[i] = prev;
+  }
+#pragma unroll
+  for (int i = N - 2; i >= 0; --i) v[i] = v[i] - iv[i] * v[i + 1];
+#pragma unroll
+  for (int i = 0; i < N; ++i) a[i * stride] = v[i];
+}
+
+template <int N, typename T>
+__device__ inline void sweep(T* a, int n, int stride, const T* __restrict__ iv) {
+  if constexpr (N > 0)
+    thomas_fixed<N, T>(a, stride, iv);
+  else
+    thomas_line(a, n, stride, iv);
+}
+
 enum { kOutPlain = 0, kOutDivD = 1, kOutAddU = 2 };
 
 // x and y sweeps of one z-plane of one sample in LDS.  Input scaled by
 // c6 * inv_eta[j] (c6 = prod 6/h_a) when inv_eta != nullptr, by c6 otherwise.
-template <typename T, int OUT>
+template <typename T, int OUT, int N>
 __global__ __launch_bounds__(kBlock) void k_minv_xy(Geo g, const T* __restrict__ in, T* __restrict__ out,
                                                     const double* __restrict__ inv_eta, int j, int kmax, double c6,
                                                     const T* __restrict__ ivx, const T* __restrict__ ivy,
@@ -904,9 +931,9 @@ __global__ __launch_bounds__(kBlock) void k_minv_xy(Geo g, const T* __restrict__
   const T s = (T)(c6 * (inv_eta != nullptr ? inv_eta[(int64_t)sb * (kmax + 1) + j] : 1.0));
   for (int t = threadIdx.x; t < np; t += kBlock) sh[t] = in[base + t] * s;
   __syncthreads();
-  for (int r = threadIdx.x; r < ny; r += kBlock) thomas_line(sh + r * nx, nx, 1, ivx);
+  for (int r = threadIdx.x; r < ny; r += kBlock) sweep<N, T>(sh + r * nx, nx, 1, ivx);
   __syncthreads();
-  for (int c = threadIdx.x; c < nx; c += kBlock) thomas_line(sh + c, ny, nx, ivy);
+  for (int c = threadIdx.x; c < nx; c += kBlock) sweep<N, T>(sh + c, ny, nx, ivy);
   __syncthreads();
   for (int t = threadIdx.x; t < np; t += kBlock) {
     T v = sh[t];
@@ -923,7 +950,7 @@ __global__ __launch_bounds__(kBlock) void k_minv_xy(Geo g, const T* __restrict__
 }
 
 // z sweeps of one x-z plane (fixed y) of one sample in LDS, then the division by (1 + d).
-template <typename T, int OUT>
+template <typename T, int OUT, int N>
 __global__ __launch_bounds__(kBlock) void k_minv_z(Geo g, const T* __restrict__ in, T* __restrict__ out,
                                                    const T* __restrict__ ivz, const T* __restrict__ d,
                                                    double* __restrict__ u, const int32_t* __restrict__ active) {
@@ -937,7 +964,7 @@ __global__ __launch_bounds__(kBlock) void k_minv_z(Geo g, const T* __restrict__ 
   const int np = nx * nz;
   for (int t = threadIdx.x; t < np; t += kBlock) sh[t] = in[base + (int64_t)(t / nx) * plane + (t % nx)];
   __syncthreads();
-  for (int c = threadIdx.x; c < nx; c += kBlock) thomas_line(sh + c, nz, nx, ivz);
+  for (int c = threadIdx.x; c < nx; c += kBlock) sweep<N, T>(sh + c, nz, nx, ivz);
   __syncthreads();
   for (int t = threadIdx.x; t < np; t += kBlock) {
     const int64_t o = base + (int64_t)(t / nx) * plane + (t % nx);
@@ -950,10 +977,11 @@ __global__ __launch_bounds__(kBlock) void k_minv_z(Geo g, const T* __restrict__ 
 }
 
 // z <- P^-1 (scale * src); with add_u the result is added to u instead (FP64).
-template <typename T>
-static void minv_dispatch(const Geo& g, const T* src, T* tmp, T* dst, const double* inv_eta, int j, int kmax,
-                          const T* tri, int nmax, const T* d, double* u, bool add_u, const int32_t* active,
-                          int32_t B, hipStream_t s) {
+// N: common line length of all axes when it is one of the unrolled sizes, else 0.
+template <typename T, int N>
+static void minv_launch(const Geo& g, const T* src, T* tmp, T* dst, const double* inv_eta, int j, int kmax,
+                        const T* tri, int nmax, const T* d, double* u, bool add_u, const int32_t* active, int32_t B,
+                        hipStream_t s) {
   const T* ivx = tri;
   const T* ivy = tri + nmax;
   const T* ivz = tri + 2 * nmax;
@@ -961,22 +989,41 @@ static void minv_dispatch(const Geo& g, const T* src, T* tmp, T* dst, const doub
     const double c6 = 36.0 / g.Hm;
     const size_t sh = sizeof(T) * (size_t)g.nx * g.ny;
     if (add_u)
-      hipLaunchKernelGGL((k_minv_xy<T, kOutAddU>), dim3(1, B), dim3(kBlock), sh, s, g, src, dst, inv_eta, j, kmax, c6,
-                         ivx, ivy, d, u, active);
+      hipLaunchKernelGGL((k_minv_xy<T, kOutAddU, N>), dim3(1, B), dim3(kBlock), sh, s, g, src, dst, inv_eta, j, kmax,
+                         c6, ivx, ivy, d, u, active);
     else
-      hipLaunchKernelGGL((k_minv_xy<T, kOutDivD>), dim3(1, B), dim3(kBlock), sh, s, g, src, dst, inv_eta, j, kmax, c6,
-                         ivx, ivy, d, u, active);
+      hipLaunchKernelGGL((k_minv_xy<T, kOutDivD, N>), dim3(1, B), dim3(kBlock), sh, s, g, src, dst, inv_eta, j, kmax,
+                         c6, ivx, ivy, d, u, active);
     return;
   }
   const double c6 = 216.0 / g.Hm;
   const size_t shxy = sizeof(T) * (size_t)g.nx * g.ny;
   const size_t shxz = sizeof(T) * (size_t)g.nx * g.nz;
-  hipLaunchKernelGGL((k_minv_xy<T, kOutPlain>), dim3(g.nz, B), dim3(kBlock), shxy, s, g, src, tmp, inv_eta, j, kmax,
-                     c6, ivx, ivy, d, u, active);
+  hipLaunchKernelGGL((k_minv_xy<T, kOutPlain, N>), dim3(g.nz, B), dim3(kBlock), shxy, s, g, src, tmp, inv_eta, j,
+                     kmax, c6, ivx, ivy, d, u, active);
   if (add_u)
-    hipLaunchKernelGGL((k_minv_z<T, kOutAddU>), dim3(g.ny, B), dim3(kBlock), shxz, s, g, tmp, dst, ivz, d, u, active);
+    hipLaunchKernelGGL((k_minv_z<T, kOutAddU, N>), dim3(g.ny, B), dim3(kBlock), shxz, s, g, tmp, dst, ivz, d, u,
+                       active);
   else
-    hipLaunchKernelGGL((k_minv_z<T, kOutDivD>), dim3(g.ny, B), dim3(kBlock), shxz, s, g, tmp, dst, ivz, d, u, active);
+    hipLaunchKernelGGL((k_minv_z<T, kOutDivD, N>), dim3(g.ny, B), dim3(kBlock), shxz, s, g, tmp, dst, ivz, d, u,
+                       active);
+}
+
+template <typename T>
+static void minv_dispatch(const Geo& g, const T* src, T* tmp, T* dst, const double* inv_eta, int j, int kmax,
+                          const T* tri, int nmax, const T* d, double* u, bool add_u, const int32_t* active,
+                          int32_t B, hipStream_t s) {
+  const bool cube = g.nx == g.ny && (g.dim == 2 || g.nz == g.nx);
+  const int n = cube ? g.nx : 0;
+#define MLQ_MINV(NN) minv_launch<T, NN>(g, src, tmp, dst, inv_eta, j, kmax, tri, nmax, d, u, add_u, active, B, s)
+  switch (n) {
+    case 9: MLQ_MINV(9); break;
+    case 17: MLQ_MINV(17); break;
+    case 33: MLQ_MINV(33); break;
+    case 65: MLQ_MINV(65); break;
+    default: MLQ_MINV(0); break;
+  }
+#undef MLQ_MINV
 }
 
 // GMRES preconditioner step: z = P^-1 v_j (v_j = stored basis vector times inv_eta_j); w is scratch.
@@ -1079,19 +1126,20 @@ hipError_t prepare_minv_kernels(size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
   const int b = (int)bytes;
   hipError_t e = hipSuccess;
-#define MLQ_ATTR(K)                                                                                    \
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)(K), hipFuncAttributeMaxDynamicSharedMemorySize, b)
-  MLQ_ATTR((k_minv_xy<double, kOutPlain>));
-  MLQ_ATTR((k_minv_xy<double, kOutDivD>));
-  MLQ_ATTR((k_minv_xy<double, kOutAddU>));
-  MLQ_ATTR((k_minv_z<double, kOutDivD>));
-  MLQ_ATTR((k_minv_z<double, kOutAddU>));
-  MLQ_ATTR((k_minv_xy<float, kOutPlain>));
-  MLQ_ATTR((k_minv_xy<float, kOutDivD>));
-  MLQ_ATTR((k_minv_xy<float, kOutAddU>));
-  MLQ_ATTR((k_minv_z<float, kOutDivD>));
-  MLQ_ATTR((k_minv_z<float, kOutAddU>));
-#undef MLQ_ATTR
+  auto set = [&](const void* k) {
+    if (e == hipSuccess) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  };
+  // planes above 64 KB only occur for lines longer than the unrolled sizes (N = 0)
+  set((const void*)(k_minv_xy<double, kOutPlain, 0>));
+  set((const void*)(k_minv_xy<double, kOutDivD, 0>));
+  set((const void*)(k_minv_xy<double, kOutAddU, 0>));
+  set((const void*)(k_minv_z<double, kOutDivD, 0>));
+  set((const void*)(k_minv_z<double, kOutAddU, 0>));
+  set((const void*)(k_minv_xy<float, kOutPlain, 0>));
+  set((const void*)(k_minv_xy<float, kOutDivD, 0>));
+  set((const void*)(k_minv_xy<float, kOutAddU, 0>));
+  set((const void*)(k_minv_z<float, kOutDivD, 0>));
+  set((const void*)(k_minv_z<float, kOutAddU, 0>));
   return e;
 }
 
