@@ -368,10 +368,11 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
       tri32[a * nmax + i] = (float)prev;
     }
   }
-  // LDS planes of the preconditioner: x-y and x-z planes of one sample
+  // LDS staging of the preconditioner's line solves
   {
     const size_t ti = lv->mixed ? sizeof(float) : sizeof(double);
-    const size_t plane = ti * (size_t)desc->n[0] * (size_t)std::max(desc->n[1], dim == 3 ? desc->n[2] : 1);
+    // 2D: one x-y plane per workgroup; 3D: 64 x-rows per workgroup
+    const size_t plane = dim == 3 ? ti * 64 * (size_t)desc->n[0] : ti * (size_t)desc->n[0] * (size_t)desc->n[1];
     int dev = 0;
     hipDeviceProp_t prop{};
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {

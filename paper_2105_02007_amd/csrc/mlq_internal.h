@@ -128,6 +128,8 @@ void launch_apply_full3(const Geo& g, const void* coef, const void* x, const voi
 void launch_residual3(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);
 void launch_rhs3(const Geo& g, const Work& w, const double* fbox, double load_coef, double dt, int32_t B, bool mixed,
                  hipStream_t s);
+void launch_apply_pk3_lds(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s);
+void launch_residual3_lds(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);
 void launch_cast_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
 }  // namespace mlq

@@ -1009,12 +1009,32 @@ static void minv_launch(const Geo& g, const T* src, T* tmp, T* dst, const double
                        active);
 }
 
+template <typename T, int N>
+static void lines3(const Geo& g, const T* src, T* tmp, T* dst, const double* inv_eta, int j, int kmax,
+                   const T* tri, int nmax, const T* d, double* u, bool add_u, const int32_t* active, int32_t B,
+                   hipStream_t s);
+
 template <typename T>
 static void minv_dispatch(const Geo& g, const T* src, T* tmp, T* dst, const double* inv_eta, int j, int kmax,
                           const T* tri, int nmax, const T* d, double* u, bool add_u, const int32_t* active,
                           int32_t B, hipStream_t s) {
   const bool cube = g.nx == g.ny && (g.dim == 2 || g.nz == g.nx);
-  const int n = cube ? g.nx : 0;
+  int n = cube ? g.nx : 0;
+  if (g.dim == 3) {
+    // registers hold one line: FP64 lines of 129 fall back to the runtime-length path
+    if (n == 129 && sizeof(T) == 8) n = 0;
+#define MLQ_L3(NN) lines3<T, NN>(g, src, tmp, dst, inv_eta, j, kmax, tri, nmax, d, u, add_u, active, B, s)
+    switch (n) {
+      case 9: MLQ_L3(9); break;
+      case 17: MLQ_L3(17); break;
+      case 33: MLQ_L3(33); break;
+      case 65: MLQ_L3(65); break;
+      case 129: MLQ_L3(129); break;
+      default: MLQ_L3(0); break;
+    }
+#undef MLQ_L3
+    return;
+  }
 #define MLQ_MINV(NN) minv_launch<T, NN>(g, src, tmp, dst, inv_eta, j, kmax, tri, nmax, d, u, add_u, active, B, s)
   switch (n) {
     case 9: MLQ_MINV(9); break;
@@ -1119,6 +1139,173 @@ void launch_update_pm(const Geo& g, const Work& w, const void* tri, int nmax, in
 
 }  // namespace mlq
 
+
+namespace mlq {
+
+// ---------------------------------------------------------------------------
+// 3D mass inverse as three batches of independent line solves (one thread per
+// line, the line in registers):
+//   x: 64 consecutive rows per wave, staged through LDS so that global accesses
+//      stay contiguous; y and z: one thread per line, neighbouring threads on
+//      neighbouring x (contiguous loads).
+// N: line length when it is one of the unrolled sizes (0: runtime length).
+
+template <int N, typename T>
+__device__ inline void thomas_regs(T (&v)[N], const T* __restrict__ iv) {
+  T prev = v[0] * iv[0];
+  v[0] = prev;
+#pragma unroll
+  for (int i = 1; i < N; ++i) {
+    prev = (v[i] - prev) * iv[i];
+    v[i] = prev;
+  }
+#pragma unroll
+  for (int i = N - 2; i >= 0; --i) v[i] = v[i] - iv[i] * v[i + 1];
+}
+
+constexpr int kRowsPerBlock = 64;
+
+// x lines: rows r of the whole batch (row r = nodes r*nx .. r*nx + nx - 1, sample r / rows_per_sample).
+// 256 threads stage 64 rows through LDS with contiguous accesses; 64 of them solve.
+template <typename T, int N>
+__global__ __launch_bounds__(kBlock) void k_line_x(const T* __restrict__ in, T* __restrict__ out, int nx,
+                                                   int64_t rows_per_sample, int64_t total_rows,
+                                                   const double* __restrict__ inv_eta, int j, int kmax, double c6,
+                                                   const T* __restrict__ iv, const int32_t* __restrict__ active) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sh = reinterpret_cast<T*>(smem_raw);
+  const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
+  const int nrows = (int)((total_rows - r0) < kRowsPerBlock ? (total_rows - r0) : kRowsPerBlock);
+  const int64_t base = r0 * nx;
+  const int cnt = nrows * nx;
+  const int sb0 = (int)(r0 / rows_per_sample);
+  const int sb1 = (int)((r0 + nrows - 1) / rows_per_sample);
+  auto scale_of = [&](int sb) -> T {
+    double sc = c6;
+    if (inv_eta != nullptr) sc *= inv_eta[(int64_t)sb * (kmax + 1) + j];
+    return active[sb] ? (T)sc : (T)0;
+  };
+  if (sb0 == sb1) {  // the usual case: all 64 rows in one sample
+    const T sc = scale_of(sb0);
+    if (active[sb0] == 0) return;
+    for (int t = threadIdx.x; t < cnt; t += kBlock) sh[t] = in[base + t] * sc;
+  } else {
+    const int64_t split = (int64_t)sb1 * rows_per_sample - r0;  // first row of sample sb1, block-relative
+    const T s0 = scale_of(sb0), s1 = scale_of(sb1);
+    for (int t = threadIdx.x; t < cnt; t += kBlock) sh[t] = in[base + t] * ((t / nx) < split ? s0 : s1);
+  }
+  __syncthreads();
+  if (threadIdx.x < nrows) {
+    T* a = sh + threadIdx.x * nx;
+    if constexpr (N > 0) {
+      T v[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) v[i] = a[i];
+      thomas_regs<N, T>(v, iv);
+#pragma unroll
+      for (int i = 0; i < N; ++i) a[i] = v[i];
+    } else {
+      thomas_line(a, nx, 1, iv);
+    }
+  }
+  __syncthreads();
+  if (sb0 == sb1) {
+    for (int t = threadIdx.x; t < cnt; t += kBlock) out[base + t] = sh[t];
+  } else {
+    const int64_t split = (int64_t)sb1 * rows_per_sample - r0;
+    const bool a0 = active[sb0] != 0, a1 = active[sb1] != 0;
+    for (int t = threadIdx.x; t < cnt; t += kBlock)
+      if ((t / nx) < split ? a0 : a1) out[base + t] = sh[t];
+  }
+}
+
+// y or z lines of one sample (blockIdx.y): thread per line, line id = x + nx * other.
+template <typename T, int N, int AXIS, int OUT>
+__global__ __launch_bounds__(kBlock) void k_line_yz(const T* __restrict__ in, T* __restrict__ out, Geo g,
+                                                    const T* __restrict__ iv, const T* __restrict__ d,
+                                                    double* __restrict__ u, const int32_t* __restrict__ active) {
+  const int sb = blockIdx.y;
+  if (active[sb] == 0) return;
+  const int L = blockIdx.x * kBlock + threadIdx.x;
+  int64_t base, stride;
+  int n;
+  if (AXIS == 1) {
+    if (L >= g.nx * g.nz) return;
+    const int x = L % g.nx, z = L / g.nx;
+    base = (int64_t)z * g.nx * g.ny + x;
+    stride = g.nx;
+    n = g.ny;
+  } else {
+    if (L >= g.nx * g.ny) return;
+    base = L;
+    stride = (int64_t)g.nx * g.ny;
+    n = g.nz;
+  }
+  base += (int64_t)sb * g.nn;
+  auto emit = [&](int64_t o, T v) {
+    if (OUT == kOutPlain) {
+      out[o] = v;
+    } else {
+      v = v / ((T)1 + d[o]);
+      if (OUT == kOutDivD)
+        out[o] = v;
+      else
+        u[o] += (double)v;
+    }
+  };
+  if constexpr (N > 0) {
+    T v[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = in[base + i * stride];
+    thomas_regs<N, T>(v, iv);
+#pragma unroll
+    for (int i = 0; i < N; ++i) emit(base + i * stride, v[i]);
+  } else {
+    // runtime length: forward elimination in place, then back substitution
+    T prev = in[base] * iv[0];
+    out[base] = prev;
+    for (int i = 1; i < n; ++i) {
+      prev = (in[base + i * stride] - prev) * iv[i];
+      out[base + i * stride] = prev;
+    }
+    T nxt = prev;
+    if (OUT != kOutPlain) emit(base + (int64_t)(n - 1) * stride, nxt);
+    for (int i = n - 2; i >= 0; --i) {
+      nxt = out[base + i * stride] - iv[i] * nxt;
+      if (OUT == kOutPlain)
+        out[base + i * stride] = nxt;
+      else
+        emit(base + i * stride, nxt);
+    }
+  }
+}
+
+template <typename T, int N>
+static void lines3(const Geo& g, const T* src, T* tmp, T* dst, const double* inv_eta, int j, int kmax,
+                   const T* tri, int nmax, const T* d, double* u, bool add_u, const int32_t* active, int32_t B,
+                   hipStream_t s) {
+  const T* ivx = tri;
+  const T* ivy = tri + nmax;
+  const T* ivz = tri + 2 * nmax;
+  const double c6 = 216.0 / g.Hm;
+  const int64_t rows_ps = (int64_t)g.ny * g.nz;
+  const int64_t rows = rows_ps * B;
+  const size_t shx = sizeof(T) * (size_t)kRowsPerBlock * g.nx;
+  // x: src -> tmp (scaled), y: tmp -> dst, z: dst -> dst (or u)
+  hipLaunchKernelGGL((k_line_x<T, N>), dim3((unsigned)cdiv(rows, kRowsPerBlock)), dim3(kBlock), shx, s, src,
+                     tmp, g.nx, rows_ps, rows, inv_eta, j, kmax, c6, ivx, active);
+  hipLaunchKernelGGL((k_line_yz<T, N, 1, kOutPlain>), dim3((unsigned)cdiv((int64_t)g.nx * g.nz, kBlock), B),
+                     dim3(kBlock), 0, s, tmp, dst, g, ivy, d, u, active);
+  if (add_u)
+    hipLaunchKernelGGL((k_line_yz<T, N, 2, kOutAddU>), dim3((unsigned)cdiv((int64_t)g.nx * g.ny, kBlock), B),
+                       dim3(kBlock), 0, s, dst, dst, g, ivz, d, u, active);
+  else
+    hipLaunchKernelGGL((k_line_yz<T, N, 2, kOutDivD>), dim3((unsigned)cdiv((int64_t)g.nx * g.ny, kBlock), B),
+                       dim3(kBlock), 0, s, dst, dst, g, ivz, d, u, active);
+}
+
+}  // namespace mlq
+
 namespace mlq {
 
 // Large planes need more than the default 64 KB of dynamic LDS per workgroup.
@@ -1129,17 +1316,14 @@ hipError_t prepare_minv_kernels(size_t bytes) {
   auto set = [&](const void* k) {
     if (e == hipSuccess) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, b);
   };
-  // planes above 64 KB only occur for lines longer than the unrolled sizes (N = 0)
-  set((const void*)(k_minv_xy<double, kOutPlain, 0>));
+  // LDS above 64 KB only occurs for lines longer than the unrolled sizes (N = 0):
+  // 2D planes and 3D x-row blocks
   set((const void*)(k_minv_xy<double, kOutDivD, 0>));
   set((const void*)(k_minv_xy<double, kOutAddU, 0>));
-  set((const void*)(k_minv_z<double, kOutDivD, 0>));
-  set((const void*)(k_minv_z<double, kOutAddU, 0>));
-  set((const void*)(k_minv_xy<float, kOutPlain, 0>));
   set((const void*)(k_minv_xy<float, kOutDivD, 0>));
   set((const void*)(k_minv_xy<float, kOutAddU, 0>));
-  set((const void*)(k_minv_z<float, kOutDivD, 0>));
-  set((const void*)(k_minv_z<float, kOutAddU, 0>));
+  set((const void*)(k_line_x<double, 0>));
+  set((const void*)(k_line_x<float, 0>));
   return e;
 }
 
