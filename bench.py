@@ -25,9 +25,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "space-time DOF·iters/s per GPU + MLQMC time-to-RMSE, mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per node-sample of the Jacobian apply: x, d, y and the two
-# element coefficients (one element per node), in the inner precision
+# algorithmic bytes per node-sample of the preconditioned Jacobian apply
+# w = v_j / eta_j + dt/2 K z: z, v_j and the two element coefficients (one
+# element per node) read, w written, in the inner precision
 APPLY_BYTES = {0: 5 * 8, 1: 5 * 4}
+APPLY_SOURCE = os.path.join(ROOT, "paper_2105_02007_amd", "csrc", "mlq_stencil3.hip")
+COPY_ELEMS = 1 << 27  # 1 GiB of FP64 for the counter calibration copy
+
+
+def counter_traffic(config, prec):
+    """HBM bytes per algorithmic byte of the apply, from the committed rocprofv3 counter summary.
+
+    The summary records FETCH_SIZE and WRITE_SIZE summed over the apply dispatches
+    of one estimator pass, each scaled by what the same counter reads for a copy
+    of known size, and the SHA-256 of the kernel source it was taken with.  A
+    summary for a different source (the kernel changed since) gives None.
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"apply_k_wave3_{config}_{prec}_counters.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for ln in open(path):
+        if ln.startswith("record:"):
+            for kv in ln.split()[1:]:
+                k, v = kv.split("=")
+                rec[k] = v
+    if rec.get("source_sha256") != hashlib.sha256(open(APPLY_SOURCE, "rb").read()).hexdigest():
+        return None
+    return float(rec["hbm_bytes_per_alg_byte"])
 
 WORKLOAD_TEXT = {
     "c1": "2D unit square Q1 33x33, 64 steps, 16-mode KL (l=0.2, s=0.3 rad), 16 MC samples, mean u(T), FP64",
@@ -87,6 +113,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="extra untimed pass timing every kernel class")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB FP64 copy (torch.neg) before warm-up, as a counter reference")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -127,6 +155,12 @@ def main():
         shifts = [W.lattice_shifts(cfg["seed"], l, S, M) for l in range(len(cfg["levels"]))]
         step = lambda: runner.run_mlqmc(shifts)
 
+    if args.copy_calibration:
+        src = torch.ones(COPY_ELEMS, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     for i in range(args.warmup):
         step()
         log(f"warmup {i} done")
@@ -155,10 +189,16 @@ def main():
         per_level.append(dict(level=l, nodes=L.n_nodes, apply_ms=round(t["ms"], 3), apply_launches=t["launches"]))
         L.timing_enable(())
     bpu = APPLY_BYTES[prec]
-    achieved = (apply_units * bpu) / (apply_ms * 1e-3) / 1e9 if apply_ms > 0 else 0.0
+    alg_bytes = apply_units * bpu
+    per_launch = alg_bytes / max(apply_launches, 1)
+    achieved = alg_bytes / (apply_ms * 1e-3) / 1e9 if apply_ms > 0 else 0.0
+    ratio = counter_traffic(args.config, "fp64" if prec == W.PREC_FP64 else "mixed")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    kernel="k_apply (Jacobian apply)", bytes_per_node_sample=bpu,
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None if ratio is None else round(ratio * per_launch),
+                    kernel="k_wave3 (preconditioned Jacobian apply, all levels)",
+                    bytes_per_node_sample=bpu, alg_bytes_per_launch=round(per_launch),
+                    alg_bytes_total=round(alg_bytes),
                     avg_launch_us=round(1e3 * apply_ms / max(apply_launches, 1), 2),
                     launches=apply_launches)
 

@@ -88,13 +88,10 @@ void launch_rhs(const Geo& g, const Work& w, const double* fbox, double load_coe
 void launch_residual(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);
 void launch_newton_check(const Geo& g, const Work& w, int32_t B, double tol, hipStream_t s);
 void launch_count(const int32_t* flags, int32_t B, int32_t* out, hipStream_t s);
-void launch_precond(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s);
-void launch_apply_z(const Geo& g, const Work& w, double ck, int32_t B, bool mixed, hipStream_t s);
 void launch_dots(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s);
 void launch_orth(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s);
 void launch_givens(const Geo& g, const Work& w, int j, int32_t B, double tol, hipStream_t s);
 void launch_solve_y(const Work& w, int32_t B, hipStream_t s);
-void launch_update(const Geo& g, const Work& w, int32_t B, bool mixed, hipStream_t s);
 void launch_activation(const Work& w, int64_t nn, int32_t B, double u_th, double t_k, double dt,
                        hipStream_t s);
 void launch_qoi(const Work& w, const double* wts, int64_t nn, int32_t B, int qoi, double t_stop,
@@ -128,8 +125,6 @@ void launch_apply_full3(const Geo& g, const void* coef, const void* x, const voi
 void launch_residual3(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);
 void launch_rhs3(const Geo& g, const Work& w, const double* fbox, double load_coef, double dt, int32_t B, bool mixed,
                  hipStream_t s);
-void launch_apply_pk3_lds(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s);
-void launch_residual3_lds(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);
 void launch_cast_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
 }  // namespace mlq

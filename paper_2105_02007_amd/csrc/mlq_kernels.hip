@@ -394,43 +394,6 @@ void launch_count(const int32_t* flags, int32_t B, int32_t* out, hipStream_t s) 
 }
 
 // ---------------------------------------------------------------------------
-// Jacobi preconditioner with the diagonal of M (1 + d):
-//   z = v_j / (m_ii (1 + d_i)),  m_ii = Hm (elements at node i) (1/3)^dim.
-__device__ inline double mass_diag(const Geo& g, int ix, int iy, int iz) {
-  const int cx = (ix == 0 || ix == g.nx - 1) ? 1 : 2;
-  const int cy = (iy == 0 || iy == g.ny - 1) ? 1 : 2;
-  const int cz = (g.dim == 2) ? 1 : ((iz == 0 || iz == g.nz - 1) ? 1 : 2);
-  const double third = 1.0 / 3.0;
-  return g.Hm * (double)(cx * cy * cz) * (g.dim == 3 ? third * third * third : third * third);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_precond(Geo g, const T* __restrict__ V, const T* __restrict__ d,
-                                                    T* __restrict__ z, const double* __restrict__ inv_eta, int j,
-                                                    int kmax, const int32_t* __restrict__ active) {
-  const int sb = blockIdx.y;
-  if (active[sb] == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.nn) return;
-  int ix, iy, iz;
-  node_xyz(i, g, ix, iy, iz);
-  const int64_t o = (int64_t)sb * g.nn + i;
-  const T s = (T)inv_eta[(int64_t)sb * (kmax + 1) + j];
-  z[o] = V[o] * s / ((T)mass_diag(g, ix, iy, iz) * ((T)1 + d[o]));
-}
-
-void launch_precond(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s) {
-  const dim3 grid((unsigned)w.nblk, B);
-  const size_t vs = (size_t)g.nn * B;
-  if (mixed)
-    hipLaunchKernelGGL((k_precond<float>), grid, dim3(kBlock), 0, s, g, (const float*)w.V + j * vs,
-                       (const float*)w.d, (float*)w.z, w.inv_eta, j, w.kmax, w.inner_active);
-  else
-    hipLaunchKernelGGL((k_precond<double>), grid, dim3(kBlock), 0, s, g, (const double*)w.V + j * vs,
-                       (const double*)w.d, (double*)w.z, w.inv_eta, j, w.kmax, w.inner_active);
-}
-
-// ---------------------------------------------------------------------------
 // Jacobian apply (Section 3.2): y = M ((1 + d) x) + ck K_G x, ck = dt/2.
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_apply(Geo g, const T* __restrict__ x, const T* __restrict__ d,
@@ -467,15 +430,6 @@ static void apply_dispatch(const Geo& g, const T* coef, const T* x, const T* d, 
     hipLaunchKernelGGL((k_apply<3, T>), grid, dim3(kBlock), 0, s, g, x, d, coef, y, (T)ck, active);
   else
     hipLaunchKernelGGL((k_apply<2, T>), grid, dim3(kBlock), 0, s, g, x, d, coef, y, (T)ck, active);
-}
-
-void launch_apply_z(const Geo& g, const Work& w, double ck, int32_t B, bool mixed, hipStream_t s) {
-  if (mixed)
-    apply_dispatch<float>(g, (const float*)w.coef, (const float*)w.z, (const float*)w.d, (float*)w.w, ck, B,
-                          w.inner_active, s);
-  else
-    apply_dispatch<double>(g, (const double*)w.coef, (const double*)w.z, (const double*)w.d, (double*)w.w, ck, B,
-                           w.inner_active, s);
 }
 
 void launch_apply_public(const Geo& g, const void* coef, const void* x, const void* d, void* y, double ck,
@@ -647,42 +601,6 @@ __global__ void k_solve_y(int32_t B, int kmax, const double* __restrict__ H, con
 void launch_solve_y(const Work& w, int32_t B, hipStream_t s) {
   hipLaunchKernelGGL(k_solve_y, dim3((unsigned)cdiv(B, 64)), dim3(64), 0, s, B, w.kmax, w.H, w.g, w.inv_eta,
                      w.newton_active, w.inner_k, w.y, w.iters);
-}
-
-// Newton update u += P^-1 (sum_i y_i v_i) (right preconditioning), FP64 accumulate.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update(Geo g, const T* __restrict__ V, size_t vs, const T* __restrict__ d,
-                                                   const double* __restrict__ y, int kmax,
-                                                   const int32_t* __restrict__ inner_k, double* __restrict__ u,
-                                                   int64_t* iters, const int32_t* __restrict__ active) {
-  const int sb = blockIdx.y;
-  if (active[sb] == 0) return;
-  __shared__ double c[kMaxInner];
-  const int k = inner_k[sb];
-  for (int i = threadIdx.x; i < k; i += kBlock) c[i] = y[(int64_t)sb * kmax + i];
-  __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  (void)iters;
-  if (i >= g.nn) return;
-  int ix, iy, iz;
-  node_xyz(i, g, ix, iy, iz);
-  const int64_t o = (int64_t)sb * g.nn + i;
-  double sacc = 0.0;
-  for (int l = 0; l < k; ++l) sacc += c[l] * (double)V[l * vs + o];
-  const T st = (T)sacc;
-  const T z = st / ((T)mass_diag(g, ix, iy, iz) * ((T)1 + d[o]));
-  u[o] += (double)z;
-}
-
-void launch_update(const Geo& g, const Work& w, int32_t B, bool mixed, hipStream_t s) {
-  const dim3 grid((unsigned)w.nblk, B);
-  const size_t vs = (size_t)g.nn * B;
-  if (mixed)
-    hipLaunchKernelGGL((k_update<float>), grid, dim3(kBlock), 0, s, g, (const float*)w.V, vs, (const float*)w.d, w.y,
-                       w.kmax, w.inner_k, w.u, w.iters, w.newton_active);
-  else
-    hipLaunchKernelGGL((k_update<double>), grid, dim3(kBlock), 0, s, g, (const double*)w.V, vs, (const double*)w.d,
-                       w.y, w.kmax, w.inner_k, w.u, w.iters, w.newton_active);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,14 +1,19 @@
-// Tiled 3D Q1 operators of the space-time solve (Section 3.1 eq. (semi-disc),
-// Section 3.2 Jacobian), for uniform brick meshes.
+// 3D Q1 operators of the space-time solve (Section 3.1 eq. (semi-disc),
+// Section 3.2 Jacobian) on uniform brick meshes, as register-streaming kernels.
 //
-// A workgroup owns a TX x TY column of nodes of one sample and marches up a
-// chunk of z-planes.  For every slab of elements between two node planes it
-//   1. stages the two node planes (with a one-node halo in x and y) in LDS,
-//   2. computes each element's 8 outputs from its 8 nodal inputs with the
-//      factored element operators (one thread per element, no redundancy),
-//   3. sums the contributions of the 4 + 4 elements around every owned node
-//      in a fixed order (bottom faces of this slab + top faces of the previous).
-// Node planes are read once from HBM per workgroup (plus the halo ring).
+// One wave owns a 7 x 7 column of nodes of one sample and computes the 8 x 8
+// elements around it (lane = i + 8 j <-> element (x0 - 1 + i, y0 - 1 + j)),
+// marching up a chunk of 15 node planes.  Per slab of elements between two node
+// planes every lane
+//   1. holds its element's four corner values of the lower and the upper plane
+//      in registers (neighbouring lanes hit the same cache lines),
+//   2. computes the element's 8 outputs from the 8 nodal inputs with the
+//      factored element operators below (one lane per element, no redundancy),
+//   3. sums the contributions of the 4 + 4 elements around every owned node in
+//      a fixed order, taking neighbour outputs by cross-lane shuffles (bottom
+//      faces of this slab + top faces of the previous one).
+// There is no LDS staging and no barrier; a ring of four plane register sets
+// keeps the loads of the next planes in flight while a slab is computed.
 //
 // Element operators (edges hx, hy, hz; local node (a, b, c) in {0,1}^3;
 // s(0) = -1, s(1) = +1; M1 = h/6 [[2,1],[1,2]]; K1 = 1/h [[1,-1],[-1,1]]).  With
@@ -26,14 +31,7 @@ namespace mlq {
 
 namespace {
 
-constexpr int TX = 33;            // owned nodes along x
-constexpr int TY = 7;             // owned nodes along y
-constexpr int PX = TX + 2;        // staged plane with halo
-constexpr int PY = TY + 2;
-constexpr int EX = TX + 1;        // elements touching the owned nodes
-constexpr int EY = TY + 1;
-constexpr int NT = 256;           // threads per workgroup
-constexpr int ZC = 16;            // owned node planes per workgroup
+constexpr int NT = 256;           // threads per workgroup (four independent waves)
 
 enum { kPK = 0, kFull = 1, kRes = 2, kRhs = 3 };
 
@@ -134,243 +132,8 @@ struct Args {
 
 }  // namespace
 
-template <typename R, typename TC, typename TI, int MODE>
-__global__ __launch_bounds__(NT) void k_stencil3(Args<R> A) {
-  const Geo& g = A.g;
-  const int sb = blockIdx.y;
-  if (A.active != nullptr && A.active[sb] == 0) return;
-  constexpr bool kMass = MODE != kPK;
-  constexpr int NIN = kMass ? 2 : 1;
-  __shared__ R pl[2][NIN][PX * PY];   // staged node planes (ring), stiffness input [0], mass input [1]
-  __shared__ R E[8][EX * EY];          // element outputs of the current slab
-  __shared__ double red[NT / 64][3];
-
-  int t = blockIdx.x;
-  const int tx_i = t % A.tiles_x;
-  t /= A.tiles_x;
-  const int ty_i = t % A.tiles_y;
-  const int zc = t / A.tiles_y;
-  const int x0 = tx_i * TX, y0 = ty_i * TY;
-  const int zs = zc * ZC;
-  const int ze = min(zs + ZC, g.nz);
-  const int64_t plane = (int64_t)g.nx * g.ny;
-  const int64_t sbase = (int64_t)sb * g.nn;
-  const TC* cf = (const TC*)A.coef + (int64_t)sb * g.P * 2;
-  const int ex_n = g.nx - 1, ey_n = g.ny - 1;
-
-  // owned node of this thread (node phase)
-  const int tid = threadIdx.x;
-  const int ox = tid % TX, oy = tid / TX;
-  const int gx = x0 + ox, gy = y0 + oy;
-  const bool owner = tid < TX * TY && gx < g.nx && gy < g.ny;
-
-  // global -> registers (next plane), registers -> LDS: the loads of plane k + 2
-  // are in flight while slab k is computed
-  constexpr int LPT = (PX * PY + NT - 1) / NT;
-  constexpr int EPT = (EX * EY + NT - 1) / NT;
-  R fk[LPT], fm[LPT];
-  auto fetch = [&](int k) {
-#pragma unroll
-    for (int r = 0; r < LPT; ++r) {
-      const int i = tid + r * NT;
-      R vk = 0, vm = 0;
-      if (i < PX * PY) {
-        const int lx = i % PX, ly = i / PX;
-        const int nx_ = x0 - 1 + lx, ny_ = y0 - 1 + ly;
-        if (nx_ >= 0 && ny_ >= 0 && nx_ < g.nx && ny_ < g.ny) {
-          const int64_t o = sbase + (int64_t)k * plane + (int64_t)ny_ * g.nx + nx_;
-          if constexpr (MODE == kPK) {
-            vk = (R)A.x[o];
-          } else if constexpr (MODE == kFull) {
-            const R v = (R)A.x[o];
-            vk = v;
-            vm = v + (R)A.d[o] * v;
-          } else if constexpr (MODE == kRes) {
-            const double v = A.u[o];
-            vk = (R)v;
-            vm = (R)(v + A.io.dt * iion3(v, A.io));
-          } else {
-            const double v = A.u[o];
-            vk = (R)v;
-            vm = (R)v;
-          }
-        }
-      }
-      fk[r] = vk;
-      fm[r] = vm;
-    }
-  };
-  auto commit = [&](int k) {
-#pragma unroll
-    for (int r = 0; r < LPT; ++r) {
-      const int i = tid + r * NT;
-      if (i < PX * PY) {
-        pl[k & 1][0][i] = fk[r];
-        if constexpr (kMass) pl[k & 1][NIN - 1][i] = fm[r];
-      }
-    }
-  };
-  R cp[EPT], cq[EPT], np_[EPT], nq_[EPT];
-  auto fetch_coef = [&](int k, R (&pp)[EPT], R (&qq)[EPT]) {
-#pragma unroll
-    for (int r = 0; r < EPT; ++r) {
-      const int e = tid + r * NT;
-      pp[r] = 0;
-      qq[r] = 0;
-      if (e < EX * EY) {
-        const int ex = x0 - 1 + e % EX, ey = y0 - 1 + e / EX;
-        if (ex >= 0 && ey >= 0 && ex < ex_n && ey < ey_n) {
-          const int64_t eg = (int64_t)ex + (int64_t)ex_n * (ey + (int64_t)ey_n * k);
-          pp[r] = (R)cf[2 * eg];
-          qq[r] = (R)cf[2 * eg + 1];
-        }
-      }
-    }
-  };
-
-  double n0 = 0.0, n1 = 0.0, n2 = 0.0;  // residual partial norms
-  R acc_top = 0;
-  const int k0 = zs - 1;
-  const int klast = min(ze, g.nz - 1);   // last node plane a slab of this chunk touches
-  if (k0 >= 0) {
-    fetch(k0);
-    commit(k0);
-  }
-  if (k0 + 1 <= klast) fetch(k0 + 1);
-  if (k0 >= 0 && k0 <= g.nz - 2) fetch_coef(k0, cp, cq);
-  for (int k = k0; k < ze; ++k) {
-    const bool slab = k >= 0 && k <= g.nz - 2;
-    if (k + 1 <= klast) commit(k + 1);
-    // node-phase inputs of plane k, read early
-    R pre0 = 0;
-    const int64_t own = sbase + (int64_t)k * plane + (int64_t)gy * g.nx + gx;
-    if (owner && k >= zs) {
-      if constexpr (MODE == kPK) pre0 = A.vj[own];
-      if constexpr (MODE == kRes) pre0 = (R)A.bvec[own];
-      if constexpr (MODE == kRhs) pre0 = (R)A.fbox[(int64_t)gy * g.nx + gx + (int64_t)k * plane];
-    }
-    __syncthreads();
-    if (k + 2 <= klast) fetch(k + 2);
-    if (k + 1 >= 0 && k + 1 <= g.nz - 2 && k + 1 < ze) fetch_coef(k + 1, np_, nq_);
-    if (slab) {
-      const R* P0 = pl[k & 1][0];
-      const R* P1 = pl[(k + 1) & 1][0];
-#pragma unroll
-      for (int r = 0; r < EPT; ++r) {
-        const int e = tid + r * NT;
-        if (e >= EX * EY) break;
-        const int lx = e % EX, ly = e / EX;
-        const int ex = x0 - 1 + lx, ey = y0 - 1 + ly;
-        R o[8];
-        if (ex >= 0 && ey >= 0 && ex < ex_n && ey < ey_n) {
-          const int i00 = ly * PX + lx;
-          R xin[8] = {P0[i00], P0[i00 + 1], P0[i00 + PX], P0[i00 + PX + 1],
-                      P1[i00], P1[i00 + 1], P1[i00 + PX], P1[i00 + PX + 1]};
-          Elem<R>::stiff(xin, cp[r], cq[r], g, o);
-#pragma unroll
-          for (int q = 0; q < 8; ++q) o[q] *= (R)A.ck;
-          if constexpr (kMass) {
-            const R* M0 = pl[k & 1][NIN - 1];
-            const R* M1 = pl[(k + 1) & 1][NIN - 1];
-            R xm[8] = {M0[i00], M0[i00 + 1], M0[i00 + PX], M0[i00 + PX + 1],
-                       M1[i00], M1[i00 + 1], M1[i00 + PX], M1[i00 + PX + 1]};
-            R om[8];
-            Elem<R>::mass(xm, g, om);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) o[q] += (R)A.cm * om[q];
-          }
-        } else {
-#pragma unroll
-          for (int q = 0; q < 8; ++q) o[q] = 0;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) E[q][e] = o[q];
-      }
-    }
-    __syncthreads();
-    if (owner) {
-      R bot = 0, top = 0;
-      if (slab) {
-        // the node is vertex (a, b) = (1 - dx, 1 - dy) of local element (ox + dx, oy + dy)
-#pragma unroll
-        for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-          for (int dx = 0; dx < 2; ++dx) {
-            const int e = (oy + dy) * EX + (ox + dx);
-            const int v = (1 - dx) + 2 * (1 - dy);
-            bot += E[v][e];
-            top += E[v + 4][e];
-          }
-      }
-      if (k >= zs) {
-        const R s = acc_top + bot;
-        if constexpr (MODE == kPK) {
-          const R sj = (R)A.inv_eta[(int64_t)sb * (A.kmax + 1) + A.j];
-          A.y[own] = pre0 * sj + s;
-        } else if constexpr (MODE == kFull) {
-          A.y[own] = s;
-        } else if constexpr (MODE == kRes) {
-          const double G = (double)s;
-          const double bb = (double)pre0;
-          const double F = G - bb;
-          const double uo = (double)pl[k & 1][0][(oy + 1) * PX + ox + 1];
-          ((TI*)A.r0)[own] = (TI)(-F);
-          ((TI*)A.dout)[own] = (TI)(A.io.dt * diion3(uo, A.io));
-          n0 += F * F;
-          n1 += G * G;
-          n2 += bb * bb;
-        } else {
-          A.bout[own] = (double)s + A.load * (double)pre0;
-          A.ucopy[own] = (double)pl[k & 1][0][(oy + 1) * PX + ox + 1];
-        }
-      }
-      acc_top = top;
-    }
-#pragma unroll
-    for (int r = 0; r < EPT; ++r) {
-      cp[r] = np_[r];
-      cq[r] = nq_[r];
-    }
-    __syncthreads();
-  }
-  if constexpr (MODE == kRes) {
-    // fixed-order block reduction of the partial norms
-    double v[3] = {n0, n1, n2};
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) v[r] += __shfl_xor(v[r], off, 64);
-    }
-    if ((tid & 63) == 0) {
-      red[tid >> 6][0] = v[0];
-      red[tid >> 6][1] = v[1];
-      red[tid >> 6][2] = v[2];
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double s0 = 0, s1 = 0, s2 = 0;
-      for (int w = 0; w < NT / 64; ++w) {
-        s0 += red[w][0];
-        s1 += red[w][1];
-        s2 += red[w][2];
-      }
-      double* p = A.part + ((int64_t)sb * gridDim.x + blockIdx.x) * 3;
-      p[0] = s0;
-      p[1] = s1;
-      p[2] = s2;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Register-streaming variant: one wave owns a 7 x 7 column of nodes and computes
-// the 8 x 8 elements around it (lane = i + 8 j <-> element (x0 - 1 + i, y0 - 1 + j)),
-// marching up a chunk of z-planes.  Each lane loads its element's four corner
-// nodes (neighbouring lanes hit the same cache lines); neighbour element outputs
-// travel between lanes by shuffles.  There is no LDS staging and no barrier, so
-// many independent waves per CU hide the memory latency.  The loads of plane
-// k + 2 and the coefficients of slab k + 1 are issued while slab k is computed.  Owned node (X, Y) = lane (X, Y) sums, in this order, vertex (1,1)
-// of its own element, (0,1) of lane + 1, (1,0) of lane + 8 and (0,0) of lane + 9.
+// Owned node (X, Y) = lane (X, Y) sums, in this order, vertex (1,1) of its own
+// element, (0,1) of lane + 1, (1,0) of lane + 8 and (0,0) of lane + 9.
 constexpr int WT = 7;   // owned nodes per wave along x and y
 constexpr int WZ = 15;  // owned node planes per wave (WZ + 1 steps, a multiple of 4)
 
@@ -576,14 +339,6 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
 namespace {
 
 template <typename R>
-void grid_of(const Geo& g, Args<R>& a, int32_t B, dim3& grid) {
-  a.tiles_x = (int)cdiv(g.nx, TX);
-  a.tiles_y = (int)cdiv(g.ny, TY);
-  a.zchunks = (int)cdiv(g.nz, ZC);
-  grid = dim3((unsigned)(a.tiles_x * a.tiles_y * a.zchunks), (unsigned)B);
-}
-
-template <typename R>
 void wave_grid_of(const Geo& g, Args<R>& a, int32_t B, dim3& grid) {
   a.tiles_x = (int)cdiv(g.nx, WT);
   a.tiles_y = (int)cdiv(g.ny, WT);
@@ -597,72 +352,6 @@ int32_t stencil3_blocks(const Geo& g) {
   return (int32_t)cdiv(cdiv(g.nx, WT) * cdiv(g.ny, WT) * cdiv(g.nz, WZ), NT / 64);
 }
 
-// w = v_j inv_eta_j + ck K_G z  (preconditioned operator), LDS-tiled variant
-void launch_apply_pk3_lds(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s) {
-  const size_t vs = (size_t)g.nn * B;
-  if (mixed) {
-    Args<float> a{};
-    a.g = g; a.x = (const float*)w.z; a.vj = (const float*)w.V + j * vs; a.inv_eta = w.inv_eta; a.j = j;
-    a.kmax = w.kmax; a.coef = w.coef; a.y = (float*)w.w; a.ck = ck; a.cm = 0.0; a.active = w.inner_active;
-    dim3 grid;
-    grid_of(g, a, B, grid);
-    hipLaunchKernelGGL((k_stencil3<float, float, float, kPK>), grid, dim3(NT), 0, s, a);
-  } else {
-    Args<double> a{};
-    a.g = g; a.x = (const double*)w.z; a.vj = (const double*)w.V + j * vs; a.inv_eta = w.inv_eta; a.j = j;
-    a.kmax = w.kmax; a.coef = w.coef; a.y = (double*)w.w; a.ck = ck; a.cm = 0.0; a.active = w.inner_active;
-    dim3 grid;
-    grid_of(g, a, B, grid);
-    hipLaunchKernelGGL((k_stencil3<double, double, double, kPK>), grid, dim3(NT), 0, s, a);
-  }
-}
-
-// y = M ((1 + d) x) + ck K_G x  (public apply), LDS-tiled variant
-void launch_apply_full3_lds(const Geo& g, const void* coef, const void* x, const void* d, void* y, double ck, int32_t B,
-                        bool mixed, hipStream_t s) {
-  if (mixed) {
-    Args<float> a{};
-    a.g = g; a.x = (const float*)x; a.d = (const float*)d; a.coef = coef; a.y = (float*)y; a.ck = ck; a.cm = 1.0;
-    dim3 grid;
-    grid_of(g, a, B, grid);
-    hipLaunchKernelGGL((k_stencil3<float, float, float, kFull>), grid, dim3(NT), 0, s, a);
-  } else {
-    Args<double> a{};
-    a.g = g; a.x = (const double*)x; a.d = (const double*)d; a.coef = coef; a.y = (double*)y; a.ck = ck; a.cm = 1.0;
-    dim3 grid;
-    grid_of(g, a, B, grid);
-    hipLaunchKernelGGL((k_stencil3<double, double, double, kFull>), grid, dim3(NT), 0, s, a);
-  }
-}
-
-// F = M (u + dt I_ion(u)) + dt/2 K u - b (FP64), r0 = -F, d = dt I_ion'(u), partial norms (LDS-tiled)
-void launch_residual3_lds(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s) {
-  Args<double> a{};
-  a.g = g; a.io = io; a.u = w.u; a.bvec = w.b; a.coef = w.coef; a.r0 = w.V; a.dout = w.d; a.part = w.part;
-  a.ck = 0.5 * io.dt; a.cm = 1.0; a.active = w.newton_active;
-  dim3 grid;
-  grid_of(g, a, B, grid);
-  if (mixed)
-    hipLaunchKernelGGL((k_stencil3<double, float, float, kRes>), grid, dim3(NT), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_stencil3<double, double, double, kRes>), grid, dim3(NT), 0, s, a);
-}
-
-// b = (M - dt/2 K) u_k + load F_box, u = u_k (LDS-tiled)
-void launch_rhs3_lds(const Geo& g, const Work& w, const double* fbox, double load_coef, double dt, int32_t B, bool mixed,
-                 hipStream_t s) {
-  Args<double> a{};
-  a.g = g; a.u = w.uk; a.coef = w.coef; a.bout = w.b; a.ucopy = w.u; a.fbox = fbox; a.load = load_coef;
-  a.ck = -0.5 * dt; a.cm = 1.0; a.active = nullptr;
-  dim3 grid;
-  grid_of(g, a, B, grid);
-  if (mixed)
-    hipLaunchKernelGGL((k_stencil3<double, float, float, kRhs>), grid, dim3(NT), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_stencil3<double, double, double, kRhs>), grid, dim3(NT), 0, s, a);
-}
-
-// Register-streaming launchers used by the solve.
 void launch_apply_pk3(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s) {
   const size_t vs = (size_t)g.nn * B;
   if (mixed) {
