@@ -69,7 +69,7 @@ enum { MLQ_SAMPLE_OK = 0, MLQ_SAMPLE_NOCONV = 1, MLQ_SAMPLE_NAN = 2 };
 typedef struct {
   int32_t dim;        /* 2 or 3 */
   int32_t mesh_kind;  /* MLQ_MESH_Q1_BOX */
-  int64_t n[3];       /* nodes per axis (>= 2 each; unused axes ignored) */
+  int64_t n[3];       /* nodes per axis (>= 2 each; unused axes ignored; at most 2^27 nodes in total) */
   double lo[3], hi[3];/* box corners */
   int32_t n_steps;    /* time steps on [0, t_end]; dt = t_end / n_steps */
   double t_end;

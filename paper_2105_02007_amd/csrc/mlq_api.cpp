@@ -165,6 +165,12 @@ mlq_status validate(const mlq_level_desc* d) {
     if (d->n[a] < 2 || d->n[a] > (1 << 20)) return fail(MLQ_EINVAL, "n[%d] = %lld out of range", a, (long long)d->n[a]);
     if (!(d->hi[a] > d->lo[a])) return fail(MLQ_EINVAL, "box axis %d is empty", a);
   }
+  {
+    // per-sample offsets inside the kernels are 32-bit byte offsets
+    double nn = 1.0;
+    for (int a = 0; a < d->dim; ++a) nn *= (double)d->n[a];
+    if (nn > (double)(1 << 27)) return fail(MLQ_EINVAL, "%.0f nodes per sample exceed the limit of 2^27", nn);
+  }
   if (d->n_steps < 1) return fail(MLQ_EINVAL, "n_steps must be >= 1");
   if (!(d->t_end > 0.0)) return fail(MLQ_EINVAL, "t_end must be positive");
   if (!(d->sigma_l > 0.0) || !(d->sigma_t > 0.0)) return fail(MLQ_EINVAL, "conductivities must be positive");
@@ -371,8 +377,8 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   // LDS staging of the preconditioner's line solves
   {
     const size_t ti = lv->mixed ? sizeof(float) : sizeof(double);
-    // 2D: one x-y plane per workgroup; 3D: 64 x-rows per workgroup
-    const size_t plane = dim == 3 ? ti * 64 * (size_t)desc->n[0] : ti * (size_t)desc->n[0] * (size_t)desc->n[1];
+    // one x-y plane per workgroup (2D: the whole sample)
+    const size_t plane = ti * (size_t)desc->n[0] * (size_t)desc->n[1];
     int dev = 0;
     hipDeviceProp_t prop{};
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {

@@ -785,30 +785,17 @@ namespace mlq {
 // preconditioning the mass part of J P^-1 is the identity, so the Krylov
 // operator is v -> v + dt/2 K P^-1 v.
 //
-// Thomas elimination of tridiag(1, 4, 1) (2 at the ends) along a strided line;
-// iv[i] = 1 / (pivot i) is precomputed per axis.
-template <typename T>
-__device__ inline void thomas_line(T* a, int n, int stride, const T* __restrict__ iv) {
-  T prev = a[0] * iv[0];
-  a[0] = prev;
-  for (int i = 1; i < n; ++i) {
-    prev = (a[i * stride] - prev) * iv[i];
-    a[i * stride] = prev;
-  }
-  T nxt = prev;
-  for (int i = n - 2; i >= 0; --i) {
-    nxt = a[i * stride] - iv[i] * nxt;
-    a[i * stride] = nxt;
-  }
-}
-
-// Same elimination with the line length known at compile time (fully unrolled,
-// so the LDS loads of later entries are issued ahead of the recurrence).
+// The 3D inverse runs as two passes: z-line solves (one thread per (x, y) column,
+// the line in registers, the input scaled on the way in), then one workgroup per
+// z-plane that stages the plane in LDS and solves its x lines and y lines before
+// the pointwise output.  A 2D sample is one plane.  Every pass issues all of a
+// thread's global loads before it uses the first one.
+//
+// Thomas elimination of tridiag(1, 4, 1) (2 at the ends); iv[i] = 1 / (pivot i)
+// is precomputed per axis:  y_0 = v_0 iv_0,  y_i = (v_i - y_{i-1}) iv_i,
+// x_{n-1} = y_{n-1},  x_i = y_i - iv_i x_{i+1}.
 template <int N, typename T>
-__device__ inline void thomas_fixed(T* a, int stride, const T* __restrict__ iv) {
-  T v[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = a[i * stride];
+__device__ inline void thomas_regs(T (&v)[N], const T* __restrict__ iv) {
   T prev = v[0] * iv[0];
   v[0] = prev;
 #pragma unroll
@@ -818,83 +805,172 @@ __device__ inline void thomas_fixed(T* a, int stride, const T* __restrict__ iv) 
   }
 #pragma unroll
   for (int i = N - 2; i >= 0; --i) v[i] = v[i] - iv[i] * v[i + 1];
-#pragma unroll
-  for (int i = 0; i < N; ++i) a[i * stride] = v[i];
 }
 
-template <int N, typename T>
-__device__ inline void sweep(T* a, int n, int stride, const T* __restrict__ iv) {
-  if constexpr (N > 0)
-    thomas_fixed<N, T>(a, stride, iv);
-  else
-    thomas_line(a, n, stride, iv);
+// The same elimination on a strided line a[i * stride] (LDS or global memory) of
+// runtime length, in chunks of 16 entries whose loads are issued together.
+template <typename T>
+__device__ inline void line_solve(T* a, int n, int64_t stride, const T* __restrict__ iv) {
+  constexpr int CH = 16;
+  T prev = 0;
+#pragma unroll 1
+  for (int c0 = 0; c0 < n; c0 += CH) {
+    T v[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (c0 + i < n) v[i] = a[(c0 + i) * stride];
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (c0 + i < n) {
+        prev = (c0 + i == 0) ? v[i] * iv[0] : (v[i] - prev) * iv[c0 + i];
+        v[i] = prev;
+      }
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (c0 + i < n) a[(c0 + i) * stride] = v[i];
+  }
+  T nxt = prev;  // x_{n-1} = y_{n-1}
+#pragma unroll 1
+  for (int hi = n - 2; hi >= 0; hi -= CH) {
+    T v[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (hi - i >= 0) v[i] = a[(hi - i) * stride];
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (hi - i >= 0) {
+        nxt = v[i] - iv[hi - i] * nxt;
+        v[i] = nxt;
+      }
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (hi - i >= 0) a[(hi - i) * stride] = v[i];
+  }
 }
 
 enum { kOutPlain = 0, kOutDivD = 1, kOutAddU = 2 };
 
-// x and y sweeps of one z-plane of one sample in LDS.  Input scaled by
-// c6 * inv_eta[j] (c6 = prod 6/h_a) when inv_eta != nullptr, by c6 otherwise.
-template <typename T, int OUT, int N>
-__global__ __launch_bounds__(kBlock) void k_minv_xy(Geo g, const T* __restrict__ in, T* __restrict__ out,
-                                                    const double* __restrict__ inv_eta, int j, int kmax, double c6,
-                                                    const T* __restrict__ ivx, const T* __restrict__ ivy,
-                                                    const T* __restrict__ d, double* __restrict__ u,
-                                                    const int32_t* __restrict__ active) {
-  extern __shared__ unsigned char smem_raw[];
-  T* sh = reinterpret_cast<T*>(smem_raw);
+__device__ inline double minv_scale(const double* __restrict__ inv_eta, int sb, int j, int kmax, double c6) {
+  return c6 * (inv_eta != nullptr ? inv_eta[(int64_t)sb * (kmax + 1) + j] : 1.0);
+}
+
+// z lines: thread per (x, y) column of one sample (blockIdx.y); out = Mz^-1 (scale in).
+template <typename T, int N>
+__global__ __launch_bounds__(kBlock) void k_line_z(Geo g, const T* __restrict__ in, T* __restrict__ out,
+                                                   const double* __restrict__ inv_eta, int j, int kmax, double c6,
+                                                   const T* __restrict__ iv, const int32_t* __restrict__ active) {
   const int sb = blockIdx.y;
   if (active[sb] == 0) return;
-  const int nx = g.nx, ny = g.ny, np = nx * ny;
-  const int64_t base = (int64_t)sb * g.nn + (int64_t)blockIdx.x * np;
-  const T s = (T)(c6 * (inv_eta != nullptr ? inv_eta[(int64_t)sb * (kmax + 1) + j] : 1.0));
-  for (int t = threadIdx.x; t < np; t += kBlock) sh[t] = in[base + t] * s;
-  __syncthreads();
-  for (int r = threadIdx.x; r < ny; r += kBlock) sweep<N, T>(sh + r * nx, nx, 1, ivx);
-  __syncthreads();
-  for (int c = threadIdx.x; c < nx; c += kBlock) sweep<N, T>(sh + c, ny, nx, ivy);
-  __syncthreads();
-  for (int t = threadIdx.x; t < np; t += kBlock) {
-    T v = sh[t];
-    if (OUT == kOutPlain) {
-      out[base + t] = v;
-    } else {
-      v = v / ((T)1 + d[base + t]);
-      if (OUT == kOutDivD)
-        out[base + t] = v;
-      else
-        u[base + t] += (double)v;
+  const int L = blockIdx.x * kBlock + threadIdx.x;
+  if (L >= g.nx * g.ny) return;
+  const int64_t stride = (int64_t)g.nx * g.ny;
+  const int64_t base = (int64_t)sb * g.nn + L;
+  const T s = (T)minv_scale(inv_eta, sb, j, kmax, c6);
+  if constexpr (N > 0) {
+    T v[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = in[base + i * stride] * s;
+    thomas_regs<N, T>(v, iv);
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[base + i * stride] = v[i];
+  } else {
+    // runtime length: scaled copy into out, then the chunked elimination in place
+    const int n = g.nz;
+    for (int c0 = 0; c0 < n; c0 += 16) {
+      T v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (c0 + i < n) v[i] = in[base + (c0 + i) * stride];
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (c0 + i < n) out[base + (c0 + i) * stride] = v[i] * s;
     }
+    line_solve<T>(out + base, n, stride, iv);
   }
 }
 
-// z sweeps of one x-z plane (fixed y) of one sample in LDS, then the division by (1 + d).
+// x and y lines of one z-plane (blockIdx.x) of one sample (blockIdx.y) in LDS, then
+// the output: divided by (1 + d), or added (divided by 1 + d) to u in FP64.
+// The input is scaled by c6 inv_eta_j (inv_eta != nullptr) or c6.
+// N: nx = ny when it is one of the unrolled sizes (each line solved in registers by
+// one thread), else 0 (runtime size, chunked solves).  d (and u) are fetched after
+// the sweeps, so the sweeps hold no prefetched registers.
 template <typename T, int OUT, int N>
-__global__ __launch_bounds__(kBlock) void k_minv_z(Geo g, const T* __restrict__ in, T* __restrict__ out,
-                                                   const T* __restrict__ ivz, const T* __restrict__ d,
-                                                   double* __restrict__ u, const int32_t* __restrict__ active) {
+__global__ __launch_bounds__(kBlock) void k_plane_xy(Geo g, const T* __restrict__ in, T* __restrict__ out,
+                                                     const double* __restrict__ inv_eta, int j, int kmax, double c6,
+                                                     const T* __restrict__ ivx, const T* __restrict__ ivy,
+                                                     const T* __restrict__ d, double* __restrict__ u,
+                                                     const int32_t* __restrict__ active) {
   extern __shared__ unsigned char smem_raw[];
   T* sh = reinterpret_cast<T*>(smem_raw);
   const int sb = blockIdx.y;
   if (active[sb] == 0) return;
-  const int nx = g.nx, nz = g.nz;
-  const int64_t plane = (int64_t)g.nx * g.ny;
-  const int64_t base = (int64_t)sb * g.nn + (int64_t)blockIdx.x * nx;
-  const int np = nx * nz;
-  for (int t = threadIdx.x; t < np; t += kBlock) sh[t] = in[base + (int64_t)(t / nx) * plane + (t % nx)];
+  const int nx = N > 0 ? N : g.nx, ny = N > 0 ? N : g.ny;
+  const int np = nx * ny;
+  const int64_t base = (int64_t)sb * g.nn + (int64_t)blockIdx.x * np;
+  const T s = (T)minv_scale(inv_eta, sb, j, kmax, c6);
+  const int t0 = threadIdx.x;
+  // entries t0 + q kBlock of the plane, in batches of PB whose loads are all issued first
+  constexpr int PB = (N > 0 && N * N <= 24 * kBlock) ? (N * N + kBlock - 1) / kBlock : 16;
+  for (int b0 = 0; b0 < np; b0 += PB * kBlock) {
+    T r[PB];
+#pragma unroll
+    for (int q = 0; q < PB; ++q)
+      if (b0 + t0 + q * kBlock < np) r[q] = in[base + b0 + t0 + q * kBlock];
+#pragma unroll
+    for (int q = 0; q < PB; ++q)
+      if (b0 + t0 + q * kBlock < np) sh[b0 + t0 + q * kBlock] = r[q] * s;
+  }
   __syncthreads();
-  for (int c = threadIdx.x; c < nx; c += kBlock) sweep<N, T>(sh + c, nz, nx, ivz);
+  if constexpr (N > 0) {
+    if (t0 < N) {
+      T v[N];
+      T* a = sh + t0 * N;
+#pragma unroll
+      for (int i = 0; i < N; ++i) v[i] = a[i];
+      thomas_regs<N, T>(v, ivx);
+#pragma unroll
+      for (int i = 0; i < N; ++i) a[i] = v[i];
+    }
+    __syncthreads();
+    if (t0 < N) {
+      T v[N];
+      T* a = sh + t0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) v[i] = a[i * N];
+      thomas_regs<N, T>(v, ivy);
+#pragma unroll
+      for (int i = 0; i < N; ++i) a[i * N] = v[i];
+    }
+  } else {
+    for (int r = t0; r < ny; r += kBlock) line_solve<T>(sh + r * nx, nx, 1, ivx);
+    __syncthreads();
+    for (int c = t0; c < nx; c += kBlock) line_solve<T>(sh + c, ny, nx, ivy);
+  }
   __syncthreads();
-  for (int t = threadIdx.x; t < np; t += kBlock) {
-    const int64_t o = base + (int64_t)(t / nx) * plane + (t % nx);
-    const T v = sh[t] / ((T)1 + d[o]);
-    if (OUT == kOutDivD)
-      out[o] = v;
-    else
-      u[o] += (double)v;
+  for (int b0 = 0; b0 < np; b0 += PB * kBlock) {
+    T dv[PB];
+    double uv[PB];
+#pragma unroll
+    for (int q = 0; q < PB; ++q)
+      if (b0 + t0 + q * kBlock < np) {
+        dv[q] = d[base + b0 + t0 + q * kBlock];
+        if constexpr (OUT == kOutAddU) uv[q] = u[base + b0 + t0 + q * kBlock];
+      }
+#pragma unroll
+    for (int q = 0; q < PB; ++q)
+      if (b0 + t0 + q * kBlock < np) {
+        const int64_t o = base + b0 + t0 + q * kBlock;
+        const T v = sh[b0 + t0 + q * kBlock] / ((T)1 + dv[q]);
+        if constexpr (OUT == kOutDivD)
+          out[o] = v;
+        else
+          u[o] = uv[q] + (double)v;
+      }
   }
 }
 
-// z <- P^-1 (scale * src); with add_u the result is added to u instead (FP64).
+// dst (or u) <- P^-1 (scale src); tmp holds the z-solved field in 3D.
 // N: common line length of all axes when it is one of the unrolled sizes, else 0.
 template <typename T, int N>
 static void minv_launch(const Geo& g, const T* src, T* tmp, T* dst, const double* inv_eta, int j, int kmax,
@@ -903,34 +979,26 @@ static void minv_launch(const Geo& g, const T* src, T* tmp, T* dst, const double
   const T* ivx = tri;
   const T* ivy = tri + nmax;
   const T* ivz = tri + 2 * nmax;
-  if (g.dim == 2) {
-    const double c6 = 36.0 / g.Hm;
-    const size_t sh = sizeof(T) * (size_t)g.nx * g.ny;
-    if (add_u)
-      hipLaunchKernelGGL((k_minv_xy<T, kOutAddU, N>), dim3(1, B), dim3(kBlock), sh, s, g, src, dst, inv_eta, j, kmax,
-                         c6, ivx, ivy, d, u, active);
-    else
-      hipLaunchKernelGGL((k_minv_xy<T, kOutDivD, N>), dim3(1, B), dim3(kBlock), sh, s, g, src, dst, inv_eta, j, kmax,
-                         c6, ivx, ivy, d, u, active);
-    return;
+  const size_t sh = sizeof(T) * (size_t)g.nx * g.ny;
+  const T* pin = src;
+  const double* peta = inv_eta;
+  double c6 = 36.0 / g.Hm;
+  unsigned planes = 1;
+  if (g.dim == 3) {
+    hipLaunchKernelGGL((k_line_z<T, N>), dim3((unsigned)cdiv((int64_t)g.nx * g.ny, kBlock), B), dim3(kBlock), 0, s, g,
+                       src, tmp, inv_eta, j, kmax, 216.0 / g.Hm, ivz, active);
+    pin = tmp;
+    peta = nullptr;
+    c6 = 1.0;
+    planes = (unsigned)g.nz;
   }
-  const double c6 = 216.0 / g.Hm;
-  const size_t shxy = sizeof(T) * (size_t)g.nx * g.ny;
-  const size_t shxz = sizeof(T) * (size_t)g.nx * g.nz;
-  hipLaunchKernelGGL((k_minv_xy<T, kOutPlain, N>), dim3(g.nz, B), dim3(kBlock), shxy, s, g, src, tmp, inv_eta, j,
-                     kmax, c6, ivx, ivy, d, u, active);
   if (add_u)
-    hipLaunchKernelGGL((k_minv_z<T, kOutAddU, N>), dim3(g.ny, B), dim3(kBlock), shxz, s, g, tmp, dst, ivz, d, u,
-                       active);
+    hipLaunchKernelGGL((k_plane_xy<T, kOutAddU, N>), dim3(planes, B), dim3(kBlock), sh, s, g, pin, dst, peta, j, kmax,
+                       c6, ivx, ivy, d, u, active);
   else
-    hipLaunchKernelGGL((k_minv_z<T, kOutDivD, N>), dim3(g.ny, B), dim3(kBlock), shxz, s, g, tmp, dst, ivz, d, u,
-                       active);
+    hipLaunchKernelGGL((k_plane_xy<T, kOutDivD, N>), dim3(planes, B), dim3(kBlock), sh, s, g, pin, dst, peta, j, kmax,
+                       c6, ivx, ivy, d, u, active);
 }
-
-template <typename T, int N>
-static void lines3(const Geo& g, const T* src, T* tmp, T* dst, const double* inv_eta, int j, int kmax,
-                   const T* tri, int nmax, const T* d, double* u, bool add_u, const int32_t* active, int32_t B,
-                   hipStream_t s);
 
 template <typename T>
 static void minv_dispatch(const Geo& g, const T* src, T* tmp, T* dst, const double* inv_eta, int j, int kmax,
@@ -938,27 +1006,16 @@ static void minv_dispatch(const Geo& g, const T* src, T* tmp, T* dst, const doub
                           int32_t B, hipStream_t s) {
   const bool cube = g.nx == g.ny && (g.dim == 2 || g.nz == g.nx);
   int n = cube ? g.nx : 0;
-  if (g.dim == 3) {
-    // registers hold one line: FP64 lines of 129 fall back to the runtime-length path
-    if (n == 129 && sizeof(T) == 8) n = 0;
-#define MLQ_L3(NN) lines3<T, NN>(g, src, tmp, dst, inv_eta, j, kmax, tri, nmax, d, u, add_u, active, B, s)
-    switch (n) {
-      case 9: MLQ_L3(9); break;
-      case 17: MLQ_L3(17); break;
-      case 33: MLQ_L3(33); break;
-      case 65: MLQ_L3(65); break;
-      case 129: MLQ_L3(129); break;
-      default: MLQ_L3(0); break;
-    }
-#undef MLQ_L3
-    return;
-  }
+  // the z pass holds a whole line in registers: FP64 up to 65 entries, FP32 up to 129
 #define MLQ_MINV(NN) minv_launch<T, NN>(g, src, tmp, dst, inv_eta, j, kmax, tri, nmax, d, u, add_u, active, B, s)
   switch (n) {
     case 9: MLQ_MINV(9); break;
     case 17: MLQ_MINV(17); break;
     case 33: MLQ_MINV(33); break;
     case 65: MLQ_MINV(65); break;
+    case 129:
+      if constexpr (sizeof(T) == 4) MLQ_MINV(129); else MLQ_MINV(0);
+      break;
     default: MLQ_MINV(0); break;
   }
 #undef MLQ_MINV
@@ -1060,173 +1117,8 @@ void launch_update_pm(const Geo& g, const Work& w, const void* tri, int nmax, in
 
 namespace mlq {
 
-// ---------------------------------------------------------------------------
-// 3D mass inverse as three batches of independent line solves (one thread per
-// line, the line in registers):
-//   x: 64 consecutive rows per wave, staged through LDS so that global accesses
-//      stay contiguous; y and z: one thread per line, neighbouring threads on
-//      neighbouring x (contiguous loads).
-// N: line length when it is one of the unrolled sizes (0: runtime length).
-
-template <int N, typename T>
-__device__ inline void thomas_regs(T (&v)[N], const T* __restrict__ iv) {
-  T prev = v[0] * iv[0];
-  v[0] = prev;
-#pragma unroll
-  for (int i = 1; i < N; ++i) {
-    prev = (v[i] - prev) * iv[i];
-    v[i] = prev;
-  }
-#pragma unroll
-  for (int i = N - 2; i >= 0; --i) v[i] = v[i] - iv[i] * v[i + 1];
-}
-
-constexpr int kRowsPerBlock = 64;
-
-// x lines: rows r of the whole batch (row r = nodes r*nx .. r*nx + nx - 1, sample r / rows_per_sample).
-// 256 threads stage 64 rows through LDS with contiguous accesses; 64 of them solve.
-template <typename T, int N>
-__global__ __launch_bounds__(kBlock) void k_line_x(const T* __restrict__ in, T* __restrict__ out, int nx,
-                                                   int64_t rows_per_sample, int64_t total_rows,
-                                                   const double* __restrict__ inv_eta, int j, int kmax, double c6,
-                                                   const T* __restrict__ iv, const int32_t* __restrict__ active) {
-  extern __shared__ unsigned char smem_raw[];
-  T* sh = reinterpret_cast<T*>(smem_raw);
-  const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
-  const int nrows = (int)((total_rows - r0) < kRowsPerBlock ? (total_rows - r0) : kRowsPerBlock);
-  const int64_t base = r0 * nx;
-  const int cnt = nrows * nx;
-  const int sb0 = (int)(r0 / rows_per_sample);
-  const int sb1 = (int)((r0 + nrows - 1) / rows_per_sample);
-  auto scale_of = [&](int sb) -> T {
-    double sc = c6;
-    if (inv_eta != nullptr) sc *= inv_eta[(int64_t)sb * (kmax + 1) + j];
-    return active[sb] ? (T)sc : (T)0;
-  };
-  if (sb0 == sb1) {  // the usual case: all 64 rows in one sample
-    const T sc = scale_of(sb0);
-    if (active[sb0] == 0) return;
-    for (int t = threadIdx.x; t < cnt; t += kBlock) sh[t] = in[base + t] * sc;
-  } else {
-    const int64_t split = (int64_t)sb1 * rows_per_sample - r0;  // first row of sample sb1, block-relative
-    const T s0 = scale_of(sb0), s1 = scale_of(sb1);
-    for (int t = threadIdx.x; t < cnt; t += kBlock) sh[t] = in[base + t] * ((t / nx) < split ? s0 : s1);
-  }
-  __syncthreads();
-  if (threadIdx.x < nrows) {
-    T* a = sh + threadIdx.x * nx;
-    if constexpr (N > 0) {
-      T v[N];
-#pragma unroll
-      for (int i = 0; i < N; ++i) v[i] = a[i];
-      thomas_regs<N, T>(v, iv);
-#pragma unroll
-      for (int i = 0; i < N; ++i) a[i] = v[i];
-    } else {
-      thomas_line(a, nx, 1, iv);
-    }
-  }
-  __syncthreads();
-  if (sb0 == sb1) {
-    for (int t = threadIdx.x; t < cnt; t += kBlock) out[base + t] = sh[t];
-  } else {
-    const int64_t split = (int64_t)sb1 * rows_per_sample - r0;
-    const bool a0 = active[sb0] != 0, a1 = active[sb1] != 0;
-    for (int t = threadIdx.x; t < cnt; t += kBlock)
-      if ((t / nx) < split ? a0 : a1) out[base + t] = sh[t];
-  }
-}
-
-// y or z lines of one sample (blockIdx.y): thread per line, line id = x + nx * other.
-template <typename T, int N, int AXIS, int OUT>
-__global__ __launch_bounds__(kBlock) void k_line_yz(const T* __restrict__ in, T* __restrict__ out, Geo g,
-                                                    const T* __restrict__ iv, const T* __restrict__ d,
-                                                    double* __restrict__ u, const int32_t* __restrict__ active) {
-  const int sb = blockIdx.y;
-  if (active[sb] == 0) return;
-  const int L = blockIdx.x * kBlock + threadIdx.x;
-  int64_t base, stride;
-  int n;
-  if (AXIS == 1) {
-    if (L >= g.nx * g.nz) return;
-    const int x = L % g.nx, z = L / g.nx;
-    base = (int64_t)z * g.nx * g.ny + x;
-    stride = g.nx;
-    n = g.ny;
-  } else {
-    if (L >= g.nx * g.ny) return;
-    base = L;
-    stride = (int64_t)g.nx * g.ny;
-    n = g.nz;
-  }
-  base += (int64_t)sb * g.nn;
-  auto emit = [&](int64_t o, T v) {
-    if (OUT == kOutPlain) {
-      out[o] = v;
-    } else {
-      v = v / ((T)1 + d[o]);
-      if (OUT == kOutDivD)
-        out[o] = v;
-      else
-        u[o] += (double)v;
-    }
-  };
-  if constexpr (N > 0) {
-    T v[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = in[base + i * stride];
-    thomas_regs<N, T>(v, iv);
-#pragma unroll
-    for (int i = 0; i < N; ++i) emit(base + i * stride, v[i]);
-  } else {
-    // runtime length: forward elimination in place, then back substitution
-    T prev = in[base] * iv[0];
-    out[base] = prev;
-    for (int i = 1; i < n; ++i) {
-      prev = (in[base + i * stride] - prev) * iv[i];
-      out[base + i * stride] = prev;
-    }
-    T nxt = prev;
-    if (OUT != kOutPlain) emit(base + (int64_t)(n - 1) * stride, nxt);
-    for (int i = n - 2; i >= 0; --i) {
-      nxt = out[base + i * stride] - iv[i] * nxt;
-      if (OUT == kOutPlain)
-        out[base + i * stride] = nxt;
-      else
-        emit(base + i * stride, nxt);
-    }
-  }
-}
-
-template <typename T, int N>
-static void lines3(const Geo& g, const T* src, T* tmp, T* dst, const double* inv_eta, int j, int kmax,
-                   const T* tri, int nmax, const T* d, double* u, bool add_u, const int32_t* active, int32_t B,
-                   hipStream_t s) {
-  const T* ivx = tri;
-  const T* ivy = tri + nmax;
-  const T* ivz = tri + 2 * nmax;
-  const double c6 = 216.0 / g.Hm;
-  const int64_t rows_ps = (int64_t)g.ny * g.nz;
-  const int64_t rows = rows_ps * B;
-  const size_t shx = sizeof(T) * (size_t)kRowsPerBlock * g.nx;
-  // x: src -> tmp (scaled), y: tmp -> dst, z: dst -> dst (or u)
-  hipLaunchKernelGGL((k_line_x<T, N>), dim3((unsigned)cdiv(rows, kRowsPerBlock)), dim3(kBlock), shx, s, src,
-                     tmp, g.nx, rows_ps, rows, inv_eta, j, kmax, c6, ivx, active);
-  hipLaunchKernelGGL((k_line_yz<T, N, 1, kOutPlain>), dim3((unsigned)cdiv((int64_t)g.nx * g.nz, kBlock), B),
-                     dim3(kBlock), 0, s, tmp, dst, g, ivy, d, u, active);
-  if (add_u)
-    hipLaunchKernelGGL((k_line_yz<T, N, 2, kOutAddU>), dim3((unsigned)cdiv((int64_t)g.nx * g.ny, kBlock), B),
-                       dim3(kBlock), 0, s, dst, dst, g, ivz, d, u, active);
-  else
-    hipLaunchKernelGGL((k_line_yz<T, N, 2, kOutDivD>), dim3((unsigned)cdiv((int64_t)g.nx * g.ny, kBlock), B),
-                       dim3(kBlock), 0, s, dst, dst, g, ivz, d, u, active);
-}
-
-}  // namespace mlq
-
-namespace mlq {
-
-// Large planes need more than the default 64 KB of dynamic LDS per workgroup.
+// Planes above 64 KB of LDS (129^2 in FP32 or FP64, non-unrolled sizes) need the
+// dynamic LDS limit of the plane kernels raised.
 hipError_t prepare_minv_kernels(size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
   const int b = (int)bytes;
@@ -1234,14 +1126,12 @@ hipError_t prepare_minv_kernels(size_t bytes) {
   auto set = [&](const void* k) {
     if (e == hipSuccess) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, b);
   };
-  // LDS above 64 KB only occurs for lines longer than the unrolled sizes (N = 0):
-  // 2D planes and 3D x-row blocks
-  set((const void*)(k_minv_xy<double, kOutDivD, 0>));
-  set((const void*)(k_minv_xy<double, kOutAddU, 0>));
-  set((const void*)(k_minv_xy<float, kOutDivD, 0>));
-  set((const void*)(k_minv_xy<float, kOutAddU, 0>));
-  set((const void*)(k_line_x<double, 0>));
-  set((const void*)(k_line_x<float, 0>));
+  set((const void*)(k_plane_xy<double, kOutDivD, 0>));
+  set((const void*)(k_plane_xy<double, kOutAddU, 0>));
+  set((const void*)(k_plane_xy<float, kOutDivD, 0>));
+  set((const void*)(k_plane_xy<float, kOutAddU, 0>));
+  set((const void*)(k_plane_xy<float, kOutDivD, 129>));
+  set((const void*)(k_plane_xy<float, kOutAddU, 129>));
   return e;
 }
 

@@ -37,62 +37,51 @@ enum { kPK = 0, kFull = 1, kRes = 2, kRhs = 3 };
 
 template <typename R>
 struct Elem {
-  // element outputs (8, index a + 2b + 4c) of M_e xm (scaled later) and K_e xk
-  __host__ __device__ static inline void stiff(const R (&x)[8], R p, R q, const Geo& g, R (&o)[8]) {
-    const R hx = (R)g.Hx, hy = (R)g.Hy, hz = (R)g.Hz;
-    const R sb = (R)g.sbar, st = (R)g.st;
-    const R z6 = hz / (R)6;
-    // z-mix with M1z
-    R m[2][4];
-#pragma unroll
-    for (int ab = 0; ab < 4; ++ab) {
-      m[0][ab] = z6 * ((R)2 * x[ab] + x[ab + 4]);
-      m[1][ab] = z6 * (x[ab] + (R)2 * x[ab + 4]);
-    }
-    const R cx = hy / ((R)6 * hx), cy = hx / ((R)6 * hy);
-    const R ap = sb + p, am = sb - p, q4 = (R)0.25 * q;
+  // element outputs (8, index a + 2b + 4c) of K_e x, with every constant folded into four
+  // per-element scalars:
+  //   AX = s (sbar + p) hy hz / (36 hx),  BY = s (sbar - p) hx hz / (36 hy),
+  //   Q4 = s q hz / 24,                   CZ = s st hx hy / (36 hz),
+  // s = the operator's scale (0 for an element that contributes nothing).
+  __host__ __device__ static inline void stiff_f(const R (&x)[8], R AX, R BY, R Q4, R CZ, R (&o)[8]) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      const R* u = m[c];
-      const R dx0 = u[1] - u[0], dx1 = u[3] - u[2];  // b = 0, 1
-      const R dy0 = u[2] - u[0], dy1 = u[3] - u[1];  // a = 0, 1
-      const R X0 = cx * ((R)2 * dx0 + dx1), X1 = cx * (dx0 + (R)2 * dx1);
-      const R Y0 = cy * ((R)2 * dy0 + dy1), Y1 = cy * (dy0 + (R)2 * dy1);
-      const R Dx = dx0 + dx1, Dy = dy0 + dy1;
-      const R A0 = ap * X0 + q4 * Dy, A1 = ap * X1 + q4 * Dy;
-      const R B0 = am * Y0 + q4 * Dx, B1 = am * Y1 + q4 * Dx;
-      o[4 * c + 0] = -A0 - B0;  // a = 0, b = 0
-      o[4 * c + 1] = A0 - B1;   // a = 1, b = 0
-      o[4 * c + 2] = -A1 + B0;  // a = 0, b = 1
-      o[4 * c + 3] = A1 + B1;   // a = 1, b = 1
+      R u[4];
+#pragma unroll
+      for (int ab = 0; ab < 4; ++ab) u[ab] = c == 0 ? (R)2 * x[ab] + x[ab + 4] : x[ab] + (R)2 * x[ab + 4];
+      const R dx0 = u[1] - u[0], dx1 = u[3] - u[2];
+      const R dy0 = u[2] - u[0], dy1 = u[3] - u[1];
+      const R qy = Q4 * (dy0 + dy1), qx = Q4 * (dx0 + dx1);
+      const R A0 = AX * ((R)2 * dx0 + dx1) + qy, A1 = AX * (dx0 + (R)2 * dx1) + qy;
+      const R B0 = BY * ((R)2 * dy0 + dy1) + qx, B1 = BY * (dy0 + (R)2 * dy1) + qx;
+      o[4 * c + 0] = -A0 - B0;
+      o[4 * c + 1] = A0 - B1;
+      o[4 * c + 2] = -A1 + B0;
+      o[4 * c + 3] = A1 + B1;
     }
-    // st M1x (x) M1y (x) K1z
     R dz[4];
 #pragma unroll
-    for (int ab = 0; ab < 4; ++ab) dz[ab] = x[ab + 4] - x[ab];
-    const R r0 = (R)2 * dz[0] + dz[1], r1 = dz[0] + (R)2 * dz[1];  // x-pass, b = 0
-    const R r2 = (R)2 * dz[2] + dz[3], r3 = dz[2] + (R)2 * dz[3];  // x-pass, b = 1
-    const R cz = st * hx * hy / ((R)36 * hz);
-    const R t0 = cz * ((R)2 * r0 + r2), t1 = cz * ((R)2 * r1 + r3);
-    const R t2 = cz * (r0 + (R)2 * r2), t3 = cz * (r1 + (R)2 * r3);
+    for (int ab = 0; ab < 4; ++ab) dz[ab] = CZ * (x[ab + 4] - x[ab]);
+    const R r0 = (R)2 * dz[0] + dz[1], r1 = dz[0] + (R)2 * dz[1];
+    const R r2 = (R)2 * dz[2] + dz[3], r3 = dz[2] + (R)2 * dz[3];
+    const R t0 = (R)2 * r0 + r2, t1 = (R)2 * r1 + r3;
+    const R t2 = r0 + (R)2 * r2, t3 = r1 + (R)2 * r3;
     o[0] -= t0; o[1] -= t1; o[2] -= t2; o[3] -= t3;
     o[4] += t0; o[5] += t1; o[6] += t2; o[7] += t3;
   }
 
-  // M_e x (full mass, scaled by hx hy hz / 216)
-  __host__ __device__ static inline void mass(const R (&x)[8], const Geo& g, R (&o)[8]) {
-    const R f = (R)g.Hm / (R)216;
+  // f M1x (x) M1y (x) M1z x with the factor f = s hx hy hz / 216 applied once
+  __host__ __device__ static inline void mass_f(const R (&x)[8], R f, R (&o)[8]) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       R t[4];
 #pragma unroll
-      for (int ab = 0; ab < 4; ++ab) t[ab] = (c == 0) ? ((R)2 * x[ab] + x[ab + 4]) : (x[ab] + (R)2 * x[ab + 4]);
+      for (int ab = 0; ab < 4; ++ab) t[ab] = f * ((c == 0) ? ((R)2 * x[ab] + x[ab + 4]) : (x[ab] + (R)2 * x[ab + 4]));
       const R r0 = (R)2 * t[0] + t[1], r1 = t[0] + (R)2 * t[1];
       const R r2 = (R)2 * t[2] + t[3], r3 = t[2] + (R)2 * t[3];
-      o[4 * c + 0] = f * ((R)2 * r0 + r2);
-      o[4 * c + 1] = f * ((R)2 * r1 + r3);
-      o[4 * c + 2] = f * (r0 + (R)2 * r2);
-      o[4 * c + 3] = f * (r1 + (R)2 * r3);
+      o[4 * c + 0] = (R)2 * r0 + r2;
+      o[4 * c + 1] = (R)2 * r1 + r3;
+      o[4 * c + 2] = r0 + (R)2 * r2;
+      o[4 * c + 3] = r1 + (R)2 * r3;
     }
   }
 };
@@ -128,6 +117,7 @@ struct Args {
   double ck, cm;
   const int32_t* active;
   int tiles_x, tiles_y, zchunks;
+  int bps;            // workgroups per sample
 };
 
 }  // namespace
@@ -135,7 +125,7 @@ struct Args {
 // Owned node (X, Y) = lane (X, Y) sums, in this order, vertex (1,1) of its own
 // element, (0,1) of lane + 1, (1,0) of lane + 8 and (0,0) of lane + 9.
 constexpr int WT = 7;   // owned nodes per wave along x and y
-constexpr int WZ = 15;  // owned node planes per wave (WZ + 1 steps, a multiple of 4)
+constexpr int WZ = 11;  // owned node planes per wave (WZ + 1 steps, a multiple of 4)
 
 template <typename R>
 __device__ inline R shdn(R v, int d) {
@@ -145,7 +135,13 @@ __device__ inline R shdn(R v, int d) {
 template <typename R, typename TC, typename TI, int MODE>
 __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
   const Geo& g = A.g;
-  const int sb = blockIdx.y;
+  // Workgroups go to the 8 XCDs round-robin (linear id mod 8).  Renumber them so
+  // that each XCD owns one contiguous range of (sample, tile) blocks: tiles that
+  // share cache lines (x/y halos, the plane above a z-chunk) then meet in one L2.
+  const int L = blockIdx.x, NB = gridDim.x;
+  const int q = NB >> 3, r = NB & 7, xcd = L & 7;
+  const int W = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + (L >> 3);
+  const int sb = W / A.bps, blk = W - sb * A.bps;
   const bool sample_on = A.active == nullptr || A.active[sb] != 0;
   constexpr bool kMass = MODE != kPK;
   __shared__ double red[NT / 64][3];
@@ -153,7 +149,7 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
   // the wave index is uniform across the wave: keep it (and everything derived
   // from it: tile, z-chunk, plane offsets) in scalar registers
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int gw = blockIdx.x * (NT / 64) + wid;
+  const int gw = blk * (NT / 64) + wid;
   const int nwaves = A.tiles_x * A.tiles_y * A.zchunks;
   const bool wave_on = sample_on && gw < nwaves;
   double n0 = 0.0, n1 = 0.0, n2 = 0.0;
@@ -182,19 +178,39 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     const int64_t ce = (int64_t)cx0 + (int64_t)ex_n * cy0;              // clamped element in its layer
     const int64_t layer = (int64_t)ex_n * ey_n;
 
-    auto in_val = [&](int64_t o, R& vk, R& vm) {
+    // Loads and stores address a wave-uniform base (sample, plane) plus a 32-bit
+    // per-lane byte offset that stays fixed while the wave marches up in z.
+    const uint32_t lb = (uint32_t)c00 * (uint32_t)sizeof(R);     // corner (0,0), node arrays of type R
+    const uint32_t lbd = (uint32_t)c00 * 8u;                      // same, FP64 node arrays
+    const uint32_t ob = (uint32_t)oof * (uint32_t)sizeof(R);     // owned node, type R
+    const uint32_t obd = (uint32_t)oof * 8u;                      // owned node, FP64
+    const uint32_t eb = (uint32_t)ce * 2u * (uint32_t)sizeof(TC); // element (p, q)
+    auto at = [](auto* base, uint32_t byte_off) { return *(decltype(base))((const char*)base + byte_off); };
+    const int nxs = g.nx;
+
+    // Per-sample base pointers (64-bit, uniform) are formed once; a plane is then a
+    // 32-bit byte offset (kk * plane fits in 32 bits for every mesh the library accepts).
+    const uint32_t pbR = (uint32_t)plane * (uint32_t)sizeof(R), pbD = (uint32_t)plane * 8u;
+    const uint32_t lbR = (uint32_t)layer * 2u * (uint32_t)sizeof(TC);
+    const R* xs = nullptr;
+    const R* ds_ = nullptr;
+    const double* us = nullptr;
+    if constexpr (MODE == kPK || MODE == kFull) xs = A.x + sbase;
+    if constexpr (MODE == kFull) ds_ = A.d + sbase;
+    if constexpr (MODE == kRes || MODE == kRhs) us = A.u + sbase;
+    auto in_val = [&](uint32_t po, int dn, R& vk, R& vm) {
       if constexpr (MODE == kPK) {
-        vk = (R)A.x[o];
+        vk = (R)at(xs + dn, lb + po);
       } else if constexpr (MODE == kFull) {
-        const R v = (R)A.x[o];
+        const R v = (R)at(xs + dn, lb + po);
         vk = v;
-        vm = v + (R)A.d[o] * v;
+        vm = v + (R)at(ds_ + dn, lb + po) * v;
       } else if constexpr (MODE == kRes) {
-        const double v = A.u[o];
+        const double v = at(us + dn, lbd + po);
         vk = (R)v;
         vm = (R)(v + A.io.dt * iion3(v, A.io));
       } else {
-        const double v = A.u[o];
+        const double v = at(us + dn, lbd + po);
         vk = (R)v;
         vm = (R)v;
       }
@@ -203,35 +219,41 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
       R k[4], m[4];
     };
     auto fetch = [&](int k, Pl& r) {
-      const int kk = min(max(k, 0), g.nz - 1);
-      const int64_t pb = sbase + (int64_t)kk * plane + c00;
-      in_val(pb, r.k[0], r.m[0]);
-      in_val(pb + 1, r.k[1], r.m[1]);
-      in_val(pb + g.nx, r.k[2], r.m[2]);
-      in_val(pb + g.nx + 1, r.k[3], r.m[3]);
+      const uint32_t kk = (uint32_t)min(max(k, 0), g.nz - 1);
+      const uint32_t po = kk * ((MODE == kRes || MODE == kRhs) ? pbD : pbR);
+      in_val(po, 0, r.k[0], r.m[0]);
+      in_val(po, 1, r.k[1], r.m[1]);
+      in_val(po, nxs, r.k[2], r.m[2]);
+      in_val(po, nxs + 1, r.k[3], r.m[3]);
     };
     auto fetch_coef = [&](int k, R& p, R& q) {
-      const int kk = min(max(k, 0), g.nz - 2);
-      const int64_t eg = ce + layer * kk;
-      p = (R)cf[2 * eg];
-      q = (R)cf[2 * eg + 1];
+      const uint32_t kk = (uint32_t)min(max(k, 0), g.nz - 2);
+      p = (R)at(cf, eb + kk * lbR);
+      q = (R)at(cf + 1, eb + kk * lbR);
     };
 
+    const R* vjs = nullptr;
+    const double* bs = nullptr;
+    if constexpr (MODE == kPK) vjs = A.vj + sbase;
+    if constexpr (MODE == kRes) bs = A.bvec + sbase;
     auto fetch_pre = [&](int k, R& p0, R& p1) {
-      const int kc = min(max(k, 0), g.nz - 1);
-      const int64_t own = sbase + (int64_t)kc * plane + oof;
+      const uint32_t kc = (uint32_t)min(max(k, 0), g.nz - 1);
       p0 = 0;
       p1 = 0;
-      if constexpr (MODE == kPK) p0 = A.vj[own];
+      if constexpr (MODE == kPK) p0 = at(vjs, ob + kc * pbR);
       if constexpr (MODE == kRes) {
-        p0 = (R)A.bvec[own];
-        p1 = (R)A.u[own];
+        p0 = (R)at(bs, obd + kc * pbD);
+        p1 = (R)at(us, obd + kc * pbD);
       }
       if constexpr (MODE == kRhs) {
-        p0 = (R)A.fbox[own - sbase];
-        p1 = (R)A.u[own];
+        p0 = (R)at(A.fbox, obd + kc * pbD);
+        p1 = (R)at(us, obd + kc * pbD);
       }
     };
+    // folded constants of the element operators (uniform)
+    const R KX = (R)(g.Hy / (6.0 * g.Hx) * g.Hz / 6.0), KY = (R)(g.Hx / (6.0 * g.Hy) * g.Hz / 6.0);
+    const R KQ = (R)(0.25 * g.Hz / 6.0), KZ = (R)(g.st * g.Hx * g.Hy / (36.0 * g.Hz));
+    const R KM = (R)(g.Hm / 216.0), SB = (R)g.sbar;
     R sj = 0;
     if constexpr (MODE == kPK) sj = (R)A.inv_eta[(int64_t)sb * (A.kmax + 1) + A.j];
 
@@ -246,42 +268,44 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
       const bool slab = k >= 0 && k <= g.nz - 2;
       R o[8];
       {
+        const bool on = slab && elem_xy;
+        const R sc = on ? (R)A.ck : (R)0;
         R xin[8] = {lo.k[0], lo.k[1], lo.k[2], lo.k[3], hi.k[0], hi.k[1], hi.k[2], hi.k[3]};
-        Elem<R>::stiff(xin, cp, cq, g, o);
-        const R sc = (slab && elem_xy) ? (R)A.ck : (R)0;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) o[c] *= sc;
+        Elem<R>::stiff_f(xin, (SB + cp) * (sc * KX), (SB - cp) * (sc * KY), cq * (sc * KQ), sc * KZ, o);
         if constexpr (kMass) {
           R xm[8] = {lo.m[0], lo.m[1], lo.m[2], lo.m[3], hi.m[0], hi.m[1], hi.m[2], hi.m[3]};
           R om[8];
-          Elem<R>::mass(xm, g, om);
-          const R sm = (slab && elem_xy) ? (R)A.cm : (R)0;
+          Elem<R>::mass_f(xm, on ? (R)A.cm * KM : (R)0, om);
 #pragma unroll
-          for (int c = 0; c < 8; ++c) o[c] += sm * om[c];
+          for (int c = 0; c < 8; ++c) o[c] += om[c];
         }
       }
       // assemble the owned node: bottom faces of slab k (plane k), top faces (plane k + 1)
       const R bot = o[3] + shdn(o[2], 1) + shdn(o[1], 8) + shdn(o[0], 9);
       const R top = o[7] + shdn(o[6], 1) + shdn(o[5], 8) + shdn(o[4], 9);
       if (owner && k >= zs && k < ze) {
-        const int64_t own = sbase + (int64_t)k * plane + oof;
+        const uint32_t kk = (uint32_t)k;
         const R sres = acc_top + bot;
+        auto put = [&](auto* base, uint32_t byte_off, auto v) {
+          *(decltype(base))((char*)base + byte_off) = v;
+        };
         if constexpr (MODE == kPK) {
-          A.y[own] = p0 * sj + sres;
+          put(A.y + sbase, ob + kk * pbR, p0 * sj + sres);
         } else if constexpr (MODE == kFull) {
-          A.y[own] = sres;
+          put(A.y + sbase, ob + kk * pbR, sres);
         } else if constexpr (MODE == kRes) {
           const double G = (double)sres;
           const double bb = (double)p0;
           const double F = G - bb;
-          ((TI*)A.r0)[own] = (TI)(-F);
-          ((TI*)A.dout)[own] = (TI)(A.io.dt * diion3((double)p1, A.io));
+          const uint32_t oi = (uint32_t)oof * (uint32_t)sizeof(TI) + kk * (uint32_t)plane * (uint32_t)sizeof(TI);
+          put((TI*)A.r0 + sbase, oi, (TI)(-F));
+          put((TI*)A.dout + sbase, oi, (TI)(A.io.dt * diion3((double)p1, A.io)));
           n0 += F * F;
           n1 += G * G;
           n2 += bb * bb;
         } else {
-          A.bout[own] = (double)sres + A.load * (double)p0;
-          A.ucopy[own] = (double)p1;
+          put(A.bout + sbase, obd + kk * pbD, (double)sres + A.load * (double)p0);
+          put(A.ucopy + sbase, obd + kk * pbD, (double)p1);
         }
       }
       acc_top = top;
@@ -328,7 +352,7 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
         s1 += red[w][1];
         s2 += red[w][2];
       }
-      double* p = A.part + ((int64_t)sb * gridDim.x + blockIdx.x) * 3;
+      double* p = A.part + ((int64_t)sb * A.bps + blk) * 3;
       p[0] = s0;
       p[1] = s1;
       p[2] = s2;
@@ -343,7 +367,8 @@ void wave_grid_of(const Geo& g, Args<R>& a, int32_t B, dim3& grid) {
   a.tiles_x = (int)cdiv(g.nx, WT);
   a.tiles_y = (int)cdiv(g.ny, WT);
   a.zchunks = (int)cdiv(g.nz, WZ);
-  grid = dim3((unsigned)cdiv((int64_t)a.tiles_x * a.tiles_y * a.zchunks, NT / 64), (unsigned)B);
+  a.bps = (int)cdiv((int64_t)a.tiles_x * a.tiles_y * a.zchunks, NT / 64);
+  grid = dim3((unsigned)((int64_t)a.bps * B));
 }
 
 }  // namespace
