@@ -78,9 +78,11 @@ def cpu_baseline(cfg, budget_s):
     phys = cfg["physics"]
     dof_iters, st_dof, n_solves = 0.0, 0.0, 0
     t0 = time.perf_counter()
-    plan = []
-    for l in range(min(2, len(meshes))):
-        plan += [(l, i) for i in range(8 if l == 0 else 1)]
+    # level 0 and level 1 samples, interleaved so that a cut at the budget keeps both
+    plan = [(0, i) for i in range(8)]
+    if len(meshes) > 1:
+        for i in range(8):
+            plan += [(1, i), (0, 8 + i)]
     done = []
     for l, i in plan:
         if time.perf_counter() - t0 > budget_s:

@@ -153,3 +153,58 @@ def source_load(mesh: BoxMesh, f):
 def node_weights(M):
     """w = M 1: integrating the FE interpolant of nodal values gives w . values."""
     return np.asarray(M @ np.ones(M.shape[0])).ravel()
+
+
+def row_products(mesh: BoxMesh, theta, sigma_l, sigma_t, rows, vecs):
+    """Rows of M v and K v for the listed nodes only, each from the (up to 2^d)
+    elements around the node, with K for per-element fibre angles theta (E,).
+
+    The same element matrices as ``assemble``; meant for meshes too large to
+    assemble.  Returns (Mv, Kv), each of shape (len(vecs), len(rows)).
+    """
+    d = mesh.d
+    rows = np.asarray(rows, dtype=np.int64)
+    ijk = np.zeros((rows.size, d), dtype=np.int64)
+    r = rows.copy()
+    for a in range(d):
+        ijk[:, a] = r % mesh.n[a]
+        r //= mesh.n[a]
+    Mv = np.zeros((len(vecs), rows.size))
+    Kv = np.zeros((len(vecs), rows.size))
+    ne = np.array(mesh.ne)
+    for a, off in enumerate(local_offsets(d)):
+        e = ijk - np.array(off)
+        ok = np.all((e >= 0) & (e < ne), axis=1)
+        if not ok.any():
+            continue
+        ek = e[ok]
+        eid = ek[:, 0].copy()
+        stride = 1
+        for k in range(1, d):
+            stride *= ne[k - 1]
+            eid += stride * ek[:, k]
+        G = conductivity_from_angle(np.asarray(theta)[eid], d, sigma_l, sigma_t)
+        Me, Ke = element_matrices(mesh, G)
+        conn = mesh.node_id(ek[:, None, :] + np.array(local_offsets(d))[None, :, :])
+        for v, vec in enumerate(vecs):
+            vals = np.asarray(vec)[conn]  # (k, 2^d)
+            Mv[v, ok] += vals @ Me[a]
+            Kv[v, ok] += np.einsum("kb,kb->k", Ke[:, a, :], vals)
+    return Mv, Kv
+
+
+def stiffness_row_bound(mesh: BoxMesh, sigma_l, sigma_t):
+    """An upper bound of max_i sum_j |K_ij| over every fibre field.
+
+    K_e depends on the angle only through (cos 2t, sin 2t) linearly, K_e = A + cos 2t Bc
+    + sin 2t Bs, so |K_e[a, b]| <= |A[a, b]| + sqrt(Bc[a, b]^2 + Bs[a, b]^2); a node
+    touches at most 2^d elements.
+    """
+    d = mesh.d
+    th = np.array([0.0, 0.5 * np.pi, 0.25 * np.pi])
+    _, Ke = element_matrices(mesh, conductivity_from_angle(th, d, sigma_l, sigma_t))
+    A = 0.5 * (Ke[0] + Ke[1])
+    Bc = 0.5 * (Ke[0] - Ke[1])
+    Bs = Ke[2] - A
+    per_elem = (np.abs(A) + np.sqrt(Bc ** 2 + Bs ** 2)).sum(axis=1).max()
+    return (2 ** d) * per_elem

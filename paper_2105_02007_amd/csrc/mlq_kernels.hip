@@ -443,35 +443,67 @@ void launch_apply_public(const Geo& g, const void* coef, const void* x, const vo
 
 // ---------------------------------------------------------------------------
 // Classical Gram-Schmidt, step j of GMRES, per sample:
-//   part[b][blk][i] = sum_chunk w . Vs_i  (i <= j)
-template <typename T>
+//   part[b][i][blk] = sum_chunk w . Vs_i  (i <= j)
+// One pass: w is read once and all j + 1 projections accumulate in registers
+// (JB >= j + 1 accumulators); each is summed in a fixed order.
+template <typename T, int JB>
 __global__ __launch_bounds__(kBlock) void k_dots(int64_t nn, const T* __restrict__ w, const T* __restrict__ V,
                                                  size_t vs, int j, int kmax, double* __restrict__ part,
                                                  const int32_t* __restrict__ active) {
   const int sb = blockIdx.y;
   if (active[sb] == 0) return;
-  __shared__ double sh[kBlock / 64];
+  __shared__ double sh[JB][kBlock / 64];
   const int64_t base = (int64_t)blockIdx.x * kRedChunk;
   const int64_t end = base + kRedChunk < nn ? base + kRedChunk : nn;
   const T* ws = w + (int64_t)sb * nn;
-  for (int i = 0; i <= j; ++i) {
-    const T* vi = V + i * vs + (int64_t)sb * nn;
-    double acc = 0.0;
-    for (int64_t t = base + threadIdx.x; t < end; t += kBlock) acc += (double)ws[t] * (double)vi[t];
-    acc = block_sum<kBlock>(acc, sh);
-    if (threadIdx.x == 0) part[((int64_t)sb * (kmax + 1) + i) * gridDim.x + blockIdx.x] = acc;
+  const T* vs0 = V + (int64_t)sb * nn;
+  double acc[JB];
+#pragma unroll
+  for (int i = 0; i < JB; ++i) acc[i] = 0.0;
+  for (int64_t t = base + threadIdx.x; t < end; t += kBlock) {
+    const double wv = (double)ws[t];
+#pragma unroll
+    for (int i = 0; i < JB; ++i)
+      if (i <= j) acc[i] += wv * (double)vs0[i * vs + t];
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < JB; ++i)
+    if (i <= j) {
+      const double v = wave_sum(acc[i]);
+      if (lane == 0) sh[i][wid] = v;
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j; i += kBlock) {
+    double r = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) r += sh[i][q];
+    part[((int64_t)sb * (kmax + 1) + i) * gridDim.x + blockIdx.x] = r;
   }
 }
 
 void launch_dots(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s) {
   const dim3 grid((unsigned)w.nred, B);
   const size_t vs = (size_t)g.nn * B;
-  if (mixed)
-    hipLaunchKernelGGL((k_dots<float>), grid, dim3(kBlock), 0, s, g.nn, (const float*)w.w, (const float*)w.V, vs,
-                       j, w.kmax, w.dpart, w.inner_active);
-  else
-    hipLaunchKernelGGL((k_dots<double>), grid, dim3(kBlock), 0, s, g.nn, (const double*)w.w, (const double*)w.V,
-                       vs, j, w.kmax, w.dpart, w.inner_active);
+#define MLQ_DOTS(T, JB)                                                                                       \
+  hipLaunchKernelGGL((k_dots<T, JB>), grid, dim3(kBlock), 0, s, g.nn, (const T*)w.w, (const T*)w.V, vs, j, \
+                     w.kmax, w.dpart, w.inner_active)
+#define MLQ_DOTS_T(T)            \
+  if (j < 4)                     \
+    MLQ_DOTS(T, 4);              \
+  else if (j < 8)                \
+    MLQ_DOTS(T, 8);              \
+  else if (j < 16)               \
+    MLQ_DOTS(T, 16);             \
+  else                           \
+    MLQ_DOTS(T, kMaxInner + 1);
+  if (mixed) {
+    MLQ_DOTS_T(float)
+  } else {
+    MLQ_DOTS_T(double)
+  }
+#undef MLQ_DOTS_T
+#undef MLQ_DOTS
 }
 
 // Vs_{j+1} = w - sum_i hc_i Vs_i, partial |Vs_{j+1}|^2.  Each block first sums the
@@ -1006,16 +1038,15 @@ static void minv_dispatch(const Geo& g, const T* src, T* tmp, T* dst, const doub
                           int32_t B, hipStream_t s) {
   const bool cube = g.nx == g.ny && (g.dim == 2 || g.nz == g.nx);
   int n = cube ? g.nx : 0;
-  // the z pass holds a whole line in registers: FP64 up to 65 entries, FP32 up to 129
+  // both passes hold whole lines in registers (FP64 lines of 129 run at one wave per
+  // SIMD, which the 133 KB LDS plane of the xy pass imposes anyway)
 #define MLQ_MINV(NN) minv_launch<T, NN>(g, src, tmp, dst, inv_eta, j, kmax, tri, nmax, d, u, add_u, active, B, s)
   switch (n) {
     case 9: MLQ_MINV(9); break;
     case 17: MLQ_MINV(17); break;
     case 33: MLQ_MINV(33); break;
     case 65: MLQ_MINV(65); break;
-    case 129:
-      if constexpr (sizeof(T) == 4) MLQ_MINV(129); else MLQ_MINV(0);
-      break;
+    case 129: MLQ_MINV(129); break;
     default: MLQ_MINV(0); break;
   }
 #undef MLQ_MINV
@@ -1132,6 +1163,8 @@ hipError_t prepare_minv_kernels(size_t bytes) {
   set((const void*)(k_plane_xy<float, kOutAddU, 0>));
   set((const void*)(k_plane_xy<float, kOutDivD, 129>));
   set((const void*)(k_plane_xy<float, kOutAddU, 129>));
+  set((const void*)(k_plane_xy<double, kOutDivD, 129>));
+  set((const void*)(k_plane_xy<double, kOutAddU, 129>));
   return e;
 }
 

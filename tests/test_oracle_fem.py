@@ -145,3 +145,37 @@ def test_source_load_reproduces_mass_action():
     g = np.array([0.3, -1.0, 2.0])
     F = fem.source_load(mesh, lambda X: X @ g + 0.5)
     assert np.allclose(F, M @ (mesh.nodes @ g + 0.5), rtol=1e-13, atol=1e-16)
+
+
+def test_row_products_match_assembled():
+    """Row-wise products (used on meshes too large to assemble) equal the assembled rows."""
+    from oracle.fem import row_products
+    for n in ([7, 6, 5], [9, 8]):
+        mesh = BoxMesh(n, hi=[1.0, 0.7, 1.2][:len(n)])
+        ph = W.physics(len(n))
+        th = W.random_angles(11, 1, mesh.n_elems)[0]
+        G = fem.conductivity_from_angle(th, mesh.d, ph["sigma_l"], ph["sigma_t"])
+        M, K = fem.assemble(mesh, G)
+        v1 = W.random_nodal(12, 1, mesh.n_nodes)[0]
+        v2 = W.random_nodal(13, 1, mesh.n_nodes)[0]
+        rows = np.unique(np.concatenate([[0, mesh.n_nodes - 1, n[0] - 1], np.arange(3, mesh.n_nodes, 7)]))
+        Mv, Kv = row_products(mesh, th, ph["sigma_l"], ph["sigma_t"], rows, [v1, v2])
+        for k, v in enumerate((v1, v2)):
+            np.testing.assert_allclose(Mv[k], (M @ v)[rows], rtol=0, atol=1e-15 * np.abs(M @ v).max())
+            np.testing.assert_allclose(Kv[k], (K @ v)[rows], rtol=0, atol=1e-14 * np.abs(K @ v).max())
+
+
+def test_stiffness_row_bound_holds_for_any_field():
+    from oracle.fem import stiffness_row_bound
+    mesh = BoxMesh([6, 5, 4], hi=[1.0, 0.7, 1.2])
+    ph = W.physics(3)
+    bound = stiffness_row_bound(mesh, ph["sigma_l"], ph["sigma_t"])
+    worst = 0.0
+    for seed in range(6):
+        th = W.random_angles(20 + seed, 1, mesh.n_elems)[0]
+        if seed == 0:
+            th[:] = 0.3  # a uniform field
+        G = fem.conductivity_from_angle(th, 3, ph["sigma_l"], ph["sigma_t"])
+        _, K = fem.assemble(mesh, G)
+        worst = max(worst, np.asarray(abs(K).sum(axis=1)).max())
+    assert worst <= bound <= 3.0 * worst
