@@ -67,8 +67,8 @@ struct mlq_level {
   bool mixed = false;
   int kmax = 30;
   // device pointers inside the caller's level blob
-  double* phi64 = nullptr;
-  float* phi32 = nullptr;
+  double* phi64 = nullptr;  // KL basis at the element centres, mode-major (M x P)
+  float* phi32 = nullptr;   // its FP32 copy (mixed-precision synthesis)
   double* sqrt_lambda = nullptr;
   double* theta0 = nullptr;
   double* fbox = nullptr;
@@ -403,11 +403,14 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   };
   hipError_t e = hipSuccess;
   std::vector<float> phi32;
+  std::vector<double> phiT;
   std::vector<double> th0;
   if (desc->arrays_on_device) {
     const hipMemcpyKind k = hipMemcpyDeviceToDevice;
     if (M > 0) {
-      e = hipMemcpyAsync(lv->phi64, desc->phi, sizeof(double) * P * M, k, s);
+      // the blob keeps the basis mode-major (M x P): contiguous per mode for the MFMA synthesis
+      launch_transpose_f64(desc->phi, lv->phi64, P, M, s);
+      e = hipGetLastError();
       if (e == hipSuccess) launch_cast_f32(lv->phi64, lv->phi32, P * M, s);
       if (e == hipSuccess) e = hipMemcpyAsync(lv->sqrt_lambda, desc->sqrt_lambda, sizeof(double) * M, k, s);
     }
@@ -418,12 +421,18 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
         e = hipMemsetAsync(lv->theta0, 0, sizeof(double) * P, s);
     }
   } else {
+    // mode-major copies (M x P) of the P x M row-major input
+    phiT.resize((size_t)P * M);
     phi32.resize((size_t)P * M);
-    for (size_t i = 0; i < phi32.size(); ++i) phi32[i] = (float)desc->phi[i];
+    for (int64_t p = 0; p < P; ++p)
+      for (int32_t k = 0; k < M; ++k) {
+        phiT[(size_t)k * P + p] = desc->phi[(size_t)p * M + k];
+        phi32[(size_t)k * P + p] = (float)desc->phi[(size_t)p * M + k];
+      }
     th0.assign(P, 0.0);
     if (desc->theta0 != nullptr) std::memcpy(th0.data(), desc->theta0, sizeof(double) * P);
     if (M > 0) {
-      e = hipMemcpyAsync(lv->phi64, desc->phi, sizeof(double) * P * M, hipMemcpyHostToDevice, s);
+      e = hipMemcpyAsync(lv->phi64, phiT.data(), sizeof(double) * P * M, hipMemcpyHostToDevice, s);
       if (e == hipSuccess) e = hipMemcpyAsync(lv->phi32, phi32.data(), sizeof(float) * P * M, hipMemcpyHostToDevice, s);
       if (e == hipSuccess) e = hipMemcpyAsync(lv->sqrt_lambda, desc->sqrt_lambda, sizeof(double) * M, hipMemcpyHostToDevice, s);
     }
@@ -486,7 +495,7 @@ mlq_status mlq_sample_fields(mlq_level* level, const double* Y_dev, int32_t batc
   if (level == nullptr || Y_dev == nullptr || theta_dev == nullptr) return fail(MLQ_EINVAL, "NULL argument");
   if (batch < 1 || batch > level->d.max_batch) return fail(MLQ_EINVAL, "batch %d outside [1, max_batch]", batch);
   if (level->M < 1) return fail(MLQ_ESTATE, "level has no KL modes");
-  launch_kl(level->phi64, level->sqrt_lambda, level->theta0, Y_dev, level->P, level->M, batch, theta_dev,
+  launch_kl(level->phi64, level->phi32, level->sqrt_lambda, level->theta0, Y_dev, level->P, level->M, batch, theta_dev,
             level->mixed, (hipStream_t)hip_stream);
   HIP_OK(hipGetLastError());
   return MLQ_OK;

@@ -98,8 +98,9 @@ void launch_qoi(const Work& w, const double* wts, int64_t nn, int32_t B, int qoi
                 double vol, double* qoi_out, hipStream_t s);
 void launch_apply_public(const Geo& g, const void* coef, const void* x, const void* d, void* y,
                          double ck, int32_t B, bool mixed, hipStream_t s);
-void launch_kl(const void* phi, const double* sqrt_lambda, const double* theta0, const double* Y,
-               int64_t P, int32_t M, int32_t B, void* theta, bool mixed, hipStream_t s);
+void launch_kl(const double* phi64T, const float* phi32T, const double* sqrt_lambda, const double* theta0,
+               const double* Y, int64_t P, int32_t M, int32_t B, void* theta, bool mixed, hipStream_t s);
+void launch_transpose_f64(const double* src, double* dst, int64_t rows, int64_t cols, hipStream_t s);
 void launch_lattice(const int64_t* z, const double* shift, int32_t sdim, int64_t N, int64_t first,
                     int32_t count, double* Y, hipStream_t s);
 void launch_newton_reset(const Work& w, int32_t B, hipStream_t s);

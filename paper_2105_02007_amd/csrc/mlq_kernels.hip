@@ -674,48 +674,113 @@ void launch_qoi(const Work& w, const double* wts, int64_t nn, int32_t B, int qoi
 }
 
 // ---------------------------------------------------------------------------
-// KL synthesis eq. (KLlowrank): theta[b][p] = theta0[p] + sum_k phi[p][k] sqrt_lambda[k] Y[k + M b].
-// FP64 reference kernel: a block covers 256 element centres x 8 samples; the
-// scaled coordinates of the 8 samples sit in LDS.
-constexpr int kKLSamples = 8;
-template <typename TO>
-__global__ __launch_bounds__(kBlock) void k_kl64(const double* __restrict__ phi, const double* __restrict__ sl,
-                                                 const double* __restrict__ theta0, const double* __restrict__ Y,
-                                                 int64_t P, int32_t M, int32_t B, TO* __restrict__ theta) {
-  extern __shared__ double ys[];  // [M][kKLSamples]
-  const int b0 = blockIdx.y * kKLSamples;
-  for (int t = threadIdx.x; t < M * kKLSamples; t += kBlock) {
-    const int k = t / kKLSamples, bb = t % kKLSamples;
-    ys[t] = (b0 + bb < B) ? sl[k] * Y[(int64_t)(b0 + bb) * M + k] : 0.0;
+// KL synthesis on the matrix cores, eq. (KLlowrank):
+//   theta[b][p] = theta0[p] + sum_k phiT[k][p] (sqrt(lambda_k) Y[b][k]),
+// a (P x M) (M x B) product with the basis stored mode-major (phiT, M x P), so that
+// the A operand of a wave is 16 consecutive elements of one mode (one contiguous
+// segment).  MFMA 16x16x4 (f32 in mixed mode, f64 in FP64 mode): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; its four results are rows
+// 4 (l / 16) + r (f32) or l / 16 + 4 r (f64) of column l % 16.  A wave owns 16
+// elements and the 64 samples of the block's sample chunk (four 16 x 16 tiles);
+// the block's four waves own 64 consecutive elements.  sqrt(lambda) Y is staged
+// in LDS, 128 modes at a time.
+constexpr int kKLModesPerStage = 128;
+
+template <typename T>
+struct MfmaKL;
+template <>
+struct MfmaKL<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 mma(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <>
+struct MfmaKL<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 mma(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_kl_mfma(const T* __restrict__ phiT, const double* __restrict__ sl,
+                                                    const double* __restrict__ theta0, const double* __restrict__ Y,
+                                                    int64_t P, int32_t M, int32_t B, T* __restrict__ theta) {
+  typedef typename MfmaKL<T>::v4 v4;
+  __shared__ T ys[kKLModesPerStage][64];
+  const int b0 = blockIdx.y * 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t pt = ((int64_t)blockIdx.x * (kBlock / 64) + wid) * 16;  // the wave's first element
+  const int64_t pa = (pt + li < P) ? pt + li : P - 1;                    // clamped A row
+  v4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = v4{0, 0, 0, 0};
+  for (int ks = 0; ks < M; ks += kKLModesPerStage) {
+    const int mk = (M - ks) < kKLModesPerStage ? (M - ks) : kKLModesPerStage;
+    __syncthreads();
+    for (int t = threadIdx.x; t < kKLModesPerStage * 64; t += kBlock) {
+      const int k = t >> 6, bb = t & 63;
+      ys[k][bb] = (k < mk && b0 + bb < B) ? (T)(sl[ks + k] * Y[(int64_t)(b0 + bb) * M + ks + k]) : (T)0;
+    }
+    __syncthreads();
+    if (pt < P) {
+      for (int k0 = 0; k0 < mk; k0 += 32) {
+        T a[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = k0 + 4 * q + lk;
+          a[q] = k < mk ? phiT[(int64_t)(ks + k) * P + pa] : (T)0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = k0 + 4 * q + lk;  // ys rows past mk hold zeros
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[c] = MfmaKL<T>::mma(a[q], ys[k][16 * c + li], acc[c]);
+        }
+      }
+    }
   }
-  __syncthreads();
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= P) return;
-  double acc[kKLSamples];
-  const double t0 = theta0 != nullptr ? theta0[p] : 0.0;
+  if (pt >= P) return;
 #pragma unroll
-  for (int bb = 0; bb < kKLSamples; ++bb) acc[bb] = 0.0;
-  const double* row = phi + p * M;
-  for (int k = 0; k < M; ++k) {
-    const double f = row[k];
+  for (int c = 0; c < 4; ++c) {
+    const int b = b0 + 16 * c + li;
+    if (b >= B) continue;
 #pragma unroll
-    for (int bb = 0; bb < kKLSamples; ++bb) acc[bb] += f * ys[k * kKLSamples + bb];
+    for (int r = 0; r < 4; ++r) {
+      const int64_t p = pt + MfmaKL<T>::row(lane, r);
+      if (p < P) theta[(int64_t)b * P + p] = (T)((theta0 != nullptr ? theta0[p] : 0.0) + (double)acc[c][r]);
+    }
   }
-#pragma unroll
-  for (int bb = 0; bb < kKLSamples; ++bb)
-    if (b0 + bb < B) theta[(int64_t)(b0 + bb) * P + p] = (TO)(t0 + acc[bb]);
 }
 
-void launch_kl(const void* phi, const double* sqrt_lambda, const double* theta0, const double* Y, int64_t P,
-               int32_t M, int32_t B, void* theta, bool mixed, hipStream_t s) {
-  const dim3 grid((unsigned)cdiv(P, kBlock), (unsigned)cdiv(B, kKLSamples));
-  const size_t sh = (size_t)M * kKLSamples * sizeof(double);
+void launch_kl(const double* phi64T, const float* phi32T, const double* sqrt_lambda, const double* theta0,
+               const double* Y, int64_t P, int32_t M, int32_t B, void* theta, bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)cdiv(P, 16 * (kBlock / 64)), (unsigned)cdiv(B, 64));
   if (mixed)
-    hipLaunchKernelGGL((k_kl64<float>), grid, dim3(kBlock), sh, s, (const double*)phi, sqrt_lambda, theta0, Y, P, M,
-                       B, (float*)theta);
+    hipLaunchKernelGGL((k_kl_mfma<float>), grid, dim3(kBlock), 0, s, phi32T, sqrt_lambda, theta0, Y, P, M, B,
+                       (float*)theta);
   else
-    hipLaunchKernelGGL((k_kl64<double>), grid, dim3(kBlock), sh, s, (const double*)phi, sqrt_lambda, theta0, Y, P,
-                       M, B, (double*)theta);
+    hipLaunchKernelGGL((k_kl_mfma<double>), grid, dim3(kBlock), 0, s, phi64T, sqrt_lambda, theta0, Y, P, M, B,
+                       (double*)theta);
+}
+
+// dst (cols x rows) = transpose of src (rows x cols), FP64, through 32 x 33 LDS tiles.
+__global__ void k_transpose_f64(const double* __restrict__ src, double* __restrict__ dst, int64_t rows,
+                                int64_t cols) {
+  __shared__ double t[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows at a time
+  for (int i = ty; i < 32; i += 8)
+    if (r0 + i < rows && c0 + tx < cols) t[i][tx] = src[(r0 + i) * cols + c0 + tx];
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8)
+    if (c0 + i < cols && r0 + tx < rows) dst[(c0 + i) * rows + r0 + tx] = t[tx][i];
+}
+
+void launch_transpose_f64(const double* src, double* dst, int64_t rows, int64_t cols, hipStream_t s) {
+  if (rows < 1 || cols < 1) return;
+  hipLaunchKernelGGL(k_transpose_f64, dim3((unsigned)cdiv(cols, 32), (unsigned)cdiv(rows, 32)), dim3(256), 0, s,
+                     src, dst, rows, cols);
 }
 
 // ---------------------------------------------------------------------------

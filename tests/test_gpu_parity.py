@@ -186,6 +186,31 @@ def test_sample_fields_matches_oracle(env):
         assert np.abs(th - ref).max() <= tol * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("n,n_modes,B", [([10, 7, 6], 13, 70), ([9, 9, 9], 150, 5), ([33, 33, 33], 64, 128)])
+def test_sample_fields_ragged_shapes(env, n, n_modes, B):
+    """The synthesis contraction on shapes that leave partial tiles in every dimension
+    (elements, modes past one LDS stage, samples) against eq. (KLlowrank) in FP64."""
+    torch, mlq = env
+    from oracle import kl
+    from oracle.mesh import BoxMesh
+    mesh = BoxMesh(n)
+    phi = W.random_nodal(41, n_modes, mesh.n_elems).T.copy()
+    sl = W.random_nodal(42, 1, n_modes, 0.01, 0.3)[0]
+    th0 = W.random_nodal(43, 1, mesh.n_elems, -0.5, 0.5)[0]
+    Y = W.mc_normals(3, 0, B, n_modes)
+    ref = kl.field(th0, phi, sl, Y)
+    for prec in (W.PREC_FP64, W.PREC_MIXED):
+        desc, keep = mlq.make_desc(_level(3, n, 8), W.physics(3), n_modes=n_modes, phi=phi, sqrt_lambda=sl,
+                                   theta0=th0, prec=prec, max_batch=B)
+        lv = mlq.Level(desc, keep)
+        th = lv.sample_fields(torch.as_tensor(Y, device="cuda")).double().cpu().numpy()
+        # a dot product of n terms summed in precision u errs by at most ~n u sum|terms|;
+        # FP32 also rounds the basis, the scaled coordinates and the result once each
+        u = 2.0 ** -53 if prec == W.PREC_FP64 else 2.0 ** -24
+        bound = (n_modes + 4) * u * (np.abs(th0)[None, :] + (np.abs(phi) @ (sl[:, None] * np.abs(Y))).T)
+        assert (np.abs(th - ref) <= bound).all(), (prec, (np.abs(th - ref) / bound).max())
+
+
 def test_lattice_normals_match_oracle(env):
     torch, mlq = env
     from oracle import qmc
