@@ -105,6 +105,37 @@ def cpu_baseline(cfg, budget_s):
                 st_dof_per_s=st_dof / el, seconds=el)
 
 
+def kl_synthesis(runner, cfg, dev, reps=5):
+    """Time the KL synthesis (MFMA contraction) of the finest level's batch: HIP events
+    on the stream the binding launches on (torch's current stream)."""
+    import torch
+
+    import workloads as W
+    l = len(runner.levels) - 1
+    L = runner.levels[l]
+    M = cfg["kl"]["n_modes"]
+    B = cfg["sampling"]["n_per_level"][l] * cfg["sampling"].get("n_shifts", 1)
+    Y = torch.as_tensor(W.mc_normals(cfg["seed"], l, B, M), device=dev)
+    theta = L.sample_fields(Y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        L.sample_fields(Y, theta)
+    e1.record()
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    P = L.n_elems
+    wb = 4 if L.mixed else 8
+    flops = 2.0 * P * M * B
+    peak = 157.3 if L.mixed else 78.6  # dense MFMA TFLOP/s for the synthesis dtype
+    gb = (P * M * wb + P * B * wb) / 1e9
+    return dict(kernel="k_kl_mfma", dtype="f32" if L.mixed else "f64", shape=dict(elements=P, modes=M, samples=B),
+                us=round(us, 2), tflops=round(flops / us / 1e6, 2), peak_tflops=peak,
+                frac_mfma=round(flops / us / 1e6 / peak, 4), hbm_gbs=round(gb / us * 1e6, 1),
+                frac_hbm=round(gb / us * 1e6 / HBM_PEAK_GBS, 4))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +270,7 @@ def main():
     }
     if breakdown:
         line["breakdown"] = breakdown
+    line["kl_synthesis"] = kl_synthesis(runner, cfg, dev)
     runner.log = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")

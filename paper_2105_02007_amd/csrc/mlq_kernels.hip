@@ -675,15 +675,17 @@ void launch_qoi(const Work& w, const double* wts, int64_t nn, int32_t B, int qoi
 
 // ---------------------------------------------------------------------------
 // KL synthesis on the matrix cores, eq. (KLlowrank):
-//   theta[b][p] = theta0[p] + sum_k phiT[k][p] (sqrt(lambda_k) Y[b][k]),
-// a (P x M) (M x B) product with the basis stored mode-major (phiT, M x P), so that
-// the A operand of a wave is 16 consecutive elements of one mode (one contiguous
-// segment).  MFMA 16x16x4 (f32 in mixed mode, f64 in FP64 mode): lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16]; its four results are rows
-// 4 (l / 16) + r (f32) or l / 16 + 4 r (f64) of column l % 16.  A wave owns 16
-// elements and the 64 samples of the block's sample chunk (four 16 x 16 tiles);
-// the block's four waves own 64 consecutive elements.  sqrt(lambda) Y is staged
-// in LDS, 128 modes at a time.
+//   theta[b][p] = theta0[p] + sum_k (sqrt(lambda_k) Y[b][k]) phiT[k][p],
+// a (B x M) (M x P) product with the basis stored mode-major (phiT, M x P).  MFMA
+// 16x16x4 (f32 in mixed mode, f64 in FP64 mode) with samples as rows and elements as
+// columns: lane l supplies A[l % 16][l / 16] = sqrt(lambda) Y of sample l % 16 and
+// B[l / 16][l % 16] = phiT of element l % 16 (16 consecutive elements of one mode:
+// one contiguous segment); its four results are rows 4 (l / 16) + r (f32) or
+// l / 16 + 4 r (f64) of column l % 16, so the stores of a 16-lane group cover 16
+// consecutive elements of one sample.  A wave tile is 16 elements by the 64 samples
+// of the block's sample chunk (four 16 x 16 tiles); the block's four waves cover 64
+// consecutive elements, and the block walks kKLTilesPerWave such groups with one
+// staged chunk of sqrt(lambda) Y (128 modes at a time, in LDS).
 constexpr int kKLModesPerStage = 128;
 
 template <typename T>
@@ -701,61 +703,69 @@ struct MfmaKL<double> {
   __device__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
+constexpr int kKLTilesPerWave = 8;  // 16-element tiles a wave walks with one staged chunk
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_kl_mfma(const T* __restrict__ phiT, const double* __restrict__ sl,
                                                     const double* __restrict__ theta0, const double* __restrict__ Y,
                                                     int64_t P, int32_t M, int32_t B, T* __restrict__ theta) {
   typedef typename MfmaKL<T>::v4 v4;
-  __shared__ T ys[kKLModesPerStage][64];
+  __shared__ T ys[kKLModesPerStage][64 + 1];
   const int b0 = blockIdx.y * 64;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int64_t pt = ((int64_t)blockIdx.x * (kBlock / 64) + wid) * 16;  // the wave's first element
-  const int64_t pa = (pt + li < P) ? pt + li : P - 1;                    // clamped A row
-  v4 acc[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) acc[c] = v4{0, 0, 0, 0};
   for (int ks = 0; ks < M; ks += kKLModesPerStage) {
     const int mk = (M - ks) < kKLModesPerStage ? (M - ks) : kKLModesPerStage;
     __syncthreads();
+    // consecutive threads read consecutive modes of one sample (Y is sample-major)
     for (int t = threadIdx.x; t < kKLModesPerStage * 64; t += kBlock) {
-      const int k = t >> 6, bb = t & 63;
+      const int bb = t / kKLModesPerStage, k = t % kKLModesPerStage;
       ys[k][bb] = (k < mk && b0 + bb < B) ? (T)(sl[ks + k] * Y[(int64_t)(b0 + bb) * M + ks + k]) : (T)0;
     }
     __syncthreads();
-    if (pt < P) {
-      for (int k0 = 0; k0 < mk; k0 += 32) {
-        T a[8];
+    for (int it = 0; it < kKLTilesPerWave; ++it) {
+      const int64_t pt = (((int64_t)blockIdx.x * kKLTilesPerWave + it) * (kBlock / 64) + wid) * 16;
+      if (pt >= P) break;
+      const int64_t p = pt + li;
+      const int64_t pa = p < P ? p : P - 1;  // clamped element (B column)
+      v4 acc[4];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int k = k0 + 4 * q + lk;
-          a[q] = k < mk ? phiT[(int64_t)(ks + k) * P + pa] : (T)0;
-        }
+      for (int c = 0; c < 4; ++c) acc[c] = v4{0, 0, 0, 0};
+      // all basis values of the stage for this tile are loaded before the first product
+      T a[kKLModesPerStage / 4];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int k = k0 + 4 * q + lk;  // ys rows past mk hold zeros
+      for (int q = 0; q < kKLModesPerStage / 4; ++q) {
+        const int k = 4 * q + lk;
+        a[q] = k < mk ? phiT[(int64_t)(ks + k) * P + pa] : (T)0;
+      }
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[c] = MfmaKL<T>::mma(a[q], ys[k][16 * c + li], acc[c]);
+      for (int q = 0; q < kKLModesPerStage / 4; ++q) {
+        if (4 * q >= mk) break;  // rows of ys past mk hold zeros
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = MfmaKL<T>::mma(ys[4 * q + lk][16 * c + li], a[q], acc[c]);
+      }
+      if (p < P) {
+        const double t0 = ks == 0 ? (theta0 != nullptr ? theta0[p] : 0.0) : 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int b = b0 + 16 * c + MfmaKL<T>::row(lane, r);
+            if (b < B) {
+              T* o = theta + (int64_t)b * P + p;
+              // modes beyond the first stage add to the partial field written before
+              *o = ks == 0 ? (T)(t0 + (double)acc[c][r]) : (T)((double)*o + (double)acc[c][r]);
+            }
+          }
         }
       }
-    }
-  }
-  if (pt >= P) return;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int b = b0 + 16 * c + li;
-    if (b >= B) continue;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t p = pt + MfmaKL<T>::row(lane, r);
-      if (p < P) theta[(int64_t)b * P + p] = (T)((theta0 != nullptr ? theta0[p] : 0.0) + (double)acc[c][r]);
     }
   }
 }
 
 void launch_kl(const double* phi64T, const float* phi32T, const double* sqrt_lambda, const double* theta0,
                const double* Y, int64_t P, int32_t M, int32_t B, void* theta, bool mixed, hipStream_t s) {
-  const dim3 grid((unsigned)cdiv(P, 16 * (kBlock / 64)), (unsigned)cdiv(B, 64));
+  const dim3 grid((unsigned)cdiv(P, 16 * (kBlock / 64) * kKLTilesPerWave), (unsigned)cdiv(B, 64));
   if (mixed)
     hipLaunchKernelGGL((k_kl_mfma<float>), grid, dim3(kBlock), 0, s, phi32T, sqrt_lambda, theta0, Y, P, M, B,
                        (float*)theta);
