@@ -12,6 +12,8 @@ Modules and the paper passages they follow:
 * ``mesh``       -- uniform Q1 box meshes (Section 3.1, nested meshes h_l ~ 2^-l).
 * ``fem``        -- conductivity eq. (AdmV), mass and stiffness matrices and the
                     load vector of the Galerkin semi-discretisation eq. (semi-disc).
+* ``tetfem``     -- the same on P1 tetrahedral meshes, with the per-element fibre
+                    frame and the point location of the non-nested transfer.
 * ``ionic``      -- the cubic ionic current eq. (ionic_term).
 * ``stepper``    -- Crank-Nicolson space-time system eq. (st-system) with the
                     reaction term eq. (mono_disc), solved by forward substitution

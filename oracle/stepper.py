@@ -43,10 +43,14 @@ class Problem:
     def __init__(self, mesh: BoxMesh, G, p, n_steps, source=None):
         self.mesh, self.p, self.n_steps = mesh, p, int(n_steps)
         self.dt = p["t_end"] / self.n_steps
-        self.M, self.K = fem.assemble(mesh, G)
+        if isinstance(mesh, BoxMesh):
+            self.M, self.K = fem.assemble(mesh, G)
+            self.F_box = fem.box_load(mesh, p["stim_lo"], p["stim_hi"])
+        else:  # P1 tetrahedra (oracle/tetfem.py): own assembly, ball stimulus
+            self.M, self.K = mesh.assemble(G)
+            self.F_box = mesh.stim_load(p)
         self.A = (self.M + 0.5 * self.dt * self.K).tocsr()
         self.B = (self.M - 0.5 * self.dt * self.K).tocsr()
-        self.F_box = fem.box_load(mesh, p["stim_lo"], p["stim_hi"])
         self.source = source  # optional callable t -> load vector (manufactured solutions)
         self.w = fem.node_weights(self.M)
         self.lin_iters = 0  # linear-solver iterations (a direct solve counts as one)
