@@ -58,7 +58,7 @@ typedef enum {
 
 typedef enum { MLQ_FP64 = 0, MLQ_MIXED = 1 } mlq_precision;
 typedef enum { MLQ_QOI_MEAN_U_FINAL = 0, MLQ_QOI_MEAN_ACT_TIME = 1 } mlq_qoi;
-typedef enum { MLQ_MESH_Q1_BOX = 0 } mlq_mesh_kind;
+typedef enum { MLQ_MESH_Q1_BOX = 0, MLQ_MESH_P1_TET = 1 } mlq_mesh_kind;
 
 /* per-sample status codes written by mlq_solve_batch */
 enum { MLQ_SAMPLE_OK = 0, MLQ_SAMPLE_NOCONV = 1, MLQ_SAMPLE_NAN = 2 };
@@ -67,9 +67,9 @@ enum { MLQ_SAMPLE_OK = 0, MLQ_SAMPLE_NOCONV = 1, MLQ_SAMPLE_NAN = 2 };
  * constants).  The arrays are read during mlq_create_level; they are host
  * pointers unless arrays_on_device is 1. */
 typedef struct {
-  int32_t dim;        /* 2 or 3 */
-  int32_t mesh_kind;  /* MLQ_MESH_Q1_BOX */
-  int64_t n[3];       /* nodes per axis (>= 2 each; unused axes ignored; at most 2^27 nodes in total) */
+  int32_t dim;        /* 2 or 3 (3 for tetrahedra) */
+  int32_t mesh_kind;  /* MLQ_MESH_Q1_BOX or MLQ_MESH_P1_TET */
+  int64_t n[3];       /* box: nodes per axis (>= 2 each; unused axes ignored; at most 2^27 nodes in total) */
   double lo[3], hi[3];/* box corners */
   int32_t n_steps;    /* time steps on [0, t_end]; dt = t_end / n_steps */
   double t_end;
@@ -90,6 +90,19 @@ typedef struct {
   int32_t max_inner;                  /* GMRES iterations per Newton step (<= 64) */
   int32_t max_batch;                  /* largest batch used with this level (<= 65535) */
   int32_t arrays_on_device;           /* 1: phi, sqrt_lambda, theta0 are device pointers */
+  /* P1 tetrahedra (mesh_kind = MLQ_MESH_P1_TET; Section 3.1 with the P1 space of a
+   * shape-regular tetrahedral mesh).  Host arrays, always; copied at creation.
+   * The elements of the level are the tetrahedra (P = n_tet); the fibre of
+   * element e is f = cos(theta_e) e_circ[e] + sin(theta_e) e_long[e], eq. (AdmV)
+   * with V = sigma_l f.  The stimulus is the ball (stim_center, stim_radius):
+   * load F = M chi with chi the indicator of the vertices inside it.  The
+   * Krylov preconditioner is the diagonal of M (1 + D). */
+  int64_t n_vert, n_tet;              /* vertices (<= 2^27), tetrahedra (<= 2^27) */
+  const double* xyz;                  /* n_vert x 3 */
+  const int32_t* tets;                /* n_tet x 4 vertex indices, positively oriented */
+  const double* e_circ;               /* n_tet x 3 unit vectors */
+  const double* e_long;               /* n_tet x 3 unit vectors orthogonal to e_circ */
+  double stim_center[3], stim_radius;
 } mlq_level_desc;
 
 typedef struct mlq_level mlq_level; /* opaque */

@@ -74,6 +74,8 @@ struct mlq_level {
   double* fbox = nullptr;
   double* wts = nullptr;
   void* tri = nullptr;  // 1 / pivots of tridiag(1, 4, 1) per axis, [3][nmax], inner precision
+  bool tet = false;     // P1 tetrahedra
+  TetDev td{};          // their device data (inside the blob)
   int nmax = 0;
   // pinned host flags
   int32_t* host_flags = nullptr;
@@ -140,10 +142,12 @@ void harvest(mlq_level* lv) {
 namespace {
 
 struct BlobLayout {
-  size_t phi64, phi32, sl, th0, fbox, wts, tri, total;
+  size_t phi64, phi32, sl, th0, fbox, wts, tri;
+  size_t rowptr, col, mval, mval32, mdiag, mdiag32, cptr, cdat, geo;  // tetrahedral levels
+  size_t total;
 };
 
-BlobLayout blob_layout(int64_t P, int64_t M, int64_t nn, int64_t nmax) {
+BlobLayout blob_layout(int64_t P, int64_t M, int64_t nn, int64_t nmax, const mlq::TetHost* th = nullptr) {
   BlobLayout L{};
   size_t o = 0;
   L.tri = o;   o = align256(o + sizeof(double) * 3 * nmax);
@@ -153,6 +157,17 @@ BlobLayout blob_layout(int64_t P, int64_t M, int64_t nn, int64_t nmax) {
   L.th0 = o;   o = align256(o + sizeof(double) * P);
   L.fbox = o;  o = align256(o + sizeof(double) * nn);
   L.wts = o;   o = align256(o + sizeof(double) * nn);
+  if (th != nullptr) {
+    L.rowptr = o;  o = align256(o + sizeof(int32_t) * (th->nv + 1));
+    L.col = o;     o = align256(o + sizeof(int32_t) * th->nnz);
+    L.mval = o;    o = align256(o + sizeof(double) * th->nnz);
+    L.mval32 = o;  o = align256(o + sizeof(float) * th->nnz);
+    L.mdiag = o;   o = align256(o + sizeof(double) * th->nv);
+    L.mdiag32 = o; o = align256(o + sizeof(float) * th->nv);
+    L.cptr = o;    o = align256(o + sizeof(int32_t) * (th->nnz + 1));
+    L.cdat = o;    o = align256(o + sizeof(int32_t) * th->nc);
+    L.geo = o;     o = align256(o + sizeof(double) * mlq::kTetGeo * th->nt);
+  }
   L.total = o;
   return L;
 }
@@ -160,12 +175,15 @@ BlobLayout blob_layout(int64_t P, int64_t M, int64_t nn, int64_t nmax) {
 mlq_status validate(const mlq_level_desc* d) {
   if (d == nullptr) return fail(MLQ_EINVAL, "descriptor is NULL");
   if (d->dim != 2 && d->dim != 3) return fail(MLQ_EINVAL, "dim must be 2 or 3 (got %d)", d->dim);
-  if (d->mesh_kind != MLQ_MESH_Q1_BOX) return fail(MLQ_EINVAL, "unsupported mesh_kind %d", d->mesh_kind);
-  for (int a = 0; a < d->dim; ++a) {
+  if (d->mesh_kind != MLQ_MESH_Q1_BOX && d->mesh_kind != MLQ_MESH_P1_TET)
+    return fail(MLQ_EINVAL, "unsupported mesh_kind %d", d->mesh_kind);
+  if (d->mesh_kind == MLQ_MESH_P1_TET) {
+    if (d->dim != 3) return fail(MLQ_EINVAL, "tetrahedral levels are 3D");
+  } else for (int a = 0; a < d->dim; ++a) {
     if (d->n[a] < 2 || d->n[a] > (1 << 20)) return fail(MLQ_EINVAL, "n[%d] = %lld out of range", a, (long long)d->n[a]);
     if (!(d->hi[a] > d->lo[a])) return fail(MLQ_EINVAL, "box axis %d is empty", a);
   }
-  {
+  if (d->mesh_kind == MLQ_MESH_Q1_BOX) {
     // per-sample offsets inside the kernels are 32-bit byte offsets
     double nn = 1.0;
     for (int a = 0; a < d->dim; ++a) nn *= (double)d->n[a];
@@ -195,6 +213,11 @@ mlq_status validate(const mlq_level_desc* d) {
 }
 
 void sizes_of(const mlq_level_desc* d, int64_t* nn, int64_t* P) {
+  if (d->mesh_kind == MLQ_MESH_P1_TET) {
+    *nn = d->n_vert;
+    *P = d->n_tet;
+    return;
+  }
   int64_t a = 1, b = 1;
   for (int k = 0; k < d->dim; ++k) {
     a *= d->n[k];
@@ -214,7 +237,7 @@ Work carve_workspace(void* base, const Geo& geo, int32_t B, int kmax, bool mixed
   w.kmax = kmax;
   w.nblk = (int32_t)cdiv(nn, kBlock);
   w.nred = (int32_t)cdiv(nn, kRedChunk);
-  w.nres = geo.dim == 3 ? stencil3_blocks(geo) : w.nblk;
+  w.nres = (geo.dim == 3 && !geo.tet) ? stencil3_blocks(geo) : w.nblk;
   const size_t ti = mixed ? sizeof(float) : sizeof(double);
   const size_t vn = (size_t)nn * B;
   char* p = (char*)base;
@@ -232,7 +255,8 @@ Work carve_workspace(void* base, const Geo& geo, int32_t B, int kmax, bool mixed
   w.z = take(vn * ti);
   w.w = take(vn * ti);
   w.V = take(vn * ti * (kmax + 1));
-  w.coef = take((size_t)P * B * 2 * ti);
+  // box: per element (p, q); tetrahedra: per-sample stiffness values of the CSR
+  w.coef = take(geo.tet ? (size_t)geo.nnz * B * ti : (size_t)P * B * 2 * ti);
   const size_t npart = std::max((size_t)std::max(w.nblk, w.nres) * 3, (size_t)w.nred * (kmax + 1));
   w.part = (double*)take(npart * B * sizeof(double));
   w.dpart = (double*)take((size_t)w.nred * (kmax + 1) * B * sizeof(double));
@@ -266,6 +290,13 @@ mlq_status mlq_level_bytes(const mlq_level_desc* desc, size_t* level_bytes) {
   if (st != MLQ_OK) return st;
   int64_t nn, P;
   sizes_of(desc, &nn, &P);
+  if (desc->mesh_kind == MLQ_MESH_P1_TET) {
+    mlq::TetHost th;
+    const std::string err = mlq::tet_build(desc, th, false);
+    if (!err.empty()) return fail(MLQ_EINVAL, "%s", err.c_str());
+    *level_bytes = blob_layout(P, desc->n_modes, nn, 1, &th).total;
+    return MLQ_OK;
+  }
   *level_bytes = blob_layout(P, desc->n_modes, nn, std::max({desc->n[0], desc->n[1], desc->n[2]})).total;
   return MLQ_OK;
 }
@@ -281,8 +312,14 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   int64_t nn, P;
   sizes_of(desc, &nn, &P);
   const int64_t M = desc->n_modes;
-  const int64_t nmax = std::max({desc->n[0], desc->n[1], desc->n[2]});
-  const BlobLayout L = blob_layout(P, M, nn, nmax);
+  const bool tet = desc->mesh_kind == MLQ_MESH_P1_TET;
+  mlq::TetHost th;
+  if (tet) {
+    const std::string err = mlq::tet_build(desc, th, true);
+    if (!err.empty()) return fail(MLQ_EINVAL, "%s", err.c_str());
+  }
+  const int64_t nmax = tet ? 1 : std::max({desc->n[0], desc->n[1], desc->n[2]});
+  const BlobLayout L = blob_layout(P, M, nn, nmax, tet ? &th : nullptr);
   if (level_bytes < L.total) return fail(MLQ_ESIZE, "level blob too small: %zu < %zu", level_bytes, L.total);
   hipStream_t s = (hipStream_t)hip_stream;
 
@@ -296,7 +333,9 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   lv->mixed = desc->prec == MLQ_MIXED;
   lv->kmax = desc->max_inner;
   const int dim = desc->dim;
-  for (int a = 0; a < 3; ++a) lv->h[a] = a < dim ? (desc->hi[a] - desc->lo[a]) / (double)(desc->n[a] - 1) : 1.0;
+  lv->tet = tet;
+  if (!tet)
+    for (int a = 0; a < 3; ++a) lv->h[a] = a < dim ? (desc->hi[a] - desc->lo[a]) / (double)(desc->n[a] - 1) : 1.0;
   const double hx = lv->h[0], hy = lv->h[1], hz = lv->h[2];
 
   Geo& g = lv->geo;
@@ -324,13 +363,16 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   g.Hz = hz;
   g.sbar = 0.5 * (desc->sigma_l + desc->sigma_t);
   g.st = desc->sigma_t;
+  g.tet = tet ? 1 : 0;
+  g.nnz = tet ? th.nnz : 0;
+  if (tet) g.nx = g.ny = g.nz = 0;
   lv->io = Ionic{desc->alpha, desc->u_rest, desc->u_th, desc->u_peak, desc->t_end / desc->n_steps};
 
   // host-side level data: stimulus load vector (exact integral of the box
   // indicator against each tensor-product hat) and node weights w = M 1
   std::vector<double> f1[3], w1[3];
   double vol = 1.0;
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < 3 && !tet; ++a) {
     const int64_t n = a < dim ? desc->n[a] : 1;
     f1[a].assign(n, 1.0);
     w1[a].assign(n, 1.0);
@@ -341,9 +383,16 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
     }
     vol *= desc->hi[a] - desc->lo[a];
   }
-  lv->vol = vol;
-  std::vector<double> fbox(nn), wts(nn);
-  for (int64_t k = 0; k < (dim == 3 ? desc->n[2] : 1); ++k)
+  lv->vol = tet ? th.vol : vol;
+  std::vector<double> fbox, wts;
+  if (tet) {
+    fbox.swap(th.fload);
+    wts.swap(th.wts);
+  } else {
+    fbox.resize(nn);
+    wts.resize(nn);
+  }
+  for (int64_t k = 0; k < (tet ? 0 : (dim == 3 ? desc->n[2] : 1)); ++k)
     for (int64_t j = 0; j < desc->n[1]; ++j)
       for (int64_t i = 0; i < desc->n[0]; ++i) {
         const int64_t id = i + desc->n[0] * (j + desc->n[1] * k);
@@ -363,7 +412,7 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   // preconditioner tables: pivots of tridiag(1, 4, 1) with 2 at both ends, per axis
   std::vector<double> tri64(3 * nmax, 0.0);
   std::vector<float> tri32(3 * nmax, 0.0f);
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < 3 && !tet; ++a) {
     const int64_t n = a < dim ? desc->n[a] : 1;
     double prev = 0.0;
     for (int64_t i = 0; i < n; ++i) {
@@ -375,7 +424,7 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
     }
   }
   // LDS staging of the preconditioner's line solves
-  {
+  if (!tet) {
     const size_t ti = lv->mixed ? sizeof(float) : sizeof(double);
     // one x-y plane per workgroup (2D: the whole sample)
     const size_t plane = ti * (size_t)desc->n[0] * (size_t)desc->n[1];
@@ -444,6 +493,37 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
     else
       e = hipMemcpyAsync(lv->tri, tri64.data(), sizeof(double) * 3 * nmax, hipMemcpyHostToDevice, s);
   }
+  if (e == hipSuccess && tet) {
+    TetDev& t = lv->td;
+    t.nv = th.nv;
+    t.nt = th.nt;
+    t.nnz = th.nnz;
+    t.nc = th.nc;
+    t.rowptr = (const int32_t*)(base + L.rowptr);
+    t.col = (const int32_t*)(base + L.col);
+    t.mval = (const double*)(base + L.mval);
+    t.mval32 = (const float*)(base + L.mval32);
+    t.mdiag = (const double*)(base + L.mdiag);
+    t.mdiag32 = (const float*)(base + L.mdiag32);
+    t.cptr = (const int32_t*)(base + L.cptr);
+    t.cdat = (const int32_t*)(base + L.cdat);
+    t.geo = (const double*)(base + L.geo);
+    std::vector<float> m32(th.mval.begin(), th.mval.end()), d32(th.mdiag.begin(), th.mdiag.end());
+    auto up = [&](const void* dst, const void* src, size_t bytes) {
+      if (e == hipSuccess) e = hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    up(t.rowptr, th.rowptr.data(), sizeof(int32_t) * th.rowptr.size());
+    up(t.col, th.col.data(), sizeof(int32_t) * th.col.size());
+    up(t.mval, th.mval.data(), sizeof(double) * th.mval.size());
+    up(t.mval32, m32.data(), sizeof(float) * m32.size());
+    up(t.mdiag, th.mdiag.data(), sizeof(double) * th.mdiag.size());
+    up(t.mdiag32, d32.data(), sizeof(float) * d32.size());
+    up(t.cptr, th.cptr.data(), sizeof(int32_t) * th.cptr.size());
+    up(t.cdat, th.cdat.data(), sizeof(int32_t) * th.cdat.size());
+    up(t.geo, th.geo.data(), sizeof(double) * th.geo.size());
+    // the host vectors must outlive the asynchronous copies
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
   if (e == hipSuccess) e = hipMemcpyAsync(lv->fbox, fbox.data(), sizeof(double) * nn, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(lv->wts, wts.data(), sizeof(double) * nn, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -510,6 +590,13 @@ mlq_status mlq_apply(mlq_level* level, const void* theta_dev, int32_t batch, con
   Work w = carve_workspace(ws_dev, level->geo, batch, level->kmax, level->mixed);
   if (ws_bytes < w.bytes) return fail(MLQ_ESIZE, "workspace too small: %zu < %zu", ws_bytes, w.bytes);
   hipStream_t s = (hipStream_t)hip_stream;
+  if (level->tet) {
+    launch_tet_assemble(level->td, theta_dev, w.coef, batch, level->d.sigma_t, level->d.sigma_l - level->d.sigma_t,
+                        level->mixed, s);
+    launch_tet_apply(level->td, w.coef, x_dev, d_dev, y_dev, 0.5 * level->io.dt, batch, nullptr, level->mixed, s);
+    HIP_OK(hipGetLastError());
+    return MLQ_OK;
+  }
   launch_coefs(theta_dev, w.coef, level->P, batch, 0.5 * (level->d.sigma_l - level->d.sigma_t), level->mixed, s);
   if (level->geo.dim == 3)
     launch_apply_full3(level->geo, w.coef, x_dev, d_dev, y_dev, 0.5 * level->io.dt, batch, level->mixed, s);
@@ -545,7 +632,12 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
   const double dt = level->io.dt;
   const int kmax = level->kmax;
 
-  launch_coefs(theta_dev, w.coef, level->P, batch, 0.5 * (d.sigma_l - d.sigma_t), mixed, s);
+  const bool tet = level->tet;
+  const TetDev& td = level->td;
+  if (tet)
+    launch_tet_assemble(td, theta_dev, w.coef, batch, d.sigma_t, d.sigma_l - d.sigma_t, mixed, s);
+  else
+    launch_coefs(theta_dev, w.coef, level->P, batch, 0.5 * (d.sigma_l - d.sigma_t), mixed, s);
   launch_init(w, level->nn, batch, d.u_th, s);
   HIP_OK(hipGetLastError());
 
@@ -555,7 +647,9 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
     const double t0 = (double)k * dt, t1 = (double)(k + 1) * dt;
     const double load = 0.5 * dt * (rate(t1) + rate(t0));
     timed(level, MLQ_K_RHS, nn * batch, s, [&] {
-      if (g.dim == 3)
+      if (tet)
+        launch_tet_rhs(td, w, level->fbox, load, dt, batch, mixed, s);
+      else if (g.dim == 3)
         launch_rhs3(g, w, level->fbox, load, dt, batch, mixed, s);
       else
         launch_rhs(g, w, level->fbox, load, dt, batch, mixed, s);
@@ -564,7 +658,9 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
     int32_t active = batch;
     for (int it = 0;; ++it) {
       timed(level, MLQ_K_RESIDUAL, nn * active, s, [&] {
-        if (g.dim == 3)
+        if (tet)
+          launch_tet_residual(td, level->io, w, batch, mixed, s);
+        else if (g.dim == 3)
           launch_residual3(g, level->io, w, batch, mixed, s);
         else
           launch_residual(g, level->io, w, batch, mixed, s);
@@ -583,10 +679,16 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
       int32_t inner = active;
       for (int j = 0; j < kmax; ++j) {
         const double units = nn * inner;
-        timed(level, MLQ_K_PRECOND, units, s,
-              [&] { launch_minv_basis(g, w, level->tri, level->nmax, j, batch, mixed, s); });
+        timed(level, MLQ_K_PRECOND, units, s, [&] {
+          if (tet)
+            launch_tet_jacobi_basis(td, w, j, batch, mixed, s);
+          else
+            launch_minv_basis(g, w, level->tri, level->nmax, j, batch, mixed, s);
+        });
         timed(level, MLQ_K_APPLY, units, s, [&] {
-          if (g.dim == 3)
+          if (tet)  // Jacobi preconditioning: the operator is the full Jacobian applied to z
+            launch_tet_apply(td, w.coef, w.z, w.d, w.w, 0.5 * dt, batch, w.inner_active, mixed, s);
+          else if (g.dim == 3)
             launch_apply_pk3(g, w, j, 0.5 * dt, batch, mixed, s);
           else
             launch_apply_pk(g, w, j, 0.5 * dt, batch, mixed, s);
@@ -603,7 +705,10 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
       }
       timed(level, MLQ_K_UPDATE, nn * active, s, [&] {
         launch_solve_y(w, batch, s);
-        launch_update_pm(g, w, level->tri, level->nmax, batch, mixed, s);
+        if (tet)
+          launch_tet_update(td, w, batch, mixed, s);
+        else
+          launch_update_pm(g, w, level->tri, level->nmax, batch, mixed, s);
       });
     }
     timed(level, MLQ_K_QOI, nn * batch, s, [&] { launch_activation(w, level->nn, batch, d.u_th, t0, dt, s); });

@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/mlq.h"
 
@@ -24,7 +25,38 @@ struct Geo {
   double Hx, Hy, Hz;   // edge lengths
   double sbar;         // (sigma_l + sigma_t) / 2
   double st;           // sigma_t
+  int32_t tet;         // 1: P1 tetrahedra (TetDev holds the mesh), 0: Q1 box
+  int64_t nnz;         // tetrahedra: nonzeros of the vertex adjacency
 };
+
+// P1 tetrahedral level data on the device (inside the level blob).  The sparsity
+// of M and K is the vertex adjacency (CSR); each nonzero lists the element
+// matrix entries that add into it, in increasing element order.
+struct TetDev {
+  int64_t nv, nt, nnz, nc;
+  const int32_t* rowptr;  // nv + 1
+  const int32_t* col;     // nnz, sorted within a row
+  const double* mval;     // nnz: consistent P1 mass
+  const float* mval32;    // nnz
+  const double* mdiag;    // nv: diagonal of M
+  const float* mdiag32;   // nv
+  const int32_t* cptr;    // nnz + 1
+  const int32_t* cdat;    // nc: (tet << 4) | (4 a + b), a = local row vertex, b = local column vertex
+  const double* geo;      // nt x kTetGeo: grad phi_0..3 (12), e_circ (3), e_long (3), volume
+};
+constexpr int kTetGeo = 19;
+
+// Host-side preparation of a tetrahedral level (mlq_tetmesh.cpp).
+struct TetHost {
+  int64_t nv = 0, nt = 0, nnz = 0, nc = 0;
+  std::vector<int32_t> rowptr, col, cptr, cdat;
+  std::vector<double> mval, mdiag, geo, wts, fload;
+  double vol = 0.0;
+};
+// Validates the tetrahedral fields of desc and builds the CSR structure (and, with
+// values = true, the mass, contributions, geometry, weights and stimulus load).
+// Returns an empty string on success, else the reason.
+std::string tet_build(const mlq_level_desc* d, TetHost& h, bool values);
 
 // Physics constants of eq. (ionic_term) and the time step.
 struct Ionic {
@@ -127,5 +159,16 @@ void launch_residual3(const Geo& g, const Ionic& io, const Work& w, int32_t B, b
 void launch_rhs3(const Geo& g, const Work& w, const double* fbox, double load_coef, double dt, int32_t B, bool mixed,
                  hipStream_t s);
 void launch_cast_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+
+// P1 tetrahedra (mlq_tet.hip).  kval: per-sample stiffness values [B][nnz], inner precision.
+void launch_tet_assemble(const TetDev& t, const void* theta, void* kval, int32_t B, double sigma_t, double dsig,
+                         bool mixed, hipStream_t s);
+void launch_tet_apply(const TetDev& t, const void* kval, const void* x, const void* d, void* y, double ck, int32_t B,
+                      const int32_t* active, bool mixed, hipStream_t s);
+void launch_tet_residual(const TetDev& t, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);
+void launch_tet_rhs(const TetDev& t, const Work& w, const double* fload, double load, double dt, int32_t B,
+                    bool mixed, hipStream_t s);
+void launch_tet_jacobi_basis(const TetDev& t, const Work& w, int j, int32_t B, bool mixed, hipStream_t s);
+void launch_tet_update(const TetDev& t, const Work& w, int32_t B, bool mixed, hipStream_t s);
 
 }  // namespace mlq

@@ -1,0 +1,256 @@
+// P1 tetrahedral operators of the space-time solve (Section 3.1 eq. (semi-disc)
+// with the P1 space of a tetrahedral mesh; Section 3.2 Jacobian).
+//
+// The stiffness depends on the sample through the fibre angle of each element,
+//   K_e[a][b] = |T| ( sigma_t g_a . g_b + (sigma_l - sigma_t) (g_a . f)(g_b . f) ),
+//   f = cos(theta) e_circ + sin(theta) e_long,
+// (eq. (AdmV) with V = sigma_l f; g_a = grad phi_a).  Once per solve its values are
+// gathered per nonzero of the vertex-adjacency CSR (each nonzero sums its element
+// contributions in increasing element order: deterministic, no atomics) into
+// kval[b][nz].  The mass M (P1, |T| (1 + delta_ab) / 20) is shared by all samples.
+// Every operator application is then a row loop over the CSR with one thread per
+// (row, sample); rows of one sample are contiguous, samples on blockIdx.y.
+#include "mlq_internal.h"
+
+namespace mlq {
+
+namespace {
+
+__device__ inline double tet_iion(double u, const Ionic& io) {
+  return io.alpha * (u - io.u_rest) * (u - io.u_th) * (u - io.u_peak);
+}
+__device__ inline double tet_diion(double u, const Ionic& io) {
+  const double a = u - io.u_rest, b = u - io.u_th, c = u - io.u_peak;
+  return io.alpha * (b * c + a * c + a * b);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tet_assemble(TetDev t, const T* __restrict__ theta, T* __restrict__ kval,
+                                                         double sigma_t, double dsig) {
+  const int sb = blockIdx.y;
+  const int64_t nz = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (nz >= t.nnz) return;
+  const T* th = theta + (int64_t)sb * t.nt;
+  double acc = 0.0;
+  for (int32_t c = t.cptr[nz]; c < t.cptr[nz + 1]; ++c) {
+    const int32_t code = t.cdat[c];
+    const int64_t e = code >> 4;
+    const int a = (code >> 2) & 3, b = code & 3;
+    const double* G = t.geo + e * kTetGeo;
+    const double ga0 = G[3 * a], ga1 = G[3 * a + 1], ga2 = G[3 * a + 2];
+    const double gb0 = G[3 * b], gb1 = G[3 * b + 1], gb2 = G[3 * b + 2];
+    double sn, cs;
+    sincos((double)th[e], &sn, &cs);
+    const double f0 = cs * G[12] + sn * G[15], f1 = cs * G[13] + sn * G[16], f2 = cs * G[14] + sn * G[17];
+    const double gg = ga0 * gb0 + ga1 * gb1 + ga2 * gb2;
+    const double af = ga0 * f0 + ga1 * f1 + ga2 * f2;
+    const double bf = gb0 * f0 + gb1 * f1 + gb2 * f2;
+    acc += G[18] * (sigma_t * gg + dsig * af * bf);
+  }
+  kval[(int64_t)sb * t.nnz + nz] = (T)acc;
+}
+
+// y = M ((1 + d) x) + ck K x
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tet_apply(TetDev t, const T* __restrict__ kval, const T* __restrict__ x,
+                                                      const T* __restrict__ d, T* __restrict__ y, T ck,
+                                                      const int32_t* __restrict__ active) {
+  const int sb = blockIdx.y;
+  if (active != nullptr && active[sb] == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= t.nv) return;
+  const T* mv = nullptr;
+  if constexpr (sizeof(T) == 4) mv = (const T*)t.mval32; else mv = (const T*)t.mval;
+  const int64_t so = (int64_t)sb * t.nv;
+  const T* kv = kval + (int64_t)sb * t.nnz;
+  T acc = 0;
+  for (int32_t nz = t.rowptr[i]; nz < t.rowptr[i + 1]; ++nz) {
+    const int64_t j = so + t.col[nz];
+    acc += (mv[nz] * ((T)1 + d[j]) + ck * kv[nz]) * x[j];
+  }
+  y[so + i] = acc;
+}
+
+// F = M (u + dt I_ion(u)) + dt/2 K u - b (FP64), r0 = -F, d = dt I_ion'(u), partial norms
+template <typename TI>
+__global__ __launch_bounds__(kBlock) void k_tet_residual(TetDev t, Ionic io, const TI* __restrict__ kval,
+                                                         const double* __restrict__ u, const double* __restrict__ bv,
+                                                         TI* __restrict__ r0, TI* __restrict__ dout,
+                                                         double* __restrict__ part,
+                                                         const int32_t* __restrict__ active) {
+  const int sb = blockIdx.y;
+  if (active[sb] == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+  if (i < t.nv) {
+    const int64_t so = (int64_t)sb * t.nv;
+    const TI* kv = kval + (int64_t)sb * t.nnz;
+    const double ck = 0.5 * io.dt;
+    double G = 0.0;
+    for (int32_t nz = t.rowptr[i]; nz < t.rowptr[i + 1]; ++nz) {
+      const double uj = u[so + t.col[nz]];
+      G += t.mval[nz] * (uj + io.dt * tet_iion(uj, io)) + ck * (double)kv[nz] * uj;
+    }
+    const double b = bv[so + i];
+    const double F = G - b;
+    r0[so + i] = (TI)(-F);
+    dout[so + i] = (TI)(io.dt * tet_diion(u[so + i], io));
+    n0 = F * F;
+    n1 = G * G;
+    n2 = b * b;
+  }
+  __shared__ double red[kBlock / 64][3];
+  double v[3] = {n0, n1, n2};
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[r] += __shfl_xor(v[r], off, 64);
+  }
+  if (lane == 0) {
+    red[wid][0] = v[0];
+    red[wid][1] = v[1];
+    red[wid][2] = v[2];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int q = 0; q < kBlock / 64; ++q) {
+      s0 += red[q][0];
+      s1 += red[q][1];
+      s2 += red[q][2];
+    }
+    double* p = part + ((int64_t)sb * gridDim.x + blockIdx.x) * 3;
+    p[0] = s0;
+    p[1] = s1;
+    p[2] = s2;
+  }
+}
+
+// b = M u_k - dt/2 K u_k + load F (FP64), u = u_k
+template <typename TI>
+__global__ __launch_bounds__(kBlock) void k_tet_rhs(TetDev t, const TI* __restrict__ kval,
+                                                    const double* __restrict__ uk, const double* __restrict__ fload,
+                                                    double load, double ck, double* __restrict__ bout,
+                                                    double* __restrict__ ucopy) {
+  const int sb = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= t.nv) return;
+  const int64_t so = (int64_t)sb * t.nv;
+  const TI* kv = kval + (int64_t)sb * t.nnz;
+  double acc = 0.0;
+  for (int32_t nz = t.rowptr[i]; nz < t.rowptr[i + 1]; ++nz) {
+    const double uj = uk[so + t.col[nz]];
+    acc += (t.mval[nz] - ck * (double)kv[nz]) * uj;
+  }
+  bout[so + i] = acc + load * fload[i];
+  ucopy[so + i] = uk[so + i];
+}
+
+// GMRES preconditioner step: z = v_j inv_eta_j / (m_ii (1 + d_i))
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tet_jacobi(TetDev t, const T* __restrict__ v, const T* __restrict__ d,
+                                                       T* __restrict__ z, const double* __restrict__ inv_eta, int j,
+                                                       int kmax, const int32_t* __restrict__ active) {
+  const int sb = blockIdx.y;
+  if (active[sb] == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= t.nv) return;
+  const T* md = nullptr;
+  if constexpr (sizeof(T) == 4) md = (const T*)t.mdiag32; else md = (const T*)t.mdiag;
+  const int64_t o = (int64_t)sb * t.nv + i;
+  const T s = (T)inv_eta[(int64_t)sb * (kmax + 1) + j];
+  z[o] = v[o] * s / (md[i] * ((T)1 + d[o]));
+}
+
+// Newton update with right preconditioning: u += P^-1 sum_l y_l v_l (y_l carries inv_eta_l)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tet_update(TetDev t, const T* __restrict__ V, size_t vs,
+                                                       const T* __restrict__ d, const double* __restrict__ y, int kmax,
+                                                       const int32_t* __restrict__ inner_k, double* __restrict__ u,
+                                                       const int32_t* __restrict__ active) {
+  const int sb = blockIdx.y;
+  if (active[sb] == 0) return;
+  __shared__ double c[kMaxInner];
+  const int k = inner_k[sb];
+  for (int q = threadIdx.x; q < k; q += kBlock) c[q] = y[(int64_t)sb * kmax + q];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= t.nv) return;
+  const int64_t o = (int64_t)sb * t.nv + i;
+  double acc = 0.0;
+  for (int l = 0; l < k; ++l) acc += c[l] * (double)V[l * vs + o];
+  const T sv = (T)acc;
+  const T* md = nullptr;
+  if constexpr (sizeof(T) == 4) md = (const T*)t.mdiag32; else md = (const T*)t.mdiag;
+  u[o] += (double)(sv / (md[i] * ((T)1 + d[o])));
+}
+
+}  // namespace
+
+void launch_tet_assemble(const TetDev& t, const void* theta, void* kval, int32_t B, double sigma_t, double dsig,
+                         bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)cdiv(t.nnz, kBlock), B);
+  if (mixed)
+    hipLaunchKernelGGL((k_tet_assemble<float>), grid, dim3(kBlock), 0, s, t, (const float*)theta, (float*)kval,
+                       sigma_t, dsig);
+  else
+    hipLaunchKernelGGL((k_tet_assemble<double>), grid, dim3(kBlock), 0, s, t, (const double*)theta, (double*)kval,
+                       sigma_t, dsig);
+}
+
+void launch_tet_apply(const TetDev& t, const void* kval, const void* x, const void* d, void* y, double ck, int32_t B,
+                      const int32_t* active, bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)cdiv(t.nv, kBlock), B);
+  if (mixed)
+    hipLaunchKernelGGL((k_tet_apply<float>), grid, dim3(kBlock), 0, s, t, (const float*)kval, (const float*)x,
+                       (const float*)d, (float*)y, (float)ck, active);
+  else
+    hipLaunchKernelGGL((k_tet_apply<double>), grid, dim3(kBlock), 0, s, t, (const double*)kval, (const double*)x,
+                       (const double*)d, (double*)y, ck, active);
+}
+
+void launch_tet_residual(const TetDev& t, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)cdiv(t.nv, kBlock), B);  // = w.nres blocks per sample
+  if (mixed)
+    hipLaunchKernelGGL((k_tet_residual<float>), grid, dim3(kBlock), 0, s, t, io, (const float*)w.coef, w.u, w.b,
+                       (float*)w.V, (float*)w.d, w.part, w.newton_active);
+  else
+    hipLaunchKernelGGL((k_tet_residual<double>), grid, dim3(kBlock), 0, s, t, io, (const double*)w.coef, w.u, w.b,
+                       (double*)w.V, (double*)w.d, w.part, w.newton_active);
+}
+
+void launch_tet_rhs(const TetDev& t, const Work& w, const double* fload, double load, double dt, int32_t B,
+                    bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)cdiv(t.nv, kBlock), B);
+  if (mixed)
+    hipLaunchKernelGGL((k_tet_rhs<float>), grid, dim3(kBlock), 0, s, t, (const float*)w.coef, w.uk, fload, load,
+                       0.5 * dt, w.b, w.u);
+  else
+    hipLaunchKernelGGL((k_tet_rhs<double>), grid, dim3(kBlock), 0, s, t, (const double*)w.coef, w.uk, fload, load,
+                       0.5 * dt, w.b, w.u);
+}
+
+void launch_tet_jacobi_basis(const TetDev& t, const Work& w, int j, int32_t B, bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)cdiv(t.nv, kBlock), B);
+  const size_t vs = (size_t)t.nv * B;
+  if (mixed)
+    hipLaunchKernelGGL((k_tet_jacobi<float>), grid, dim3(kBlock), 0, s, t, (const float*)w.V + j * vs,
+                       (const float*)w.d, (float*)w.z, w.inv_eta, j, w.kmax, w.inner_active);
+  else
+    hipLaunchKernelGGL((k_tet_jacobi<double>), grid, dim3(kBlock), 0, s, t, (const double*)w.V + j * vs,
+                       (const double*)w.d, (double*)w.z, w.inv_eta, j, w.kmax, w.inner_active);
+}
+
+void launch_tet_update(const TetDev& t, const Work& w, int32_t B, bool mixed, hipStream_t s) {
+  const dim3 grid((unsigned)cdiv(t.nv, kBlock), B);
+  const size_t vs = (size_t)t.nv * B;
+  if (mixed)
+    hipLaunchKernelGGL((k_tet_update<float>), grid, dim3(kBlock), 0, s, t, (const float*)w.V, vs, (const float*)w.d,
+                       w.y, w.kmax, w.inner_k, w.u, w.newton_active);
+  else
+    hipLaunchKernelGGL((k_tet_update<double>), grid, dim3(kBlock), 0, s, t, (const double*)w.V, vs,
+                       (const double*)w.d, w.y, w.kmax, w.inner_k, w.u, w.newton_active);
+}
+
+}  // namespace mlq

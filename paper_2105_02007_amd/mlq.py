@@ -19,6 +19,7 @@ MLQ_OK, MLQ_EINVAL, MLQ_EHIP, MLQ_ENOCONV, MLQ_ESIZE, MLQ_ESTATE = 0, -1, -2, -3
 MLQ_FP64, MLQ_MIXED = 0, 1
 MLQ_QOI_MEAN_U_FINAL, MLQ_QOI_MEAN_ACT_TIME = 0, 1
 MLQ_EST_MC, MLQ_EST_MLMC, MLQ_EST_MLQMC, MLQ_EST_COMBINATION = 0, 1, 2, 3
+MLQ_MESH_Q1_BOX, MLQ_MESH_P1_TET = 0, 1
 
 EXPORTED = [
     "mlq_level_bytes", "mlq_create_level", "mlq_destroy_level", "mlq_level_sizes", "mlq_workspace_bytes",
@@ -50,6 +51,10 @@ class LevelDesc(C.Structure):
         ("newton_tol", C.c_double), ("inner_tol", C.c_double),
         ("max_newton", C.c_int32), ("max_inner", C.c_int32), ("max_batch", C.c_int32),
         ("arrays_on_device", C.c_int32),
+        ("n_vert", C.c_int64), ("n_tet", C.c_int64),
+        ("xyz", C.POINTER(C.c_double)), ("tets", C.POINTER(C.c_int32)),
+        ("e_circ", C.POINTER(C.c_double)), ("e_long", C.POINTER(C.c_double)),
+        ("stim_center", C.c_double * 3), ("stim_radius", C.c_double),
     ]
 
 
@@ -132,17 +137,35 @@ def make_desc(level: dict, phys: dict, *, n_modes=0, phi=None, sqrt_lambda=None,
     """Fills an mlq_level_desc from a workload level and physics dict.  Returns (desc, keepalive)."""
     d = LevelDesc()
     dim = level["dim"]
-    d.dim, d.mesh_kind = dim, 0
-    for a in range(3):
-        d.n[a] = level["n"][a] if a < dim else 1
-        d.lo[a] = level["lo"][a] if a < dim else 0.0
-        d.hi[a] = level["hi"][a] if a < dim else 1.0
-        d.stim_lo[a] = phys["stim_lo"][a] if a < dim else 0.0
-        d.stim_hi[a] = phys["stim_hi"][a] if a < dim else 1.0
+    keep = []
+    if level.get("kind") == "tet":
+        # P1 tetrahedra: level["mesh"] holds xyz (V, 3), tets (T, 4), e_circ / e_long (T, 3)
+        m = level["mesh"]
+        xyz = np.ascontiguousarray(m["xyz"], dtype=np.float64)
+        tets = np.ascontiguousarray(m["tets"], dtype=np.int32)
+        ec = np.ascontiguousarray(m["e_circ"], dtype=np.float64)
+        el = np.ascontiguousarray(m["e_long"], dtype=np.float64)
+        keep += [xyz, tets, ec, el]
+        d.dim, d.mesh_kind = 3, MLQ_MESH_P1_TET
+        d.n_vert, d.n_tet = xyz.shape[0], tets.shape[0]
+        d.xyz = xyz.ctypes.data_as(C.POINTER(C.c_double))
+        d.tets = tets.ctypes.data_as(C.POINTER(C.c_int32))
+        d.e_circ = ec.ctypes.data_as(C.POINTER(C.c_double))
+        d.e_long = el.ctypes.data_as(C.POINTER(C.c_double))
+        for a in range(3):
+            d.stim_center[a] = float(phys["stim_center"][a])
+        d.stim_radius = float(phys["stim_radius"])
+    else:
+        d.dim, d.mesh_kind = dim, MLQ_MESH_Q1_BOX
+        for a in range(3):
+            d.n[a] = level["n"][a] if a < dim else 1
+            d.lo[a] = level["lo"][a] if a < dim else 0.0
+            d.hi[a] = level["hi"][a] if a < dim else 1.0
+            d.stim_lo[a] = phys["stim_lo"][a] if a < dim else 0.0
+            d.stim_hi[a] = phys["stim_hi"][a] if a < dim else 1.0
     d.n_steps, d.t_end = int(level["n_steps"]), float(phys["t_end"])
     for k in ("alpha", "u_rest", "u_th", "u_peak", "sigma_l", "sigma_t", "stim_t_on", "stim_t_off", "stim_amp"):
         setattr(d, k, float(phys[k]))
-    keep = []
     d.n_modes = int(n_modes)
     on_dev = n_modes > 0 and hasattr(phi, "data_ptr")
     d.arrays_on_device = 1 if on_dev else 0

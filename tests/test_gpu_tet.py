@@ -1,0 +1,110 @@
+"""GPU parity of the P1 tetrahedral path (seeded non-nested shells) against the oracle.
+
+Bars as for the boxes: FP64 apply within 1e-13 of the row scale and solves
+within 1e-10 relative per node; mixed apply within 2e-6, QoI statistics 1e-6.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads import tetshell
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_02007_amd import mlq
+    return torch, mlq
+
+
+def _shell(cells, seed=5):
+    xyz, tets, ec, el, th0 = tetshell.shell_mesh(cells, seed)
+    return dict(xyz=xyz, tets=tets, e_circ=ec, e_long=el), th0
+
+
+def _phys(radius_frac=0.3):
+    ph = W.physics(3)
+    c, r = tetshell.stimulus_ball(radius_frac)
+    ph.update(stim_center=c.tolist(), stim_radius=float(r))
+    return ph
+
+
+@pytest.mark.parametrize("cells,mixed", [((2, 6, 12), False), ((3, 10, 20), False), ((2, 6, 12), True),
+                                         ((3, 10, 20), True)])
+def test_tet_apply_matches_assembled_jacobian(env, cells, mixed):
+    torch, mlq = env
+    from oracle.tetfem import TetMesh
+    mesh_d, _ = _shell(cells)
+    ph = _phys()
+    steps = 16
+    lvl = dict(kind="tet", dim=3, n_steps=steps, mesh=mesh_d)
+    B = 3
+    desc, keep = mlq.make_desc(lvl, ph, prec=mlq.MLQ_MIXED if mixed else mlq.MLQ_FP64, max_batch=B)
+    lv = mlq.Level(desc, keep)
+    mesh = TetMesh(mesh_d["xyz"], mesh_d["tets"])
+    dt = ph["t_end"] / steps
+    theta = W.random_angles(3, B, mesh.n_elems)
+    x = W.random_nodal(4, B, mesh.n_nodes)
+    dv = W.random_nodal(5, B, mesh.n_nodes, -0.05, 0.14)
+    tdt = torch.float32 if mixed else torch.float64
+    th_d = torch.as_tensor(theta, dtype=tdt, device="cuda")
+    x_d = torch.as_tensor(x, dtype=tdt, device="cuda")
+    d_d = torch.as_tensor(dv, dtype=tdt, device="cuda")
+    y = lv.apply(th_d, x_d, d_d).double().cpu().numpy()
+    for b in range(B):
+        tb, xb, db = (a[b].double().cpu().numpy() for a in (th_d, x_d, d_d))
+        G = mesh.conductivity(tb, mesh_d["e_circ"], mesh_d["e_long"], ph["sigma_l"], ph["sigma_t"])
+        M, K = mesh.assemble(G)
+        ref = M @ ((1.0 + db) * xb) + 0.5 * dt * (K @ xb)
+        scale = abs(M) @ np.abs((1.0 + db) * xb) + 0.5 * dt * (abs(K) @ np.abs(xb))
+        tol = (2e-6 if mixed else 1e-13) * scale.max()
+        assert np.abs(y[b] - ref).max() <= tol, (b, np.abs(y[b] - ref).max() / scale.max())
+
+
+def _tet_solve_pair(env, cells, steps, B, prec, stop=None):
+    torch, mlq = env
+    from oracle import stepper
+    from oracle.tetfem import TetMesh
+    mesh_d, th0 = _shell(cells)
+    ph = _phys()
+    tol = W.NEWTON_TOL[prec]
+    lvl = dict(kind="tet", dim=3, n_steps=steps, mesh=mesh_d)
+    desc, keep = mlq.make_desc(lvl, ph, prec=prec, qoi=W.QOI_MEAN_ACT_TIME, newton_tol=tol,
+                               inner_tol=W.INNER_TOL[prec], max_batch=B)
+    lv = mlq.Level(desc, keep)
+    mesh = TetMesh(mesh_d["xyz"], mesh_d["tets"])
+    theta = th0[None, :] + 0.3 * W.random_nodal(9, B, mesh.n_elems)
+    th_d = torch.as_tensor(theta, device="cuda").to(lv.theta_dtype)
+    out = lv.solve(th_d, n_steps=stop, want_state=True)
+    torch.cuda.synchronize()
+    refs = []
+    for b in range(B):
+        tb = th_d[b].double().cpu().numpy()
+        G = mesh.conductivity(tb, mesh_d["e_circ"], mesh_d["e_long"], ph["sigma_l"], ph["sigma_t"])
+        refs.append(stepper.solve(mesh, G, ph, steps, tol=1e-13, stop_after=stop))
+    return out, refs
+
+
+def test_tet_solve_fp64_matches_oracle(env):
+    out, refs = _tet_solve_pair(env, (2, 6, 12), 32, 3, W.PREC_FP64)
+    assert int(out["status"].abs().sum()) == 0
+    q = out["qoi"].cpu().numpy()
+    u = out["u"].cpu().numpy()
+    for b, r in enumerate(refs):
+        assert np.abs(u[b] - r["u"]).max() <= 1e-10 * np.abs(r["u"]).max()
+        assert abs(q[b] - r["mean_act"]) <= 1e-10 * abs(r["mean_act"])
+    assert np.abs(refs[0]["u"]).max() > 1.0  # the stimulus moved the solution
+
+
+def test_tet_solve_mixed_statistics(env):
+    out, refs = _tet_solve_pair(env, (3, 10, 20), 16, 4, W.PREC_MIXED)
+    assert int(out["status"].abs().sum()) == 0
+    q = out["qoi"].cpu().numpy()
+    ref = np.array([r["mean_act"] for r in refs])
+    assert abs(q.mean() - ref.mean()) <= 1e-6 * abs(ref.mean())
+    u = out["u"].cpu().numpy()
+    assert max(np.abs(u[b] - r["u"]).max() / np.abs(r["u"]).max() for b, r in enumerate(refs)) < 1e-5
