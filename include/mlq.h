@@ -210,7 +210,7 @@ mlq_status mlq_estimate(int32_t kind, int32_t n_levels, int32_t n_shifts, const 
 
 /* ---- KL basis set-up (Section 2.3; element-midpoint transfer of Section 4) ----
  * Covariance C(x, x') = std_dev^2 exp(-|x - x'|_2 / corr_len) on the nodes of a
- * uniform Q1 box (normally the finest level).  eq. (algEig) is reduced by a
+ * uniform Q1 box or of a tetrahedral mesh (normally the finest level).  eq. (algEig) is reduced by a
  * pivoted Cholesky factor C ~ L L^T (largest remaining diagonal first, lowest
  * index on ties; stops at rank max_rank, or once the rank is >= n_modes and
  * trace(C - L L^T) <= eps trace(C)) to eq. (redEig), L^T M L v~ = lambda v~. */
@@ -223,6 +223,12 @@ typedef struct {
   int32_t n_modes;      /* M <= 1024 */
   int32_t max_rank;     /* n_modes <= max_rank <= min(4096, nodes) */
   double eps;           /* relative trace tolerance of the pivoted Cholesky */
+  /* mesh_kind = MLQ_MESH_P1_TET: the KL lives on the vertices of a tetrahedral
+   * mesh (host arrays, dim = 3, n/lo/hi ignored) with its P1 mass matrix */
+  int32_t mesh_kind;
+  int64_t n_vert, n_tet;
+  const double* xyz;    /* n_vert x 3 */
+  const int32_t* tets;  /* n_tet x 4, positively oriented */
 } mlq_kl_desc;
 
 /* Device workspace bytes of mlq_kl_modes (dominated by two n x max_rank FP64 arrays). */
@@ -240,6 +246,20 @@ mlq_status mlq_kl_modes(const mlq_kl_desc* kd, void* ws_dev, size_t ws_bytes, do
  * (level_n nodes per axis on [level_lo, level_hi]).  Enqueues only. */
 mlq_status mlq_kl_transfer(const mlq_kl_desc* kd, const double* psi_dev, const int64_t* level_n,
                            const double* level_lo, const double* level_hi, double* phi_dev, void* hip_stream);
+
+/* Non-nested transfer to a tetrahedral level (Section 4, with the reading for
+ * non-nested meshes): phi_dev (n_tet x M row-major FP64, device) = the P1
+ * interpolant of the KL modes (kd a tetrahedral KL mesh) at the centroids of the
+ * level's tetrahedra (host arrays xyz, tets).  Each centroid takes the KL
+ * tetrahedron with the largest smallest barycentric coordinate (lowest index on
+ * ties within 1e-12; a point outside the KL mesh takes the best nearby one) and
+ * its barycentric weights clipped at 0 and renormalised.  ws_dev (>=
+ * mlq_kl_transfer_tet_bytes) holds the located weights; enqueues the
+ * interpolation and returns after it finished. */
+mlq_status mlq_kl_transfer_tet_bytes(int64_t n_tet, size_t* ws_bytes);
+mlq_status mlq_kl_transfer_tet(const mlq_kl_desc* kd, const double* psi_dev, int64_t n_vert, const double* xyz,
+                               int64_t n_tet, const int32_t* tets, void* ws_dev, size_t ws_bytes,
+                               double* phi_dev, void* hip_stream);
 
 /* ---- kernel timing (HIP events on the solve's stream) ----
  * Kernel classes of mlq_solve_batch; `units` counts node-samples processed. */

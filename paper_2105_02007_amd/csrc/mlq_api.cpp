@@ -931,4 +931,28 @@ mlq_status mlq_kl_transfer(const mlq_kl_desc* kd, const double* psi_dev, const i
   return MLQ_OK;
 }
 
+mlq_status mlq_kl_transfer_tet_bytes(int64_t n_tet, size_t* ws_bytes) {
+  if (ws_bytes == nullptr || n_tet < 1) return fail(MLQ_EINVAL, "invalid argument");
+  *ws_bytes = kl_transfer_tet_bytes(n_tet);
+  return MLQ_OK;
+}
+
+mlq_status mlq_kl_transfer_tet(const mlq_kl_desc* kd, const double* psi_dev, int64_t n_vert, const double* xyz,
+                               int64_t n_tet, const int32_t* tets, void* ws_dev, size_t ws_bytes, double* phi_dev,
+                               void* hip_stream) {
+  if (kl_validate(kd) != MLQ_OK || kd->mesh_kind != MLQ_MESH_P1_TET)
+    return fail(MLQ_EINVAL, "invalid tetrahedral KL descriptor");
+  if (psi_dev == nullptr || xyz == nullptr || tets == nullptr || ws_dev == nullptr || phi_dev == nullptr)
+    return fail(MLQ_EINVAL, "NULL argument");
+  if (n_vert < 4 || n_tet < 1) return fail(MLQ_EINVAL, "invalid level mesh");
+  for (int64_t i = 0; i < 4 * n_tet; ++i)
+    if (tets[i] < 0 || tets[i] >= n_vert) return fail(MLQ_EINVAL, "level vertex index out of range");
+  if (ws_bytes < kl_transfer_tet_bytes(n_tet)) return fail(MLQ_ESIZE, "transfer workspace too small");
+  if (((uintptr_t)ws_dev & 255) != 0) return fail(MLQ_EINVAL, "workspace must be 256-byte aligned");
+  std::string err;
+  mlq_status st = kl_transfer_tet(kd, psi_dev, n_vert, xyz, n_tet, tets, ws_dev, phi_dev, (hipStream_t)hip_stream, err);
+  if (st != MLQ_OK) return fail(st, "%s", err.c_str());
+  return MLQ_OK;
+}
+
 }  // extern "C"

@@ -146,6 +146,9 @@ mlq_status kl_modes(const mlq_kl_desc* kd, void* ws, double* lambda_host, double
                     double* resid_out, hipStream_t s, std::string& err);
 mlq_status kl_transfer(const mlq_kl_desc* kd, const double* psi_dev, const int64_t* level_n, const double* level_lo,
                        const double* level_hi, double* phi_dev, hipStream_t s);
+size_t kl_transfer_tet_bytes(int64_t n_tet);
+mlq_status kl_transfer_tet(const mlq_kl_desc* kd, const double* psi_dev, int64_t nv, const double* xyz, int64_t nt,
+                           const int32_t* tets, void* ws, double* phi_dev, hipStream_t s, std::string& err);
 void launch_minv_basis(const Geo& g, const Work& w, const void* tri, int nmax, int j, int32_t B, bool mixed,
                        hipStream_t s);
 void launch_apply_pk(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s);

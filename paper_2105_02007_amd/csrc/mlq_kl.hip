@@ -31,9 +31,16 @@ struct Box {
   int64_t n[3];
   double lo[3], h[3];
   int64_t nn;
+  const double* xyz;  // tetrahedral KL mesh: vertex coordinates (device), else nullptr
 };
 
 __host__ __device__ inline void box_xyz(const Box& b, int64_t i, double x[3]) {
+  if (b.xyz != nullptr) {
+    x[0] = b.xyz[3 * i];
+    x[1] = b.xyz[3 * i + 1];
+    x[2] = b.xyz[3 * i + 2];
+    return;
+  }
   const int64_t ix = i % b.n[0];
   const int64_t r = i / b.n[0];
   const int64_t iy = r % b.n[1];
@@ -179,6 +186,33 @@ __global__ __launch_bounds__(kT) void k_mass_cols(Box b, const double* __restric
     }
   }
   Y[c * b.nn + i] = acc;
+}
+
+// P1 mass (CSR) applied to every column: grid (blocks, columns).
+__global__ __launch_bounds__(kT) void k_mass_csr_cols(int64_t n, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ col, const double* __restrict__ mval,
+                                                      const double* __restrict__ X, double* __restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  const int64_t c = blockIdx.y;
+  const double* x = X + c * n;
+  double acc = 0.0;
+  for (int32_t nz = rowptr[i]; nz < rowptr[i + 1]; ++nz) acc += mval[nz] * x[col[nz]];
+  Y[c * n + i] = acc;
+}
+
+// phi[p][k] = sum_a w[p][a] psi[k][v[p][a]]  (psi column-major n x M, phi row-major P x M)
+__global__ __launch_bounds__(kT) void k_transfer_bary(const double* __restrict__ psi, int64_t n, int M,
+                                                      const int32_t* __restrict__ v, const double* __restrict__ w,
+                                                      int64_t P, double* __restrict__ phi) {
+  const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (t >= P * M) return;
+  const int64_t p = t / M;
+  const int k = (int)(t % M);
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) acc += w[4 * p + a] * psi[(int64_t)k * n + v[4 * p + a]];
+  phi[t] = acc;
 }
 
 // Split-K Gram matrix: part[chunk][a][c] = sum_{rows in chunk} A[:, a] B[:, c] (A, B column-major, n rows).
@@ -345,6 +379,11 @@ void jacobi_eig(std::vector<double>& A, std::vector<double>& V, int R) {
 
 Box make_box(const mlq_kl_desc* kd) {
   Box b{};
+  if (kd->mesh_kind == MLQ_MESH_P1_TET) {
+    b.dim = 3;
+    b.nn = kd->n_vert;
+    return b;
+  }
   b.dim = kd->dim;
   b.nn = 1;
   for (int a = 0; a < 3; ++a) {
@@ -361,10 +400,26 @@ inline size_t al(size_t v) { return (v + 255) & ~size_t(255); }
 struct KlWork {
   double *L, *ML, *d, *pv, *ps, *stat, *part, *S, *W;
   int64_t *pi, *idx;
+  double *xyz, *mval;   // tetrahedral KL mesh
+  int32_t *rowptr, *col;
   size_t bytes;
 };
 
-KlWork kl_carve(void* base, int64_t n, int R, int M) {
+// The P1 mass matrix of a tetrahedral KL mesh (CSR on the host).
+std::string kl_tet_mass(const mlq_kl_desc* kd, TetHost& h, bool values) {
+  mlq_level_desc d{};
+  d.dim = 3;
+  d.mesh_kind = MLQ_MESH_P1_TET;
+  d.n_vert = kd->n_vert;
+  d.n_tet = kd->n_tet;
+  d.xyz = kd->xyz;
+  d.tets = kd->tets;
+  std::vector<double> frame(values ? 3 * (size_t)kd->n_tet : 3, 0.0);  // unused by the mass
+  d.e_circ = d.e_long = frame.data();
+  return tet_build(&d, h, values);
+}
+
+KlWork kl_carve(void* base, int64_t n, int R, int M, int64_t nnz = -1) {
   KlWork w{};
   char* p = (char*)base;
   size_t o = 0;
@@ -386,6 +441,12 @@ KlWork kl_carve(void* base, int64_t n, int R, int M) {
   w.part = (double*)take(sizeof(double) * nchunk * R * R);
   w.S = (double*)take(sizeof(double) * R * R);
   w.W = (double*)take(sizeof(double) * R * M);
+  if (nnz >= 0) {
+    w.xyz = (double*)take(sizeof(double) * 3 * n);
+    w.rowptr = (int32_t*)take(sizeof(int32_t) * (n + 1));
+    w.col = (int32_t*)take(sizeof(int32_t) * nnz);
+    w.mval = (double*)take(sizeof(double) * nnz);
+  }
   w.bytes = o;
   return w;
 }
@@ -394,11 +455,19 @@ KlWork kl_carve(void* base, int64_t n, int R, int M) {
 
 mlq_status kl_validate(const mlq_kl_desc* kd) {
   if (kd == nullptr) return MLQ_EINVAL;
-  if (kd->dim != 2 && kd->dim != 3) return MLQ_EINVAL;
   int64_t n = 1;
-  for (int a = 0; a < kd->dim; ++a) {
-    if (kd->n[a] < 2 || !(kd->hi[a] > kd->lo[a])) return MLQ_EINVAL;
-    n *= kd->n[a];
+  if (kd->mesh_kind == MLQ_MESH_P1_TET) {
+    if (kd->n_vert < 4 || kd->n_vert > (int64_t(1) << 27) || kd->n_tet < 1 || kd->n_tet >= (int64_t(1) << 27) ||
+        kd->xyz == nullptr || kd->tets == nullptr)
+      return MLQ_EINVAL;
+    n = kd->n_vert;
+  } else {
+    if (kd->mesh_kind != MLQ_MESH_Q1_BOX) return MLQ_EINVAL;
+    if (kd->dim != 2 && kd->dim != 3) return MLQ_EINVAL;
+    for (int a = 0; a < kd->dim; ++a) {
+      if (kd->n[a] < 2 || !(kd->hi[a] > kd->lo[a])) return MLQ_EINVAL;
+      n *= kd->n[a];
+    }
   }
   if (kd->n_modes < 1 || kd->n_modes > 1024) return MLQ_EINVAL;
   if (kd->max_rank < kd->n_modes || kd->max_rank > 4096 || kd->max_rank > n) return MLQ_EINVAL;
@@ -408,16 +477,39 @@ mlq_status kl_validate(const mlq_kl_desc* kd) {
 
 size_t kl_workspace_bytes(const mlq_kl_desc* kd) {
   const Box b = make_box(kd);
+  if (kd->mesh_kind == MLQ_MESH_P1_TET) {
+    TetHost h;
+    if (!kl_tet_mass(kd, h, false).empty()) return 0;
+    return kl_carve(nullptr, b.nn, kd->max_rank, kd->n_modes, h.nnz).bytes;
+  }
   return kl_carve(nullptr, b.nn, kd->max_rank, kd->n_modes).bytes;
 }
 
 // Returns MLQ_OK or MLQ_EHIP; error text in err.
 mlq_status kl_modes(const mlq_kl_desc* kd, void* ws, double* lambda_host, double* psi_dev, int32_t* rank_out,
                     double* resid_out, hipStream_t s, std::string& err) {
-  const Box b = make_box(kd);
+  Box b = make_box(kd);
   const int64_t n = b.nn;
   const int Rmax = kd->max_rank, M = kd->n_modes;
-  KlWork w = kl_carve(ws, n, Rmax, M);
+  const bool tet = kd->mesh_kind == MLQ_MESH_P1_TET;
+  TetHost th;
+  if (tet) {
+    err = kl_tet_mass(kd, th, true);
+    if (!err.empty()) return MLQ_EINVAL;
+  }
+  KlWork w = kl_carve(ws, n, Rmax, M, tet ? th.nnz : -1);
+  if (tet) {
+    hipError_t e = hipMemcpyAsync(w.xyz, kd->xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(w.rowptr, th.rowptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(w.col, th.col.data(), sizeof(int32_t) * th.nnz, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(w.mval, th.mval.data(), sizeof(double) * th.nnz, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      err = std::string("KL mesh upload: ") + hipGetErrorString(e);
+      return MLQ_EHIP;
+    }
+    b.xyz = w.xyz;
+  }
   const int64_t nb = cdiv(n, kT * 16);
   const double s2 = kd->std_dev * kd->std_dev;
   const double tr0 = s2 * (double)n;
@@ -457,7 +549,11 @@ mlq_status kl_modes(const mlq_kl_desc* kd, void* ws, double* lambda_host, double
   }
   const int R = rank;
   // reduced eigenproblem eq. (redEig): S = L^T M L
-  hipLaunchKernelGGL(k_mass_cols, dim3((unsigned)cdiv(n, kT), R), dim3(kT), 0, s, b, w.L, w.ML);
+  if (tet)
+    hipLaunchKernelGGL(k_mass_csr_cols, dim3((unsigned)cdiv(n, kT), R), dim3(kT), 0, s, n, w.rowptr, w.col, w.mval,
+                       w.L, w.ML);
+  else
+    hipLaunchKernelGGL(k_mass_cols, dim3((unsigned)cdiv(n, kT), R), dim3(kT), 0, s, b, w.L, w.ML);
   const int nchunk = (int)cdiv(n, kGChunk);
   hipLaunchKernelGGL(k_gram, dim3((unsigned)cdiv(R, kGT), (unsigned)cdiv(R, kGT), nchunk), dim3(kGT * kGT), 0, s,
                      w.L, w.ML, n, R, w.part);
@@ -513,6 +609,155 @@ mlq_status kl_transfer(const mlq_kl_desc* kd, const double* psi_dev, const int64
   const int M = kd->n_modes;
   hipLaunchKernelGGL(k_transfer, dim3((unsigned)cdiv(P * M, kT)), dim3(kT), 0, s, kb, lb, psi_dev, M, phi_dev, P);
   return hipGetLastError() == hipSuccess ? MLQ_OK : MLQ_EHIP;
+}
+
+}  // namespace mlq
+
+namespace mlq {
+
+size_t kl_transfer_tet_bytes(int64_t P) { return al(sizeof(int32_t) * 4 * P) + al(sizeof(double) * 4 * P); }
+
+// Non-nested transfer: locate the centroids of the level's tetrahedra in the KL
+// mesh (uniform bucket grid over the KL mesh; the tetrahedron with the largest
+// smallest barycentric coordinate, lowest index on ties within 1e-12; the search
+// widens to the neighbouring cells for a point no candidate contains), then
+// interpolate the modes on the device.
+mlq_status kl_transfer_tet(const mlq_kl_desc* kd, const double* psi_dev, int64_t nv, const double* xyz, int64_t nt,
+                           const int32_t* tets, void* ws, double* phi_dev, hipStream_t s, std::string& err) {
+  TetHost h;
+  err = kl_tet_mass(kd, h, true);  // gradients of the KL tetrahedra (geo)
+  if (!err.empty()) return MLQ_EINVAL;
+  const int64_t kn = kd->n_vert, kt = kd->n_tet;
+  const double* kx = kd->xyz;
+  const int32_t* kT4 = kd->tets;
+  // bucket grid
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t v = 0; v < kn; ++v)
+    for (int m = 0; m < 3; ++m) {
+      lo[m] = std::min(lo[m], kx[3 * v + m]);
+      hi[m] = std::max(hi[m], kx[3 * v + m]);
+    }
+  const double cell = 2.0 * std::cbrt(h.vol / (double)kt);
+  int64_t dims[3];
+  for (int m = 0; m < 3; ++m) dims[m] = std::max<int64_t>(1, (int64_t)std::ceil((hi[m] - lo[m]) / cell));
+  while (dims[0] * dims[1] * dims[2] > 8 * kt + 64)
+    for (int m = 0; m < 3; ++m) dims[m] = std::max<int64_t>(1, dims[m] / 2);
+  const double cw[3] = {(hi[0] - lo[0]) / dims[0] + 1e-300, (hi[1] - lo[1]) / dims[1] + 1e-300,
+                        (hi[2] - lo[2]) / dims[2] + 1e-300};
+  auto cidx = [&](const double* x, int m) {
+    const int64_t c = (int64_t)std::floor((x[m] - lo[m]) / cw[m]);
+    return std::min(std::max<int64_t>(c, 0), dims[m] - 1);
+  };
+  const int64_t ncell = dims[0] * dims[1] * dims[2];
+  std::vector<int64_t> cptr(ncell + 1, 0);
+  std::vector<int32_t> clist;
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int64_t> fill;
+    if (pass == 1) {
+      for (int64_t c = 0; c < ncell; ++c) cptr[c + 1] += cptr[c];
+      clist.assign(cptr[ncell], 0);
+      fill.assign(cptr.begin(), cptr.end() - 1);
+    }
+    for (int64_t e = 0; e < kt; ++e) {
+      double blo[3] = {1e300, 1e300, 1e300}, bhi[3] = {-1e300, -1e300, -1e300};
+      for (int a = 0; a < 4; ++a)
+        for (int m = 0; m < 3; ++m) {
+          blo[m] = std::min(blo[m], kx[3 * (int64_t)kT4[4 * e + a] + m]);
+          bhi[m] = std::max(bhi[m], kx[3 * (int64_t)kT4[4 * e + a] + m]);
+        }
+      int64_t c0[3], c1[3];
+      for (int m = 0; m < 3; ++m) {
+        c0[m] = cidx(blo, m);
+        c1[m] = cidx(bhi, m);
+      }
+      for (int64_t z = c0[2]; z <= c1[2]; ++z)
+        for (int64_t y = c0[1]; y <= c1[1]; ++y)
+          for (int64_t x = c0[0]; x <= c1[0]; ++x) {
+            const int64_t c = x + dims[0] * (y + dims[1] * z);
+            if (pass == 0)
+              cptr[c + 1]++;
+            else
+              clist[fill[c]++] = (int32_t)e;
+          }
+    }
+  }
+  auto bary = [&](int64_t e, const double* x, double lam[4]) {
+    const double* G = h.geo.data() + e * kTetGeo;
+    const double* p0 = kx + 3 * (int64_t)kT4[4 * e];
+    const double d0 = x[0] - p0[0], d1 = x[1] - p0[1], d2 = x[2] - p0[2];
+    double s1 = 0.0;
+    for (int a = 1; a < 4; ++a) {
+      lam[a] = G[3 * a] * d0 + G[3 * a + 1] * d1 + G[3 * a + 2] * d2;
+      s1 += lam[a];
+    }
+    lam[0] = 1.0 - s1;
+  };
+  auto score = [&](int64_t e, const double* x) {
+    double lam[4];
+    bary(e, x, lam);
+    return std::min(std::min(lam[0], lam[1]), std::min(lam[2], lam[3]));
+  };
+  std::vector<int32_t> vid((size_t)4 * nt);
+  std::vector<double> wts((size_t)4 * nt);
+  std::vector<int32_t> cand;
+  for (int64_t p = 0; p < nt; ++p) {
+    double x[3] = {0, 0, 0};
+    for (int a = 0; a < 4; ++a)
+      for (int m = 0; m < 3; ++m) x[m] += 0.25 * xyz[3 * (int64_t)tets[4 * p + a] + m];
+    int64_t ci[3];
+    for (int m = 0; m < 3; ++m) ci[m] = cidx(x, m);
+    int64_t best_e = -1;
+    for (int ring = 0; best_e < 0 || ring <= 1; ++ring) {
+      cand.clear();
+      for (int64_t z = std::max<int64_t>(0, ci[2] - ring); z <= std::min(dims[2] - 1, ci[2] + ring); ++z)
+        for (int64_t y = std::max<int64_t>(0, ci[1] - ring); y <= std::min(dims[1] - 1, ci[1] + ring); ++y)
+          for (int64_t xx = std::max<int64_t>(0, ci[0] - ring); xx <= std::min(dims[0] - 1, ci[0] + ring); ++xx) {
+            const int64_t c = xx + dims[0] * (y + dims[1] * z);
+            cand.insert(cand.end(), clist.begin() + cptr[c], clist.begin() + cptr[c + 1]);
+          }
+      if (cand.empty()) {
+        if (ring > dims[0] + dims[1] + dims[2]) break;
+        continue;
+      }
+      double best = -1e300;
+      for (int32_t e : cand) best = std::max(best, score(e, x));
+      int64_t pick = -1;
+      for (int32_t e : cand)
+        if (score(e, x) >= best - 1e-12 && (pick < 0 || e < pick)) pick = e;
+      best_e = pick;
+      if (best >= -1e-12) break;  // a containing tetrahedron: the rule is decided locally
+      if (ring >= 1) break;       // outside: the best of the neighbouring cells
+    }
+    if (best_e < 0) {
+      err = "point location failed";
+      return MLQ_EINVAL;
+    }
+    double lam[4], sum = 0.0;
+    bary(best_e, x, lam);
+    for (int a = 0; a < 4; ++a) {
+      lam[a] = std::max(lam[a], 0.0);
+      sum += lam[a];
+    }
+    for (int a = 0; a < 4; ++a) {
+      vid[4 * p + a] = kT4[4 * best_e + a];
+      wts[4 * p + a] = lam[a] / sum;
+    }
+  }
+  int32_t* dv = (int32_t*)ws;
+  double* dw = (double*)((char*)ws + al(sizeof(int32_t) * 4 * nt));
+  hipError_t e = hipMemcpyAsync(dv, vid.data(), sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dw, wts.data(), sizeof(double) * 4 * nt, hipMemcpyHostToDevice, s);
+  const int M = kd->n_modes;
+  if (e == hipSuccess)
+    hipLaunchKernelGGL(k_transfer_bary, dim3((unsigned)cdiv(nt * M, kT)), dim3(kT), 0, s, psi_dev, kn, M, dv, dw, nt,
+                       phi_dev);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host arrays must outlive the copies
+  if (e != hipSuccess) {
+    err = std::string("transfer: ") + hipGetErrorString(e);
+    return MLQ_EHIP;
+  }
+  return MLQ_OK;
 }
 
 }  // namespace mlq

@@ -26,6 +26,7 @@ EXPORTED = [
     "mlq_sample_fields", "mlq_solve_batch", "mlq_solve_batch_ex", "mlq_apply", "mlq_check",
     "mlq_lattice_normals", "mlq_cbc", "mlq_accumulate", "mlq_estimate", "mlq_last_error",
     "mlq_kl_workspace_bytes", "mlq_kl_modes", "mlq_kl_transfer", "mlq_timing_enable", "mlq_timing_read",
+    "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet",
 ]
 KERNEL_CLASSES = ["apply", "residual", "rhs", "precond", "dots", "orth", "small", "update", "qoi"]
 
@@ -63,6 +64,8 @@ class KlDesc(C.Structure):
         ("dim", C.c_int32), ("n", C.c_int64 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
         ("std_dev", C.c_double), ("corr_len", C.c_double),
         ("n_modes", C.c_int32), ("max_rank", C.c_int32), ("eps", C.c_double),
+        ("mesh_kind", C.c_int32), ("n_vert", C.c_int64), ("n_tet", C.c_int64),
+        ("xyz", C.POINTER(C.c_double)), ("tets", C.POINTER(C.c_int32)),
     ]
 
 
@@ -98,6 +101,8 @@ def _load():
         "mlq_kl_workspace_bytes": [C.POINTER(KlDesc), C.POINTER(C.c_size_t)],
         "mlq_kl_modes": [C.POINTER(KlDesc), VP, C.c_size_t, VP, VP, VP, VP, VP],
         "mlq_kl_transfer": [C.POINTER(KlDesc), VP, VP, VP, VP, VP, VP],
+        "mlq_kl_transfer_tet_bytes": [I64, C.POINTER(C.c_size_t)],
+        "mlq_kl_transfer_tet": [C.POINTER(KlDesc), VP, I64, VP, I64, VP, VP, C.c_size_t, VP, VP],
         "mlq_timing_enable": [VP, C.c_uint32],
         "mlq_timing_read": [VP, C.POINTER(Timing), I32],
     }
@@ -338,6 +343,38 @@ def kl_desc(dim, n, lo, hi, std_dev, corr_len, n_modes, max_rank=None, eps=1e-2)
     return d
 
 
+def kl_desc_tet(mesh: dict, std_dev, corr_len, n_modes, max_rank=None, eps=1e-2):
+    """KL descriptor on the vertices of a tetrahedral mesh (mesh["xyz"], mesh["tets"])."""
+    d = KlDesc()
+    xyz = np.ascontiguousarray(mesh["xyz"], dtype=np.float64)
+    tets = np.ascontiguousarray(mesh["tets"], dtype=np.int32)
+    d.dim, d.mesh_kind = 3, MLQ_MESH_P1_TET
+    d.n_vert, d.n_tet = xyz.shape[0], tets.shape[0]
+    d.xyz = xyz.ctypes.data_as(C.POINTER(C.c_double))
+    d.tets = tets.ctypes.data_as(C.POINTER(C.c_int32))
+    d._keep = (xyz, tets)
+    d.std_dev, d.corr_len = float(std_dev), float(corr_len)
+    d.n_modes = int(n_modes)
+    d.max_rank = int(max_rank if max_rank is not None else 2 * n_modes)
+    d.eps = float(eps)
+    return d
+
+
+def kl_transfer_tet(kd: KlDesc, psi, mesh: dict, device="cuda"):
+    """Phi_l (n_tet x M, device FP64) at the centroids of a tetrahedral level (non-nested)."""
+    import torch
+    xyz = np.ascontiguousarray(mesh["xyz"], dtype=np.float64)
+    tets = np.ascontiguousarray(mesh["tets"], dtype=np.int32)
+    P = tets.shape[0]
+    nbytes = C.c_size_t()
+    check(lib.mlq_kl_transfer_tet_bytes(P, C.byref(nbytes)))
+    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+    phi = torch.empty((P, kd.n_modes), dtype=torch.float64, device=device)
+    check(lib.mlq_kl_transfer_tet(C.byref(kd), _ptr(psi), xyz.shape[0], xyz.ctypes.data_as(C.c_void_p), P,
+                                  tets.ctypes.data_as(C.c_void_p), _ptr(ws), nbytes.value, _ptr(phi), _stream()))
+    return phi
+
+
 def kl_modes(kd: KlDesc, device="cuda"):
     """Returns (lambda (M,) numpy, psi (M, n) device tensor [row k = mode k], rank, relative residual)."""
     import torch
@@ -347,6 +384,8 @@ def kl_modes(kd: KlDesc, device="cuda"):
     n = 1
     for a in range(kd.dim):
         n *= kd.n[a]
+    if kd.mesh_kind == MLQ_MESH_P1_TET:
+        n = kd.n_vert
     psi = torch.empty((kd.n_modes, n), dtype=torch.float64, device=device)  # column-major n x M
     lam = np.zeros(kd.n_modes)
     rank, resid = C.c_int32(), C.c_double()

@@ -108,3 +108,38 @@ def test_tet_solve_mixed_statistics(env):
     assert abs(q.mean() - ref.mean()) <= 1e-6 * abs(ref.mean())
     u = out["u"].cpu().numpy()
     assert max(np.abs(u[b] - r["u"]).max() / np.abs(r["u"]).max() for b, r in enumerate(refs)) < 1e-5
+
+
+def test_tet_kl_modes_match_oracle(env):
+    """KL on the vertices of a tetrahedral mesh (full-rank Cholesky) vs the oracle's dense route."""
+    torch, mlq = env
+    from oracle import kl
+    from oracle.tetfem import TetMesh
+    mesh_d, _ = _shell((2, 6, 12))
+    mesh = TetMesh(mesh_d["xyz"], mesh_d["tets"])
+    n_modes = 8
+    kd = mlq.kl_desc_tet(mesh_d, 0.3, 0.5, n_modes, max_rank=mesh.n_nodes, eps=0.0)
+    lam, psi, rank, resid = mlq.kl_modes(kd)
+    M, _ = mesh.assemble(np.zeros((mesh.n_elems, 3, 3)))
+    lam_ref, v_ref = kl.kl_dense(mesh.nodes, M, 0.3, 0.5, n_modes)
+    assert np.allclose(lam, lam_ref, rtol=1e-9, atol=0)
+    psi_ref = v_ref / np.sqrt(lam_ref)
+    p = psi.cpu().numpy().T  # n x M
+    assert np.abs(p - psi_ref).max() <= 1e-8 * np.abs(psi_ref).max()
+
+
+def test_tet_nonnested_transfer_matches_oracle(env):
+    """Centroids of a coarse shell located in a finer, non-nested one: P1 interpolation of the
+    same modes (fed to both sides) agrees with the oracle's brute-force location."""
+    torch, mlq = env
+    from oracle.tetfem import TetMesh
+    fine_d, _ = _shell((3, 10, 20), seed=7)
+    coarse_d, _ = _shell((2, 6, 12), seed=5)
+    fine = TetMesh(fine_d["xyz"], fine_d["tets"])
+    coarse = TetMesh(coarse_d["xyz"], coarse_d["tets"])
+    n_modes = 5
+    psi = W.random_nodal(17, n_modes, fine.n_nodes)          # (M, n): row k = mode k
+    kd = mlq.kl_desc_tet(fine_d, 0.3, 0.5, n_modes)
+    phi = mlq.kl_transfer_tet(kd, torch.as_tensor(psi, device="cuda"), coarse_d).cpu().numpy()
+    ref = fine.interpolate(psi.T, coarse.centres)              # (P, M)
+    assert np.abs(phi - ref).max() <= 1e-13 * np.abs(psi).max()
