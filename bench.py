@@ -63,7 +63,38 @@ WORKLOAD_TEXT = {
           "mean activation time, FP32 inner + FP64 Newton residual",
     "c4": "3D unit cube Q1 9^3..129^3 nested, 32..512 steps, 128-mode KL, MLQMC 16 shifts x 256/64/16/4/1, "
           "mean activation time",
+    "c5": "non-nested prolate-ellipsoidal shell, P1 tetrahedra 26k/187k/1.4M vertices, 512 steps, 256-mode KL "
+          "(l = 0.1 long axis), rule-based +60/-60 deg fibres, combination estimator 16/64/256 nested MC points, "
+          "mean activation time",
 }
+
+
+def cpu_baseline_tet(cfg, budget_s):
+    """The oracle on the coarsest shell: one sample (rule-based angle plus a seeded random
+    perturbation in place of the KL field), as many steps as the budget allows."""
+    import workloads as W
+    from oracle import stepper
+    from oracle.tetfem import TetMesh
+    lv = cfg["levels"][0]
+    m = W.tet_mesh(lv)
+    mesh = TetMesh(m["xyz"], m["tets"])
+    ph = cfg["physics"]
+    th = m["theta0"] + 0.3 * W.random_nodal(cfg["seed"], 1, mesh.n_elems)[0]
+    G = mesh.conductivity(th, m["e_circ"], m["e_long"], ph["sigma_l"], ph["sigma_t"])
+    t0 = time.perf_counter()
+    steps = 2
+    while True:  # grow the step count until the budget is used (each run starts from u = 0)
+        t1 = time.perf_counter()
+        out = stepper.solve(mesh, G, ph, lv["n_steps"], tol=1e-13, stop_after=steps)
+        el = time.perf_counter() - t1
+        if time.perf_counter() - t0 + 2.5 * el > budget_s or steps >= lv["n_steps"]:
+            break
+        steps *= 2
+    n = mesh.n_nodes
+    return dict(value=n * out["lin_iters"] / el, unit="DOF·iters/s", cores=1, kind="oracle",
+                sample=f"1 sample of level 0 ({n} vertices, first {steps} of {lv['n_steps']} steps); single process; "
+                       f"GMRES iterations; KL set-up excluded (seeded perturbation of the rule-based angle); {el:.1f} s",
+                st_dof_per_s=n * steps / el, seconds=el)
 
 
 def cpu_baseline(cfg, budget_s):
@@ -72,6 +103,8 @@ def cpu_baseline(cfg, budget_s):
 
     import workloads as W
     from oracle import run
+    if cfg["levels"][0].get("kind") == "tet":
+        return cpu_baseline_tet(cfg, budget_s)
     meshes = run.level_meshes(cfg)
     B = run.kl_basis(cfg, meshes, max_rank=2 * cfg["kl"]["n_modes"])
     M = cfg["kl"]["n_modes"]
@@ -114,7 +147,11 @@ def kl_synthesis(runner, cfg, dev, reps=5):
     l = len(runner.levels) - 1
     L = runner.levels[l]
     M = cfg["kl"]["n_modes"]
-    B = cfg["sampling"]["n_per_level"][l] * cfg["sampling"].get("n_shifts", 1)
+    samp = cfg["sampling"]
+    if samp["kind"] == "combination":  # the finest level sees the points of Q_0
+        B = samp["n_per_level"][0]
+    else:
+        B = samp["n_per_level"][l] * samp.get("n_shifts", 1)
     Y = torch.as_tensor(W.mc_normals(cfg["seed"], l, B, M), device=dev)
     theta = L.sample_fields(Y)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -167,16 +204,19 @@ def main():
     dev = "cuda:0"
     cfg = W.config(args.config)
     prec = cfg["prec"] if args.prec is None else (W.PREC_FP64 if args.prec == "fp64" else W.PREC_MIXED)
-    t_setup = time.perf_counter()
-    runner = ConfigRunner(cfg, prec=prec, device=dev)
-    t_setup = time.perf_counter() - t_setup
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    t_setup = time.perf_counter()
+    runner = ConfigRunner(cfg, prec=prec, device=dev, log=log)
+    t_setup = time.perf_counter() - t_setup
     log(f"set-up done in {t_setup:.1f} s (KL rank {runner.kl_rank})")
     runner.log = log
     samp = cfg["sampling"]
     M = cfg["kl"]["n_modes"]
     kind = samp["kind"]
-    if kind in ("mc", "mlmc"):
+    if kind == "combination":
+        Yc = torch.as_tensor(W.mc_normals(cfg["seed"], 0, max(samp["n_per_level"]), M), device=dev)
+        step = lambda: runner.run_combination(Yc)
+    elif kind in ("mc", "mlmc"):
         Ys = [torch.as_tensor(W.mc_normals(cfg["seed"], l, n, M), device=dev)
               for l, n in enumerate(samp["n_per_level"])]
         if kind == "mc":

@@ -11,6 +11,8 @@ from __future__ import annotations
 import numpy as np
 import torch
 
+import workloads as W
+
 from . import mlq
 
 EST_OF = {"mc": mlq.MLQ_EST_MC, "qmc": mlq.MLQ_EST_MLQMC, "mlmc": mlq.MLQ_EST_MLMC, "mlqmc": mlq.MLQ_EST_MLQMC}
@@ -20,7 +22,8 @@ class ConfigRunner:
     """Levels of one workload with their KL bases (Section 2.3) on one device."""
 
     def __init__(self, cfg: dict, prec: int | None = None, device="cuda", newton_tol=None, inner_tol=None,
-                 max_inner=30, kl_rank_factor=2, kl_eps=1e-2):
+                 max_inner=30, kl_rank_factor=2, kl_eps=1e-2, log=None):
+        say = log if log is not None else (lambda m: None)
         self.cfg = cfg
         self.device = device
         self.prec = cfg["prec"] if prec is None else prec
@@ -28,28 +31,51 @@ class ConfigRunner:
         kcfg = cfg["kl"]
         M = kcfg["n_modes"]
         kl_level = cfg["levels"][kcfg["grid_level"]]
-        self.kd = mlq.kl_desc(cfg["dim"], kl_level["n"], kl_level["lo"], kl_level["hi"], kcfg["std"],
-                              kcfg["corr_len"], M, max_rank=kl_rank_factor * M, eps=kl_eps)
+        self.tet = kl_level.get("kind") == "tet"
+        if self.tet:
+            # tetrahedral levels: the seeded shells of the workload (non-nested), the KL on
+            # the vertices of the finest one, the transfer by point location
+            self.meshes = [W.tet_mesh(lv) for lv in cfg["levels"]]
+            self.kd = mlq.kl_desc_tet(self.meshes[kcfg["grid_level"]], kcfg["std"], kcfg["corr_len"], M,
+                                      max_rank=kl_rank_factor * M, eps=kl_eps)
+        else:
+            self.kd = mlq.kl_desc(cfg["dim"], kl_level["n"], kl_level["lo"], kl_level["hi"], kcfg["std"],
+                                  kcfg["corr_len"], M, max_rank=kl_rank_factor * M, eps=kl_eps)
+        say("KL set-up")
         lam, psi, self.kl_rank, self.kl_resid = mlq.kl_modes(self.kd, device=device)
+        say(f"KL modes done (rank {self.kl_rank})")
         self.lam = lam
         sl = torch.as_tensor(np.sqrt(lam), dtype=torch.float64, device=device)
         self.levels = []
         samp = cfg["sampling"]
         n_shifts = samp.get("n_shifts", 1)
+        top = len(cfg["levels"]) - 1
         for l, lv in enumerate(cfg["levels"]):
-            # the largest batch a level sees: its own samples and, as the coarse side, level l+1's
-            nb = samp["n_per_level"][l] * n_shifts
-            if l + 1 < len(cfg["levels"]):
-                nb = max(nb, samp["n_per_level"][l + 1] * n_shifts)
-            phi = mlq.kl_transfer(self.kd, psi, lv, device=device)
+            if samp["kind"] == "combination":
+                # level j is evaluated on the points of Q_{L-j}
+                nb = samp["n_per_level"][top - l]
+            else:
+                # the largest batch a level sees: its own samples and, as the coarse side, level l+1's
+                nb = samp["n_per_level"][l] * n_shifts
+                if l + 1 < len(cfg["levels"]):
+                    nb = max(nb, samp["n_per_level"][l + 1] * n_shifts)
+            theta0 = None
+            if self.tet:
+                mesh = self.meshes[l]
+                lv = dict(lv, mesh=mesh)
+                phi = mlq.kl_transfer_tet(self.kd, psi, mesh, device=device)
+                theta0 = torch.as_tensor(mesh["theta0"], dtype=torch.float64, device=device)
+            else:
+                phi = mlq.kl_transfer(self.kd, psi, lv, device=device)
             desc, keep = mlq.make_desc(
-                lv, self.phys, n_modes=M, phi=phi, sqrt_lambda=sl, prec=self.prec, qoi=cfg["qoi"],
+                lv, self.phys, n_modes=M, phi=phi, sqrt_lambda=sl, theta0=theta0, prec=self.prec, qoi=cfg["qoi"],
                 newton_tol=newton_tol if newton_tol is not None else (1e-13 if self.prec == mlq.MLQ_FP64 else 1e-10),
                 inner_tol=inner_tol if inner_tol is not None else (1e-6 if self.prec == mlq.MLQ_FP64 else 1e-5),
                 max_inner=max_inner, max_batch=nb)
             L = mlq.Level(desc, keep, device=device)
             L._keep = None  # arrays were copied into the level blob
             self.levels.append(L)
+            say(f"level {l} created ({L.n_nodes} nodes, {L.n_elems} elements)")
             del phi
         del psi
         torch.cuda.synchronize()
@@ -110,6 +136,14 @@ class ConfigRunner:
             fc.append(self.solve(l - 1, Y) if l > 0 else None)
             npl.append(Y.shape[1] // S)
         return self._estimate(mlq.MLQ_EST_MLQMC, ff, fc, npl, S)
+
+    def run_combination(self, Y):
+        """eq. (PimpedML) with nested Monte Carlo points: Y (M x N_max) device normals; level j
+        is solved at the first N_{L-j} points (Q_{L-j})."""
+        npl = self.cfg["sampling"]["n_per_level"]
+        L = len(self.levels) - 1
+        f = [self.solve(j, Y[:, :npl[L - j]].contiguous()) for j in range(L + 1)]
+        return self._estimate(mlq.MLQ_EST_COMBINATION, f, None, list(npl), 1)
 
     def _estimate(self, kind, ff, fc, npl, S):
         ffh = [f.cpu().numpy() for f in ff]

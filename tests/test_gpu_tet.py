@@ -143,3 +143,46 @@ def test_tet_nonnested_transfer_matches_oracle(env):
     phi = mlq.kl_transfer_tet(kd, torch.as_tensor(psi, device="cuda"), coarse_d).cpu().numpy()
     ref = fine.interpolate(psi.T, coarse.centres)              # (P, M)
     assert np.abs(phi - ref).max() <= 1e-13 * np.abs(psi).max()
+
+
+def test_c5_pipeline_small_matches_oracle(env):
+    """The whole non-nested path at small size through the driver (library KL on the finest
+    shell, point-location transfer, rule-based base angle, solves, combination estimator
+    eq. (PimpedML)) against the oracle's own pipeline, FP64."""
+    torch, mlq = env
+    from oracle import estimators, kl, stepper
+    from oracle.tetfem import TetMesh
+    from paper_2105_02007_amd.driver import ConfigRunner
+    cfg = W.config("c5")
+    cfg["levels"] = W._tet_levels([(2, 6, 12), (3, 8, 16), (4, 10, 20)], [12, 12, 12], 5)
+    cfg["kl"]["n_modes"] = 6
+    cfg["sampling"]["n_per_level"] = [2, 3, 5]
+    cfg["prec"] = W.PREC_FP64
+    M = cfg["kl"]["n_modes"]
+    n_kl = (cfg["levels"][-1]["cells"][0] + 1) * (cfg["levels"][-1]["cells"][1] + 1) * cfg["levels"][-1]["cells"][2]
+    factor = n_kl // M  # near-full-rank Cholesky on both sides, same rank
+    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0)
+    Y = W.mc_normals(cfg["seed"], 0, 5, M)
+    res = runner.run_combination(torch.as_tensor(Y, device="cuda"))
+    # oracle pipeline
+    ph = cfg["physics"]
+    meshes = [W.tet_mesh(lv) for lv in cfg["levels"]]
+    tm = [TetMesh(m["xyz"], m["tets"]) for m in meshes]
+    Mk, _ = tm[-1].assemble(np.zeros((tm[-1].n_elems, 3, 3)))
+    assert tm[-1].n_nodes == n_kl
+    lam, psi = kl.kl_modes(tm[-1], Mk, cfg["kl"]["std"], cfg["kl"]["corr_len"], M, max_rank=factor * M, eps=0.0)
+    npl = cfg["sampling"]["n_per_level"]
+    L = len(meshes) - 1
+    f = []
+    for j in range(L + 1):
+        phi = tm[-1].interpolate(psi, tm[j].centres)
+        th = kl.field(meshes[j]["theta0"], phi, np.sqrt(lam), Y[:, :npl[L - j]])
+        vals = []
+        for b in range(th.shape[0]):
+            G = tm[j].conductivity(th[b], meshes[j]["e_circ"], meshes[j]["e_long"], ph["sigma_l"], ph["sigma_t"])
+            vals.append(stepper.solve(tm[j], G, ph, cfg["levels"][j]["n_steps"], tol=1e-13)["mean_act"])
+        f.append(np.array(vals))
+    est = estimators.combination(f, npl)
+    for j in range(L + 1):
+        assert np.abs(res["f_fine"][j] - f[j]).max() <= 1e-10 * np.abs(f[j]).max(), j
+    assert abs(res["estimate"] - est) <= 1e-10 * abs(est)

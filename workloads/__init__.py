@@ -18,6 +18,8 @@ from __future__ import annotations
 import copy
 import numpy as np
 
+from . import tetshell
+
 # --- physical constants (Section 5.1) --------------------------------------
 ALPHA = 1.4e-3          # mV^-2 ms^-1
 U_REST = 0.0            # mV
@@ -56,6 +58,18 @@ def _box_levels(dim, nodes, steps):
                  n_steps=int(m)) for n, m in zip(nodes, steps)]
 
 
+def _tet_levels(cells, steps, seed):
+    """Non-nested tetrahedral shells (workloads/tetshell.py), one mesh seed per level."""
+    return [dict(kind="tet", dim=3, cells=list(c), mesh_seed=int(100 * seed + l), n_steps=int(m))
+            for l, (c, m) in enumerate(zip(cells, steps))]
+
+
+def tet_mesh(level: dict) -> dict:
+    """Vertices, tetrahedra, fibre frame and rule-based base angle of a tetrahedral level."""
+    xyz, tets, ec, el, th0 = tetshell.shell_mesh(level["cells"], level["mesh_seed"])
+    return dict(xyz=xyz, tets=tets, e_circ=ec, e_long=el, theta0=th0)
+
+
 # --- the five synthetic workloads -------------------------------------------
 CONFIGS = {
     "c1": dict(
@@ -82,6 +96,15 @@ CONFIGS = {
         kl=dict(n_modes=128, corr_len=0.1, std=0.3, grid_level=4),
         sampling=dict(kind="mlqmc", n_per_level=[256, 64, 16, 4, 1], n_shifts=16),
         qoi=QOI_MEAN_ACT_TIME, prec=PREC_MIXED, seed=4),
+    # combination form eq. (PimpedML): Q_0, Q_1, Q_2 with 16, 64, 256 nested Monte Carlo
+    # points (prefixes of one stream) on the fine, middle and coarse shell
+    "c5": dict(
+        name="c5", title="non-nested multilevel, prolate-ellipsoidal shell, P1 tetrahedra 26k/187k/1.4M "
+                         "vertices, 512 steps, 256-mode KL, combination estimator",
+        dim=3, levels=_tet_levels([(4, 40, 128), (8, 80, 256), (16, 160, 512)], [512, 512, 512], 5),
+        kl=dict(n_modes=256, corr_len=0.1 * tetshell.LONG_AXIS, std=0.3, grid_level=2),
+        sampling=dict(kind="combination", n_per_level=[16, 64, 256]),
+        qoi=QOI_MEAN_ACT_TIME, prec=PREC_MIXED, seed=5),
 }
 
 # solver tolerances: normwise backward error of the nonlinear step equation
@@ -94,6 +117,10 @@ MAX_INNER = 30
 def config(name: str) -> dict:
     cfg = copy.deepcopy(CONFIGS[name])
     cfg["physics"] = physics(cfg["dim"])
+    if cfg["levels"][0].get("kind") == "tet":
+        # stimulus: the ball around the epicardial apex (radius 1/8 of the long axis)
+        c, r = tetshell.stimulus_ball()
+        cfg["physics"].update(stim_center=c.tolist(), stim_radius=float(r))
     return cfg
 
 
