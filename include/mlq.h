@@ -280,6 +280,8 @@ typedef struct {
   double ms[16];        /* summed kernel time per class */
   int64_t launches[16]; /* launches per class */
   double units[16];     /* node-samples processed per class */
+  double bytes[16];     /* algorithmic bytes per class (MLQ_K_APPLY only; 0 elsewhere): the
+                           operand bytes the launches must read and write at least once */
 } mlq_timing;
 
 /* Times the kernel classes whose bit is set in kernel_mask (0 turns timing off)

@@ -84,7 +84,7 @@ struct mlq_level {
   mlq_timing tim{};
   struct Pending {
     int cls;
-    double units;
+    double units, bytes;
     hipEvent_t a, b;
   };
   std::vector<Pending> pending;
@@ -106,7 +106,7 @@ hipEvent_t take_event(mlq_level* lv) {
 
 // Brackets one launch with events when its class is timed.
 template <typename F>
-void timed(mlq_level* lv, int cls, double units, hipStream_t s, F&& launch) {
+void timed(mlq_level* lv, int cls, double units, hipStream_t s, F&& launch, double bytes = 0.0) {
   if (!(lv->tmask & (1u << cls))) {
     launch();
     return;
@@ -119,7 +119,7 @@ void timed(mlq_level* lv, int cls, double units, hipStream_t s, F&& launch) {
   (void)hipEventRecord(a, s);
   launch();
   (void)hipEventRecord(b, s);
-  lv->pending.push_back({cls, units, a, b});
+  lv->pending.push_back({cls, units, bytes, a, b});
 }
 
 // After a stream synchronisation: fold finished event pairs into the totals.
@@ -130,6 +130,7 @@ void harvest(mlq_level* lv) {
       lv->tim.ms[p.cls] += ms;
       lv->tim.launches[p.cls] += 1;
       lv->tim.units[p.cls] += p.units;
+      lv->tim.bytes[p.cls] += p.bytes;
     }
     lv->free_events.push_back(p.a);
     lv->free_events.push_back(p.b);
@@ -238,6 +239,7 @@ Work carve_workspace(void* base, const Geo& geo, int32_t B, int kmax, bool mixed
   w.nblk = (int32_t)cdiv(nn, kBlock);
   w.nred = (int32_t)cdiv(nn, kRedChunk);
   w.nres = (geo.dim == 3 && !geo.tet) ? stencil3_blocks(geo) : w.nblk;
+  w.nwav = (geo.dim == 3 && !geo.tet) ? stencil3_blocks(geo) : 0;
   const size_t ti = mixed ? sizeof(float) : sizeof(double);
   const size_t vn = (size_t)nn * B;
   char* p = (char*)base;
@@ -259,7 +261,7 @@ Work carve_workspace(void* base, const Geo& geo, int32_t B, int kmax, bool mixed
   w.coef = take(geo.tet ? (size_t)geo.nnz * B * ti : (size_t)P * B * 2 * ti);
   const size_t npart = std::max((size_t)std::max(w.nblk, w.nres) * 3, (size_t)w.nred * (kmax + 1));
   w.part = (double*)take(npart * B * sizeof(double));
-  w.dpart = (double*)take((size_t)w.nred * (kmax + 1) * B * sizeof(double));
+  w.dpart = (double*)take((size_t)std::max(w.nred, w.nwav) * (kmax + 1) * B * sizeof(double));
   w.H = (double*)take((size_t)B * (kmax + 1) * kmax * sizeof(double));
   w.cs = (double*)take((size_t)B * kmax * sizeof(double));
   w.sn = (double*)take((size_t)B * kmax * sizeof(double));
@@ -685,16 +687,25 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
           else
             launch_minv_basis(g, w, level->tri, level->nmax, j, batch, mixed, s);
         });
-        timed(level, MLQ_K_APPLY, units, s, [&] {
-          if (tet)  // Jacobi preconditioning: the operator is the full Jacobian applied to z
-            launch_tet_apply(td, w.coef, w.z, w.d, w.w, 0.5 * dt, batch, w.inner_active, mixed, s);
-          else if (g.dim == 3)
-            launch_apply_pk3(g, w, j, 0.5 * dt, batch, mixed, s);
-          else
-            launch_apply_pk(g, w, j, 0.5 * dt, batch, mixed, s);
-        });
-        timed(level, MLQ_K_DOTS, units, s, [&] { launch_dots(g, w, j, batch, mixed, s); });
-        timed(level, MLQ_K_ORTH, units, s, [&] { launch_orth(g, w, j, batch, mixed, s); });
+        // 3D boxes, j < 8: the apply kernel also forms the projections w . v_i (i <= j)
+        const bool fuse = g.dim == 3 && !tet && j < 8;
+        const double ti = mixed ? 4.0 : 8.0;
+        // algorithmic bytes: z, v_j, the element coefficients (p, q) read, w written; fused: v_0..v_{j-1} read
+        const double apply_bytes = units * ti * (5.0 + (fuse ? j : 0));
+        timed(
+            level, MLQ_K_APPLY, units, s,
+            [&] {
+              if (tet)  // Jacobi preconditioning: the operator is the full Jacobian applied to z
+                launch_tet_apply(td, w.coef, w.z, w.d, w.w, 0.5 * dt, batch, w.inner_active, mixed, s);
+              else if (g.dim == 3)
+                launch_apply_pk3(g, w, j, 0.5 * dt, batch, mixed, s, fuse ? (j < 4 ? 4 : 8) : 0);
+              else
+                launch_apply_pk(g, w, j, 0.5 * dt, batch, mixed, s);
+            },
+            apply_bytes);
+        if (!fuse) timed(level, MLQ_K_DOTS, units, s, [&] { launch_dots(g, w, j, batch, mixed, s); });
+        timed(level, MLQ_K_ORTH, units, s,
+              [&] { launch_orth(g, w, j, batch, mixed, s, fuse ? w.nwav : w.nred); });
         timed(level, MLQ_K_SMALL, 0.0, s, [&] {
           launch_givens(g, w, j, batch, d.inner_tol, s);
           launch_count(w.inner_active, batch, w.counter, s);

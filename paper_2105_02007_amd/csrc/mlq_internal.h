@@ -105,6 +105,7 @@ struct Work {
   int32_t nblk;            // blocks per sample of the nodal kernels
   int32_t nred;            // blocks per sample of the reduction kernels
   int32_t nres;            // blocks per sample of the residual kernel (partial norms)
+  int32_t nwav;            // workgroups per sample of the 3D stencil kernels (projection partials when fused)
   size_t bytes;
 };
 
@@ -121,7 +122,7 @@ void launch_residual(const Geo& g, const Ionic& io, const Work& w, int32_t B, bo
 void launch_newton_check(const Geo& g, const Work& w, int32_t B, double tol, hipStream_t s);
 void launch_count(const int32_t* flags, int32_t B, int32_t* out, hipStream_t s);
 void launch_dots(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s);
-void launch_orth(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s);
+void launch_orth(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s, int32_t npart);
 void launch_givens(const Geo& g, const Work& w, int j, int32_t B, double tol, hipStream_t s);
 void launch_solve_y(const Work& w, int32_t B, hipStream_t s);
 void launch_activation(const Work& w, int64_t nn, int32_t B, double u_th, double t_k, double dt,
@@ -155,7 +156,10 @@ void launch_apply_pk(const Geo& g, const Work& w, int j, double ck, int32_t B, b
 void launch_update_pm(const Geo& g, const Work& w, const void* tri, int nmax, int32_t B, bool mixed, hipStream_t s);
 hipError_t prepare_minv_kernels(size_t bytes);
 int32_t stencil3_blocks(const Geo& g);
-void launch_apply_pk3(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s);
+// jb > 0: also accumulate the Gram-Schmidt projections w . v_i (i <= j < jb) into dpart,
+// one partial per workgroup (Work::nwav per sample)
+void launch_apply_pk3(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s, int jb);
+int32_t stencil3_waves(const Geo& g);
 void launch_apply_full3(const Geo& g, const void* coef, const void* x, const void* d, void* y, double ck, int32_t B,
                         bool mixed, hipStream_t s);
 void launch_residual3(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);

@@ -507,23 +507,24 @@ void launch_dots(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipS
 }
 
 // Vs_{j+1} = w - sum_i hc_i Vs_i, partial |Vs_{j+1}|^2.  Each block first sums the
-// projection partials of k_dots (one wave per coefficient, fixed order):
+// npart projection partials (of k_dots, or of the apply kernel that fused them;
+// one wave per coefficient, fixed order):
 // h_ij = inv_eta_i sum_blk part, hc_i = h_ij inv_eta_i; block 0 stores column j of H.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_orth(int64_t nn, const T* __restrict__ w, T* __restrict__ V, size_t vs,
                                                  int j, int kmax, const double* __restrict__ dpart,
                                                  const double* __restrict__ inv_eta, double* __restrict__ H,
-                                                 double* __restrict__ part, const int32_t* __restrict__ active) {
+                                                 double* __restrict__ part, const int32_t* __restrict__ active,
+                                                 int npart) {
   const int sb = blockIdx.y;
   if (active[sb] == 0) return;
   __shared__ double sh[kBlock / 64];
   __shared__ double c[kMaxInner + 1];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int nred = gridDim.x;
   for (int i = wid; i <= j; i += kBlock / 64) {
-    const double* pi = dpart + ((int64_t)sb * (kmax + 1) + i) * nred;
+    const double* pi = dpart + ((int64_t)sb * (kmax + 1) + i) * npart;
     double a = 0.0;
-    for (int b = lane; b < nred; b += 64) a += pi[b];
+    for (int b = lane; b < npart; b += 64) a += pi[b];
     a = wave_sum(a);
     if (lane == 0) {
       const double ie = inv_eta[(int64_t)sb * (kmax + 1) + i];
@@ -549,15 +550,15 @@ __global__ __launch_bounds__(kBlock) void k_orth(int64_t nn, const T* __restrict
   if (threadIdx.x == 0) part[(int64_t)sb * gridDim.x + blockIdx.x] = acc;
 }
 
-void launch_orth(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s) {
+void launch_orth(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s, int32_t npart) {
   const dim3 grid((unsigned)w.nred, B);
   const size_t vs = (size_t)g.nn * B;
   if (mixed)
     hipLaunchKernelGGL((k_orth<float>), grid, dim3(kBlock), 0, s, g.nn, (const float*)w.w, (float*)w.V, vs, j,
-                       w.kmax, w.dpart, w.inv_eta, w.H, w.part, w.inner_active);
+                       w.kmax, w.dpart, w.inv_eta, w.H, w.part, w.inner_active, (int)npart);
   else
     hipLaunchKernelGGL((k_orth<double>), grid, dim3(kBlock), 0, s, g.nn, (const double*)w.w, (double*)w.V, vs, j,
-                       w.kmax, w.dpart, w.inv_eta, w.H, w.part, w.inner_active);
+                       w.kmax, w.dpart, w.inv_eta, w.H, w.part, w.inner_active, (int)npart);
 }
 
 // Norm of the new vector, Givens rotations of column j, residual estimate |g_{j+1}|.

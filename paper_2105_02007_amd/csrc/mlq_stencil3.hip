@@ -25,6 +25,8 @@
 //   out_ab = s(a) [(sbar + p) X_b + q Dy / 4] + s(b) [(sbar - p) Y_a + q Dx / 4],
 //   X = M1y dx / hx, Y = M1x dy / hy, dx_b = u_1b - u_0b, dy_a = u_a1 - u_a0,
 //   Dx = dx_0 + dx_1, Dy = dy_0 + dy_1.
+#include <type_traits>
+
 #include "mlq_internal.h"
 
 namespace mlq {
@@ -118,6 +120,11 @@ struct Args {
   const int32_t* active;
   int tiles_x, tiles_y, zchunks;
   int bps;            // workgroups per sample
+  // kPK with fused projections: partials of w . v_i (i <= j) per wave
+  const T* V;         // basis vectors v_0.., stride vs
+  size_t vs;
+  double* dpart;      // [B][kmax + 1][npart]
+  int npart;          // partials per sample (= waves per sample)
 };
 
 }  // namespace
@@ -132,7 +139,7 @@ __device__ inline R shdn(R v, int d) {
   return __shfl_down(v, d, 64);
 }
 
-template <typename R, typename TC, typename TI, int MODE>
+template <typename R, typename TC, typename TI, int MODE, int JB = 0>
 __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
   const Geo& g = A.g;
   // Workgroups go to the 8 XCDs round-robin (linear id mod 8).  Renumber them so
@@ -153,6 +160,12 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
   const int nwaves = A.tiles_x * A.tiles_y * A.zchunks;
   const bool wave_on = sample_on && gw < nwaves;
   double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+  double dacc[JB > 0 ? JB : 1];
+#pragma unroll
+  for (int i = 0; i < (JB > 0 ? JB : 1); ++i) dacc[i] = 0.0;
+  R wk[JB > 0 ? WZ : 1];  // w at the owned node of each plane of the wave (0 where not owned)
+#pragma unroll
+  for (int t = 0; t < (JB > 0 ? WZ : 1); ++t) wk[t] = 0;
   if (wave_on) {
     int t = gw;
     const int tx_i = t % A.tiles_x;
@@ -290,7 +303,16 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
           *(decltype(base))((char*)base + byte_off) = v;
         };
         if constexpr (MODE == kPK) {
-          put(A.y + sbase, ob + kk * pbR, p0 * sj + sres);
+          const R wv = p0 * sj + sres;
+          put(A.y + sbase, ob + kk * pbR, wv);
+          if constexpr (JB > 0) {
+            // kept for the projections after the march (the ring loop is unrolled, so
+            // k - zs is a compile-time index here)
+            const int q = k - zs;
+#pragma unroll
+            for (int t = 0; t < WZ; ++t)
+              if (t == q) wk[t] = wv;
+          }
         } else if constexpr (MODE == kFull) {
           put(A.y + sbase, ob + kk * pbR, sres);
         } else if constexpr (MODE == kRes) {
@@ -324,12 +346,51 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     fetch_coef(k0 + 1, C1p, C1q);
     fetch_pre(k0, Q00, Q01);
     fetch_pre(k0 + 1, Q10, Q11);
+#pragma unroll
     for (int it = 0; it < (WZ + 1) / 4; ++it) {
       const int k = k0 + 4 * it;
       step(k + 0, P0, P1, P3, C0p, C0q, C2p, C2q, Q00, Q01, Q20, Q21);
       step(k + 1, P1, P2, P0, C1p, C1q, C3p, C3q, Q10, Q11, Q30, Q31);
       step(k + 2, P2, P3, P1, C2p, C2q, C0p, C0q, Q20, Q21, Q00, Q01);
       step(k + 3, P3, P0, P2, C3p, C3q, C1p, C1q, Q30, Q31, Q10, Q11);
+    }
+    if constexpr (MODE == kPK && JB > 0) {
+      // projections w . v_i (i <= j) over the wave's owned nodes: all loads of one
+      // basis vector are issued together (addresses clamped into the grid; wk is 0
+      // wherever the node is not owned)
+      if (owner) {
+#pragma unroll
+        for (int i = 0; i < JB; ++i) {
+          if (i > A.j) break;
+          R v[WZ];
+#pragma unroll
+          for (int t = 0; t < WZ; ++t) {
+            const uint32_t kk = (uint32_t)min(zs + t, g.nz - 1);
+            v[t] = at(A.V + i * A.vs + sbase, ob + kk * pbR);
+          }
+#pragma unroll
+          for (int t = 0; t < WZ; ++t) dacc[i] += (double)wk[t] * (double)v[t];
+        }
+      }
+    }
+  }
+  if constexpr (MODE == kPK && JB > 0) {
+    // one partial per workgroup: waves summed in a fixed order
+    __shared__ double redp[NT / 64][JB];
+#pragma unroll
+    for (int i = 0; i < JB; ++i) {
+      double v = dacc[i];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) redp[wid][i] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < JB && (int)threadIdx.x <= A.j) {
+      const int i = threadIdx.x;
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < NT / 64; ++q) v += redp[q][i];
+      A.dpart[((int64_t)sb * (A.kmax + 1) + i) * A.npart + blk] = v;
     }
   }
   if constexpr (MODE == kRes) {
@@ -377,22 +438,41 @@ int32_t stencil3_blocks(const Geo& g) {
   return (int32_t)cdiv(cdiv(g.nx, WT) * cdiv(g.ny, WT) * cdiv(g.nz, WZ), NT / 64);
 }
 
-void launch_apply_pk3(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s) {
+int32_t stencil3_waves(const Geo& g) {
+  return (int32_t)(cdiv(g.nx, WT) * cdiv(g.ny, WT) * cdiv(g.nz, WZ));
+}
+
+void launch_apply_pk3(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s, int jb) {
   const size_t vs = (size_t)g.nn * B;
+  auto fill = [&](auto& a) {
+    using T = std::remove_const_t<std::remove_pointer_t<decltype(a.x)>>;
+    a.g = g; a.x = (const T*)w.z; a.vj = (const T*)w.V + j * vs; a.inv_eta = w.inv_eta;
+    a.j = j; a.kmax = w.kmax; a.coef = w.coef; a.y = (T*)w.w; a.ck = ck; a.cm = 0.0; a.active = w.inner_active;
+    a.V = (const T*)w.V; a.vs = vs; a.dpart = w.dpart;
+  };
+  dim3 grid;
   if (mixed) {
     Args<float> a{};
-    a.g = g; a.x = (const float*)w.z; a.vj = (const float*)w.V + j * vs; a.inv_eta = w.inv_eta; a.j = j;
-    a.kmax = w.kmax; a.coef = w.coef; a.y = (float*)w.w; a.ck = ck; a.cm = 0.0; a.active = w.inner_active;
-    dim3 grid;
+    fill(a);
     wave_grid_of(g, a, B, grid);
-    hipLaunchKernelGGL((k_wave3<float, float, float, kPK>), grid, dim3(NT), 0, s, a);
+    a.npart = a.bps;
+    if (jb == 0)
+      hipLaunchKernelGGL((k_wave3<float, float, float, kPK, 0>), grid, dim3(NT), 0, s, a);
+    else if (jb <= 4)
+      hipLaunchKernelGGL((k_wave3<float, float, float, kPK, 4>), grid, dim3(NT), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_wave3<float, float, float, kPK, 8>), grid, dim3(NT), 0, s, a);
   } else {
     Args<double> a{};
-    a.g = g; a.x = (const double*)w.z; a.vj = (const double*)w.V + j * vs; a.inv_eta = w.inv_eta; a.j = j;
-    a.kmax = w.kmax; a.coef = w.coef; a.y = (double*)w.w; a.ck = ck; a.cm = 0.0; a.active = w.inner_active;
-    dim3 grid;
+    fill(a);
     wave_grid_of(g, a, B, grid);
-    hipLaunchKernelGGL((k_wave3<double, double, double, kPK>), grid, dim3(NT), 0, s, a);
+    a.npart = a.bps;
+    if (jb == 0)
+      hipLaunchKernelGGL((k_wave3<double, double, double, kPK, 0>), grid, dim3(NT), 0, s, a);
+    else if (jb <= 4)
+      hipLaunchKernelGGL((k_wave3<double, double, double, kPK, 4>), grid, dim3(NT), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_wave3<double, double, double, kPK, 8>), grid, dim3(NT), 0, s, a);
   }
 }
 

@@ -70,7 +70,8 @@ class KlDesc(C.Structure):
 
 
 class Timing(C.Structure):
-    _fields_ = [("ms", C.c_double * 16), ("launches", C.c_int64 * 16), ("units", C.c_double * 16)]
+    _fields_ = [("ms", C.c_double * 16), ("launches", C.c_int64 * 16), ("units", C.c_double * 16),
+                ("bytes", C.c_double * 16)]
 
 
 class EstimateOut(C.Structure):
@@ -273,7 +274,7 @@ class Level:
     def timing_read(self, reset=True):
         t = Timing()
         check(lib.mlq_timing_read(self.handle, C.byref(t), 1 if reset else 0))
-        return {c: dict(ms=t.ms[i], launches=int(t.launches[i]), units=t.units[i])
+        return {c: dict(ms=t.ms[i], launches=int(t.launches[i]), units=t.units[i], bytes=t.bytes[i])
                 for i, c in enumerate(KERNEL_CLASSES)}
 
     def apply(self, theta, x, d, y=None):
