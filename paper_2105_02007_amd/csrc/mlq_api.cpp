@@ -144,7 +144,7 @@ namespace {
 
 struct BlobLayout {
   size_t phi64, phi32, sl, th0, fbox, wts, tri;
-  size_t rowptr, col, mval, mval32, mdiag, mdiag32, cptr, cdat, geo;  // tetrahedral levels
+  size_t ecol, em, em32, mdiag, mdiag32, ecptr, ecdat, geo;  // tetrahedral levels
   size_t total;
 };
 
@@ -159,14 +159,13 @@ BlobLayout blob_layout(int64_t P, int64_t M, int64_t nn, int64_t nmax, const mlq
   L.fbox = o;  o = align256(o + sizeof(double) * nn);
   L.wts = o;   o = align256(o + sizeof(double) * nn);
   if (th != nullptr) {
-    L.rowptr = o;  o = align256(o + sizeof(int32_t) * (th->nv + 1));
-    L.col = o;     o = align256(o + sizeof(int32_t) * th->nnz);
-    L.mval = o;    o = align256(o + sizeof(double) * th->nnz);
-    L.mval32 = o;  o = align256(o + sizeof(float) * th->nnz);
+    L.ecol = o;    o = align256(o + sizeof(int32_t) * th->nell);
+    L.em = o;      o = align256(o + sizeof(double) * th->nell);
+    L.em32 = o;    o = align256(o + sizeof(float) * th->nell);
     L.mdiag = o;   o = align256(o + sizeof(double) * th->nv);
     L.mdiag32 = o; o = align256(o + sizeof(float) * th->nv);
-    L.cptr = o;    o = align256(o + sizeof(int32_t) * (th->nnz + 1));
-    L.cdat = o;    o = align256(o + sizeof(int32_t) * th->nc);
+    L.ecptr = o;   o = align256(o + sizeof(int32_t) * (th->nell + 1));
+    L.ecdat = o;   o = align256(o + sizeof(int32_t) * th->nc);
     L.geo = o;     o = align256(o + sizeof(double) * mlq::kTetGeo * th->nt);
   }
   L.total = o;
@@ -366,7 +365,7 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   g.sbar = 0.5 * (desc->sigma_l + desc->sigma_t);
   g.st = desc->sigma_t;
   g.tet = tet ? 1 : 0;
-  g.nnz = tet ? th.nnz : 0;
+  g.nnz = tet ? th.nell : 0;
   if (tet) g.nx = g.ny = g.nz = 0;
   lv->io = Ionic{desc->alpha, desc->u_rest, desc->u_th, desc->u_peak, desc->t_end / desc->n_steps};
 
@@ -499,29 +498,28 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
     TetDev& t = lv->td;
     t.nv = th.nv;
     t.nt = th.nt;
-    t.nnz = th.nnz;
+    t.nell = th.nell;
+    t.width = th.width;
     t.nc = th.nc;
-    t.rowptr = (const int32_t*)(base + L.rowptr);
-    t.col = (const int32_t*)(base + L.col);
-    t.mval = (const double*)(base + L.mval);
-    t.mval32 = (const float*)(base + L.mval32);
+    t.ecol = (const int32_t*)(base + L.ecol);
+    t.em = (const double*)(base + L.em);
+    t.em32 = (const float*)(base + L.em32);
     t.mdiag = (const double*)(base + L.mdiag);
     t.mdiag32 = (const float*)(base + L.mdiag32);
-    t.cptr = (const int32_t*)(base + L.cptr);
-    t.cdat = (const int32_t*)(base + L.cdat);
+    t.ecptr = (const int32_t*)(base + L.ecptr);
+    t.ecdat = (const int32_t*)(base + L.ecdat);
     t.geo = (const double*)(base + L.geo);
-    std::vector<float> m32(th.mval.begin(), th.mval.end()), d32(th.mdiag.begin(), th.mdiag.end());
+    std::vector<float> m32(th.em.begin(), th.em.end()), d32(th.mdiag.begin(), th.mdiag.end());
     auto up = [&](const void* dst, const void* src, size_t bytes) {
       if (e == hipSuccess) e = hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, s);
     };
-    up(t.rowptr, th.rowptr.data(), sizeof(int32_t) * th.rowptr.size());
-    up(t.col, th.col.data(), sizeof(int32_t) * th.col.size());
-    up(t.mval, th.mval.data(), sizeof(double) * th.mval.size());
-    up(t.mval32, m32.data(), sizeof(float) * m32.size());
+    up(t.ecol, th.ecol.data(), sizeof(int32_t) * th.ecol.size());
+    up(t.em, th.em.data(), sizeof(double) * th.em.size());
+    up(t.em32, m32.data(), sizeof(float) * m32.size());
     up(t.mdiag, th.mdiag.data(), sizeof(double) * th.mdiag.size());
     up(t.mdiag32, d32.data(), sizeof(float) * d32.size());
-    up(t.cptr, th.cptr.data(), sizeof(int32_t) * th.cptr.size());
-    up(t.cdat, th.cdat.data(), sizeof(int32_t) * th.cdat.size());
+    up(t.ecptr, th.ecptr.data(), sizeof(int32_t) * th.ecptr.size());
+    up(t.ecdat, th.ecdat.data(), sizeof(int32_t) * th.ecdat.size());
     up(t.geo, th.geo.data(), sizeof(double) * th.geo.size());
     // the host vectors must outlive the asynchronous copies
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -690,8 +688,13 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
         // 3D boxes, j < 8: the apply kernel also forms the projections w . v_i (i <= j)
         const bool fuse = g.dim == 3 && !tet && j < 8;
         const double ti = mixed ? 4.0 : 8.0;
-        // algorithmic bytes: z, v_j, the element coefficients (p, q) read, w written; fused: v_0..v_{j-1} read
-        const double apply_bytes = units * ti * (5.0 + (fuse ? j : 0));
+        // algorithmic bytes.  Boxes: z, v_j, the element coefficients (p, q) read, w written;
+        // fused: v_0..v_{j-1} read.  Tetrahedra: per row and sample the stiffness values of its
+        // slots, z and d read, w written; the shared pattern (columns, mass) once per launch.
+        const double slots = tet ? (double)td.nell / (double)td.nv : 0.0;
+        const double apply_bytes =
+            tet ? units * (ti * (slots + 3.0)) + (double)td.nell * (4.0 + ti)
+                : units * ti * (5.0 + (fuse ? j : 0));
         timed(
             level, MLQ_K_APPLY, units, s,
             [&] {

@@ -26,31 +26,35 @@ struct Geo {
   double sbar;         // (sigma_l + sigma_t) / 2
   double st;           // sigma_t
   int32_t tet;         // 1: P1 tetrahedra (TetDev holds the mesh), 0: Q1 box
-  int64_t nnz;         // tetrahedra: nonzeros of the vertex adjacency
+  int64_t nnz;         // tetrahedra: stored (padded, slot-major) entries of the vertex adjacency
 };
 
 // P1 tetrahedral level data on the device (inside the level blob).  The sparsity
 // of M and K is the vertex adjacency (CSR); each nonzero lists the element
 // matrix entries that add into it, in increasing element order.
 struct TetDev {
-  int64_t nv, nt, nnz, nc;
-  const int32_t* rowptr;  // nv + 1
-  const int32_t* col;     // nnz, sorted within a row
-  const double* mval;     // nnz: consistent P1 mass
-  const float* mval32;    // nnz
-  const double* mdiag;    // nv: diagonal of M
-  const float* mdiag32;   // nv
-  const int32_t* cptr;    // nnz + 1
-  const int32_t* cdat;    // nc: (tet << 4) | (4 a + b), a = local row vertex, b = local column vertex
-  const double* geo;      // nt x kTetGeo: grad phi_0..3 (12), e_circ (3), e_long (3), volume
+  int64_t nv, nt, nell, nc;
+  int32_t width;           // slots per row: the longest row of the P1 pattern
+  // the pattern stored slot-major: entry (s, i) at s * nv + i (consecutive rows are
+  // consecutive in memory for every slot); padded slots point at row i with value 0
+  const int32_t* ecol;     // nell: column
+  const double* em;        // nell: consistent P1 mass
+  const float* em32;       // nell
+  const double* mdiag;     // nv: diagonal of M
+  const float* mdiag32;    // nv
+  const int32_t* ecptr;    // nell + 1
+  const int32_t* ecdat;    // nc: (tet << 4) | (4 a + b), a = local row vertex, b = local column vertex
+  const double* geo;       // nt x kTetGeo: grad phi_0..3 (12), e_circ (3), e_long (3), volume
 };
 constexpr int kTetGeo = 19;
 
 // Host-side preparation of a tetrahedral level (mlq_tetmesh.cpp).
 struct TetHost {
-  int64_t nv = 0, nt = 0, nnz = 0, nc = 0;
-  std::vector<int32_t> rowptr, col, cptr, cdat;
-  std::vector<double> mval, mdiag, geo, wts, fload;
+  int64_t nv = 0, nt = 0, nnz = 0, nc = 0, nell = 0;
+  int32_t width = 0;
+  std::vector<int32_t> rowptr, col, cptr, cdat;   // CSR (rows sorted)
+  std::vector<int32_t> ecol, ecptr, ecdat;        // the same, slot-major padded (TetDev)
+  std::vector<double> mval, em, mdiag, geo, wts, fload;
   double vol = 0.0;
 };
 // Validates the tetrahedral fields of desc and builds the CSR structure (and, with
@@ -159,7 +163,6 @@ int32_t stencil3_blocks(const Geo& g);
 // jb > 0: also accumulate the Gram-Schmidt projections w . v_i (i <= j < jb) into dpart,
 // one partial per workgroup (Work::nwav per sample)
 void launch_apply_pk3(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s, int jb);
-int32_t stencil3_waves(const Geo& g);
 void launch_apply_full3(const Geo& g, const void* coef, const void* x, const void* d, void* y, double ck, int32_t B,
                         bool mixed, hipStream_t s);
 void launch_residual3(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);
@@ -167,7 +170,8 @@ void launch_rhs3(const Geo& g, const Work& w, const double* fbox, double load_co
                  hipStream_t s);
 void launch_cast_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
-// P1 tetrahedra (mlq_tet.hip).  kval: per-sample stiffness values [B][nnz], inner precision.
+// P1 tetrahedra (mlq_tet.hip).  kval: per-sample stiffness values [B][nell] (slot-major
+// padded pattern of TetDev), inner precision.
 void launch_tet_assemble(const TetDev& t, const void* theta, void* kval, int32_t B, double sigma_t, double dsig,
                          bool mixed, hipStream_t s);
 void launch_tet_apply(const TetDev& t, const void* kval, const void* x, const void* d, void* y, double ck, int32_t B,

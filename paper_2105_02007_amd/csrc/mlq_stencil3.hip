@@ -130,17 +130,34 @@ struct Args {
 }  // namespace
 
 // Owned node (X, Y) = lane (X, Y) sums, in this order, vertex (1,1) of its own
-// element, (0,1) of lane + 1, (1,0) of lane + 8 and (0,0) of lane + 9.
-constexpr int WT = 7;   // owned nodes per wave along x and y
-constexpr int WZ = 11;  // owned node planes per wave (WZ + 1 steps, a multiple of 4)
+// element, (0,1) of lane + 1, (1,0) of lane + LX and (0,0) of lane + LX + 1.
+// Lane layouts of a wave: LX lanes along x times 64 / LX along y.  With 16 lanes along x
+// every load of a plane reads rows of 16 consecutive nodes (one 128-byte line in FP64)
+// instead of 8; it owns 15 x 3 nodes instead of 7 x 7 and wastes more of a small grid
+// on partial tiles, so grids narrower than kWideMinNx nodes use the 8 x 8 layout.
+constexpr int kWideMinNx = 48;
+inline int wave_lx(const Geo& g) { return g.nx >= kWideMinNx ? 16 : 8; }
+constexpr int WZ = 11;  // owned node planes per wave (WZ + 1 steps)
+
+// steps between issuing a slab's loads and using them
+template <typename R>
+constexpr int wave_prefetch() {
+#ifdef MLQ_WAVE_PD
+  return MLQ_WAVE_PD;
+#else
+  return 2;
+#endif
+}
 
 template <typename R>
 __device__ inline R shdn(R v, int d) {
   return __shfl_down(v, d, 64);
 }
 
-template <typename R, typename TC, typename TI, int MODE, int JB = 0>
+template <typename R, typename TC, typename TI, int MODE, int JB, int LX>
 __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
+  constexpr int LY = 64 / LX;
+  constexpr int WTX = LX - 1, WTY = LY - 1;  // owned nodes per wave along x and y
   const Geo& g = A.g;
   // Workgroups go to the 8 XCDs round-robin (linear id mod 8).  Renumber them so
   // that each XCD owns one contiguous range of (sample, tile) blocks: tiles that
@@ -172,15 +189,15 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     t /= A.tiles_x;
     const int ty_i = t % A.tiles_y;
     const int zc = t / A.tiles_y;
-    const int i = lane & 7, j = lane >> 3;
-    const int ex = tx_i * WT - 1 + i, ey = ty_i * WT - 1 + j;  // this lane's element (= its node (0,0))
+    const int i = lane % LX, j = lane / LX;
+    const int ex = tx_i * WTX - 1 + i, ey = ty_i * WTY - 1 + j;  // this lane's element (= its node (0,0))
     const int zs = zc * WZ, ze = min(zs + WZ, g.nz);
     const int64_t plane = (int64_t)g.nx * g.ny;
     const int64_t sbase = (int64_t)sb * g.nn;
     const TC* cf = (const TC*)A.coef + (int64_t)sb * g.P * 2;
     const int ex_n = g.nx - 1, ey_n = g.ny - 1;
     const bool elem_xy = ex >= 0 && ey >= 0 && ex < ex_n && ey < ey_n;
-    const bool owner = i < WT && j < WT && ex + 1 < g.nx && ey + 1 < g.ny;
+    const bool owner = i < WTX && j < WTY && ex + 1 < g.nx && ey + 1 < g.ny;
     // every load below uses an address clamped into the grid, so no lane branches around
     // a load and the compiler can count outstanding loads exactly; values of clamped
     // addresses only ever feed elements or nodes that are discarded
@@ -270,14 +287,10 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     R sj = 0;
     if constexpr (MODE == kPK) sj = (R)A.inv_eta[(int64_t)sb * (A.kmax + 1) + A.j];
 
-    // one slab: planes lo (k) and hi (k + 1) are resident; the loads of plane k + 3,
-    // the coefficients of slab k + 2 and the node inputs of plane k + 2 are issued here
+    // one slab: planes lo (k) and hi (k + 1), its coefficients and the node inputs of
+    // plane k are resident (loaded PD steps earlier)
     R acc_top = 0;
-    auto step = [&](int k, const Pl& lo, const Pl& hi, Pl& ld, R cp, R cq, R& lp, R& lq, R p0, R p1, R& lp0,
-                    R& lp1) {
-      fetch(k + 3, ld);
-      fetch_coef(k + 2, lp, lq);
-      fetch_pre(k + 2, lp0, lp1);
+    auto step = [&](int k, const Pl& lo, const Pl& hi, R cp, R cq, R p0, R p1) {
       const bool slab = k >= 0 && k <= g.nz - 2;
       R o[8];
       {
@@ -294,8 +307,8 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
         }
       }
       // assemble the owned node: bottom faces of slab k (plane k), top faces (plane k + 1)
-      const R bot = o[3] + shdn(o[2], 1) + shdn(o[1], 8) + shdn(o[0], 9);
-      const R top = o[7] + shdn(o[6], 1) + shdn(o[5], 8) + shdn(o[4], 9);
+      const R bot = o[3] + shdn(o[2], 1) + shdn(o[1], LX) + shdn(o[0], LX + 1);
+      const R top = o[7] + shdn(o[6], 1) + shdn(o[5], LX) + shdn(o[4], LX + 1);
       if (owner && k >= zs && k < ze) {
         const uint32_t kk = (uint32_t)k;
         const R sres = acc_top + bot;
@@ -333,26 +346,30 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
       acc_top = top;
     };
 
-    // ring of four plane sets (P), coefficient sets (C) and node-input sets (Q), rotated by
-    // unrolling four steps; a wave covers slabs zs - 1 .. zs + WZ - 1 (16 steps)
+    // The march over slabs zs - 1 .. zs + WZ - 1 is unrolled, so every array below is
+    // indexed by compile-time constants and lives in registers.  Step s consumes planes
+    // s and s + 1, the coefficients and node inputs of s; the loads for step s + PD are
+    // issued at step s.
+    constexpr int NS = WZ + 1;
+    constexpr int PD = wave_prefetch<R>();
     const int k0 = zs - 1;
-    Pl P0, P1, P2, P3;
-    R C0p, C0q, C1p, C1q, C2p, C2q, C3p, C3q;
-    R Q00, Q01, Q10, Q11, Q20, Q21, Q30, Q31;
-    fetch(k0, P0);
-    fetch(k0 + 1, P1);
-    fetch(k0 + 2, P2);
-    fetch_coef(k0, C0p, C0q);
-    fetch_coef(k0 + 1, C1p, C1q);
-    fetch_pre(k0, Q00, Q01);
-    fetch_pre(k0 + 1, Q10, Q11);
+    Pl P[NS + 1];
+    R Cp[NS], Cq[NS], Q0[NS], Q1[NS];
 #pragma unroll
-    for (int it = 0; it < (WZ + 1) / 4; ++it) {
-      const int k = k0 + 4 * it;
-      step(k + 0, P0, P1, P3, C0p, C0q, C2p, C2q, Q00, Q01, Q20, Q21);
-      step(k + 1, P1, P2, P0, C1p, C1q, C3p, C3q, Q10, Q11, Q30, Q31);
-      step(k + 2, P2, P3, P1, C2p, C2q, C0p, C0q, Q20, Q21, Q00, Q01);
-      step(k + 3, P3, P0, P2, C3p, C3q, C1p, C1q, Q30, Q31, Q10, Q11);
+    for (int t = 0; t <= PD; ++t) fetch(k0 + t, P[t]);
+#pragma unroll
+    for (int t = 0; t < PD; ++t) {
+      fetch_coef(k0 + t, Cp[t], Cq[t]);
+      fetch_pre(k0 + t, Q0[t], Q1[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      if (t + PD + 1 <= NS) fetch(k0 + t + PD + 1, P[t + PD + 1]);
+      if (t + PD < NS) {
+        fetch_coef(k0 + t + PD, Cp[t + PD], Cq[t + PD]);
+        fetch_pre(k0 + t + PD, Q0[t + PD], Q1[t + PD]);
+      }
+      step(k0 + t, P[t], P[t + 1], Cp[t], Cq[t], Q0[t], Q1[t]);
     }
     if constexpr (MODE == kPK && JB > 0) {
       // projections w . v_i (i <= j) over the wave's owned nodes: all loads of one
@@ -425,21 +442,30 @@ namespace {
 
 template <typename R>
 void wave_grid_of(const Geo& g, Args<R>& a, int32_t B, dim3& grid) {
-  a.tiles_x = (int)cdiv(g.nx, WT);
-  a.tiles_y = (int)cdiv(g.ny, WT);
+  const int lx = wave_lx(g);
+  a.tiles_x = (int)cdiv(g.nx, lx - 1);
+  a.tiles_y = (int)cdiv(g.ny, 64 / lx - 1);
   a.zchunks = (int)cdiv(g.nz, WZ);
   a.bps = (int)cdiv((int64_t)a.tiles_x * a.tiles_y * a.zchunks, NT / 64);
+  a.npart = a.bps;
   grid = dim3((unsigned)((int64_t)a.bps * B));
+}
+
+template <typename R, typename TC, typename TI, int MODE, int JB = 0>
+void launch_wave3(const Geo& g, Args<R>& a, int32_t B, hipStream_t s) {
+  dim3 grid;
+  wave_grid_of(g, a, B, grid);
+  if (wave_lx(g) == 16)
+    hipLaunchKernelGGL((k_wave3<R, TC, TI, MODE, JB, 16>), grid, dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_wave3<R, TC, TI, MODE, JB, 8>), grid, dim3(NT), 0, s, a);
 }
 
 }  // namespace
 
 int32_t stencil3_blocks(const Geo& g) {
-  return (int32_t)cdiv(cdiv(g.nx, WT) * cdiv(g.ny, WT) * cdiv(g.nz, WZ), NT / 64);
-}
-
-int32_t stencil3_waves(const Geo& g) {
-  return (int32_t)(cdiv(g.nx, WT) * cdiv(g.ny, WT) * cdiv(g.nz, WZ));
+  const int lx = wave_lx(g);
+  return (int32_t)cdiv(cdiv(g.nx, lx - 1) * cdiv(g.ny, 64 / lx - 1) * cdiv(g.nz, WZ), NT / 64);
 }
 
 void launch_apply_pk3(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s, int jb) {
@@ -450,29 +476,24 @@ void launch_apply_pk3(const Geo& g, const Work& w, int j, double ck, int32_t B, 
     a.j = j; a.kmax = w.kmax; a.coef = w.coef; a.y = (T*)w.w; a.ck = ck; a.cm = 0.0; a.active = w.inner_active;
     a.V = (const T*)w.V; a.vs = vs; a.dpart = w.dpart;
   };
-  dim3 grid;
   if (mixed) {
     Args<float> a{};
     fill(a);
-    wave_grid_of(g, a, B, grid);
-    a.npart = a.bps;
     if (jb == 0)
-      hipLaunchKernelGGL((k_wave3<float, float, float, kPK, 0>), grid, dim3(NT), 0, s, a);
+      launch_wave3<float, float, float, kPK, 0>(g, a, B, s);
     else if (jb <= 4)
-      hipLaunchKernelGGL((k_wave3<float, float, float, kPK, 4>), grid, dim3(NT), 0, s, a);
+      launch_wave3<float, float, float, kPK, 4>(g, a, B, s);
     else
-      hipLaunchKernelGGL((k_wave3<float, float, float, kPK, 8>), grid, dim3(NT), 0, s, a);
+      launch_wave3<float, float, float, kPK, 8>(g, a, B, s);
   } else {
     Args<double> a{};
     fill(a);
-    wave_grid_of(g, a, B, grid);
-    a.npart = a.bps;
     if (jb == 0)
-      hipLaunchKernelGGL((k_wave3<double, double, double, kPK, 0>), grid, dim3(NT), 0, s, a);
+      launch_wave3<double, double, double, kPK, 0>(g, a, B, s);
     else if (jb <= 4)
-      hipLaunchKernelGGL((k_wave3<double, double, double, kPK, 4>), grid, dim3(NT), 0, s, a);
+      launch_wave3<double, double, double, kPK, 4>(g, a, B, s);
     else
-      hipLaunchKernelGGL((k_wave3<double, double, double, kPK, 8>), grid, dim3(NT), 0, s, a);
+      launch_wave3<double, double, double, kPK, 8>(g, a, B, s);
   }
 }
 
@@ -481,15 +502,11 @@ void launch_apply_full3(const Geo& g, const void* coef, const void* x, const voi
   if (mixed) {
     Args<float> a{};
     a.g = g; a.x = (const float*)x; a.d = (const float*)d; a.coef = coef; a.y = (float*)y; a.ck = ck; a.cm = 1.0;
-    dim3 grid;
-    wave_grid_of(g, a, B, grid);
-    hipLaunchKernelGGL((k_wave3<float, float, float, kFull>), grid, dim3(NT), 0, s, a);
+    launch_wave3<float, float, float, kFull>(g, a, B, s);
   } else {
     Args<double> a{};
     a.g = g; a.x = (const double*)x; a.d = (const double*)d; a.coef = coef; a.y = (double*)y; a.ck = ck; a.cm = 1.0;
-    dim3 grid;
-    wave_grid_of(g, a, B, grid);
-    hipLaunchKernelGGL((k_wave3<double, double, double, kFull>), grid, dim3(NT), 0, s, a);
+    launch_wave3<double, double, double, kFull>(g, a, B, s);
   }
 }
 
@@ -497,12 +514,10 @@ void launch_residual3(const Geo& g, const Ionic& io, const Work& w, int32_t B, b
   Args<double> a{};
   a.g = g; a.io = io; a.u = w.u; a.bvec = w.b; a.coef = w.coef; a.r0 = w.V; a.dout = w.d; a.part = w.part;
   a.ck = 0.5 * io.dt; a.cm = 1.0; a.active = w.newton_active;
-  dim3 grid;
-  wave_grid_of(g, a, B, grid);
   if (mixed)
-    hipLaunchKernelGGL((k_wave3<double, float, float, kRes>), grid, dim3(NT), 0, s, a);
+    launch_wave3<double, float, float, kRes>(g, a, B, s);
   else
-    hipLaunchKernelGGL((k_wave3<double, double, double, kRes>), grid, dim3(NT), 0, s, a);
+    launch_wave3<double, double, double, kRes>(g, a, B, s);
 }
 
 void launch_rhs3(const Geo& g, const Work& w, const double* fbox, double load_coef, double dt, int32_t B, bool mixed,
@@ -510,12 +525,10 @@ void launch_rhs3(const Geo& g, const Work& w, const double* fbox, double load_co
   Args<double> a{};
   a.g = g; a.u = w.uk; a.coef = w.coef; a.bout = w.b; a.ucopy = w.u; a.fbox = fbox; a.load = load_coef;
   a.ck = -0.5 * dt; a.cm = 1.0; a.active = nullptr;
-  dim3 grid;
-  wave_grid_of(g, a, B, grid);
   if (mixed)
-    hipLaunchKernelGGL((k_wave3<double, float, float, kRhs>), grid, dim3(NT), 0, s, a);
+    launch_wave3<double, float, float, kRhs>(g, a, B, s);
   else
-    hipLaunchKernelGGL((k_wave3<double, double, double, kRhs>), grid, dim3(NT), 0, s, a);
+    launch_wave3<double, double, double, kRhs>(g, a, B, s);
 }
 
 }  // namespace mlq

@@ -5,11 +5,14 @@
 //   K_e[a][b] = |T| ( sigma_t g_a . g_b + (sigma_l - sigma_t) (g_a . f)(g_b . f) ),
 //   f = cos(theta) e_circ + sin(theta) e_long,
 // (eq. (AdmV) with V = sigma_l f; g_a = grad phi_a).  Once per solve its values are
-// gathered per nonzero of the vertex-adjacency CSR (each nonzero sums its element
-// contributions in increasing element order: deterministic, no atomics) into
-// kval[b][nz].  The mass M (P1, |T| (1 + delta_ab) / 20) is shared by all samples.
-// Every operator application is then a row loop over the CSR with one thread per
-// (row, sample); rows of one sample are contiguous, samples on blockIdx.y.
+// gathered per stored entry of the vertex-adjacency pattern (each entry sums its
+// element contributions in increasing element order: deterministic, no atomics) into
+// kval[b][e].  The mass M (P1, |T| (1 + delta_ab) / 20) is shared by all samples.
+// The pattern is stored slot-major and padded to the longest row (entry (s, i) at
+// s * nv + i), so that in every operator application (one thread per (row, sample),
+// rows of one sample contiguous, samples on blockIdx.y) a wave reads the columns,
+// mass and stiffness values of slot s for 64 consecutive rows in one coalesced load.
+// Within a row the slots follow increasing column order.
 #include "mlq_internal.h"
 
 namespace mlq {
@@ -29,11 +32,11 @@ __global__ __launch_bounds__(kBlock) void k_tet_assemble(TetDev t, const T* __re
                                                          double sigma_t, double dsig) {
   const int sb = blockIdx.y;
   const int64_t nz = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (nz >= t.nnz) return;
+  if (nz >= t.nell) return;
   const T* th = theta + (int64_t)sb * t.nt;
   double acc = 0.0;
-  for (int32_t c = t.cptr[nz]; c < t.cptr[nz + 1]; ++c) {
-    const int32_t code = t.cdat[c];
+  for (int32_t c = t.ecptr[nz]; c < t.ecptr[nz + 1]; ++c) {
+    const int32_t code = t.ecdat[c];
     const int64_t e = code >> 4;
     const int a = (code >> 2) & 3, b = code & 3;
     const double* G = t.geo + e * kTetGeo;
@@ -47,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_assemble(TetDev t, const T* __re
     const double bf = gb0 * f0 + gb1 * f1 + gb2 * f2;
     acc += G[18] * (sigma_t * gg + dsig * af * bf);
   }
-  kval[(int64_t)sb * t.nnz + nz] = (T)acc;
+  kval[(int64_t)sb * t.nell + nz] = (T)acc;
 }
 
 // y = M ((1 + d) x) + ck K x
@@ -60,13 +63,14 @@ __global__ __launch_bounds__(kBlock) void k_tet_apply(TetDev t, const T* __restr
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= t.nv) return;
   const T* mv = nullptr;
-  if constexpr (sizeof(T) == 4) mv = (const T*)t.mval32; else mv = (const T*)t.mval;
+  if constexpr (sizeof(T) == 4) mv = (const T*)t.em32; else mv = (const T*)t.em;
   const int64_t so = (int64_t)sb * t.nv;
-  const T* kv = kval + (int64_t)sb * t.nnz;
+  const T* kv = kval + (int64_t)sb * t.nell;
   T acc = 0;
-  for (int32_t nz = t.rowptr[i]; nz < t.rowptr[i + 1]; ++nz) {
-    const int64_t j = so + t.col[nz];
-    acc += (mv[nz] * ((T)1 + d[j]) + ck * kv[nz]) * x[j];
+  for (int32_t sl = 0; sl < t.width; ++sl) {
+    const int64_t e = (int64_t)sl * t.nv + i;
+    const int64_t j = so + t.ecol[e];
+    acc += (mv[e] * ((T)1 + d[j]) + ck * kv[e]) * x[j];
   }
   y[so + i] = acc;
 }
@@ -84,12 +88,13 @@ __global__ __launch_bounds__(kBlock) void k_tet_residual(TetDev t, Ionic io, con
   double n0 = 0.0, n1 = 0.0, n2 = 0.0;
   if (i < t.nv) {
     const int64_t so = (int64_t)sb * t.nv;
-    const TI* kv = kval + (int64_t)sb * t.nnz;
+    const TI* kv = kval + (int64_t)sb * t.nell;
     const double ck = 0.5 * io.dt;
     double G = 0.0;
-    for (int32_t nz = t.rowptr[i]; nz < t.rowptr[i + 1]; ++nz) {
-      const double uj = u[so + t.col[nz]];
-      G += t.mval[nz] * (uj + io.dt * tet_iion(uj, io)) + ck * (double)kv[nz] * uj;
+    for (int32_t sl = 0; sl < t.width; ++sl) {
+      const int64_t e = (int64_t)sl * t.nv + i;
+      const double uj = u[so + t.ecol[e]];
+      G += t.em[e] * (uj + io.dt * tet_iion(uj, io)) + ck * (double)kv[e] * uj;
     }
     const double b = bv[so + i];
     const double F = G - b;
@@ -137,11 +142,12 @@ __global__ __launch_bounds__(kBlock) void k_tet_rhs(TetDev t, const TI* __restri
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= t.nv) return;
   const int64_t so = (int64_t)sb * t.nv;
-  const TI* kv = kval + (int64_t)sb * t.nnz;
+  const TI* kv = kval + (int64_t)sb * t.nell;
   double acc = 0.0;
-  for (int32_t nz = t.rowptr[i]; nz < t.rowptr[i + 1]; ++nz) {
-    const double uj = uk[so + t.col[nz]];
-    acc += (t.mval[nz] - ck * (double)kv[nz]) * uj;
+  for (int32_t sl = 0; sl < t.width; ++sl) {
+    const int64_t e = (int64_t)sl * t.nv + i;
+    const double uj = uk[so + t.ecol[e]];
+    acc += (t.em[e] - ck * (double)kv[e]) * uj;
   }
   bout[so + i] = acc + load * fload[i];
   ucopy[so + i] = uk[so + i];
@@ -190,7 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_update(TetDev t, const T* __rest
 
 void launch_tet_assemble(const TetDev& t, const void* theta, void* kval, int32_t B, double sigma_t, double dsig,
                          bool mixed, hipStream_t s) {
-  const dim3 grid((unsigned)cdiv(t.nnz, kBlock), B);
+  const dim3 grid((unsigned)cdiv(t.nell, kBlock), B);
   if (mixed)
     hipLaunchKernelGGL((k_tet_assemble<float>), grid, dim3(kBlock), 0, s, t, (const float*)theta, (float*)kval,
                        sigma_t, dsig);

@@ -68,6 +68,10 @@ std::string tet_build(const mlq_level_desc* d, TetHost& h, bool values) {
   }
   h.nnz = (int64_t)h.col.size();
   h.nc = 16 * nt;
+  h.width = 0;
+  for (int64_t v = 0; v < nv; ++v) h.width = std::max(h.width, h.rowptr[v + 1] - h.rowptr[v]);
+  h.nell = (int64_t)h.width * nv;
+  if (h.nell > (int64_t)INT32_MAX) return "too many padded nonzeros for 32-bit indices";
   if (!values) return "";
   // element geometry: gradients (rows of inverse edge matrix), frame, volume
   h.geo.assign((size_t)nt * kTetGeo, 0.0);
@@ -130,6 +134,28 @@ std::string tet_build(const mlq_level_desc* d, TetHost& h, bool values) {
     }
     if (pass == 0)
       for (int64_t nz = 0; nz < h.nnz; ++nz) h.cptr[nz + 1] += h.cptr[nz];
+  }
+  // slot-major padded rows: entry (slot s, row v) at s * nv + v; a padded slot points at the
+  // row itself with a zero value and no contributions
+  h.ecol.assign(h.nell, 0);
+  h.em.assign(h.nell, 0.0);
+  h.ecptr.assign(h.nell + 1, 0);
+  h.ecdat.assign(h.nc, 0);
+  {
+    int64_t c = 0;
+    for (int32_t sl = 0; sl < h.width; ++sl)
+      for (int64_t v = 0; v < nv; ++v) {
+        const int64_t idx = (int64_t)sl * nv + v;
+        if (sl < h.rowptr[v + 1] - h.rowptr[v]) {
+          const int64_t nz = h.rowptr[v] + sl;
+          h.ecol[idx] = h.col[nz];
+          h.em[idx] = h.mval[nz];
+          for (int32_t q = h.cptr[nz]; q < h.cptr[nz + 1]; ++q) h.ecdat[c++] = h.cdat[q];
+        } else {
+          h.ecol[idx] = (int32_t)v;
+        }
+        h.ecptr[idx + 1] = (int32_t)c;
+      }
   }
   h.mdiag.assign(nv, 0.0);
   h.wts.assign(nv, 0.0);

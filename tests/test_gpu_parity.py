@@ -44,6 +44,8 @@ def _oracle_apply(mesh, theta, x, d, phys, dt):
 @pytest.mark.parametrize("dim,n,mixed", [
     (3, [9, 7, 5], False), (3, [17, 17, 17], False), (2, [33, 33], False), (2, [13, 30], False),
     (3, [9, 7, 5], True), (3, [17, 17, 17], True), (2, [33, 33], True),
+    # x-extent >= 48: the 16 x 4 lane layout of the 3D kernels, ragged in every direction
+    (3, [49, 7, 5], False), (3, [61, 11, 13], True), (3, [64, 4, 12], False),
 ])
 def test_apply_matches_assembled_jacobian(env, dim, n, mixed):
     torch, mlq = env
@@ -132,6 +134,17 @@ def test_solve_fp64_ragged_3d_truncated(env):
     """A ragged box spanning several blocks, stopped after 6 of 64 steps."""
     torch, mlq = env
     out, refs, mesh = _solve_pair(env, 3, [19, 13, 11], 64, 2, W.QOI_MEAN_U_FINAL, W.PREC_FP64, stop=6)
+    u = out["u"].cpu().numpy()
+    for b, r in enumerate(refs):
+        assert np.abs(u[b] - r["u"]).max() <= 1e-10 * np.abs(r["u"]).max()
+
+
+def test_solve_fp64_ragged_wide_3d_truncated(env):
+    """A box wide enough in x for the 16 x 4 lane layout (ragged tiles in x, y and z), with
+    the fused projections of the apply kernel, stopped after 5 of 64 steps."""
+    torch, mlq = env
+    out, refs, mesh = _solve_pair(env, 3, [53, 8, 6], 64, 2, W.QOI_MEAN_U_FINAL, W.PREC_FP64, stop=5)
+    assert int(out["status"].abs().sum()) == 0
     u = out["u"].cpu().numpy()
     for b, r in enumerate(refs):
         assert np.abs(u[b] - r["u"]).max() <= 1e-10 * np.abs(r["u"]).max()
