@@ -123,7 +123,9 @@ void mlq_destroy_level(mlq_level* level);
 /* Level geometry: nodes n and elements P per sample. */
 mlq_status mlq_level_sizes(const mlq_level* level, int64_t* n_nodes, int64_t* n_elems);
 
-/* Workspace bytes for one mlq_solve_batch call with `batch` samples. */
+/* Workspace bytes for one mlq_solve_batch call with `batch` samples: per sample and
+ * node four FP64 state vectors, and in the inner precision the GMRES basis (max_inner + 1
+ * vectors), on boxes the preconditioned basis (max_inner vectors), and three more. */
 mlq_status mlq_workspace_bytes(const mlq_level* level, int32_t batch, size_t* ws_bytes);
 
 /* KL synthesis, eq. (KLlowrank) at the level's element centres:

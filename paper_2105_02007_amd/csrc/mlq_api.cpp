@@ -77,14 +77,18 @@ struct mlq_level {
   bool tet = false;     // P1 tetrahedra
   TetDev td{};          // their device data (inside the blob)
   int nmax = 0;
-  // pinned host flags
+  // pinned host flags: [0] Newton-active count as read, [1] the count entering the
+  // current GMRES solve, [kFlagInner + j] GMRES-active count after iteration j (read
+  // one iteration behind the launches)
   int32_t* host_flags = nullptr;
+  hipEvent_t flag_ev[2] = {nullptr, nullptr};
   // kernel timing
   uint32_t tmask = 0;
   mlq_timing tim{};
   struct Pending {
     int cls;
-    double units, bytes;
+    double units, bytes, bytes_fixed;
+    const int32_t* count;  // host count of active samples the per-sample figures scale with
     hipEvent_t a, b;
   };
   std::vector<Pending> pending;
@@ -92,6 +96,8 @@ struct mlq_level {
 };
 
 namespace {
+
+constexpr int kFlagInner = 8;  // first host flag slot of the GMRES-active counts
 
 hipEvent_t take_event(mlq_level* lv) {
   if (!lv->free_events.empty()) {
@@ -104,9 +110,12 @@ hipEvent_t take_event(mlq_level* lv) {
   return e;
 }
 
-// Brackets one launch with events when its class is timed.
+// Brackets one launch with events when its class is timed.  units and bytes are totals,
+// or, with count set, per active sample: the launch's figures are then resolved when the
+// count (a pinned host slot filled by an asynchronous copy) is known, at harvest.
 template <typename F>
-void timed(mlq_level* lv, int cls, double units, hipStream_t s, F&& launch, double bytes = 0.0) {
+void timed(mlq_level* lv, int cls, double units, hipStream_t s, F&& launch, double bytes = 0.0,
+           const int32_t* count = nullptr, double bytes_fixed = 0.0) {
   if (!(lv->tmask & (1u << cls))) {
     launch();
     return;
@@ -119,7 +128,7 @@ void timed(mlq_level* lv, int cls, double units, hipStream_t s, F&& launch, doub
   (void)hipEventRecord(a, s);
   launch();
   (void)hipEventRecord(b, s);
-  lv->pending.push_back({cls, units, bytes, a, b});
+  lv->pending.push_back({cls, units, bytes, bytes_fixed, count, a, b});
 }
 
 // After a stream synchronisation: fold finished event pairs into the totals.
@@ -127,10 +136,11 @@ void harvest(mlq_level* lv) {
   for (auto& p : lv->pending) {
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      const double n = p.count != nullptr ? (double)*p.count : 1.0;
       lv->tim.ms[p.cls] += ms;
       lv->tim.launches[p.cls] += 1;
-      lv->tim.units[p.cls] += p.units;
-      lv->tim.bytes[p.cls] += p.bytes;
+      lv->tim.units[p.cls] += p.units * n;
+      lv->tim.bytes[p.cls] += p.bytes * n + p.bytes_fixed;
     }
     lv->free_events.push_back(p.a);
     lv->free_events.push_back(p.b);
@@ -253,7 +263,7 @@ Work carve_workspace(void* base, const Geo& geo, int32_t B, int kmax, bool mixed
   w.b = (double*)take(vn * sizeof(double));
   w.act = (double*)take(vn * sizeof(double));
   w.d = take(vn * ti);
-  w.z = take(vn * ti);
+  w.z = take(vn * ti * (geo.tet ? 1 : kmax));
   w.w = take(vn * ti);
   w.V = take(vn * ti * (kmax + 1));
   // box: per element (p, q); tetrahedra: per-sample stiffness values of the CSR
@@ -527,7 +537,9 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   if (e == hipSuccess) e = hipMemcpyAsync(lv->fbox, fbox.data(), sizeof(double) * nn, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(lv->wts, wts.data(), sizeof(double) * nn, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&lv->host_flags, 64, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&lv->host_flags, sizeof(int32_t) * (kFlagInner + kMaxInner + 1), hipHostMallocDefault);
+  for (int q = 0; q < 2 && e == hipSuccess; ++q) e = hipEventCreateWithFlags(&lv->flag_ev[q], hipEventDisableTiming);
   if (e != hipSuccess) return cleanup(fail(MLQ_EHIP, "level upload failed: %s", hipGetErrorString(e)));
   *out = lv;
   return MLQ_OK;
@@ -540,6 +552,8 @@ void mlq_destroy_level(mlq_level* level) {
     (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : level->free_events) (void)hipEventDestroy(e);
+  for (hipEvent_t e : level->flag_ev)
+    if (e) (void)hipEventDestroy(e);
   if (level->host_flags) (void)hipHostFree(level->host_flags);
   delete level;
 }
@@ -676,27 +690,31 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
         launch_mark_failed(w, batch, s);
         break;
       }
-      int32_t inner = active;
+      // active samples entering iteration j: the Newton count for j = 0, else the host
+      // slot of iteration j - 1 (filled by then whenever the launch figures are harvested)
+      int32_t* const cnt = level->host_flags + kFlagInner;
+      level->host_flags[1] = active;  // slot 0 is refilled by the next Newton check before harvest
+      auto entering = [&](int j) -> const int32_t* { return j == 0 ? &level->host_flags[1] : &cnt[j - 1]; };
       for (int j = 0; j < kmax; ++j) {
-        const double units = nn * inner;
-        timed(level, MLQ_K_PRECOND, units, s, [&] {
+        const int32_t* nin = entering(j);
+        timed(level, MLQ_K_PRECOND, nn, s, [&] {
           if (tet)
             launch_tet_jacobi_basis(td, w, j, batch, mixed, s);
           else
             launch_minv_basis(g, w, level->tri, level->nmax, j, batch, mixed, s);
-        });
+        }, 0.0, nin);
         // 3D boxes, j < 8: the apply kernel also forms the projections w . v_i (i <= j)
         const bool fuse = g.dim == 3 && !tet && j < 8;
         const double ti = mixed ? 4.0 : 8.0;
-        // algorithmic bytes.  Boxes: z, v_j, the element coefficients (p, q) read, w written;
-        // fused: v_0..v_{j-1} read.  Tetrahedra: per row and sample the stiffness values of its
-        // slots, z and d read, w written; the shared pattern (columns, mass) once per launch.
+        // algorithmic bytes per active sample.  Boxes: z, v_j, the element coefficients
+        // (p, q) read, w written; fused: v_0..v_{j-1} read.  Tetrahedra: per row the
+        // stiffness values of its slots, z and d read, w written; the shared pattern
+        // (columns, mass) once per launch.
         const double slots = tet ? (double)td.nell / (double)td.nv : 0.0;
-        const double apply_bytes =
-            tet ? units * (ti * (slots + 3.0)) + (double)td.nell * (4.0 + ti)
-                : units * ti * (5.0 + (fuse ? j : 0));
+        const double apply_bytes = nn * ti * (tet ? slots + 3.0 : 5.0 + (fuse ? j : 0));
+        const double apply_fixed = tet ? (double)td.nell * (4.0 + ti) : 0.0;
         timed(
-            level, MLQ_K_APPLY, units, s,
+            level, MLQ_K_APPLY, nn, s,
             [&] {
               if (tet)  // Jacobi preconditioning: the operator is the full Jacobian applied to z
                 launch_tet_apply(td, w.coef, w.z, w.d, w.w, 0.5 * dt, batch, w.inner_active, mixed, s);
@@ -705,24 +723,30 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
               else
                 launch_apply_pk(g, w, j, 0.5 * dt, batch, mixed, s);
             },
-            apply_bytes);
-        if (!fuse) timed(level, MLQ_K_DOTS, units, s, [&] { launch_dots(g, w, j, batch, mixed, s); });
-        timed(level, MLQ_K_ORTH, units, s,
-              [&] { launch_orth(g, w, j, batch, mixed, s, fuse ? w.nwav : w.nred); });
+            apply_bytes, nin, apply_fixed);
+        if (!fuse) timed(level, MLQ_K_DOTS, nn, s, [&] { launch_dots(g, w, j, batch, mixed, s); }, 0.0, nin);
+        timed(level, MLQ_K_ORTH, nn, s,
+              [&] { launch_orth(g, w, j, batch, mixed, s, fuse ? w.nwav : w.nred); }, 0.0, nin);
         timed(level, MLQ_K_SMALL, 0.0, s, [&] {
-          launch_givens(g, w, j, batch, d.inner_tol, s);
-          launch_count(w.inner_active, batch, w.counter, s);
+          launch_givens(g, w, j, batch, d.inner_tol, s, w.nred);
+          launch_count(w.inner_active, batch, w.counter + 1 + (j & 1), s);
         });
-        st = read_counter(level, w, s, &inner);
-        if (st != MLQ_OK) return st;
-        if (inner == 0) break;
+        // The count of iteration j is read while iteration j + 1 is already queued, so
+        // the GPU does not idle during the host round trip; an iteration queued after
+        // every sample has stopped finds no active sample and does nothing.
+        HIP_OK(hipMemcpyAsync(&cnt[j], w.counter + 1 + (j & 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipEventRecord(level->flag_ev[j & 1], s));
+        if (j > 0) {
+          HIP_OK(hipEventSynchronize(level->flag_ev[(j - 1) & 1]));
+          if (cnt[j - 1] == 0) break;
+        }
       }
       timed(level, MLQ_K_UPDATE, nn * active, s, [&] {
-        launch_solve_y(w, batch, s);
+        launch_solve_y(w, batch, tet, s);
         if (tet)
           launch_tet_update(td, w, batch, mixed, s);
         else
-          launch_update_pm(g, w, level->tri, level->nmax, batch, mixed, s);
+          launch_update_zbasis(g, w, batch, mixed, s);
       });
     }
     timed(level, MLQ_K_QOI, nn * batch, s, [&] { launch_activation(w, level->nn, batch, d.u_th, t0, dt, s); });

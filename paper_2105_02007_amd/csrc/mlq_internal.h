@@ -83,7 +83,8 @@ struct Work {
   double* act;   // activation times (-1: not yet activated)
   // inner precision per-node vectors, [B][n]
   void* d;       // dt * I_ion'(u)
-  void* z;       // preconditioned basis vector
+  void* z;       // boxes: preconditioned basis z_j = P^-1 v_j inv_eta_j, kmax vectors of [B][n];
+                 // tetrahedra: one vector
   void* w;       // operator output
   void* V;       // GMRES basis, (kmax + 1) vectors of [B][n]
   // per element coefficients [B][P][2] (inner precision)
@@ -127,8 +128,8 @@ void launch_newton_check(const Geo& g, const Work& w, int32_t B, double tol, hip
 void launch_count(const int32_t* flags, int32_t B, int32_t* out, hipStream_t s);
 void launch_dots(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s);
 void launch_orth(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s, int32_t npart);
-void launch_givens(const Geo& g, const Work& w, int j, int32_t B, double tol, hipStream_t s);
-void launch_solve_y(const Work& w, int32_t B, hipStream_t s);
+void launch_givens(const Geo& g, const Work& w, int j, int32_t B, double tol, hipStream_t s, int32_t nparts);
+void launch_solve_y(const Work& w, int32_t B, bool scaled, hipStream_t s);
 void launch_activation(const Work& w, int64_t nn, int32_t B, double u_th, double t_k, double dt,
                        hipStream_t s);
 void launch_qoi(const Work& w, const double* wts, int64_t nn, int32_t B, int qoi, double t_stop,
@@ -157,7 +158,7 @@ mlq_status kl_transfer_tet(const mlq_kl_desc* kd, const double* psi_dev, int64_t
 void launch_minv_basis(const Geo& g, const Work& w, const void* tri, int nmax, int j, int32_t B, bool mixed,
                        hipStream_t s);
 void launch_apply_pk(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s);
-void launch_update_pm(const Geo& g, const Work& w, const void* tri, int nmax, int32_t B, bool mixed, hipStream_t s);
+void launch_update_zbasis(const Geo& g, const Work& w, int32_t B, bool mixed, hipStream_t s);
 hipError_t prepare_minv_kernels(size_t bytes);
 int32_t stencil3_blocks(const Geo& g);
 // jb > 0: also accumulate the Gram-Schmidt projections w . v_i (i <= j < jb) into dpart,

@@ -605,16 +605,17 @@ __global__ __launch_bounds__(kBlock) void k_givens(const double* __restrict__ pa
   }
 }
 
-void launch_givens(const Geo& g, const Work& w, int j, int32_t B, double tol, hipStream_t s) {
+void launch_givens(const Geo& g, const Work& w, int j, int32_t B, double tol, hipStream_t s, int32_t nparts) {
   (void)g;
-  hipLaunchKernelGGL(k_givens, dim3(B), dim3(kBlock), 0, s, w.part, w.nred, j, w.kmax, tol, w.H, w.cs, w.sn, w.g,
+  hipLaunchKernelGGL(k_givens, dim3(B), dim3(kBlock), 0, s, w.part, nparts, j, w.kmax, tol, w.H, w.cs, w.sn, w.g,
                      w.inv_eta, w.beta, w.inner_active, w.inner_k);
 }
 
-// Back substitution R y = g on the rotated Hessenberg matrix; stores y_i inv_eta_i.
+// Back substitution R y = g on the rotated Hessenberg matrix; stores y_i, times inv_eta_i
+// when scaled (the combination then runs over the unnormalised basis v_i).
 __global__ void k_solve_y(int32_t B, int kmax, const double* __restrict__ H, const double* __restrict__ gv,
                           const double* __restrict__ inv_eta, const int32_t* __restrict__ newton_active,
-                          const int32_t* __restrict__ inner_k, double* y, int64_t* iters) {
+                          const int32_t* __restrict__ inner_k, double* y, int64_t* iters, int scaled) {
   const int sb = blockIdx.x * blockDim.x + threadIdx.x;
   if (sb >= B || newton_active[sb] == 0) return;
   const int k = inner_k[sb];
@@ -628,12 +629,13 @@ __global__ void k_solve_y(int32_t B, int kmax, const double* __restrict__ H, con
     for (int l = i + 1; l < k; ++l) v -= Hs[i * kmax + l] * ys[l];
     ys[i] = Hs[i * kmax + i] != 0.0 ? v / Hs[i * kmax + i] : 0.0;
   }
-  for (int i = 0; i < k; ++i) ys[i] *= inv_eta[(int64_t)sb * (kmax + 1) + i];
+  if (scaled)
+    for (int i = 0; i < k; ++i) ys[i] *= inv_eta[(int64_t)sb * (kmax + 1) + i];
 }
 
-void launch_solve_y(const Work& w, int32_t B, hipStream_t s) {
+void launch_solve_y(const Work& w, int32_t B, bool scaled, hipStream_t s) {
   hipLaunchKernelGGL(k_solve_y, dim3((unsigned)cdiv(B, 64)), dim3(64), 0, s, B, w.kmax, w.H, w.g, w.inv_eta,
-                     w.newton_active, w.inner_k, w.y, w.iters);
+                     w.newton_active, w.inner_k, w.y, w.iters, scaled ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -956,7 +958,7 @@ __device__ inline void line_solve(T* a, int n, int64_t stride, const T* __restri
   }
 }
 
-enum { kOutPlain = 0, kOutDivD = 1, kOutAddU = 2 };
+enum { kOutDivD = 1 };
 
 __device__ inline double minv_scale(const double* __restrict__ inv_eta, int sb, int j, int kmax, double c6) {
   return c6 * (inv_eta != nullptr ? inv_eta[(int64_t)sb * (kmax + 1) + j] : 1.0);
@@ -998,17 +1000,15 @@ __global__ __launch_bounds__(kBlock) void k_line_z(Geo g, const T* __restrict__ 
 }
 
 // x and y lines of one z-plane (blockIdx.x) of one sample (blockIdx.y) in LDS, then
-// the output: divided by (1 + d), or added (divided by 1 + d) to u in FP64.
-// The input is scaled by c6 inv_eta_j (inv_eta != nullptr) or c6.
-// N: nx = ny when it is one of the unrolled sizes (each line solved in registers by
-// one thread), else 0 (runtime size, chunked solves).  d (and u) are fetched after
+// the output divided by (1 + d).  The input is scaled by c6 inv_eta_j (inv_eta !=
+// nullptr) or c6.  N: nx = ny when it is one of the unrolled sizes (each line solved in
+// registers by one thread), else 0 (runtime size, chunked solves).  d is fetched after
 // the sweeps, so the sweeps hold no prefetched registers.
 template <typename T, int OUT, int N>
 __global__ __launch_bounds__(kBlock) void k_plane_xy(Geo g, const T* __restrict__ in, T* __restrict__ out,
                                                      const double* __restrict__ inv_eta, int j, int kmax, double c6,
                                                      const T* __restrict__ ivx, const T* __restrict__ ivy,
-                                                     const T* __restrict__ d, double* __restrict__ u,
-                                                     const int32_t* __restrict__ active) {
+                                                     const T* __restrict__ d, const int32_t* __restrict__ active) {
   extern __shared__ unsigned char smem_raw[];
   T* sh = reinterpret_cast<T*>(smem_raw);
   const int sb = blockIdx.y;
@@ -1058,32 +1058,23 @@ __global__ __launch_bounds__(kBlock) void k_plane_xy(Geo g, const T* __restrict_
   __syncthreads();
   for (int b0 = 0; b0 < np; b0 += PB * kBlock) {
     T dv[PB];
-    double uv[PB];
 #pragma unroll
     for (int q = 0; q < PB; ++q)
-      if (b0 + t0 + q * kBlock < np) {
-        dv[q] = d[base + b0 + t0 + q * kBlock];
-        if constexpr (OUT == kOutAddU) uv[q] = u[base + b0 + t0 + q * kBlock];
-      }
+      if (b0 + t0 + q * kBlock < np) dv[q] = d[base + b0 + t0 + q * kBlock];
 #pragma unroll
     for (int q = 0; q < PB; ++q)
       if (b0 + t0 + q * kBlock < np) {
         const int64_t o = base + b0 + t0 + q * kBlock;
-        const T v = sh[b0 + t0 + q * kBlock] / ((T)1 + dv[q]);
-        if constexpr (OUT == kOutDivD)
-          out[o] = v;
-        else
-          u[o] = uv[q] + (double)v;
+        out[o] = sh[b0 + t0 + q * kBlock] / ((T)1 + dv[q]);
       }
   }
 }
 
-// dst (or u) <- P^-1 (scale src); tmp holds the z-solved field in 3D.
+// dst <- P^-1 (scale src); tmp holds the z-solved field in 3D.
 // N: common line length of all axes when it is one of the unrolled sizes, else 0.
 template <typename T, int N>
 static void minv_launch(const Geo& g, const T* src, T* tmp, T* dst, const double* inv_eta, int j, int kmax,
-                        const T* tri, int nmax, const T* d, double* u, bool add_u, const int32_t* active, int32_t B,
-                        hipStream_t s) {
+                        const T* tri, int nmax, const T* d, const int32_t* active, int32_t B, hipStream_t s) {
   const T* ivx = tri;
   const T* ivy = tri + nmax;
   const T* ivz = tri + 2 * nmax;
@@ -1100,23 +1091,18 @@ static void minv_launch(const Geo& g, const T* src, T* tmp, T* dst, const double
     c6 = 1.0;
     planes = (unsigned)g.nz;
   }
-  if (add_u)
-    hipLaunchKernelGGL((k_plane_xy<T, kOutAddU, N>), dim3(planes, B), dim3(kBlock), sh, s, g, pin, dst, peta, j, kmax,
-                       c6, ivx, ivy, d, u, active);
-  else
-    hipLaunchKernelGGL((k_plane_xy<T, kOutDivD, N>), dim3(planes, B), dim3(kBlock), sh, s, g, pin, dst, peta, j, kmax,
-                       c6, ivx, ivy, d, u, active);
+  hipLaunchKernelGGL((k_plane_xy<T, kOutDivD, N>), dim3(planes, B), dim3(kBlock), sh, s, g, pin, dst, peta, j, kmax,
+                     c6, ivx, ivy, d, active);
 }
 
 template <typename T>
 static void minv_dispatch(const Geo& g, const T* src, T* tmp, T* dst, const double* inv_eta, int j, int kmax,
-                          const T* tri, int nmax, const T* d, double* u, bool add_u, const int32_t* active,
-                          int32_t B, hipStream_t s) {
+                          const T* tri, int nmax, const T* d, const int32_t* active, int32_t B, hipStream_t s) {
   const bool cube = g.nx == g.ny && (g.dim == 2 || g.nz == g.nx);
   int n = cube ? g.nx : 0;
   // both passes hold whole lines in registers (FP64 lines of 129 run at one wave per
   // SIMD, which the 133 KB LDS plane of the xy pass imposes anyway)
-#define MLQ_MINV(NN) minv_launch<T, NN>(g, src, tmp, dst, inv_eta, j, kmax, tri, nmax, d, u, add_u, active, B, s)
+#define MLQ_MINV(NN) minv_launch<T, NN>(g, src, tmp, dst, inv_eta, j, kmax, tri, nmax, d, active, B, s)
   switch (n) {
     case 9: MLQ_MINV(9); break;
     case 17: MLQ_MINV(17); break;
@@ -1128,16 +1114,17 @@ static void minv_dispatch(const Geo& g, const T* src, T* tmp, T* dst, const doub
 #undef MLQ_MINV
 }
 
-// GMRES preconditioner step: z = P^-1 v_j (v_j = stored basis vector times inv_eta_j); w is scratch.
+// GMRES preconditioner step: z_j = P^-1 v_j (v_j = stored basis vector times inv_eta_j),
+// kept as vector j of the preconditioned basis; w is scratch.
 void launch_minv_basis(const Geo& g, const Work& w, const void* tri, int nmax, int j, int32_t B, bool mixed,
                        hipStream_t s) {
   const size_t vs = (size_t)g.nn * B;
   if (mixed)
-    minv_dispatch<float>(g, (const float*)w.V + j * vs, (float*)w.w, (float*)w.z, w.inv_eta, j, w.kmax,
-                         (const float*)tri, nmax, (const float*)w.d, nullptr, false, w.inner_active, B, s);
+    minv_dispatch<float>(g, (const float*)w.V + j * vs, (float*)w.w, (float*)w.z + j * vs, w.inv_eta, j, w.kmax,
+                         (const float*)tri, nmax, (const float*)w.d, w.inner_active, B, s);
   else
-    minv_dispatch<double>(g, (const double*)w.V + j * vs, (double*)w.w, (double*)w.z, w.inv_eta, j, w.kmax,
-                          (const double*)tri, nmax, (const double*)w.d, nullptr, false, w.inner_active, B, s);
+    minv_dispatch<double>(g, (const double*)w.V + j * vs, (double*)w.w, (double*)w.z + j * vs, w.inv_eta, j, w.kmax,
+                          (const double*)tri, nmax, (const double*)w.d, w.inner_active, B, s);
 }
 
 // Preconditioned operator: w = v_j + dt/2 K_G z  (the mass part of J P^-1 is the identity).
@@ -1173,7 +1160,7 @@ void launch_apply_pk(const Geo& g, const Work& w, int j, double ck, int32_t B, b
   const dim3 grid((unsigned)w.nblk, B);
   const size_t vs = (size_t)g.nn * B;
 #define MLQ_APK(D, T)                                                                                         \
-  hipLaunchKernelGGL((k_apply_pk<D, T>), grid, dim3(kBlock), 0, s, g, (const T*)w.z, (const T*)w.V + j * vs, \
+  hipLaunchKernelGGL((k_apply_pk<D, T>), grid, dim3(kBlock), 0, s, g, (const T*)w.z + j * vs, (const T*)w.V + j * vs, \
                      w.inv_eta, j, w.kmax, (const T*)w.coef, (T*)w.w, (T)ck, w.inner_active)
   if (g.dim == 3) {
     if (mixed) MLQ_APK(3, float); else MLQ_APK(3, double);
@@ -1184,10 +1171,12 @@ void launch_apply_pk(const Geo& g, const Work& w, int j, double ck, int32_t B, b
 }
 
 // Newton update, right preconditioning: u += P^-1 (sum_l y_l v_l).
+// Newton update with right preconditioning on boxes: u += sum_l y_l z_l over the
+// preconditioned basis (z_l = P^-1 v_l inv_eta_l, y_l from k_solve_y unscaled).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_combine_basis(int64_t nn, const T* __restrict__ V, size_t vs,
+__global__ __launch_bounds__(kBlock) void k_update_zbasis(int64_t nn, const T* __restrict__ Z, size_t vs,
                                                           const double* __restrict__ y, int kmax,
-                                                          const int32_t* __restrict__ inner_k, T* __restrict__ out,
+                                                          const int32_t* __restrict__ inner_k, double* __restrict__ u,
                                                           const int32_t* __restrict__ active) {
   const int sb = blockIdx.y;
   if (active[sb] == 0) return;
@@ -1199,24 +1188,19 @@ __global__ __launch_bounds__(kBlock) void k_combine_basis(int64_t nn, const T* _
   if (i >= nn) return;
   const int64_t o = (int64_t)sb * nn + i;
   double acc = 0.0;
-  for (int l = 0; l < k; ++l) acc += c[l] * (double)V[l * vs + o];
-  out[o] = (T)acc;
+  for (int l = 0; l < k; ++l) acc += c[l] * (double)Z[l * vs + o];
+  u[o] += acc;
 }
 
-void launch_update_pm(const Geo& g, const Work& w, const void* tri, int nmax, int32_t B, bool mixed, hipStream_t s) {
+void launch_update_zbasis(const Geo& g, const Work& w, int32_t B, bool mixed, hipStream_t s) {
   const dim3 grid((unsigned)w.nblk, B);
   const size_t vs = (size_t)g.nn * B;
-  if (mixed) {
-    hipLaunchKernelGGL((k_combine_basis<float>), grid, dim3(kBlock), 0, s, g.nn, (const float*)w.V, vs, w.y, w.kmax,
-                       w.inner_k, (float*)w.w, w.newton_active);
-    minv_dispatch<float>(g, (const float*)w.w, (float*)w.z, (float*)w.z, nullptr, 0, w.kmax, (const float*)tri, nmax,
-                         (const float*)w.d, w.u, true, w.newton_active, B, s);
-  } else {
-    hipLaunchKernelGGL((k_combine_basis<double>), grid, dim3(kBlock), 0, s, g.nn, (const double*)w.V, vs, w.y,
-                       w.kmax, w.inner_k, (double*)w.w, w.newton_active);
-    minv_dispatch<double>(g, (const double*)w.w, (double*)w.z, (double*)w.z, nullptr, 0, w.kmax, (const double*)tri,
-                          nmax, (const double*)w.d, w.u, true, w.newton_active, B, s);
-  }
+  if (mixed)
+    hipLaunchKernelGGL((k_update_zbasis<float>), grid, dim3(kBlock), 0, s, g.nn, (const float*)w.z, vs, w.y, w.kmax,
+                       w.inner_k, w.u, w.newton_active);
+  else
+    hipLaunchKernelGGL((k_update_zbasis<double>), grid, dim3(kBlock), 0, s, g.nn, (const double*)w.z, vs, w.y,
+                       w.kmax, w.inner_k, w.u, w.newton_active);
 }
 
 }  // namespace mlq
@@ -1234,13 +1218,9 @@ hipError_t prepare_minv_kernels(size_t bytes) {
     if (e == hipSuccess) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, b);
   };
   set((const void*)(k_plane_xy<double, kOutDivD, 0>));
-  set((const void*)(k_plane_xy<double, kOutAddU, 0>));
   set((const void*)(k_plane_xy<float, kOutDivD, 0>));
-  set((const void*)(k_plane_xy<float, kOutAddU, 0>));
   set((const void*)(k_plane_xy<float, kOutDivD, 129>));
-  set((const void*)(k_plane_xy<float, kOutAddU, 129>));
   set((const void*)(k_plane_xy<double, kOutDivD, 129>));
-  set((const void*)(k_plane_xy<double, kOutAddU, 129>));
   return e;
 }
 

@@ -319,8 +319,10 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
           const R wv = p0 * sj + sres;
           put(A.y + sbase, ob + kk * pbR, wv);
           if constexpr (JB > 0) {
-            // kept for the projections after the march (the ring loop is unrolled, so
-            // k - zs is a compile-time index here)
+            // w . v_j at once (p0 is v_j here); w is kept for the projections on v_0 ..
+            // v_{j-1} after the march (the march is unrolled, so k - zs is a
+            // compile-time index)
+            dacc[0] += (double)wv * (double)p0;
             const int q = k - zs;
 #pragma unroll
             for (int t = 0; t < WZ; ++t)
@@ -372,13 +374,13 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
       step(k0 + t, P[t], P[t + 1], Cp[t], Cq[t], Q0[t], Q1[t]);
     }
     if constexpr (MODE == kPK && JB > 0) {
-      // projections w . v_i (i <= j) over the wave's owned nodes: all loads of one
-      // basis vector are issued together (addresses clamped into the grid; wk is 0
-      // wherever the node is not owned)
+      // projections w . v_i (i < j) over the wave's owned nodes, into dacc[i + 1]: all
+      // loads of one basis vector are issued together (addresses clamped into the grid;
+      // wk is 0 wherever the node is not owned)
       if (owner) {
 #pragma unroll
-        for (int i = 0; i < JB; ++i) {
-          if (i > A.j) break;
+        for (int i = 0; i + 1 < JB; ++i) {
+          if (i >= A.j) break;
           R v[WZ];
 #pragma unroll
           for (int t = 0; t < WZ; ++t) {
@@ -386,7 +388,7 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
             v[t] = at(A.V + i * A.vs + sbase, ob + kk * pbR);
           }
 #pragma unroll
-          for (int t = 0; t < WZ; ++t) dacc[i] += (double)wk[t] * (double)v[t];
+          for (int t = 0; t < WZ; ++t) dacc[i + 1] += (double)wk[t] * (double)v[t];
         }
       }
     }
@@ -402,11 +404,13 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
       if (lane == 0) redp[wid][i] = v;
     }
     __syncthreads();
+    // redp[.][0] holds w . v_j, redp[.][i + 1] holds w . v_i
     if ((int)threadIdx.x < JB && (int)threadIdx.x <= A.j) {
       const int i = threadIdx.x;
+      const int src = i == A.j ? 0 : i + 1;
       double v = 0.0;
 #pragma unroll
-      for (int q = 0; q < NT / 64; ++q) v += redp[q][i];
+      for (int q = 0; q < NT / 64; ++q) v += redp[q][src];
       A.dpart[((int64_t)sb * (A.kmax + 1) + i) * A.npart + blk] = v;
     }
   }
@@ -472,7 +476,7 @@ void launch_apply_pk3(const Geo& g, const Work& w, int j, double ck, int32_t B, 
   const size_t vs = (size_t)g.nn * B;
   auto fill = [&](auto& a) {
     using T = std::remove_const_t<std::remove_pointer_t<decltype(a.x)>>;
-    a.g = g; a.x = (const T*)w.z; a.vj = (const T*)w.V + j * vs; a.inv_eta = w.inv_eta;
+    a.g = g; a.x = (const T*)w.z + j * vs; a.vj = (const T*)w.V + j * vs; a.inv_eta = w.inv_eta;
     a.j = j; a.kmax = w.kmax; a.coef = w.coef; a.y = (T*)w.w; a.ck = ck; a.cm = 0.0; a.active = w.inner_active;
     a.V = (const T*)w.V; a.vs = vs; a.dpart = w.dpart;
   };
