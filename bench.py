@@ -272,7 +272,11 @@ def main():
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=None if ratio is None else round(ratio * per_launch),
-                    kernel="k_wave3 (preconditioned Jacobian apply + fused projections, all levels)",
+                    kernel=("k_tet_apply (Jacobian apply on the padded slot-major P1 pattern, all levels)"
+                            if runner.tet else
+                            "k_wave3 (preconditioned Jacobian apply + fused projections, all levels)"
+                            if cfg["dim"] == 3 else
+                            "k_apply_pk (2D preconditioned Jacobian apply, all levels)"),
                     bytes_per_node_sample=round(alg_bytes / max(apply_units, 1.0), 2),
                     alg_bytes_per_launch=round(per_launch),
                     alg_bytes_total=round(alg_bytes),
@@ -305,7 +309,11 @@ def main():
                    "samples_per_level": samp["n_per_level"], "n_shifts": samp.get("n_shifts", 1),
                    "parallelism": "single GPU, samples batched per level"},
         "st_dof_per_s": st_dof / el,
-        "estimate": res["estimate"], "rmse_est": res["rmse"],
+        # no error estimate: the combination form over nested point sets, or a lattice rule
+        # with a single random shift
+        "estimate": res["estimate"],
+        "rmse_est": None if samp["kind"] == "combination" or (samp["kind"] in ("qmc", "mlqmc")
+                                                            and samp.get("n_shifts", 1) < 2) else res["rmse"],
         "level_means": res["level_mean"],
         "kl": {"rank": runner.kl_rank, "trace_resid": runner.kl_resid},
         "setup_s": round(t_setup, 2),
