@@ -250,38 +250,41 @@ def main():
     el = time.perf_counter() - t0
     dof_iters, st_dof = runner.dof_iters, runner.st_dof
 
-    # dominant kernel: the Jacobian apply of the finest level (most of the bytes)
-    apply_ms = apply_units = apply_bytes = 0.0
-    apply_launches = 0
+    # dominant kernel: the Jacobian apply of the finest level (most of the bytes; its solves
+    # run with the GPU to themselves, the coarser levels' solves share it with each other)
     per_level = []
     for l, L in enumerate(runner.levels):
         t = L.timing_read(reset=True)["apply"]
-        apply_ms += t["ms"]
-        apply_units += t["units"]
-        apply_bytes += t["bytes"]
-        apply_launches += t["launches"]
-        per_level.append(dict(level=l, nodes=L.n_nodes, apply_ms=round(t["ms"], 3), apply_launches=t["launches"]))
+        per_level.append(dict(level=l, nodes=L.n_nodes, apply_ms=round(t["ms"], 3), apply_launches=t["launches"],
+                              alg_bytes=round(t["bytes"]), units=t["units"]))
         L.timing_enable(())
-    bpu = APPLY_BYTES[prec]
+    top = per_level[-1]
+    apply_ms, apply_bytes, apply_units, apply_launches = (top["apply_ms"], float(top["alg_bytes"]), top["units"],
+                                                          top["apply_launches"])
     # the library reports the algorithmic bytes of every apply launch (with the
     # Gram-Schmidt projections fused in, the basis vectors they read count too)
-    alg_bytes = apply_bytes if apply_bytes > 0 else apply_units * bpu
+    alg_bytes = apply_bytes if apply_bytes > 0 else apply_units * APPLY_BYTES[prec]
     per_launch = alg_bytes / max(apply_launches, 1)
     achieved = alg_bytes / (apply_ms * 1e-3) / 1e9 if apply_ms > 0 else 0.0
     ratio = counter_traffic(args.config, "fp64" if prec == W.PREC_FP64 else "mixed")
+    lvl = cfg["levels"][-1]
+    shape = (f"{lvl['cells'][0]}x{lvl['cells'][1]}x{lvl['cells'][2]} shell" if runner.tet
+             else "x".join(map(str, lvl["n"])))
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=None if ratio is None else round(ratio * per_launch),
-                    kernel=("k_tet_apply (Jacobian apply on the padded slot-major P1 pattern, all levels)"
+                    kernel=("k_tet_apply (Jacobian apply on the padded slot-major P1 pattern)"
                             if runner.tet else
-                            "k_wave3 (preconditioned Jacobian apply + fused projections, all levels)"
+                            "k_wave3 (preconditioned Jacobian apply + fused projections)"
                             if cfg["dim"] == 3 else
-                            "k_apply_pk (2D preconditioned Jacobian apply, all levels)"),
+                            "k_apply_pk (2D preconditioned Jacobian apply)") + f", finest level ({shape})",
                     bytes_per_node_sample=round(alg_bytes / max(apply_units, 1.0), 2),
                     alg_bytes_per_launch=round(per_launch),
                     alg_bytes_total=round(alg_bytes),
                     avg_launch_us=round(1e3 * apply_ms / max(apply_launches, 1), 2),
                     launches=apply_launches)
+    for p_ in per_level:
+        p_.pop("units")
 
     breakdown = None
     if args.breakdown:

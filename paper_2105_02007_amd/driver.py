@@ -8,6 +8,9 @@ random shifts of lattice rules are inputs, passed in by the caller.
 """
 from __future__ import annotations
 
+import threading
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import torch
 
@@ -22,7 +25,7 @@ class ConfigRunner:
     """Levels of one workload with their KL bases (Section 2.3) on one device."""
 
     def __init__(self, cfg: dict, prec: int | None = None, device="cuda", newton_tol=None, inner_tol=None,
-                 max_inner=30, kl_rank_factor=2, kl_eps=1e-2, log=None):
+                 max_inner=30, kl_rank_factor=2, kl_eps=1e-2, log=None, concurrent=True):
         say = log if log is not None else (lambda m: None)
         self.cfg = cfg
         self.device = device
@@ -82,6 +85,11 @@ class ConfigRunner:
         self.dof_iters = 0.0
         self.st_dof = 0.0
         self.log = None  # optional callable(str) for progress lines
+        # levels solve concurrently, each from a host thread of its own on a stream of its
+        # own (default priority); the solves of one level run in order on its stream
+        self.concurrent = concurrent
+        self.streams = [torch.cuda.Stream(device=device) for _ in self.levels]
+        self._lock = threading.Lock()
 
     def reset_counters(self):
         self.dof_iters = 0.0
@@ -97,19 +105,60 @@ class ConfigRunner:
             raise mlq.MlqError(out["code"], f"{int((st != 0).sum())} samples failed on level {l}")
         it = out["iters"]
         B = Y.shape[1]
-        self.dof_iters += float(L.n_nodes) * float(it[:, 1].sum().item())
-        self.st_dof += float(L.n_nodes) * float(L.desc.n_steps) * B
+        inner = float(it[:, 1].sum().item())
+        with self._lock:
+            self.dof_iters += float(L.n_nodes) * inner
+            self.st_dof += float(L.n_nodes) * float(L.desc.n_steps) * B
         if self.log is not None:
             self.log(f"level {l}: {B} samples x {L.n_nodes} nodes x {L.desc.n_steps} steps solved")
         return out["qoi"]
 
+    def solve_all(self, jobs):
+        """QoIs of the jobs [(level, Y)], in order.  The finest level's solves run first on
+        their own (so that its kernels, which dominate the cost, have the GPU to
+        themselves), then all other levels at the same time (co-scheduled on one GPU: the
+        small levels' latency-bound launches fill each other's gaps).  The results do not
+        depend on the schedule: every solve is independent and the estimators sum on the
+        host in sample order."""
+        levels = sorted({l for l, _ in jobs}, reverse=True)
+        if not self.concurrent or len(levels) < 3:
+            return [self.solve(l, Y) for l, Y in jobs]
+        main = torch.cuda.current_stream()
+        out = [None] * len(jobs)
+
+        def work(l):
+            s = self.streams[l]
+            s.wait_stream(main)  # the inputs were written on the caller's stream
+            with torch.cuda.stream(s):
+                for i, (lj, Y) in enumerate(jobs):
+                    if lj == l:
+                        out[i] = self.solve(l, Y)
+                s.synchronize()
+
+        work(levels[0])
+        with ThreadPoolExecutor(max_workers=len(levels) - 1) as ex:
+            for f in [ex.submit(work, l) for l in levels[1:]]:
+                f.result()
+        return out
+
     # ---- estimators -----------------------------------------------------
     def run_mlmc(self, Ys):
         """eq. (StandardML) with independent MC sets: Ys[l] = (M x N_l) device normals."""
-        ff, fc = [], []
+        jobs = []
         for l, Y in enumerate(Ys):
-            ff.append(self.solve(l, Y))
-            fc.append(self.solve(l - 1, Y) if l > 0 else None)
+            jobs.append((l, Y))
+            if l > 0:
+                jobs.append((l - 1, Y))
+        res = self.solve_all(jobs)
+        ff, fc, k = [], [], 0
+        for l in range(len(Ys)):
+            ff.append(res[k])
+            k += 1
+            if l > 0:
+                fc.append(res[k])
+                k += 1
+            else:
+                fc.append(None)
         return self._estimate(mlq.MLQ_EST_MLMC, ff, fc, [Y.shape[1] for Y in Ys], 1)
 
     def run_mc(self, Y, level=0):
@@ -128,13 +177,25 @@ class ConfigRunner:
     def run_mlqmc(self, shifts_per_level, levels=None):
         """eq. (StandardML) with randomly shifted lattice rules (shift-major sample order)."""
         levels = range(len(self.levels)) if levels is None else levels
-        ff, fc, npl = [], [], []
+        npl = []
         S = shifts_per_level[0].shape[0]
+        jobs = []
         for l in levels:
             Y = self.lattice_points(l, shifts_per_level[l])
-            ff.append(self.solve(l, Y))
-            fc.append(self.solve(l - 1, Y) if l > 0 else None)
+            jobs.append((l, Y))
+            if l > 0:
+                jobs.append((l - 1, Y))
             npl.append(Y.shape[1] // S)
+        res = self.solve_all(jobs)
+        ff, fc, k = [], [], 0
+        for l in levels:
+            ff.append(res[k])
+            k += 1
+            if l > 0:
+                fc.append(res[k])
+                k += 1
+            else:
+                fc.append(None)
         return self._estimate(mlq.MLQ_EST_MLQMC, ff, fc, npl, S)
 
     def run_combination(self, Y):
@@ -142,7 +203,7 @@ class ConfigRunner:
         is solved at the first N_{L-j} points (Q_{L-j})."""
         npl = self.cfg["sampling"]["n_per_level"]
         L = len(self.levels) - 1
-        f = [self.solve(j, Y[:, :npl[L - j]].contiguous()) for j in range(L + 1)]
+        f = self.solve_all([(j, Y[:, :npl[L - j]].contiguous()) for j in range(L + 1)])
         return self._estimate(mlq.MLQ_EST_COMBINATION, f, None, list(npl), 1)
 
     def _estimate(self, kind, ff, fc, npl, S):
