@@ -9,10 +9,11 @@
 // element contributions in increasing element order: deterministic, no atomics) into
 // kval[b][e].  The mass M (P1, |T| (1 + delta_ab) / 20) is shared by all samples.
 // The pattern is stored slot-major and padded to the longest row (entry (s, i) at
-// s * nv + i), so that in every operator application (one thread per (row, sample),
-// rows of one sample contiguous, samples on blockIdx.y) a wave reads the columns,
-// mass and stiffness values of slot s for 64 consecutive rows in one coalesced load.
-// Within a row the slots follow increasing column order.
+// s * nv + i), so that in every operator application (one thread per row and sample,
+// or per row and group of samples in the Jacobian apply; rows of one sample contiguous,
+// samples on blockIdx.y) a wave reads the columns, mass and stiffness values of slot s
+// for 64 consecutive rows in one coalesced load.  Within a row the slots follow
+// increasing column order.
 #include "mlq_internal.h"
 
 namespace mlq {
@@ -53,26 +54,46 @@ __global__ __launch_bounds__(kBlock) void k_tet_assemble(TetDev t, const T* __re
   kval[(int64_t)sb * t.nell + nz] = (T)acc;
 }
 
-// y = M ((1 + d) x) + ck K x
+// y = M ((1 + d) x) + ck K x.  A thread takes one row for kTetSamples samples, so that the
+// shared pattern (columns, mass) is read once for all of them; each sample's sum runs over
+// the slots in the same order as for one sample.
+constexpr int kTetSamples = 4;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tet_apply(TetDev t, const T* __restrict__ kval, const T* __restrict__ x,
-                                                      const T* __restrict__ d, T* __restrict__ y, T ck,
+                                                      const T* __restrict__ d, T* __restrict__ y, T ck, int32_t B,
                                                       const int32_t* __restrict__ active) {
-  const int sb = blockIdx.y;
-  if (active != nullptr && active[sb] == 0) return;
+  constexpr int S = kTetSamples;
+  const int sb0 = blockIdx.y * S;
+  bool on[S];
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    on[q] = sb0 + q < B && (active == nullptr || active[sb0 + q] != 0);
+    any = any || on[q];
+  }
+  if (!any) return;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= t.nv) return;
   const T* mv = nullptr;
   if constexpr (sizeof(T) == 4) mv = (const T*)t.em32; else mv = (const T*)t.em;
-  const int64_t so = (int64_t)sb * t.nv;
-  const T* kv = kval + (int64_t)sb * t.nell;
-  T acc = 0;
+  T acc[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) acc[q] = 0;
   for (int32_t sl = 0; sl < t.width; ++sl) {
     const int64_t e = (int64_t)sl * t.nv + i;
-    const int64_t j = so + t.ecol[e];
-    acc += (mv[e] * ((T)1 + d[j]) + ck * kv[e]) * x[j];
+    const int64_t c = t.ecol[e];
+    const T m = mv[e];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      if (!on[q]) continue;
+      const int64_t so = (int64_t)(sb0 + q) * t.nv;
+      const int64_t j = so + c;
+      acc[q] += (m * ((T)1 + d[j]) + ck * kval[(int64_t)(sb0 + q) * t.nell + e]) * x[j];
+    }
   }
-  y[so + i] = acc;
+#pragma unroll
+  for (int q = 0; q < S; ++q)
+    if (on[q]) y[(int64_t)(sb0 + q) * t.nv + i] = acc[q];
 }
 
 // F = M (u + dt I_ion(u)) + dt/2 K u - b (FP64), r0 = -F, d = dt I_ion'(u), partial norms
@@ -207,13 +228,13 @@ void launch_tet_assemble(const TetDev& t, const void* theta, void* kval, int32_t
 
 void launch_tet_apply(const TetDev& t, const void* kval, const void* x, const void* d, void* y, double ck, int32_t B,
                       const int32_t* active, bool mixed, hipStream_t s) {
-  const dim3 grid((unsigned)cdiv(t.nv, kBlock), B);
+  const dim3 grid((unsigned)cdiv(t.nv, kBlock), (unsigned)cdiv(B, kTetSamples));
   if (mixed)
     hipLaunchKernelGGL((k_tet_apply<float>), grid, dim3(kBlock), 0, s, t, (const float*)kval, (const float*)x,
-                       (const float*)d, (float*)y, (float)ck, active);
+                       (const float*)d, (float*)y, (float)ck, B, active);
   else
     hipLaunchKernelGGL((k_tet_apply<double>), grid, dim3(kBlock), 0, s, t, (const double*)kval, (const double*)x,
-                       (const double*)d, (double*)y, ck, active);
+                       (const double*)d, (double*)y, ck, B, active);
 }
 
 void launch_tet_residual(const TetDev& t, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s) {
