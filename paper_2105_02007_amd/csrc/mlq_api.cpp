@@ -154,7 +154,7 @@ namespace {
 
 struct BlobLayout {
   size_t phi64, phi32, sl, th0, fbox, wts, tri;
-  size_t ecol, em, em32, mdiag, mdiag32, ecptr, ecdat, geo;  // tetrahedral levels
+  size_t ecol, ediag, em, em32, mdiag, mdiag32, ecptr, ecdat, geo;  // tetrahedral levels
   size_t total;
 };
 
@@ -170,6 +170,7 @@ BlobLayout blob_layout(int64_t P, int64_t M, int64_t nn, int64_t nmax, const mlq
   L.wts = o;   o = align256(o + sizeof(double) * nn);
   if (th != nullptr) {
     L.ecol = o;    o = align256(o + sizeof(int32_t) * th->nell);
+    L.ediag = o;   o = align256(o + sizeof(int32_t) * th->nv);
     L.em = o;      o = align256(o + sizeof(double) * th->nell);
     L.em32 = o;    o = align256(o + sizeof(float) * th->nell);
     L.mdiag = o;   o = align256(o + sizeof(double) * th->nv);
@@ -263,7 +264,7 @@ Work carve_workspace(void* base, const Geo& geo, int32_t B, int kmax, bool mixed
   w.b = (double*)take(vn * sizeof(double));
   w.act = (double*)take(vn * sizeof(double));
   w.d = take(vn * ti);
-  w.z = take(vn * ti * (geo.tet ? 1 : kmax));
+  w.z = take(vn * ti * kmax);
   w.w = take(vn * ti);
   w.V = take(vn * ti * (kmax + 1));
   // box: per element (p, q); tetrahedra: per-sample stiffness values of the CSR
@@ -512,6 +513,7 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
     t.width = th.width;
     t.nc = th.nc;
     t.ecol = (const int32_t*)(base + L.ecol);
+    t.ediag = (const int32_t*)(base + L.ediag);
     t.em = (const double*)(base + L.em);
     t.em32 = (const float*)(base + L.em32);
     t.mdiag = (const double*)(base + L.mdiag);
@@ -524,6 +526,7 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
       if (e == hipSuccess) e = hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, s);
     };
     up(t.ecol, th.ecol.data(), sizeof(int32_t) * th.ecol.size());
+    up(t.ediag, th.ediag.data(), sizeof(int32_t) * th.ediag.size());
     up(t.em, th.em.data(), sizeof(double) * th.em.size());
     up(t.em32, m32.data(), sizeof(float) * m32.size());
     up(t.mdiag, th.mdiag.data(), sizeof(double) * th.mdiag.size());
@@ -699,7 +702,7 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
         const int32_t* nin = entering(j);
         timed(level, MLQ_K_PRECOND, nn, s, [&] {
           if (tet)
-            launch_tet_jacobi_basis(td, w, j, batch, mixed, s);
+            launch_tet_jacobi_basis(td, w, j, 0.5 * dt, batch, mixed, s);
           else
             launch_minv_basis(g, w, level->tri, level->nmax, j, batch, mixed, s);
         }, 0.0, nin);
@@ -716,8 +719,9 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
         timed(
             level, MLQ_K_APPLY, nn, s,
             [&] {
-              if (tet)  // Jacobi preconditioning: the operator is the full Jacobian applied to z
-                launch_tet_apply(td, w.coef, w.z, w.d, w.w, 0.5 * dt, batch, w.inner_active, mixed, s);
+              if (tet)  // the full Jacobian applied to z_j
+                launch_tet_apply(td, w.coef, (const char*)w.z + (size_t)j * level->nn * batch * (size_t)ti, w.d,
+                                 w.w, 0.5 * dt, batch, w.inner_active, mixed, s);
               else if (g.dim == 3)
                 launch_apply_pk3(g, w, j, 0.5 * dt, batch, mixed, s, fuse ? (j < 4 ? 4 : 8) : 0);
               else
@@ -742,11 +746,8 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
         }
       }
       timed(level, MLQ_K_UPDATE, nn * active, s, [&] {
-        launch_solve_y(w, batch, tet, s);
-        if (tet)
-          launch_tet_update(td, w, batch, mixed, s);
-        else
-          launch_update_zbasis(g, w, batch, mixed, s);
+        launch_solve_y(w, batch, false, s);
+        launch_update_zbasis(g, w, batch, mixed, s);
       });
     }
     timed(level, MLQ_K_QOI, nn * batch, s, [&] { launch_activation(w, level->nn, batch, d.u_th, t0, dt, s); });

@@ -38,6 +38,7 @@ struct TetDev {
   // the pattern stored slot-major: entry (s, i) at s * nv + i (consecutive rows are
   // consecutive in memory for every slot); padded slots point at row i with value 0
   const int32_t* ecol;     // nell: column
+  const int32_t* ediag;    // nv: slot of the diagonal entry of each row
   const double* em;        // nell: consistent P1 mass
   const float* em32;       // nell
   const double* mdiag;     // nv: diagonal of M
@@ -53,7 +54,7 @@ struct TetHost {
   int64_t nv = 0, nt = 0, nnz = 0, nc = 0, nell = 0;
   int32_t width = 0;
   std::vector<int32_t> rowptr, col, cptr, cdat;   // CSR (rows sorted)
-  std::vector<int32_t> ecol, ecptr, ecdat;        // the same, slot-major padded (TetDev)
+  std::vector<int32_t> ecol, ecptr, ecdat, ediag; // the same, slot-major padded (TetDev)
   std::vector<double> mval, em, mdiag, geo, wts, fload;
   double vol = 0.0;
 };
@@ -83,8 +84,7 @@ struct Work {
   double* act;   // activation times (-1: not yet activated)
   // inner precision per-node vectors, [B][n]
   void* d;       // dt * I_ion'(u)
-  void* z;       // boxes: preconditioned basis z_j = P^-1 v_j inv_eta_j, kmax vectors of [B][n];
-                 // tetrahedra: one vector
+  void* z;       // preconditioned basis z_j = P^-1 v_j inv_eta_j, kmax vectors of [B][n]
   void* w;       // operator output
   void* V;       // GMRES basis, (kmax + 1) vectors of [B][n]
   // per element coefficients [B][P][2] (inner precision)
@@ -180,7 +180,8 @@ void launch_tet_apply(const TetDev& t, const void* kval, const void* x, const vo
 void launch_tet_residual(const TetDev& t, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);
 void launch_tet_rhs(const TetDev& t, const Work& w, const double* fload, double load, double dt, int32_t B,
                     bool mixed, hipStream_t s);
-void launch_tet_jacobi_basis(const TetDev& t, const Work& w, int j, int32_t B, bool mixed, hipStream_t s);
-void launch_tet_update(const TetDev& t, const Work& w, int32_t B, bool mixed, hipStream_t s);
+// z_j = v_j inv_eta_j / diag(J) into the preconditioned basis, ck = dt / 2.
+void launch_tet_jacobi_basis(const TetDev& t, const Work& w, int j, double ck, int32_t B, bool mixed,
+                             hipStream_t s);
 
 }  // namespace mlq

@@ -174,43 +174,24 @@ __global__ __launch_bounds__(kBlock) void k_tet_rhs(TetDev t, const TI* __restri
   ucopy[so + i] = uk[so + i];
 }
 
-// GMRES preconditioner step: z = v_j inv_eta_j / (m_ii (1 + d_i))
+// GMRES preconditioner step (Jacobi on the whole Jacobian): z_j = v_j inv_eta_j / J_ii with
+// J_ii = m_ii (1 + d_i) + ck k_ii, into the preconditioned basis.  The stiffness diagonal
+// matters where the mesh is fine (near the apex dt sigma / h^2 is of order one there).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tet_jacobi(TetDev t, const T* __restrict__ v, const T* __restrict__ d,
-                                                       T* __restrict__ z, const double* __restrict__ inv_eta, int j,
-                                                       int kmax, const int32_t* __restrict__ active) {
-  const int sb = blockIdx.y;
-  if (active[sb] == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= t.nv) return;
-  const T* md = nullptr;
-  if constexpr (sizeof(T) == 4) md = (const T*)t.mdiag32; else md = (const T*)t.mdiag;
-  const int64_t o = (int64_t)sb * t.nv + i;
-  const T s = (T)inv_eta[(int64_t)sb * (kmax + 1) + j];
-  z[o] = v[o] * s / (md[i] * ((T)1 + d[o]));
-}
-
-// Newton update with right preconditioning: u += P^-1 sum_l y_l v_l (y_l carries inv_eta_l)
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_tet_update(TetDev t, const T* __restrict__ V, size_t vs,
-                                                       const T* __restrict__ d, const double* __restrict__ y, int kmax,
-                                                       const int32_t* __restrict__ inner_k, double* __restrict__ u,
+                                                       const T* __restrict__ kval, T ck, T* __restrict__ z,
+                                                       const double* __restrict__ inv_eta, int j, int kmax,
                                                        const int32_t* __restrict__ active) {
   const int sb = blockIdx.y;
   if (active[sb] == 0) return;
-  __shared__ double c[kMaxInner];
-  const int k = inner_k[sb];
-  for (int q = threadIdx.x; q < k; q += kBlock) c[q] = y[(int64_t)sb * kmax + q];
-  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= t.nv) return;
-  const int64_t o = (int64_t)sb * t.nv + i;
-  double acc = 0.0;
-  for (int l = 0; l < k; ++l) acc += c[l] * (double)V[l * vs + o];
-  const T sv = (T)acc;
   const T* md = nullptr;
   if constexpr (sizeof(T) == 4) md = (const T*)t.mdiag32; else md = (const T*)t.mdiag;
-  u[o] += (double)(sv / (md[i] * ((T)1 + d[o])));
+  const int64_t o = (int64_t)sb * t.nv + i;
+  const T kii = kval[(int64_t)sb * t.nell + (int64_t)t.ediag[i] * t.nv + i];
+  const T s = (T)inv_eta[(int64_t)sb * (kmax + 1) + j];
+  z[o] = v[o] * s / (md[i] * ((T)1 + d[o]) + ck * kii);
 }
 
 }  // namespace
@@ -258,26 +239,18 @@ void launch_tet_rhs(const TetDev& t, const Work& w, const double* fload, double 
                        0.5 * dt, w.b, w.u);
 }
 
-void launch_tet_jacobi_basis(const TetDev& t, const Work& w, int j, int32_t B, bool mixed, hipStream_t s) {
+void launch_tet_jacobi_basis(const TetDev& t, const Work& w, int j, double ck, int32_t B, bool mixed,
+                             hipStream_t s) {
   const dim3 grid((unsigned)cdiv(t.nv, kBlock), B);
   const size_t vs = (size_t)t.nv * B;
   if (mixed)
     hipLaunchKernelGGL((k_tet_jacobi<float>), grid, dim3(kBlock), 0, s, t, (const float*)w.V + j * vs,
-                       (const float*)w.d, (float*)w.z, w.inv_eta, j, w.kmax, w.inner_active);
+                       (const float*)w.d, (const float*)w.coef, (float)ck, (float*)w.z + j * vs, w.inv_eta, j, w.kmax,
+                       w.inner_active);
   else
     hipLaunchKernelGGL((k_tet_jacobi<double>), grid, dim3(kBlock), 0, s, t, (const double*)w.V + j * vs,
-                       (const double*)w.d, (double*)w.z, w.inv_eta, j, w.kmax, w.inner_active);
-}
-
-void launch_tet_update(const TetDev& t, const Work& w, int32_t B, bool mixed, hipStream_t s) {
-  const dim3 grid((unsigned)cdiv(t.nv, kBlock), B);
-  const size_t vs = (size_t)t.nv * B;
-  if (mixed)
-    hipLaunchKernelGGL((k_tet_update<float>), grid, dim3(kBlock), 0, s, t, (const float*)w.V, vs, (const float*)w.d,
-                       w.y, w.kmax, w.inner_k, w.u, w.newton_active);
-  else
-    hipLaunchKernelGGL((k_tet_update<double>), grid, dim3(kBlock), 0, s, t, (const double*)w.V, vs,
-                       (const double*)w.d, w.y, w.kmax, w.inner_k, w.u, w.newton_active);
+                       (const double*)w.d, (const double*)w.coef, ck, (double*)w.z + j * vs, w.inv_eta, j, w.kmax,
+                       w.inner_active);
 }
 
 }  // namespace mlq

@@ -69,7 +69,10 @@ std::string tet_build(const mlq_level_desc* d, TetHost& h, bool values) {
   h.nnz = (int64_t)h.col.size();
   h.nc = 16 * nt;
   h.width = 0;
-  for (int64_t v = 0; v < nv; ++v) h.width = std::max(h.width, h.rowptr[v + 1] - h.rowptr[v]);
+  for (int64_t v = 0; v < nv; ++v) {
+    if (h.rowptr[v + 1] == h.rowptr[v]) return "a vertex belongs to no tetrahedron";
+    h.width = std::max(h.width, h.rowptr[v + 1] - h.rowptr[v]);
+  }
   h.nell = (int64_t)h.width * nv;
   if (h.nell > (int64_t)INT32_MAX) return "too many padded nonzeros for 32-bit indices";
   if (!values) return "";
@@ -137,6 +140,10 @@ std::string tet_build(const mlq_level_desc* d, TetHost& h, bool values) {
   }
   // slot-major padded rows: entry (slot s, row v) at s * nv + v; a padded slot points at the
   // row itself with a zero value and no contributions
+  h.ediag.assign(nv, -1);
+  for (int64_t v = 0; v < nv; ++v)
+    for (int32_t nz = h.rowptr[v]; nz < h.rowptr[v + 1]; ++nz)
+      if (h.col[nz] == v) h.ediag[v] = nz - h.rowptr[v];
   h.ecol.assign(h.nell, 0);
   h.em.assign(h.nell, 0.0);
   h.ecptr.assign(h.nell + 1, 0);
