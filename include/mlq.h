@@ -59,6 +59,7 @@ typedef enum {
 typedef enum { MLQ_FP64 = 0, MLQ_MIXED = 1 } mlq_precision;
 typedef enum { MLQ_QOI_MEAN_U_FINAL = 0, MLQ_QOI_MEAN_ACT_TIME = 1 } mlq_qoi;
 typedef enum { MLQ_MESH_Q1_BOX = 0, MLQ_MESH_P1_TET = 1 } mlq_mesh_kind;
+typedef enum { MLQ_GUESS_PREVIOUS = 0, MLQ_GUESS_EXTRAPOLATE = 1 } mlq_newton_guess;
 
 /* per-sample status codes written by mlq_solve_batch */
 enum { MLQ_SAMPLE_OK = 0, MLQ_SAMPLE_NOCONV = 1, MLQ_SAMPLE_NAN = 2 };
@@ -96,13 +97,18 @@ typedef struct {
    * element e is f = cos(theta_e) e_circ[e] + sin(theta_e) e_long[e], eq. (AdmV)
    * with V = sigma_l f.  The stimulus is the ball (stim_center, stim_radius):
    * load F = M chi with chi the indicator of the vertices inside it.  The
-   * Krylov preconditioner is the diagonal of M (1 + D). */
+   * Krylov preconditioner is the diagonal of the Jacobian. */
   int64_t n_vert, n_tet;              /* vertices (<= 2^27), tetrahedra (<= 2^27) */
   const double* xyz;                  /* n_vert x 3 */
   const int32_t* tets;                /* n_tet x 4 vertex indices, positively oriented */
   const double* e_circ;               /* n_tet x 3 unit vectors */
   const double* e_long;               /* n_tet x 3 unit vectors orthogonal to e_circ */
   double stim_center[3], stim_radius;
+  /* Newton initial guess of step k + 1 (the discrete solution does not depend on it
+   * beyond the stopping test): 0 = u_k, the previous time level (the multiple-time-block
+   * strategy of Section 3.3 with one step per block); 1 = 2 u_k - u_{k-1}, linear
+   * extrapolation from the two previous time levels (u_k at the first step). */
+  int32_t newton_guess;               /* mlq_newton_guess */
 } mlq_level_desc;
 
 typedef struct mlq_level mlq_level; /* opaque */

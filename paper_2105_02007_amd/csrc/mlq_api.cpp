@@ -213,6 +213,8 @@ mlq_status validate(const mlq_level_desc* d) {
   if (d->max_newton < 1 || d->max_newton > 1000) return fail(MLQ_EINVAL, "max_newton out of range");
   if (d->max_inner < 1 || d->max_inner > kMaxInner) return fail(MLQ_EINVAL, "max_inner must be in [1, %d]", kMaxInner);
   if (d->max_batch < 1 || d->max_batch > 65535) return fail(MLQ_EINVAL, "max_batch must be in [1, 65535]");
+  if (d->newton_guess != MLQ_GUESS_PREVIOUS && d->newton_guess != MLQ_GUESS_EXTRAPOLATE)
+    return fail(MLQ_EINVAL, "newton_guess must be MLQ_GUESS_PREVIOUS or MLQ_GUESS_EXTRAPOLATE");
   // uniqueness of the step equation: dt * |min I_ion'| < 1 (min over u of the cubic's derivative)
   const double dt = d->t_end / d->n_steps;
   const double r = d->u_rest, t = d->u_th, p = d->u_peak;
@@ -260,6 +262,7 @@ Work carve_workspace(void* base, const Geo& geo, int32_t B, int kmax, bool mixed
     return r;
   };
   w.uk = (double*)take(vn * sizeof(double));
+  w.ukm1 = (double*)take(vn * sizeof(double));
   w.u = (double*)take(vn * sizeof(double));
   w.b = (double*)take(vn * sizeof(double));
   w.act = (double*)take(vn * sizeof(double));
@@ -671,6 +674,8 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
       else
         launch_rhs(g, w, level->fbox, load, dt, batch, mixed, s);
     });
+    // the rhs kernels start Newton from u = u_k; the extrapolated guess replaces it
+    if (d.newton_guess == MLQ_GUESS_EXTRAPOLATE && k > 0) launch_extrapolate(w, level->nn, batch, s);
     launch_newton_reset(w, batch, s);
     int32_t active = batch;
     for (int it = 0;; ++it) {
@@ -751,7 +756,11 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
       });
     }
     timed(level, MLQ_K_QOI, nn * batch, s, [&] { launch_activation(w, level->nn, batch, d.u_th, t0, dt, s); });
-    std::swap(w.uk, w.u);
+    // u_{k-1} <- u_k <- u (the old u_{k-1} becomes the next Newton iterate's storage)
+    double* old = w.ukm1;
+    w.ukm1 = w.uk;
+    w.uk = w.u;
+    w.u = old;
   }
   launch_qoi(w, level->wts, level->nn, batch, d.qoi, (double)n_steps * dt, level->vol, qoi_dev, s);
   HIP_OK(hipMemcpyAsync(status_dev, w.status, sizeof(int32_t) * batch, hipMemcpyDeviceToDevice, s));

@@ -79,6 +79,7 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Work {
   // FP64 per-node state, [B][n]
   double* uk;    // u_k, state at the current time level
+  double* ukm1;  // u_{k-1} (extrapolated Newton guess)
   double* u;     // Newton iterate for u_{k+1}
   double* b;     // right-hand side of the step
   double* act;   // activation times (-1: not yet activated)
@@ -121,6 +122,8 @@ Work carve_workspace(void* base, const Geo& g, int32_t batch, int kmax, bool mix
 void launch_coefs(const void* theta, void* coef, int64_t P, int32_t B, double half_dsig, bool mixed,
                   hipStream_t s);
 void launch_init(const Work& w, int64_t nn, int32_t B, double u_th, hipStream_t s);
+// Newton initial guess u = 2 u_k - u_{k-1}
+void launch_extrapolate(const Work& w, int64_t nn, int32_t B, hipStream_t s);
 void launch_rhs(const Geo& g, const Work& w, const double* fbox, double load_coef, double dt, int32_t B,
                 bool mixed, hipStream_t s);
 void launch_residual(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);

@@ -226,6 +226,18 @@ void launch_init(const Work& w, int64_t nn, int32_t B, double u_th, hipStream_t 
                      w.status, w.iters, B);
 }
 
+__global__ void k_extrapolate(double* __restrict__ u, const double* __restrict__ uk, const double* __restrict__ ukm1,
+                              int64_t total) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < total) u[i] = 2.0 * uk[i] - ukm1[i];
+}
+
+void launch_extrapolate(const Work& w, int64_t nn, int32_t B, hipStream_t s) {
+  const int64_t total = nn * B;
+  hipLaunchKernelGGL(k_extrapolate, dim3((unsigned)cdiv(total, kBlock)), dim3(kBlock), 0, s, w.u, w.uk, w.ukm1,
+                     total);
+}
+
 // ---------------------------------------------------------------------------
 // Right-hand side of step k (eq. (st-system)):  b = (M - dt/2 K) u_k + c_k F_box,
 // c_k = dt/2 (s(t_{k+1}) + s(t_k)).  Also starts Newton from u = u_k.

@@ -25,7 +25,8 @@ class ConfigRunner:
     """Levels of one workload with their KL bases (Section 2.3) on one device."""
 
     def __init__(self, cfg: dict, prec: int | None = None, device="cuda", newton_tol=None, inner_tol=None,
-                 max_inner=30, kl_rank_factor=2, kl_eps=1e-2, log=None, concurrent=True):
+                 max_inner=30, kl_rank_factor=2, kl_eps=1e-2, log=None, concurrent=True,
+                 newton_guess=mlq.MLQ_GUESS_EXTRAPOLATE):
         say = log if log is not None else (lambda m: None)
         self.cfg = cfg
         self.device = device
@@ -74,7 +75,7 @@ class ConfigRunner:
                 lv, self.phys, n_modes=M, phi=phi, sqrt_lambda=sl, theta0=theta0, prec=self.prec, qoi=cfg["qoi"],
                 newton_tol=newton_tol if newton_tol is not None else (1e-13 if self.prec == mlq.MLQ_FP64 else 1e-10),
                 inner_tol=inner_tol if inner_tol is not None else (1e-6 if self.prec == mlq.MLQ_FP64 else 1e-5),
-                max_inner=max_inner, max_batch=nb)
+                max_inner=max_inner, max_batch=nb, newton_guess=newton_guess)
             L = mlq.Level(desc, keep, device=device)
             L._keep = None  # arrays were copied into the level blob
             self.levels.append(L)

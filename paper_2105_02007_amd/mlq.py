@@ -28,6 +28,7 @@ EXPORTED = [
     "mlq_kl_workspace_bytes", "mlq_kl_modes", "mlq_kl_transfer", "mlq_timing_enable", "mlq_timing_read",
     "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet",
 ]
+MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE = 0, 1
 KERNEL_CLASSES = ["apply", "residual", "rhs", "precond", "dots", "orth", "small", "update", "qoi"]
 
 
@@ -56,6 +57,7 @@ class LevelDesc(C.Structure):
         ("xyz", C.POINTER(C.c_double)), ("tets", C.POINTER(C.c_int32)),
         ("e_circ", C.POINTER(C.c_double)), ("e_long", C.POINTER(C.c_double)),
         ("stim_center", C.c_double * 3), ("stim_radius", C.c_double),
+        ("newton_guess", C.c_int32),
     ]
 
 
@@ -139,7 +141,7 @@ def _stream(stream=None):
 
 def make_desc(level: dict, phys: dict, *, n_modes=0, phi=None, sqrt_lambda=None, theta0=None,
               prec=MLQ_FP64, qoi=MLQ_QOI_MEAN_U_FINAL, newton_tol=1e-13, inner_tol=1e-6,
-              max_newton=20, max_inner=30, max_batch=1):
+              max_newton=20, max_inner=30, max_batch=1, newton_guess=MLQ_GUESS_PREVIOUS):
     """Fills an mlq_level_desc from a workload level and physics dict.  Returns (desc, keepalive)."""
     d = LevelDesc()
     dim = level["dim"]
@@ -195,6 +197,7 @@ def make_desc(level: dict, phys: dict, *, n_modes=0, phi=None, sqrt_lambda=None,
     d.prec, d.qoi = int(prec), int(qoi)
     d.newton_tol, d.inner_tol = float(newton_tol), float(inner_tol)
     d.max_newton, d.max_inner, d.max_batch = int(max_newton), int(max_inner), int(max_batch)
+    d.newton_guess = int(newton_guess)
     return d, keep
 
 

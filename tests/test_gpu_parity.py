@@ -75,7 +75,7 @@ def test_apply_matches_assembled_jacobian(env, dim, n, mixed):
         assert np.abs(y[b] - ref).max() <= tol, (b, np.abs(y[b] - ref).max() / scale.max())
 
 
-def _solve_pair(env, dim, n, steps, B, qoi, prec, n_modes=8, seed=7, phys=None, stop=None):
+def _solve_pair(env, dim, n, steps, B, qoi, prec, n_modes=8, seed=7, phys=None, stop=None, guess=0):
     torch, mlq = env
     from oracle import fem, kl, stepper
     from oracle.mesh import BoxMesh
@@ -85,7 +85,8 @@ def _solve_pair(env, dim, n, steps, B, qoi, prec, n_modes=8, seed=7, phys=None, 
     Y = W.mc_normals(seed, 0, B, n_modes)
     tol = W.NEWTON_TOL[prec]
     desc, keep = mlq.make_desc(_level(dim, n, steps), phys, n_modes=n_modes, phi=phi, sqrt_lambda=sl, prec=prec,
-                               qoi=qoi, newton_tol=tol, inner_tol=W.INNER_TOL[prec], max_batch=B)
+                               qoi=qoi, newton_tol=tol, inner_tol=W.INNER_TOL[prec], max_batch=B,
+                               newton_guess=guess)
     lv = mlq.Level(desc, keep)
     theta = lv.sample_fields(torch.as_tensor(Y, device="cuda"))
     out = lv.solve(theta, n_steps=stop, want_state=True)
@@ -148,6 +149,26 @@ def test_solve_fp64_ragged_wide_3d_truncated(env):
     u = out["u"].cpu().numpy()
     for b, r in enumerate(refs):
         assert np.abs(u[b] - r["u"]).max() <= 1e-10 * np.abs(r["u"]).max()
+
+
+@pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
+def test_solve_extrapolated_newton_guess(env, prec):
+    """Newton started from 2 u_k - u_{k-1}: the same discrete solution as the oracle's Newton
+    from u_k (FP64 per node and per QoI 1e-10; mixed within its stopping test), in fewer
+    Newton iterations."""
+    torch, mlq = env
+    out, refs, mesh = _solve_pair(env, 3, [9, 9, 9], 32, 3, W.QOI_MEAN_ACT_TIME, prec, guess=1)
+    out0, _, _ = _solve_pair(env, 3, [9, 9, 9], 32, 3, W.QOI_MEAN_ACT_TIME, prec, guess=0)
+    assert int(out["status"].abs().sum()) == 0
+    u = out["u"].cpu().numpy()
+    q = out["qoi"].cpu().numpy()
+    tol = 1e-10 if prec == W.PREC_FP64 else 1e-6
+    for b, r in enumerate(refs):
+        assert np.abs(u[b] - r["u"]).max() <= tol * np.abs(r["u"]).max()
+        assert abs(q[b] - r["mean_act"]) <= tol * abs(r["mean_act"])
+    n1 = int(out["iters"][:, 0].sum())
+    n0 = int(out0["iters"][:, 0].sum())
+    assert n1 < n0, (n1, n0)
 
 
 def test_solve_mixed_statistics(env):
