@@ -138,6 +138,39 @@ def cpu_baseline(cfg, budget_s):
                 st_dof_per_s=st_dof / el, seconds=el)
 
 
+def qoi_vs_fp64(cfg, runner, res, dev, log, Ys=None, Yc=None, shifts=None, nq=4):
+    """The first nq samples of the finest level re-solved by the FP64 path (the same KL
+    set-up and the same points), against the mixed run's QoIs of those samples.  The FP64
+    path itself is pinned to the oracle (1e-10 per QoI) by the parity tests."""
+    import numpy as np
+    import torch
+
+    from paper_2105_02007_amd import mlq
+    from paper_2105_02007_amd.driver import ConfigRunner
+    L = len(cfg["levels"]) - 1
+    samp = cfg["sampling"]
+    if samp["kind"] == "combination":
+        Y = Yc
+    elif samp["kind"] in ("mc", "mlmc"):
+        Y = Ys[L]
+    else:
+        Y = runner.lattice_points(L, shifts[L])
+    nq = min(nq, Y.shape[1])
+    Y = Y[:, :nq].contiguous()
+    mixed_q = np.asarray(res["f_fine"][L][:nq])
+    log(f"FP64 re-solve of {nq} finest-level samples")
+    t0 = time.perf_counter()
+    r64 = ConfigRunner(cfg, prec=mlq.MLQ_FP64, device=dev, concurrent=False)
+    q64 = r64.solve(L, Y).cpu().numpy()
+    el = time.perf_counter() - t0
+    del r64
+    torch.cuda.empty_cache()
+    rel = np.abs(mixed_q - q64) / np.abs(q64)
+    return dict(level=L, samples=nq, max_rel_diff=float(rel.max()), mean_rel_diff=float(rel.mean()),
+                fp64_seconds=round(el, 1),
+                reference="FP64 GPU solve of the same samples (the FP64 path is pinned to the oracle at 1e-10)")
+
+
 def kl_synthesis(runner, cfg, dev, reps=5):
     """Time the KL synthesis (MFMA contraction) of the finest level's batch: HIP events
     on the stream the binding launches on (torch's current stream)."""
@@ -183,6 +216,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="extra untimed pass timing every kernel class")
+    ap.add_argument("--no-qoi-check", action="store_true",
+                    help="skip the FP64 re-solve of a few finest-level samples after a mixed-precision run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB FP64 copy (torch.neg) before warm-up, as a counter reference")
     args = ap.parse_args()
@@ -213,6 +248,7 @@ def main():
     samp = cfg["sampling"]
     M = cfg["kl"]["n_modes"]
     kind = samp["kind"]
+    Ys = Yc = shifts = None
     if kind == "combination":
         Yc = torch.as_tensor(W.mc_normals(cfg["seed"], 0, max(samp["n_per_level"]), M), device=dev)
         step = lambda: runner.run_combination(Yc)
@@ -323,9 +359,17 @@ def main():
         "roofline": roofline,
         "apply_per_level": per_level,
     }
+    # per level: its solves' DOF x iterations over their host wall time (the coarser levels
+    # run concurrently, so their rates are while sharing the GPU)
+    line["levels"] = [dict(level=l, dof_iters_per_s=(runner.level_dof_iters[l] / runner.level_seconds[l]
+                                                     if runner.level_seconds[l] > 0 else None),
+                           seconds=round(runner.level_seconds[l] / max(args.steps, 1), 4))
+                      for l in range(len(runner.levels))]
     if breakdown:
         line["breakdown"] = breakdown
     line["kl_synthesis"] = kl_synthesis(runner, cfg, dev)
+    if prec == W.PREC_MIXED and not args.no_qoi_check and not runner.tet:
+        line["qoi_vs_fp64"] = qoi_vs_fp64(cfg, runner, res, dev, log, Ys, Yc, shifts)
     runner.log = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")

@@ -9,6 +9,7 @@ random shifts of lattice rules are inputs, passed in by the caller.
 from __future__ import annotations
 
 import threading
+import time
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -91,14 +92,19 @@ class ConfigRunner:
         self.concurrent = concurrent
         self.streams = [torch.cuda.Stream(device=device) for _ in self.levels]
         self._lock = threading.Lock()
+        self.level_dof_iters = [0.0] * len(self.levels)
+        self.level_seconds = [0.0] * len(self.levels)
 
     def reset_counters(self):
         self.dof_iters = 0.0
         self.st_dof = 0.0
+        self.level_dof_iters = [0.0] * len(self.levels)
+        self.level_seconds = [0.0] * len(self.levels)
 
     def solve(self, l: int, Y: torch.Tensor):
         """QoIs (device FP64) of the samples Y (M x B, device FP64) on level l."""
         L = self.levels[l]
+        t0 = time.perf_counter()
         theta = L.sample_fields(Y)
         out = L.solve(theta)
         if out["code"] != mlq.MLQ_OK:
@@ -106,10 +112,13 @@ class ConfigRunner:
             raise mlq.MlqError(out["code"], f"{int((st != 0).sum())} samples failed on level {l}")
         it = out["iters"]
         B = Y.shape[1]
-        inner = float(it[:, 1].sum().item())
+        inner = float(it[:, 1].sum().item())  # waits for the solve on this stream
+        el = time.perf_counter() - t0
         with self._lock:
             self.dof_iters += float(L.n_nodes) * inner
             self.st_dof += float(L.n_nodes) * float(L.desc.n_steps) * B
+            self.level_dof_iters[l] += float(L.n_nodes) * inner
+            self.level_seconds[l] += el
         if self.log is not None:
             self.log(f"level {l}: {B} samples x {L.n_nodes} nodes x {L.desc.n_steps} steps solved")
         return out["qoi"]
