@@ -60,6 +60,8 @@ typedef enum { MLQ_FP64 = 0, MLQ_MIXED = 1 } mlq_precision;
 typedef enum { MLQ_QOI_MEAN_U_FINAL = 0, MLQ_QOI_MEAN_ACT_TIME = 1 } mlq_qoi;
 typedef enum { MLQ_MESH_Q1_BOX = 0, MLQ_MESH_P1_TET = 1 } mlq_mesh_kind;
 typedef enum { MLQ_GUESS_PREVIOUS = 0, MLQ_GUESS_EXTRAPOLATE = 1 } mlq_newton_guess;
+typedef enum { MLQ_DIFF_FIBRE = 0, MLQ_DIFF_ISO = 1 } mlq_diffusion;
+typedef enum { MLQ_COV_EXP = 0, MLQ_COV_SQEXP = 1 } mlq_cov_kernel;
 
 /* per-sample status codes written by mlq_solve_batch */
 enum { MLQ_SAMPLE_OK = 0, MLQ_SAMPLE_NOCONV = 1, MLQ_SAMPLE_NAN = 2 };
@@ -109,6 +111,12 @@ typedef struct {
    * strategy of Section 3.3 with one step per block); 1 = 2 u_k - u_{k-1}, linear
    * extrapolation from the two previous time levels (u_k at the first step). */
   int32_t newton_guess;               /* mlq_newton_guess */
+  /* Conductivity model of the elements (boxes): MLQ_DIFF_FIBRE: the field is the fibre
+   * angle theta, G = sigma_t I + (sigma_l - sigma_t) f f^T with f = (cos theta, sin theta[, 0]),
+   * eq. (AdmV) with V = sigma_l f; MLQ_DIFF_ISO: the field is a scalar conductivity v > 0,
+   * G = v I (isotropic diffusion, the paper's cube experiments of Section 5.2; sigma_l,
+   * sigma_t unused).  Tetrahedra: MLQ_DIFF_FIBRE only. */
+  int32_t diffusion;
 } mlq_level_desc;
 
 typedef struct mlq_level mlq_level; /* opaque */
@@ -217,8 +225,9 @@ mlq_status mlq_estimate(int32_t kind, int32_t n_levels, int32_t n_shifts, const 
                         mlq_estimate_out* out);
 
 /* ---- KL basis set-up (Section 2.3; element-midpoint transfer of Section 4) ----
- * Covariance C(x, x') = std_dev^2 exp(-|x - x'|_2 / corr_len) on the nodes of a
- * uniform Q1 box or of a tetrahedral mesh (normally the finest level).  eq. (algEig) is reduced by a
+ * Covariance C(x, x') = std_dev^2 exp(-|x - x'|_2 / corr_len) (or the squared-exponential
+ * kernel, cov_kernel) on the nodes of a uniform Q1 box or of a tetrahedral mesh (normally
+ * the finest level).  eq. (algEig) is reduced by a
  * pivoted Cholesky factor C ~ L L^T (largest remaining diagonal first, lowest
  * index on ties; stops at rank max_rank, or once the rank is >= n_modes and
  * trace(C - L L^T) <= eps trace(C)) to eq. (redEig), L^T M L v~ = lambda v~. */
@@ -237,6 +246,10 @@ typedef struct {
   int64_t n_vert, n_tet;
   const double* xyz;    /* n_vert x 3 */
   const int32_t* tets;  /* n_tet x 4, positively oriented */
+  /* covariance kernel: MLQ_COV_EXP, std_dev^2 exp(-|x - x'|_2 / corr_len) (the default), or
+   * MLQ_COV_SQEXP, std_dev^2 exp(-|x - x'|_2^2 / corr_len) (the paper's kernel of Section 5.1,
+   * with corr_len = sigma_KL) */
+  int32_t cov_kernel;
 } mlq_kl_desc;
 
 /* Device workspace bytes of mlq_kl_modes (dominated by two n x max_rank FP64 arrays). */

@@ -47,6 +47,12 @@ def conductivity_from_angle(theta, d, sigma_l, sigma_t):
     return conductivity(sigma_l * fibre_direction(theta, d), sigma_t)
 
 
+def conductivity_iso(v, d):
+    """Isotropic scalar conductivity G = v I per element (the paper's cube model, Section 5.1)."""
+    v = np.asarray(v, dtype=np.float64)
+    return v[..., None, None] * np.broadcast_to(np.eye(d), v.shape + (d, d))
+
+
 def _ref_basis(d, xi):
     """Q1 reference basis values (2^d,) and reference gradients (2^d, d) at xi in [0,1]^d."""
     offs = local_offsets(d)

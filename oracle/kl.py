@@ -11,8 +11,11 @@ M-orthonormal modes psi_k.  The discrete field is eq. (KLlowrank); here it is
 the scalar fibre angle  theta(x) = theta0(x) + sum_k sqrt(lambda_k) psi_k(x) y_k.
 
 Readings (where the paper leaves a choice):
-* kernel C(x, x') = s^2 exp(-|x - x'|_2 / l) (exponential, Euclidean distance);
-* y_k standard normal (the workloads draw Gaussian coordinates);
+* kernel C(x, x') = s^2 exp(-|x - x'|_2 / l) (exponential, Euclidean distance), or the
+  paper's squared-exponential s^2 exp(-|x - x'|_2^2 / l) (Section 5.1, l = sigma_KL);
+* y_k standard normal (the workloads' fibre-angle model) or uniform on [-1, 1] with the
+  modes scaled by sqrt(3 lambda_k) (the paper's model, Section 5.1): the field is linear
+  in y either way, see ``field``;
 * pivoted Cholesky stops when trace(C - L L^T) <= eps trace(C) or at rank r_max;
 * sign of each mode: its first entry of largest magnitude is positive (entries
   within a relative 1e-9 of the maximum count as ties);
@@ -27,12 +30,16 @@ import scipy.linalg as sla
 from .mesh import BoxMesh, local_offsets
 
 
-def exp_cov(X, Y, std, corr_len):
-    d = np.sqrt(np.maximum(((X[:, None, :] - Y[None, :, :]) ** 2).sum(-1), 0.0))
-    return std * std * np.exp(-d / corr_len)
+def exp_cov(X, Y, std, corr_len, kernel="exp"):
+    """s^2 exp(-|x - y|_2 / l) (kernel "exp"), or s^2 exp(-|x - y|_2^2 / l) (kernel "sqexp",
+    the paper's squared-exponential kernel of Section 5.1 with l = sigma_KL)."""
+    d2 = np.maximum(((X[:, None, :] - Y[None, :, :]) ** 2).sum(-1), 0.0)
+    if kernel == "sqexp":
+        return std * std * np.exp(-d2 / corr_len)
+    return std * std * np.exp(-np.sqrt(d2) / corr_len)
 
 
-def pivoted_cholesky(nodes, std, corr_len, max_rank, eps=0.0):
+def pivoted_cholesky(nodes, std, corr_len, max_rank, eps=0.0, kernel="exp"):
     """Greedy pivoted Cholesky of C_ij = k(x_i, x_j).  Returns L (n, r) and pivots."""
     n = nodes.shape[0]
     diag = np.full(n, std * std)
@@ -43,7 +50,7 @@ def pivoted_cholesky(nodes, std, corr_len, max_rank, eps=0.0):
         p = int(np.argmax(diag))
         if diag[p] <= 0.0:
             break
-        col = exp_cov(nodes, nodes[p:p + 1], std, corr_len)[:, 0]
+        col = exp_cov(nodes, nodes[p:p + 1], std, corr_len, kernel)[:, 0]
         col = col - L[:, :r] @ L[p, :r]
         L[:, r] = col / np.sqrt(diag[p])
         diag = diag - L[:, r] ** 2
@@ -82,23 +89,23 @@ def kl_from_cholesky(L, M, n_modes):
     return lam, V
 
 
-def kl_dense(nodes, M, std, corr_len, n_modes):
+def kl_dense(nodes, M, std, corr_len, n_modes, kernel="exp"):
     """Direct solution of eq. (algEig) on small meshes: M C M v = lambda M v."""
     Md = M.toarray() if hasattr(M, "toarray") else np.asarray(M)
-    C = exp_cov(nodes, nodes, std, corr_len)
+    C = exp_cov(nodes, nodes, std, corr_len, kernel)
     lam, V = sla.eigh(Md @ C @ Md, Md)
     order = np.argsort(lam)[::-1][:n_modes]
     lam, V = lam[order], V[:, order]  # V^T M V = I
     return lam, fix_signs(V * np.sqrt(np.maximum(lam, 0.0)))
 
 
-def kl_modes(mesh: BoxMesh, M, std, corr_len, n_modes, max_rank=None, eps=1e-2):
+def kl_modes(mesh: BoxMesh, M, std, corr_len, n_modes, max_rank=None, eps=1e-2, kernel="exp"):
     """KL on the nodes of ``mesh``: returns lambda (n_modes,) and unit modes psi (n, n_modes)."""
     if max_rank is None:
         max_rank = 2 * n_modes
-    L, _ = pivoted_cholesky(mesh.nodes, std, corr_len, max(max_rank, n_modes), eps)
+    L, _ = pivoted_cholesky(mesh.nodes, std, corr_len, max(max_rank, n_modes), eps, kernel)
     if L.shape[1] < n_modes:
-        L, _ = pivoted_cholesky(mesh.nodes, std, corr_len, n_modes, 0.0)
+        L, _ = pivoted_cholesky(mesh.nodes, std, corr_len, n_modes, 0.0, kernel)
     lam, V = kl_from_cholesky(L, M, n_modes)
     return lam, V / np.sqrt(lam)
 

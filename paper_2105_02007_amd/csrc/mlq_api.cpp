@@ -215,6 +215,10 @@ mlq_status validate(const mlq_level_desc* d) {
   if (d->max_batch < 1 || d->max_batch > 65535) return fail(MLQ_EINVAL, "max_batch must be in [1, 65535]");
   if (d->newton_guess != MLQ_GUESS_PREVIOUS && d->newton_guess != MLQ_GUESS_EXTRAPOLATE)
     return fail(MLQ_EINVAL, "newton_guess must be MLQ_GUESS_PREVIOUS or MLQ_GUESS_EXTRAPOLATE");
+  if (d->diffusion != MLQ_DIFF_FIBRE && d->diffusion != MLQ_DIFF_ISO)
+    return fail(MLQ_EINVAL, "diffusion must be MLQ_DIFF_FIBRE or MLQ_DIFF_ISO");
+  if (d->diffusion == MLQ_DIFF_ISO && d->mesh_kind != MLQ_MESH_Q1_BOX)
+    return fail(MLQ_EINVAL, "the isotropic scalar diffusion model is for boxes");
   // uniqueness of the step equation: dt * |min I_ion'| < 1 (min over u of the cubic's derivative)
   const double dt = d->t_end / d->n_steps;
   const double r = d->u_rest, t = d->u_th, p = d->u_peak;
@@ -376,8 +380,16 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   g.Hx = hx;
   g.Hy = hy;
   g.Hz = hz;
-  g.sbar = 0.5 * (desc->sigma_l + desc->sigma_t);
-  g.st = desc->sigma_t;
+  if (desc->diffusion == MLQ_DIFF_ISO) {
+    g.cx0 = g.cy0 = g.cz0 = 0.0;
+    g.cx1 = g.cy1 = g.cz1 = 1.0;
+  } else {
+    g.cx0 = g.cy0 = 0.5 * (desc->sigma_l + desc->sigma_t);
+    g.cx1 = 1.0;
+    g.cy1 = -1.0;
+    g.cz0 = desc->sigma_t;
+    g.cz1 = 0.0;
+  }
   g.tet = tet ? 1 : 0;
   g.nnz = tet ? th.nell : 0;
   if (tet) g.nx = g.ny = g.nz = 0;
@@ -617,7 +629,8 @@ mlq_status mlq_apply(mlq_level* level, const void* theta_dev, int32_t batch, con
     HIP_OK(hipGetLastError());
     return MLQ_OK;
   }
-  launch_coefs(theta_dev, w.coef, level->P, batch, 0.5 * (level->d.sigma_l - level->d.sigma_t), level->mixed, s);
+  launch_coefs(theta_dev, w.coef, level->P, batch, 0.5 * (level->d.sigma_l - level->d.sigma_t),
+               level->d.diffusion == MLQ_DIFF_ISO, level->mixed, s);
   if (level->geo.dim == 3)
     launch_apply_full3(level->geo, w.coef, x_dev, d_dev, y_dev, 0.5 * level->io.dt, batch, level->mixed, s);
   else
@@ -657,7 +670,8 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
   if (tet)
     launch_tet_assemble(td, theta_dev, w.coef, batch, d.sigma_t, d.sigma_l - d.sigma_t, mixed, s);
   else
-    launch_coefs(theta_dev, w.coef, level->P, batch, 0.5 * (d.sigma_l - d.sigma_t), mixed, s);
+    launch_coefs(theta_dev, w.coef, level->P, batch, 0.5 * (d.sigma_l - d.sigma_t), d.diffusion == MLQ_DIFF_ISO,
+                 mixed, s);
   launch_init(w, level->nn, batch, d.u_th, s);
   HIP_OK(hipGetLastError());
 

@@ -23,8 +23,12 @@ struct Geo {
   int64_t P;           // elements per sample
   double Hm, Hxx, Hyy, Hzz, Hxy;
   double Hx, Hy, Hz;   // edge lengths
-  double sbar;         // (sigma_l + sigma_t) / 2
-  double st;           // sigma_t
+  // Box elements carry per-sample coefficients (p, q); the conductivity of an element is
+  //   G_xx = cx0 + cx1 p,  G_yy = cy0 + cy1 p,  G_zz = cz0 + cz1 p,  G_xy = q.
+  // Fibre angle model: p, q = (s_l - s_t)/2 (cos 2t, sin 2t), cx0 = cy0 = (s_l + s_t)/2,
+  // cx1 = 1, cy1 = -1, cz0 = s_t, cz1 = 0.  Isotropic scalar model: p = v, q = 0,
+  // cx0 = cy0 = cz0 = 0, cx1 = cy1 = cz1 = 1 (G = v I).
+  double cx0, cx1, cy0, cy1, cz0, cz1;
   int32_t tet;         // 1: P1 tetrahedra (TetDev holds the mesh), 0: Q1 box
   int64_t nnz;         // tetrahedra: stored (padded, slot-major) entries of the vertex adjacency
 };
@@ -119,7 +123,7 @@ struct Work {
 Work carve_workspace(void* base, const Geo& g, int32_t batch, int kmax, bool mixed);
 
 // ---- kernel launchers (mlq_kernels.hip) --------------------------------------
-void launch_coefs(const void* theta, void* coef, int64_t P, int32_t B, double half_dsig, bool mixed,
+void launch_coefs(const void* theta, void* coef, int64_t P, int32_t B, double half_dsig, bool iso, bool mixed,
                   hipStream_t s);
 void launch_init(const Work& w, int64_t nn, int32_t B, double u_th, hipStream_t s);
 // Newton initial guess u = 2 u_k - u_{k-1}

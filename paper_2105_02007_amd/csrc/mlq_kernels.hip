@@ -55,9 +55,11 @@ __device__ inline double diion(double u, const Ionic& io) {
 
 // ---------------------------------------------------------------------------
 // Matrix-free gather of the mass and anisotropic stiffness rows of node i.
-// G_e = sbar I + p_e (e_x e_x^T - e_y e_y^T) + q_e (e_x e_y^T + e_y e_x^T) [+ (st - sbar) e_z e_z^T]
-// which equals eq. (AdmV) with V = sigma_l (cos t, sin t, 0), g = sigma_t when
-// p = (sigma_l - sigma_t)/2 cos 2t and q = (sigma_l - sigma_t)/2 sin 2t.
+// G_e = (cx0 + cx1 p_e) e_x e_x^T + (cy0 + cy1 p_e) e_y e_y^T + q_e (e_x e_y^T + e_y e_x^T)
+//       [+ (cz0 + cz1 p_e) e_z e_z^T]  (the constants of the conductivity model in Geo), which
+// equals eq. (AdmV) with V = sigma_l (cos t, sin t, 0), g = sigma_t for the fibre model
+// (p = (sigma_l - sigma_t)/2 cos 2t, q = (sigma_l - sigma_t)/2 sin 2t) and v I for the
+// isotropic one (p = v, q = 0).
 // xm / xk: the 3^d neighbourhood values of the mass input and stiffness input.
 // Returns SM = sum_e (M_e xm)_a / Hm and SK = sum_e (K_e xk)_a.
 template <typename R, typename TC>
@@ -91,8 +93,8 @@ __host__ __device__ inline void gather3(int ix, int iy, int iz, const Geo& g, co
               sc += (R)(0.25 * (ss(ax) * ss(by) + ss(ay) * ss(bx)) * mm(az, bz)) * xk[nb];
             }
         SM += sm;
-        SK += ((R)g.sbar + p) * (R)g.Hxx * sx + ((R)g.sbar - p) * (R)g.Hyy * sy +
-              (R)g.st * (R)g.Hzz * sz + q * (R)g.Hxy * sc;
+        SK += ((R)g.cx0 + (R)g.cx1 * p) * (R)g.Hxx * sx + ((R)g.cy0 + (R)g.cy1 * p) * (R)g.Hyy * sy +
+              ((R)g.cz0 + (R)g.cz1 * p) * (R)g.Hzz * sz + q * (R)g.Hxy * sc;
       }
 }
 
@@ -122,7 +124,8 @@ __host__ __device__ inline void gather2(int ix, int iy, const Geo& g, const TC* 
           sc += (R)(0.25 * (ss(ax) * ss(by) + ss(ay) * ss(bx))) * xk[nb];
         }
       SM += sm;
-      SK += ((R)g.sbar + p) * (R)g.Hxx * sx + ((R)g.sbar - p) * (R)g.Hyy * sy + q * (R)g.Hxy * sc;
+      SK += ((R)g.cx0 + (R)g.cx1 * p) * (R)g.Hxx * sx + ((R)g.cy0 + (R)g.cy1 * p) * (R)g.Hyy * sy +
+            q * (R)g.Hxy * sc;
     }
 }
 
@@ -171,12 +174,17 @@ __host__ __device__ inline void gather(int ix, int iy, int iz, const Geo& g, con
 }
 
 // ---------------------------------------------------------------------------
-// Per-element coefficients from fibre angles: p = (s_l - s_t)/2 cos 2t, q = (s_l - s_t)/2 sin 2t.
+// Per-element coefficients.  Fibre angles: p = (s_l - s_t)/2 cos 2t, q = (s_l - s_t)/2 sin 2t.
+// Isotropic scalar field (iso): p = v, q = 0.
 template <typename TT, typename TC>
-__global__ void k_coefs(const TT* __restrict__ theta, TC* __restrict__ coef, int64_t total, double half_dsig) {
+__global__ void k_coefs(const TT* __restrict__ theta, TC* __restrict__ coef, int64_t total, double half_dsig,
+                        int iso) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
-  if constexpr (sizeof(TC) == 4) {
+  if (iso) {
+    coef[2 * i] = (TC)theta[i];
+    coef[2 * i + 1] = (TC)0;
+  } else if constexpr (sizeof(TC) == 4) {
     const float t2 = 2.0f * (float)theta[i];
     float sv, cv;
     sincosf(t2, &sv, &cv);
@@ -191,16 +199,16 @@ __global__ void k_coefs(const TT* __restrict__ theta, TC* __restrict__ coef, int
   }
 }
 
-void launch_coefs(const void* theta, void* coef, int64_t P, int32_t B, double half_dsig, bool mixed,
+void launch_coefs(const void* theta, void* coef, int64_t P, int32_t B, double half_dsig, bool iso, bool mixed,
                   hipStream_t s) {
   const int64_t total = P * (int64_t)B;
   const dim3 grid((unsigned)cdiv(total, kBlock));
   if (mixed)
     hipLaunchKernelGGL((k_coefs<float, float>), grid, dim3(kBlock), 0, s, (const float*)theta, (float*)coef,
-                       total, half_dsig);
+                       total, half_dsig, iso ? 1 : 0);
   else
     hipLaunchKernelGGL((k_coefs<double, double>), grid, dim3(kBlock), 0, s, (const double*)theta,
-                       (double*)coef, total, half_dsig);
+                       (double*)coef, total, half_dsig, iso ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------

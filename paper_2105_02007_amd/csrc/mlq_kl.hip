@@ -1,8 +1,9 @@
-// Discrete Karhunen-Loeve basis of the fibre-angle field (Section 2.3) on the
-// nodes of a uniform Q1 box, and its element-midpoint transfer to the element
-// centres of a level (Section 4).
+// Discrete Karhunen-Loeve basis of the random field (fibre angle, or scalar
+// conductivity; Section 2.3) on the nodes of a uniform Q1 box or a tetrahedral mesh,
+// and its element-midpoint transfer to the element centres of a level (Section 4).
 //
 //   eq. (algEig)    M C M v = lambda M v,     C_ij = s^2 exp(-|x_i - x_j|_2 / l)
+//                   (or s^2 exp(-|x_i - x_j|_2^2 / l), the squared-exponential kernel)
 //   C ~ L L^T       pivoted Cholesky (largest remaining diagonal, lowest index on
 //                   ties; columns of C evaluated on the fly on the GPU)
 //   eq. (redEig)    L^T M L v~ = lambda v~ (R x R, cyclic Jacobi on the host)
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(kT) void k_argmax_final(const double* __restrict__ 
 //   L[:, r] = (C[:, p] - L[:, :r] L[p, :r]^T) / sqrt(d_p),  d -= L[:, r]^2,  d_p = 0.
 __global__ __launch_bounds__(kT) void k_chol_col(Box b, double* __restrict__ L, double* __restrict__ d, int r,
                                                  const int64_t* __restrict__ pivp, const double* __restrict__ stat,
-                                                 double s2, double inv_len) {
+                                                 double s2, double inv_len, int sqexp) {
   const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (i >= b.nn) return;
   const int64_t p = pivp[0];
@@ -151,7 +152,8 @@ __global__ __launch_bounds__(kT) void k_chol_col(Box b, double* __restrict__ L, 
   box_xyz(b, i, xi);
   box_xyz(b, p, xp);
   const double dx = xi[0] - xp[0], dy = xi[1] - xp[1], dz = xi[2] - xp[2];
-  double c = s2 * exp(-sqrt(dx * dx + dy * dy + dz * dz) * inv_len);
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  double c = s2 * exp(-(sqexp ? r2 : sqrt(r2)) * inv_len);
   for (int j = 0; j < r; ++j) c -= L[(int64_t)j * b.nn + i] * L[(int64_t)j * b.nn + p];
   const double l = c / sqrt(dp);
   L[(int64_t)r * b.nn + i] = l;
@@ -472,6 +474,7 @@ mlq_status kl_validate(const mlq_kl_desc* kd) {
   if (kd->n_modes < 1 || kd->n_modes > 1024) return MLQ_EINVAL;
   if (kd->max_rank < kd->n_modes || kd->max_rank > 4096 || kd->max_rank > n) return MLQ_EINVAL;
   if (!(kd->std_dev > 0.0) || !(kd->corr_len > 0.0) || !(kd->eps >= 0.0)) return MLQ_EINVAL;
+  if (kd->cov_kernel != MLQ_COV_EXP && kd->cov_kernel != MLQ_COV_SQEXP) return MLQ_EINVAL;
   return MLQ_OK;
 }
 
@@ -533,7 +536,7 @@ mlq_status kl_modes(const mlq_kl_desc* kd, void* ws, double* lambda_host, double
     if (hstat[0] <= 0.0) break;                            // exact low rank reached
     if (r >= M && resid <= kd->eps * tr0) break;           // truncation criterion
     hipLaunchKernelGGL(k_chol_col, dim3((unsigned)cdiv(n, kT)), dim3(kT), 0, s, b, w.L, w.d, r, w.idx, w.stat, s2,
-                       1.0 / kd->corr_len);
+                       1.0 / kd->corr_len, kd->cov_kernel == MLQ_COV_SQEXP ? 1 : 0);
     rank = r + 1;
   }
   if (rank < M) {

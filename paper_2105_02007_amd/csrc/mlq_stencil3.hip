@@ -17,12 +17,14 @@
 //
 // Element operators (edges hx, hy, hz; local node (a, b, c) in {0,1}^3;
 // s(0) = -1, s(1) = +1; M1 = h/6 [[2,1],[1,2]]; K1 = 1/h [[1,-1],[-1,1]]).  With
-//   G = sbar I + p (ex ex^T - ey ey^T) + q (ex ey^T + ey ex^T) + (st - sbar) ez ez^T
-// (eq. (AdmV) for V = sigma_l (cos t, sin t, 0), p = ds/2 cos 2t, q = ds/2 sin 2t):
-//   K_e = [(sbar + p) K1x (x) M1y + (sbar - p) M1x (x) K1y + q (C1x^T (x) C1y + C1x (x) C1y^T)] (x) M1z
-//         + st M1x (x) M1y (x) K1z,      C1[i][j] = int phi_i phi_j' = s(j)/2,
+//   G = G_xx ex ex^T + G_yy ey ey^T + G_xy (ex ey^T + ey ex^T) + G_zz ez ez^T
+// (G_xx = cx0 + cx1 p, G_yy = cy0 + cy1 p, G_zz = cz0 + cz1 p, G_xy = q from the per-element
+// coefficients; eq. (AdmV) for V = sigma_l (cos t, sin t, 0) is G_xx, G_yy = sbar +- p,
+// G_zz = sigma_t with p = ds/2 cos 2t, q = ds/2 sin 2t; the isotropic model is G = v I):
+//   K_e = [G_xx K1x (x) M1y + G_yy M1x (x) K1y + G_xy (C1x^T (x) C1y + C1x (x) C1y^T)] (x) M1z
+//         + G_zz M1x (x) M1y (x) K1z,    C1[i][j] = int phi_i phi_j' = s(j)/2,
 // which on the z-mixed 2x2 layer u = (M1z x)_c reduces to
-//   out_ab = s(a) [(sbar + p) X_b + q Dy / 4] + s(b) [(sbar - p) Y_a + q Dx / 4],
+//   out_ab = s(a) [G_xx X_b + G_xy Dy / 4] + s(b) [G_yy Y_a + G_xy Dx / 4],
 //   X = M1y dx / hx, Y = M1x dy / hy, dx_b = u_1b - u_0b, dy_a = u_a1 - u_a0,
 //   Dx = dx_0 + dx_1, Dy = dy_0 + dy_1.
 #include <type_traits>
@@ -41,8 +43,8 @@ template <typename R>
 struct Elem {
   // element outputs (8, index a + 2b + 4c) of K_e x, with every constant folded into four
   // per-element scalars:
-  //   AX = s (sbar + p) hy hz / (36 hx),  BY = s (sbar - p) hx hz / (36 hy),
-  //   Q4 = s q hz / 24,                   CZ = s st hx hy / (36 hz),
+  //   AX = s G_xx hy hz / (36 hx),  BY = s G_yy hx hz / (36 hy),
+  //   Q4 = s G_xy hz / 24,          CZ = s G_zz hx hy / (36 hz),
   // s = the operator's scale (0 for an element that contributes nothing).
   __host__ __device__ static inline void stiff_f(const R (&x)[8], R AX, R BY, R Q4, R CZ, R (&o)[8]) {
 #pragma unroll
@@ -282,8 +284,9 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     };
     // folded constants of the element operators (uniform)
     const R KX = (R)(g.Hy / (6.0 * g.Hx) * g.Hz / 6.0), KY = (R)(g.Hx / (6.0 * g.Hy) * g.Hz / 6.0);
-    const R KQ = (R)(0.25 * g.Hz / 6.0), KZ = (R)(g.st * g.Hx * g.Hy / (36.0 * g.Hz));
-    const R KM = (R)(g.Hm / 216.0), SB = (R)g.sbar;
+    const R KQ = (R)(0.25 * g.Hz / 6.0), KZ = (R)(g.Hx * g.Hy / (36.0 * g.Hz));
+    const R KM = (R)(g.Hm / 216.0);
+    const R CX0 = (R)g.cx0, CX1 = (R)g.cx1, CY0 = (R)g.cy0, CY1 = (R)g.cy1, CZ0 = (R)g.cz0, CZ1 = (R)g.cz1;
     R sj = 0;
     if constexpr (MODE == kPK) sj = (R)A.inv_eta[(int64_t)sb * (A.kmax + 1) + A.j];
 
@@ -297,7 +300,8 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
         const bool on = slab && elem_xy;
         const R sc = on ? (R)A.ck : (R)0;
         R xin[8] = {lo.k[0], lo.k[1], lo.k[2], lo.k[3], hi.k[0], hi.k[1], hi.k[2], hi.k[3]};
-        Elem<R>::stiff_f(xin, (SB + cp) * (sc * KX), (SB - cp) * (sc * KY), cq * (sc * KQ), sc * KZ, o);
+        Elem<R>::stiff_f(xin, (CX0 + CX1 * cp) * (sc * KX), (CY0 + CY1 * cp) * (sc * KY), cq * (sc * KQ),
+                         (CZ0 + CZ1 * cp) * (sc * KZ), o);
         if constexpr (kMass) {
           R xm[8] = {lo.m[0], lo.m[1], lo.m[2], lo.m[3], hi.m[0], hi.m[1], hi.m[2], hi.m[3]};
           R om[8];

@@ -29,6 +29,8 @@ EXPORTED = [
     "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet",
 ]
 MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE = 0, 1
+MLQ_DIFF_FIBRE, MLQ_DIFF_ISO = 0, 1
+MLQ_COV_EXP, MLQ_COV_SQEXP = 0, 1
 KERNEL_CLASSES = ["apply", "residual", "rhs", "precond", "dots", "orth", "small", "update", "qoi"]
 
 
@@ -57,7 +59,7 @@ class LevelDesc(C.Structure):
         ("xyz", C.POINTER(C.c_double)), ("tets", C.POINTER(C.c_int32)),
         ("e_circ", C.POINTER(C.c_double)), ("e_long", C.POINTER(C.c_double)),
         ("stim_center", C.c_double * 3), ("stim_radius", C.c_double),
-        ("newton_guess", C.c_int32),
+        ("newton_guess", C.c_int32), ("diffusion", C.c_int32),
     ]
 
 
@@ -68,6 +70,7 @@ class KlDesc(C.Structure):
         ("n_modes", C.c_int32), ("max_rank", C.c_int32), ("eps", C.c_double),
         ("mesh_kind", C.c_int32), ("n_vert", C.c_int64), ("n_tet", C.c_int64),
         ("xyz", C.POINTER(C.c_double)), ("tets", C.POINTER(C.c_int32)),
+        ("cov_kernel", C.c_int32),
     ]
 
 
@@ -141,7 +144,8 @@ def _stream(stream=None):
 
 def make_desc(level: dict, phys: dict, *, n_modes=0, phi=None, sqrt_lambda=None, theta0=None,
               prec=MLQ_FP64, qoi=MLQ_QOI_MEAN_U_FINAL, newton_tol=1e-13, inner_tol=1e-6,
-              max_newton=20, max_inner=30, max_batch=1, newton_guess=MLQ_GUESS_PREVIOUS):
+              max_newton=20, max_inner=30, max_batch=1, newton_guess=MLQ_GUESS_PREVIOUS,
+              diffusion=MLQ_DIFF_FIBRE):
     """Fills an mlq_level_desc from a workload level and physics dict.  Returns (desc, keepalive)."""
     d = LevelDesc()
     dim = level["dim"]
@@ -198,6 +202,7 @@ def make_desc(level: dict, phys: dict, *, n_modes=0, phi=None, sqrt_lambda=None,
     d.newton_tol, d.inner_tol = float(newton_tol), float(inner_tol)
     d.max_newton, d.max_inner, d.max_batch = int(max_newton), int(max_inner), int(max_batch)
     d.newton_guess = int(newton_guess)
+    d.diffusion = int(diffusion)
     return d, keep
 
 
@@ -333,8 +338,9 @@ def estimate(kind, f_fine, f_coarse=None, n_per_level=None, n_shifts=1):
                 level_var=list(out.level_var[:L]))
 
 
-def kl_desc(dim, n, lo, hi, std_dev, corr_len, n_modes, max_rank=None, eps=1e-2):
+def kl_desc(dim, n, lo, hi, std_dev, corr_len, n_modes, max_rank=None, eps=1e-2, cov_kernel=MLQ_COV_EXP):
     d = KlDesc()
+    d.cov_kernel = int(cov_kernel)
     d.dim = int(dim)
     for a in range(3):
         d.n[a] = int(n[a]) if a < dim else 1

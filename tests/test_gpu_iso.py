@@ -1,0 +1,117 @@
+"""GPU parity of the isotropic scalar conductivity model (G = v I per element, the paper's
+cube model of Section 5.1) and of the squared-exponential KL kernel against the oracle.
+
+Bars as elsewhere: FP64 apply within 3e-14 of the row scale, FP32 within 2e-6; FP64 solves
+within 1e-10 relative per node and per QoI; KL eigenvalues 1e-10, simple modes 1e-8."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_02007_amd import mlq
+    return torch, mlq
+
+
+def _level(n, steps, hi=None):
+    return dict(dim=3, n=list(n), lo=[0.0] * 3, hi=hi or [1.0] * 3, n_steps=steps)
+
+
+def _positive_field(seed, B, P, mean=3.325e-3, amp=0.3):
+    return mean * (1.0 + amp * (2.0 * W.random_nodal(seed, B, P, 0.0, 1.0) - 1.0))
+
+
+@pytest.mark.parametrize("n,mixed", [([9, 7, 5], False), ([9, 7, 5], True), ([53, 6, 7], False),
+                                     ([61, 5, 9], True)])
+def test_iso_apply_matches_assembled_jacobian(env, n, mixed):
+    torch, mlq = env
+    from oracle import fem
+    from oracle.mesh import BoxMesh
+    phys = W.physics(3)
+    lv = _level(n, 16, hi=[1.0, 0.8, 1.3])
+    B = 3
+    desc, keep = mlq.make_desc(lv, phys, prec=mlq.MLQ_MIXED if mixed else mlq.MLQ_FP64, max_batch=B,
+                               diffusion=mlq.MLQ_DIFF_ISO)
+    level = mlq.Level(desc, keep)
+    mesh = BoxMesh(n, hi=lv["hi"])
+    dt = phys["t_end"] / 16
+    v = _positive_field(3, B, mesh.n_elems)
+    x = W.random_nodal(4, B, mesh.n_nodes)
+    dv = W.random_nodal(5, B, mesh.n_nodes, -0.05, 0.14)
+    tdt = torch.float32 if mixed else torch.float64
+    v_d, x_d, d_d = (torch.as_tensor(a, dtype=tdt, device="cuda") for a in (v, x, dv))
+    y = level.apply(v_d, x_d, d_d).double().cpu().numpy()
+    for b in range(B):
+        vb, xb, db = (a[b].double().cpu().numpy() for a in (v_d, x_d, d_d))
+        M, K = fem.assemble(mesh, fem.conductivity_iso(vb, 3))
+        ref = M @ ((1.0 + db) * xb) + 0.5 * dt * (K @ xb)
+        scale = abs(M) @ np.abs((1.0 + db) * xb) + 0.5 * dt * (abs(K) @ np.abs(xb))
+        tol = (2e-6 if mixed else 3e-14) * scale.max()
+        assert np.abs(y[b] - ref).max() <= tol, (b, np.abs(y[b] - ref).max() / scale.max())
+
+
+def test_iso_solve_fp64_matches_oracle(env):
+    torch, mlq = env
+    from oracle import fem, stepper
+    from oracle.mesh import BoxMesh
+    phys = W.physics(3)
+    n, steps, B = [9, 9, 9], 32, 3
+    desc, keep = mlq.make_desc(_level(n, steps), phys, qoi=mlq.MLQ_QOI_MEAN_ACT_TIME, newton_tol=1e-13,
+                               max_batch=B, diffusion=mlq.MLQ_DIFF_ISO, newton_guess=mlq.MLQ_GUESS_EXTRAPOLATE)
+    level = mlq.Level(desc, keep)
+    mesh = BoxMesh(n)
+    v = _positive_field(8, B, mesh.n_elems)
+    out = level.solve(torch.as_tensor(v, device="cuda"), want_state=True)
+    assert int(out["status"].abs().sum()) == 0
+    u = out["u"].cpu().numpy()
+    q = out["qoi"].cpu().numpy()
+    for b in range(B):
+        r = stepper.solve(mesh, fem.conductivity_iso(v[b], 3), phys, steps, tol=1e-13)
+        assert np.abs(u[b] - r["u"]).max() <= 1e-10 * np.abs(r["u"]).max()
+        assert abs(q[b] - r["mean_act"]) <= 1e-10 * abs(r["mean_act"])
+
+
+def test_iso_model_rejected_on_tetrahedra(env):
+    torch, mlq = env
+    from workloads import tetshell
+    xyz, tets, ec, el, _ = tetshell.shell_mesh((2, 6, 12), seed=5)
+    lvl = dict(kind="tet", dim=3, n_steps=8, mesh=dict(xyz=xyz, tets=tets, e_circ=ec, e_long=el))
+    phys = W.physics(3)
+    c, r = tetshell.stimulus_ball(0.3)
+    phys.update(stim_center=c.tolist(), stim_radius=float(r))
+    desc, keep = mlq.make_desc(lvl, phys, diffusion=mlq.MLQ_DIFF_ISO)
+    with pytest.raises(mlq.MlqError):
+        mlq.Level(desc, keep)
+
+
+@pytest.mark.parametrize("n", [[7, 6, 5], [9, 8, 1]])
+def test_kl_squared_exponential_matches_oracle(env, n):
+    torch, mlq = env
+    from oracle import fem, kl
+    from oracle.mesh import BoxMesh
+    dim = 3 if n[2] > 1 else 2
+    n = n[:dim]
+    mesh = BoxMesh(n)
+    M = fem.assemble_mass(mesh)
+    k = 8
+    lam_ref, V_ref = kl.kl_dense(mesh.nodes, M, 0.3, 0.25, k, kernel="sqexp")
+    # full rank (the factorisation stops early only if a pivot's remaining variance is zero)
+    kd = mlq.kl_desc(dim, n, [0.0] * dim, [1.0] * dim, 0.3, 0.25, k, max_rank=mesh.n_nodes, eps=0.0,
+                     cov_kernel=mlq.MLQ_COV_SQEXP)
+    lam, psi, rank, resid = mlq.kl_modes(kd)
+    assert resid < 1e-12
+    assert np.allclose(lam, lam_ref, rtol=1e-9, atol=0)
+    P = psi.cpu().numpy().T
+    assert np.abs(P.T @ (M @ P) - np.eye(k)).max() < 1e-9
+    gaps = np.abs(np.diff(lam_ref)) > 1e-3 * lam_ref[0]
+    for j in range(k - 1):
+        if gaps[j] and (j == 0 or gaps[j - 1]):
+            ref = V_ref[:, j] / np.sqrt(lam_ref[j])
+            assert np.abs(P[:, j] - ref).max() < 1e-5 * np.abs(ref).max()

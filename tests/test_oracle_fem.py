@@ -179,3 +179,22 @@ def test_stiffness_row_bound_holds_for_any_field():
         _, K = fem.assemble(mesh, G)
         worst = max(worst, np.asarray(abs(K).sum(axis=1)).max())
     assert worst <= bound <= 3.0 * worst
+
+
+def test_isotropic_scalar_model_equals_isotropic_fibre_model():
+    """G = v I (the paper's cube model) equals eq. (AdmV) with sigma_l = sigma_t = v for any
+    fibre direction; its assembled stiffness is v times the Laplacian stiffness."""
+    from oracle import fem
+    mesh = BoxMesh([5, 4, 6])
+    rng = np.random.default_rng(2)
+    v = 3.3e-3 * (1.0 + 0.3 * rng.uniform(-1, 1, mesh.n_elems))
+    th = rng.uniform(0, np.pi, mesh.n_elems)
+    Gi = fem.conductivity_iso(v, 3)
+    Gf = np.stack([fem.conductivity_from_angle(th[e:e + 1], 3, v[e], v[e])[0] for e in range(mesh.n_elems)])
+    assert np.abs(Gi - Gf).max() <= 1e-14 * v.max()  # |V| = v up to rounding
+    _, K = fem.assemble(mesh, Gi)
+    _, K1 = fem.assemble(mesh, fem.conductivity_iso(np.ones(mesh.n_elems), 3))
+    # element by element: K = sum_e v_e K1_e, so a uniform v scales the Laplacian stiffness
+    _, Ku = fem.assemble(mesh, fem.conductivity_iso(np.full(mesh.n_elems, 2.5), 3))
+    assert abs(Ku - 2.5 * K1).max() < 1e-14 * abs(Ku).max()
+    assert np.abs(K @ np.ones(mesh.n_nodes)).max() < 1e-14 * abs(K).max()

@@ -112,3 +112,28 @@ def test_interpolation_and_midpoint_transfer():
     # on the KL grid itself the centre value is the average of the 8 corners
     phi_f = kl.level_basis(fine, vals, fine)
     assert np.allclose(phi_f, vals[fine.elems].mean(axis=1), rtol=1e-14, atol=1e-15)
+
+
+def test_squared_exponential_kernel_is_separable_on_tensor_grids():
+    """exp(-|x - x'|^2 / l) = exp(-dx^2 / l) exp(-dy^2 / l) and M = M_x (x) M_y on a box, so the
+    2D eigenvalues of eq. (algEig) are the products of the 1D ones (s^2 split as s * s).  The
+    exponential kernel exp(-|x - x'| / l) is not separable, which this also tells apart."""
+    nx, ny = 9, 7
+    mx, my = BoxMesh([nx], hi=[1.0]), BoxMesh([ny], hi=[0.8])
+    lx, _ = kl.kl_dense(mx.nodes, fem.assemble_mass(mx), 0.3, 0.25, nx, kernel="sqexp")
+    ly, _ = kl.kl_dense(my.nodes, fem.assemble_mass(my), 1.0, 0.25, ny, kernel="sqexp")
+    m2 = BoxMesh([nx, ny], hi=[1.0, 0.8])
+    M2 = fem.assemble_mass(m2)
+    k = 12
+    l2, _ = kl.kl_dense(m2.nodes, M2, 0.3, 0.25, k, kernel="sqexp")
+    prod = np.sort(np.outer(lx, ly).ravel())[::-1][:k]
+    assert np.allclose(l2, prod, rtol=1e-9, atol=1e-14 * l2[0])
+    le, _ = kl.kl_dense(m2.nodes, M2, 0.3, 0.25, k, kernel="exp")
+    assert not np.allclose(le, prod, rtol=1e-3)
+    # the pivoted-Cholesky route at full rank agrees, with the identities after eq. (redEig)
+    L, _ = kl.pivoted_cholesky(m2.nodes, 0.3, 0.25, m2.n_nodes, kernel="sqexp")
+    C = kl.exp_cov(m2.nodes, m2.nodes, 0.3, 0.25, "sqexp")
+    assert np.abs(L @ L.T - C).max() < 1e-12
+    lam_c, V_c = kl.kl_from_cholesky(L, M2, m2.n_nodes)
+    assert np.allclose(lam_c[:k], l2, rtol=1e-9, atol=1e-14 * l2[0])
+    assert np.isclose(lam_c.sum(), np.sum(C * M2.toarray()), rtol=1e-12)
