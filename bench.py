@@ -66,12 +66,17 @@ WORKLOAD_TEXT = {
     "c5": "non-nested prolate-ellipsoidal shell, P1 tetrahedra 26k/187k/1.4M vertices, 512 steps, 256-mode KL "
           "(l = 0.1 long axis), rule-based +60/-60 deg fibres, combination estimator 16/64/256 nested MC points, "
           "mean activation time",
+    "c5v": "the c5 shells with the paper's heart model: eq. (AdmV) with a random vector field V = sigma_l f0 + W, "
+           "W three independent squared-exponential KL fields (0.3 sigma_l, sigma_KL = 0.64), 3 x 45 uniform "
+           "coordinates, combination estimator 16/64/256 nested MC points, mean activation time",
 }
 
 
 def cpu_baseline_tet(cfg, budget_s):
-    """The oracle on the coarsest shell: one sample (rule-based angle plus a seeded random
-    perturbation in place of the KL field), as many steps as the budget allows."""
+    """The oracle on the coarsest shell: one sample (rule-based angle or mean vector field plus
+    a seeded random perturbation in place of the KL field), as many steps as the budget allows."""
+    import numpy as np
+
     import workloads as W
     from oracle import stepper
     from oracle.tetfem import TetMesh
@@ -79,8 +84,14 @@ def cpu_baseline_tet(cfg, budget_s):
     m = W.tet_mesh(lv)
     mesh = TetMesh(m["xyz"], m["tets"])
     ph = cfg["physics"]
-    th = m["theta0"] + 0.3 * W.random_nodal(cfg["seed"], 1, mesh.n_elems)[0]
-    G = mesh.conductivity(th, m["e_circ"], m["e_long"], ph["sigma_l"], ph["sigma_t"])
+    if cfg.get("model") == "vector":  # E[V] plus a seeded perturbation of each component
+        from oracle import fem
+        f0 = np.cos(m["theta0"])[:, None] * m["e_circ"] + np.sin(m["theta0"])[:, None] * m["e_long"]
+        V = ph["sigma_l"] * (f0 + 0.3 * W.random_nodal(cfg["seed"], 3, mesh.n_elems).T)
+        G = fem.conductivity(V, ph["sigma_t"])
+    else:
+        th = m["theta0"] + 0.3 * W.random_nodal(cfg["seed"], 1, mesh.n_elems)[0]
+        G = mesh.conductivity(th, m["e_circ"], m["e_long"], ph["sigma_l"], ph["sigma_t"])
     t0 = time.perf_counter()
     steps = 2
     while True:  # grow the step count until the budget is used (each run starts from u = 0)
@@ -249,11 +260,13 @@ def main():
     M = cfg["kl"]["n_modes"]
     kind = samp["kind"]
     Ys = Yc = shifts = None
+    draw = W.mc_uniforms if cfg["kl"].get("variables") == "uniform" else W.mc_normals
+    n_dims = M * int(cfg["kl"].get("components", 1))
     if kind == "combination":
-        Yc = torch.as_tensor(W.mc_normals(cfg["seed"], 0, max(samp["n_per_level"]), M), device=dev)
+        Yc = torch.as_tensor(draw(cfg["seed"], 0, max(samp["n_per_level"]), n_dims), device=dev)
         step = lambda: runner.run_combination(Yc)
     elif kind in ("mc", "mlmc"):
-        Ys = [torch.as_tensor(W.mc_normals(cfg["seed"], l, n, M), device=dev)
+        Ys = [torch.as_tensor(draw(cfg["seed"], l, n, n_dims), device=dev)
               for l, n in enumerate(samp["n_per_level"])]
         if kind == "mc":
             step = lambda: runner.run_mc(Ys[0])

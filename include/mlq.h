@@ -60,7 +60,7 @@ typedef enum { MLQ_FP64 = 0, MLQ_MIXED = 1 } mlq_precision;
 typedef enum { MLQ_QOI_MEAN_U_FINAL = 0, MLQ_QOI_MEAN_ACT_TIME = 1 } mlq_qoi;
 typedef enum { MLQ_MESH_Q1_BOX = 0, MLQ_MESH_P1_TET = 1 } mlq_mesh_kind;
 typedef enum { MLQ_GUESS_PREVIOUS = 0, MLQ_GUESS_EXTRAPOLATE = 1 } mlq_newton_guess;
-typedef enum { MLQ_DIFF_FIBRE = 0, MLQ_DIFF_ISO = 1 } mlq_diffusion;
+typedef enum { MLQ_DIFF_FIBRE = 0, MLQ_DIFF_ISO = 1, MLQ_DIFF_VECTOR = 2 } mlq_diffusion;
 typedef enum { MLQ_COV_EXP = 0, MLQ_COV_SQEXP = 1 } mlq_cov_kernel;
 
 /* per-sample status codes written by mlq_solve_batch */
@@ -115,8 +115,12 @@ typedef struct {
    * angle theta, G = sigma_t I + (sigma_l - sigma_t) f f^T with f = (cos theta, sin theta[, 0]),
    * eq. (AdmV) with V = sigma_l f; MLQ_DIFF_ISO: the field is a scalar conductivity v > 0,
    * G = v I (isotropic diffusion, the paper's cube experiments of Section 5.2; sigma_l,
-   * sigma_t unused).  Tetrahedra: MLQ_DIFF_FIBRE only. */
+   * sigma_t unused); MLQ_DIFF_VECTOR (tetrahedra): eq. (AdmV) itself with a random vector
+   * field, G = g I + (|V| - g) V V^T / V^T V, g = sigma_t, V = v_mean + the field, whose three
+   * components the solve and apply calls take component-major ([3][B][P]: component c of
+   * sample b at (c B + b) P + e).  Tetrahedra: MLQ_DIFF_FIBRE or MLQ_DIFF_VECTOR. */
   int32_t diffusion;
+  const double* v_mean;               /* MLQ_DIFF_VECTOR: n_tet x 3 host array, E[V] per element */
 } mlq_level_desc;
 
 typedef struct mlq_level mlq_level; /* opaque */

@@ -154,7 +154,7 @@ namespace {
 
 struct BlobLayout {
   size_t phi64, phi32, sl, th0, fbox, wts, tri;
-  size_t ecol, ediag, em, em32, mdiag, mdiag32, ecptr, ecdat, geo;  // tetrahedral levels
+  size_t ecol, ediag, em, em32, mdiag, mdiag32, ecptr, ecdat, geo, vmean;  // tetrahedral levels
   size_t total;
 };
 
@@ -178,6 +178,7 @@ BlobLayout blob_layout(int64_t P, int64_t M, int64_t nn, int64_t nmax, const mlq
     L.ecptr = o;   o = align256(o + sizeof(int32_t) * (th->nell + 1));
     L.ecdat = o;   o = align256(o + sizeof(int32_t) * th->nc);
     L.geo = o;     o = align256(o + sizeof(double) * mlq::kTetGeo * th->nt);
+    L.vmean = o;   o = align256(o + sizeof(double) * 3 * th->nt);
   }
   L.total = o;
   return L;
@@ -215,10 +216,13 @@ mlq_status validate(const mlq_level_desc* d) {
   if (d->max_batch < 1 || d->max_batch > 65535) return fail(MLQ_EINVAL, "max_batch must be in [1, 65535]");
   if (d->newton_guess != MLQ_GUESS_PREVIOUS && d->newton_guess != MLQ_GUESS_EXTRAPOLATE)
     return fail(MLQ_EINVAL, "newton_guess must be MLQ_GUESS_PREVIOUS or MLQ_GUESS_EXTRAPOLATE");
-  if (d->diffusion != MLQ_DIFF_FIBRE && d->diffusion != MLQ_DIFF_ISO)
-    return fail(MLQ_EINVAL, "diffusion must be MLQ_DIFF_FIBRE or MLQ_DIFF_ISO");
+  if (d->diffusion != MLQ_DIFF_FIBRE && d->diffusion != MLQ_DIFF_ISO && d->diffusion != MLQ_DIFF_VECTOR)
+    return fail(MLQ_EINVAL, "diffusion must be MLQ_DIFF_FIBRE, MLQ_DIFF_ISO or MLQ_DIFF_VECTOR");
   if (d->diffusion == MLQ_DIFF_ISO && d->mesh_kind != MLQ_MESH_Q1_BOX)
     return fail(MLQ_EINVAL, "the isotropic scalar diffusion model is for boxes");
+  if (d->diffusion == MLQ_DIFF_VECTOR && d->mesh_kind != MLQ_MESH_P1_TET)
+    return fail(MLQ_EINVAL, "the vector diffusion model is for tetrahedra");
+  if (d->diffusion == MLQ_DIFF_VECTOR && d->v_mean == nullptr) return fail(MLQ_EINVAL, "v_mean is NULL");
   // uniqueness of the step equation: dt * |min I_ion'| < 1 (min over u of the cubic's derivative)
   const double dt = d->t_end / d->n_steps;
   const double r = d->u_rest, t = d->u_th, p = d->u_peak;
@@ -536,6 +540,8 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
     t.ecptr = (const int32_t*)(base + L.ecptr);
     t.ecdat = (const int32_t*)(base + L.ecdat);
     t.geo = (const double*)(base + L.geo);
+    t.vec = desc->diffusion == MLQ_DIFF_VECTOR ? 1 : 0;
+    t.vmean = (const double*)(base + L.vmean);
     std::vector<float> m32(th.em.begin(), th.em.end()), d32(th.mdiag.begin(), th.mdiag.end());
     auto up = [&](const void* dst, const void* src, size_t bytes) {
       if (e == hipSuccess) e = hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, s);
@@ -549,6 +555,7 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
     up(t.ecptr, th.ecptr.data(), sizeof(int32_t) * th.ecptr.size());
     up(t.ecdat, th.ecdat.data(), sizeof(int32_t) * th.ecdat.size());
     up(t.geo, th.geo.data(), sizeof(double) * th.geo.size());
+    if (t.vec) up(t.vmean, desc->v_mean, sizeof(double) * 3 * th.nt);
     // the host vectors must outlive the asynchronous copies
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }

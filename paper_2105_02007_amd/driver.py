@@ -37,20 +37,27 @@ class ConfigRunner:
         M = kcfg["n_modes"]
         kl_level = cfg["levels"][kcfg["grid_level"]]
         self.tet = kl_level.get("kind") == "tet"
+        # the paper's vector model: `components` independent fields with the same KL basis
+        # (block-diagonal covariance), uniform coordinates (modes scaled by sqrt(3 lambda))
+        self.vector = cfg.get("model") == "vector"
+        self.components = int(kcfg.get("components", 1))
+        self.uniform = kcfg.get("variables") == "uniform"
+        cov = mlq.MLQ_COV_SQEXP if kcfg.get("kernel") == "sqexp" else mlq.MLQ_COV_EXP
+        std = kcfg["std"] * (self.phys["sigma_l"] if self.vector else 1.0)
         if self.tet:
             # tetrahedral levels: the seeded shells of the workload (non-nested), the KL on
             # the vertices of the finest one, the transfer by point location
             self.meshes = [W.tet_mesh(lv) for lv in cfg["levels"]]
-            self.kd = mlq.kl_desc_tet(self.meshes[kcfg["grid_level"]], kcfg["std"], kcfg["corr_len"], M,
-                                      max_rank=kl_rank_factor * M, eps=kl_eps)
+            self.kd = mlq.kl_desc_tet(self.meshes[kcfg["grid_level"]], std, kcfg["corr_len"], M,
+                                      max_rank=kl_rank_factor * M, eps=kl_eps, cov_kernel=cov)
         else:
-            self.kd = mlq.kl_desc(cfg["dim"], kl_level["n"], kl_level["lo"], kl_level["hi"], kcfg["std"],
-                                  kcfg["corr_len"], M, max_rank=kl_rank_factor * M, eps=kl_eps)
+            self.kd = mlq.kl_desc(cfg["dim"], kl_level["n"], kl_level["lo"], kl_level["hi"], std,
+                                  kcfg["corr_len"], M, max_rank=kl_rank_factor * M, eps=kl_eps, cov_kernel=cov)
         say("KL set-up")
         lam, psi, self.kl_rank, self.kl_resid = mlq.kl_modes(self.kd, device=device)
         say(f"KL modes done (rank {self.kl_rank})")
         self.lam = lam
-        sl = torch.as_tensor(np.sqrt(lam), dtype=torch.float64, device=device)
+        sl = torch.as_tensor(np.sqrt((3.0 if self.uniform else 1.0) * lam), dtype=torch.float64, device=device)
         self.levels = []
         samp = cfg["sampling"]
         n_shifts = samp.get("n_shifts", 1)
@@ -64,19 +71,24 @@ class ConfigRunner:
                 nb = samp["n_per_level"][l] * n_shifts
                 if l + 1 < len(cfg["levels"]):
                     nb = max(nb, samp["n_per_level"][l + 1] * n_shifts)
-            theta0 = None
+            theta0 = v_mean = None
             if self.tet:
                 mesh = self.meshes[l]
                 lv = dict(lv, mesh=mesh)
                 phi = mlq.kl_transfer_tet(self.kd, psi, mesh, device=device)
-                theta0 = torch.as_tensor(mesh["theta0"], dtype=torch.float64, device=device)
+                if self.vector:  # E[V] = sigma_l f0 with the rule-based fibre f0
+                    th = mesh["theta0"][:, None]
+                    v_mean = self.phys["sigma_l"] * (np.cos(th) * mesh["e_circ"] + np.sin(th) * mesh["e_long"])
+                else:
+                    theta0 = torch.as_tensor(mesh["theta0"], dtype=torch.float64, device=device)
             else:
                 phi = mlq.kl_transfer(self.kd, psi, lv, device=device)
             desc, keep = mlq.make_desc(
                 lv, self.phys, n_modes=M, phi=phi, sqrt_lambda=sl, theta0=theta0, prec=self.prec, qoi=cfg["qoi"],
                 newton_tol=newton_tol if newton_tol is not None else (1e-13 if self.prec == mlq.MLQ_FP64 else 1e-10),
                 inner_tol=inner_tol if inner_tol is not None else (1e-6 if self.prec == mlq.MLQ_FP64 else 1e-5),
-                max_inner=max_inner, max_batch=nb, newton_guess=newton_guess)
+                max_inner=max_inner, max_batch=nb, newton_guess=newton_guess,
+                diffusion=mlq.MLQ_DIFF_VECTOR if self.vector else mlq.MLQ_DIFF_FIBRE, v_mean=v_mean)
             L = mlq.Level(desc, keep, device=device)
             L._keep = None  # arrays were copied into the level blob
             self.levels.append(L)
@@ -105,7 +117,12 @@ class ConfigRunner:
         """QoIs (device FP64) of the samples Y (M x B, device FP64) on level l."""
         L = self.levels[l]
         t0 = time.perf_counter()
-        theta = L.sample_fields(Y)
+        if self.vector:  # Y stacks the coordinates of the components: (components x M, B)
+            M = self.kd.n_modes
+            theta = torch.stack([L.sample_fields(Y[c * M:(c + 1) * M].contiguous())
+                                 for c in range(self.components)])
+        else:
+            theta = L.sample_fields(Y)
         out = L.solve(theta)
         if out["code"] != mlq.MLQ_OK:
             st = out["status"].cpu().numpy()

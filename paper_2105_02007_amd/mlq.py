@@ -29,7 +29,7 @@ EXPORTED = [
     "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet",
 ]
 MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE = 0, 1
-MLQ_DIFF_FIBRE, MLQ_DIFF_ISO = 0, 1
+MLQ_DIFF_FIBRE, MLQ_DIFF_ISO, MLQ_DIFF_VECTOR = 0, 1, 2
 MLQ_COV_EXP, MLQ_COV_SQEXP = 0, 1
 KERNEL_CLASSES = ["apply", "residual", "rhs", "precond", "dots", "orth", "small", "update", "qoi"]
 
@@ -59,7 +59,7 @@ class LevelDesc(C.Structure):
         ("xyz", C.POINTER(C.c_double)), ("tets", C.POINTER(C.c_int32)),
         ("e_circ", C.POINTER(C.c_double)), ("e_long", C.POINTER(C.c_double)),
         ("stim_center", C.c_double * 3), ("stim_radius", C.c_double),
-        ("newton_guess", C.c_int32), ("diffusion", C.c_int32),
+        ("newton_guess", C.c_int32), ("diffusion", C.c_int32), ("v_mean", C.POINTER(C.c_double)),
     ]
 
 
@@ -145,7 +145,7 @@ def _stream(stream=None):
 def make_desc(level: dict, phys: dict, *, n_modes=0, phi=None, sqrt_lambda=None, theta0=None,
               prec=MLQ_FP64, qoi=MLQ_QOI_MEAN_U_FINAL, newton_tol=1e-13, inner_tol=1e-6,
               max_newton=20, max_inner=30, max_batch=1, newton_guess=MLQ_GUESS_PREVIOUS,
-              diffusion=MLQ_DIFF_FIBRE):
+              diffusion=MLQ_DIFF_FIBRE, v_mean=None):
     """Fills an mlq_level_desc from a workload level and physics dict.  Returns (desc, keepalive)."""
     d = LevelDesc()
     dim = level["dim"]
@@ -203,6 +203,10 @@ def make_desc(level: dict, phys: dict, *, n_modes=0, phi=None, sqrt_lambda=None,
     d.max_newton, d.max_inner, d.max_batch = int(max_newton), int(max_inner), int(max_batch)
     d.newton_guess = int(newton_guess)
     d.diffusion = int(diffusion)
+    if v_mean is not None:  # vector model: E[V] per element (n_tet, 3)
+        vm = np.ascontiguousarray(v_mean, dtype=np.float64)
+        keep.append(vm)
+        d.v_mean = vm.ctypes.data_as(C.POINTER(C.c_double))
     return d, keep
 
 
@@ -256,8 +260,9 @@ class Level:
         return theta
 
     def solve(self, theta, n_steps=None, want_state=False):
+        """theta: (B, P) field, or (3, B, P) components of the vector model."""
         import torch
-        B = theta.shape[0]
+        B = theta.shape[-2]
         ws, nbytes = self.workspace(B)
         qoi = torch.empty(B, dtype=torch.float64, device=self.device)
         status = torch.empty(B, dtype=torch.int32, device=self.device)
@@ -287,7 +292,7 @@ class Level:
 
     def apply(self, theta, x, d, y=None):
         import torch
-        B = theta.shape[0]
+        B = theta.shape[-2]
         ws, nbytes = self.workspace(B)
         if y is None:
             y = torch.empty_like(x)
@@ -353,9 +358,10 @@ def kl_desc(dim, n, lo, hi, std_dev, corr_len, n_modes, max_rank=None, eps=1e-2,
     return d
 
 
-def kl_desc_tet(mesh: dict, std_dev, corr_len, n_modes, max_rank=None, eps=1e-2):
+def kl_desc_tet(mesh: dict, std_dev, corr_len, n_modes, max_rank=None, eps=1e-2, cov_kernel=MLQ_COV_EXP):
     """KL descriptor on the vertices of a tetrahedral mesh (mesh["xyz"], mesh["tets"])."""
     d = KlDesc()
+    d.cov_kernel = int(cov_kernel)
     xyz = np.ascontiguousarray(mesh["xyz"], dtype=np.float64)
     tets = np.ascontiguousarray(mesh["tets"], dtype=np.int32)
     d.dim, d.mesh_kind = 3, MLQ_MESH_P1_TET

@@ -186,3 +186,118 @@ def test_c5_pipeline_small_matches_oracle(env):
     for j in range(L + 1):
         assert np.abs(res["f_fine"][j] - f[j]).max() <= 1e-10 * np.abs(f[j]).max(), j
     assert abs(res["estimate"] - est) <= 1e-10 * abs(est)
+
+
+def _vector_fields(mesh_d, mesh, B, sigma_l, amp=0.3, seed=21):
+    """E[V] = sigma_l f0 (rule-based fibre) and B seeded perturbations of its three components."""
+    f0 = np.cos(mesh_d["theta0"])[:, None] * mesh_d["e_circ"] + np.sin(mesh_d["theta0"])[:, None] * mesh_d["e_long"]
+    vmean = sigma_l * f0
+    W3 = sigma_l * amp * W.random_nodal(seed, 3 * B, mesh.n_elems).reshape(3, B, mesh.n_elems)
+    return vmean, W3
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_tet_vector_model_apply_matches_assembled_jacobian(env, mixed):
+    """eq. (AdmV) with a random vector field V = E[V] + W per element (the paper's heart model)."""
+    torch, mlq = env
+    from oracle import fem
+    from oracle.tetfem import TetMesh
+    mesh_d, th0 = _shell((3, 10, 20))
+    mesh_d["theta0"] = th0
+    ph = _phys()
+    steps, B = 16, 3
+    mesh = TetMesh(mesh_d["xyz"], mesh_d["tets"])
+    vmean, W3 = _vector_fields(mesh_d, mesh, B, ph["sigma_l"])
+    lvl = dict(kind="tet", dim=3, n_steps=steps, mesh=mesh_d)
+    desc, keep = mlq.make_desc(lvl, ph, prec=mlq.MLQ_MIXED if mixed else mlq.MLQ_FP64, max_batch=B,
+                               diffusion=mlq.MLQ_DIFF_VECTOR, v_mean=vmean)
+    lv = mlq.Level(desc, keep)
+    dt = ph["t_end"] / steps
+    x = W.random_nodal(4, B, mesh.n_nodes)
+    dv = W.random_nodal(5, B, mesh.n_nodes, -0.05, 0.14)
+    tdt = torch.float32 if mixed else torch.float64
+    w_d = torch.as_tensor(W3, dtype=tdt, device="cuda")
+    x_d = torch.as_tensor(x, dtype=tdt, device="cuda")
+    d_d = torch.as_tensor(dv, dtype=tdt, device="cuda")
+    y = lv.apply(w_d, x_d, d_d).double().cpu().numpy()
+    for b in range(B):
+        Wb = w_d[:, b].double().cpu().numpy().T
+        xb, db = (a[b].double().cpu().numpy() for a in (x_d, d_d))
+        M, K = mesh.assemble(fem.conductivity(vmean + Wb, ph["sigma_t"]))
+        ref = M @ ((1.0 + db) * xb) + 0.5 * dt * (K @ xb)
+        scale = abs(M) @ np.abs((1.0 + db) * xb) + 0.5 * dt * (abs(K) @ np.abs(xb))
+        tol = (2e-6 if mixed else 1e-13) * scale.max()
+        assert np.abs(y[b] - ref).max() <= tol, (b, np.abs(y[b] - ref).max() / scale.max())
+
+
+def test_tet_vector_model_solve_fp64_matches_oracle(env):
+    torch, mlq = env
+    from oracle import fem, stepper
+    from oracle.tetfem import TetMesh
+    mesh_d, th0 = _shell((2, 6, 12))
+    mesh_d["theta0"] = th0
+    ph = _phys()
+    steps, B = 32, 2
+    mesh = TetMesh(mesh_d["xyz"], mesh_d["tets"])
+    vmean, W3 = _vector_fields(mesh_d, mesh, B, ph["sigma_l"])
+    lvl = dict(kind="tet", dim=3, n_steps=steps, mesh=mesh_d)
+    desc, keep = mlq.make_desc(lvl, ph, qoi=W.QOI_MEAN_ACT_TIME, newton_tol=1e-13, max_batch=B,
+                               diffusion=mlq.MLQ_DIFF_VECTOR, v_mean=vmean,
+                               newton_guess=mlq.MLQ_GUESS_EXTRAPOLATE)
+    lv = mlq.Level(desc, keep)
+    out = lv.solve(torch.as_tensor(W3, device="cuda"), want_state=True)
+    assert int(out["status"].abs().sum()) == 0
+    u = out["u"].cpu().numpy()
+    q = out["qoi"].cpu().numpy()
+    for b in range(B):
+        G = fem.conductivity(vmean + W3[:, b].T, ph["sigma_t"])
+        r = stepper.solve(mesh, G, ph, steps, tol=1e-13)
+        assert np.abs(u[b] - r["u"]).max() <= 1e-10 * np.abs(r["u"]).max()
+        assert abs(q[b] - r["mean_act"]) <= 1e-10 * abs(r["mean_act"])
+
+
+def test_c5v_pipeline_small_matches_oracle(env):
+    """The paper's heart model end to end at small size through the driver: squared-exponential
+    KL on the finest shell, three uniform-coordinate components, point-location transfer,
+    vector-field solves, combination estimator, against the oracle's own pipeline (FP64)."""
+    torch, mlq = env
+    from oracle import estimators, fem, kl, stepper
+    from oracle.tetfem import TetMesh
+    from paper_2105_02007_amd.driver import ConfigRunner
+    cfg = W.config("c5v")
+    cfg["levels"] = W._tet_levels([(2, 6, 12), (3, 8, 16), (4, 10, 20)], [12, 12, 12], 6)
+    cfg["kl"]["n_modes"] = 5
+    cfg["sampling"]["n_per_level"] = [2, 3, 4]
+    cfg["prec"] = W.PREC_FP64
+    M = cfg["kl"]["n_modes"]
+    n_kl = (cfg["levels"][-1]["cells"][0] + 1) * (cfg["levels"][-1]["cells"][1] + 1) * cfg["levels"][-1]["cells"][2]
+    factor = n_kl // M
+    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0)
+    Y = W.mc_uniforms(cfg["seed"], 0, 4, 3 * M)
+    res = runner.run_combination(torch.as_tensor(Y, device="cuda"))
+    ph = cfg["physics"]
+    meshes = [W.tet_mesh(lv) for lv in cfg["levels"]]
+    tm = [TetMesh(m["xyz"], m["tets"]) for m in meshes]
+    Mk, _ = tm[-1].assemble(np.zeros((tm[-1].n_elems, 3, 3)))
+    lam, psi = kl.kl_modes(tm[-1], Mk, cfg["kl"]["std"] * ph["sigma_l"], cfg["kl"]["corr_len"], M,
+                           max_rank=factor * M, eps=0.0, kernel="sqexp")
+    npl = cfg["sampling"]["n_per_level"]
+    L = len(meshes) - 1
+    f = []
+    for j in range(L + 1):
+        m = meshes[j]
+        phi = tm[-1].interpolate(psi, tm[j].centres)
+        f0 = np.cos(m["theta0"])[:, None] * m["e_circ"] + np.sin(m["theta0"])[:, None] * m["e_long"]
+        n = npl[L - j]
+        comps = [kl.field(np.zeros(tm[j].n_elems), phi, np.sqrt(3.0 * lam), Y[c * M:(c + 1) * M, :n])
+                 for c in range(3)]                                  # each (n, P)
+        vals = []
+        for b in range(n):
+            V = ph["sigma_l"] * f0 + np.stack([comps[c][b] for c in range(3)], axis=1)
+            G = fem.conductivity(V, ph["sigma_t"])
+            vals.append(stepper.solve(tm[j], G, ph, cfg["levels"][j]["n_steps"], tol=1e-13)["mean_act"])
+        f.append(np.array(vals))
+    est = estimators.combination(f, npl)
+    for j in range(L + 1):
+        assert np.abs(res["f_fine"][j] - f[j]).max() <= 1e-10 * np.abs(f[j]).max(), j
+    assert abs(res["estimate"] - est) <= 1e-10 * abs(est)

@@ -198,3 +198,18 @@ def test_isotropic_scalar_model_equals_isotropic_fibre_model():
     _, Ku = fem.assemble(mesh, fem.conductivity_iso(np.full(mesh.n_elems, 2.5), 3))
     assert abs(Ku - 2.5 * K1).max() < 1e-14 * abs(Ku).max()
     assert np.abs(K @ np.ones(mesh.n_nodes)).max() < 1e-14 * abs(K).max()
+
+
+def test_vector_field_conductivity_eigenstructure():
+    """eq. (AdmV) for a general vector field: G V = |V| V and G n = g n for n orthogonal to V,
+    so G is SPD with eigenvalues g (twice) and |V| whenever V != 0."""
+    from oracle import fem
+    rng = np.random.default_rng(4)
+    V = rng.normal(size=(50, 3)) * 3e-3
+    g = 1.625e-3
+    G = fem.conductivity(V, g)
+    nv = np.linalg.norm(V, axis=1)
+    assert np.allclose(np.einsum("eij,ej->ei", G, V), nv[:, None] * V, rtol=0, atol=1e-15 * nv.max() ** 2)
+    n = np.cross(V, rng.normal(size=(50, 3)))
+    assert np.allclose(np.einsum("eij,ej->ei", G, n), g * n, rtol=0, atol=1e-15 * np.abs(n).max())
+    assert np.allclose(G, np.transpose(G, (0, 2, 1)), rtol=0, atol=0)

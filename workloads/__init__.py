@@ -105,6 +105,19 @@ CONFIGS = {
         kl=dict(n_modes=256, corr_len=0.1 * tetshell.LONG_AXIS, std=0.3, grid_level=2),
         sampling=dict(kind="combination", n_per_level=[16, 64, 256]),
         qoi=QOI_MEAN_ACT_TIME, prec=PREC_MIXED, seed=5),
+    # the paper's own heart model (Section 5.1) on the c5 shells: eq. (AdmV) with a random
+    # vector field V = sigma_l f0 + W, f0 the rule-based fibre, W three independent components
+    # with the squared-exponential covariance (0.3 sigma_l)^2 exp(-|x - x'|^2 / sigma_KL),
+    # uniform coordinates on [-1, 1] (modes scaled by sqrt(3 lambda)), 45 modes per component
+    "c5v": dict(
+        name="c5v", title="non-nested shells with the paper's heart model: random fibre vector field, "
+                          "uniform coordinates, 3 x 45 modes, combination estimator",
+        dim=3, levels=_tet_levels([(4, 40, 128), (8, 80, 256), (16, 160, 512)], [512, 512, 512], 5),
+        kl=dict(n_modes=45, corr_len=0.16 * (tetshell.LONG_AXIS / 1.0) ** 2, std=0.3, grid_level=2,
+                kernel="sqexp", components=3, variables="uniform"),
+        model="vector",
+        sampling=dict(kind="combination", n_per_level=[16, 64, 256]),
+        qoi=QOI_MEAN_ACT_TIME, prec=PREC_MIXED, seed=6),
 }
 
 # solver tolerances: normwise backward error of the nonlinear step equation
@@ -155,6 +168,13 @@ def mc_normals(seed: int, level: int, n_samples: int, n_modes: int, stream: int 
     """
     g = _gen(seed, level, stream, 0x4D43)
     return np.ascontiguousarray(g.standard_normal((n_samples, n_modes)).T)
+
+
+def mc_uniforms(seed: int, level: int, n_samples: int, n_dims: int, stream: int = 0) -> np.ndarray:
+    """Uniform coordinates on [-1, 1], shape (n_dims, n_samples), column i = sample i (drawn
+    as for mc_normals: sample i does not depend on how many samples are drawn)."""
+    g = _gen(seed, level, stream, 0x4D55)
+    return np.ascontiguousarray(g.uniform(-1.0, 1.0, (n_samples, n_dims)).T)
 
 
 def lattice_shifts(seed: int, level: int, n_shifts: int, n_dims: int) -> np.ndarray:
