@@ -63,6 +63,9 @@ WORKLOAD_TEXT = {
           "mean activation time, FP32 inner + FP64 Newton residual",
     "c4": "3D unit cube Q1 9^3..129^3 nested, 32..512 steps, 128-mode KL, MLQMC 16 shifts x 256/64/16/4/1, "
           "mean activation time",
+    "c2i": "the paper's cube model: isotropic G = max(v, 0.1 E[V]) I, v = E[V] + W, E[V] = 3.325e-3, W a "
+           "squared-exponential KL field (0.3 E[V], sigma_KL = 0.25) with 66 uniform coordinates, 3D unit cube "
+           "Q1 9^3..65^3 nested, 32..256 steps, MLMC 2048/512/128/32 samples, mean activation time, FP64",
     "c5": "non-nested prolate-ellipsoidal shell, P1 tetrahedra 26k/187k/1.4M vertices, 512 steps, 256-mode KL "
           "(l = 0.1 long axis), rule-based +60/-60 deg fibres, combination estimator 16/64/256 nested MC points, "
           "mean activation time",
@@ -128,12 +131,13 @@ def cpu_baseline(cfg, budget_s):
         for i in range(8):
             plan += [(1, i), (0, 8 + i)]
     done = []
+    draw = W.mc_uniforms if cfg["kl"].get("variables") == "uniform" else W.mc_normals
     for l, i in plan:
         if time.perf_counter() - t0 > budget_s:
             break
-        Y = W.mc_normals(cfg["seed"], l, i + 1, M)[:, i:i + 1]
-        th = run.sample_theta(B["phi"][l], B["sqrt_lam"], Y)[0]
-        out = run.solve_theta(meshes[l], th, phys, cfg["levels"][l]["n_steps"])
+        Y = draw(cfg["seed"], l, i + 1, M)[:, i:i + 1]
+        th = run.sample_theta(B["phi"][l], B["sqrt_lam"], Y, run.level_theta0(cfg, meshes[l]))[0]
+        out = run.solve_theta(meshes[l], th, phys, cfg["levels"][l]["n_steps"], model=cfg.get("model"))
         n = meshes[l].n_nodes
         dof_iters += n * out["lin_iters"]
         st_dof += n * cfg["levels"][l]["n_steps"]

@@ -113,9 +113,9 @@ typedef struct {
   int32_t newton_guess;               /* mlq_newton_guess */
   /* Conductivity model of the elements (boxes): MLQ_DIFF_FIBRE: the field is the fibre
    * angle theta, G = sigma_t I + (sigma_l - sigma_t) f f^T with f = (cos theta, sin theta[, 0]),
-   * eq. (AdmV) with V = sigma_l f; MLQ_DIFF_ISO: the field is a scalar conductivity v > 0,
-   * G = v I (isotropic diffusion, the paper's cube experiments of Section 5.2; sigma_l,
-   * sigma_t unused); MLQ_DIFF_VECTOR (tetrahedra): eq. (AdmV) itself with a random vector
+   * eq. (AdmV) with V = sigma_l f; MLQ_DIFF_ISO: the field is a scalar conductivity v,
+   * G = max(v, sigma_t) I (isotropic diffusion, the paper's cube experiments of Section 5.2;
+   * sigma_t is the lower bound b_min that keeps G positive definite, sigma_l is unused); MLQ_DIFF_VECTOR (tetrahedra): eq. (AdmV) itself with a random vector
    * field, G = g I + (|V| - g) V V^T / V^T V, g = sigma_t, V = v_mean + the field, whose three
    * components the solve and apply calls take component-major ([3][B][P]: component c of
    * sample b at (c B + b) P + e).  Tetrahedra: MLQ_DIFF_FIBRE or MLQ_DIFF_VECTOR. */

@@ -47,9 +47,10 @@ def conductivity_from_angle(theta, d, sigma_l, sigma_t):
     return conductivity(sigma_l * fibre_direction(theta, d), sigma_t)
 
 
-def conductivity_iso(v, d):
-    """Isotropic scalar conductivity G = v I per element (the paper's cube model, Section 5.1)."""
-    v = np.asarray(v, dtype=np.float64)
+def conductivity_iso(v, d, floor=0.0):
+    """Isotropic scalar conductivity G = max(v, floor) I per element (the paper's cube model,
+    Section 5.1; the floor is the lower bound b_min the model assumes)."""
+    v = np.maximum(np.asarray(v, dtype=np.float64), floor)
     return v[..., None, None] * np.broadcast_to(np.eye(d), v.shape + (d, d))
 
 

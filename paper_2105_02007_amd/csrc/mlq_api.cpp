@@ -636,8 +636,9 @@ mlq_status mlq_apply(mlq_level* level, const void* theta_dev, int32_t batch, con
     HIP_OK(hipGetLastError());
     return MLQ_OK;
   }
-  launch_coefs(theta_dev, w.coef, level->P, batch, 0.5 * (level->d.sigma_l - level->d.sigma_t),
-               level->d.diffusion == MLQ_DIFF_ISO, level->mixed, s);
+  const bool iso = level->d.diffusion == MLQ_DIFF_ISO;
+  launch_coefs(theta_dev, w.coef, level->P, batch, iso ? level->d.sigma_t : 0.5 * (level->d.sigma_l - level->d.sigma_t),
+               iso, level->mixed, s);
   if (level->geo.dim == 3)
     launch_apply_full3(level->geo, w.coef, x_dev, d_dev, y_dev, 0.5 * level->io.dt, batch, level->mixed, s);
   else
@@ -677,7 +678,8 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
   if (tet)
     launch_tet_assemble(td, theta_dev, w.coef, batch, d.sigma_t, d.sigma_l - d.sigma_t, mixed, s);
   else
-    launch_coefs(theta_dev, w.coef, level->P, batch, 0.5 * (d.sigma_l - d.sigma_t), d.diffusion == MLQ_DIFF_ISO,
+    launch_coefs(theta_dev, w.coef, level->P, batch,
+                 d.diffusion == MLQ_DIFF_ISO ? d.sigma_t : 0.5 * (d.sigma_l - d.sigma_t), d.diffusion == MLQ_DIFF_ISO,
                  mixed, s);
   launch_init(w, level->nn, batch, d.u_th, s);
   HIP_OK(hipGetLastError());

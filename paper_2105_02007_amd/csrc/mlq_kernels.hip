@@ -174,15 +174,16 @@ __host__ __device__ inline void gather(int ix, int iy, int iz, const Geo& g, con
 }
 
 // ---------------------------------------------------------------------------
-// Per-element coefficients.  Fibre angles: p = (s_l - s_t)/2 cos 2t, q = (s_l - s_t)/2 sin 2t.
-// Isotropic scalar field (iso): p = v, q = 0.
+// Per-element coefficients.  Fibre angles: p = (s_l - s_t)/2 cos 2t, q = (s_l - s_t)/2 sin 2t
+// (a = (s_l - s_t)/2).  Isotropic scalar field (iso): p = max(v, a), q = 0 (a = the floor).
 template <typename TT, typename TC>
 __global__ void k_coefs(const TT* __restrict__ theta, TC* __restrict__ coef, int64_t total, double half_dsig,
                         int iso) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
   if (iso) {
-    coef[2 * i] = (TC)theta[i];
+    const double v = (double)theta[i];
+    coef[2 * i] = (TC)(v > half_dsig ? v : half_dsig);
     coef[2 * i + 1] = (TC)0;
   } else if constexpr (sizeof(TC) == 4) {
     const float t2 = 2.0f * (float)theta[i];

@@ -43,7 +43,9 @@ class ConfigRunner:
         self.components = int(kcfg.get("components", 1))
         self.uniform = kcfg.get("variables") == "uniform"
         cov = mlq.MLQ_COV_SQEXP if kcfg.get("kernel") == "sqexp" else mlq.MLQ_COV_EXP
-        std = kcfg["std"] * (self.phys["sigma_l"] if self.vector else 1.0)
+        self.iso = cfg.get("model") == "iso"
+        # the KL standard deviation is relative to sigma_l (vector model) or E[V] (isotropic)
+        std = kcfg["std"] * (self.phys["sigma_l"] if self.vector else kcfg["mean"] if self.iso else 1.0)
         if self.tet:
             # tetrahedral levels: the seeded shells of the workload (non-nested), the KL on
             # the vertices of the finest one, the transfer by point location
@@ -83,12 +85,16 @@ class ConfigRunner:
                     theta0 = torch.as_tensor(mesh["theta0"], dtype=torch.float64, device=device)
             else:
                 phi = mlq.kl_transfer(self.kd, psi, lv, device=device)
+                if self.iso:  # the field is v = E[V] + W
+                    n_el = int(np.prod([n - 1 for n in lv["n"]]))
+                    theta0 = torch.full((n_el,), float(kcfg["mean"]), dtype=torch.float64, device=device)
             desc, keep = mlq.make_desc(
                 lv, self.phys, n_modes=M, phi=phi, sqrt_lambda=sl, theta0=theta0, prec=self.prec, qoi=cfg["qoi"],
                 newton_tol=newton_tol if newton_tol is not None else (1e-13 if self.prec == mlq.MLQ_FP64 else 1e-10),
                 inner_tol=inner_tol if inner_tol is not None else (1e-6 if self.prec == mlq.MLQ_FP64 else 1e-5),
                 max_inner=max_inner, max_batch=nb, newton_guess=newton_guess,
-                diffusion=mlq.MLQ_DIFF_VECTOR if self.vector else mlq.MLQ_DIFF_FIBRE, v_mean=v_mean)
+                diffusion=(mlq.MLQ_DIFF_VECTOR if self.vector else mlq.MLQ_DIFF_ISO if self.iso
+                           else mlq.MLQ_DIFF_FIBRE), v_mean=v_mean)
             L = mlq.Level(desc, keep, device=device)
             L._keep = None  # arrays were copied into the level blob
             self.levels.append(L)
@@ -194,6 +200,8 @@ class ConfigRunner:
 
     def lattice_points(self, l, shifts):
         """Shifted lattice normals for level l: (M x S*N_l) device tensor, shift-major."""
+        if self.uniform:
+            raise ValueError("lattice points are mapped to normal coordinates; this workload draws uniform ones")
         N = self.cfg["sampling"]["n_per_level"][l]
         M = self.kd.n_modes
         gamma = self.lam / self.lam[0]

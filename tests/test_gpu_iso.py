@@ -78,6 +78,79 @@ def test_iso_solve_fp64_matches_oracle(env):
         assert abs(q[b] - r["mean_act"]) <= 1e-10 * abs(r["mean_act"])
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_iso_floor_clips_the_field(env, mixed):
+    """A field that crosses the lower bound: G = max(v, sigma_t) I element by element (values
+    down to -0.5 E[V] and up to 2.5 E[V], the floor at 0.1 E[V])."""
+    torch, mlq = env
+    from oracle import fem
+    from oracle.mesh import BoxMesh
+    phys = W.physics(3)
+    phys["sigma_t"] = 0.1 * 3.325e-3
+    n = [17, 9, 6]
+    lv = _level(n, 16, hi=[1.0, 0.6, 0.4])
+    B = 2
+    desc, keep = mlq.make_desc(lv, phys, prec=mlq.MLQ_MIXED if mixed else mlq.MLQ_FP64, max_batch=B,
+                               diffusion=mlq.MLQ_DIFF_ISO)
+    level = mlq.Level(desc, keep)
+    mesh = BoxMesh(n, hi=lv["hi"])
+    dt = phys["t_end"] / 16
+    v = _positive_field(13, B, mesh.n_elems, amp=1.5)
+    assert (v < phys["sigma_t"]).mean() > 0.1
+    x = W.random_nodal(14, B, mesh.n_nodes)
+    dv = W.random_nodal(15, B, mesh.n_nodes, -0.05, 0.14)
+    tdt = torch.float32 if mixed else torch.float64
+    v_d, x_d, d_d = (torch.as_tensor(a, dtype=tdt, device="cuda") for a in (v, x, dv))
+    y = level.apply(v_d, x_d, d_d).double().cpu().numpy()
+    for b in range(B):
+        vb, xb, db = (a[b].double().cpu().numpy() for a in (v_d, x_d, d_d))
+        M, K = fem.assemble(mesh, fem.conductivity_iso(vb, 3, phys["sigma_t"]))
+        ref = M @ ((1.0 + db) * xb) + 0.5 * dt * (K @ xb)
+        scale = abs(M) @ np.abs((1.0 + db) * xb) + 0.5 * dt * (abs(K) @ np.abs(xb))
+        tol = (2e-6 if mixed else 3e-14) * scale.max()
+        assert np.abs(y[b] - ref).max() <= tol, (b, np.abs(y[b] - ref).max() / scale.max())
+
+
+def test_c2i_pipeline_small_matches_oracle(env):
+    """The cube model end to end at small size through the driver: squared-exponential KL
+    relative to E[V] with uniform coordinates, midpoint transfer, v = E[V] + W bounded below,
+    nested box levels, MLMC estimator eq. (StandardML), against the oracle's own pipeline (FP64).
+    The box is not a cube, so the KL eigenvalues are simple and the modes comparable; the
+    standard deviation is raised so that the floor is reached."""
+    torch, mlq = env
+    from oracle import estimators, run
+    from paper_2105_02007_amd.driver import ConfigRunner
+    cfg = W.config("c2i")
+    hi = [1.0, 0.8, 1.3]
+    cfg["levels"] = [dict(dim=3, n=[n] * 3, lo=[0.0] * 3, hi=hi, n_steps=m) for n, m in zip([5, 9], [8, 16])]
+    cfg["kl"].update(n_modes=5, grid_level=1, std=1.5)
+    cfg["sampling"]["n_per_level"] = [4, 2]
+    M = cfg["kl"]["n_modes"]
+    meshes = run.level_meshes(cfg)
+    factor = meshes[-1].n_nodes // M  # near-full-rank Cholesky on both sides, same rank
+    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0)
+    Ys = [W.mc_uniforms(cfg["seed"], l, n, M) for l, n in enumerate(cfg["sampling"]["n_per_level"])]
+    res = runner.run_mlmc([torch.as_tensor(Y, device="cuda") for Y in Ys])
+    B = run.kl_basis(cfg, meshes, max_rank=factor * M, eps=0.0)
+    ph = cfg["physics"]
+    floor_hit = False
+
+    def qois(l, Y):
+        nonlocal floor_hit
+        th = run.sample_theta(B["phi"][l], B["sqrt_lam"], Y, run.level_theta0(cfg, meshes[l]))
+        floor_hit |= bool((th < ph["sigma_t"]).any())
+        return np.array([run.qoi_of(run.solve_theta(meshes[l], th[b], ph, cfg["levels"][l]["n_steps"],
+                                                    model="iso"), cfg["qoi"]) for b in range(th.shape[0])])
+    ff = [qois(l, Ys[l]) for l in range(2)]
+    fc = [None, qois(0, Ys[1])]
+    assert floor_hit
+    for l in range(2):
+        assert np.abs(res["f_fine"][l] - ff[l]).max() <= 1e-10 * np.abs(ff[l]).max(), l
+    assert np.abs(res["f_coarse"][1] - fc[1]).max() <= 1e-10 * np.abs(fc[1]).max()
+    est = estimators.standard_ml(ff, fc)[0]
+    assert abs(res["estimate"] - est) <= 1e-10 * abs(est)
+
+
 def test_iso_model_rejected_on_tetrahedra(env):
     torch, mlq = env
     from workloads import tetshell

@@ -200,6 +200,27 @@ def test_isotropic_scalar_model_equals_isotropic_fibre_model():
     assert np.abs(K @ np.ones(mesh.n_nodes)).max() < 1e-14 * abs(K).max()
 
 
+def test_isotropic_model_floor():
+    """The lower bound b_min of the cube model: a field entirely below it gives b_min times the
+    Laplacian stiffness, a field entirely above it is untouched, and the stiffness of a mixed
+    field is positive semi-definite with the constants as its only null space (all element
+    conductivities positive)."""
+    from oracle import fem
+    mesh = BoxMesh([4, 5, 3])
+    rng = np.random.default_rng(6)
+    b = 3.3e-4
+    _, K1 = fem.assemble(mesh, fem.conductivity_iso(np.ones(mesh.n_elems), 3))
+    _, Klow = fem.assemble(mesh, fem.conductivity_iso(rng.uniform(-2e-3, 0.9 * b, mesh.n_elems), 3, b))
+    assert abs(Klow - b * K1).max() <= 1e-14 * b * abs(K1).max()
+    v = rng.uniform(1.1 * b, 5e-3, mesh.n_elems)
+    assert np.array_equal(fem.conductivity_iso(v, 3, b), fem.conductivity_iso(v, 3))
+    vm = 3.3e-3 * (1.0 + 1.5 * rng.uniform(-1, 1, mesh.n_elems))
+    assert (vm < 0).any()
+    _, Km = fem.assemble(mesh, fem.conductivity_iso(vm, 3, b))
+    ev = np.linalg.eigvalsh(Km.toarray() if hasattr(Km, "toarray") else Km)
+    assert abs(ev[0]) < 1e-12 * ev[-1] and ev[1] > 1e-6 * ev[-1]
+
+
 def test_vector_field_conductivity_eigenstructure():
     """eq. (AdmV) for a general vector field: G V = |V| V and G n = g n for n orthogonal to V,
     so G is SPD with eigenvalues g (twice) and |V| whenever V != 0."""

@@ -105,6 +105,18 @@ CONFIGS = {
         kl=dict(n_modes=256, corr_len=0.1 * tetshell.LONG_AXIS, std=0.3, grid_level=2),
         sampling=dict(kind="combination", n_per_level=[16, 64, 256]),
         qoi=QOI_MEAN_ACT_TIME, prec=PREC_MIXED, seed=5),
+    # the paper's cube model (Section 5.1): isotropic G = v I with v = E[V] (1 + W), W a KL field
+    # with the squared-exponential covariance 0.3^2 exp(-|x - x'|^2 / 0.25) relative to
+    # E[V] = 3.325e-3, 66 modes with uniform coordinates (modes scaled by sqrt(3 lambda)),
+    # bounded below by 0.1 E[V]; the nested levels and sample plan of c2
+    "c2i": dict(
+        name="c2i", title="the paper's cube model: isotropic random scalar diffusion, MLMC 9^3..65^3",
+        dim=3, levels=_box_levels(3, [9, 17, 33, 65], [32, 64, 128, 256]),
+        kl=dict(n_modes=66, corr_len=0.25, std=0.3, grid_level=3, kernel="sqexp", variables="uniform",
+                mean=SIGMA_L, floor=0.1),
+        model="iso",
+        sampling=dict(kind="mlmc", n_per_level=[2048, 512, 128, 32]),
+        qoi=QOI_MEAN_ACT_TIME, prec=PREC_FP64, seed=7),
     # the paper's own heart model (Section 5.1) on the c5 shells: eq. (AdmV) with a random
     # vector field V = sigma_l f0 + W, f0 the rule-based fibre, W three independent components
     # with the squared-exponential covariance (0.3 sigma_l)^2 exp(-|x - x'|^2 / sigma_KL),
@@ -130,6 +142,8 @@ MAX_INNER = 30
 def config(name: str) -> dict:
     cfg = copy.deepcopy(CONFIGS[name])
     cfg["physics"] = physics(cfg["dim"])
+    if cfg.get("model") == "iso":  # sigma_t is the lower bound of the isotropic conductivity
+        cfg["physics"]["sigma_t"] = cfg["kl"]["floor"] * cfg["kl"]["mean"]
     if cfg["levels"][0].get("kind") == "tet":
         # stimulus: the ball around the epicardial apex (radius 1/8 of the long axis)
         c, r = tetshell.stimulus_ball()
