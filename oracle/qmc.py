@@ -1,9 +1,15 @@
-"""Randomly shifted rank-1 lattice rules (test infrastructure; see ``oracle/__init__``).
+"""Quasi-Monte Carlo point sets (test infrastructure; see ``oracle/__init__``).
 
-The paper uses quasi-Monte Carlo quadrature (Section 5.1, Halton points); the
-workloads use randomly shifted rank-1 lattice rules instead, whose shift
-average gives an error estimate.  Points: x_i = frac(i z / N + Delta),
-i = 0..N-1, mapped to Gaussian coordinates y = Phi^-1(x).
+Halton points (the paper's QMC rule, Section 5.1 and its quadrature-methods
+paragraph): coordinate k of point i is the radical inverse of i in the base of
+the (k+1)-th prime, optionally shifted at random mod 1 (randomised QMC, which
+gives an error estimate over independent shifts), mapped to the uniform
+coordinates y = 2x - 1 of the parametrisation on [-1, 1]^M or to Gaussian ones.
+The radical inverse is formed as an exact rational and rounded once.
+
+Randomly shifted rank-1 lattice rules, the other QMC rule of the workloads:
+x_i = frac(i z / N + Delta), i = 0..N-1, mapped to Gaussian coordinates
+y = Phi^-1(x).
 
 Generating vector: component-by-component (CBC) construction minimising the
 shift-averaged worst-case error in the weighted unanchored Sobolev space of
@@ -17,6 +23,7 @@ is reproducible bit for bit by any implementation doing the same operations.
 """
 from __future__ import annotations
 
+from fractions import Fraction
 from math import gcd
 
 import numpy as np
@@ -74,3 +81,43 @@ def to_normal(x):
 def lattice_normals(z, N, shift):
     """Gaussian KL coordinates (s, N) of a shifted lattice rule."""
     return np.ascontiguousarray(to_normal(lattice_points(z, N, shift)).T)
+
+
+def first_primes(n):
+    """The first n primes, by trial division against the primes found so far."""
+    ps = []
+    c = 2
+    while len(ps) < n:
+        if all(c % q for q in ps if q * q <= c):
+            ps.append(c)
+        c += 1
+    return ps
+
+
+def radical_inverse(i, p):
+    """phi_p(i) = sum_j d_j p^(-j-1) for i = sum_j d_j p^j, rounded once from the exact rational."""
+    x, scale = Fraction(0), Fraction(1, p)
+    while i > 0:
+        i, d = divmod(i, p)
+        x += d * scale
+        scale /= p
+    return float(x)
+
+
+def halton_points(s, first, count, shift=None):
+    """Points i = first .. first + count - 1 of the s-dimensional Halton sequence, (count, s) in
+    [0, 1); with a shift, x = frac(phi + shift) (the sum rounded in FP64, then 1 subtracted
+    once if it reached 1)."""
+    ps = first_primes(s)
+    X = np.array([[radical_inverse(first + i, p) for p in ps] for i in range(count)]).reshape(count, s)
+    if shift is not None:
+        X = X + np.asarray(shift, dtype=np.float64)[None, :]
+        X = np.where(X >= 1.0, X - 1.0, X)
+    return X
+
+
+def halton_coordinates(s, first, count, shift=None, uniform=True):
+    """KL coordinates (s, count): y = 2x - 1 in [-1, 1] (uniform) or y = Phi^-1(x) (Gaussian)."""
+    X = halton_points(s, first, count, shift)
+    Y = 2.0 * X - 1.0 if uniform else to_normal(X)
+    return np.ascontiguousarray(Y.T)
