@@ -66,6 +66,9 @@ WORKLOAD_TEXT = {
     "c2i": "the paper's cube model: isotropic G = max(v, 0.1 E[V]) I, v = E[V] + W, E[V] = 3.325e-3, W a "
            "squared-exponential KL field (0.3 E[V], sigma_KL = 0.25) with 66 uniform coordinates, 3D unit cube "
            "Q1 9^3..65^3 nested, 32..256 steps, MLMC 2048/512/128/32 samples, mean activation time, FP64",
+    "c4i": "the paper's cube model (as c2i) with the paper's QMC rule: MLQMC with Halton points (indices 1..N_l, "
+           "16 random shifts mod 1), 3D unit cube Q1 9^3..129^3 nested, 32..512 steps, 256/64/16/4/1 points, "
+           "mean activation time",
     "c5": "non-nested prolate-ellipsoidal shell, P1 tetrahedra 26k/187k/1.4M vertices, 512 steps, 256-mode KL "
           "(l = 0.1 long axis), rule-based +60/-60 deg fibres, combination estimator 16/64/256 nested MC points, "
           "mean activation time",
@@ -169,7 +172,7 @@ def qoi_vs_fp64(cfg, runner, res, dev, log, Ys=None, Yc=None, shifts=None, nq=4)
     elif samp["kind"] in ("mc", "mlmc"):
         Y = Ys[L]
     else:
-        Y = runner.lattice_points(L, shifts[L])
+        Y = runner.qmc_points(L, shifts[L])
     nq = min(nq, Y.shape[1])
     Y = Y[:, :nq].contiguous()
     mixed_q = np.asarray(res["f_fine"][L][:nq])
@@ -278,7 +281,7 @@ def main():
             step = lambda: runner.run_mlmc(Ys)
     else:
         S = samp.get("n_shifts", 1)
-        shifts = [W.lattice_shifts(cfg["seed"], l, S, M) for l in range(len(cfg["levels"]))]
+        shifts = [W.lattice_shifts(cfg["seed"], l, S, n_dims) for l in range(len(cfg["levels"]))]
         step = lambda: runner.run_mlqmc(shifts)
 
     if args.copy_calibration:
@@ -360,12 +363,13 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == W.PREC_FP64 else "f32+f64",
-        "data": "synthetic (seeded KL fibre-angle fields, MC normals / rank-1 lattice points)",
+        "data": "synthetic (seeded KL random fields; MC normal or uniform coordinates, shifted rank-1 "
+                "lattice or Halton points)",
         "config": {"workload": f"{args.config}: {WORKLOAD_TEXT[args.config]}", "levels": len(cfg["levels"]),
                    "samples_per_level": samp["n_per_level"], "n_shifts": samp.get("n_shifts", 1),
                    "parallelism": "single GPU, samples batched per level"},
         "st_dof_per_s": st_dof / el,
-        # no error estimate: the combination form over nested point sets, or a lattice rule
+        # no error estimate: the combination form over nested point sets, or a QMC rule
         # with a single random shift
         "estimate": res["estimate"],
         "rmse_est": None if samp["kind"] == "combination" or (samp["kind"] in ("qmc", "mlqmc")

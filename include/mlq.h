@@ -192,6 +192,20 @@ mlq_status mlq_check(const int32_t* status_host, int32_t batch);
 mlq_status mlq_lattice_normals(const int64_t* z_dev, const double* shift_dev, int32_t s, int64_t N,
                                int64_t first, int32_t count, double* Y_dev, void* hip_stream);
 
+/* Halton points, the paper's quasi-Monte Carlo rule (Section 5.1, quadrature methods):
+ *   x_k(i) = phi_{p_k}(i), p_k the (k+1)-th prime, phi_p(i) = sum_j d_j p^(-j-1) for the base-p
+ *   digits i = sum_j d_j p^j, rounded once from the exact rational; with shift_dev (s values in
+ *   [0, 1), device) x_k = x_k + shift_k, minus 1 if that reached 1 (randomised QMC);
+ *   map MLQ_MAP_UNIFORM: Y = 2x - 1, the coordinates y in [-1, 1] of Section 4;
+ *   map MLQ_MAP_NORMAL:  Y = Phi^-1(x), x clamped to [2^-53, 1 - 2^-53].
+ * Y[k + s (i - first)] for i = first .. first + count - 1, column-major s x count FP64 on the
+ * device (may be NULL when count = 0).  shift_dev may be NULL (no shift).  1 <= s <= 1024,
+ * first >= 0, first + count <= 2^32; MLQ_EINVAL otherwise.  Point 0 is the origin; samplers usually
+ * start at first = 1.  Enqueues only. */
+typedef enum { MLQ_MAP_NORMAL = 0, MLQ_MAP_UNIFORM = 1 } mlq_coordinate_map;
+mlq_status mlq_halton(int32_t s, int64_t first, int32_t count, const double* shift_dev, int32_t map, double* Y_dev,
+                      void* hip_stream);
+
 /* Component-by-component generating vector of an N-point rank-1 lattice in s
  * dimensions, product weights gamma (s), minimising the shift-averaged
  * worst-case error of the unanchored Sobolev space.  Host only. */

@@ -63,7 +63,8 @@ def shifted_lattice(per_shift_values):
 
 
 def standard_mlqmc(f_fine, f_coarse):
-    """eq. (StandardML) with shifted lattice rules: f_fine[l][s][i], f_coarse[l][s][i]."""
+    """eq. (StandardML) with randomly shifted QMC rules (lattice or Halton): f_fine[l][s][i],
+    f_coarse[l][s][i]."""
     est, mse, means = 0.0, 0.0, []
     for l in range(len(f_fine)):
         q = []

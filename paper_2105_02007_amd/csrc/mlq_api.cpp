@@ -826,6 +826,18 @@ mlq_status mlq_lattice_normals(const int64_t* z_dev, const double* shift_dev, in
   return MLQ_OK;
 }
 
+mlq_status mlq_halton(int32_t s, int64_t first, int32_t count, const double* shift_dev, int32_t map, double* Y_dev,
+                      void* hip_stream) {
+  if (map != MLQ_MAP_NORMAL && map != MLQ_MAP_UNIFORM) return fail(MLQ_EINVAL, "unknown coordinate map");
+  if (s < 1 || s > kHaltonMaxDims) return fail(MLQ_EINVAL, "Halton dimension outside [1, 1024]");
+  if (first < 0 || count < 0 || first + count > (int64_t(1) << 32)) return fail(MLQ_EINVAL, "Halton index range");
+  if (count == 0) return MLQ_OK;
+  if (Y_dev == nullptr) return fail(MLQ_EINVAL, "NULL argument");
+  launch_halton(s, first, count, shift_dev, map == MLQ_MAP_UNIFORM, Y_dev, (hipStream_t)hip_stream);
+  HIP_OK(hipGetLastError());
+  return MLQ_OK;
+}
+
 mlq_status mlq_accumulate(const double* f_fine_dev, const double* f_coarse_dev, int32_t count, double* acc_dev,
                           void* hip_stream) {
   if (f_fine_dev == nullptr || acc_dev == nullptr || count < 0) return fail(MLQ_EINVAL, "invalid argument");

@@ -150,6 +150,9 @@ void launch_kl(const double* phi64T, const float* phi32T, const double* sqrt_lam
 void launch_transpose_f64(const double* src, double* dst, int64_t rows, int64_t cols, hipStream_t s);
 void launch_lattice(const int64_t* z, const double* shift, int32_t sdim, int64_t N, int64_t first,
                     int32_t count, double* Y, hipStream_t s);
+constexpr int kHaltonMaxDims = 1024;
+void launch_halton(int32_t sdim, int64_t first, int32_t count, const double* shift, bool uniform, double* Y,
+                   hipStream_t s);
 void launch_newton_reset(const Work& w, int32_t B, hipStream_t s);
 void launch_mark_failed(const Work& w, int32_t B, hipStream_t s);
 void launch_accumulate(const double* ff, const double* fc, int32_t count, double* acc, hipStream_t s);

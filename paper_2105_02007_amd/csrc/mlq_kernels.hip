@@ -841,6 +841,69 @@ void launch_lattice(const int64_t* z, const double* shift, int32_t sdim, int64_t
 }
 
 // ---------------------------------------------------------------------------
+// Halton points: coordinate k of point i is the radical inverse of i in the base of the
+// (k+1)-th prime.  The digits of i, least significant first, are accumulated as the integer
+// numerator r of r / p^J (J digits); both stay below 2^53 for i < 2^32 and p < 2^13, so the
+// quotient is the exact rational rounded once.  Optional shift mod 1, then the map to uniform
+// coordinates 2x - 1 or to Gaussian ones Phi^-1(x).
+
+// The first kHaltonMaxDims primes, sieved at compile time.
+struct PrimeTable {
+  uint16_t p[kHaltonMaxDims];
+};
+
+constexpr PrimeTable make_primes() {
+  constexpr int kLimit = 8192;  // the 1024th prime is 8161
+  bool composite[kLimit] = {};
+  PrimeTable t{};
+  int n = 0;
+  for (int c = 2; c < kLimit && n < kHaltonMaxDims; ++c) {
+    if (composite[c]) continue;
+    t.p[n++] = (uint16_t)c;
+    for (int m = 2 * c; m < kLimit; m += c) composite[m] = true;
+  }
+  return t;
+}
+
+constexpr PrimeTable kPrimeTable = make_primes();
+static_assert(kPrimeTable.p[kHaltonMaxDims - 1] == 8161, "prime table");
+__constant__ PrimeTable kPrimes = kPrimeTable;
+
+__global__ void k_halton(int32_t sdim, int64_t first, int32_t count, const double* __restrict__ shift,
+                         int32_t uniform, double* __restrict__ Y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)sdim * count) return;
+  const int k = (int)(t % sdim);
+  const uint64_t p = kPrimes.p[k];
+  uint64_t n = (uint64_t)(first + t / sdim), r = 0, q = 1;
+  while (n > 0) {
+    const uint64_t d = n / p;
+    r = r * p + (n - d * p);
+    n = d;
+    q *= p;
+  }
+  double x = (double)r / (double)q;
+  if (shift != nullptr) {
+    x += shift[k];
+    if (x >= 1.0) x -= 1.0;
+  }
+  if (uniform) {
+    Y[t] = 2.0 * x - 1.0;
+  } else {
+    const double eps = 1.1102230246251565e-16;  // 2^-53
+    x = x < eps ? eps : (x > 1.0 - eps ? 1.0 - eps : x);
+    Y[t] = normcdfinv(x);
+  }
+}
+
+void launch_halton(int32_t sdim, int64_t first, int32_t count, const double* shift, bool uniform, double* Y,
+                   hipStream_t s) {
+  const int64_t total = (int64_t)sdim * count;
+  hipLaunchKernelGGL(k_halton, dim3((unsigned)cdiv(total, kBlock)), dim3(kBlock), 0, s, sdim, first, count, shift,
+                     uniform ? 1 : 0, Y);
+}
+
+// ---------------------------------------------------------------------------
 // Level difference and FP64 accumulation, one block, fixed order.
 __global__ void k_accumulate(const double* __restrict__ ff, const double* __restrict__ fc, int32_t count,
                              double* acc) {

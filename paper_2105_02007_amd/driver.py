@@ -198,25 +198,32 @@ class ConfigRunner:
         f = self.solve(level, Y)
         return self._estimate(mlq.MLQ_EST_MC, [f], None, [Y.shape[1]], 1)
 
-    def lattice_points(self, l, shifts):
-        """Shifted lattice normals for level l: (M x S*N_l) device tensor, shift-major."""
-        if self.uniform:
-            raise ValueError("lattice points are mapped to normal coordinates; this workload draws uniform ones")
-        N = self.cfg["sampling"]["n_per_level"][l]
-        M = self.kd.n_modes
+    def qmc_points(self, l, shifts):
+        """Randomly shifted QMC points for level l: (M x S*N_l) device tensor, shift-major.
+        Rank-1 lattices (CBC generating vector, Gaussian coordinates) or the paper's Halton
+        points (indices 1..N_l, uniform or Gaussian coordinates as the workload draws them)."""
+        samp = self.cfg["sampling"]
+        N = samp["n_per_level"][l]
+        M = shifts.shape[1]
+        if samp.get("rule", "lattice") == "halton":
+            cols = [mlq.halton(M, 1, N, shifts[s], uniform=self.uniform, device=self.device)
+                    for s in range(shifts.shape[0])]
+            return torch.cat(cols, dim=1)
+        if self.uniform or self.components > 1:
+            raise ValueError("the lattice rule here maps to Gaussian coordinates of one field")
         gamma = self.lam / self.lam[0]
         z = mlq.cbc(N, M, gamma)
         cols = [mlq.lattice_normals(z, shifts[s], N, 0, N, device=self.device) for s in range(shifts.shape[0])]
         return torch.cat(cols, dim=1)
 
     def run_mlqmc(self, shifts_per_level, levels=None):
-        """eq. (StandardML) with randomly shifted lattice rules (shift-major sample order)."""
+        """eq. (StandardML) with randomly shifted QMC rules (shift-major sample order)."""
         levels = range(len(self.levels)) if levels is None else levels
         npl = []
         S = shifts_per_level[0].shape[0]
         jobs = []
         for l in levels:
-            Y = self.lattice_points(l, shifts_per_level[l])
+            Y = self.qmc_points(l, shifts_per_level[l])
             jobs.append((l, Y))
             if l > 0:
                 jobs.append((l - 1, Y))

@@ -24,13 +24,14 @@ MLQ_MESH_Q1_BOX, MLQ_MESH_P1_TET = 0, 1
 EXPORTED = [
     "mlq_level_bytes", "mlq_create_level", "mlq_destroy_level", "mlq_level_sizes", "mlq_workspace_bytes",
     "mlq_sample_fields", "mlq_solve_batch", "mlq_solve_batch_ex", "mlq_apply", "mlq_check",
-    "mlq_lattice_normals", "mlq_cbc", "mlq_accumulate", "mlq_estimate", "mlq_last_error",
+    "mlq_lattice_normals", "mlq_halton", "mlq_cbc", "mlq_accumulate", "mlq_estimate", "mlq_last_error",
     "mlq_kl_workspace_bytes", "mlq_kl_modes", "mlq_kl_transfer", "mlq_timing_enable", "mlq_timing_read",
     "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet",
 ]
 MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE = 0, 1
 MLQ_DIFF_FIBRE, MLQ_DIFF_ISO, MLQ_DIFF_VECTOR = 0, 1, 2
 MLQ_COV_EXP, MLQ_COV_SQEXP = 0, 1
+MLQ_MAP_NORMAL, MLQ_MAP_UNIFORM = 0, 1
 KERNEL_CLASSES = ["apply", "residual", "rhs", "precond", "dots", "orth", "small", "update", "qoi"]
 
 
@@ -101,6 +102,7 @@ def _load():
         "mlq_apply": [VP, VP, I32, VP, VP, VP, VP, C.c_size_t, VP],
         "mlq_check": [VP, I32],
         "mlq_lattice_normals": [VP, VP, I32, I64, I64, I32, VP, VP],
+        "mlq_halton": [I32, I64, I32, VP, I32, VP, VP],
         "mlq_cbc": [I64, I32, VP, VP],
         "mlq_accumulate": [VP, VP, I32, VP, VP],
         "mlq_estimate": [I32, I32, I32, VP, VP, VP, C.POINTER(EstimateOut)],
@@ -309,6 +311,17 @@ def lattice_normals(z, shift, N, first, count, device="cuda"):
     s = zd.numel()
     Y = torch.empty((count, s), dtype=torch.float64, device=device)  # column-major s x count
     check(lib.mlq_lattice_normals(_ptr(zd), _ptr(sd), int(s), int(N), int(first), int(count), _ptr(Y), _stream()))
+    return Y.t()
+
+
+def halton(s, first, count, shift=None, uniform=True, device="cuda"):
+    """(s, count) FP64 device tensor of Halton coordinates (uniform on [-1, 1] or Gaussian),
+    optionally shifted mod 1."""
+    import torch
+    sd = None if shift is None else torch.as_tensor(np.asarray(shift, dtype=np.float64), device=device)
+    Y = torch.empty((count, s), dtype=torch.float64, device=device)  # column-major s x count
+    check(lib.mlq_halton(int(s), int(first), int(count), None if sd is None else _ptr(sd),
+                         MLQ_MAP_UNIFORM if uniform else MLQ_MAP_NORMAL, _ptr(Y), _stream()))
     return Y.t()
 
 

@@ -67,6 +67,21 @@ def test_cbc_bit_exact_with_oracle(mlq, N, s):
     assert np.array_equal(mlq.cbc(N, s, gamma), qmc.cbc(N, s, gamma))
 
 
+def test_halton_argument_validation(mlq):
+    """Invalid Halton requests are refused on the host before anything is enqueued (run where no
+    GPU is visible: the pointer below is a placeholder that must never be dereferenced)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("host-side checks only")
+    lib = mlq.lib
+    fake = 4096
+    assert lib.mlq_halton(4, 1, 8, None, mlq.MLQ_MAP_UNIFORM, None, None) == mlq.MLQ_EINVAL
+    for s, first, count, m in [(0, 1, 8, 1), (1025, 1, 8, 1), (4, -1, 8, 1), (4, 1, -1, 1),
+                               (4, 2 ** 32 - 3, 4, 1), (4, 1, 8, 2)]:
+        assert lib.mlq_halton(s, first, count, None, m, fake, None) == mlq.MLQ_EINVAL, (s, first, count, m)
+    assert lib.mlq_halton(4, 5, 0, None, mlq.MLQ_MAP_UNIFORM, fake, None) == mlq.MLQ_OK
+
+
 def test_estimators_match_oracle(mlq):
     from oracle import estimators as E
     rng = np.random.default_rng(3)

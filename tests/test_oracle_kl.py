@@ -137,3 +137,23 @@ def test_squared_exponential_kernel_is_separable_on_tensor_grids():
     lam_c, V_c = kl.kl_from_cholesky(L, M2, m2.n_nodes)
     assert np.allclose(lam_c[:k], l2, rtol=1e-9, atol=1e-14 * l2[0])
     assert np.isclose(lam_c.sum(), np.sum(C * M2.toarray()), rtol=1e-12)
+
+
+def test_cube_stochastic_dimension_matches_the_paper():
+    """Section 5.1 reports M = 66 for the cube (squared-exponential kernel with sigma_KL = 0.25,
+    truncation error 1e-2 in the pivoted Cholesky decomposition).  The oracle's factorisation
+    stops within one of it on the cube grids: at 65 with the nodal trace, at 66 with the
+    mass-weighted (L2) trace on 17^3 nodes.  Other readings of the kernel are far off: sigma_KL
+    as a length (exp(-|x - y|^2 / 0.25^2)) or the exponential kernel need well over 100."""
+    mesh = BoxMesh([17, 17, 17])
+    L, _ = kl.pivoted_cholesky(mesh.nodes, 0.3, 0.25, 200, eps=1e-2, kernel="sqexp")
+    assert L.shape[1] == 65
+    L80, _ = kl.pivoted_cholesky(mesh.nodes, 0.3, 0.25, 80, eps=0.0, kernel="sqexp")
+    assert np.array_equal(L80[:, :65], L)
+    w = np.asarray(fem.assemble_mass(mesh).sum(axis=1)).ravel()
+    resid = 0.09 * w.sum() - np.cumsum((w[:, None] * L80 ** 2).sum(axis=0))
+    assert (resid <= 1e-2 * 0.09 * w.sum()).any()
+    assert int(np.argmax(resid <= 1e-2 * 0.09 * w.sum())) + 1 == 66
+    for kernel, ell in (("sqexp", 0.25 ** 2), ("exp", 0.25)):
+        L2, _ = kl.pivoted_cholesky(mesh.nodes, 0.3, ell, 100, eps=1e-2, kernel=kernel)
+        assert L2.shape[1] == 100

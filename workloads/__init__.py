@@ -117,6 +117,16 @@ CONFIGS = {
         model="iso",
         sampling=dict(kind="mlmc", n_per_level=[2048, 512, 128, 32]),
         qoi=QOI_MEAN_ACT_TIME, prec=PREC_FP64, seed=7),
+    # the cube model with the paper's QMC rule: MLQMC with Halton points (randomly shifted,
+    # 16 shifts, for the error estimate) on the c4 hierarchy, N_l = 2^(2(L - l)) points
+    "c4i": dict(
+        name="c4i", title="the paper's cube model, MLQMC with shifted Halton points, Q1 9^3..129^3",
+        dim=3, levels=_box_levels(3, [9, 17, 33, 65, 129], [32, 64, 128, 256, 512]),
+        kl=dict(n_modes=66, corr_len=0.25, std=0.3, grid_level=4, kernel="sqexp", variables="uniform",
+                mean=SIGMA_L, floor=0.1),
+        model="iso",
+        sampling=dict(kind="mlqmc", rule="halton", n_per_level=[256, 64, 16, 4, 1], n_shifts=16),
+        qoi=QOI_MEAN_ACT_TIME, prec=PREC_MIXED, seed=8),
     # the paper's own heart model (Section 5.1) on the c5 shells: eq. (AdmV) with a random
     # vector field V = sigma_l f0 + W, f0 the rule-based fibre, W three independent components
     # with the squared-exponential covariance (0.3 sigma_l)^2 exp(-|x - x'|^2 / sigma_KL),
