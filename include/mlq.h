@@ -174,6 +174,61 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
                               int64_t* iters_dev, double* u_out_dev, double* act_out_dev,
                               void* hip_stream);
 
+/* Field quantities of interest (Section 2.4: the transmembrane potential u itself, the
+ * activation map, the action potential u(x0, t) at a point), streamed while a batch is
+ * solved.  Each output pointer may be NULL (that output is skipped).  Device arrays, FP64:
+ *   u_sum    (n_steps + 1) x n, ACCUMULATED: u_sum[k n + i] += sum_b u_b(x_i, t_k) for
+ *            k = 0 .. n_steps (row 0 holds the initial state), the space-time field summed
+ *            over the batch's samples;
+ *   act_sum  n, ACCUMULATED: act_sum[i] += sum_b a_b(x_i), the activation times with nodes
+ *            that never reach u_th counted at the stop time (as for MLQ_QOI_MEAN_ACT_TIME);
+ *   probe    batch x n_probe x (n_steps + 1), WRITTEN: probe[(b n_probe + p)(n_steps + 1) + k]
+ *            = sum_j probe_w[8 p + j] u_b(node probe_node[8 p + j], t_k);
+ *   probe_sum n_probe x (n_steps + 1), ACCUMULATED: probe_sum[p (n_steps + 1) + k] += the sum
+ *            over the batch of the same values (the action potential summed over samples).
+ * Accumulated outputs let several batches add into one sum; the caller clears them first.
+ * probe_node and probe_w are HOST arrays of n_probe x 8 entries (unused slots: weight 0 and
+ * any valid node), e.g. from mlq_probe_weights; 1 <= n_probe <= 16 when probe or probe_sum
+ * is not NULL.
+ * MLQ_EINVAL for a node outside the level or a weight that is not finite. */
+typedef struct {
+  double* u_sum;
+  double* act_sum;
+  double* probe;
+  int32_t n_probe;
+  const int64_t* probe_node;
+  const double* probe_w;
+  double* probe_sum;
+} mlq_field_out;
+
+/* mlq_solve_batch with field outputs (see mlq_field_out); same arguments, results and
+ * errors otherwise. */
+mlq_status mlq_solve_batch_fields(mlq_level* level, const void* theta_dev, int32_t batch, void* ws_dev,
+                                  size_t ws_bytes, double* qoi_dev, int32_t* status_dev, int64_t* iters_dev,
+                                  const mlq_field_out* fields, void* hip_stream);
+
+/* Interpolation weights of points for probe outputs, host only: for point p (xyz_host[3 p ..],
+ * the unused coordinate of a 2D box ignored) the nodes of the box cell that contains it and
+ * their Q1 weights, node_out[8 p + j] and w_out[8 p + j] (2D: 4 used, the rest weight 0).
+ * MLQ_EINVAL for a point outside the box or a tetrahedral level (on tetrahedra, probe a
+ * vertex: node v with weight 1). */
+mlq_status mlq_probe_weights(const mlq_level* level, const double* xyz_host, int32_t n_points, int64_t* node_out,
+                             double* w_out);
+
+/* Transfer of fields between the grids of two levels (Section 5, the error measures: the
+ * tensor product of the space and the time interpolation), accumulated:
+ *   dst += alpha * (T x S) src.
+ * space = 1: S is the Q1 interpolation from the nodes of `from` to those of `to` (box levels
+ * over the same box, (n_to - 1) a multiple of (n_from - 1) on every axis), else the identity
+ * on a single column;  time = 1: T is the linear interpolation from the time nodes of `from`
+ * to those of `to` (the same end time, n_steps of `to` a multiple of that of `from`), else the
+ * identity on a single time node.  Layout, row-major: src rows x T_f x S_f, dst rows x T_t x
+ * S_t with T = n_steps + 1 or 1 and S = n_nodes or 1, e.g. u_sum (rows = 1, space and time),
+ * act_sum (rows = 1, space only), probe series (rows = batch n_probe, time only).  Device
+ * arrays of those sizes; from == to gives the identity.  Enqueues only. */
+mlq_status mlq_transfer_add(const mlq_level* from, const mlq_level* to, int32_t space, int32_t time, int64_t rows,
+                            double alpha, const double* src_dev, double* dst_dev, void* hip_stream);
+
 /* Jacobian of one step (Section 3.2) applied matrix-free to a batch:
  *   y = M ((1 + d) x) + dt/2 K_G x,
  * with G per element from theta (level precision).  x, d, y: batch x n in the

@@ -51,12 +51,12 @@ def sample_theta(phi_l, sqrt_lam, Y, theta0=None):
     return kl.field(theta0, phi_l, sqrt_lam, Y)
 
 
-def solve_theta(mesh, theta_e, phys, n_steps, tol=1e-13, stop_after=None, model=None):
+def solve_theta(mesh, theta_e, phys, n_steps, tol=1e-13, stop_after=None, model=None, keep_all=False):
     if model == "iso":
         G = fem.conductivity_iso(theta_e, mesh.d, phys["sigma_t"])
     else:
         G = fem.conductivity_from_angle(theta_e, mesh.d, phys["sigma_l"], phys["sigma_t"])
-    return stepper.solve(mesh, G, phys, n_steps, tol=tol, stop_after=stop_after)
+    return stepper.solve(mesh, G, phys, n_steps, tol=tol, stop_after=stop_after, keep_all=keep_all)
 
 
 def qoi_of(out, qoi):

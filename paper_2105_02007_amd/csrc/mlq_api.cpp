@@ -655,12 +655,37 @@ static mlq_status read_counter(mlq_level* lv, const Work& w, hipStream_t s, int3
   return MLQ_OK;
 }
 
-mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t batch, int32_t n_steps, void* ws_dev,
-                              size_t ws_bytes, double* qoi_dev, int32_t* status_dev, int64_t* iters_dev,
-                              double* u_out_dev, double* act_out_dev, void* hip_stream) {
+// Probe table of a field request: validated against the level's node count.
+static mlq_status probe_table(const mlq_level* level, const mlq_field_out* f, ProbeTab* tab) {
+  tab->n = 0;
+  if (f == nullptr || (f->probe == nullptr && f->probe_sum == nullptr)) return MLQ_OK;
+  if (f->n_probe < 1 || f->n_probe > kMaxProbes) return fail(MLQ_EINVAL, "n_probe outside [1, %d]", kMaxProbes);
+  if (f->probe_node == nullptr || f->probe_w == nullptr) return fail(MLQ_EINVAL, "probe nodes or weights are NULL");
+  for (int i = 0; i < f->n_probe * kProbeNodes; ++i) {
+    if (f->probe_node[i] < 0 || f->probe_node[i] >= level->nn) return fail(MLQ_EINVAL, "probe node out of range");
+    if (!std::isfinite(f->probe_w[i])) return fail(MLQ_EINVAL, "probe weight not finite");
+    tab->node[i] = f->probe_node[i];
+    tab->w[i] = f->probe_w[i];
+  }
+  tab->n = f->n_probe;
+  return MLQ_OK;
+}
+
+static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t batch, int32_t n_steps, void* ws_dev,
+                             size_t ws_bytes, double* qoi_dev, int32_t* status_dev, int64_t* iters_dev,
+                             double* u_out_dev, double* act_out_dev, const mlq_field_out* fields, void* hip_stream) {
   if (level == nullptr || theta_dev == nullptr || ws_dev == nullptr || qoi_dev == nullptr || status_dev == nullptr ||
       iters_dev == nullptr)
     return fail(MLQ_EINVAL, "NULL argument");
+  ProbeTab tab;
+  {
+    const mlq_status pst = probe_table(level, fields, &tab);
+    if (pst != MLQ_OK) return pst;
+  }
+  double* const u_sum = fields != nullptr ? fields->u_sum : nullptr;
+  double* const act_sum = fields != nullptr ? fields->act_sum : nullptr;
+  double* const probe = tab.n > 0 ? fields->probe : nullptr;
+  double* const probe_sum = tab.n > 0 ? fields->probe_sum : nullptr;
   if (batch < 1 || batch > level->d.max_batch) return fail(MLQ_EINVAL, "batch %d outside [1, max_batch]", batch);
   if (n_steps < 0 || n_steps > level->d.n_steps) return fail(MLQ_EINVAL, "n_steps %d outside [0, %d]", n_steps, level->d.n_steps);
   if (((uintptr_t)ws_dev & 255) != 0) return fail(MLQ_EINVAL, "workspace must be 256-byte aligned");
@@ -683,6 +708,13 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
                  mixed, s);
   launch_init(w, level->nn, batch, d.u_th, s);
   HIP_OK(hipGetLastError());
+  // field outputs of time level k (the state u_k sits in w.uk)
+  auto stream_fields = [&](int32_t k) {
+    if (u_sum != nullptr) launch_field_sum(w.uk, batch, level->nn, u_sum + (size_t)k * level->nn, s);
+    if (probe != nullptr) launch_probe(w.uk, batch, level->nn, tab, k, n_steps + 1, probe, s);
+    if (probe_sum != nullptr) launch_probe_sum(w.uk, batch, level->nn, tab, k, n_steps + 1, probe_sum, s);
+  };
+  stream_fields(0);
 
   auto rate = [&](double t) { return (d.stim_t_on <= t && t < d.stim_t_off) ? d.stim_amp : 0.0; };
   const double nn = (double)level->nn;
@@ -784,7 +816,9 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
     w.ukm1 = w.uk;
     w.uk = w.u;
     w.u = old;
+    stream_fields(k + 1);
   }
+  if (act_sum != nullptr) launch_act_sum(w.act, batch, level->nn, (double)n_steps * dt, act_sum, s);
   launch_qoi(w, level->wts, level->nn, batch, d.qoi, (double)n_steps * dt, level->vol, qoi_dev, s);
   HIP_OK(hipMemcpyAsync(status_dev, w.status, sizeof(int32_t) * batch, hipMemcpyDeviceToDevice, s));
   HIP_OK(hipMemcpyAsync(iters_dev, w.iters, sizeof(int64_t) * 2 * batch, hipMemcpyDeviceToDevice, s));
@@ -800,11 +834,103 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
   return mlq_check(stat.data(), batch);
 }
 
+mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t batch, int32_t n_steps, void* ws_dev,
+                              size_t ws_bytes, double* qoi_dev, int32_t* status_dev, int64_t* iters_dev,
+                              double* u_out_dev, double* act_out_dev, void* hip_stream) {
+  return solve_impl(level, theta_dev, batch, n_steps, ws_dev, ws_bytes, qoi_dev, status_dev, iters_dev, u_out_dev,
+                    act_out_dev, nullptr, hip_stream);
+}
+
 mlq_status mlq_solve_batch(mlq_level* level, const void* theta_dev, int32_t batch, void* ws_dev, size_t ws_bytes,
                            double* qoi_dev, int32_t* status_dev, int64_t* iters_dev, void* hip_stream) {
   if (level == nullptr) return fail(MLQ_EINVAL, "level is NULL");
-  return mlq_solve_batch_ex(level, theta_dev, batch, level->d.n_steps, ws_dev, ws_bytes, qoi_dev, status_dev,
-                            iters_dev, nullptr, nullptr, hip_stream);
+  return solve_impl(level, theta_dev, batch, level->d.n_steps, ws_dev, ws_bytes, qoi_dev, status_dev, iters_dev,
+                    nullptr, nullptr, nullptr, hip_stream);
+}
+
+mlq_status mlq_solve_batch_fields(mlq_level* level, const void* theta_dev, int32_t batch, void* ws_dev,
+                                  size_t ws_bytes, double* qoi_dev, int32_t* status_dev, int64_t* iters_dev,
+                                  const mlq_field_out* fields, void* hip_stream) {
+  if (level == nullptr || fields == nullptr) return fail(MLQ_EINVAL, "NULL argument");
+  return solve_impl(level, theta_dev, batch, level->d.n_steps, ws_dev, ws_bytes, qoi_dev, status_dev, iters_dev,
+                    nullptr, nullptr, fields, hip_stream);
+}
+
+mlq_status mlq_probe_weights(const mlq_level* level, const double* xyz, int32_t n_points, int64_t* node_out,
+                             double* w_out) {
+  if (level == nullptr || (n_points > 0 && (xyz == nullptr || node_out == nullptr || w_out == nullptr)))
+    return fail(MLQ_EINVAL, "NULL argument");
+  if (n_points < 0) return fail(MLQ_EINVAL, "negative point count");
+  if (level->tet) return fail(MLQ_EINVAL, "probe weights are computed for box levels; use vertex probes on tetrahedra");
+  const mlq_level_desc& d = level->d;
+  for (int32_t p = 0; p < n_points; ++p) {
+    int64_t q[3] = {0, 0, 0};
+    double x[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d.dim; ++a) {
+      const double h = (d.hi[a] - d.lo[a]) / (double)(d.n[a] - 1);
+      const double r = (xyz[3 * p + a] - d.lo[a]) / h;
+      if (!(r >= -1e-12 * (double)(d.n[a] - 1) && r <= (double)(d.n[a] - 1) * (1.0 + 1e-12)))
+        return fail(MLQ_EINVAL, "probe point %d lies outside the box", p);
+      int64_t c = (int64_t)std::floor(r);
+      c = std::min<int64_t>(std::max<int64_t>(c, 0), d.n[a] - 2);
+      q[a] = c;
+      x[a] = std::min(std::max(r - (double)c, 0.0), 1.0);
+    }
+    for (int c = 0; c < kProbeNodes; ++c) {
+      double w = 1.0;
+      int64_t idx = 0, stride = 1;
+      bool used = true;
+      for (int a = 0; a < 3; ++a) {
+        const int o = (c >> a) & 1;
+        if (a >= d.dim) {
+          if (o) used = false;
+          continue;
+        }
+        w *= o ? x[a] : 1.0 - x[a];
+        idx += (q[a] + o) * stride;
+        stride *= d.n[a];
+      }
+      node_out[kProbeNodes * p + c] = used ? idx : 0;
+      w_out[kProbeNodes * p + c] = used ? w : 0.0;
+    }
+  }
+  return MLQ_OK;
+}
+
+mlq_status mlq_transfer_add(const mlq_level* from, const mlq_level* to, int32_t space, int32_t time, int64_t rows,
+                            double alpha, const double* src_dev, double* dst_dev, void* hip_stream) {
+  if (from == nullptr || to == nullptr || src_dev == nullptr || dst_dev == nullptr)
+    return fail(MLQ_EINVAL, "NULL argument");
+  if (rows < 1) return fail(MLQ_EINVAL, "rows must be >= 1");
+  XferGeo g;
+  for (int a = 0; a < 3; ++a) g.sn_f[a] = g.sn_t[a] = 1;
+  g.tn_f = g.tn_t = 1;
+  g.m_f = g.m_t = 1;
+  const mlq_level_desc& df = from->d;
+  const mlq_level_desc& dt = to->d;
+  if (space) {
+    if (from->tet || to->tet) return fail(MLQ_EINVAL, "space transfer needs nested box levels");
+    if (df.dim != dt.dim) return fail(MLQ_EINVAL, "levels of different dimension");
+    for (int a = 0; a < df.dim; ++a) {
+      const double tol = 1e-12 * std::max(1.0, std::fabs(df.hi[a] - df.lo[a]));
+      if (std::fabs(df.lo[a] - dt.lo[a]) > tol || std::fabs(df.hi[a] - dt.hi[a]) > tol)
+        return fail(MLQ_EINVAL, "levels cover different boxes");
+      if ((dt.n[a] - 1) % (df.n[a] - 1) != 0) return fail(MLQ_EINVAL, "levels are not nested along axis %d", a);
+      g.sn_f[a] = df.n[a];
+      g.sn_t[a] = dt.n[a];
+    }
+  }
+  if (time) {
+    if (std::fabs(df.t_end - dt.t_end) > 1e-12 * df.t_end) return fail(MLQ_EINVAL, "levels end at different times");
+    if (dt.n_steps % df.n_steps != 0) return fail(MLQ_EINVAL, "time grids are not nested");
+    g.tn_f = df.n_steps + 1;
+    g.tn_t = dt.n_steps + 1;
+    g.m_f = df.n_steps;
+    g.m_t = dt.n_steps;
+  }
+  launch_transfer(g, rows, alpha, src_dev, dst_dev, (hipStream_t)hip_stream);
+  HIP_OK(hipGetLastError());
+  return MLQ_OK;
 }
 
 mlq_status mlq_check(const int32_t* status_host, int32_t batch) {

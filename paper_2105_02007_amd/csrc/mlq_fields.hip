@@ -1,0 +1,160 @@
+// Field quantities of interest (Section 2.4) streamed during a solve, and the transfer of
+// space-time fields between nested box levels (Section 5, error measures: the tensor product
+// of the space and the time interpolation).
+//
+// All of them are HBM-streaming kernels with no reuse beyond a cache line: one thread per
+// output node, consecutive threads on consecutive nodes so that every wave reads whole
+// 512-byte segments of each sample's state.
+#include "mlq_internal.h"
+
+namespace mlq {
+
+// u_sum[i] += sum_b u[b n + i], samples added in order b = 0 .. B-1.
+__global__ __launch_bounds__(kBlock) void k_field_sum(const double* __restrict__ u, int32_t B, int64_t n,
+                                                      double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int32_t b = 0; b < B; ++b) acc += u[(int64_t)b * n + i];
+  dst[i] += acc;
+}
+
+void launch_field_sum(const double* u, int32_t B, int64_t n, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_field_sum, dim3((unsigned)cdiv(n, kBlock)), dim3(kBlock), 0, s, u, B, n, dst);
+}
+
+// act_sum[i] += sum_b a_b(i), a never-activated node (a < 0) counted at the stop time.
+__global__ __launch_bounds__(kBlock) void k_act_sum(const double* __restrict__ act, int32_t B, int64_t n,
+                                                    double t_stop, double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int32_t b = 0; b < B; ++b) {
+    const double a = act[(int64_t)b * n + i];
+    acc += a < 0.0 ? t_stop : a;
+  }
+  dst[i] += acc;
+}
+
+void launch_act_sum(const double* act, int32_t B, int64_t n, double t_stop, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_act_sum, dim3((unsigned)cdiv(n, kBlock)), dim3(kBlock), 0, s, act, B, n, t_stop, dst);
+}
+
+// out[(b np + p) ld + k] = sum_j w[p][j] u[b n + node[p][j]]: one thread per (sample, probe).
+__global__ __launch_bounds__(kBlock) void k_probe(const double* __restrict__ u, int32_t B, int64_t n, ProbeTab tab,
+                                                  int32_t k, int32_t ld, double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B * tab.n) return;
+  const int b = t / tab.n, p = t % tab.n;
+  const double* ub = u + (int64_t)b * n;
+  double acc = 0.0;
+  for (int j = 0; j < kProbeNodes; ++j) acc += tab.w[p * kProbeNodes + j] * ub[tab.node[p * kProbeNodes + j]];
+  out[(int64_t)t * ld + k] = acc;
+}
+
+void launch_probe(const double* u, int32_t B, int64_t n, const ProbeTab& tab, int32_t k, int32_t ld, double* out,
+                  hipStream_t s) {
+  const int total = B * tab.n;
+  hipLaunchKernelGGL(k_probe, dim3((unsigned)cdiv(total, kBlock)), dim3(kBlock), 0, s, u, B, n, tab, k, ld, out);
+}
+
+// sum[p ld + k] += sum_b sum_j w[p][j] u[b n + node[p][j]]: one wave per probe, its lanes over
+// the samples, a fixed-order tree over the lanes.
+__global__ __launch_bounds__(64) void k_probe_sum(const double* __restrict__ u, int32_t B, int64_t n, ProbeTab tab,
+                                                  int32_t k, int32_t ld, double* __restrict__ sum) {
+  const int p = blockIdx.x, lane = threadIdx.x;
+  double acc = 0.0;
+  for (int b = lane; b < B; b += 64) {
+    const double* ub = u + (int64_t)b * n;
+    double v = 0.0;
+    for (int j = 0; j < kProbeNodes; ++j) v += tab.w[p * kProbeNodes + j] * ub[tab.node[p * kProbeNodes + j]];
+    acc += v;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) sum[(int64_t)p * ld + k] += acc;
+}
+
+void launch_probe_sum(const double* u, int32_t B, int64_t n, const ProbeTab& tab, int32_t k, int32_t ld, double* sum,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_probe_sum, dim3((unsigned)tab.n), dim3(64), 0, s, u, B, n, tab, k, ld, sum);
+}
+
+// dst[(r T_t + k') S_t + i'] += alpha * sum over the time and space stencils of src[(r T_f + k) S_f + i].
+// Time: coarse node kc = floor(k' m_f / m_t) with weight 1 - th and kc + 1 with th,
+// th = ((k' m_f) mod m_t) / m_t.  Space, per axis: coarse index q = floor(i'_a (n_f - 1) / (n_t - 1))
+// with weight 1 - x, q + 1 with x, x = ((i'_a (n_f - 1)) mod (n_t - 1)) / (n_t - 1).  A stencil
+// point of weight zero is not read (it may lie past the end of the grid).
+// Threads in x cover (row, fine node); the space stencil is formed once per thread and reused
+// for every output time node, which the y dimension strides over.
+__global__ __launch_bounds__(kBlock) void k_transfer(XferGeo g, int64_t rows, double alpha,
+                                                     const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t St = g.sn_t[0] * g.sn_t[1] * g.sn_t[2];
+  const int64_t Sf = g.sn_f[0] * g.sn_f[1] * g.sn_f[2];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * St) return;
+  const int64_t r = t / St;
+  int64_t rem = t - r * St;
+  const int64_t ip = rem;
+  int64_t q[3];
+  double x[3];
+  for (int a = 0; a < 3; ++a) {
+    const int64_t ia = rem % g.sn_t[a];
+    rem /= g.sn_t[a];
+    if (g.sn_t[a] > 1) {
+      const int64_t num = ia * (g.sn_f[a] - 1);
+      q[a] = num / (g.sn_t[a] - 1);
+      x[a] = (double)(num - q[a] * (g.sn_t[a] - 1)) / (double)(g.sn_t[a] - 1);
+    } else {
+      q[a] = 0;
+      x[a] = 0.0;
+    }
+  }
+  int64_t off[8];
+  double ws[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    double w = 1.0;
+    int64_t idx = 0, stride = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int o = (c >> a) & 1;
+      w *= o ? x[a] : 1.0 - x[a];
+      idx += (q[a] + o) * stride;
+      stride *= g.sn_f[a];
+    }
+    off[c] = w == 0.0 ? 0 : idx;  // a zero-weight corner is never read
+    ws[c] = w;
+  }
+  const double* sr = src + r * g.tn_f * Sf;
+  double* dr = dst + r * g.tn_t * St + ip;
+  for (int64_t kp = blockIdx.y; kp < g.tn_t; kp += gridDim.y) {
+    int64_t kc = 0;
+    double th = 0.0;
+    if (g.tn_t > 1) {
+      const int64_t num = kp * g.m_f;
+      kc = num / g.m_t;
+      th = (double)(num - kc * g.m_t) / (double)g.m_t;
+    }
+    double acc = 0.0;
+    for (int dtm = 0; dtm < 2; ++dtm) {
+      const double wt = dtm ? th : 1.0 - th;
+      if (wt == 0.0) continue;
+      const double* sk = sr + (kc + dtm) * Sf;
+      double part = 0.0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (ws[c] != 0.0) part += ws[c] * sk[off[c]];
+      acc += wt * part;
+    }
+    dr[kp * St] += alpha * acc;
+  }
+}
+
+void launch_transfer(const XferGeo& g, int64_t rows, double alpha, const double* src, double* dst, hipStream_t s) {
+  const int64_t nx = rows * g.sn_t[0] * g.sn_t[1] * g.sn_t[2];
+  if (nx < 1 || g.tn_t < 1) return;
+  const unsigned gy = (unsigned)(g.tn_t < 1024 ? g.tn_t : 1024);
+  hipLaunchKernelGGL(k_transfer, dim3((unsigned)cdiv(nx, kBlock), gy), dim3(kBlock), 0, s, g, rows, alpha, src, dst);
+}
+
+}  // namespace mlq

@@ -150,6 +150,28 @@ void launch_kl(const double* phi64T, const float* phi32T, const double* sqrt_lam
 void launch_transpose_f64(const double* src, double* dst, int64_t rows, int64_t cols, hipStream_t s);
 void launch_lattice(const int64_t* z, const double* shift, int32_t sdim, int64_t N, int64_t first,
                     int32_t count, double* Y, hipStream_t s);
+// Field quantities of interest: probe table (passed by value as a kernel argument) and the
+// geometry of a space-time transfer (spatial node counts per axis, time node counts, steps).
+constexpr int kMaxProbes = 16;
+constexpr int kProbeNodes = 8;
+struct ProbeTab {
+  int64_t node[kMaxProbes * kProbeNodes];
+  double w[kMaxProbes * kProbeNodes];
+  int32_t n;
+};
+struct XferGeo {
+  int64_t sn_f[3], sn_t[3];  // spatial nodes per axis, from / to (1 on unused axes or no space transfer)
+  int64_t tn_f, tn_t;        // time nodes, from / to (1 when no time transfer)
+  int64_t m_f, m_t;          // steps, from / to
+};
+void launch_field_sum(const double* u, int32_t B, int64_t n, double* dst, hipStream_t s);
+void launch_act_sum(const double* act, int32_t B, int64_t n, double t_stop, double* dst, hipStream_t s);
+void launch_probe(const double* u, int32_t B, int64_t n, const ProbeTab& tab, int32_t k, int32_t ld, double* out,
+                  hipStream_t s);
+void launch_probe_sum(const double* u, int32_t B, int64_t n, const ProbeTab& tab, int32_t k, int32_t ld, double* sum,
+                      hipStream_t s);
+void launch_transfer(const XferGeo& g, int64_t rows, double alpha, const double* src, double* dst, hipStream_t s);
+
 constexpr int kHaltonMaxDims = 1024;
 void launch_halton(int32_t sdim, int64_t first, int32_t count, const double* shift, bool uniform, double* Y,
                    hipStream_t s);

@@ -119,8 +119,9 @@ class ConfigRunner:
         self.level_dof_iters = [0.0] * len(self.levels)
         self.level_seconds = [0.0] * len(self.levels)
 
-    def solve(self, l: int, Y: torch.Tensor):
-        """QoIs (device FP64) of the samples Y (M x B, device FP64) on level l."""
+    def solve(self, l: int, Y: torch.Tensor, fields=None):
+        """QoIs (device FP64) of the samples Y (M x B, device FP64) on level l; with `fields`
+        (keyword arguments of Level.solve_fields) the field outputs are streamed as well."""
         L = self.levels[l]
         t0 = time.perf_counter()
         if self.vector:  # Y stacks the coordinates of the components: (components x M, B)
@@ -129,7 +130,7 @@ class ConfigRunner:
                                  for c in range(self.components)])
         else:
             theta = L.sample_fields(Y)
-        out = L.solve(theta)
+        out = L.solve(theta) if fields is None else L.solve_fields(theta, per_sample_probes=False, **fields)
         if out["code"] != mlq.MLQ_OK:
             st = out["status"].cpu().numpy()
             raise mlq.MlqError(out["code"], f"{int((st != 0).sum())} samples failed on level {l}")
@@ -147,15 +148,15 @@ class ConfigRunner:
         return out["qoi"]
 
     def solve_all(self, jobs):
-        """QoIs of the jobs [(level, Y)], in order.  The finest level's solves run first on
+        """QoIs of the jobs [(level, Y)] or [(level, Y, fields)], in order.  The finest level's solves run first on
         their own (so that its kernels, which dominate the cost, have the GPU to
         themselves), then all other levels at the same time (co-scheduled on one GPU: the
         small levels' latency-bound launches fill each other's gaps).  The results do not
         depend on the schedule: every solve is independent and the estimators sum on the
         host in sample order."""
-        levels = sorted({l for l, _ in jobs}, reverse=True)
+        levels = sorted({job[0] for job in jobs}, reverse=True)
         if not self.concurrent or len(levels) < 3:
-            return [self.solve(l, Y) for l, Y in jobs]
+            return [self.solve(*job) for job in jobs]
         main = torch.cuda.current_stream()
         out = [None] * len(jobs)
 
@@ -163,9 +164,9 @@ class ConfigRunner:
             s = self.streams[l]
             s.wait_stream(main)  # the inputs were written on the caller's stream
             with torch.cuda.stream(s):
-                for i, (lj, Y) in enumerate(jobs):
-                    if lj == l:
-                        out[i] = self.solve(l, Y)
+                for i, job in enumerate(jobs):
+                    if job[0] == l:
+                        out[i] = self.solve(*job)
                 s.synchronize()
 
         work(levels[0])
@@ -193,6 +194,56 @@ class ConfigRunner:
             else:
                 fc.append(None)
         return self._estimate(mlq.MLQ_EST_MLMC, ff, fc, [Y.shape[1] for Y in Ys], 1)
+
+    def run_mlmc_fields(self, Ys, probes=None):
+        """eq. (StandardML) for the field quantities of interest of Section 2.4, with independent
+        MC sets Ys[l] (nested box levels): the mean transmembrane potential E[u] on the finest
+        level's space-time grid ((m_L + 1) x n_L), the mean activation map on its nodes, and the
+        mean action potential at the probe points (P x 3) on its time grid.  Each solve streams
+        its sums on its own level's grid; the level terms are moved to the finest grid by the
+        space-time transfer, so that the estimate is
+            sum_l (1/N_l) (T_l S_fine(l) - T_(l-1) S_coarse(l)),
+        with S the sums over the level's samples.  Also returns the scalar estimate."""
+        if self.tet:
+            raise ValueError("field estimates transfer between nested box levels")
+        dev = self.device
+        fin = self.levels[-1]
+
+        def zeros(*shape):
+            return torch.zeros(shape, dtype=torch.float64, device=dev)
+        pw = [lv.probe_weights(probes) for lv in self.levels] if probes is not None else None
+        npr = 0 if probes is None else len(probes)
+        jobs, meta = [], []
+        for l, Y in enumerate(Ys):
+            for j, sign in [(l, 1.0)] + ([(l - 1, -1.0)] if l > 0 else []):
+                lv = self.levels[j]
+                f = dict(u_sum=zeros(lv.desc.n_steps + 1, lv.n_nodes), act_sum=zeros(lv.n_nodes))
+                if npr:
+                    f.update(probe_node=pw[j][0], probe_w=pw[j][1], probe_sum=zeros(npr, lv.desc.n_steps + 1))
+                jobs.append((j, Y, f))
+                meta.append((j, sign / Y.shape[1]))
+        res = self.solve_all(jobs)
+        est_u = zeros(fin.desc.n_steps + 1, fin.n_nodes)
+        est_a = zeros(fin.n_nodes)
+        est_p = zeros(npr, fin.desc.n_steps + 1) if npr else None
+        for (j, alpha), (_, _, f) in zip(meta, jobs):
+            lv = self.levels[j]
+            mlq.transfer_add(lv, fin, f["u_sum"], est_u, alpha=alpha)
+            mlq.transfer_add(lv, fin, f["act_sum"], est_a, alpha=alpha, time=False)
+            if npr:
+                mlq.transfer_add(lv, fin, f["probe_sum"], est_p, alpha=alpha, space=False, rows=npr)
+        ff, fc, k = [], [], 0
+        for l in range(len(Ys)):
+            ff.append(res[k])
+            k += 1
+            if l > 0:
+                fc.append(res[k])
+                k += 1
+            else:
+                fc.append(None)
+        out = self._estimate(mlq.MLQ_EST_MLMC, ff, fc, [Y.shape[1] for Y in Ys], 1)
+        out.update(mean_u=est_u, mean_act_map=est_a, mean_probe=est_p)
+        return out
 
     def run_mc(self, Y, level=0):
         f = self.solve(level, Y)

@@ -26,7 +26,8 @@ EXPORTED = [
     "mlq_sample_fields", "mlq_solve_batch", "mlq_solve_batch_ex", "mlq_apply", "mlq_check",
     "mlq_lattice_normals", "mlq_halton", "mlq_cbc", "mlq_accumulate", "mlq_estimate", "mlq_last_error",
     "mlq_kl_workspace_bytes", "mlq_kl_modes", "mlq_kl_transfer", "mlq_timing_enable", "mlq_timing_read",
-    "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet",
+    "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet", "mlq_solve_batch_fields", "mlq_probe_weights",
+    "mlq_transfer_add",
 ]
 MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE = 0, 1
 MLQ_DIFF_FIBRE, MLQ_DIFF_ISO, MLQ_DIFF_VECTOR = 0, 1, 2
@@ -103,6 +104,9 @@ def _load():
         "mlq_check": [VP, I32],
         "mlq_lattice_normals": [VP, VP, I32, I64, I64, I32, VP, VP],
         "mlq_halton": [I32, I64, I32, VP, I32, VP, VP],
+        "mlq_solve_batch_fields": [VP, VP, I32, VP, C.c_size_t, VP, VP, VP, VP, VP],
+        "mlq_probe_weights": [VP, VP, I32, VP, VP],
+        "mlq_transfer_add": [VP, VP, I32, I32, I64, C.c_double, VP, VP, VP],
         "mlq_cbc": [I64, I32, VP, VP],
         "mlq_accumulate": [VP, VP, I32, VP, VP],
         "mlq_estimate": [I32, I32, I32, VP, VP, VP, C.POINTER(EstimateOut)],
@@ -142,6 +146,14 @@ def _stream(stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+class FieldOut(C.Structure):
+    _fields_ = [("u_sum", C.c_void_p), ("act_sum", C.c_void_p), ("probe", C.c_void_p), ("n_probe", C.c_int32),
+                ("probe_node", C.c_void_p), ("probe_w", C.c_void_p), ("probe_sum", C.c_void_p)]
+
+
+PROBE_NODES = 8
 
 
 def make_desc(level: dict, phys: dict, *, n_modes=0, phi=None, sqrt_lambda=None, theta0=None,
@@ -280,6 +292,53 @@ class Level:
             check(code)
         return dict(qoi=qoi, status=status, iters=iters, u=u, act=act, code=code)
 
+    def solve_fields(self, theta, u_sum=None, act_sum=None, probe_node=None, probe_w=None, probe_sum=None,
+                     per_sample_probes=True):
+        """Solve with field outputs: u_sum ((n_steps + 1) x n), act_sum (n) and probe_sum
+        (n_probe x (n_steps + 1)) device FP64 tensors are added into; probe_node / probe_w
+        (n_probe x 8 host arrays) select probe points, whose per-sample series come back as
+        out["probe"] (B x n_probe x (n_steps + 1)) unless per_sample_probes is False."""
+        import torch
+        B = theta.shape[-2]
+        ws, nbytes = self.workspace(B)
+        qoi = torch.empty(B, dtype=torch.float64, device=self.device)
+        status = torch.empty(B, dtype=torch.int32, device=self.device)
+        iters = torch.empty((B, 2), dtype=torch.int64, device=self.device)
+        f = FieldOut()
+        keep = []
+        probe = None
+        if u_sum is not None:
+            f.u_sum = u_sum.data_ptr()
+        if act_sum is not None:
+            f.act_sum = act_sum.data_ptr()
+        if probe_node is not None:
+            pn = np.ascontiguousarray(probe_node, dtype=np.int64).reshape(-1, PROBE_NODES)
+            pw = np.ascontiguousarray(probe_w, dtype=np.float64).reshape(-1, PROBE_NODES)
+            keep += [pn, pw]
+            if per_sample_probes:
+                probe = torch.empty((B, pn.shape[0], self.desc.n_steps + 1), dtype=torch.float64,
+                                    device=self.device)
+                f.probe = probe.data_ptr()
+            if probe_sum is not None:
+                f.probe_sum = probe_sum.data_ptr()
+            f.n_probe = pn.shape[0]
+            f.probe_node, f.probe_w = pn.ctypes.data, pw.ctypes.data
+        code = lib.mlq_solve_batch_fields(self.handle, _ptr(theta), int(B), _ptr(ws), nbytes, _ptr(qoi),
+                                          _ptr(status), _ptr(iters), C.byref(f), _stream())
+        if code not in (MLQ_OK, MLQ_ENOCONV):
+            check(code)
+        return dict(qoi=qoi, status=status, iters=iters, probe=probe, code=code)
+
+    def probe_weights(self, points):
+        """(node, weight) host arrays (P x 8) of the Q1 interpolant at points (P x 3) of a box level."""
+        pts = np.zeros((len(points), 3))
+        p = np.asarray(points, dtype=np.float64)
+        pts[:, :p.shape[1]] = p
+        node = np.zeros((len(pts), PROBE_NODES), dtype=np.int64)
+        w = np.zeros((len(pts), PROBE_NODES))
+        check(lib.mlq_probe_weights(self.handle, pts.ctypes.data, int(len(pts)), node.ctypes.data, w.ctypes.data))
+        return node, w
+
     def timing_enable(self, classes=("apply",)):
         mask = 0
         for c in classes:
@@ -301,6 +360,13 @@ class Level:
         check(lib.mlq_apply(self.handle, _ptr(theta), int(B), _ptr(x), _ptr(d), _ptr(y), _ptr(ws), nbytes,
                             _stream()))
         return y
+
+
+def transfer_add(src_level, dst_level, src, dst, alpha=1.0, space=True, time=True, rows=1):
+    """dst += alpha * (time x space interpolation) src between the grids of two levels."""
+    check(lib.mlq_transfer_add(src_level.handle, dst_level.handle, 1 if space else 0, 1 if time else 0, int(rows),
+                               float(alpha), _ptr(src), _ptr(dst), _stream()))
+    return dst
 
 
 def lattice_normals(z, shift, N, first, count, device="cuda"):
