@@ -55,6 +55,10 @@ def counter_traffic(config, prec):
         return None
     return float(rec["hbm_bytes_per_alg_byte"])
 
+# probe points of the action potential (--fields), in the unit box: near the stimulus, the
+# centre, a face, the far corner
+FIELD_PROBES = [[0.05, 0.05, 0.05], [0.5, 0.5, 0.5], [1.0, 0.5, 0.25], [1.0, 1.0, 1.0]]
+
 WORKLOAD_TEXT = {
     "c1": "2D unit square Q1 33x33, 64 steps, 16-mode KL (l=0.2, s=0.3 rad), 16 MC samples, mean u(T), FP64",
     "c2": "3D unit cube Q1 9^3..65^3 nested, 32..256 steps, 64-mode KL (l=0.1, s=0.3 rad) on 65^3, "
@@ -236,6 +240,9 @@ def main():
     ap.add_argument("--breakdown", action="store_true", help="extra untimed pass timing every kernel class")
     ap.add_argument("--no-qoi-check", action="store_true",
                     help="skip the FP64 re-solve of a few finest-level samples after a mixed-precision run")
+    ap.add_argument("--fields", action="store_true",
+                    help="MLMC workloads: also estimate the field quantities of interest (mean space-time "
+                         "potential on the finest grid, mean activation map, mean action potential at 4 points)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB FP64 copy (torch.neg) before warm-up, as a counter reference")
     args = ap.parse_args()
@@ -277,6 +284,9 @@ def main():
               for l, n in enumerate(samp["n_per_level"])]
         if kind == "mc":
             step = lambda: runner.run_mc(Ys[0])
+        elif args.fields:
+            probes = np.array(FIELD_PROBES)[:, :cfg["dim"]]
+            step = lambda: runner.run_mlmc_fields(Ys, probes=probes)
         else:
             step = lambda: runner.run_mlmc(Ys)
     else:
@@ -380,6 +390,30 @@ def main():
         "roofline": roofline,
         "apply_per_level": per_level,
     }
+    if args.fields:
+        # the domain mean of the estimated activation map equals the scalar estimate (the
+        # transfer is the Q1 interpolant, which the lumped node weights integrate exactly)
+        fl = cfg["levels"][-1]
+        w1 = []
+        for a in range(cfg["dim"]):
+            h = (fl["hi"][a] - fl["lo"][a]) / (fl["n"][a] - 1)
+            v = torch.full((fl["n"][a],), h, dtype=torch.float64, device=dev)
+            v[0] = v[-1] = 0.5 * h
+            w1.append(v)
+        wts = w1[0]
+        for v in w1[1:]:
+            wts = (v[:, None] * wts[None, :]).reshape(-1)
+        ea, eu, ep = res["mean_act_map"], res["mean_u"], res["mean_probe"]
+        act_mean = float((wts * ea).sum() / wts.sum())
+        line["fields"] = {
+            "u_grid": list(eu.shape), "u_bytes": eu.numel() * 8,
+            "act_map_domain_mean": act_mean,
+            "act_map_mean_minus_estimate": act_mean - res["estimate"],
+            "probes": FIELD_PROBES,
+            # the mean action potential at the probes at a quarter, half and all of [0, T]
+            "mean_action_potential": {f"{f:g}T": [float(x) for x in ep[:, int(round(f * (ep.shape[1] - 1)))].cpu()]
+                                      for f in (0.25, 0.5, 1.0)},
+        }
     # per level: its solves' DOF x iterations over their host wall time (the coarser levels
     # run concurrently, so their rates are while sharing the GPU)
     line["levels"] = [dict(level=l, dof_iters_per_s=(runner.level_dof_iters[l] / runner.level_seconds[l]

@@ -164,3 +164,8 @@ def test_mlmc_field_estimate_matches_oracle(env):
     assert gu.shape == est_u.shape and np.abs(gu - est_u).max() <= 1e-10 * np.abs(est_u).max()
     assert np.abs(ga - est_a).max() <= 1e-8 * T
     assert np.abs(gp - est_p).max() <= 1e-10 * np.abs(est_p).max()
+    # the domain mean of the activation map estimate is the scalar estimate of the mean
+    # activation time (the lumped weights integrate the transferred Q1 fields exactly)
+    from oracle import fem
+    wts = np.asarray(fem.assemble_mass(meshes[1]).sum(axis=1)).ravel()
+    assert abs(wts @ ga / wts.sum() - res["estimate"]) <= 1e-12 * abs(res["estimate"])
