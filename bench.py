@@ -201,7 +201,7 @@ def kl_synthesis(runner, cfg, dev, reps=5):
     import workloads as W
     l = len(runner.levels) - 1
     L = runner.levels[l]
-    M = cfg["kl"]["n_modes"]
+    M = runner.n_modes
     samp = cfg["sampling"]
     if samp["kind"] == "combination":  # the finest level sees the points of Q_0
         B = samp["n_per_level"][0]
@@ -271,7 +271,7 @@ def main():
     log(f"set-up done in {t_setup:.1f} s (KL rank {runner.kl_rank})")
     runner.log = log
     samp = cfg["sampling"]
-    M = cfg["kl"]["n_modes"]
+    M = runner.n_modes
     kind = samp["kind"]
     Ys = Yc = shifts = None
     draw = W.mc_uniforms if cfg["kl"].get("variables") == "uniform" else W.mc_normals

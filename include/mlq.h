@@ -310,8 +310,8 @@ typedef struct {
   double lo[3], hi[3];
   double std_dev;       /* s */
   double corr_len;      /* l */
-  int32_t n_modes;      /* M <= 1024 */
-  int32_t max_rank;     /* n_modes <= max_rank <= min(4096, nodes) */
+  int32_t n_modes;      /* M <= 1024; 0 asks for the stochastic dimension (see mlq_kl_modes) */
+  int32_t max_rank;     /* max(n_modes, 1) <= max_rank <= min(4096, nodes) */
   double eps;           /* relative trace tolerance of the pivoted Cholesky */
   /* mesh_kind = MLQ_MESH_P1_TET: the KL lives on the vertices of a tetrahedral
    * mesh (host arrays, dim = 3, n/lo/hi ignored) with its P1 mass matrix */
@@ -331,7 +331,10 @@ mlq_status mlq_kl_workspace_bytes(const mlq_kl_desc* kd, size_t* ws_bytes);
 /* Largest n_modes eigenpairs: lambda_host (M, descending) and the M-orthonormal
  * modes psi_dev (n x M column-major FP64 device array, psi_k^T M psi_k = 1, entry of
  * largest magnitude positive).  rank_out: Cholesky rank used; resid_out:
- * trace(C - L L^T) / trace(C).  Synchronises the stream. */
+ * trace(C - L L^T) / trace(C).  Synchronises the stream.
+ * n_modes = 0: the paper's way of fixing M (Section 5.1): the factorisation runs until
+ * trace(C - L L^T) <= eps trace(C) (or max_rank) and only rank_out (that rank, the stochastic
+ * dimension M) and resid_out are written; lambda_host and psi_dev may be NULL. */
 mlq_status mlq_kl_modes(const mlq_kl_desc* kd, void* ws_dev, size_t ws_bytes, double* lambda_host,
                         double* psi_dev, int32_t* rank_out, double* resid_out, void* hip_stream);
 

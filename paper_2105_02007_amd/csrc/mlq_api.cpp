@@ -1119,7 +1119,8 @@ mlq_status mlq_kl_workspace_bytes(const mlq_kl_desc* kd, size_t* ws_bytes) {
 mlq_status mlq_kl_modes(const mlq_kl_desc* kd, void* ws_dev, size_t ws_bytes, double* lambda_host, double* psi_dev,
                         int32_t* rank_out, double* resid_out, void* hip_stream) {
   if (kl_validate(kd) != MLQ_OK) return fail(MLQ_EINVAL, "invalid KL descriptor");
-  if (ws_dev == nullptr || lambda_host == nullptr || psi_dev == nullptr) return fail(MLQ_EINVAL, "NULL argument");
+  if (ws_dev == nullptr || (kd->n_modes > 0 && (lambda_host == nullptr || psi_dev == nullptr)))
+    return fail(MLQ_EINVAL, "NULL argument");
   if (ws_bytes < kl_workspace_bytes(kd)) return fail(MLQ_ESIZE, "KL workspace too small");
   if (((uintptr_t)ws_dev & 255) != 0) return fail(MLQ_EINVAL, "workspace must be 256-byte aligned");
   std::string err;

@@ -471,8 +471,8 @@ mlq_status kl_validate(const mlq_kl_desc* kd) {
       n *= kd->n[a];
     }
   }
-  if (kd->n_modes < 1 || kd->n_modes > 1024) return MLQ_EINVAL;
-  if (kd->max_rank < kd->n_modes || kd->max_rank > 4096 || kd->max_rank > n) return MLQ_EINVAL;
+  if (kd->n_modes < 0 || kd->n_modes > 1024) return MLQ_EINVAL;  // 0: stochastic dimension query
+  if (kd->max_rank < std::max(kd->n_modes, 1) || kd->max_rank > 4096 || kd->max_rank > n) return MLQ_EINVAL;
   if (!(kd->std_dev > 0.0) || !(kd->corr_len > 0.0) || !(kd->eps >= 0.0)) return MLQ_EINVAL;
   if (kd->cov_kernel != MLQ_COV_EXP && kd->cov_kernel != MLQ_COV_SQEXP) return MLQ_EINVAL;
   return MLQ_OK;
@@ -542,6 +542,11 @@ mlq_status kl_modes(const mlq_kl_desc* kd, void* ws, double* lambda_host, double
   if (rank < M) {
     err = "covariance has numerical rank below n_modes";
     return MLQ_EINVAL;
+  }
+  if (M == 0) {  // query: the rank at which the truncation criterion holds is the dimension M
+    if (rank_out) *rank_out = rank;
+    if (resid_out) *resid_out = resid / tr0;
+    return MLQ_OK;
   }
   if (rank == Rmax) {  // residual after the last column
     hipLaunchKernelGGL(k_argmax_sum, dim3((unsigned)nb), dim3(kT), 0, s, w.d, n, 0, w.pv, w.pi, w.ps);

@@ -46,15 +46,25 @@ class ConfigRunner:
         self.iso = cfg.get("model") == "iso"
         # the KL standard deviation is relative to sigma_l (vector model) or E[V] (isotropic)
         std = kcfg["std"] * (self.phys["sigma_l"] if self.vector else kcfg["mean"] if self.iso else 1.0)
+        def make_kd(m, max_rank):
+            if self.tet:
+                return mlq.kl_desc_tet(self.meshes[kcfg["grid_level"]], std, kcfg["corr_len"], m,
+                                       max_rank=max_rank, eps=kl_eps, cov_kernel=cov)
+            return mlq.kl_desc(cfg["dim"], kl_level["n"], kl_level["lo"], kl_level["hi"], std,
+                               kcfg["corr_len"], m, max_rank=max_rank, eps=kl_eps, cov_kernel=cov)
         if self.tet:
             # tetrahedral levels: the seeded shells of the workload (non-nested), the KL on
             # the vertices of the finest one, the transfer by point location
             self.meshes = [W.tet_mesh(lv) for lv in cfg["levels"]]
-            self.kd = mlq.kl_desc_tet(self.meshes[kcfg["grid_level"]], std, kcfg["corr_len"], M,
-                                      max_rank=kl_rank_factor * M, eps=kl_eps, cov_kernel=cov)
-        else:
-            self.kd = mlq.kl_desc(cfg["dim"], kl_level["n"], kl_level["lo"], kl_level["hi"], std,
-                                  kcfg["corr_len"], M, max_rank=kl_rank_factor * M, eps=kl_eps, cov_kernel=cov)
+        if M == 0:
+            # the stochastic dimension from the truncation tolerance (Section 5.1)
+            n_kl = self.meshes[kcfg["grid_level"]]["xyz"].shape[0] if self.tet else int(np.prod(kl_level["n"]))
+            M, resid = mlq.kl_dimension(make_kd(0, min(256, n_kl)), device=device)
+            if resid > kl_eps:
+                raise ValueError(f"the truncation tolerance {kl_eps} needs more than {M} modes")
+            say(f"stochastic dimension M = {M} (trace residual {resid:.4f})")
+        self.n_modes = M
+        self.kd = make_kd(M, kl_rank_factor * M)
         say("KL set-up")
         lam, psi, self.kl_rank, self.kl_resid = mlq.kl_modes(self.kd, device=device)
         say(f"KL modes done (rank {self.kl_rank})")

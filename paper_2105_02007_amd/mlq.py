@@ -490,6 +490,18 @@ def kl_modes(kd: KlDesc, device="cuda"):
     return lam, psi, int(rank.value), float(resid.value)
 
 
+def kl_dimension(kd: KlDesc, device="cuda"):
+    """The stochastic dimension M fixed by the truncation tolerance kd.eps (the pivoted Cholesky
+    rank at which trace(C - L L^T) <= eps trace(C)), and the relative residual there."""
+    m = kd.n_modes
+    kd.n_modes = 0
+    try:
+        _, _, rank, resid = kl_modes(kd, device=device)
+    finally:
+        kd.n_modes = m
+    return rank, resid
+
+
 def kl_transfer(kd: KlDesc, psi, level: dict, device="cuda"):
     """Phi_l (P x M, device FP64) at the element centres of a Q1 box level."""
     import torch

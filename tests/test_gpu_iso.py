@@ -188,3 +188,37 @@ def test_kl_squared_exponential_matches_oracle(env, n):
         if gaps[j] and (j == 0 or gaps[j - 1]):
             ref = V_ref[:, j] / np.sqrt(lam_ref[j])
             assert np.abs(P[:, j] - ref).max() < 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,kernel,corr", [([17, 17, 17], "sqexp", 0.25), ([13, 11, 9], "sqexp", 0.5)])
+def test_stochastic_dimension_from_tolerance_matches_oracle(env, n, kernel, corr):
+    """n_modes = 0 asks the library for the rank at which the pivoted Cholesky meets the
+    truncation tolerance (the paper's way of fixing M); bit-exact integer against the oracle's
+    factorisation, and 65 on the paper's cube set-up (which reports M = 66)."""
+    torch, mlq = env
+    from oracle import kl
+    from oracle.mesh import BoxMesh
+    mesh = BoxMesh(n)
+    cov = mlq.MLQ_COV_SQEXP if kernel == "sqexp" else mlq.MLQ_COV_EXP
+    kd = mlq.kl_desc(3, n, [0.0] * 3, [1.0] * 3, 0.3, corr, 8, max_rank=300, eps=1e-2, cov_kernel=cov)
+    rank, resid = mlq.kl_dimension(kd)
+    L, _ = kl.pivoted_cholesky(mesh.nodes, 0.3, corr, 300, eps=1e-2, kernel=kernel)
+    assert rank == L.shape[1] and resid <= 1e-2
+    assert abs(resid - (1.0 - (L ** 2).sum() / (0.09 * mesh.n_nodes))) <= 1e-10
+    if corr == 0.25:  # the cube of Section 5.1
+        assert rank == 65
+    assert kd.n_modes == 8
+
+
+def test_driver_fixes_the_dimension_from_the_tolerance(env):
+    """A workload with n_modes = 0 takes M from the truncation tolerance."""
+    torch, mlq = env
+    from oracle import kl
+    from oracle.mesh import BoxMesh
+    from paper_2105_02007_amd.driver import ConfigRunner
+    cfg = W.scaled_config("c2i", nodes=[5, 9], steps=[4, 8], n_per_level=[2, 1], n_modes=0)
+    runner = ConfigRunner(cfg, prec=W.PREC_FP64)
+    L, _ = kl.pivoted_cholesky(BoxMesh([9, 9, 9]).nodes, 0.3 * cfg["kl"]["mean"], 0.25, 300, eps=1e-2,
+                               kernel="sqexp")
+    assert runner.n_modes == L.shape[1] == runner.kd.n_modes
+    assert runner.levels[0].desc.n_modes == runner.n_modes
