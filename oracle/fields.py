@@ -73,3 +73,34 @@ def mlmc_field(fine_sums, coarse_sums, n_per_level, transfer):
         if l > 0:
             est = est - transfer(l - 1, coarse_sums[l]) / N
     return est
+
+
+def space_time_norm2(mesh: BoxMesh, field, t_end, q=0):
+    """||f||^2 in L^2((0, T); H^q(D)) (eq. (space-time-error)) of the space-time interpolant of
+    the nodal values field ((m + 1, n): Q1 in space, linear in time), integrated exactly:
+    on [t_k, t_(k+1)], dt/3 (f_k' A f_k + f_k' A f_(k+1) + f_(k+1)' A f_(k+1)) with A = M (q = 0)
+    or M + K (q = 1, K the Laplacian stiffness, so the H^1 norm includes its L^2 part)."""
+    from . import fem
+    F = np.asarray(field, dtype=np.float64)
+    m = F.shape[0] - 1
+    Mm, K = fem.assemble(mesh, fem.conductivity_iso(np.ones(mesh.n_elems), mesh.d))
+    A = Mm if q == 0 else Mm + K
+    AF = np.stack([A @ F[k] for k in range(m + 1)])
+    dt = t_end / m
+    total = 0.0
+    for k in range(m):
+        total += dt / 3.0 * (F[k] @ AF[k] + F[k] @ AF[k + 1] + F[k + 1] @ AF[k + 1])
+    return float(total)
+
+
+def time_norm2(series, t_end, q=0):
+    """||f||^2 in H^q(0, T) (eq. (point-error)) of the linear interpolant of each row of series
+    (..., m + 1): sum_k dt/3 (a^2 + a b + b^2), plus sum_k (b - a)^2 / dt for q = 1."""
+    S = np.asarray(series, dtype=np.float64)
+    m = S.shape[-1] - 1
+    dt = t_end / m
+    a, b = S[..., :-1], S[..., 1:]
+    out = (dt / 3.0 * (a * a + a * b + b * b)).sum(axis=-1)
+    if q == 1:
+        out = out + ((b - a) ** 2 / dt).sum(axis=-1)
+    return out

@@ -100,3 +100,43 @@ def test_field_estimator_mean_and_vanishing_correction():
     fine = sum(fields.prolongate_space_time(Mc, 2, x, Mf, 4, T) for x in g)
     est2 = fields.mlmc_field([sum(f0), fine], [None, sum(g)], [4, 2], tr)
     assert np.allclose(est2, tr(0, sum(f0)) / 4, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("n,hi", [([4, 5, 3], [1.0, 0.7, 1.3]), ([6, 4], [0.5, 2.0])])
+def test_space_time_norms_closed_forms(n, hi):
+    """Exact integrals of functions the space-time interpolant reproduces: a constant c gives
+    c^2 |D| T in both norms; f = t gives |D| T^3 / 3; f = g . x (constant in time) gives
+    T (int (g.x)^2 + |g|^2 |D|) in H^1; the L^2 part of that by the 1D integrals of x^2."""
+    mesh = BoxMesh(n, hi=hi)
+    d = mesh.d
+    vol = float(np.prod(hi))
+    T, m = 0.32, 7
+    t = np.linspace(0, T, m + 1)
+    c = 1.7
+    F = np.full((m + 1, mesh.n_nodes), c)
+    for q in (0, 1):
+        assert np.isclose(fields.space_time_norm2(mesh, F, T, q), c * c * vol * T, rtol=1e-13)
+    F = np.outer(t, np.ones(mesh.n_nodes))
+    assert np.isclose(fields.space_time_norm2(mesh, F, T, 1), vol * T ** 3 / 3, rtol=1e-13)
+    g = np.array([0.3, -1.1, 0.7])[:d]
+    F = np.outer(np.ones(m + 1), mesh.nodes @ g)
+    # int_D (g.x)^2 over a box [0, L]: sum_a g_a^2 L_a^3/3 prod_{b != a} L_b + sum_{a<b} g_a g_b L_a^2 L_b^2/2 prod_rest
+    L = np.array(hi)
+    l2 = 0.0
+    for a in range(d):
+        l2 += g[a] ** 2 * L[a] ** 3 / 3 * np.prod(np.delete(L, a))
+        for b in range(a + 1, d):
+            l2 += 2 * g[a] * g[b] * (L[a] ** 2 / 2) * (L[b] ** 2 / 2) * np.prod(np.delete(L, [a, b]))
+    # Q1 interpolates g.x exactly but the mass of Q1 integrates (g.x)^2 exactly too (it is in Q2)
+    assert np.isclose(fields.space_time_norm2(mesh, F, T, 0), T * l2, rtol=1e-12)
+    assert np.isclose(fields.space_time_norm2(mesh, F, T, 1), T * (l2 + (g @ g) * vol), rtol=1e-12)
+
+
+def test_time_norms_closed_forms():
+    T, m = 0.32, 9
+    t = np.linspace(0, T, m + 1)
+    S = np.stack([np.full(m + 1, 2.0), t, 3.0 - 5.0 * t])
+    l2 = fields.time_norm2(S, T, 0)
+    h1 = fields.time_norm2(S, T, 1)
+    assert np.allclose(l2, [4 * T, T ** 3 / 3, 9 * T - 15 * T ** 2 + 25 * T ** 3 / 3], rtol=1e-13)
+    assert np.allclose(h1 - l2, [0.0, T, 25 * T], rtol=1e-13, atol=1e-15)
