@@ -408,6 +408,8 @@ def main():
         line["fields"] = {
             "u_grid": list(eu.shape), "u_bytes": eu.numel() * 8,
             "act_map_domain_mean": act_mean,
+            # per level: ||mean_0|| and ||mean_l - T mean_(l-1)|| in L^2((0,T); L^2), L^2((0,T); H^1)
+            "level_term_norms_l2_h1": res["level_term_norms"],
             "act_map_mean_minus_estimate": act_mean - res["estimate"],
             "probes": FIELD_PROBES,
             # the mean action potential at the probes at a quarter, half and all of [0, T]

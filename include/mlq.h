@@ -229,6 +229,18 @@ mlq_status mlq_probe_weights(const mlq_level* level, const double* xyz_host, int
 mlq_status mlq_transfer_add(const mlq_level* from, const mlq_level* to, int32_t space, int32_t time, int64_t rows,
                             double alpha, const double* src_dev, double* dst_dev, void* hip_stream);
 
+/* Squared error norms of fields on a level's grids (eq. (space-time-error), eq. (point-error)):
+ *   space = 1: f_dev is rows x (n_steps + 1) x n (space-time fields of a box level);
+ *     out_dev[r] = ||f_r||^2 in L^2((0, T); H^q(D)) of the interpolant that is Q1 in space and
+ *     linear in time, integrated exactly (q = 1: the full H^1 norm, L^2 part included);
+ *     part_dev: rows x 1024 FP64 device scratch for partial sums;
+ *   space = 0: f_dev is rows x (n_steps + 1) (time series, e.g. probe outputs);
+ *     out_dev[r] = ||f_r||^2 in H^q(0, T) of the linear interpolant; part_dev unused.
+ * q is 0 or 1, 1 <= rows <= 65535; out_dev: rows FP64 on the device.  The sums run in a fixed
+ * order (results do not vary between runs).  Enqueues only. */
+mlq_status mlq_field_norm2(const mlq_level* level, int32_t space, int32_t q, int64_t rows, const double* f_dev,
+                           double* part_dev, double* out_dev, void* hip_stream);
+
 /* Jacobian of one step (Section 3.2) applied matrix-free to a batch:
  *   y = M ((1 + d) x) + dt/2 K_G x,
  * with G per element from theta (level precision).  x, d, y: batch x n in the

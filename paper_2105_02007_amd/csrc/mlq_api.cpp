@@ -897,6 +897,34 @@ mlq_status mlq_probe_weights(const mlq_level* level, const double* xyz, int32_t 
   return MLQ_OK;
 }
 
+mlq_status mlq_field_norm2(const mlq_level* level, int32_t space, int32_t q, int64_t rows, const double* f_dev,
+                           double* part_dev, double* out_dev, void* hip_stream) {
+  if (level == nullptr || f_dev == nullptr || out_dev == nullptr) return fail(MLQ_EINVAL, "NULL argument");
+  if (q != 0 && q != 1) return fail(MLQ_EINVAL, "q must be 0 (L2) or 1 (H1)");
+  if (rows < 1 || rows > 65535) return fail(MLQ_EINVAL, "rows outside [1, 65535]");
+  const mlq_level_desc& d = level->d;
+  const double dt = d.t_end / (double)d.n_steps;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (space) {
+    if (level->tet) return fail(MLQ_EINVAL, "space-time norms are computed on box levels");
+    if (part_dev == nullptr) return fail(MLQ_EINVAL, "space-time norms need the partial-sum scratch");
+    NormGeo g;
+    g.dim = d.dim;
+    for (int a = 0; a < 3; ++a) {
+      g.n[a] = a < d.dim ? d.n[a] : 1;
+      g.h[a] = a < d.dim ? (d.hi[a] - d.lo[a]) / (double)(d.n[a] - 1) : 1.0;
+    }
+    g.m = d.n_steps;
+    g.dt = dt;
+    g.q = q;
+    launch_st_norm(g, rows, f_dev, part_dev, out_dev, s);
+  } else {
+    launch_time_norm(f_dev, rows, d.n_steps, dt, q, out_dev, s);
+  }
+  HIP_OK(hipGetLastError());
+  return MLQ_OK;
+}
+
 mlq_status mlq_transfer_add(const mlq_level* from, const mlq_level* to, int32_t space, int32_t time, int64_t rows,
                             double alpha, const double* src_dev, double* dst_dev, void* hip_stream) {
   if (from == nullptr || to == nullptr || src_dev == nullptr || dst_dev == nullptr)

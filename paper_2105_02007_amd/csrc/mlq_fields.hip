@@ -157,4 +157,104 @@ void launch_transfer(const XferGeo& g, int64_t rows, double alpha, const double*
   hipLaunchKernelGGL(k_transfer, dim3((unsigned)cdiv(nx, kBlock), gy), dim3(kBlock), 0, s, g, rows, alpha, src, dst);
 }
 
+// Squared norm in L^2((0, T); H^q(D)) of the space-time interpolant of one row of a field
+// ((m + 1) x n nodal values on a Q1 box), integrated exactly: over element e and interval k,
+// dt/3 (a'A_e a + a'A_e b + b'A_e b) with a, b the element's corner values at t_k, t_(k+1) and
+// A_e the element mass (plus the Laplacian stiffness for q = 1), both Kronecker products of the
+// 1D matrices h/6 [2 1; 1 2] and 1/h [1 -1; -1 1].  Threads stride over (element, interval);
+// per-block partials part[r * gridDim.x + block] are summed in order by k_norm_final.
+__global__ __launch_bounds__(kBlock) void k_st_norm(NormGeo g, const double* __restrict__ f,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[kBlock / 64];
+  const int64_t r = blockIdx.y;
+  const int64_t ex = g.n[0] - 1, ey = g.dim > 1 ? g.n[1] - 1 : 1, ez = g.dim > 2 ? g.n[2] - 1 : 1;
+  const int64_t ne = ex * ey * ez;
+  const int64_t nn = g.n[0] * (g.dim > 1 ? g.n[1] : 1) * (g.dim > 2 ? g.n[2] : 1);
+  const int64_t total = ne * g.m;
+  const int nc = 1 << g.dim;
+  const double* fr = f + r * (g.m + 1) * nn;
+  double acc = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = t / ne;
+    int64_t e = t - k * ne;
+    const int64_t ix = e % ex;
+    e /= ex;
+    const int64_t iy = e % ey;
+    const int64_t iz = e / ey;
+    const int64_t base = ix + g.n[0] * (iy + (g.dim > 1 ? g.n[1] : 1) * iz);
+    double a[8], b[8];
+    for (int c = 0; c < 8; ++c) {
+      if (c >= nc) {
+        a[c] = b[c] = 0.0;
+        continue;
+      }
+      const int64_t off = (c & 1) + ((c >> 1) & 1) * g.n[0] + ((c >> 2) & 1) * g.n[0] * g.n[1];
+      a[c] = fr[k * nn + base + off];
+      b[c] = fr[(k + 1) * nn + base + off];
+    }
+    double qf = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      for (int cp = 0; cp < nc; ++cp) {
+        double mass = 1.0, stiff = 0.0;
+        for (int ax = 0; ax < g.dim; ++ax) {
+          const bool same = ((c >> ax) & 1) == ((cp >> ax) & 1);
+          const double m1 = g.h[ax] * (same ? 2.0 : 1.0) / 6.0;
+          const double s1 = (same ? 1.0 : -1.0) / g.h[ax];
+          stiff = stiff * m1 + mass * s1;
+          mass *= m1;
+        }
+        const double A = g.q ? mass + stiff : mass;
+        qf += A * (a[c] * a[cp] + a[c] * b[cp] + b[c] * b[cp]);
+      }
+    }
+    acc += g.dt / 3.0 * qf;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < kBlock / 64; ++i) s += sh[i];
+    part[r * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+__global__ void k_norm_final(const double* __restrict__ part, int nb, int64_t rows, double* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  double s = 0.0;
+  for (int i = 0; i < nb; ++i) s += part[r * nb + i];
+  out[r] = s;
+}
+
+void launch_st_norm(const NormGeo& g, int64_t rows, const double* f, double* part, double* out, hipStream_t s) {
+  int64_t ne = 1;
+  for (int a = 0; a < g.dim; ++a) ne *= g.n[a] - 1;
+  int64_t nb = cdiv(ne * g.m, kBlock);
+  nb = nb < 1 ? 1 : (nb > kNormBlocks ? kNormBlocks : nb);
+  hipLaunchKernelGGL(k_st_norm, dim3((unsigned)nb, (unsigned)rows), dim3(kBlock), 0, s, g, f, part);
+  hipLaunchKernelGGL(k_norm_final, dim3((unsigned)cdiv(rows, kBlock)), dim3(kBlock), 0, s, part, (int)nb, rows, out);
+}
+
+// Squared H^q(0, T) norm of the linear interpolant of each row of (m + 1) values: one thread
+// per row, sum_k dt/3 (a^2 + a b + b^2) (+ (b - a)^2 / dt for q = 1) in order k.
+__global__ void k_time_norm(const double* __restrict__ f, int64_t rows, int64_t m, double dt, int q,
+                            double* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const double* fr = f + r * (m + 1);
+  double s = 0.0;
+  for (int64_t k = 0; k < m; ++k) {
+    const double a = fr[k], b = fr[k + 1];
+    s += dt / 3.0 * (a * a + a * b + b * b);
+    if (q) s += (b - a) * (b - a) / dt;
+  }
+  out[r] = s;
+}
+
+void launch_time_norm(const double* f, int64_t rows, int64_t m, double dt, int q, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_time_norm, dim3((unsigned)cdiv(rows, kBlock)), dim3(kBlock), 0, s, f, rows, m, dt, q, out);
+}
+
 }  // namespace mlq

@@ -171,6 +171,17 @@ void launch_probe(const double* u, int32_t B, int64_t n, const ProbeTab& tab, in
 void launch_probe_sum(const double* u, int32_t B, int64_t n, const ProbeTab& tab, int32_t k, int32_t ld, double* sum,
                       hipStream_t s);
 void launch_transfer(const XferGeo& g, int64_t rows, double alpha, const double* src, double* dst, hipStream_t s);
+constexpr int kNormBlocks = 1024;  // partial sums per row of a space-time norm
+struct NormGeo {
+  int64_t n[3];  // nodes per axis (1 on unused axes)
+  double h[3];   // spacing per axis
+  int dim;
+  int64_t m;     // time steps
+  double dt;
+  int q;         // 0: L^2 in space, 1: H^1
+};
+void launch_st_norm(const NormGeo& g, int64_t rows, const double* f, double* part, double* out, hipStream_t s);
+void launch_time_norm(const double* f, int64_t rows, int64_t m, double dt, int q, double* out, hipStream_t s);
 
 constexpr int kHaltonMaxDims = 1024;
 void launch_halton(int32_t sdim, int64_t first, int32_t count, const double* shift, bool uniform, double* Y,

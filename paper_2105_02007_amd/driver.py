@@ -242,6 +242,22 @@ class ConfigRunner:
             mlq.transfer_add(lv, fin, f["act_sum"], est_a, alpha=alpha, time=False)
             if npr:
                 mlq.transfer_add(lv, fin, f["probe_sum"], est_p, alpha=alpha, space=False, rows=npr)
+        # norms of the level terms on their own grids: mean_0 and, for l > 0, the mean level
+        # difference mean_l - T mean_(l-1) (the quantities whose decay the level hierarchy
+        # relies on), in L^2((0,T); L^2) and L^2((0,T); H^1)
+        corr = []
+        k = 0
+        for l, Y in enumerate(Ys):
+            lv = self.levels[l]
+            D = zeros(lv.desc.n_steps + 1, lv.n_nodes)
+            mlq.transfer_add(lv, lv, jobs[k][2]["u_sum"], D, alpha=1.0 / Y.shape[1])
+            k += 1
+            if l > 0:
+                mlq.transfer_add(self.levels[l - 1], lv, jobs[k][2]["u_sum"], D, alpha=-1.0 / Y.shape[1])
+                k += 1
+            corr.append([float(x) ** 0.5 for x in (mlq.field_norm2(lv, D, q=0).item(),
+                                                      mlq.field_norm2(lv, D, q=1).item())])
+            del D
         ff, fc, k = [], [], 0
         for l in range(len(Ys)):
             ff.append(res[k])
@@ -252,7 +268,7 @@ class ConfigRunner:
             else:
                 fc.append(None)
         out = self._estimate(mlq.MLQ_EST_MLMC, ff, fc, [Y.shape[1] for Y in Ys], 1)
-        out.update(mean_u=est_u, mean_act_map=est_a, mean_probe=est_p)
+        out.update(mean_u=est_u, mean_act_map=est_a, mean_probe=est_p, level_term_norms=corr)
         return out
 
     def run_mc(self, Y, level=0):

@@ -27,7 +27,7 @@ EXPORTED = [
     "mlq_lattice_normals", "mlq_halton", "mlq_cbc", "mlq_accumulate", "mlq_estimate", "mlq_last_error",
     "mlq_kl_workspace_bytes", "mlq_kl_modes", "mlq_kl_transfer", "mlq_timing_enable", "mlq_timing_read",
     "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet", "mlq_solve_batch_fields", "mlq_probe_weights",
-    "mlq_transfer_add",
+    "mlq_transfer_add", "mlq_field_norm2",
 ]
 MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE = 0, 1
 MLQ_DIFF_FIBRE, MLQ_DIFF_ISO, MLQ_DIFF_VECTOR = 0, 1, 2
@@ -107,6 +107,7 @@ def _load():
         "mlq_solve_batch_fields": [VP, VP, I32, VP, C.c_size_t, VP, VP, VP, VP, VP],
         "mlq_probe_weights": [VP, VP, I32, VP, VP],
         "mlq_transfer_add": [VP, VP, I32, I32, I64, C.c_double, VP, VP, VP],
+        "mlq_field_norm2": [VP, I32, I32, I64, VP, VP, VP, VP],
         "mlq_cbc": [I64, I32, VP, VP],
         "mlq_accumulate": [VP, VP, I32, VP, VP],
         "mlq_estimate": [I32, I32, I32, VP, VP, VP, C.POINTER(EstimateOut)],
@@ -367,6 +368,17 @@ def transfer_add(src_level, dst_level, src, dst, alpha=1.0, space=True, time=Tru
     check(lib.mlq_transfer_add(src_level.handle, dst_level.handle, 1 if space else 0, 1 if time else 0, int(rows),
                                float(alpha), _ptr(src), _ptr(dst), _stream()))
     return dst
+
+
+def field_norm2(level, f, q=0, space=True, rows=1):
+    """Squared L^2((0,T); H^q) norms of rows of space-time fields (space=True), or squared
+    H^q(0,T) norms of rows of time series (space=False): (rows,) FP64 device tensor."""
+    import torch
+    out = torch.empty(rows, dtype=torch.float64, device=f.device)
+    part = torch.empty((rows, 1024), dtype=torch.float64, device=f.device) if space else None
+    check(lib.mlq_field_norm2(level.handle, 1 if space else 0, int(q), int(rows), _ptr(f),
+                              None if part is None else _ptr(part), _ptr(out), _stream()))
+    return out
 
 
 def lattice_normals(z, shift, N, first, count, device="cuda"):

@@ -164,8 +164,36 @@ def test_mlmc_field_estimate_matches_oracle(env):
     assert gu.shape == est_u.shape and np.abs(gu - est_u).max() <= 1e-10 * np.abs(est_u).max()
     assert np.abs(ga - est_a).max() <= 1e-8 * T
     assert np.abs(gp - est_p).max() <= 1e-10 * np.abs(est_p).max()
+    # the norms of the level terms on their own grids
+    d1 = S_f[1][0] / npl[1] - fields.prolongate_space_time(meshes[0], steps[0], S_c[1][0], meshes[1], steps[1], T) / npl[1]
+    for l, D in enumerate([S_f[0][0] / npl[0], d1]):
+        for q in (0, 1):
+            ref = fields.space_time_norm2(meshes[l], D, T, q) ** 0.5
+            assert abs(res["level_term_norms"][l][q] - ref) <= 1e-9 * ref, (l, q)
     # the domain mean of the activation map estimate is the scalar estimate of the mean
     # activation time (the lumped weights integrate the transferred Q1 fields exactly)
     from oracle import fem
     wts = np.asarray(fem.assemble_mass(meshes[1]).sum(axis=1)).ravel()
     assert abs(wts @ ga / wts.sum() - res["estimate"]) <= 1e-12 * abs(res["estimate"])
+
+
+@pytest.mark.parametrize("n,hi,m", [([9, 7, 5], [0.6, 0.5, 0.4], 12), ([12, 9], [1.0, 0.7], 5)])
+def test_field_norms_match_oracle(env, n, hi, m):
+    """Squared L^2((0,T); H^q) norms of space-time fields (two rows) and H^q(0,T) norms of
+    time series (five rows) against the oracle's assembled forms, within 1e-12 relative."""
+    torch, mlq = env
+    from oracle import fields
+    from oracle.mesh import BoxMesh
+    L, _ = _level(mlq, n, m, hi)
+    mesh = BoxMesh(n, hi=hi)
+    T = W.physics(len(n))["t_end"]
+    rng = np.random.default_rng(8)
+    F = rng.normal(size=(2, m + 1, mesh.n_nodes))
+    S = rng.normal(size=(5, m + 1))
+    Fd, Sd = torch.as_tensor(F, device="cuda"), torch.as_tensor(S, device="cuda")
+    for q in (0, 1):
+        got = mlq.field_norm2(L, Fd, q=q, rows=2).cpu().numpy()
+        ref = np.array([fields.space_time_norm2(mesh, F[r], T, q) for r in range(2)])
+        assert np.allclose(got, ref, rtol=1e-12, atol=0), (q, got, ref)
+        got = mlq.field_norm2(L, Sd, q=q, space=False, rows=5).cpu().numpy()
+        assert np.allclose(got, fields.time_norm2(S, T, q), rtol=1e-13, atol=0)
