@@ -240,6 +240,10 @@ def main():
     ap.add_argument("--breakdown", action="store_true", help="extra untimed pass timing every kernel class")
     ap.add_argument("--no-qoi-check", action="store_true",
                     help="skip the FP64 re-solve of a few finest-level samples after a mixed-precision run")
+    ap.add_argument("--newton-guess", choices=["previous", "extrapolate", "reference", "reference-local"],
+                    default="extrapolate",
+                    help="Newton initial guess of each step: u_k, 2 u_k - u_(k-1), or from the unperturbed "
+                         "reference solution (global r_(k+1), or local u_k + r_(k+1) - r_k)")
     ap.add_argument("--fields", action="store_true",
                     help="MLMC workloads: also estimate the field quantities of interest (mean space-time "
                          "potential on the finest grid, mean activation map, mean action potential at 4 points)")
@@ -266,7 +270,9 @@ def main():
     prec = cfg["prec"] if args.prec is None else (W.PREC_FP64 if args.prec == "fp64" else W.PREC_MIXED)
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
     t_setup = time.perf_counter()
-    runner = ConfigRunner(cfg, prec=prec, device=dev, log=log)
+    guess = {"previous": mlq.MLQ_GUESS_PREVIOUS, "extrapolate": mlq.MLQ_GUESS_EXTRAPOLATE,
+             "reference": mlq.MLQ_GUESS_REFERENCE, "reference-local": mlq.MLQ_GUESS_REFERENCE_LOCAL}[args.newton_guess]
+    runner = ConfigRunner(cfg, prec=prec, device=dev, log=log, newton_guess=guess)
     t_setup = time.perf_counter() - t_setup
     log(f"set-up done in {t_setup:.1f} s (KL rank {runner.kl_rank})")
     runner.log = log
@@ -420,8 +426,11 @@ def main():
     # run concurrently, so their rates are while sharing the GPU)
     line["levels"] = [dict(level=l, dof_iters_per_s=(runner.level_dof_iters[l] / runner.level_seconds[l]
                                                      if runner.level_seconds[l] > 0 else None),
-                           seconds=round(runner.level_seconds[l] / max(args.steps, 1), 4))
+                           seconds=round(runner.level_seconds[l] / max(args.steps, 1), 4),
+                           newton_per_step=round(runner.level_newton[l] / runner.level_sample_steps[l], 3),
+                           gmres_per_step=round(runner.level_inner[l] / runner.level_sample_steps[l], 2))
                       for l in range(len(runner.levels))]
+    line["newton_guess"] = args.newton_guess
     if breakdown:
         line["breakdown"] = breakdown
     line["kl_synthesis"] = kl_synthesis(runner, cfg, dev)

@@ -59,7 +59,12 @@ typedef enum {
 typedef enum { MLQ_FP64 = 0, MLQ_MIXED = 1 } mlq_precision;
 typedef enum { MLQ_QOI_MEAN_U_FINAL = 0, MLQ_QOI_MEAN_ACT_TIME = 1 } mlq_qoi;
 typedef enum { MLQ_MESH_Q1_BOX = 0, MLQ_MESH_P1_TET = 1 } mlq_mesh_kind;
-typedef enum { MLQ_GUESS_PREVIOUS = 0, MLQ_GUESS_EXTRAPOLATE = 1 } mlq_newton_guess;
+typedef enum {
+  MLQ_GUESS_PREVIOUS = 0,
+  MLQ_GUESS_EXTRAPOLATE = 1,
+  MLQ_GUESS_REFERENCE = 2,       /* r_(k+1): the unperturbed reference solution (mlq_set_reference) */
+  MLQ_GUESS_REFERENCE_LOCAL = 3  /* u_k + r_(k+1) - r_k: the reference's increment on the sample's state */
+} mlq_newton_guess;
 typedef enum { MLQ_DIFF_FIBRE = 0, MLQ_DIFF_ISO = 1, MLQ_DIFF_VECTOR = 2 } mlq_diffusion;
 typedef enum { MLQ_COV_EXP = 0, MLQ_COV_SQEXP = 1 } mlq_cov_kernel;
 
@@ -109,7 +114,10 @@ typedef struct {
   /* Newton initial guess of step k + 1 (the discrete solution does not depend on it
    * beyond the stopping test): 0 = u_k, the previous time level (the multiple-time-block
    * strategy of Section 3.3 with one step per block); 1 = 2 u_k - u_{k-1}, linear
-   * extrapolation from the two previous time levels (u_k at the first step). */
+   * extrapolation from the two previous time levels (u_k at the first step); 2 and 3 start from
+   * an unperturbed reference solution r (Section 3.3, the sample-based Newton initial guess,
+   * read for time stepping): 2 = r_(k+1) (the global guess), 3 = u_k + (r_(k+1) - r_k) (the
+   * local one); r is set with mlq_set_reference. */
   int32_t newton_guess;               /* mlq_newton_guess */
   /* Conductivity model of the elements (boxes): MLQ_DIFF_FIBRE: the field is the fibre
    * angle theta, G = sigma_t I + (sigma_l - sigma_t) f f^T with f = (cos theta, sin theta[, 0]),
@@ -200,6 +208,13 @@ typedef struct {
   const double* probe_w;
   double* probe_sum;
 } mlq_field_out;
+
+/* Reference space-time solution for the Newton guesses MLQ_GUESS_REFERENCE(_LOCAL): ref_dev
+ * is (n_steps + 1) x n FP64 on the device, e.g. the u_sum of a one-sample solve of the
+ * unperturbed field; the level keeps the pointer (the caller keeps the memory alive while it
+ * solves; NULL clears it).  Without a reference these guesses start from u_k, as
+ * MLQ_GUESS_PREVIOUS (which is how the reference itself is computed). */
+mlq_status mlq_set_reference(mlq_level* level, const double* ref_dev);
 
 /* mlq_solve_batch with field outputs (see mlq_field_out); same arguments, results and
  * errors otherwise. */

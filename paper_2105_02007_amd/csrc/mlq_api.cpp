@@ -58,6 +58,7 @@ double hat_integral(int64_t i, int64_t n, double lo, double h, double a, double 
 
 struct mlq_level {
   mlq_level_desc d;
+  const double* ref = nullptr;  // reference space-time solution for the Newton guess (caller's memory)
   Geo geo;
   Ionic io;
   int64_t nn = 0, P = 0;
@@ -214,8 +215,8 @@ mlq_status validate(const mlq_level_desc* d) {
   if (d->max_newton < 1 || d->max_newton > 1000) return fail(MLQ_EINVAL, "max_newton out of range");
   if (d->max_inner < 1 || d->max_inner > kMaxInner) return fail(MLQ_EINVAL, "max_inner must be in [1, %d]", kMaxInner);
   if (d->max_batch < 1 || d->max_batch > 65535) return fail(MLQ_EINVAL, "max_batch must be in [1, 65535]");
-  if (d->newton_guess != MLQ_GUESS_PREVIOUS && d->newton_guess != MLQ_GUESS_EXTRAPOLATE)
-    return fail(MLQ_EINVAL, "newton_guess must be MLQ_GUESS_PREVIOUS or MLQ_GUESS_EXTRAPOLATE");
+  if (d->newton_guess < MLQ_GUESS_PREVIOUS || d->newton_guess > MLQ_GUESS_REFERENCE_LOCAL)
+    return fail(MLQ_EINVAL, "unknown newton_guess");
   if (d->diffusion != MLQ_DIFF_FIBRE && d->diffusion != MLQ_DIFF_ISO && d->diffusion != MLQ_DIFF_VECTOR)
     return fail(MLQ_EINVAL, "diffusion must be MLQ_DIFF_FIBRE, MLQ_DIFF_ISO or MLQ_DIFF_VECTOR");
   if (d->diffusion == MLQ_DIFF_ISO && d->mesh_kind != MLQ_MESH_Q1_BOX)
@@ -731,6 +732,10 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
     });
     // the rhs kernels start Newton from u = u_k; the extrapolated guess replaces it
     if (d.newton_guess == MLQ_GUESS_EXTRAPOLATE && k > 0) launch_extrapolate(w, level->nn, batch, s);
+    if ((d.newton_guess == MLQ_GUESS_REFERENCE || d.newton_guess == MLQ_GUESS_REFERENCE_LOCAL) &&
+        level->ref != nullptr)
+      launch_guess_reference(w, level->ref + (size_t)k * level->nn, level->ref + (size_t)(k + 1) * level->nn,
+                             level->nn, batch, d.newton_guess == MLQ_GUESS_REFERENCE_LOCAL, s);
     launch_newton_reset(w, batch, s);
     int32_t active = batch;
     for (int it = 0;; ++it) {
@@ -846,6 +851,12 @@ mlq_status mlq_solve_batch(mlq_level* level, const void* theta_dev, int32_t batc
   if (level == nullptr) return fail(MLQ_EINVAL, "level is NULL");
   return solve_impl(level, theta_dev, batch, level->d.n_steps, ws_dev, ws_bytes, qoi_dev, status_dev, iters_dev,
                     nullptr, nullptr, nullptr, hip_stream);
+}
+
+mlq_status mlq_set_reference(mlq_level* level, const double* ref_dev) {
+  if (level == nullptr) return fail(MLQ_EINVAL, "level is NULL");
+  level->ref = ref_dev;
+  return MLQ_OK;
 }
 
 mlq_status mlq_solve_batch_fields(mlq_level* level, const void* theta_dev, int32_t batch, void* ws_dev,

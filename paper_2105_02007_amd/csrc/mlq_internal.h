@@ -130,6 +130,8 @@ void launch_coefs(const void* theta, void* coef, int64_t P, int32_t B, double ha
 void launch_init(const Work& w, int64_t nn, int32_t B, double u_th, hipStream_t s);
 // Newton initial guess u = 2 u_k - u_{k-1}
 void launch_extrapolate(const Work& w, int64_t nn, int32_t B, hipStream_t s);
+void launch_guess_reference(const Work& w, const double* ref_k, const double* ref_k1, int64_t nn, int32_t B,
+                            bool local, hipStream_t s);
 void launch_rhs(const Geo& g, const Work& w, const double* fbox, double load_coef, double dt, int32_t B,
                 bool mixed, hipStream_t s);
 void launch_residual(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);

@@ -247,6 +247,25 @@ void launch_extrapolate(const Work& w, int64_t nn, int32_t B, hipStream_t s) {
                      total);
 }
 
+// Newton start from an unperturbed reference solution r_k (one space-time field shared by the
+// batch): u = r_(k+1) (global guess), or u = u_k + (r_(k+1) - r_k) (its increment added to the
+// sample's own state, local guess).
+__global__ void k_guess_reference(double* __restrict__ u, const double* __restrict__ uk,
+                                  const double* __restrict__ r0, const double* __restrict__ r1, int64_t nn,
+                                  int64_t total, int local) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int64_t j = i % nn;
+  u[i] = local ? uk[i] + (r1[j] - r0[j]) : r1[j];
+}
+
+void launch_guess_reference(const Work& w, const double* ref_k, const double* ref_k1, int64_t nn, int32_t B,
+                            bool local, hipStream_t s) {
+  const int64_t total = nn * B;
+  hipLaunchKernelGGL(k_guess_reference, dim3((unsigned)cdiv(total, kBlock)), dim3(kBlock), 0, s, w.u, w.uk, ref_k,
+                     ref_k1, nn, total, local ? 1 : 0);
+}
+
 // ---------------------------------------------------------------------------
 // Right-hand side of step k (eq. (st-system)):  b = (M - dt/2 K) u_k + c_k F_box,
 // c_k = dt/2 (s(t_{k+1}) + s(t_k)).  Also starts Newton from u = u_k.

@@ -107,6 +107,19 @@ class ConfigRunner:
                            else mlq.MLQ_DIFF_FIBRE), v_mean=v_mean)
             L = mlq.Level(desc, keep, device=device)
             L._keep = None  # arrays were copied into the level blob
+            if newton_guess in (mlq.MLQ_GUESS_REFERENCE, mlq.MLQ_GUESS_REFERENCE_LOCAL):
+                # the unperturbed reference solution (all coordinates zero: theta = its mean)
+                Y0 = torch.zeros((M * self.components, 1), dtype=torch.float64, device=device)
+                if self.vector:
+                    th0 = torch.stack([L.sample_fields(Y0[c * M:(c + 1) * M].contiguous())
+                                       for c in range(self.components)])
+                else:
+                    th0 = L.sample_fields(Y0)
+                ref = torch.zeros((L.desc.n_steps + 1, L.n_nodes), dtype=torch.float64, device=device)
+                r = L.solve_fields(th0, u_sum=ref)
+                if r["code"] != mlq.MLQ_OK:
+                    raise mlq.MlqError(r["code"], f"reference solve failed on level {l}")
+                L.set_reference(ref)
             self.levels.append(L)
             say(f"level {l} created ({L.n_nodes} nodes, {L.n_elems} elements)")
             del phi
@@ -120,14 +133,17 @@ class ConfigRunner:
         self.concurrent = concurrent
         self.streams = [torch.cuda.Stream(device=device) for _ in self.levels]
         self._lock = threading.Lock()
-        self.level_dof_iters = [0.0] * len(self.levels)
-        self.level_seconds = [0.0] * len(self.levels)
+        self.reset_counters()
 
     def reset_counters(self):
         self.dof_iters = 0.0
         self.st_dof = 0.0
-        self.level_dof_iters = [0.0] * len(self.levels)
-        self.level_seconds = [0.0] * len(self.levels)
+        n = len(self.levels)
+        self.level_dof_iters = [0.0] * n
+        self.level_seconds = [0.0] * n
+        self.level_newton = [0.0] * n       # Newton iterations (summed over samples and steps)
+        self.level_inner = [0.0] * n        # GMRES iterations
+        self.level_sample_steps = [0.0] * n
 
     def solve(self, l: int, Y: torch.Tensor, fields=None):
         """QoIs (device FP64) of the samples Y (M x B, device FP64) on level l; with `fields`
@@ -146,13 +162,17 @@ class ConfigRunner:
             raise mlq.MlqError(out["code"], f"{int((st != 0).sum())} samples failed on level {l}")
         it = out["iters"]
         B = Y.shape[1]
-        inner = float(it[:, 1].sum().item())  # waits for the solve on this stream
+        sums = it.sum(dim=0).cpu()  # waits for the solve on this stream
+        newton, inner = float(sums[0]), float(sums[1])
         el = time.perf_counter() - t0
         with self._lock:
             self.dof_iters += float(L.n_nodes) * inner
             self.st_dof += float(L.n_nodes) * float(L.desc.n_steps) * B
             self.level_dof_iters[l] += float(L.n_nodes) * inner
             self.level_seconds[l] += el
+            self.level_newton[l] += newton
+            self.level_inner[l] += inner
+            self.level_sample_steps[l] += float(B) * float(L.desc.n_steps)
         if self.log is not None:
             self.log(f"level {l}: {B} samples x {L.n_nodes} nodes x {L.desc.n_steps} steps solved")
         return out["qoi"]

@@ -27,9 +27,9 @@ EXPORTED = [
     "mlq_lattice_normals", "mlq_halton", "mlq_cbc", "mlq_accumulate", "mlq_estimate", "mlq_last_error",
     "mlq_kl_workspace_bytes", "mlq_kl_modes", "mlq_kl_transfer", "mlq_timing_enable", "mlq_timing_read",
     "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet", "mlq_solve_batch_fields", "mlq_probe_weights",
-    "mlq_transfer_add", "mlq_field_norm2",
+    "mlq_transfer_add", "mlq_field_norm2", "mlq_set_reference",
 ]
-MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE = 0, 1
+MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE, MLQ_GUESS_REFERENCE, MLQ_GUESS_REFERENCE_LOCAL = 0, 1, 2, 3
 MLQ_DIFF_FIBRE, MLQ_DIFF_ISO, MLQ_DIFF_VECTOR = 0, 1, 2
 MLQ_COV_EXP, MLQ_COV_SQEXP = 0, 1
 MLQ_MAP_NORMAL, MLQ_MAP_UNIFORM = 0, 1
@@ -108,6 +108,7 @@ def _load():
         "mlq_probe_weights": [VP, VP, I32, VP, VP],
         "mlq_transfer_add": [VP, VP, I32, I32, I64, C.c_double, VP, VP, VP],
         "mlq_field_norm2": [VP, I32, I32, I64, VP, VP, VP, VP],
+        "mlq_set_reference": [VP, VP],
         "mlq_cbc": [I64, I32, VP, VP],
         "mlq_accumulate": [VP, VP, I32, VP, VP],
         "mlq_estimate": [I32, I32, I32, VP, VP, VP, C.POINTER(EstimateOut)],
@@ -329,6 +330,12 @@ class Level:
         if code not in (MLQ_OK, MLQ_ENOCONV):
             check(code)
         return dict(qoi=qoi, status=status, iters=iters, probe=probe, code=code)
+
+    def set_reference(self, ref):
+        """Reference space-time solution ((n_steps + 1) x n device FP64) for the reference
+        Newton guesses; the level keeps a reference to the tensor."""
+        self._ref = ref
+        check(lib.mlq_set_reference(self.handle, None if ref is None else _ptr(ref)))
 
     def probe_weights(self, points):
         """(node, weight) host arrays (P x 8) of the Q1 interpolant at points (P x 3) of a box level."""
