@@ -59,6 +59,16 @@ def counter_traffic(config, prec):
 # centre, a face, the far corner
 FIELD_PROBES = [[0.05, 0.05, 0.05], [0.5, 0.5, 0.5], [1.0, 0.5, 0.25], [1.0, 1.0, 1.0]]
 
+def field_probes(cfg, runner):
+    """Probe points of --fields: FIELD_PROBES in the unit box, or on a shell four vertices of the
+    finest mesh spread over its vertex order (from the inner apex region outwards)."""
+    import numpy as np
+    if runner.tet:
+        xyz = runner.meshes[-1]["xyz"]
+        return xyz[[0, len(xyz) // 3, (2 * len(xyz)) // 3, len(xyz) - 1]]
+    return np.array(FIELD_PROBES)[:, :cfg["dim"]]
+
+
 WORKLOAD_TEXT = {
     "c1": "2D unit square Q1 33x33, 64 steps, 16-mode KL (l=0.2, s=0.3 rad), 16 MC samples, mean u(T), FP64",
     "c2": "3D unit cube Q1 9^3..65^3 nested, 32..256 steps, 64-mode KL (l=0.1, s=0.3 rad) on 65^3, "
@@ -284,14 +294,18 @@ def main():
     n_dims = M * int(cfg["kl"].get("components", 1))
     if kind == "combination":
         Yc = torch.as_tensor(draw(cfg["seed"], 0, max(samp["n_per_level"]), n_dims), device=dev)
-        step = lambda: runner.run_combination(Yc)
+        if args.fields:
+            probes = field_probes(cfg, runner)
+            step = lambda: runner.run_combination_fields(Yc, probes=probes)
+        else:
+            step = lambda: runner.run_combination(Yc)
     elif kind in ("mc", "mlmc"):
         Ys = [torch.as_tensor(draw(cfg["seed"], l, n, n_dims), device=dev)
               for l, n in enumerate(samp["n_per_level"])]
         if kind == "mc":
             step = lambda: runner.run_mc(Ys[0])
         elif args.fields:
-            probes = np.array(FIELD_PROBES)[:, :cfg["dim"]]
+            probes = field_probes(cfg, runner)
             step = lambda: runner.run_mlmc_fields(Ys, probes=probes)
         else:
             step = lambda: runner.run_mlmc(Ys)
@@ -396,7 +410,15 @@ def main():
         "roofline": roofline,
         "apply_per_level": per_level,
     }
-    if args.fields:
+    if args.fields and runner.tet:
+        eu, ep = res["mean_u"], res["mean_probe"]
+        line["fields"] = {
+            "u_grid": list(eu.shape), "u_bytes": eu.numel() * 8,
+            "probes": [list(map(float, p)) for p in field_probes(cfg, runner)],
+            "mean_action_potential": {f"{f:g}T": [float(x) for x in ep[:, int(round(f * (ep.shape[1] - 1)))].cpu()]
+                                      for f in (0.25, 0.5, 1.0)},
+        }
+    elif args.fields:
         # the domain mean of the estimated activation map equals the scalar estimate (the
         # transfer is the Q1 interpolant, which the lumped node weights integrate exactly)
         fl = cfg["levels"][-1]

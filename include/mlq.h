@@ -244,6 +244,28 @@ mlq_status mlq_probe_weights(const mlq_level* level, const double* xyz_host, int
 mlq_status mlq_transfer_add(const mlq_level* from, const mlq_level* to, int32_t space, int32_t time, int64_t rows,
                             double alpha, const double* src_dev, double* dst_dev, void* hip_stream);
 
+/* P1 interpolation weights of points in a tetrahedral mesh (host only): for point p the four
+ * vertices node_out[4 p ..] of the tetrahedron found for it and the weights w_out[4 p ..], its
+ * barycentric coordinates.  The tetrahedron is the one with the largest smallest barycentric
+ * coordinate (lowest index on ties within 1e-12), searched in a uniform bucket grid; a point
+ * outside the mesh (the boundary of a finer non-nested mesh) takes the best tetrahedron of the
+ * neighbouring cells, its negative coordinates clipped to 0 and the rest renormalised (§4, the
+ * transfer between non-nested meshes).  xyz: n_vert x 3, tets: n_tet x 4, pts: n_pts x 3, host.
+ * MLQ_EINVAL for a vertex index out of range or a failed search. */
+mlq_status mlq_tet_locate(const double* xyz, int64_t n_vert, const int32_t* tets, int64_t n_tet, const double* pts,
+                          int64_t n_pts, int64_t* node_out, double* w_out);
+
+/* Transfer between the grids of two levels with explicit interpolation weights in space (for
+ * non-nested meshes, e.g. from mlq_tet_locate at the target level's vertices), accumulated:
+ *   dst[r][k'][i'] += alpha * sum_k T[k'][k] sum_{j < K} w_dev[i' K + j] src[r][k][node_dev[i' K + j]],
+ * with T the linear time interpolation from `from`'s time nodes to `to`'s (time = 1, nested time
+ * grids with the same end time) or the identity on one time node (time = 0).  node_dev, w_dev:
+ * device arrays of n_to x K (1 <= K <= 8); node indices are clamped to [0, n_from).  src: rows x
+ * T_f x n_from, dst: rows x T_t x n_to (T = n_steps + 1 or 1), device.  Enqueues only. */
+mlq_status mlq_transfer_add_weighted(const mlq_level* from, const mlq_level* to, int32_t time, int64_t rows,
+                                     int32_t K, const int64_t* node_dev, const double* w_dev, double alpha,
+                                     const double* src_dev, double* dst_dev, void* hip_stream);
+
 /* Squared error norms of fields on a level's grids (eq. (space-time-error), eq. (point-error)):
  *   space = 1: f_dev is rows x (n_steps + 1) x n (space-time fields of a box level);
  *     out_dev[r] = ||f_r||^2 in L^2((0, T); H^q(D)) of the interpolant that is Q1 in space and

@@ -908,6 +908,61 @@ mlq_status mlq_probe_weights(const mlq_level* level, const double* xyz, int32_t 
   return MLQ_OK;
 }
 
+mlq_status mlq_tet_locate(const double* xyz, int64_t n_vert, const int32_t* tets, int64_t n_tet, const double* pts,
+                          int64_t n_pts, int64_t* node_out, double* w_out) {
+  if (xyz == nullptr || tets == nullptr || (n_pts > 0 && (pts == nullptr || node_out == nullptr || w_out == nullptr)))
+    return fail(MLQ_EINVAL, "NULL argument");
+  if (n_vert < 4 || n_tet < 1 || n_pts < 0) return fail(MLQ_EINVAL, "invalid mesh or point count");
+  for (int64_t i = 0; i < 4 * n_tet; ++i)
+    if (tets[i] < 0 || tets[i] >= n_vert) return fail(MLQ_EINVAL, "tetrahedron vertex out of range");
+  if (n_pts == 0) return MLQ_OK;
+  mlq_kl_desc kd{};
+  kd.dim = 3;
+  kd.mesh_kind = MLQ_MESH_P1_TET;
+  kd.n_vert = n_vert;
+  kd.n_tet = n_tet;
+  kd.xyz = xyz;
+  kd.tets = tets;
+  std::vector<int32_t> vid;
+  std::vector<double> wts;
+  std::string err;
+  const mlq_status st = locate_points_tet(&kd, pts, n_pts, vid, wts, err);
+  if (st != MLQ_OK) return fail(st, "%s", err.c_str());
+  for (int64_t i = 0; i < 4 * n_pts; ++i) {
+    node_out[i] = vid[i];
+    w_out[i] = wts[i];
+  }
+  return MLQ_OK;
+}
+
+mlq_status mlq_transfer_add_weighted(const mlq_level* from, const mlq_level* to, int32_t time, int64_t rows,
+                                     int32_t K, const int64_t* node_dev, const double* w_dev, double alpha,
+                                     const double* src_dev, double* dst_dev, void* hip_stream) {
+  if (from == nullptr || to == nullptr || node_dev == nullptr || w_dev == nullptr || src_dev == nullptr ||
+      dst_dev == nullptr)
+    return fail(MLQ_EINVAL, "NULL argument");
+  if (rows < 1) return fail(MLQ_EINVAL, "rows must be >= 1");
+  if (K < 1 || K > kProbeNodes) return fail(MLQ_EINVAL, "nodes per point outside [1, %d]", kProbeNodes);
+  XferGeo g;
+  for (int a = 0; a < 3; ++a) g.sn_f[a] = g.sn_t[a] = 1;
+  g.tn_f = g.tn_t = 1;
+  g.m_f = g.m_t = 1;
+  if (time) {
+    const mlq_level_desc& df = from->d;
+    const mlq_level_desc& dt = to->d;
+    if (std::fabs(df.t_end - dt.t_end) > 1e-12 * df.t_end) return fail(MLQ_EINVAL, "levels end at different times");
+    if (dt.n_steps % df.n_steps != 0) return fail(MLQ_EINVAL, "time grids are not nested");
+    g.tn_f = df.n_steps + 1;
+    g.tn_t = dt.n_steps + 1;
+    g.m_f = df.n_steps;
+    g.m_t = dt.n_steps;
+  }
+  launch_transfer_weighted(g, rows, from->nn, to->nn, K, node_dev, w_dev, alpha, src_dev, dst_dev,
+                           (hipStream_t)hip_stream);
+  HIP_OK(hipGetLastError());
+  return MLQ_OK;
+}
+
 mlq_status mlq_field_norm2(const mlq_level* level, int32_t space, int32_t q, int64_t rows, const double* f_dev,
                            double* part_dev, double* out_dev, void* hip_stream) {
   if (level == nullptr || f_dev == nullptr || out_dev == nullptr) return fail(MLQ_EINVAL, "NULL argument");

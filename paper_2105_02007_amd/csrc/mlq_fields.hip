@@ -157,6 +157,67 @@ void launch_transfer(const XferGeo& g, int64_t rows, double alpha, const double*
   hipLaunchKernelGGL(k_transfer, dim3((unsigned)cdiv(nx, kBlock), gy), dim3(kBlock), 0, s, g, rows, alpha, src, dst);
 }
 
+// Transfer with explicit interpolation weights in space (non-nested meshes): target node i'
+// takes sum_j w[i' K + j] src[node[i' K + j]] (indices clamped to the source grid), combined
+// with the linear time interpolation of k_transfer.  One thread per (row, target node), the
+// y dimension strides over the output time nodes.
+__global__ __launch_bounds__(kBlock) void k_transfer_weighted(XferGeo g, int64_t rows, int64_t n_from, int64_t n_to,
+                                                              int K, const int64_t* __restrict__ node,
+                                                              const double* __restrict__ w, double alpha,
+                                                              const double* __restrict__ src,
+                                                              double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * n_to) return;
+  const int64_t r = t / n_to;
+  const int64_t ip = t - r * n_to;
+  int64_t nd[kProbeNodes];
+  double wt[kProbeNodes];
+#pragma unroll
+  for (int jj = 0; jj < kProbeNodes; ++jj) {
+    if (jj < K) {
+      const int64_t v = node[ip * K + jj];
+      nd[jj] = v < 0 ? 0 : (v >= n_from ? n_from - 1 : v);
+      wt[jj] = w[ip * K + jj];
+    } else {
+      nd[jj] = 0;
+      wt[jj] = 0.0;
+    }
+  }
+  const double* sr = src + r * g.tn_f * n_from;
+  double* dr = dst + r * g.tn_t * n_to + ip;
+  for (int64_t kp = blockIdx.y; kp < g.tn_t; kp += gridDim.y) {
+    int64_t kc = 0;
+    double th = 0.0;
+    if (g.tn_t > 1) {
+      const int64_t num = kp * g.m_f;
+      kc = num / g.m_t;
+      th = (double)(num - kc * g.m_t) / (double)g.m_t;
+    }
+    double acc = 0.0;
+    for (int dtm = 0; dtm < 2; ++dtm) {
+      const double wtt = dtm ? th : 1.0 - th;
+      if (wtt == 0.0) continue;
+      const double* sk = sr + (kc + dtm) * n_from;
+      double part = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < kProbeNodes; ++jj)
+        if (wt[jj] != 0.0) part += wt[jj] * sk[nd[jj]];
+      acc += wtt * part;
+    }
+    dr[kp * n_to] += alpha * acc;
+  }
+}
+
+void launch_transfer_weighted(const XferGeo& g, int64_t rows, int64_t n_from, int64_t n_to, int K,
+                              const int64_t* node, const double* w, double alpha, const double* src, double* dst,
+                              hipStream_t s) {
+  const int64_t nx = rows * n_to;
+  if (nx < 1 || g.tn_t < 1) return;
+  const unsigned gy = (unsigned)(g.tn_t < 1024 ? g.tn_t : 1024);
+  hipLaunchKernelGGL(k_transfer_weighted, dim3((unsigned)cdiv(nx, kBlock), gy), dim3(kBlock), 0, s, g, rows, n_from,
+                     n_to, K, node, w, alpha, src, dst);
+}
+
 // Squared norm in L^2((0, T); H^q(D)) of the space-time interpolant of one row of a field
 // ((m + 1) x n nodal values on a Q1 box), integrated exactly: over element e and interval k,
 // dt/3 (a'A_e a + a'A_e b + b'A_e b) with a, b the element's corner values at t_k, t_(k+1) and

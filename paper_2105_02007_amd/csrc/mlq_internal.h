@@ -173,6 +173,9 @@ void launch_probe(const double* u, int32_t B, int64_t n, const ProbeTab& tab, in
 void launch_probe_sum(const double* u, int32_t B, int64_t n, const ProbeTab& tab, int32_t k, int32_t ld, double* sum,
                       hipStream_t s);
 void launch_transfer(const XferGeo& g, int64_t rows, double alpha, const double* src, double* dst, hipStream_t s);
+void launch_transfer_weighted(const XferGeo& g, int64_t rows, int64_t n_from, int64_t n_to, int K,
+                              const int64_t* node, const double* w, double alpha, const double* src, double* dst,
+                              hipStream_t s);
 constexpr int kNormBlocks = 1024;  // partial sums per row of a space-time norm
 struct NormGeo {
   int64_t n[3];  // nodes per axis (1 on unused axes)
@@ -200,6 +203,8 @@ mlq_status kl_modes(const mlq_kl_desc* kd, void* ws, double* lambda_host, double
 mlq_status kl_transfer(const mlq_kl_desc* kd, const double* psi_dev, const int64_t* level_n, const double* level_lo,
                        const double* level_hi, double* phi_dev, hipStream_t s);
 size_t kl_transfer_tet_bytes(int64_t n_tet);
+mlq_status locate_points_tet(const mlq_kl_desc* kd, const double* pts, int64_t np, std::vector<int32_t>& vid,
+                             std::vector<double>& wts, std::string& err);
 mlq_status kl_transfer_tet(const mlq_kl_desc* kd, const double* psi_dev, int64_t nv, const double* xyz, int64_t nt,
                            const int32_t* tets, void* ws, double* phi_dev, hipStream_t s, std::string& err);
 void launch_minv_basis(const Geo& g, const Work& w, const void* tri, int nmax, int j, int32_t B, bool mixed,

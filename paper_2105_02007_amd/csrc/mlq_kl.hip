@@ -625,15 +625,15 @@ namespace mlq {
 
 size_t kl_transfer_tet_bytes(int64_t P) { return al(sizeof(int32_t) * 4 * P) + al(sizeof(double) * 4 * P); }
 
-// Non-nested transfer: locate the centroids of the level's tetrahedra in the KL
-// mesh (uniform bucket grid over the KL mesh; the tetrahedron with the largest
-// smallest barycentric coordinate, lowest index on ties within 1e-12; the search
-// widens to the neighbouring cells for a point no candidate contains), then
-// interpolate the modes on the device.
-mlq_status kl_transfer_tet(const mlq_kl_desc* kd, const double* psi_dev, int64_t nv, const double* xyz, int64_t nt,
-                           const int32_t* tets, void* ws, double* phi_dev, hipStream_t s, std::string& err) {
+// Point location in a tetrahedral mesh (uniform bucket grid over the mesh; the tetrahedron
+// with the largest smallest barycentric coordinate, lowest index on ties within 1e-12; the
+// search widens to the neighbouring cells for a point no candidate contains, and a point
+// outside the mesh takes the best tetrahedron found there).  Output per point: the four
+// vertices and the barycentric weights, negative ones clipped to 0 and renormalised.
+mlq_status locate_points_tet(const mlq_kl_desc* kd, const double* pts, int64_t np, std::vector<int32_t>& vid,
+                             std::vector<double>& wts, std::string& err) {
   TetHost h;
-  err = kl_tet_mass(kd, h, true);  // gradients of the KL tetrahedra (geo)
+  err = kl_tet_mass(kd, h, true);  // gradients of the tetrahedra (geo)
   if (!err.empty()) return MLQ_EINVAL;
   const int64_t kn = kd->n_vert, kt = kd->n_tet;
   const double* kx = kd->xyz;
@@ -705,13 +705,11 @@ mlq_status kl_transfer_tet(const mlq_kl_desc* kd, const double* psi_dev, int64_t
     bary(e, x, lam);
     return std::min(std::min(lam[0], lam[1]), std::min(lam[2], lam[3]));
   };
-  std::vector<int32_t> vid((size_t)4 * nt);
-  std::vector<double> wts((size_t)4 * nt);
+  vid.assign((size_t)4 * np, 0);
+  wts.assign((size_t)4 * np, 0.0);
   std::vector<int32_t> cand;
-  for (int64_t p = 0; p < nt; ++p) {
-    double x[3] = {0, 0, 0};
-    for (int a = 0; a < 4; ++a)
-      for (int m = 0; m < 3; ++m) x[m] += 0.25 * xyz[3 * (int64_t)tets[4 * p + a] + m];
+  for (int64_t p = 0; p < np; ++p) {
+    const double* x = pts + 3 * p;
     int64_t ci[3];
     for (int m = 0; m < 3; ++m) ci[m] = cidx(x, m);
     int64_t best_e = -1;
@@ -751,6 +749,23 @@ mlq_status kl_transfer_tet(const mlq_kl_desc* kd, const double* psi_dev, int64_t
       wts[4 * p + a] = lam[a] / sum;
     }
   }
+  return MLQ_OK;
+}
+
+// Non-nested transfer: locate the centroids of the level's tetrahedra in the KL mesh, then
+// interpolate the modes on the device.
+mlq_status kl_transfer_tet(const mlq_kl_desc* kd, const double* psi_dev, int64_t nv, const double* xyz, int64_t nt,
+                           const int32_t* tets, void* ws, double* phi_dev, hipStream_t s, std::string& err) {
+  (void)nv;
+  std::vector<double> cen((size_t)3 * nt, 0.0);
+  for (int64_t p = 0; p < nt; ++p)
+    for (int a = 0; a < 4; ++a)
+      for (int m = 0; m < 3; ++m) cen[3 * p + m] += 0.25 * xyz[3 * (int64_t)tets[4 * p + a] + m];
+  std::vector<int32_t> vid;
+  std::vector<double> wts;
+  const mlq_status st = locate_points_tet(kd, cen.data(), nt, vid, wts, err);
+  if (st != MLQ_OK) return st;
+  const int64_t kn = kd->n_vert;
   int32_t* dv = (int32_t*)ws;
   double* dw = (double*)((char*)ws + al(sizeof(int32_t) * 4 * nt));
   hipError_t e = hipMemcpyAsync(dv, vid.data(), sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice, s);

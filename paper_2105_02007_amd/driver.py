@@ -225,49 +225,125 @@ class ConfigRunner:
                 fc.append(None)
         return self._estimate(mlq.MLQ_EST_MLMC, ff, fc, [Y.shape[1] for Y in Ys], 1)
 
+    # ---- field quantities of interest ------------------------------------
+    def _tet_weights(self, j):
+        """P1 interpolation of level j's shell at the finest shell's vertices: (node, w) device
+        tensors (n_L x 4), cached."""
+        if not hasattr(self, "_wcache"):
+            self._wcache = {}
+        if j not in self._wcache:
+            node, w = mlq.tet_locate(self.meshes[j], self.meshes[-1]["xyz"])
+            self._wcache[j] = (torch.as_tensor(node, device=self.device), torch.as_tensor(w, device=self.device))
+        return self._wcache[j]
+
+    def _to_finest(self, j, src, dst, alpha, space=True, time=True, rows=1):
+        """dst (finest grid) += alpha * T_j src (level j's grid): Q1 interpolation between nested
+        boxes, P1 interpolation at the finest vertices between non-nested shells, linear in time."""
+        lv, fin = self.levels[j], self.levels[-1]
+        if self.tet and space:
+            if j == len(self.levels) - 1:  # the finest shell itself: elementwise
+                mlq.transfer_add(lv, fin, src, dst, alpha=alpha, space=False, time=False, rows=src.numel())
+            else:
+                node, w = self._tet_weights(j)
+                mlq.transfer_add_weighted(lv, fin, node, w, src, dst, alpha=alpha, time=time, rows=rows)
+        else:
+            mlq.transfer_add(lv, fin, src, dst, alpha=alpha, space=space, time=time, rows=rows)
+
+    def _probe_weights(self, j, probes):
+        """(node, w) host arrays (P x 8) interpolating level j at the probe points."""
+        if not self.tet:
+            return self.levels[j].probe_weights(probes)
+        node4, w4 = mlq.tet_locate(self.meshes[j], probes)
+        node = np.zeros((len(node4), mlq.PROBE_NODES), dtype=np.int64)
+        w = np.zeros((len(node4), mlq.PROBE_NODES))
+        node[:, :4], w[:, :4] = node4, w4
+        return node, w
+
+    def _field_buffers(self, j, npr, pw):
+        lv = self.levels[j]
+        z = lambda *shape: torch.zeros(shape, dtype=torch.float64, device=self.device)
+        f = dict(u_sum=z(lv.desc.n_steps + 1, lv.n_nodes), act_sum=z(lv.n_nodes))
+        if npr:
+            f.update(probe_node=pw[j][0], probe_w=pw[j][1], probe_sum=z(npr, lv.desc.n_steps + 1))
+        return f
+
+    def _field_estimate(self, terms, npr):
+        """sum of alpha T_j S over terms [(j, alpha, buffers)] on the finest grids."""
+        fin = self.levels[-1]
+        z = lambda *shape: torch.zeros(shape, dtype=torch.float64, device=self.device)
+        est_u, est_a = z(fin.desc.n_steps + 1, fin.n_nodes), z(fin.n_nodes)
+        est_p = z(npr, fin.desc.n_steps + 1) if npr else None
+        for j, alpha, f in terms:
+            self._to_finest(j, f["u_sum"], est_u, alpha)
+            self._to_finest(j, f["act_sum"], est_a, alpha, time=False)
+            if npr:  # each probe's series: time transfer only
+                mlq.transfer_add(self.levels[j], fin, f["probe_sum"], est_p, alpha=alpha, space=False, rows=npr)
+        return est_u, est_a, est_p
+
+    def run_combination_fields(self, Y, probes=None):
+        """eq. (PimpedML) for the field quantities of interest (Section 2.4) with nested point
+        sets: level j = L - l is solved at the points of Q_l in two batches, the points of
+        Q_(l-1) and the rest, so that its term mean_Ql - mean_Q(l-1) is
+            T_j ((1/N_l - 1/N_(l-1)) S_A + (1/N_l) S_B)
+        with S_A, S_B the two batches' streamed sums; the fields are moved to the finest grids
+        (non-nested shells: P1 interpolation at the finest vertices).  Also the scalar estimate."""
+        npl = self.cfg["sampling"]["n_per_level"]
+        L = len(self.levels) - 1
+        npr = 0 if probes is None else len(probes)
+        pw = [self._probe_weights(j, probes) for j in range(L + 1)] if npr else None
+        jobs, terms, parts = [], [], []
+        for l in range(L + 1):
+            j, n_l, n_p = L - l, npl[l], (npl[l - 1] if l > 0 else 0)
+            if n_p > 0:
+                fa = self._field_buffers(j, npr, pw)
+                jobs.append((j, Y[:, :n_p].contiguous(), fa))
+                terms.append((j, 1.0 / n_l - 1.0 / n_p, fa))
+            fb = self._field_buffers(j, npr, pw)
+            jobs.append((j, Y[:, n_p:n_l].contiguous(), fb))
+            terms.append((j, 1.0 / n_l, fb))
+            parts.append((j, 2 if n_p > 0 else 1))
+        res = self.solve_all(jobs)
+        f = [None] * (L + 1)
+        k = 0
+        for j, cnt in parts:
+            f[j] = torch.cat(res[k:k + cnt])
+            k += cnt
+        est_u, est_a, est_p = self._field_estimate(terms, npr)
+        out = self._estimate(mlq.MLQ_EST_COMBINATION, f, None, list(npl), 1)
+        out.update(mean_u=est_u, mean_act_map=est_a, mean_probe=est_p)
+        return out
+
     def run_mlmc_fields(self, Ys, probes=None):
         """eq. (StandardML) for the field quantities of interest of Section 2.4, with independent
-        MC sets Ys[l] (nested box levels): the mean transmembrane potential E[u] on the finest
+        MC sets Ys[l]: the mean transmembrane potential E[u] on the finest
         level's space-time grid ((m_L + 1) x n_L), the mean activation map on its nodes, and the
         mean action potential at the probe points (P x 3) on its time grid.  Each solve streams
         its sums on its own level's grid; the level terms are moved to the finest grid by the
         space-time transfer, so that the estimate is
             sum_l (1/N_l) (T_l S_fine(l) - T_(l-1) S_coarse(l)),
-        with S the sums over the level's samples.  Also returns the scalar estimate."""
-        if self.tet:
-            raise ValueError("field estimates transfer between nested box levels")
+        with S the sums over the level's samples (non-nested shells: P1 interpolation at the
+        finest vertices; the level-term norms are computed on boxes).  Also returns the scalar
+        estimate."""
         dev = self.device
-        fin = self.levels[-1]
+        npr = 0 if probes is None else len(probes)
+        pw = [self._probe_weights(j, probes) for j in range(len(self.levels))] if npr else None
 
         def zeros(*shape):
             return torch.zeros(shape, dtype=torch.float64, device=dev)
-        pw = [lv.probe_weights(probes) for lv in self.levels] if probes is not None else None
-        npr = 0 if probes is None else len(probes)
-        jobs, meta = [], []
+        jobs, terms = [], []
         for l, Y in enumerate(Ys):
             for j, sign in [(l, 1.0)] + ([(l - 1, -1.0)] if l > 0 else []):
-                lv = self.levels[j]
-                f = dict(u_sum=zeros(lv.desc.n_steps + 1, lv.n_nodes), act_sum=zeros(lv.n_nodes))
-                if npr:
-                    f.update(probe_node=pw[j][0], probe_w=pw[j][1], probe_sum=zeros(npr, lv.desc.n_steps + 1))
+                f = self._field_buffers(j, npr, pw)
                 jobs.append((j, Y, f))
-                meta.append((j, sign / Y.shape[1]))
+                terms.append((j, sign / Y.shape[1], f))
         res = self.solve_all(jobs)
-        est_u = zeros(fin.desc.n_steps + 1, fin.n_nodes)
-        est_a = zeros(fin.n_nodes)
-        est_p = zeros(npr, fin.desc.n_steps + 1) if npr else None
-        for (j, alpha), (_, _, f) in zip(meta, jobs):
-            lv = self.levels[j]
-            mlq.transfer_add(lv, fin, f["u_sum"], est_u, alpha=alpha)
-            mlq.transfer_add(lv, fin, f["act_sum"], est_a, alpha=alpha, time=False)
-            if npr:
-                mlq.transfer_add(lv, fin, f["probe_sum"], est_p, alpha=alpha, space=False, rows=npr)
+        est_u, est_a, est_p = self._field_estimate(terms, npr)
         # norms of the level terms on their own grids: mean_0 and, for l > 0, the mean level
         # difference mean_l - T mean_(l-1) (the quantities whose decay the level hierarchy
         # relies on), in L^2((0,T); L^2) and L^2((0,T); H^1)
-        corr = []
+        corr = [] if not self.tet else None
         k = 0
-        for l, Y in enumerate(Ys):
+        for l, Y in enumerate(Ys if not self.tet else []):
             lv = self.levels[l]
             D = zeros(lv.desc.n_steps + 1, lv.n_nodes)
             mlq.transfer_add(lv, lv, jobs[k][2]["u_sum"], D, alpha=1.0 / Y.shape[1])

@@ -27,7 +27,7 @@ EXPORTED = [
     "mlq_lattice_normals", "mlq_halton", "mlq_cbc", "mlq_accumulate", "mlq_estimate", "mlq_last_error",
     "mlq_kl_workspace_bytes", "mlq_kl_modes", "mlq_kl_transfer", "mlq_timing_enable", "mlq_timing_read",
     "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet", "mlq_solve_batch_fields", "mlq_probe_weights",
-    "mlq_transfer_add", "mlq_field_norm2", "mlq_set_reference",
+    "mlq_transfer_add", "mlq_field_norm2", "mlq_set_reference", "mlq_tet_locate", "mlq_transfer_add_weighted",
 ]
 MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE, MLQ_GUESS_REFERENCE, MLQ_GUESS_REFERENCE_LOCAL = 0, 1, 2, 3
 MLQ_DIFF_FIBRE, MLQ_DIFF_ISO, MLQ_DIFF_VECTOR = 0, 1, 2
@@ -109,6 +109,8 @@ def _load():
         "mlq_transfer_add": [VP, VP, I32, I32, I64, C.c_double, VP, VP, VP],
         "mlq_field_norm2": [VP, I32, I32, I64, VP, VP, VP, VP],
         "mlq_set_reference": [VP, VP],
+        "mlq_tet_locate": [VP, I64, VP, I64, VP, I64, VP, VP],
+        "mlq_transfer_add_weighted": [VP, VP, I32, I64, I32, VP, VP, C.c_double, VP, VP, VP],
         "mlq_cbc": [I64, I32, VP, VP],
         "mlq_accumulate": [VP, VP, I32, VP, VP],
         "mlq_estimate": [I32, I32, I32, VP, VP, VP, C.POINTER(EstimateOut)],
@@ -374,6 +376,27 @@ def transfer_add(src_level, dst_level, src, dst, alpha=1.0, space=True, time=Tru
     """dst += alpha * (time x space interpolation) src between the grids of two levels."""
     check(lib.mlq_transfer_add(src_level.handle, dst_level.handle, 1 if space else 0, 1 if time else 0, int(rows),
                                float(alpha), _ptr(src), _ptr(dst), _stream()))
+    return dst
+
+
+def tet_locate(mesh: dict, pts):
+    """(node (P x 4) int64, weight (P x 4)) host arrays: P1 interpolation of the tetrahedral mesh
+    (mesh["xyz"], mesh["tets"]) at the points (P x 3)."""
+    xyz = np.ascontiguousarray(mesh["xyz"], dtype=np.float64)
+    tets = np.ascontiguousarray(mesh["tets"], dtype=np.int32)
+    p = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    node = np.zeros((p.shape[0], 4), dtype=np.int64)
+    w = np.zeros((p.shape[0], 4))
+    check(lib.mlq_tet_locate(xyz.ctypes.data, xyz.shape[0], tets.ctypes.data, tets.shape[0], p.ctypes.data,
+                             p.shape[0], node.ctypes.data, w.ctypes.data))
+    return node, w
+
+
+def transfer_add_weighted(src_level, dst_level, node, w, src, dst, alpha=1.0, time=True, rows=1):
+    """dst += alpha * (time x weighted space interpolation) src; node, w: device tensors (n_to x K)."""
+    K = node.shape[1]
+    check(lib.mlq_transfer_add_weighted(src_level.handle, dst_level.handle, 1 if time else 0, int(rows), int(K),
+                                        _ptr(node), _ptr(w), float(alpha), _ptr(src), _ptr(dst), _stream()))
     return dst
 
 

@@ -108,3 +108,19 @@ def test_estimators_match_oracle(mlq):
     fj = [F[j][:npts[2 - j]] for j in range(3)]
     r = mlq.estimate(mlq.MLQ_EST_COMBINATION, fj, n_per_level=npts)
     assert np.isclose(r["estimate"], E.combination(fj, npts), rtol=1e-14)
+
+
+def test_tet_locate_matches_oracle(mlq):
+    """mlq_tet_locate (host): the P1 interpolant of a random nodal field at the vertices of a
+    finer non-nested shell (points inside the coarse mesh and boundary points outside it)
+    equals the oracle's brute-force location (1e-12)."""
+    from oracle.tetfem import TetMesh
+    from workloads import tetshell
+    xyz_c, tets_c, _, _, _ = tetshell.shell_mesh((2, 6, 12), seed=3)
+    xyz_f, _, _, _, _ = tetshell.shell_mesh((3, 9, 18), seed=4)
+    node, w = mlq.tet_locate(dict(xyz=xyz_c, tets=tets_c), xyz_f)
+    assert np.allclose(w.sum(axis=1), 1.0) and (w >= 0).all()
+    vals = np.random.default_rng(2).normal(size=xyz_c.shape[0])
+    got = (w * vals[node]).sum(axis=1)
+    ref = TetMesh(xyz_c, tets_c).interpolate(vals, xyz_f)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(vals).max()

@@ -301,3 +301,83 @@ def test_c5v_pipeline_small_matches_oracle(env):
     for j in range(L + 1):
         assert np.abs(res["f_fine"][j] - f[j]).max() <= 1e-10 * np.abs(f[j]).max(), j
     assert abs(res["estimate"] - est) <= 1e-10 * abs(est)
+
+
+def test_weighted_transfer_between_shells_matches_oracle(env):
+    """A space-time field of a coarse shell moved to a finer non-nested shell (P1 interpolation
+    at its vertices, clipped outside the coarse mesh, and linear in time), within 1e-13."""
+    torch, mlq = env
+    from oracle import fields
+    from oracle.tetfem import TetMesh
+    ph = _phys()
+    mc, _ = _shell((2, 6, 12), seed=3)
+    mf, _ = _shell((3, 9, 18), seed=4)
+    Lc = mlq.Level(*mlq.make_desc(dict(kind="tet", dim=3, n_steps=4, mesh=mc), ph))
+    Lf = mlq.Level(*mlq.make_desc(dict(kind="tet", dim=3, n_steps=12, mesh=mf), ph))
+    rng = np.random.default_rng(7)
+    src = rng.normal(size=(5, mc["xyz"].shape[0]))
+    dst0 = rng.normal(size=(13, mf["xyz"].shape[0]))
+    node, w = mlq.tet_locate(mc, mf["xyz"])
+    dst = torch.as_tensor(dst0, device="cuda")
+    mlq.transfer_add_weighted(Lc, Lf, torch.as_tensor(node, device="cuda"), torch.as_tensor(w, device="cuda"),
+                              torch.as_tensor(src, device="cuda"), dst, alpha=-0.4)
+    sp = TetMesh(mc["xyz"], mc["tets"]).interpolate(src.T, mf["xyz"])            # (n_f, 5)
+    ref = dst0 - 0.4 * fields.prolongate_time(sp, 4, 12, ph["t_end"]).T
+    assert np.abs(dst.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_c5_field_combination_small_matches_oracle(env):
+    """The field form of eq. (PimpedML) on small non-nested shells through the driver: mean
+    space-time potential and activation map on the finest shell, mean action potential at two
+    points, against the oracle's per-sample solves, P1 transfers and the same combination."""
+    torch, mlq = env
+    from oracle import fields, kl, stepper
+    from oracle.tetfem import TetMesh
+    from paper_2105_02007_amd.driver import ConfigRunner
+    cfg = W.config("c5")
+    cfg["levels"] = W._tet_levels([(2, 6, 12), (3, 8, 16)], [8, 16], 5)
+    cfg["kl"].update(n_modes=5, grid_level=1)
+    cfg["sampling"]["n_per_level"] = [2, 5]
+    cfg["prec"] = W.PREC_FP64
+    M = cfg["kl"]["n_modes"]
+    meshes = [W.tet_mesh(lv) for lv in cfg["levels"]]
+    n_kl = meshes[-1]["xyz"].shape[0]
+    factor = n_kl // M
+    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0)
+    Y = W.mc_normals(cfg["seed"], 0, 5, M)
+    pts = 0.5 * (meshes[-1]["xyz"][[3, 40]] + meshes[-1]["xyz"][[4, 41]])  # midpoints of two vertex pairs
+    res = runner.run_combination_fields(torch.as_tensor(Y, device="cuda"), probes=pts)
+    ph = cfg["physics"]
+    tm = [TetMesh(m["xyz"], m["tets"]) for m in meshes]
+    Mk, _ = tm[-1].assemble(np.zeros((tm[-1].n_elems, 3, 3)))
+    lam, psi = kl.kl_modes(tm[-1], Mk, cfg["kl"]["std"], cfg["kl"]["corr_len"], M, max_rank=factor * M, eps=0.0)
+    npl = cfg["sampling"]["n_per_level"]
+    L = 1
+    steps = [lv["n_steps"] for lv in cfg["levels"]]
+    T = ph["t_end"]
+    est_u = est_a = est_p = 0.0
+    for l in range(L + 1):
+        j = L - l
+        phi = tm[-1].interpolate(psi, tm[j].centres)
+        th = kl.field(meshes[j]["theta0"], phi, np.sqrt(lam), Y[:, :npl[l]])
+        outs = []
+        for b in range(npl[l]):
+            G = tm[j].conductivity(th[b], meshes[j]["e_circ"], meshes[j]["e_long"], ph["sigma_l"], ph["sigma_t"])
+            outs.append(stepper.solve(tm[j], G, ph, steps[j], tol=1e-13, keep_all=True))
+        H = [fields.space_time_field(o) for o in outs]
+        A = [fields.activation_map(o) for o in outs]
+        P = [tm[j].interpolate(fields.space_time_field(o).T, pts) for o in outs]   # (2, m + 1)
+        n_p = npl[l - 1] if l > 0 else 0
+
+        def term(V):
+            return sum(V) / npl[l] - (sum(V[:n_p]) / n_p if n_p else 0.0)
+        tu, ta, tp = term(H), term(A), term(P)
+        if j != L:
+            tu = fields.prolongate_time(tm[j].interpolate(tu.T, meshes[-1]["xyz"]), steps[j], steps[-1], T).T
+            ta = tm[j].interpolate(ta, meshes[-1]["xyz"])
+            tp = fields.prolongate_time(tp, steps[j], steps[-1], T)
+        est_u, est_a, est_p = est_u + tu, est_a + ta, est_p + tp
+    gu, ga, gp = (res[k].cpu().numpy() for k in ("mean_u", "mean_act_map", "mean_probe"))
+    assert np.abs(gu - est_u).max() <= 1e-10 * np.abs(est_u).max()
+    assert np.abs(ga - est_a).max() <= 1e-8 * T
+    assert np.abs(gp - est_p).max() <= 1e-10 * np.abs(est_p).max()
