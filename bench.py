@@ -314,6 +314,9 @@ def main():
         shifts = [W.lattice_shifts(cfg["seed"], l, S, n_dims) for l in range(len(cfg["levels"]))]
         step = lambda: runner.run_mlqmc(shifts)
 
+    if args.fields:
+        runner.prepare_fields(field_probes(cfg, runner))
+        log("field transfer set-up done")
     if args.copy_calibration:
         src = torch.ones(COPY_ELEMS, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

@@ -249,7 +249,7 @@ class Level:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:  # lib is None during interpreter shutdown
             lib.mlq_destroy_level(h)
             self.handle = None
 
