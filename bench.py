@@ -254,6 +254,8 @@ def main():
                     default="extrapolate",
                     help="Newton initial guess of each step: u_k, 2 u_k - u_(k-1), or from the unperturbed "
                          "reference solution (global r_(k+1), or local u_k + r_(k+1) - r_k)")
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="relative residual at which GMRES stops (default 1e-4; mixed boxes 1e-3)")
     ap.add_argument("--fields", action="store_true",
                     help="MLMC workloads: also estimate the field quantities of interest (mean space-time "
                          "potential on the finest grid, mean activation map, mean action potential at 4 points)")
@@ -282,7 +284,7 @@ def main():
     t_setup = time.perf_counter()
     guess = {"previous": mlq.MLQ_GUESS_PREVIOUS, "extrapolate": mlq.MLQ_GUESS_EXTRAPOLATE,
              "reference": mlq.MLQ_GUESS_REFERENCE, "reference-local": mlq.MLQ_GUESS_REFERENCE_LOCAL}[args.newton_guess]
-    runner = ConfigRunner(cfg, prec=prec, device=dev, log=log, newton_guess=guess)
+    runner = ConfigRunner(cfg, prec=prec, device=dev, log=log, newton_guess=guess, inner_tol=args.inner_tol)
     t_setup = time.perf_counter() - t_setup
     log(f"set-up done in {t_setup:.1f} s (KL rank {runner.kl_rank})")
     runner.log = log
@@ -456,6 +458,7 @@ def main():
                            gmres_per_step=round(runner.level_inner[l] / runner.level_sample_steps[l], 2))
                       for l in range(len(runner.levels))]
     line["newton_guess"] = args.newton_guess
+    line["inner_tol"] = runner.levels[-1].desc.inner_tol
     if breakdown:
         line["breakdown"] = breakdown
     line["kl_synthesis"] = kl_synthesis(runner, cfg, dev)
