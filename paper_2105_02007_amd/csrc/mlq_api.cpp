@@ -749,7 +749,8 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
       });
       timed(level, MLQ_K_SMALL, 0.0, s, [&] {
         launch_newton_check(g, w, batch, d.newton_tol, s);
-        launch_count(w.newton_active, batch, w.counter, s);
+        // the Newton count; also clears the counter that GMRES iteration 0 accumulates into
+        launch_count(w.newton_active, batch, w.counter, w.counter + 1, s);
       });
       mlq_status st = read_counter(level, w, s, &active);
       if (st != MLQ_OK) return st;
@@ -797,8 +798,7 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
         timed(level, MLQ_K_ORTH, nn, s,
               [&] { launch_orth(g, w, j, batch, mixed, s, fuse ? w.nwav : w.nred); }, 0.0, nin);
         timed(level, MLQ_K_SMALL, 0.0, s, [&] {
-          launch_givens(g, w, j, batch, d.inner_tol, s, w.nred);
-          launch_count(w.inner_active, batch, w.counter + 1 + (j & 1), s);
+          launch_givens(g, w, j, batch, d.inner_tol, s, w.nred);  // counts into counter[1 + (j & 1)]
         });
         // The count of iteration j is read while iteration j + 1 is already queued, so
         // the GPU does not idle during the host round trip; an iteration queued after

@@ -136,9 +136,11 @@ void launch_rhs(const Geo& g, const Work& w, const double* fbox, double load_coe
                 bool mixed, hipStream_t s);
 void launch_residual(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);
 void launch_newton_check(const Geo& g, const Work& w, int32_t B, double tol, hipStream_t s);
-void launch_count(const int32_t* flags, int32_t B, int32_t* out, hipStream_t s);
+void launch_count(const int32_t* flags, int32_t B, int32_t* out, int32_t* zero, hipStream_t s);
 void launch_dots(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s);
 void launch_orth(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s, int32_t npart);
+// Givens rotation of column j; also counts the samples still active into counter[1 + (j & 1)]
+// and clears counter[1 + ((j + 1) & 1)] for the next iteration.
 void launch_givens(const Geo& g, const Work& w, int j, int32_t B, double tol, hipStream_t s, int32_t nparts);
 void launch_solve_y(const Work& w, int32_t B, bool scaled, hipStream_t s);
 void launch_activation(const Work& w, int64_t nn, int32_t B, double u_th, double t_k, double dt,

@@ -421,16 +421,21 @@ void launch_newton_check(const Geo& g, const Work& w, int32_t B, double tol, hip
                      w.inner_active, w.inner_k, w.status, w.beta, w.g, w.inv_eta, w.kmax);
 }
 
-__global__ void k_count(const int32_t* __restrict__ flags, int32_t B, int32_t* out) {
+// Number of set flags into out[0]; also clears `zero` (may be NULL), the counter the next
+// Givens launch accumulates into.
+__global__ void k_count(const int32_t* __restrict__ flags, int32_t B, int32_t* out, int32_t* zero) {
   __shared__ double sh[kBlock / 64];
   double c = 0;
   for (int i = threadIdx.x; i < B; i += kBlock) c += flags[i] != 0 ? 1.0 : 0.0;
   c = block_sum<kBlock>(c, sh);
-  if (threadIdx.x == 0) out[0] = (int32_t)c;
+  if (threadIdx.x == 0) {
+    out[0] = (int32_t)c;
+    if (zero != nullptr) zero[0] = 0;
+  }
 }
 
-void launch_count(const int32_t* flags, int32_t B, int32_t* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_count, dim3(1), dim3(kBlock), 0, s, flags, B, out);
+void launch_count(const int32_t* flags, int32_t B, int32_t* out, int32_t* zero, hipStream_t s) {
+  hipLaunchKernelGGL(k_count, dim3(1), dim3(kBlock), 0, s, flags, B, out, zero);
 }
 
 // ---------------------------------------------------------------------------
@@ -602,11 +607,16 @@ void launch_orth(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipS
 }
 
 // Norm of the new vector, Givens rotations of column j, residual estimate |g_{j+1}|.
+// Also counts the samples still active after this iteration into *count (one integer
+// atomic add per such sample; the order does not matter) and clears *clear, the counter of
+// the next iteration (two counters alternate, so the host can read this one meanwhile).
 __global__ __launch_bounds__(kBlock) void k_givens(const double* __restrict__ part, int32_t nred, int j, int kmax,
                                                    double tol, double* H, double* cs, double* sn, double* gv,
                                                    double* inv_eta, const double* __restrict__ beta,
-                                                   int32_t* inner_active, int32_t* inner_k) {
+                                                   int32_t* inner_active, int32_t* inner_k, int32_t* count,
+                                                   int32_t* clear) {
   const int sb = blockIdx.x;
+  if (sb == 0 && threadIdx.x == 0) *clear = 0;
   if (inner_active[sb] == 0) return;
   __shared__ double sh[kBlock / 64];
   double acc = 0.0;
@@ -642,13 +652,16 @@ __global__ __launch_bounds__(kBlock) void k_givens(const double* __restrict__ pa
   if (res <= tol * beta[sb] || hn == 0.0 || j + 1 >= kmax || !(res == res)) {
     inner_active[sb] = 0;
     inner_k[sb] = j + 1;
+  } else {
+    atomicAdd(count, 1);
   }
 }
 
 void launch_givens(const Geo& g, const Work& w, int j, int32_t B, double tol, hipStream_t s, int32_t nparts) {
   (void)g;
   hipLaunchKernelGGL(k_givens, dim3(B), dim3(kBlock), 0, s, w.part, nparts, j, w.kmax, tol, w.H, w.cs, w.sn, w.g,
-                     w.inv_eta, w.beta, w.inner_active, w.inner_k);
+                     w.inv_eta, w.beta, w.inner_active, w.inner_k, w.counter + 1 + (j & 1),
+                     w.counter + 1 + ((j + 1) & 1));
 }
 
 // Back substitution R y = g on the rotated Hessenberg matrix; stores y_i, times inv_eta_i
