@@ -86,6 +86,10 @@ WORKLOAD_TEXT = {
     "c5": "non-nested prolate-ellipsoidal shell, P1 tetrahedra 26k/187k/1.4M vertices, 512 steps, 256-mode KL "
           "(l = 0.1 long axis), rule-based +60/-60 deg fibres, combination estimator 16/64/256 nested MC points, "
           "mean activation time",
+    "c5i": "the c5 shells with the paper's idealised-ventricle model: isotropic G = max(v, 0.1 E[V]) I, "
+           "v = E[V] + W, W a squared-exponential KL field (0.3 E[V], sigma_KL = 0.5 x 2^2 for the shell's "
+           "size) with 87 uniform coordinates, combination estimator 16/64/256 nested MC points, mean "
+           "activation time",
     "c5v": "the c5 shells with the paper's heart model: eq. (AdmV) with a random vector field V = sigma_l f0 + W, "
            "W three independent squared-exponential KL fields (0.3 sigma_l, sigma_KL = 0.64), 3 x 45 uniform "
            "coordinates, combination estimator 16/64/256 nested MC points, mean activation time",
@@ -109,6 +113,10 @@ def cpu_baseline_tet(cfg, budget_s):
         f0 = np.cos(m["theta0"])[:, None] * m["e_circ"] + np.sin(m["theta0"])[:, None] * m["e_long"]
         V = ph["sigma_l"] * (f0 + 0.3 * W.random_nodal(cfg["seed"], 3, mesh.n_elems).T)
         G = fem.conductivity(V, ph["sigma_t"])
+    elif cfg.get("model") == "iso":  # E[V] times a seeded perturbation, bounded below
+        from oracle import fem
+        v = cfg["kl"]["mean"] * (1.0 + 0.3 * W.random_nodal(cfg["seed"], 1, mesh.n_elems)[0])
+        G = fem.conductivity_iso(v, 3, ph["sigma_t"])
     else:
         th = m["theta0"] + 0.3 * W.random_nodal(cfg["seed"], 1, mesh.n_elems)[0]
         G = mesh.conductivity(th, m["e_circ"], m["e_long"], ph["sigma_l"], ph["sigma_t"])

@@ -119,14 +119,16 @@ typedef struct {
    * read for time stepping): 2 = r_(k+1) (the global guess), 3 = u_k + (r_(k+1) - r_k) (the
    * local one); r is set with mlq_set_reference. */
   int32_t newton_guess;               /* mlq_newton_guess */
-  /* Conductivity model of the elements (boxes): MLQ_DIFF_FIBRE: the field is the fibre
-   * angle theta, G = sigma_t I + (sigma_l - sigma_t) f f^T with f = (cos theta, sin theta[, 0]),
-   * eq. (AdmV) with V = sigma_l f; MLQ_DIFF_ISO: the field is a scalar conductivity v,
-   * G = max(v, sigma_t) I (isotropic diffusion, the paper's cube experiments of Section 5.2;
-   * sigma_t is the lower bound b_min that keeps G positive definite, sigma_l is unused); MLQ_DIFF_VECTOR (tetrahedra): eq. (AdmV) itself with a random vector
-   * field, G = g I + (|V| - g) V V^T / V^T V, g = sigma_t, V = v_mean + the field, whose three
+  /* Conductivity model of the elements: MLQ_DIFF_FIBRE: the field is the fibre angle theta,
+   * G = sigma_t I + (sigma_l - sigma_t) f f^T with f = (cos theta, sin theta[, 0]) on boxes and
+   * f = cos theta e_circ + sin theta e_long on tetrahedra, eq. (AdmV) with V = sigma_l f;
+   * MLQ_DIFF_ISO: the field is a scalar conductivity v, G = max(v, sigma_t) I (isotropic
+   * diffusion, the paper's cube and idealised-ventricle experiments of Section 5.2; sigma_t is
+   * the lower bound b_min that keeps G positive definite, sigma_l is unused);
+   * MLQ_DIFF_VECTOR (tetrahedra only): eq. (AdmV) itself with a random vector field,
+   * G = g I + (|V| - g) V V^T / V^T V, g = sigma_t, V = v_mean + the field, whose three
    * components the solve and apply calls take component-major ([3][B][P]: component c of
-   * sample b at (c B + b) P + e).  Tetrahedra: MLQ_DIFF_FIBRE or MLQ_DIFF_VECTOR. */
+   * sample b at (c B + b) P + e). */
   int32_t diffusion;
   const double* v_mean;               /* MLQ_DIFF_VECTOR: n_tet x 3 host array, E[V] per element */
 } mlq_level_desc;

@@ -219,8 +219,6 @@ mlq_status validate(const mlq_level_desc* d) {
     return fail(MLQ_EINVAL, "unknown newton_guess");
   if (d->diffusion != MLQ_DIFF_FIBRE && d->diffusion != MLQ_DIFF_ISO && d->diffusion != MLQ_DIFF_VECTOR)
     return fail(MLQ_EINVAL, "diffusion must be MLQ_DIFF_FIBRE, MLQ_DIFF_ISO or MLQ_DIFF_VECTOR");
-  if (d->diffusion == MLQ_DIFF_ISO && d->mesh_kind != MLQ_MESH_Q1_BOX)
-    return fail(MLQ_EINVAL, "the isotropic scalar diffusion model is for boxes");
   if (d->diffusion == MLQ_DIFF_VECTOR && d->mesh_kind != MLQ_MESH_P1_TET)
     return fail(MLQ_EINVAL, "the vector diffusion model is for tetrahedra");
   if (d->diffusion == MLQ_DIFF_VECTOR && d->v_mean == nullptr) return fail(MLQ_EINVAL, "v_mean is NULL");
@@ -541,7 +539,7 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
     t.ecptr = (const int32_t*)(base + L.ecptr);
     t.ecdat = (const int32_t*)(base + L.ecdat);
     t.geo = (const double*)(base + L.geo);
-    t.vec = desc->diffusion == MLQ_DIFF_VECTOR ? 1 : 0;
+    t.model = desc->diffusion;
     t.vmean = (const double*)(base + L.vmean);
     std::vector<float> m32(th.em.begin(), th.em.end()), d32(th.mdiag.begin(), th.mdiag.end());
     auto up = [&](const void* dst, const void* src, size_t bytes) {
@@ -556,7 +554,7 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
     up(t.ecptr, th.ecptr.data(), sizeof(int32_t) * th.ecptr.size());
     up(t.ecdat, th.ecdat.data(), sizeof(int32_t) * th.ecdat.size());
     up(t.geo, th.geo.data(), sizeof(double) * th.geo.size());
-    if (t.vec) up(t.vmean, desc->v_mean, sizeof(double) * 3 * th.nt);
+    if (t.model == MLQ_DIFF_VECTOR) up(t.vmean, desc->v_mean, sizeof(double) * 3 * th.nt);
     // the host vectors must outlive the asynchronous copies
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }

@@ -50,7 +50,7 @@ struct TetDev {
   const int32_t* ecptr;    // nell + 1
   const int32_t* ecdat;    // nc: (tet << 4) | (4 a + b), a = local row vertex, b = local column vertex
   const double* geo;       // nt x kTetGeo: grad phi_0..3 (12), e_circ (3), e_long (3), volume
-  int32_t vec;             // 1: vector conductivity model (the field is V - vmean, 3 components)
+  int32_t model;           // conductivity model (MLQ_DIFF_*; vector: the field is V - vmean, 3 components)
   const double* vmean;     // nt x 3: E[V] per element (vector model), else unused
 };
 constexpr int kTetGeo = 19;

@@ -28,13 +28,14 @@ __device__ inline double tet_diion(double u, const Ionic& io) {
   return io.alpha * (b * c + a * c + a * b);
 }
 
-// Fibre-angle model: f = cos(theta) e_circ + sin(theta) e_long, G = s_t I + (s_l - s_t) f f^T.
-// Vector model (vec): the field is V = vmean + (theta_0, theta_1, theta_2) per element,
+// Fibre-angle model (model 0): f = cos(theta) e_circ + sin(theta) e_long,
+// G = s_t I + (s_l - s_t) f f^T.  Isotropic model (1): G = max(theta, s_t) I, s_t the lower
+// bound.  Vector model (2): the field is V = vmean + (theta_0, theta_1, theta_2) per element,
 // component c of sample b at theta[(c B + b) P + e], and G = g I + (|V| - g) V V^T / V^T V
 // (eq. (AdmV) with g = sigma_t).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tet_assemble(TetDev t, const T* __restrict__ theta, T* __restrict__ kval,
-                                                         double sigma_t, double dsig, int vec, int32_t B,
+                                                         double sigma_t, double dsig, int model, int32_t B,
                                                          const double* __restrict__ vmean) {
   const int sb = blockIdx.y;
   const int64_t nz = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -50,7 +51,10 @@ __global__ __launch_bounds__(kBlock) void k_tet_assemble(TetDev t, const T* __re
     const double ga0 = G[3 * a], ga1 = G[3 * a + 1], ga2 = G[3 * a + 2];
     const double gb0 = G[3 * b], gb1 = G[3 * b + 1], gb2 = G[3 * b + 2];
     const double gg = ga0 * gb0 + ga1 * gb1 + ga2 * gb2;
-    if (vec) {
+    if (model == 1) {
+      const double v = (double)th[e];
+      acc += G[18] * (v > sigma_t ? v : sigma_t) * gg;
+    } else if (model == 2) {
       const double v0 = vmean[3 * e] + (double)th[e], v1 = vmean[3 * e + 1] + (double)th[cstride + e];
       const double v2 = vmean[3 * e + 2] + (double)th[2 * cstride + e];
       const double vv = v0 * v0 + v1 * v1 + v2 * v2;
@@ -216,10 +220,10 @@ void launch_tet_assemble(const TetDev& t, const void* theta, void* kval, int32_t
   const dim3 grid((unsigned)cdiv(t.nell, kBlock), B);
   if (mixed)
     hipLaunchKernelGGL((k_tet_assemble<float>), grid, dim3(kBlock), 0, s, t, (const float*)theta, (float*)kval,
-                       sigma_t, dsig, t.vec, B, t.vmean);
+                       sigma_t, dsig, t.model, B, t.vmean);
   else
     hipLaunchKernelGGL((k_tet_assemble<double>), grid, dim3(kBlock), 0, s, t, (const double*)theta, (double*)kval,
-                       sigma_t, dsig, t.vec, B, t.vmean);
+                       sigma_t, dsig, t.model, B, t.vmean);
 }
 
 void launch_tet_apply(const TetDev& t, const void* kval, const void* x, const void* d, void* y, double ck, int32_t B,

@@ -91,6 +91,9 @@ class ConfigRunner:
                 if self.vector:  # E[V] = sigma_l f0 with the rule-based fibre f0
                     th = mesh["theta0"][:, None]
                     v_mean = self.phys["sigma_l"] * (np.cos(th) * mesh["e_circ"] + np.sin(th) * mesh["e_long"])
+                elif self.iso:  # the field is v = E[V] + W
+                    theta0 = torch.full((mesh["tets"].shape[0],), float(kcfg["mean"]), dtype=torch.float64,
+                                        device=device)
                 else:
                     theta0 = torch.as_tensor(mesh["theta0"], dtype=torch.float64, device=device)
             else:

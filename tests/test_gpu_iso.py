@@ -151,17 +151,39 @@ def test_c2i_pipeline_small_matches_oracle(env):
     assert abs(res["estimate"] - est) <= 1e-10 * abs(est)
 
 
-def test_iso_model_rejected_on_tetrahedra(env):
+@pytest.mark.parametrize("mixed", [False, True])
+def test_iso_model_on_tetrahedra_matches_assembled_jacobian(env, mixed):
+    """The isotropic model on a shell (the idealised-ventricle analogue): G = max(v, sigma_t) I
+    per tetrahedron, with part of the field below the floor."""
     torch, mlq = env
+    from oracle import fem
+    from oracle.tetfem import TetMesh
     from workloads import tetshell
-    xyz, tets, ec, el, _ = tetshell.shell_mesh((2, 6, 12), seed=5)
-    lvl = dict(kind="tet", dim=3, n_steps=8, mesh=dict(xyz=xyz, tets=tets, e_circ=ec, e_long=el))
+    xyz, tets, ec, el, _ = tetshell.shell_mesh((3, 8, 16), seed=5)
+    mesh_d = dict(xyz=xyz, tets=tets, e_circ=ec, e_long=el)
     phys = W.physics(3)
     c, r = tetshell.stimulus_ball(0.3)
-    phys.update(stim_center=c.tolist(), stim_radius=float(r))
-    desc, keep = mlq.make_desc(lvl, phys, diffusion=mlq.MLQ_DIFF_ISO)
-    with pytest.raises(mlq.MlqError):
-        mlq.Level(desc, keep)
+    phys.update(stim_center=c.tolist(), stim_radius=float(r), sigma_t=0.1 * 3.325e-3)
+    steps, B = 16, 2
+    desc, keep = mlq.make_desc(dict(kind="tet", dim=3, n_steps=steps, mesh=mesh_d), phys,
+                               prec=mlq.MLQ_MIXED if mixed else mlq.MLQ_FP64, max_batch=B, diffusion=mlq.MLQ_DIFF_ISO)
+    lv = mlq.Level(desc, keep)
+    mesh = TetMesh(xyz, tets)
+    dt = phys["t_end"] / steps
+    v = _positive_field(41, B, mesh.n_elems, amp=1.5)
+    assert (v < phys["sigma_t"]).any()
+    x = W.random_nodal(42, B, mesh.n_nodes)
+    dv = W.random_nodal(43, B, mesh.n_nodes, -0.05, 0.14)
+    tdt = torch.float32 if mixed else torch.float64
+    v_d, x_d, d_d = (torch.as_tensor(a, dtype=tdt, device="cuda") for a in (v, x, dv))
+    y = lv.apply(v_d, x_d, d_d).double().cpu().numpy()
+    for b in range(B):
+        vb, xb, db = (a[b].double().cpu().numpy() for a in (v_d, x_d, d_d))
+        M, K = mesh.assemble(fem.conductivity_iso(vb, 3, phys["sigma_t"]))
+        ref = M @ ((1.0 + db) * xb) + 0.5 * dt * (K @ xb)
+        scale = abs(M) @ np.abs((1.0 + db) * xb) + 0.5 * dt * (abs(K) @ np.abs(xb))
+        tol = (2e-6 if mixed else 1e-13) * scale.max()
+        assert np.abs(y[b] - ref).max() <= tol, (b, np.abs(y[b] - ref).max() / scale.max())
 
 
 @pytest.mark.parametrize("n", [[7, 6, 5], [9, 8, 1]])
