@@ -466,6 +466,7 @@ def main():
                            gmres_per_step=round(runner.level_inner[l] / runner.level_sample_steps[l], 2))
                       for l in range(len(runner.levels))]
     line["newton_guess"] = args.newton_guess
+    line["lanes_x"] = [getattr(L, "lanes_x", None) for L in runner.levels]
     line["inner_tol"] = runner.levels[-1].desc.inner_tol
     if breakdown:
         line["breakdown"] = breakdown

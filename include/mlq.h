@@ -211,6 +211,14 @@ typedef struct {
   double* probe_sum;
 } mlq_field_out;
 
+/* Lane layout of the 3D box kernels (a tuning knob): lanes_x = 8 (waves of 8 x 8 lanes, each
+ * owning 7 x 7 nodes per plane) or 16 (16 x 4 lanes, 15 x 3 nodes, full 128-byte rows in FP64),
+ * 0 = chosen by the grid width (16 from 48 nodes along x).  The operators give the same
+ * results in every layout; the Gram-Schmidt projections fused into the apply are summed over
+ * other partitions, so solves agree within rounding.  The workspace size depends on it: query
+ * mlq_workspace_bytes after a change.  MLQ_EINVAL for other values or levels. */
+mlq_status mlq_set_lane_layout(mlq_level* level, int32_t lanes_x);
+
 /* Reference space-time solution for the Newton guesses MLQ_GUESS_REFERENCE(_LOCAL): ref_dev
  * is (n_steps + 1) x n FP64 on the device, e.g. the u_sum of a one-sample solve of the
  * unperturbed field; the level keeps the pointer (the caller keeps the memory alive while it

@@ -395,6 +395,7 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   }
   g.tet = tet ? 1 : 0;
   g.nnz = tet ? th.nell : 0;
+  g.lx = 0;
   if (tet) g.nx = g.ny = g.nz = 0;
   lv->io = Ionic{desc->alpha, desc->u_rest, desc->u_th, desc->u_peak, desc->t_end / desc->n_steps};
 
@@ -849,6 +850,14 @@ mlq_status mlq_solve_batch(mlq_level* level, const void* theta_dev, int32_t batc
   if (level == nullptr) return fail(MLQ_EINVAL, "level is NULL");
   return solve_impl(level, theta_dev, batch, level->d.n_steps, ws_dev, ws_bytes, qoi_dev, status_dev, iters_dev,
                     nullptr, nullptr, nullptr, hip_stream);
+}
+
+mlq_status mlq_set_lane_layout(mlq_level* level, int32_t lanes_x) {
+  if (level == nullptr) return fail(MLQ_EINVAL, "level is NULL");
+  if (lanes_x != 0 && lanes_x != 8 && lanes_x != 16) return fail(MLQ_EINVAL, "lanes_x must be 0, 8 or 16");
+  if (level->tet || level->geo.dim != 3) return fail(MLQ_EINVAL, "the lane layout applies to 3D box levels");
+  level->geo.lx = lanes_x;
+  return MLQ_OK;
 }
 
 mlq_status mlq_set_reference(mlq_level* level, const double* ref_dev) {

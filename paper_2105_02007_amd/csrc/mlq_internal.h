@@ -31,6 +31,7 @@ struct Geo {
   double cx0, cx1, cy0, cy1, cz0, cz1;
   int32_t tet;         // 1: P1 tetrahedra (TetDev holds the mesh), 0: Q1 box
   int64_t nnz;         // tetrahedra: stored (padded, slot-major) entries of the vertex adjacency
+  int32_t lx;          // 3D boxes: lanes along x of a wave (8 or 16), 0 = chosen by the grid width
 };
 
 // P1 tetrahedral level data on the device (inside the level blob).  The sparsity

@@ -136,9 +136,10 @@ struct Args {
 // Lane layouts of a wave: LX lanes along x times 64 / LX along y.  With 16 lanes along x
 // every load of a plane reads rows of 16 consecutive nodes (one 128-byte line in FP64)
 // instead of 8; it owns 15 x 3 nodes instead of 7 x 7 and wastes more of a small grid
-// on partial tiles, so grids narrower than kWideMinNx nodes use the 8 x 8 layout.
+// on partial tiles, so by default grids narrower than kWideMinNx nodes use the 8 x 8
+// layout.  A level may fix the layout instead (g.lx, set by timing both).
 constexpr int kWideMinNx = 48;
-inline int wave_lx(const Geo& g) { return g.nx >= kWideMinNx ? 16 : 8; }
+inline int wave_lx(const Geo& g) { return g.lx != 0 ? g.lx : (g.nx >= kWideMinNx ? 16 : 8); }
 constexpr int WZ = 11;  // owned node planes per wave (WZ + 1 steps)
 
 // steps between issuing a slab's loads and using them

@@ -27,7 +27,7 @@ class ConfigRunner:
 
     def __init__(self, cfg: dict, prec: int | None = None, device="cuda", newton_tol=None, inner_tol=None,
                  max_inner=30, kl_rank_factor=2, kl_eps=1e-2, log=None, concurrent=True,
-                 newton_guess=mlq.MLQ_GUESS_EXTRAPOLATE):
+                 newton_guess=mlq.MLQ_GUESS_EXTRAPOLATE, tune_layout=True):
         say = log if log is not None else (lambda m: None)
         self.cfg = cfg
         self.device = device
@@ -110,6 +110,10 @@ class ConfigRunner:
                            else mlq.MLQ_DIFF_FIBRE), v_mean=v_mean)
             L = mlq.Level(desc, keep, device=device)
             L._keep = None  # arrays were copied into the level blob
+            if tune_layout and not self.tet and cfg["dim"] == 3:
+                # the faster lane layout of the 3D kernels for this grid and batch, by timing
+                t = L.tune_lane_layout()
+                say(f"level {l}: lane layout {L.lanes_x} (apply ms: 8 lanes {t[8]:.3f}, 16 lanes {t[16]:.3f})")
             if newton_guess in (mlq.MLQ_GUESS_REFERENCE, mlq.MLQ_GUESS_REFERENCE_LOCAL):
                 # the unperturbed reference solution (all coordinates zero: theta = its mean)
                 Y0 = torch.zeros((M * self.components, 1), dtype=torch.float64, device=device)

@@ -28,6 +28,7 @@ EXPORTED = [
     "mlq_kl_workspace_bytes", "mlq_kl_modes", "mlq_kl_transfer", "mlq_timing_enable", "mlq_timing_read",
     "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet", "mlq_solve_batch_fields", "mlq_probe_weights",
     "mlq_transfer_add", "mlq_field_norm2", "mlq_set_reference", "mlq_tet_locate", "mlq_transfer_add_weighted",
+    "mlq_set_lane_layout",
 ]
 MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE, MLQ_GUESS_REFERENCE, MLQ_GUESS_REFERENCE_LOCAL = 0, 1, 2, 3
 MLQ_DIFF_FIBRE, MLQ_DIFF_ISO, MLQ_DIFF_VECTOR = 0, 1, 2
@@ -109,6 +110,7 @@ def _load():
         "mlq_transfer_add": [VP, VP, I32, I32, I64, C.c_double, VP, VP, VP],
         "mlq_field_norm2": [VP, I32, I32, I64, VP, VP, VP, VP],
         "mlq_set_reference": [VP, VP],
+        "mlq_set_lane_layout": [VP, I32],
         "mlq_tet_locate": [VP, I64, VP, I64, VP, I64, VP, VP],
         "mlq_transfer_add_weighted": [VP, VP, I32, I64, I32, VP, VP, C.c_double, VP, VP, VP],
         "mlq_cbc": [I64, I32, VP, VP],
@@ -332,6 +334,35 @@ class Level:
         if code not in (MLQ_OK, MLQ_ENOCONV):
             check(code)
         return dict(qoi=qoi, status=status, iters=iters, probe=probe, code=code)
+
+    def set_lane_layout(self, lanes_x):
+        """Lanes along x of the 3D box kernels' waves: 8, 16, or 0 (by grid width)."""
+        check(lib.mlq_set_lane_layout(self.handle, int(lanes_x)))
+        self.lanes_x = int(lanes_x)
+
+    def tune_lane_layout(self, batch=None, reps=3):
+        """Times the operator apply of this level at `batch` samples (default: the level's
+        largest batch) in both lane layouts and keeps the faster.  Returns {lanes_x: ms}."""
+        import torch
+        B = int(batch or self.desc.max_batch)
+        tdt = torch.float32 if self.mixed else torch.float64
+        theta = torch.zeros((B, self.n_elems), dtype=tdt, device=self.device)
+        x = torch.ones((B, self.n_nodes), dtype=tdt, device=self.device)
+        d = torch.zeros_like(x)
+        y = torch.empty_like(x)
+        times = {}
+        for lx in (8, 16):
+            self.set_lane_layout(lx)
+            self.apply(theta, x, d, y)  # warm-up (and workspace size for this layout)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                self.apply(theta, x, d, y)
+            e1.record()
+            torch.cuda.synchronize()
+            times[lx] = e0.elapsed_time(e1) / reps
+        self.set_lane_layout(min(times, key=times.get))
+        return times
 
     def set_reference(self, ref):
         """Reference space-time solution ((n_steps + 1) x n device FP64) for the reference

@@ -320,3 +320,48 @@ def test_kl_truncated_and_transfer_match_oracle(env):
         phi = mlq.kl_transfer(kd, psi_d, lv).cpu().numpy()
         ref = kl.level_basis(fine, psi_ref, coarse)
         assert np.abs(phi - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,mixed", [([9, 9, 9], False), ([23, 11, 7], True), ([50, 13, 6], False)])
+def test_lane_layouts_give_identical_operators(env, n, mixed):
+    """The operator apply is bitwise the same in both lane layouts of the 3D kernels (each node
+    sums its element contributions in one fixed order), and the tuner keeps one of them."""
+    torch, mlq = env
+    phys = W.physics(3)
+    lv = dict(dim=3, n=n, lo=[0.0] * 3, hi=[1.0, 0.8, 0.6], n_steps=16)
+    B = 3
+    desc, keep = mlq.make_desc(lv, phys, prec=mlq.MLQ_MIXED if mixed else mlq.MLQ_FP64, max_batch=B)
+    level = mlq.Level(desc, keep)
+    P = int(np.prod([a - 1 for a in n]))
+    tdt = torch.float32 if mixed else torch.float64
+    th = torch.as_tensor(W.random_angles(5, B, P), dtype=tdt, device="cuda")
+    x = torch.as_tensor(W.random_nodal(6, B, level.n_nodes), dtype=tdt, device="cuda")
+    d = torch.as_tensor(W.random_nodal(7, B, level.n_nodes, -0.05, 0.14), dtype=tdt, device="cuda")
+    ys = []
+    for lx in (8, 16):
+        level.set_lane_layout(lx)
+        ys.append(level.apply(th, x, d).cpu().numpy())
+    assert np.array_equal(ys[0], ys[1])
+    times = level.tune_lane_layout()
+    assert set(times) == {8, 16} and level.lanes_x in (8, 16)
+    assert np.array_equal(level.apply(th, x, d).cpu().numpy(), ys[0])
+    with pytest.raises(mlq.MlqError):
+        level.set_lane_layout(32)
+
+
+def test_lane_layout_solves_agree(env):
+    """A solve in either layout agrees within the stopping test (the fused projections are
+    summed over other partitions)."""
+    torch, mlq = env
+    phys = W.physics(3)
+    lv = dict(dim=3, n=[17, 17, 17], lo=[0.0] * 3, hi=[1.0] * 3, n_steps=16)
+    desc, keep = mlq.make_desc(lv, phys, qoi=mlq.MLQ_QOI_MEAN_ACT_TIME, max_batch=2)
+    level = mlq.Level(desc, keep)
+    th = torch.as_tensor(W.random_angles(9, 2, 16 ** 3), device="cuda")
+    q = []
+    for lx in (8, 16):
+        level.set_lane_layout(lx)
+        out = level.solve(th, want_state=True)
+        q.append((out["qoi"].cpu().numpy(), out["u"].cpu().numpy()))
+    assert np.abs(q[0][0] - q[1][0]).max() <= 1e-10 * np.abs(q[0][0]).max()
+    assert np.abs(q[0][1] - q[1][1]).max() <= 1e-10 * np.abs(q[0][1]).max()
