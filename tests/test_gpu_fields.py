@@ -197,3 +197,33 @@ def test_field_norms_match_oracle(env, n, hi, m):
         assert np.allclose(got, ref, rtol=1e-12, atol=0), (q, got, ref)
         got = mlq.field_norm2(L, Sd, q=q, space=False, rows=5).cpu().numpy()
         assert np.allclose(got, fields.time_norm2(S, T, q), rtol=1e-13, atol=0)
+
+
+def test_streamed_fields_2d_match_oracle(env):
+    """The field outputs on a 2D box (the fibre-angle model of the 2D workload): u_sum, the
+    activation map and a bilinear probe, against the oracle."""
+    torch, mlq = env
+    from oracle import fem, fields, stepper
+    from oracle.mesh import BoxMesh
+    n, steps, B = [13, 9], 10, 2
+    phys = W.physics(2)
+    lv = dict(dim=2, n=n, lo=[0.0, 0.0], hi=[0.3, 0.2], n_steps=steps)
+    desc, keep = mlq.make_desc(lv, phys, qoi=mlq.MLQ_QOI_MEAN_ACT_TIME, max_batch=B)
+    L = mlq.Level(desc, keep)
+    mesh = BoxMesh(n, hi=lv["hi"])
+    th = W.random_angles(12, B, mesh.n_elems)
+    pts = np.array([[0.11, 0.07], [0.3, 0.2]])
+    node, w = L.probe_weights(pts)
+    assert (w[:, 4:] == 0).all() and np.allclose(w.sum(axis=1), 1.0)
+    u_sum = torch.zeros((steps + 1, mesh.n_nodes), dtype=torch.float64, device="cuda")
+    a_sum = torch.zeros(mesh.n_nodes, dtype=torch.float64, device="cuda")
+    out = L.solve_fields(torch.as_tensor(th, device="cuda"), u_sum=u_sum, act_sum=a_sum, probe_node=node, probe_w=w)
+    assert out["code"] == mlq.MLQ_OK
+    refs = [stepper.solve(mesh, fem.conductivity_from_angle(th[b], 2, phys["sigma_l"], phys["sigma_t"]), phys, steps,
+                          tol=1e-13, keep_all=True) for b in range(B)]
+    H = sum(fields.space_time_field(r) for r in refs)
+    assert np.abs(u_sum.cpu().numpy() - H).max() <= 1e-10 * np.abs(H).max()
+    A = sum(fields.activation_map(r) for r in refs)
+    assert np.abs(a_sum.cpu().numpy() - A).max() <= 1e-8 * B * phys["t_end"]
+    P = np.stack([fields.action_potential(mesh, r, pts) for r in refs])
+    assert np.abs(out["probe"].cpu().numpy() - P).max() <= 1e-10 * np.abs(P).max()
