@@ -124,3 +124,21 @@ def test_tet_locate_matches_oracle(mlq):
     got = (w * vals[node]).sum(axis=1)
     ref = TetMesh(xyz_c, tets_c).interpolate(vals, xyz_f)
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(vals).max()
+
+
+def test_estimator_edge_cases(mlq):
+    """A level with one sample contributes no variance (as the oracle's estimator); a level
+    without samples, non-nested combination point sets and a multi-level MC call are refused."""
+    from oracle import estimators as E
+    rng = np.random.default_rng(8)
+    ff = [rng.normal(size=5), rng.normal(size=1)]
+    fc = [None, rng.normal(size=1)]
+    r = mlq.estimate(mlq.MLQ_EST_MLMC, ff, fc)
+    est, rmse, _, vars_ = E.standard_ml([list(a) for a in ff], [None, list(fc[1])])
+    assert np.isclose(r["estimate"], est, rtol=1e-14) and np.isclose(r["rmse"], rmse, rtol=1e-13)
+    assert vars_[1] == 0.0 and r["level_var"][1] == 0.0
+    for args in ((mlq.MLQ_EST_MLMC, [np.zeros(0)], None), (mlq.MLQ_EST_MC, [np.ones(3), np.ones(3)], None)):
+        with pytest.raises(mlq.MlqError):
+            mlq.estimate(*args)
+    with pytest.raises(mlq.MlqError):
+        mlq.estimate(mlq.MLQ_EST_COMBINATION, [np.ones(4), np.ones(2)], None, n_per_level=[4, 2])
