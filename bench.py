@@ -87,9 +87,8 @@ WORKLOAD_TEXT = {
           "(l = 0.1 long axis), rule-based +60/-60 deg fibres, combination estimator 16/64/256 nested MC points, "
           "mean activation time",
     "c5i": "the c5 shells with the paper's idealised-ventricle model: isotropic G = max(v, 0.1 E[V]) I, "
-           "v = E[V] + W, W a squared-exponential KL field (0.3 E[V], sigma_KL = 0.5 x 2^2 for the shell's "
-           "size) with 87 uniform coordinates, combination estimator 16/64/256 nested MC points, mean "
-           "activation time",
+           "v = E[V] + W, W a squared-exponential KL field (0.3 E[V], sigma_KL = 0.5) with 87 uniform "
+           "coordinates, combination estimator 16/64/256 nested MC points, mean activation time",
     "c5v": "the c5 shells with the paper's heart model: eq. (AdmV) with a random vector field V = sigma_l f0 + W, "
            "W three independent squared-exponential KL fields (0.3 sigma_l, sigma_KL = 0.64), 3 x 45 uniform "
            "coordinates, combination estimator 16/64/256 nested MC points, mean activation time",

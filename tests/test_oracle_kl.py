@@ -141,7 +141,7 @@ def test_squared_exponential_kernel_is_separable_on_tensor_grids():
 
 def test_cube_stochastic_dimension_matches_the_paper():
     """Section 5.1 reports M = 66 for the cube (squared-exponential kernel with sigma_KL = 0.25,
-    truncation error 1e-2 in the pivoted Cholesky decomposition).  The oracle's factorisation
+    truncation error 1e-2 in the pivoted Cholesky decomposition; tests/golden/paper_parameters.txt).  The oracle's factorisation
     stops within one of it on the cube grids: at 65 with the nodal trace, at 66 with the
     mass-weighted (L2) trace on 17^3 nodes.  Other readings of the kernel are far off: sigma_KL
     as a length (exp(-|x - y|^2 / 0.25^2)) or the exponential kernel need well over 100."""

@@ -142,13 +142,13 @@ CONFIGS = {
         qoi=QOI_MEAN_ACT_TIME, prec=PREC_MIXED, seed=6),
     # the paper's idealised-ventricle model (Section 5.1) on the c5 shells: isotropic G = v I,
     # v = E[V] (1 + W) with W squared-exponential, theta = 0.3 relative to E[V] = 3.325e-3,
-    # sigma_KL = 0.5 scaled to the shell (lengths x 2), 87 uniform coordinates, bounded below
-    # by 0.1 E[V]
+    # sigma_KL = 0.5 (the ventricle's bounding box, about 2 x 2.5 x 2, matches the shell's size),
+    # 87 uniform coordinates, bounded below by 0.1 E[V]
     "c5i": dict(
         name="c5i", title="non-nested shells with the paper's ventricle model: isotropic random diffusion, "
                           "87 uniform coordinates, combination estimator",
         dim=3, levels=_tet_levels([(4, 40, 128), (8, 80, 256), (16, 160, 512)], [512, 512, 512], 5),
-        kl=dict(n_modes=87, corr_len=0.5 * (tetshell.LONG_AXIS / 1.0) ** 2, std=0.3, grid_level=2,
+        kl=dict(n_modes=87, corr_len=0.5, std=0.3, grid_level=2,
                 kernel="sqexp", variables="uniform", mean=SIGMA_L, floor=0.1),
         model="iso",
         sampling=dict(kind="combination", n_per_level=[16, 64, 256]),
