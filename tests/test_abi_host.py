@@ -142,3 +142,34 @@ def test_estimator_edge_cases(mlq):
             mlq.estimate(*args)
     with pytest.raises(mlq.MlqError):
         mlq.estimate(mlq.MLQ_EST_COMBINATION, [np.ones(4), np.ones(2)], None, n_per_level=[4, 2])
+
+
+def test_header_is_plain_c_and_the_library_links_from_c(mlq, tmp_path):
+    """include/mlq.h compiles as C99 and a C program linked against libmlq.so calls the host-only
+    entry points: the CBC construction (against the oracle) and an argument check."""
+    import shutil
+    import subprocess
+    from oracle import qmc
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use_mlq.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include "mlq.h"
+int main(void) {
+  double gamma[3] = {1.0, 0.5, 0.25};
+  int64_t z[3];
+  if (mlq_cbc(31, 3, gamma, z) != MLQ_OK) return 1;
+  printf("%lld %lld %lld\n", (long long)z[0], (long long)z[1], (long long)z[2]);
+  double y[4];
+  printf("%d\n", (int)mlq_halton(0, 1, 2, NULL, MLQ_MAP_UNIFORM, y, NULL));
+  return 0;
+}
+''')
+    libdir = os.path.join(ROOT, "paper_2105_02007_amd")
+    exe = tmp_path / "use_mlq"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-L", libdir, "-lmlq", "-Wl,-rpath," + libdir, "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    assert [int(v) for v in out[0].split()] == list(qmc.cbc(31, 3, [1.0, 0.5, 0.25]))
+    assert int(out[1]) == mlq.MLQ_EINVAL
