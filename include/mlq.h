@@ -320,6 +320,13 @@ typedef enum { MLQ_MAP_NORMAL = 0, MLQ_MAP_UNIFORM = 1 } mlq_coordinate_map;
 mlq_status mlq_halton(int32_t s, int64_t first, int32_t count, const double* shift_dev, int32_t map, double* Y_dev,
                       void* hip_stream);
 
+/* The same shifted lattice points in either coordinate map (mlq_coordinate_map, declared with
+ * mlq_halton): MLQ_MAP_NORMAL as mlq_lattice_normals, MLQ_MAP_UNIFORM y = 2x - 1, the uniform
+ * coordinates on [-1, 1] of the paper's parametrisation (Section 4).  Same arguments, layout and
+ * errors as mlq_lattice_normals otherwise.  Enqueues only. */
+mlq_status mlq_lattice_points(const int64_t* z_dev, const double* shift_dev, int32_t s, int64_t N, int64_t first,
+                              int32_t count, int32_t map, double* Y_dev, void* hip_stream);
+
 /* Component-by-component generating vector of an N-point rank-1 lattice in s
  * dimensions, product weights gamma (s), minimising the shift-averaged
  * worst-case error of the unanchored Sobolev space.  Host only. */

@@ -83,6 +83,11 @@ def lattice_normals(z, N, shift):
     return np.ascontiguousarray(to_normal(lattice_points(z, N, shift)).T)
 
 
+def lattice_uniforms(z, N, shift):
+    """Uniform coordinates y = 2x - 1 on [-1, 1] (s, N) of a shifted lattice rule."""
+    return np.ascontiguousarray((2.0 * lattice_points(z, N, shift) - 1.0).T)
+
+
 def first_primes(n):
     """The first n primes, by trial division against the primes found so far."""
     ps = []

@@ -1048,7 +1048,19 @@ mlq_status mlq_lattice_normals(const int64_t* z_dev, const double* shift_dev, in
   if (s < 1 || N < 1 || first < 0 || count < 0 || N > (int64_t(1) << 31))
     return fail(MLQ_EINVAL, "invalid lattice size");
   if (count == 0) return MLQ_OK;
-  launch_lattice(z_dev, shift_dev, s, N, first, count, Y_dev, (hipStream_t)hip_stream);
+  launch_lattice(z_dev, shift_dev, s, N, first, count, false, Y_dev, (hipStream_t)hip_stream);
+  HIP_OK(hipGetLastError());
+  return MLQ_OK;
+}
+
+mlq_status mlq_lattice_points(const int64_t* z_dev, const double* shift_dev, int32_t s, int64_t N, int64_t first,
+                              int32_t count, int32_t map, double* Y_dev, void* hip_stream) {
+  if (z_dev == nullptr || shift_dev == nullptr || Y_dev == nullptr) return fail(MLQ_EINVAL, "NULL argument");
+  if (map != MLQ_MAP_NORMAL && map != MLQ_MAP_UNIFORM) return fail(MLQ_EINVAL, "unknown coordinate map");
+  if (s < 1 || N < 1 || first < 0 || count < 0 || N > (int64_t(1) << 31))
+    return fail(MLQ_EINVAL, "invalid lattice size");
+  if (count == 0) return MLQ_OK;
+  launch_lattice(z_dev, shift_dev, s, N, first, count, map == MLQ_MAP_UNIFORM, Y_dev, (hipStream_t)hip_stream);
   HIP_OK(hipGetLastError());
   return MLQ_OK;
 }

@@ -153,8 +153,8 @@ void launch_apply_public(const Geo& g, const void* coef, const void* x, const vo
 void launch_kl(const double* phi64T, const float* phi32T, const double* sqrt_lambda, const double* theta0,
                const double* Y, int64_t P, int32_t M, int32_t B, void* theta, bool mixed, hipStream_t s);
 void launch_transpose_f64(const double* src, double* dst, int64_t rows, int64_t cols, hipStream_t s);
-void launch_lattice(const int64_t* z, const double* shift, int32_t sdim, int64_t N, int64_t first,
-                    int32_t count, double* Y, hipStream_t s);
+void launch_lattice(const int64_t* z, const double* shift, int32_t sdim, int64_t N, int64_t first, int32_t count,
+                    bool uniform, double* Y, hipStream_t s);
 // Field quantities of interest: probe table (passed by value as a kernel argument) and the
 // geometry of a space-time transfer (spatial node counts per axis, time node counts, steps).
 constexpr int kMaxProbes = 16;

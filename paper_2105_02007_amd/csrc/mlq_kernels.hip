@@ -851,8 +851,9 @@ void launch_transpose_f64(const double* src, double* dst, int64_t rows, int64_t 
 
 // ---------------------------------------------------------------------------
 // Shifted rank-1 lattice points mapped to N(0,1): y = Phi^-1(frac(((i z) mod N)/N + shift)).
+// uniform != 0: y = 2x - 1 (the uniform coordinates on [-1, 1]) instead of Phi^-1(x).
 __global__ void k_lattice(const int64_t* __restrict__ z, const double* __restrict__ shift, int32_t sdim, int64_t N,
-                          int64_t first, int32_t count, double* __restrict__ Y) {
+                          int64_t first, int32_t count, int uniform, double* __restrict__ Y) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)sdim * count) return;
   const int k = (int)(t % sdim);
@@ -860,16 +861,20 @@ __global__ void k_lattice(const int64_t* __restrict__ z, const double* __restric
   const int64_t r = (i % N) * (z[k] % N) % N;
   double x = (double)r / (double)N + shift[k];
   if (x >= 1.0) x -= 1.0;
+  if (uniform) {
+    Y[t] = 2.0 * x - 1.0;
+    return;
+  }
   const double eps = 1.1102230246251565e-16;  // 2^-53
   x = x < eps ? eps : (x > 1.0 - eps ? 1.0 - eps : x);
   Y[t] = normcdfinv(x);
 }
 
 void launch_lattice(const int64_t* z, const double* shift, int32_t sdim, int64_t N, int64_t first, int32_t count,
-                    double* Y, hipStream_t s) {
+                    bool uniform, double* Y, hipStream_t s) {
   const int64_t total = (int64_t)sdim * count;
   hipLaunchKernelGGL(k_lattice, dim3((unsigned)cdiv(total, kBlock)), dim3(kBlock), 0, s, z, shift, sdim, N, first,
-                     count, Y);
+                     count, uniform ? 1 : 0, Y);
 }
 
 // ---------------------------------------------------------------------------

@@ -415,11 +415,11 @@ class ConfigRunner:
             cols = [mlq.halton(M, 1, N, shifts[s], uniform=self.uniform, device=self.device)
                     for s in range(shifts.shape[0])]
             return torch.cat(cols, dim=1)
-        if self.uniform or self.components > 1:
-            raise ValueError("the lattice rule here maps to Gaussian coordinates of one field")
-        gamma = self.lam / self.lam[0]
+        # product weights from the KL eigenvalues, repeated for every component of a vector field
+        gamma = np.tile(self.lam / self.lam[0], M // len(self.lam))
         z = mlq.cbc(N, M, gamma)
-        cols = [mlq.lattice_normals(z, shifts[s], N, 0, N, device=self.device) for s in range(shifts.shape[0])]
+        cols = [mlq.lattice_points(z, shifts[s], N, 0, N, uniform=self.uniform, device=self.device)
+                for s in range(shifts.shape[0])]
         return torch.cat(cols, dim=1)
 
     def run_mlqmc(self, shifts_per_level, levels=None):

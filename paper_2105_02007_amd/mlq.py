@@ -28,7 +28,7 @@ EXPORTED = [
     "mlq_kl_workspace_bytes", "mlq_kl_modes", "mlq_kl_transfer", "mlq_timing_enable", "mlq_timing_read",
     "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet", "mlq_solve_batch_fields", "mlq_probe_weights",
     "mlq_transfer_add", "mlq_field_norm2", "mlq_set_reference", "mlq_tet_locate", "mlq_transfer_add_weighted",
-    "mlq_set_lane_layout",
+    "mlq_set_lane_layout", "mlq_lattice_points",
 ]
 MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE, MLQ_GUESS_REFERENCE, MLQ_GUESS_REFERENCE_LOCAL = 0, 1, 2, 3
 MLQ_DIFF_FIBRE, MLQ_DIFF_ISO, MLQ_DIFF_VECTOR = 0, 1, 2
@@ -111,6 +111,7 @@ def _load():
         "mlq_field_norm2": [VP, I32, I32, I64, VP, VP, VP, VP],
         "mlq_set_reference": [VP, VP],
         "mlq_set_lane_layout": [VP, I32],
+        "mlq_lattice_points": [VP, VP, I32, I64, I64, I32, I32, VP, VP],
         "mlq_tet_locate": [VP, I64, VP, I64, VP, I64, VP, VP],
         "mlq_transfer_add_weighted": [VP, VP, I32, I64, I32, VP, VP, C.c_double, VP, VP, VP],
         "mlq_cbc": [I64, I32, VP, VP],
@@ -450,6 +451,18 @@ def lattice_normals(z, shift, N, first, count, device="cuda"):
     s = zd.numel()
     Y = torch.empty((count, s), dtype=torch.float64, device=device)  # column-major s x count
     check(lib.mlq_lattice_normals(_ptr(zd), _ptr(sd), int(s), int(N), int(first), int(count), _ptr(Y), _stream()))
+    return Y.t()
+
+
+def lattice_points(z, shift, N, first, count, uniform=True, device="cuda"):
+    """(s, count) FP64 device tensor of shifted-lattice coordinates, uniform on [-1, 1] or Gaussian."""
+    import torch
+    zd = torch.as_tensor(np.asarray(z, dtype=np.int64), device=device)
+    sd = torch.as_tensor(np.asarray(shift, dtype=np.float64), device=device)
+    s = zd.numel()
+    Y = torch.empty((count, s), dtype=torch.float64, device=device)  # column-major s x count
+    check(lib.mlq_lattice_points(_ptr(zd), _ptr(sd), int(s), int(N), int(first), int(count),
+                                 MLQ_MAP_UNIFORM if uniform else MLQ_MAP_NORMAL, _ptr(Y), _stream()))
     return Y.t()
 
 

@@ -84,3 +84,31 @@ def test_c4i_pipeline_small_matches_oracle(env):
     est, rmse, _ = estimators.standard_mlqmc(ff, fc)
     assert abs(res["estimate"] - est) <= 1e-10 * abs(est)
     assert abs(res["rmse"] - rmse) <= 1e-9 * abs(est)
+
+
+def test_lattice_uniform_coordinates_match_oracle(env):
+    """Shifted lattice points in the uniform map y = 2x - 1 (bit-exact: the same exact fraction,
+    one rounded addition of the shift, an exact doubling and one rounded subtraction), and the
+    driver's QMC points of a uniform-coordinate workload with the lattice rule."""
+    torch, mlq = env
+    from oracle import qmc
+    from paper_2105_02007_amd.driver import ConfigRunner
+    N, s = 61, 12
+    gamma = 0.7 ** np.arange(s)
+    z = qmc.cbc(N, s, gamma)
+    shift = W.lattice_shifts(3, 0, 1, s)[0]
+    Y = mlq.lattice_points(z, shift, N, 0, N, uniform=True).cpu().numpy()
+    assert np.array_equal(Y, qmc.lattice_uniforms(z, N, shift))
+    Yn = mlq.lattice_points(z, shift, N, 0, N, uniform=False).cpu().numpy()
+    assert np.array_equal(Yn, mlq.lattice_normals(z, shift, N, 0, N).cpu().numpy())
+    cfg = W.scaled_config("c4i", nodes=[5, 9], steps=[4, 8], n_per_level=[8, 2], n_modes=5)
+    cfg["sampling"].update(rule="lattice", n_shifts=2)
+    cfg["prec"] = W.PREC_FP64
+    runner = ConfigRunner(cfg, prec=W.PREC_FP64)
+    shifts = W.lattice_shifts(cfg["seed"], 0, 2, 5)
+    P = runner.qmc_points(0, shifts).cpu().numpy()
+    zr = qmc.cbc(8, 5, runner.lam / runner.lam[0])
+    ref = np.concatenate([qmc.lattice_uniforms(zr, 8, shifts[k]) for k in range(2)], axis=1)
+    assert np.array_equal(P, ref)
+    res = runner.run_mlqmc([W.lattice_shifts(cfg["seed"], l, 2, 5) for l in range(2)])
+    assert np.isfinite(res["estimate"]) and res["rmse"] >= 0

@@ -103,3 +103,12 @@ def test_halton_shift_and_maps():
     Yn = qmc.halton_coordinates(5, 1, 40, sh, uniform=False)
     assert np.allclose(Yn, qmc.to_normal(Xs).T)
     assert np.array_equal(qmc.halton_points(5, 11, 7, sh), Xs[10:17])
+
+
+def test_lattice_uniform_map():
+    """The uniform map of a shifted lattice: 2x - 1 of the same points, in [-1, 1)."""
+    z, N = np.array([1, 5, 7]), 16
+    sh = np.array([0.1, 0.5, 0.9])
+    U = qmc.lattice_uniforms(z, N, sh)
+    assert np.array_equal(U, (2.0 * qmc.lattice_points(z, N, sh) - 1.0).T)
+    assert U.shape == (3, N) and np.all((U >= -1) & (U < 1))
