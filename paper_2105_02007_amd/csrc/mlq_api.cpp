@@ -724,13 +724,15 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
     timed(level, MLQ_K_RHS, nn * batch, s, [&] {
       if (tet)
         launch_tet_rhs(td, w, level->fbox, load, dt, batch, mixed, s);
-      else if (g.dim == 3)
-        launch_rhs3(g, w, level->fbox, load, dt, batch, mixed, s);
+      else if (g.dim == 3)  // also the extrapolated start and the previous step's activation
+        launch_rhs3(g, w, level->fbox, load, dt, batch, mixed, s, k > 0 ? w.ukm1 : nullptr,
+                    d.newton_guess == MLQ_GUESS_EXTRAPOLATE, d.u_th, (double)(k - 1) * dt);
       else
         launch_rhs(g, w, level->fbox, load, dt, batch, mixed, s);
     });
     // the rhs kernels start Newton from u = u_k; the extrapolated guess replaces it
-    if (d.newton_guess == MLQ_GUESS_EXTRAPOLATE && k > 0) launch_extrapolate(w, level->nn, batch, s);
+    const bool fused3 = g.dim == 3 && !tet;  // the 3D rhs kernel did the two steps below
+    if (d.newton_guess == MLQ_GUESS_EXTRAPOLATE && k > 0 && !fused3) launch_extrapolate(w, level->nn, batch, s);
     if ((d.newton_guess == MLQ_GUESS_REFERENCE || d.newton_guess == MLQ_GUESS_REFERENCE_LOCAL) &&
         level->ref != nullptr)
       launch_guess_reference(w, level->ref + (size_t)k * level->nn, level->ref + (size_t)(k + 1) * level->nn,
@@ -814,7 +816,8 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
         launch_update_zbasis(g, w, batch, mixed, s);
       });
     }
-    timed(level, MLQ_K_QOI, nn * batch, s, [&] { launch_activation(w, level->nn, batch, d.u_th, t0, dt, s); });
+    if (!fused3)
+      timed(level, MLQ_K_QOI, nn * batch, s, [&] { launch_activation(w, level->nn, batch, d.u_th, t0, dt, s); });
     // u_{k-1} <- u_k <- u (the old u_{k-1} becomes the next Newton iterate's storage)
     double* old = w.ukm1;
     w.ukm1 = w.uk;
@@ -822,6 +825,11 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
     w.u = old;
     stream_fields(k + 1);
   }
+  // 3D boxes: the last step's activation (the rhs kernel of each step recorded the one before)
+  if (g.dim == 3 && !tet && n_steps > 0)
+    timed(level, MLQ_K_QOI, nn * batch, s, [&] {
+      launch_activation_between(w.ukm1, w.uk, w.act, level->nn, batch, d.u_th, (double)(n_steps - 1) * dt, dt, s);
+    });
   if (act_sum != nullptr) launch_act_sum(w.act, batch, level->nn, (double)n_steps * dt, act_sum, s);
   launch_qoi(w, level->wts, level->nn, batch, d.qoi, (double)n_steps * dt, level->vol, qoi_dev, s);
   HIP_OK(hipMemcpyAsync(status_dev, w.status, sizeof(int32_t) * batch, hipMemcpyDeviceToDevice, s));

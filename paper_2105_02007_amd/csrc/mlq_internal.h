@@ -222,8 +222,14 @@ void launch_apply_pk3(const Geo& g, const Work& w, int j, double ck, int32_t B, 
 void launch_apply_full3(const Geo& g, const void* coef, const void* x, const void* d, void* y, double ck, int32_t B,
                         bool mixed, hipStream_t s);
 void launch_residual3(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);
+// 3D boxes: b = (M - dt/2 K) u_k + load F_box and the Newton start u := u_k; with uprev
+// (u_{k-1}, may be NULL) also the extrapolated start 2 u_k - u_{k-1} (extrap) and the activation
+// times of the step from t_prev = t_{k-1} to t_k (first crossing of u_th) into w.act.
 void launch_rhs3(const Geo& g, const Work& w, const double* fbox, double load_coef, double dt, int32_t B, bool mixed,
-                 hipStream_t s);
+                 hipStream_t s, const double* uprev = nullptr, bool extrap = false, double u_th = 0.0,
+                 double t_prev = 0.0);
+void launch_activation_between(const double* uold, const double* unew, double* act, int64_t nn, int32_t B,
+                               double u_th, double t_k, double dt, hipStream_t s);
 void launch_cast_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
 // P1 tetrahedra (mlq_tet.hip).  kval: per-sample stiffness values [B][nell] (slot-major

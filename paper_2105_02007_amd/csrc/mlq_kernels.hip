@@ -702,8 +702,13 @@ __global__ void k_activation(const double* __restrict__ uk, const double* __rest
 }
 
 void launch_activation(const Work& w, int64_t nn, int32_t B, double u_th, double t_k, double dt, hipStream_t s) {
+  launch_activation_between(w.uk, w.u, w.act, nn, B, u_th, t_k, dt, s);
+}
+
+void launch_activation_between(const double* uold, const double* unew, double* act, int64_t nn, int32_t B,
+                               double u_th, double t_k, double dt, hipStream_t s) {
   const int64_t total = nn * B;
-  hipLaunchKernelGGL(k_activation, dim3((unsigned)cdiv(total, kBlock)), dim3(kBlock), 0, s, w.uk, w.u, w.act, total,
+  hipLaunchKernelGGL(k_activation, dim3((unsigned)cdiv(total, kBlock)), dim3(kBlock), 0, s, uold, unew, act, total,
                      u_th, t_k, dt);
 }
 

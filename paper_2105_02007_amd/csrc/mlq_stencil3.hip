@@ -112,8 +112,14 @@ struct Args {
   const double* u;   // kRes / kRhs input (FP64)
   const double* bvec; // kRes: b
   double* bout;       // kRhs: b
-  double* ucopy;      // kRhs: u := u_k
+  double* ucopy;      // kRhs: u := u_k (or 2 u_k - u_{k-1} with extrap)
   const double* fbox; // kRhs
+  // kRhs, previous time level (may be NULL): u_{k-1} for the extrapolated Newton start and for
+  // the activation times of the step from t_{k-1} to t_k, which the kernel records in act
+  const double* uprev;
+  double* act;
+  double u_th, t_prev, dt_act;
+  int extrap;
   double load;
   void* r0;           // kRes: -F (inner precision)
   void* dout;         // kRes: dt I'(u) (inner precision)
@@ -347,7 +353,15 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
           n2 += bb * bb;
         } else {
           put(A.bout + sbase, obd + kk * pbD, (double)sres + A.load * (double)p0);
-          put(A.ucopy + sbase, obd + kk * pbD, (double)p1);
+          const double uk = (double)p1;
+          double ustart = uk;
+          if (A.uprev != nullptr) {
+            const double um = at(A.uprev + sbase, obd + kk * pbD);
+            if (A.extrap) ustart = 2.0 * uk - um;
+            double* ap = (double*)((char*)(A.act + sbase) + obd + kk * pbD);
+            if (*ap < 0.0 && um < A.u_th && uk >= A.u_th) *ap = A.t_prev + A.dt_act * (A.u_th - um) / (uk - um);
+          }
+          put(A.ucopy + sbase, obd + kk * pbD, ustart);
         }
       }
       acc_top = top;
@@ -530,10 +544,11 @@ void launch_residual3(const Geo& g, const Ionic& io, const Work& w, int32_t B, b
 }
 
 void launch_rhs3(const Geo& g, const Work& w, const double* fbox, double load_coef, double dt, int32_t B, bool mixed,
-                 hipStream_t s) {
+                 hipStream_t s, const double* uprev, bool extrap, double u_th, double t_prev) {
   Args<double> a{};
   a.g = g; a.u = w.uk; a.coef = w.coef; a.bout = w.b; a.ucopy = w.u; a.fbox = fbox; a.load = load_coef;
   a.ck = -0.5 * dt; a.cm = 1.0; a.active = nullptr;
+  a.uprev = uprev; a.act = w.act; a.u_th = u_th; a.t_prev = t_prev; a.dt_act = dt; a.extrap = extrap ? 1 : 0;
   if (mixed)
     launch_wave3<double, float, float, kRhs>(g, a, B, s);
   else
