@@ -341,9 +341,11 @@ class Level:
         check(lib.mlq_set_lane_layout(self.handle, int(lanes_x)))
         self.lanes_x = int(lanes_x)
 
-    def tune_lane_layout(self, batch=None, reps=3):
+    def tune_lane_layout(self, batch=None, reps=5, margin=0.05):
         """Times the operator apply of this level at `batch` samples (default: the level's
-        largest batch) in both lane layouts and keeps the faster.  Returns {lanes_x: ms}."""
+        largest batch) in both lane layouts and keeps the other layout than the default (by grid
+        width) only if it is faster by more than `margin`, so that near ties do not flip between
+        runs.  Returns {lanes_x: ms}."""
         import torch
         B = int(batch or self.desc.max_batch)
         tdt = torch.float32 if self.mixed else torch.float64
@@ -362,7 +364,9 @@ class Level:
             e1.record()
             torch.cuda.synchronize()
             times[lx] = e0.elapsed_time(e1) / reps
-        self.set_lane_layout(min(times, key=times.get))
+        default = 16 if self.desc.n[0] >= 48 else 8
+        other = 8 if default == 16 else 16
+        self.set_lane_layout(other if times[other] < (1.0 - margin) * times[default] else default)
         return times
 
     def set_reference(self, ref):
