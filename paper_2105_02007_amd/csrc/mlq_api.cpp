@@ -722,16 +722,17 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
     const double t0 = (double)k * dt, t1 = (double)(k + 1) * dt;
     const double load = 0.5 * dt * (rate(t1) + rate(t0));
     timed(level, MLQ_K_RHS, nn * batch, s, [&] {
-      if (tet)
-        launch_tet_rhs(td, w, level->fbox, load, dt, batch, mixed, s);
-      else if (g.dim == 3)  // also the extrapolated start and the previous step's activation
+      if (tet)  // also the extrapolated start and the previous step's activation
+        launch_tet_rhs(td, w, level->fbox, load, dt, batch, mixed, s, k > 0 ? w.ukm1 : nullptr,
+                       d.newton_guess == MLQ_GUESS_EXTRAPOLATE, d.u_th, (double)(k - 1) * dt);
+      else if (g.dim == 3)  // the same
         launch_rhs3(g, w, level->fbox, load, dt, batch, mixed, s, k > 0 ? w.ukm1 : nullptr,
                     d.newton_guess == MLQ_GUESS_EXTRAPOLATE, d.u_th, (double)(k - 1) * dt);
       else
         launch_rhs(g, w, level->fbox, load, dt, batch, mixed, s);
     });
     // the rhs kernels start Newton from u = u_k; the extrapolated guess replaces it
-    const bool fused3 = g.dim == 3 && !tet;  // the 3D rhs kernel did the two steps below
+    const bool fused3 = g.dim == 3 || tet;  // the 3D and tetrahedral rhs kernels did the two steps below
     if (d.newton_guess == MLQ_GUESS_EXTRAPOLATE && k > 0 && !fused3) launch_extrapolate(w, level->nn, batch, s);
     if ((d.newton_guess == MLQ_GUESS_REFERENCE || d.newton_guess == MLQ_GUESS_REFERENCE_LOCAL) &&
         level->ref != nullptr)
@@ -825,8 +826,9 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
     w.u = old;
     stream_fields(k + 1);
   }
-  // 3D boxes: the last step's activation (the rhs kernel of each step recorded the one before)
-  if (g.dim == 3 && !tet && n_steps > 0)
+  // 3D boxes and tetrahedra: the last step's activation (the rhs kernel of each step recorded
+  // the one before)
+  if ((g.dim == 3 || tet) && n_steps > 0)
     timed(level, MLQ_K_QOI, nn * batch, s, [&] {
       launch_activation_between(w.ukm1, w.uk, w.act, level->nn, batch, d.u_th, (double)(n_steps - 1) * dt, dt, s);
     });

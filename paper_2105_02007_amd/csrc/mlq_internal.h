@@ -240,7 +240,8 @@ void launch_tet_apply(const TetDev& t, const void* kval, const void* x, const vo
                       const int32_t* active, bool mixed, hipStream_t s);
 void launch_tet_residual(const TetDev& t, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);
 void launch_tet_rhs(const TetDev& t, const Work& w, const double* fload, double load, double dt, int32_t B,
-                    bool mixed, hipStream_t s);
+                    bool mixed, hipStream_t s, const double* uprev = nullptr, bool extrap = false,
+                    double u_th = 0.0, double t_prev = 0.0);
 // z_j = v_j inv_eta_j / diag(J) into the preconditioned basis, ck = dt / 2.
 void launch_tet_jacobi_basis(const TetDev& t, const Work& w, int j, double ck, int32_t B, bool mixed,
                              hipStream_t s);

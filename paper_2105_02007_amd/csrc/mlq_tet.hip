@@ -174,10 +174,14 @@ __global__ __launch_bounds__(kBlock) void k_tet_residual(TetDev t, Ionic io, con
 
 // b = M u_k - dt/2 K u_k + load F (FP64), u = u_k
 template <typename TI>
+// Also, with uprev (u_{k-1}, may be NULL): the extrapolated Newton start 2 u_k - u_{k-1}
+// (extrap) and the activation times of the step from t_prev = t_{k-1} to t_k into act.
 __global__ __launch_bounds__(kBlock) void k_tet_rhs(TetDev t, const TI* __restrict__ kval,
                                                     const double* __restrict__ uk, const double* __restrict__ fload,
                                                     double load, double ck, double* __restrict__ bout,
-                                                    double* __restrict__ ucopy) {
+                                                    double* __restrict__ ucopy, const double* __restrict__ uprev,
+                                                    double* __restrict__ act, double u_th, double t_prev, double dt,
+                                                    int extrap) {
   const int sb = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= t.nv) return;
@@ -190,7 +194,14 @@ __global__ __launch_bounds__(kBlock) void k_tet_rhs(TetDev t, const TI* __restri
     acc += (t.em[e] - ck * (double)kv[e]) * uj;
   }
   bout[so + i] = acc + load * fload[i];
-  ucopy[so + i] = uk[so + i];
+  const double u0 = uk[so + i];
+  double ustart = u0;
+  if (uprev != nullptr) {
+    const double um = uprev[so + i];
+    if (extrap) ustart = 2.0 * u0 - um;
+    if (act[so + i] < 0.0 && um < u_th && u0 >= u_th) act[so + i] = t_prev + dt * (u_th - um) / (u0 - um);
+  }
+  ucopy[so + i] = ustart;
 }
 
 // GMRES preconditioner step (Jacobi on the whole Jacobian): z_j = v_j inv_eta_j / J_ii with
@@ -248,14 +259,14 @@ void launch_tet_residual(const TetDev& t, const Ionic& io, const Work& w, int32_
 }
 
 void launch_tet_rhs(const TetDev& t, const Work& w, const double* fload, double load, double dt, int32_t B,
-                    bool mixed, hipStream_t s) {
+                    bool mixed, hipStream_t s, const double* uprev, bool extrap, double u_th, double t_prev) {
   const dim3 grid((unsigned)cdiv(t.nv, kBlock), B);
   if (mixed)
     hipLaunchKernelGGL((k_tet_rhs<float>), grid, dim3(kBlock), 0, s, t, (const float*)w.coef, w.uk, fload, load,
-                       0.5 * dt, w.b, w.u);
+                       0.5 * dt, w.b, w.u, uprev, w.act, u_th, t_prev, dt, extrap ? 1 : 0);
   else
     hipLaunchKernelGGL((k_tet_rhs<double>), grid, dim3(kBlock), 0, s, t, (const double*)w.coef, w.uk, fload, load,
-                       0.5 * dt, w.b, w.u);
+                       0.5 * dt, w.b, w.u, uprev, w.act, u_th, t_prev, dt, extrap ? 1 : 0);
 }
 
 void launch_tet_jacobi_basis(const TetDev& t, const Work& w, int j, double ck, int32_t B, bool mixed,
