@@ -227,3 +227,33 @@ def test_streamed_fields_2d_match_oracle(env):
     assert np.abs(a_sum.cpu().numpy() - A).max() <= 1e-8 * B * phys["t_end"]
     P = np.stack([fields.action_potential(mesh, r, pts) for r in refs])
     assert np.abs(out["probe"].cpu().numpy() - P).max() <= 1e-10 * np.abs(P).max()
+
+
+def test_streamed_fields_mixed_precision(env):
+    """The field outputs of a mixed-precision solve (FP32 inner solves, FP64 states and
+    residuals; FP32 field values) against the oracle on the same rounded field: the mixed bar
+    1e-6 of the scale."""
+    torch, mlq = env
+    from oracle import fem, fields, stepper
+    from oracle.mesh import BoxMesh
+    n, steps, B = [9, 7, 5], 12, 2
+    hi = [0.6, 0.5, 0.4]
+    phys = W.physics(3)
+    lv = dict(dim=3, n=n, lo=[0.0] * 3, hi=hi, n_steps=steps)
+    desc, keep = mlq.make_desc(lv, phys, qoi=mlq.MLQ_QOI_MEAN_ACT_TIME, max_batch=B, diffusion=mlq.MLQ_DIFF_ISO,
+                               prec=mlq.MLQ_MIXED)
+    L = mlq.Level(desc, keep)
+    mesh = BoxMesh(n, hi=hi)
+    v = 3.325e-3 * 4.0 * (1.0 + 0.3 * (2.0 * W.random_nodal(22, B, mesh.n_elems, 0.0, 1.0) - 1.0))
+    v32 = v.astype(np.float32)
+    pts = np.array([[0.11, 0.23, 0.07]])
+    node, w = L.probe_weights(pts)
+    u_sum = torch.zeros((steps + 1, mesh.n_nodes), dtype=torch.float64, device="cuda")
+    out = L.solve_fields(torch.as_tensor(v32, device="cuda"), u_sum=u_sum, probe_node=node, probe_w=w)
+    assert out["code"] == mlq.MLQ_OK
+    refs = [stepper.solve(mesh, fem.conductivity_iso(v32[b].astype(np.float64), 3, phys["sigma_t"]), phys, steps,
+                          tol=1e-13, keep_all=True) for b in range(B)]
+    H = sum(fields.space_time_field(r) for r in refs)
+    assert np.abs(u_sum.cpu().numpy() - H).max() <= 1e-6 * np.abs(H).max()
+    P = np.stack([fields.action_potential(mesh, r, pts) for r in refs])
+    assert np.abs(out["probe"].cpu().numpy() - P).max() <= 1e-6 * np.abs(P).max()
