@@ -30,10 +30,11 @@ HBM_PEAK_GBS = 8000.0
 # element per node) read, w written, in the inner precision
 APPLY_BYTES = {0: 5 * 8, 1: 5 * 4}
 APPLY_SOURCE = os.path.join(ROOT, "paper_2105_02007_amd", "csrc", "mlq_stencil3.hip")
+TET_APPLY_SOURCE = os.path.join(ROOT, "paper_2105_02007_amd", "csrc", "mlq_tet.hip")
 COPY_ELEMS = 1 << 27  # 1 GiB of FP64 for the counter calibration copy
 
 
-def counter_traffic(config, prec):
+def counter_traffic(config, prec, tet=False):
     """HBM bytes per algorithmic byte of the apply, from the committed rocprofv3 counter summary.
 
     The summary records FETCH_SIZE and WRITE_SIZE summed over the apply dispatches
@@ -42,7 +43,8 @@ def counter_traffic(config, prec):
     summary for a different source (the kernel changed since) gives None.
     """
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"apply_k_wave3_{config}_{prec}_counters.md")
+    kernel, source = ("k_tet_apply", TET_APPLY_SOURCE) if tet else ("k_wave3", APPLY_SOURCE)
+    path = os.path.join(ROOT, "profiles", f"apply_{kernel}_{config}_{prec}_counters.md")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -51,7 +53,7 @@ def counter_traffic(config, prec):
             for kv in ln.split()[1:]:
                 k, v = kv.split("=")
                 rec[k] = v
-    if rec.get("source_sha256") != hashlib.sha256(open(APPLY_SOURCE, "rb").read()).hexdigest():
+    if rec.get("source_sha256") != hashlib.sha256(open(source, "rb").read()).hexdigest():
         return None
     return float(rec["hbm_bytes_per_alg_byte"])
 
@@ -364,7 +366,7 @@ def main():
     alg_bytes = apply_bytes if apply_bytes > 0 else apply_units * APPLY_BYTES[prec]
     per_launch = alg_bytes / max(apply_launches, 1)
     achieved = alg_bytes / (apply_ms * 1e-3) / 1e9 if apply_ms > 0 else 0.0
-    ratio = counter_traffic(args.config, "fp64" if prec == W.PREC_FP64 else "mixed")
+    ratio = counter_traffic(args.config, "fp64" if prec == W.PREC_FP64 else "mixed", tet=runner.tet)
     lvl = cfg["levels"][-1]
     shape = (f"{lvl['cells'][0]}x{lvl['cells'][1]}x{lvl['cells'][2]} shell" if runner.tet
              else "x".join(map(str, lvl["n"])))

@@ -20,6 +20,18 @@ namespace mlq {
 
 namespace {
 
+// XCD-aware block numbering: workgroups go to the 8 XCDs round-robin by linear id.  Give each
+// XCD one contiguous range of (row block, sample group) blocks, so that the column gathers of
+// neighbouring row blocks meet in one L2.  (bx, by) replace (blockIdx.x, blockIdx.y).
+__device__ inline void xcd_block(int64_t& bx, int64_t& by) {
+  const int64_t NB = (int64_t)gridDim.x * gridDim.y;
+  const int64_t L = (int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+  const int64_t q = NB >> 3, r = NB & 7, x = L & 7;
+  const int64_t W = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + (L >> 3);
+  bx = W % gridDim.x;
+  by = W / gridDim.x;
+}
+
 __device__ inline double tet_iion(double u, const Ionic& io) {
   return io.alpha * (u - io.u_rest) * (u - io.u_th) * (u - io.u_peak);
 }
@@ -82,7 +94,9 @@ __global__ __launch_bounds__(kBlock) void k_tet_apply(TetDev t, const T* __restr
                                                       const T* __restrict__ d, T* __restrict__ y, T ck, int32_t B,
                                                       const int32_t* __restrict__ active) {
   constexpr int S = kTetSamples;
-  const int sb0 = blockIdx.y * S;
+  int64_t bx, by;
+  xcd_block(bx, by);
+  const int sb0 = (int)by * S;
   bool on[S];
   bool any = false;
 #pragma unroll
@@ -91,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_apply(TetDev t, const T* __restr
     any = any || on[q];
   }
   if (!any) return;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = bx * kBlock + threadIdx.x;
   if (i >= t.nv) return;
   const T* mv = nullptr;
   if constexpr (sizeof(T) == 4) mv = (const T*)t.em32; else mv = (const T*)t.em;
@@ -122,9 +136,11 @@ __global__ __launch_bounds__(kBlock) void k_tet_residual(TetDev t, Ionic io, con
                                                          TI* __restrict__ r0, TI* __restrict__ dout,
                                                          double* __restrict__ part,
                                                          const int32_t* __restrict__ active) {
-  const int sb = blockIdx.y;
+  int64_t bx, by;
+  xcd_block(bx, by);
+  const int sb = (int)by;
   if (active[sb] == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = bx * kBlock + threadIdx.x;
   double n0 = 0.0, n1 = 0.0, n2 = 0.0;
   if (i < t.nv) {
     const int64_t so = (int64_t)sb * t.nv;
@@ -165,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_residual(TetDev t, Ionic io, con
       s1 += red[q][1];
       s2 += red[q][2];
     }
-    double* p = part + ((int64_t)sb * gridDim.x + blockIdx.x) * 3;
+    double* p = part + ((int64_t)sb * gridDim.x + bx) * 3;
     p[0] = s0;
     p[1] = s1;
     p[2] = s2;
@@ -182,8 +198,10 @@ __global__ __launch_bounds__(kBlock) void k_tet_rhs(TetDev t, const TI* __restri
                                                     double* __restrict__ ucopy, const double* __restrict__ uprev,
                                                     double* __restrict__ act, double u_th, double t_prev, double dt,
                                                     int extrap) {
-  const int sb = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int64_t bx, by;
+  xcd_block(bx, by);
+  const int sb = (int)by;
+  const int64_t i = bx * kBlock + threadIdx.x;
   if (i >= t.nv) return;
   const int64_t so = (int64_t)sb * t.nv;
   const TI* kv = kval + (int64_t)sb * t.nell;
