@@ -112,6 +112,33 @@ __global__ __launch_bounds__(kBlock) void k_tet_apply(TetDev t, const T* __restr
   T acc[S];
 #pragma unroll
   for (int q = 0; q < S; ++q) acc[q] = 0;
+  bool all = true;
+#pragma unroll
+  for (int q = 0; q < S; ++q) all = all && on[q];
+  if (all) {
+    // Every sample of the group active (the usual case): no per-sample branch in the slot loop, so
+    // the gathers of all samples and of the next slot are in flight together. Same arithmetic, in
+    // the same order, as the general loop below.
+#pragma unroll 2
+    for (int32_t sl = 0; sl < t.width; ++sl) {
+      const int64_t e = (int64_t)sl * t.nv + i;
+      const int64_t c = t.ecol[e];
+      const T m = mv[e];
+      T dv[S], xv[S], kv[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        const int64_t j = (int64_t)(sb0 + q) * t.nv + c;
+        dv[q] = d[j];
+        xv[q] = x[j];
+        kv[q] = kval[(int64_t)(sb0 + q) * t.nell + e];
+      }
+#pragma unroll
+      for (int q = 0; q < S; ++q) acc[q] += (m * ((T)1 + dv[q]) + ck * kv[q]) * xv[q];
+    }
+#pragma unroll
+    for (int q = 0; q < S; ++q) y[(int64_t)(sb0 + q) * t.nv + i] = acc[q];
+    return;
+  }
   for (int32_t sl = 0; sl < t.width; ++sl) {
     const int64_t e = (int64_t)sl * t.nv + i;
     const int64_t c = t.ecol[e];
