@@ -174,6 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_residual(TetDev t, Ionic io, con
     const TI* kv = kval + (int64_t)sb * t.nell;
     const double ck = 0.5 * io.dt;
     double G = 0.0;
+#pragma unroll 4
     for (int32_t sl = 0; sl < t.width; ++sl) {
       const int64_t e = (int64_t)sl * t.nv + i;
       const double uj = u[so + t.ecol[e]];
@@ -233,6 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_rhs(TetDev t, const TI* __restri
   const int64_t so = (int64_t)sb * t.nv;
   const TI* kv = kval + (int64_t)sb * t.nell;
   double acc = 0.0;
+#pragma unroll 4
   for (int32_t sl = 0; sl < t.width; ++sl) {
     const int64_t e = (int64_t)sl * t.nv + i;
     const double uj = uk[so + t.ecol[e]];
