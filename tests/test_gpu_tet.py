@@ -33,16 +33,17 @@ def _phys(radius_frac=0.3):
     return ph
 
 
-@pytest.mark.parametrize("cells,mixed", [((2, 6, 12), False), ((3, 10, 20), False), ((2, 6, 12), True),
-                                         ((3, 10, 20), True)])
-def test_tet_apply_matches_assembled_jacobian(env, cells, mixed):
+# B = 3: one sample group with an inactive lane (general slot loop); B = 6: one full group (the
+# branch-free slot loop) and one ragged group.
+@pytest.mark.parametrize("cells,mixed,B", [((2, 6, 12), False, 3), ((3, 10, 20), False, 3), ((2, 6, 12), True, 3),
+                                           ((3, 10, 20), True, 3), ((3, 10, 20), False, 6), ((3, 10, 20), True, 6)])
+def test_tet_apply_matches_assembled_jacobian(env, cells, mixed, B):
     torch, mlq = env
     from oracle.tetfem import TetMesh
     mesh_d, _ = _shell(cells)
     ph = _phys()
     steps = 16
     lvl = dict(kind="tet", dim=3, n_steps=steps, mesh=mesh_d)
-    B = 3
     desc, keep = mlq.make_desc(lvl, ph, prec=mlq.MLQ_MIXED if mixed else mlq.MLQ_FP64, max_batch=B)
     lv = mlq.Level(desc, keep)
     mesh = TetMesh(mesh_d["xyz"], mesh_d["tets"])
