@@ -20,9 +20,11 @@
  *   - estimators eqs. (SL), (StandardML), (PimpedML) of Section 4.
  *
  * Conventions
- *   Ownership: the library never allocates device memory.  Every device buffer
- *     (level blob, fields, workspace, outputs) is passed in by the caller and
- *     stays owned by the caller.  Host arrays given to mlq_create_level are
+ *   Ownership: the library never allocates device memory at run time.  Every
+ *     device buffer (level blob, fields, workspace, outputs) is passed in by the
+ *     caller and stays owned by the caller; the one exception is the static
+ *     workspace array of mlq_solve_batch_static, part of the library's code
+ *     object on each GPU.  Host arrays given to mlq_create_level are
  *     copied during the call.  Each level object owns a few bytes of pinned host
  *     memory for convergence flags.
  *   Layouts: a batch of B samples on a level with n nodes and P elements stores
@@ -174,6 +176,20 @@ mlq_status mlq_sample_fields(mlq_level* level, const double* Y_dev, int32_t batc
 mlq_status mlq_solve_batch(mlq_level* level, const void* theta_dev, int32_t batch, void* ws_dev,
                            size_t ws_bytes, double* qoi_dev, int32_t* status_dev, int64_t* iters_dev,
                            void* hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): mlq_solve_batch with the library's own static
+ * workspace instead of a caller's buffer.  Same arguments (minus the workspace), results and
+ * errors as mlq_solve_batch; allocates nothing.  The workspace is a device array of
+ * MLQ_STATIC_WS_BYTES (64 MiB) that every GPU the library runs on holds once, from the first
+ * use of the library on it until the process ends.  MLQ_ESIZE when the batch needs more
+ * (mlq_workspace_bytes tells); MLQ_EINVAL when the current device is not the level's.  All calls
+ * on one GPU share its array: calls that overlap in time on one GPU (other streams, other host
+ * threads) race and give undefined results.  The array keeps the last call's contents; the solve
+ * initialises everything it reads, so nothing has to be cleared between calls. */
+#define MLQ_STATIC_WS_BYTES (64u << 20)
+mlq_status mlq_solve_batch_static(mlq_level* level, const void* theta_dev, int32_t batch, double* qoi_dev,
+                                  int32_t* status_dev, int64_t* iters_dev, void* hip_stream);
 
 /* Same as mlq_solve_batch but stops after `n_steps` steps (<= the level's) and
  * also copies the final nodal state (batch x n, FP64) to u_out_dev (may be

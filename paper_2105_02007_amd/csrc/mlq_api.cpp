@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -58,6 +59,7 @@ double hat_integral(int64_t i, int64_t n, double lo, double h, double a, double 
 
 struct mlq_level {
   mlq_level_desc d;
+  int device = -1;              // HIP device current at creation (the blob's device)
   const double* ref = nullptr;  // reference space-time solution for the Newton guess (caller's memory)
   Geo geo;
   Ionic io;
@@ -301,6 +303,18 @@ Work carve_workspace(void* base, const Geo& geo, int32_t B, int kmax, bool mixed
 }
 
 }  // namespace mlq
+
+// Workspace of mlq_solve_batch_static: a file-scope device array, one copy per GPU, held
+// until the process ends.  Host code never passes `scratch` itself to a kernel or a copy
+// (on the host the name only stands for the symbol); it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device and kept in g_scratch.
+static __device__ __align__(256) unsigned char scratch[MLQ_STATIC_WS_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void* g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+}  // namespace
 
 extern "C" {
 
@@ -565,6 +579,7 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&lv->host_flags, sizeof(int32_t) * (kFlagInner + kMaxInner + 1), hipHostMallocDefault);
   for (int q = 0; q < 2 && e == hipSuccess; ++q) e = hipEventCreateWithFlags(&lv->flag_ev[q], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipGetDevice(&lv->device);
   if (e != hipSuccess) return cleanup(fail(MLQ_EHIP, "level upload failed: %s", hipGetErrorString(e)));
   *out = lv;
   return MLQ_OK;
@@ -840,12 +855,15 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
     HIP_OK(hipMemcpyAsync(u_out_dev, w.uk, sizeof(double) * level->nn * batch, hipMemcpyDeviceToDevice, s));
   if (act_out_dev)
     HIP_OK(hipMemcpyAsync(act_out_dev, w.act, sizeof(double) * level->nn * batch, hipMemcpyDeviceToDevice, s));
+  // samples that failed: counted on the device, one integer read back
+  launch_count(w.status, batch, w.counter + 3, nullptr, s);
   HIP_OK(hipGetLastError());
-  std::vector<int32_t> stat(batch);
-  HIP_OK(hipMemcpyAsync(stat.data(), w.status, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(level->host_flags + 2, w.counter + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   harvest(level);
-  return mlq_check(stat.data(), batch);
+  const int32_t bad = level->host_flags[2];
+  if (bad) return fail(MLQ_ENOCONV, "%d of %d samples did not converge", bad, batch);
+  return MLQ_OK;
 }
 
 mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t batch, int32_t n_steps, void* ws_dev,
@@ -860,6 +878,34 @@ mlq_status mlq_solve_batch(mlq_level* level, const void* theta_dev, int32_t batc
   if (level == nullptr) return fail(MLQ_EINVAL, "level is NULL");
   return solve_impl(level, theta_dev, batch, level->d.n_steps, ws_dev, ws_bytes, qoi_dev, status_dev, iters_dev,
                     nullptr, nullptr, nullptr, hip_stream);
+}
+
+mlq_status mlq_solve_batch_static(mlq_level* level, const void* theta_dev, int32_t batch, double* qoi_dev,
+                                  int32_t* status_dev, int64_t* iters_dev, void* hip_stream) {
+  if (level == nullptr) return fail(MLQ_EINVAL, "level is NULL");
+  if (batch < 1 || batch > level->d.max_batch) return fail(MLQ_EINVAL, "batch %d outside [1, max_batch]", batch);
+  const size_t need = carve_workspace(nullptr, level->geo, batch, level->kmax, level->mixed).bytes;
+  if (need > (size_t)MLQ_STATIC_WS_BYTES)
+    return fail(MLQ_ESIZE, "the solve needs %zu workspace bytes, more than the static %zu", need,
+                (size_t)MLQ_STATIC_WS_BYTES);
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev != level->device)
+    return fail(MLQ_EINVAL, "device %d is current, the level lives on device %d", dev, level->device);
+  if (dev < 0 || dev >= kMaxDevices) return fail(MLQ_EINVAL, "device index %d not supported", dev);
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev] == nullptr) {
+      void* p = nullptr;
+      HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+      if (p == nullptr) return fail(MLQ_EHIP, "hipGetSymbolAddress returned NULL for the static workspace");
+      g_scratch[dev] = p;
+    }
+    ws = g_scratch[dev];
+  }
+  return solve_impl(level, theta_dev, batch, level->d.n_steps, ws, (size_t)MLQ_STATIC_WS_BYTES, qoi_dev, status_dev,
+                    iters_dev, nullptr, nullptr, nullptr, hip_stream);
 }
 
 mlq_status mlq_set_lane_layout(mlq_level* level, int32_t lanes_x) {

@@ -28,8 +28,9 @@ EXPORTED = [
     "mlq_kl_workspace_bytes", "mlq_kl_modes", "mlq_kl_transfer", "mlq_timing_enable", "mlq_timing_read",
     "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet", "mlq_solve_batch_fields", "mlq_probe_weights",
     "mlq_transfer_add", "mlq_field_norm2", "mlq_set_reference", "mlq_tet_locate", "mlq_transfer_add_weighted",
-    "mlq_set_lane_layout", "mlq_lattice_points",
+    "mlq_set_lane_layout", "mlq_lattice_points", "mlq_solve_batch_static",
 ]
+STATIC_WS_BYTES = 64 << 20
 MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE, MLQ_GUESS_REFERENCE, MLQ_GUESS_REFERENCE_LOCAL = 0, 1, 2, 3
 MLQ_DIFF_FIBRE, MLQ_DIFF_ISO, MLQ_DIFF_VECTOR = 0, 1, 2
 MLQ_COV_EXP, MLQ_COV_SQEXP = 0, 1
@@ -101,6 +102,7 @@ def _load():
         "mlq_sample_fields": [VP, VP, I32, VP, VP],
         "mlq_solve_batch": [VP, VP, I32, VP, C.c_size_t, VP, VP, VP, VP],
         "mlq_solve_batch_ex": [VP, VP, I32, I32, VP, C.c_size_t, VP, VP, VP, VP, VP, VP],
+        "mlq_solve_batch_static": [VP, VP, I32, VP, VP, VP, VP],
         "mlq_apply": [VP, VP, I32, VP, VP, VP, VP, C.c_size_t, VP],
         "mlq_check": [VP, I32],
         "mlq_lattice_normals": [VP, VP, I32, I64, I64, I32, VP, VP],
@@ -298,6 +300,20 @@ class Level:
         if code not in (MLQ_OK, MLQ_ENOCONV):
             check(code)
         return dict(qoi=qoi, status=status, iters=iters, u=u, act=act, code=code)
+
+    def solve_static(self, theta):
+        """mlq_solve_batch_static: the solve with the library's static device workspace (no
+        workspace from torch).  Returns the same dict as solve (without states)."""
+        import torch
+        B = theta.shape[-2]
+        qoi = torch.empty(B, dtype=torch.float64, device=self.device)
+        status = torch.empty(B, dtype=torch.int32, device=self.device)
+        iters = torch.empty((B, 2), dtype=torch.int64, device=self.device)
+        code = lib.mlq_solve_batch_static(self.handle, _ptr(theta), int(B), _ptr(qoi), _ptr(status), _ptr(iters),
+                                          _stream())
+        if code not in (MLQ_OK, MLQ_ENOCONV):
+            check(code)
+        return dict(qoi=qoi, status=status, iters=iters, code=code)
 
     def solve_fields(self, theta, u_sum=None, act_sum=None, probe_node=None, probe_w=None, probe_sum=None,
                      per_sample_probes=True):
