@@ -343,6 +343,28 @@ mlq_status mlq_halton(int32_t s, int64_t first, int32_t count, const double* shi
 mlq_status mlq_lattice_points(const int64_t* z_dev, const double* shift_dev, int32_t s, int64_t N, int64_t first,
                               int32_t count, int32_t map, double* Y_dev, void* hip_stream);
 
+/* Mode weights of eq. (KLlowrank) for the distribution of the coordinates (host only):
+ *   out[k] = sqrt(lambda[k])      map = MLQ_MAP_NORMAL  (standard normal y_k, E[y^2] = 1),
+ *   out[k] = sqrt(3 lambda[k])    map = MLQ_MAP_UNIFORM (y_k uniform on [-1, 1], E[y^2] = 1/3;
+ *                                  the paper's parametrisation, Section 5.1),
+ * so that the field sum_k out[k] psi_k y_k has the covariance sum_k lambda_k psi_k psi_k^T in
+ * either case; out is the sqrt_lambda array of mlq_level_desc.  lambda, out: M host values.
+ * MLQ_EINVAL for a negative or non-finite eigenvalue or an unknown map. */
+mlq_status mlq_kl_weights(const double* lambda, int32_t M, int32_t map, double* out);
+
+/* Product weights of the lattice construction (mlq_cbc) from the KL eigenvalues (host only):
+ * gamma_out[c M + k] = lambda[k] / lambda[0] for each of `components` independent fields with
+ * the same basis (the coordinates of component c follow those of component c - 1).
+ * lambda: M host values, descending, lambda[0] > 0; gamma_out: components x M host values. */
+mlq_status mlq_lattice_weights(const double* lambda, int32_t M, int32_t components, double* gamma_out);
+
+/* Mean field of the vector conductivity model (host only): the rule-based fibre of angle theta0
+ * in the element frame, scaled, eq. (AdmV) with V = scale f:
+ *   v_out[3 e + a] = scale (cos theta0[e] e_circ[3 e + a] + sin theta0[e] e_long[3 e + a]),
+ * e < n; with scale = sigma_l this is the v_mean array of mlq_level_desc for MLQ_DIFF_VECTOR. */
+mlq_status mlq_fibre_field(int64_t n, const double* theta0, const double* e_circ, const double* e_long, double scale,
+                           double* v_out);
+
 /* Component-by-component generating vector of an N-point rank-1 lattice in s
  * dimensions, product weights gamma (s), minimising the shift-averaged
  * worst-case error of the unanchored Sobolev space.  Host only. */

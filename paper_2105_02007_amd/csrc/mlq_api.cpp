@@ -1141,6 +1141,40 @@ mlq_status mlq_accumulate(const double* f_fine_dev, const double* f_coarse_dev, 
   return MLQ_OK;
 }
 
+mlq_status mlq_kl_weights(const double* lambda, int32_t M, int32_t map, double* out) {
+  if (M < 0 || (M > 0 && (lambda == nullptr || out == nullptr))) return fail(MLQ_EINVAL, "invalid arguments");
+  if (map != MLQ_MAP_NORMAL && map != MLQ_MAP_UNIFORM) return fail(MLQ_EINVAL, "unknown coordinate map %d", map);
+  // E[y^2] = 1 for a standard normal coordinate, 1/3 for a uniform one on [-1, 1]
+  const double inv_second_moment = map == MLQ_MAP_UNIFORM ? 3.0 : 1.0;
+  for (int32_t k = 0; k < M; ++k) {
+    if (!(lambda[k] >= 0.0) || !std::isfinite(lambda[k])) return fail(MLQ_EINVAL, "eigenvalue %d is %g", k, lambda[k]);
+    out[k] = std::sqrt(inv_second_moment * lambda[k]);
+  }
+  return MLQ_OK;
+}
+
+mlq_status mlq_lattice_weights(const double* lambda, int32_t M, int32_t components, double* gamma_out) {
+  if (M < 1 || components < 1 || lambda == nullptr || gamma_out == nullptr) return fail(MLQ_EINVAL, "invalid arguments");
+  if (!(lambda[0] > 0.0) || !std::isfinite(lambda[0])) return fail(MLQ_EINVAL, "the largest eigenvalue must be positive");
+  for (int32_t c = 0; c < components; ++c)
+    for (int32_t k = 0; k < M; ++k) {
+      if (!(lambda[k] >= 0.0) || lambda[k] > lambda[0]) return fail(MLQ_EINVAL, "eigenvalues must be in [0, lambda_0]");
+      gamma_out[(int64_t)c * M + k] = lambda[k] / lambda[0];
+    }
+  return MLQ_OK;
+}
+
+mlq_status mlq_fibre_field(int64_t n, const double* theta0, const double* e_circ, const double* e_long, double scale,
+                           double* v_out) {
+  if (n < 0 || (n > 0 && (theta0 == nullptr || e_circ == nullptr || e_long == nullptr || v_out == nullptr)))
+    return fail(MLQ_EINVAL, "invalid arguments");
+  for (int64_t e = 0; e < n; ++e) {
+    const double c = std::cos(theta0[e]), sn = std::sin(theta0[e]);
+    for (int a = 0; a < 3; ++a) v_out[3 * e + a] = scale * (c * e_circ[3 * e + a] + sn * e_long[3 * e + a]);
+  }
+  return MLQ_OK;
+}
+
 // Component-by-component construction; operations in the order k = 0..N-1 with
 // one accumulator and no contraction, so the argmin is reproducible exactly.
 mlq_status mlq_cbc(int64_t N, int32_t s, const double* gamma, int64_t* z_out) {

@@ -69,7 +69,7 @@ class ConfigRunner:
         lam, psi, self.kl_rank, self.kl_resid = mlq.kl_modes(self.kd, device=device)
         say(f"KL modes done (rank {self.kl_rank})")
         self.lam = lam
-        sl = torch.as_tensor(np.sqrt((3.0 if self.uniform else 1.0) * lam), dtype=torch.float64, device=device)
+        sl = torch.as_tensor(mlq.kl_weights(lam, uniform=self.uniform), dtype=torch.float64, device=device)
         self.levels = []
         samp = cfg["sampling"]
         n_shifts = samp.get("n_shifts", 1)
@@ -89,8 +89,7 @@ class ConfigRunner:
                 lv = dict(lv, mesh=mesh)
                 phi = mlq.kl_transfer_tet(self.kd, psi, mesh, device=device)
                 if self.vector:  # E[V] = sigma_l f0 with the rule-based fibre f0
-                    th = mesh["theta0"][:, None]
-                    v_mean = self.phys["sigma_l"] * (np.cos(th) * mesh["e_circ"] + np.sin(th) * mesh["e_long"])
+                    v_mean = mlq.fibre_field(mesh["theta0"], mesh["e_circ"], mesh["e_long"], self.phys["sigma_l"])
                 elif self.iso:  # the field is v = E[V] + W
                     theta0 = torch.full((mesh["tets"].shape[0],), float(kcfg["mean"]), dtype=torch.float64,
                                         device=device)
@@ -416,7 +415,7 @@ class ConfigRunner:
                     for s in range(shifts.shape[0])]
             return torch.cat(cols, dim=1)
         # product weights from the KL eigenvalues, repeated for every component of a vector field
-        gamma = np.tile(self.lam / self.lam[0], M // len(self.lam))
+        gamma = mlq.lattice_weights(self.lam, M // len(self.lam))
         z = mlq.cbc(N, M, gamma)
         cols = [mlq.lattice_points(z, shifts[s], N, 0, N, uniform=self.uniform, device=self.device)
                 for s in range(shifts.shape[0])]

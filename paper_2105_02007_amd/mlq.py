@@ -29,6 +29,7 @@ EXPORTED = [
     "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet", "mlq_solve_batch_fields", "mlq_probe_weights",
     "mlq_transfer_add", "mlq_field_norm2", "mlq_set_reference", "mlq_tet_locate", "mlq_transfer_add_weighted",
     "mlq_set_lane_layout", "mlq_lattice_points", "mlq_solve_batch_static",
+    "mlq_kl_weights", "mlq_lattice_weights", "mlq_fibre_field",
 ]
 STATIC_WS_BYTES = 64 << 20
 MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE, MLQ_GUESS_REFERENCE, MLQ_GUESS_REFERENCE_LOCAL = 0, 1, 2, 3
@@ -117,6 +118,9 @@ def _load():
         "mlq_tet_locate": [VP, I64, VP, I64, VP, I64, VP, VP],
         "mlq_transfer_add_weighted": [VP, VP, I32, I64, I32, VP, VP, C.c_double, VP, VP, VP],
         "mlq_cbc": [I64, I32, VP, VP],
+        "mlq_kl_weights": [VP, I32, I32, VP],
+        "mlq_lattice_weights": [VP, I32, I32, VP],
+        "mlq_fibre_field": [I64, VP, VP, VP, C.c_double, VP],
         "mlq_accumulate": [VP, VP, I32, VP, VP],
         "mlq_estimate": [I32, I32, I32, VP, VP, VP, C.POINTER(EstimateOut)],
         "mlq_kl_workspace_bytes": [C.POINTER(KlDesc), C.POINTER(C.c_size_t)],
@@ -502,6 +506,35 @@ def cbc(N, s, gamma):
     z = np.zeros(s, dtype=np.int64)
     check(lib.mlq_cbc(int(N), int(s), g.ctypes.data_as(C.c_void_p), z.ctypes.data_as(C.c_void_p)))
     return z
+
+
+def kl_weights(lam, uniform=False):
+    """sqrt(lambda) (normal coordinates) or sqrt(3 lambda) (uniform on [-1, 1]), host array."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    out = np.zeros_like(lam)
+    check(lib.mlq_kl_weights(lam.ctypes.data_as(C.c_void_p), int(lam.size), MLQ_MAP_UNIFORM if uniform else MLQ_MAP_NORMAL,
+                             out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def lattice_weights(lam, components=1):
+    """Product weights lambda_k / lambda_0, repeated for each component (host array)."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    out = np.zeros(lam.size * int(components))
+    check(lib.mlq_lattice_weights(lam.ctypes.data_as(C.c_void_p), int(lam.size), int(components),
+                                  out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def fibre_field(theta0, e_circ, e_long, scale):
+    """scale (cos theta0 e_circ + sin theta0 e_long) per element (host arrays, n x 3)."""
+    th = np.ascontiguousarray(theta0, dtype=np.float64)
+    ec = np.ascontiguousarray(e_circ, dtype=np.float64)
+    el = np.ascontiguousarray(e_long, dtype=np.float64)
+    out = np.zeros((th.size, 3))
+    check(lib.mlq_fibre_field(int(th.size), th.ctypes.data_as(C.c_void_p), ec.ctypes.data_as(C.c_void_p),
+                              el.ctypes.data_as(C.c_void_p), float(scale), out.ctypes.data_as(C.c_void_p)))
+    return out
 
 
 def accumulate(f_fine, f_coarse, acc):

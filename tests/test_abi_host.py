@@ -173,3 +173,41 @@ int main(void) {
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
     assert [int(v) for v in out[0].split()] == list(qmc.cbc(31, 3, [1.0, 0.5, 0.25]))
     assert int(out[1]) == mlq.MLQ_EINVAL
+
+
+@pytest.mark.parametrize("uniform", [False, True])
+def test_kl_weights_reproduce_the_covariance(mlq, uniform):
+    """The library's mode weights (sqrt(lambda) for normal, sqrt(3 lambda) for uniform coordinates on
+    [-1, 1], Section 5.1) with the oracle's full-rank eigenpairs: the exact covariance of the field,
+    sum_k w_k^2 psi_k psi_k^T E[y^2] (E[y^2] from a Gauss rule exact for quadratics), is the kernel."""
+    from oracle import fem, kl
+    from oracle.mesh import BoxMesh
+    mesh = BoxMesh([4, 3, 3])
+    n = mesh.n_nodes
+    lam, psi = kl.kl_modes(mesh, fem.assemble_mass(mesh), 0.3, 0.2, n, max_rank=n, eps=0.0)
+    w = mlq.kl_weights(lam, uniform=uniform)
+    y, q = np.polynomial.legendre.leggauss(2) if uniform else np.polynomial.hermite_e.hermegauss(2)
+    ey2 = float((q * y * y).sum() / q.sum())
+    cov = (psi * w ** 2) @ psi.T * ey2
+    d = np.sqrt(((mesh.nodes[:, None, :] - mesh.nodes[None, :, :]) ** 2).sum(-1))
+    assert np.abs(cov - 0.09 * np.exp(-d / 0.2)).max() <= 1e-10 * 0.09
+    with pytest.raises(mlq.MlqError):
+        mlq.kl_weights(np.array([1.0, -1.0]))
+
+
+def test_lattice_weights_and_fibre_field(mlq):
+    lam = np.array([2.0, 1.0, 0.5, 0.0])
+    g = mlq.lattice_weights(lam, components=3)
+    assert np.array_equal(g, np.tile(lam / 2.0, 3))
+    rng = np.random.default_rng(3)
+    n = 50
+    a = rng.normal(size=(n, 3))
+    ec = a / np.linalg.norm(a, axis=1)[:, None]
+    b = rng.normal(size=(n, 3))
+    b -= (b * ec).sum(1)[:, None] * ec
+    el = b / np.linalg.norm(b, axis=1)[:, None]
+    th = rng.uniform(-np.pi, np.pi, n)
+    v = mlq.fibre_field(th, ec, el, 3.325e-3)
+    # |V| = sigma_l and V makes the angle theta with e_circ in the (e_circ, e_long) plane
+    assert np.allclose(np.linalg.norm(v, axis=1), 3.325e-3, rtol=1e-14)
+    assert np.allclose(np.arctan2((v * el).sum(1), (v * ec).sum(1)), th, atol=1e-13)

@@ -157,3 +157,54 @@ def test_cube_stochastic_dimension_matches_the_paper():
     for kernel, ell in (("sqexp", 0.25 ** 2), ("exp", 0.25)):
         L2, _ = kl.pivoted_cholesky(mesh.nodes, 0.3, ell, 100, eps=1e-2, kernel=kernel)
         assert L2.shape[1] == 100
+
+
+@pytest.mark.parametrize("name", ["c2", "c2i"])
+def test_coordinate_scaling_reproduces_the_covariance(name):
+    """The modes' weights of eq. (KLlowrank) for normal coordinates (sqrt(lambda)) and for uniform
+    ones on [-1, 1] (sqrt(3 lambda), Section 5.1): with all modes kept, the exact covariance of the
+    synthesised nodal field, sum_k w_k^2 psi_k psi_k^T E[y^2], is the covariance kernel itself.
+    E[y^2] comes from a Gauss rule exact for quadratics (Gauss-Legendre on [-1, 1], Gauss-Hermite
+    for the standard normal), the kernel from the node coordinates; a weight off by the factor 3
+    misses by a factor 3."""
+    import workloads as W
+    from oracle import run
+    cfg = W.scaled_config(name, nodes=[3, 4], steps=[2, 2], n_per_level=[2, 1])
+    mesh = BoxMesh([4, 4, 4])
+    n = mesh.n_nodes
+    cfg["kl"]["n_modes"] = n
+    B = run.kl_basis(cfg, [BoxMesh([3, 3, 3]), mesh], max_rank=n, eps=0.0)
+    kc = cfg["kl"]
+    if kc.get("variables") == "uniform":
+        y, w = np.polynomial.legendre.leggauss(2)
+        ey2 = float((w * y * y).sum() / w.sum())
+    else:
+        y, w = np.polynomial.hermite_e.hermegauss(2)
+        ey2 = float((w * y * y).sum() / w.sum())
+    cov = (B["psi"] * B["sqrt_lam"] ** 2) @ B["psi"].T * ey2
+    x = mesh.nodes
+    d2 = ((x[:, None, :] - x[None, :, :]) ** 2).sum(-1)
+    s = kc["std"] * (kc["mean"] if cfg.get("model") == "iso" else 1.0)
+    ref = s * s * (np.exp(-d2 / kc["corr_len"]) if kc.get("kernel") == "sqexp" else np.exp(-np.sqrt(d2) / kc["corr_len"]))
+    assert np.abs(cov - ref).max() <= 1e-10 * s * s
+
+
+def test_truncated_route_eigenvalues_rise_to_the_dense_ones():
+    """The pivoted-Cholesky factor of rank R leaves the Schur complement C - L_R L_R^T, which is
+    positive semi-definite and shrinks as R grows; so the eigenvalues of eq. (redEig) at rank R
+    are bounded by those of eq. (algEig) and do not decrease with R (Weyl's monotonicity),
+    reaching them at full rank.  On a rough kernel (exponential, l = 0.1) a rank of twice the
+    number of modes falls far short."""
+    mesh = BoxMesh([7, 7, 7])
+    M = fem.assemble_mass(mesh)
+    k = 16
+    lam_d, _ = kl.kl_dense(mesh.nodes, M, 0.3, 0.1, k)
+    prev = np.zeros(k)
+    for R in (k, 2 * k, 4 * k, 8 * k, mesh.n_nodes):
+        L, _ = kl.pivoted_cholesky(mesh.nodes, 0.3, 0.1, R)
+        lam, _ = kl.kl_from_cholesky(L, M, k)
+        assert np.all(lam <= lam_d * (1 + 1e-12)) and np.all(lam >= prev * (1 - 1e-12)), R
+        prev = lam
+        if R == 2 * k:
+            assert (1.0 - lam / lam_d).max() > 0.1  # the rank-2M shortfall on this kernel
+    assert np.allclose(prev, lam_d, rtol=1e-10)
