@@ -5,12 +5,17 @@ One step = one pass of the whole path over one batch of synthetic input: the
 configured estimator end to end (sample points, KL synthesis, Crank-Nicolson /
 Newton / GMRES solves on every level and the coarse partner level, QoIs,
 level differences, estimator).  The KL basis and level set-up are one-time
-set-up outside the timed region; Monte Carlo normals are inputs and are
+set-up outside the timed region; sample points and normals are produced or
 resident in HBM before timing starts.
 
-Prints one JSON line (rank 0).  Metric: space-time DOF x inner iterations per
-second = sum over samples, steps and Newton iterations of n_l * (GMRES
-iterations), over wall time.
+Default workload: the batched uneven MLQMC estimator (c4, 9^3..129^3, 16 shifts) in
+mixed precision, with its FP64 companion run on the same sample plan: the line
+reports both passes' time to the same RMSE (one pass gives the estimate and its
+shift-based RMSE) and their ratio.
+
+Prints one JSON line.  Metric: space-time DOF x inner iterations per second =
+sum over samples, steps and Newton iterations of n_l * (GMRES iterations), over
+wall time, for the headline precision.
 """
 from __future__ import annotations
 
@@ -25,10 +30,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "space-time DOF·iters/s per GPU + MLQMC time-to-RMSE, mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per node-sample of the preconditioned Jacobian apply
-# w = v_j / eta_j + dt/2 K z: z, v_j and the two element coefficients (one
-# element per node) read, w written, in the inner precision
-APPLY_BYTES = {0: 5 * 8, 1: 5 * 4}
 APPLY_SOURCE = os.path.join(ROOT, "paper_2105_02007_amd", "csrc", "mlq_stencil3.hip")
 TET_APPLY_SOURCE = os.path.join(ROOT, "paper_2105_02007_amd", "csrc", "mlq_tet.hip")
 COPY_ELEMS = 1 << 27  # 1 GiB of FP64 for the counter calibration copy
@@ -97,119 +98,87 @@ WORKLOAD_TEXT = {
 }
 
 
-def cpu_baseline_tet(cfg, budget_s):
-    """The oracle on the coarsest shell: one sample (rule-based angle or mean vector field plus
-    a seeded random perturbation in place of the KL field), as many steps as the budget allows."""
+CPU_STEPS = 16  # time steps per sample of the CPU baseline (the first steps of every solve)
+
+
+def _cpu_job(args):
+    """One oracle solve for the CPU baseline (a worker of the process pool, one BLAS thread): the
+    sample's field is a seeded perturbation in place of the KL field (the KL set-up is not part of
+    the timed solve).  Returns (vertices, steps, oracle iterations, seconds)."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     import workloads as W
-    from oracle import stepper
-    from oracle.tetfem import TetMesh
-    lv = cfg["levels"][0]
-    m = W.tet_mesh(lv)
-    mesh = TetMesh(m["xyz"], m["tets"])
-    ph = cfg["physics"]
-    if cfg.get("model") == "vector":  # E[V] plus a seeded perturbation of each component
-        from oracle import fem
-        f0 = np.cos(m["theta0"])[:, None] * m["e_circ"] + np.sin(m["theta0"])[:, None] * m["e_long"]
-        V = ph["sigma_l"] * (f0 + 0.3 * W.random_nodal(cfg["seed"], 3, mesh.n_elems).T)
-        G = fem.conductivity(V, ph["sigma_t"])
-    elif cfg.get("model") == "iso":  # E[V] times a seeded perturbation, bounded below
-        from oracle import fem
-        v = cfg["kl"]["mean"] * (1.0 + 0.3 * W.random_nodal(cfg["seed"], 1, mesh.n_elems)[0])
-        G = fem.conductivity_iso(v, 3, ph["sigma_t"])
-    else:
-        th = m["theta0"] + 0.3 * W.random_nodal(cfg["seed"], 1, mesh.n_elems)[0]
-        G = mesh.conductivity(th, m["e_circ"], m["e_long"], ph["sigma_l"], ph["sigma_t"])
-    t0 = time.perf_counter()
-    steps = 2
-    while True:  # grow the step count until the budget is used (each run starts from u = 0)
-        t1 = time.perf_counter()
-        out = stepper.solve(mesh, G, ph, lv["n_steps"], tol=1e-13, stop_after=steps)
-        el = time.perf_counter() - t1
-        if time.perf_counter() - t0 + 2.5 * el > budget_s or steps >= lv["n_steps"]:
-            break
-        steps *= 2
-    n = mesh.n_nodes
-    return dict(value=n * out["lin_iters"] / el, unit="DOF·iters/s", cores=1, kind="oracle",
-                sample=f"1 sample of level 0 ({n} vertices, first {steps} of {lv['n_steps']} steps); single process; "
-                       f"GMRES iterations; KL set-up excluded (seeded perturbation of the rule-based angle); {el:.1f} s",
-                st_dof_per_s=n * steps / el, seconds=el)
+    from oracle import fem, run, stepper
+    name, l, i = args
+    cfg = W.config(name)
+    lv, ph = cfg["levels"][l], cfg["physics"]
+    steps = min(CPU_STEPS, lv["n_steps"])
+    with threadpool_limits(1):
+        if lv.get("kind") == "tet":
+            from oracle.tetfem import TetMesh
+            m = W.tet_mesh(lv)
+            mesh = TetMesh(m["xyz"], m["tets"])
+            r = W.random_nodal(cfg["seed"] + 1000 * l + i, 3, mesh.n_elems)
+            if cfg.get("model") == "vector":
+                f0 = np.cos(m["theta0"])[:, None] * m["e_circ"] + np.sin(m["theta0"])[:, None] * m["e_long"]
+                G = fem.conductivity(ph["sigma_l"] * (f0 + 0.3 * r.T), ph["sigma_t"])
+            elif cfg.get("model") == "iso":
+                G = fem.conductivity_iso(cfg["kl"]["mean"] * (1.0 + 0.3 * r[0]), 3, ph["sigma_t"])
+            else:
+                G = mesh.conductivity(m["theta0"] + 0.3 * r[0], m["e_circ"], m["e_long"], ph["sigma_l"],
+                                      ph["sigma_t"])
+            t0 = time.perf_counter()
+            out = stepper.solve(mesh, G, ph, lv["n_steps"], tol=1e-13, stop_after=steps)
+            el = time.perf_counter() - t0
+        else:
+            mesh = run.level_meshes(cfg)[l]
+            th = 0.3 * W.random_nodal(cfg["seed"] + 1000 * l + i, 1, mesh.n_elems)[0]
+            if cfg.get("model") == "iso":
+                th = cfg["kl"]["mean"] * (1.0 + th)
+            t0 = time.perf_counter()
+            out = run.solve_theta(mesh, th, ph, lv["n_steps"], stop_after=steps, model=cfg.get("model"))
+            el = time.perf_counter() - t0
+    return mesh.n_nodes, steps, out["lin_iters"], el
 
 
-def cpu_baseline(cfg, budget_s):
-    """The oracle on a bounded sample of the same workload (level 0 and 1 samples of its first two levels)."""
-    import numpy as np
-
-    import workloads as W
-    from oracle import run
-    if cfg["levels"][0].get("kind") == "tet":
-        return cpu_baseline_tet(cfg, budget_s)
-    meshes = run.level_meshes(cfg)
-    B = run.kl_basis(cfg, meshes, max_rank=2 * cfg["kl"]["n_modes"])
-    M = cfg["kl"]["n_modes"]
-    phys = cfg["physics"]
-    dof_iters, st_dof, n_solves = 0.0, 0.0, 0
-    t0 = time.perf_counter()
-    # level 0 and level 1 samples, interleaved so that a cut at the budget keeps both
-    plan = [(0, i) for i in range(8)]
-    if len(meshes) > 1:
-        for i in range(8):
-            plan += [(1, i), (0, 8 + i)]
-    done = []
-    draw = W.mc_uniforms if cfg["kl"].get("variables") == "uniform" else W.mc_normals
-    for l, i in plan:
-        if time.perf_counter() - t0 > budget_s:
-            break
-        Y = draw(cfg["seed"], l, i + 1, M)[:, i:i + 1]
-        th = run.sample_theta(B["phi"][l], B["sqrt_lam"], Y, run.level_theta0(cfg, meshes[l]))[0]
-        out = run.solve_theta(meshes[l], th, phys, cfg["levels"][l]["n_steps"], model=cfg.get("model"))
-        n = meshes[l].n_nodes
-        dof_iters += n * out["lin_iters"]
-        st_dof += n * cfg["levels"][l]["n_steps"]
-        n_solves += 1
-        done.append(l)
-    el = time.perf_counter() - t0
-    counts = {l: done.count(l) for l in sorted(set(done))}
-    desc = ", ".join(f"{c} sample(s) of level {l} ({'x'.join(map(str, cfg['levels'][l]['n']))} nodes, "
-                     f"{cfg['levels'][l]['n_steps']} steps)" for l, c in counts.items())
-    return dict(value=dof_iters / el, unit="DOF·iters/s", cores=1, kind="oracle",
-                sample=f"{desc}; single process; a direct sparse solve counts as one iteration, "
-                       f"GMRES iterations otherwise; KL set-up excluded; {el:.1f} s",
-                st_dof_per_s=st_dof / el, seconds=el)
-
-
-def qoi_vs_fp64(cfg, runner, res, dev, log, Ys=None, Yc=None, shifts=None, nq=4):
-    """The first nq samples of the finest level re-solved by the FP64 path (the same KL
-    set-up and the same points), against the mixed run's QoIs of those samples.  The FP64
-    path itself is pinned to the oracle (1e-10 per QoI) by the parity tests."""
-    import numpy as np
-    import torch
-
-    from paper_2105_02007_amd import mlq
-    from paper_2105_02007_amd.driver import ConfigRunner
-    L = len(cfg["levels"]) - 1
-    samp = cfg["sampling"]
-    if samp["kind"] == "combination":
-        Y = Yc
-    elif samp["kind"] in ("mc", "mlmc"):
-        Y = Ys[L]
-    else:
-        Y = runner.qmc_points(L, shifts[L])
-    nq = min(nq, Y.shape[1])
-    Y = Y[:, :nq].contiguous()
-    mixed_q = np.asarray(res["f_fine"][L][:nq])
-    log(f"FP64 re-solve of {nq} finest-level samples")
-    t0 = time.perf_counter()
-    r64 = ConfigRunner(cfg, prec=mlq.MLQ_FP64, device=dev, concurrent=False)
-    q64 = r64.solve(L, Y).cpu().numpy()
-    el = time.perf_counter() - t0
-    del r64
-    torch.cuda.empty_cache()
-    rel = np.abs(mixed_q - q64) / np.abs(q64)
-    return dict(level=L, samples=nq, max_rel_diff=float(rel.max()), mean_rel_diff=float(rel.mean()),
-                fp64_seconds=round(el, 1),
-                reference="FP64 GPU solve of the same samples (the FP64 path is pinned to the oracle at 1e-10)")
+def cpu_baseline(name, cfg, budget_s):
+    """The oracle timed on the host's cores, sample-parallel: one process per core (at most 16, the
+    GPU machine's share), one BLAS thread each, every worker solving seeded samples of the workload's
+    levels (coarsest first, as many levels as the budget allows; the first CPU_STEPS steps of each
+    solve).  Runs before the GPU is touched, so the pool can fork.  The oracle's iteration count is
+    its own: Krylov iterations on meshes above its direct-solver size, one per Newton step where it
+    factorises (so DOF·iters/s is not comparable with the GPU's; the space-time DOF rate is)."""
+    import multiprocessing as mp
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    levels = list(range(len(cfg["levels"])))
+    done, per_level = [], {}
+    t_all = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        for l in levels:
+            # estimate the level's cost from the previous one before committing the pool to it
+            if per_level and time.perf_counter() - t_all > 0.5 * budget_s:
+                break
+            t0 = time.perf_counter()
+            res = pool.map(_cpu_job, [(name, l, i) for i in range(cores)], chunksize=1)
+            el = time.perf_counter() - t0
+            done += res
+            n, steps = res[0][0], res[0][1]
+            per_level[l] = dict(vertices=n, steps=steps, samples=len(res), wall_s=round(el, 2),
+                                s_per_sample_step=round(sum(r[3] for r in res) / (len(res) * steps), 4))
+            if time.perf_counter() - t_all + 5.0 * el > budget_s:  # the next level costs about 5x
+                break
+    wall = sum(v["wall_s"] for v in per_level.values())
+    dof_iters = sum(r[0] * r[2] for r in done)
+    st_dof = sum(r[0] * r[1] for r in done)
+    desc = "; ".join(f"level {l}: {v['samples']} samples x first {v['steps']} steps, {v['vertices']} nodes"
+                     for l, v in per_level.items())
+    return dict(value=dof_iters / wall, unit="DOF·iters/s", cores=cores, kind="oracle",
+                sample=f"{desc}; one process per core, one BLAS thread each; seeded fields in place of the KL "
+                       f"field; {wall:.1f} s",
+                st_dof_per_s=st_dof / wall, seconds=round(wall, 2), levels=per_level,
+                iterations="the oracle's own: Krylov iterations above its direct-solver size, one per Newton "
+                           "step where it factorises")
 
 
 def kl_synthesis(runner, cfg, dev, reps=5):
@@ -247,18 +216,137 @@ def kl_synthesis(runner, cfg, dev, reps=5):
                 frac_hbm=round(gb / us * 1e6 / HBM_PEAK_GBS, 4))
 
 
+def make_step(cfg, runner, args, dev):
+    """The estimator pass of the workload and its inputs (resident on the device)."""
+    import torch
+
+    import workloads as W
+    samp = cfg["sampling"]
+    M = runner.n_modes
+    kind = samp["kind"]
+    draw = W.mc_uniforms if cfg["kl"].get("variables") == "uniform" else W.mc_normals
+    n_dims = M * int(cfg["kl"].get("components", 1))
+    if kind == "combination":
+        Yc = torch.as_tensor(draw(cfg["seed"], 0, max(samp["n_per_level"]), n_dims), device=dev)
+        if args.fields:
+            probes = field_probes(cfg, runner)
+            return lambda: runner.run_combination_fields(Yc, probes=probes)
+        return lambda: runner.run_combination(Yc)
+    if kind in ("mc", "mlmc"):
+        Ys = [torch.as_tensor(draw(cfg["seed"], l, n, n_dims), device=dev) for l, n in enumerate(samp["n_per_level"])]
+        if kind == "mc":
+            return lambda: runner.run_mc(Ys[0])
+        if args.fields:
+            probes = field_probes(cfg, runner)
+            return lambda: runner.run_mlmc_fields(Ys, probes=probes)
+        return lambda: runner.run_mlmc(Ys)
+    S = samp.get("n_shifts", 1)
+    shifts = [W.lattice_shifts(cfg["seed"], l, S, n_dims) for l in range(len(cfg["levels"]))]
+    return lambda: runner.run_mlqmc(shifts)
+
+
+def timed_passes(step, runner, steps, warmup, log, tag):
+    """warmup untimed passes, then `steps` timed ones between two device synchronisations; the
+    finest levels' apply launches are timed by HIP events on their streams meanwhile."""
+    import torch
+    for i in range(warmup):
+        step()
+        log(f"{tag}: warmup {i} done")
+    for L in runner.levels:
+        L.timing_enable(("apply",))
+        L.timing_read(reset=True)
+    runner.reset_counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = None
+    for i in range(steps):
+        res = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    log(f"{tag}: {steps} timed passes, {el / steps:.3f} s each")
+    per_level = []
+    for l, L in enumerate(runner.levels):
+        t = L.timing_read(reset=True)["apply"]
+        per_level.append(dict(level=l, nodes=L.n_nodes, apply_ms=round(t["ms"], 3), apply_launches=t["launches"],
+                              alg_bytes=round(t["bytes"]), kernel_bytes=round(t["kernel_bytes"]), units=t["units"]))
+        L.timing_enable(())
+    return el, res, per_level
+
+
+def roofline_of(cfg, runner, config_name, prec, per_level):
+    """The finest level's Jacobian apply, the kernel that carries most of the bytes: algorithmic
+    bytes (every operand once: 16 B per node-sample in FP32 plus the fused projections' basis reads)
+    over the summed HIP-event time of its launches."""
+    import workloads as W
+    top = per_level[-1]
+    ms, launches = top["apply_ms"], max(top["apply_launches"], 1)
+    alg, kb = float(top["alg_bytes"]), float(top["kernel_bytes"])
+    achieved = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    ratio = counter_traffic(config_name, "fp64" if prec == W.PREC_FP64 else "mixed", tet=runner.tet)
+    lvl = cfg["levels"][-1]
+    shape = (f"{lvl['cells'][0]}x{lvl['cells'][1]}x{lvl['cells'][2]} shell" if runner.tet
+             else "x".join(map(str, lvl["n"])))
+    kernel = ("k_tet_apply (Jacobian apply on the padded slot-major P1 pattern)" if runner.tet else
+              "k_wave3 (preconditioned Jacobian apply + fused projections)" if cfg["dim"] == 3 else
+              "k_apply_pk (2D preconditioned Jacobian apply)")
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=None if ratio is None else round(ratio * kb / launches),
+                kernel=f"{kernel}, finest level ({shape})",
+                alg_bytes_per_launch=round(alg / launches), alg_bytes_per_unit=round(alg / max(top["units"], 1.0), 2),
+                kernel_bytes_per_launch=round(kb / launches),
+                frac_kernel_bytes=round(kb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else 0.0,
+                avg_launch_us=round(1e3 * ms / launches, 2), launches=top["apply_launches"])
+
+
+def level_stats(runner, steps):
+    """Per level: its solves' DOF x iterations over their host wall time (the coarser levels run
+    concurrently, so their rates are while sharing the GPU), Newton and GMRES iterations per step."""
+    return [dict(level=l, dof_iters_per_s=(runner.level_dof_iters[l] / runner.level_seconds[l]
+                                           if runner.level_seconds[l] > 0 else None),
+                 seconds=round(runner.level_seconds[l] / max(steps, 1), 4),
+                 newton_per_step=round(runner.level_newton[l] / max(runner.level_sample_steps[l], 1.0), 3),
+                 gmres_per_step=round(runner.level_inner[l] / max(runner.level_sample_steps[l], 1.0), 2))
+            for l in range(len(runner.levels))]
+
+
+def compare_runs(cfg, a, b):
+    """Mixed-precision estimator a against the FP64 one b on the same sample plan: relative
+    differences of the estimate, the level means and every per-sample QoI, also relative to the
+    informative part T - QoI of the censored mean activation time."""
+    import numpy as np
+    T = cfg["physics"]["t_end"]
+    est_a, est_b = a["estimate"], b["estimate"]
+    out = dict(estimate_mixed=est_a, estimate_fp64=est_b, estimate_rel_diff=abs(est_a - est_b) / abs(est_b))
+    if cfg["qoi"] == 1:
+        out["estimate_diff_rel_to_T_minus_qoi"] = abs(est_a - est_b) / abs(T - est_b)
+    lm = [abs(x - y) / abs(y) for x, y in zip(a["level_mean"], b["level_mean"]) if y != 0.0]
+    out["level_mean_max_rel_diff"] = max(lm) if lm else 0.0
+    diffs, scale = [], []
+    for fa, fb in [(a["f_fine"], b["f_fine"]), (a.get("f_coarse") or [], b.get("f_coarse") or [])]:
+        for x, y in zip(fa, fb):
+            if x is None or y is None:
+                continue
+            x, y = np.asarray(x), np.asarray(y)
+            diffs.append(np.abs(x - y).max())
+            scale.append(np.abs(y).min())
+    out["per_sample_max_abs_diff"] = float(max(diffs)) if diffs else 0.0
+    out["per_sample_max_rel_diff"] = float(max(d / s for d, s in zip(diffs, scale))) if diffs else 0.0
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--config", default="c4", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--prec", choices=["fp64", "mixed"], default=None)
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--companion-steps", type=int, default=3,
+                    help="timed passes of the FP64 companion of a mixed-precision run (0: no companion)")
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="extra untimed pass timing every kernel class")
-    ap.add_argument("--no-qoi-check", action="store_true",
-                    help="skip the FP64 re-solve of a few finest-level samples after a mixed-precision run")
     ap.add_argument("--newton-guess", choices=["previous", "extrapolate", "reference", "reference-local"],
                     default="extrapolate",
                     help="Newton initial guess of each step: u_k, 2 u_k - u_(k-1), or from the unperturbed "
@@ -277,54 +365,33 @@ def main():
               "(samples would shard across GPUs with one all-reduce of the estimator sums).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    import workloads as W
+    cfg = W.config(args.config)
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:  # before any GPU call: the worker pool forks
+        log("timing the CPU oracle")
+        cpu = cpu_baseline(args.config, cfg, args.cpu_seconds)
+        log(f"CPU oracle: {cpu['sample']}")
+
     import torch
 
-    import workloads as W
     from paper_2105_02007_amd import mlq
     from paper_2105_02007_amd.driver import ConfigRunner
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     dev = "cuda:0"
-    cfg = W.config(args.config)
     prec = cfg["prec"] if args.prec is None else (W.PREC_FP64 if args.prec == "fp64" else W.PREC_MIXED)
-    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
-    t_setup = time.perf_counter()
     guess = {"previous": mlq.MLQ_GUESS_PREVIOUS, "extrapolate": mlq.MLQ_GUESS_EXTRAPOLATE,
              "reference": mlq.MLQ_GUESS_REFERENCE, "reference-local": mlq.MLQ_GUESS_REFERENCE_LOCAL}[args.newton_guess]
+    t_setup = time.perf_counter()
     runner = ConfigRunner(cfg, prec=prec, device=dev, log=log, newton_guess=guess, inner_tol=args.inner_tol)
     t_setup = time.perf_counter() - t_setup
     log(f"set-up done in {t_setup:.1f} s (KL rank {runner.kl_rank})")
     runner.log = log
     samp = cfg["sampling"]
-    M = runner.n_modes
-    kind = samp["kind"]
-    Ys = Yc = shifts = None
-    draw = W.mc_uniforms if cfg["kl"].get("variables") == "uniform" else W.mc_normals
-    n_dims = M * int(cfg["kl"].get("components", 1))
-    if kind == "combination":
-        Yc = torch.as_tensor(draw(cfg["seed"], 0, max(samp["n_per_level"]), n_dims), device=dev)
-        if args.fields:
-            probes = field_probes(cfg, runner)
-            step = lambda: runner.run_combination_fields(Yc, probes=probes)
-        else:
-            step = lambda: runner.run_combination(Yc)
-    elif kind in ("mc", "mlmc"):
-        Ys = [torch.as_tensor(draw(cfg["seed"], l, n, n_dims), device=dev)
-              for l, n in enumerate(samp["n_per_level"])]
-        if kind == "mc":
-            step = lambda: runner.run_mc(Ys[0])
-        elif args.fields:
-            probes = field_probes(cfg, runner)
-            step = lambda: runner.run_mlmc_fields(Ys, probes=probes)
-        else:
-            step = lambda: runner.run_mlmc(Ys)
-    else:
-        S = samp.get("n_shifts", 1)
-        shifts = [W.lattice_shifts(cfg["seed"], l, S, n_dims) for l in range(len(cfg["levels"]))]
-        step = lambda: runner.run_mlqmc(shifts)
-
+    step = make_step(cfg, runner, args, dev)
     if args.fields:
         runner.prepare_fields(field_probes(cfg, runner))
         log("field transfer set-up done")
@@ -334,57 +401,12 @@ def main():
         torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    for i in range(args.warmup):
-        step()
-        log(f"warmup {i} done")
-    for L in runner.levels:
-        L.timing_enable(("apply",))
-        L.timing_read(reset=True)
-    runner.reset_counters()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = None
-    for _ in range(args.steps):
-        res = step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el, res, per_level = timed_passes(step, runner, args.steps, args.warmup, log, "main")
     dof_iters, st_dof = runner.dof_iters, runner.st_dof
-
-    # dominant kernel: the Jacobian apply of the finest level (most of the bytes; its solves
-    # run with the GPU to themselves, the coarser levels' solves share it with each other)
-    per_level = []
-    for l, L in enumerate(runner.levels):
-        t = L.timing_read(reset=True)["apply"]
-        per_level.append(dict(level=l, nodes=L.n_nodes, apply_ms=round(t["ms"], 3), apply_launches=t["launches"],
-                              alg_bytes=round(t["bytes"]), units=t["units"]))
-        L.timing_enable(())
-    top = per_level[-1]
-    apply_ms, apply_bytes, apply_units, apply_launches = (top["apply_ms"], float(top["alg_bytes"]), top["units"],
-                                                          top["apply_launches"])
-    # the library reports the algorithmic bytes of every apply launch (with the
-    # Gram-Schmidt projections fused in, the basis vectors they read count too)
-    alg_bytes = apply_bytes if apply_bytes > 0 else apply_units * APPLY_BYTES[prec]
-    per_launch = alg_bytes / max(apply_launches, 1)
-    achieved = alg_bytes / (apply_ms * 1e-3) / 1e9 if apply_ms > 0 else 0.0
-    ratio = counter_traffic(args.config, "fp64" if prec == W.PREC_FP64 else "mixed", tet=runner.tet)
-    lvl = cfg["levels"][-1]
-    shape = (f"{lvl['cells'][0]}x{lvl['cells'][1]}x{lvl['cells'][2]} shell" if runner.tet
-             else "x".join(map(str, lvl["n"])))
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=None if ratio is None else round(ratio * per_launch),
-                    kernel=("k_tet_apply (Jacobian apply on the padded slot-major P1 pattern)"
-                            if runner.tet else
-                            "k_wave3 (preconditioned Jacobian apply + fused projections)"
-                            if cfg["dim"] == 3 else
-                            "k_apply_pk (2D preconditioned Jacobian apply)") + f", finest level ({shape})",
-                    bytes_per_node_sample=round(alg_bytes / max(apply_units, 1.0), 2),
-                    alg_bytes_per_launch=round(per_launch),
-                    alg_bytes_total=round(alg_bytes),
-                    avg_launch_us=round(1e3 * apply_ms / max(apply_launches, 1), 2),
-                    launches=apply_launches)
+    roofline = roofline_of(cfg, runner, args.config, prec, per_level)
     for p_ in per_level:
         p_.pop("units")
+    levels = level_stats(runner, args.steps)
 
     breakdown = None
     if args.breakdown:
@@ -402,6 +424,7 @@ def main():
             L.timing_enable(())
         breakdown = dict(wall_ms=round(tb * 1e3, 1), kernel_ms={c: round(v, 2) for c, v in tot.items()})
 
+    has_rmse = not (samp["kind"] == "combination" or (samp["kind"] in ("qmc", "mlqmc") and samp.get("n_shifts", 1) < 2))
     line = {
         "metric": METRIC, "value": dof_iters / el, "unit": "DOF·iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
@@ -411,74 +434,79 @@ def main():
                 "lattice or Halton points)",
         "config": {"workload": f"{args.config}: {WORKLOAD_TEXT[args.config]}", "levels": len(cfg["levels"]),
                    "samples_per_level": samp["n_per_level"], "n_shifts": samp.get("n_shifts", 1),
+                   "precision": "mixed: FP32 KL synthesis, operator and Krylov; FP64 residual, Newton update, QoIs "
+                                "and estimator" if prec == W.PREC_MIXED else "FP64 throughout",
                    "parallelism": "single GPU, samples batched per level"},
         "st_dof_per_s": st_dof / el,
-        # no error estimate: the combination form over nested point sets, or a QMC rule
-        # with a single random shift
         "estimate": res["estimate"],
-        "rmse_est": None if samp["kind"] == "combination" or (samp["kind"] in ("qmc", "mlqmc")
-                                                            and samp.get("n_shifts", 1) < 2) else res["rmse"],
+        # no error estimate: the combination form over nested point sets, or a QMC rule with one shift
+        "rmse_est": res["rmse"] if has_rmse else None,
         "level_means": res["level_mean"],
         "kl": {"rank": runner.kl_rank, "trace_resid": runner.kl_resid},
         "setup_s": round(t_setup, 2),
         "roofline": roofline,
         "apply_per_level": per_level,
+        "levels": levels,
+        "newton_guess": args.newton_guess,
+        "lanes_x": [getattr(L, "lanes_x", None) for L in runner.levels],
+        "inner_tol": runner.levels[-1].desc.inner_tol,
     }
-    if args.fields and runner.tet:
-        eu, ep = res["mean_u"], res["mean_probe"]
-        line["fields"] = {
-            "u_grid": list(eu.shape), "u_bytes": eu.numel() * 8,
-            "probes": [list(map(float, p)) for p in field_probes(cfg, runner)],
-            "mean_action_potential": {f"{f:g}T": [float(x) for x in ep[:, int(round(f * (ep.shape[1] - 1)))].cpu()]
-                                      for f in (0.25, 0.5, 1.0)},
-        }
-    elif args.fields:
-        # the domain mean of the estimated activation map equals the scalar estimate (the
-        # transfer is the Q1 interpolant, which the lumped node weights integrate exactly)
-        fl = cfg["levels"][-1]
-        w1 = []
-        for a in range(cfg["dim"]):
-            h = (fl["hi"][a] - fl["lo"][a]) / (fl["n"][a] - 1)
-            v = torch.full((fl["n"][a],), h, dtype=torch.float64, device=dev)
-            v[0] = v[-1] = 0.5 * h
-            w1.append(v)
-        wts = w1[0]
-        for v in w1[1:]:
-            wts = (v[:, None] * wts[None, :]).reshape(-1)
-        ea, eu, ep = res["mean_act_map"], res["mean_u"], res["mean_probe"]
-        act_mean = float((wts * ea).sum() / wts.sum())
-        line["fields"] = {
-            "u_grid": list(eu.shape), "u_bytes": eu.numel() * 8,
-            "act_map_domain_mean": act_mean,
-            # per level: ||mean_0|| and ||mean_l - T mean_(l-1)|| in L^2((0,T); L^2), L^2((0,T); H^1)
-            "level_term_norms_l2_h1": res["level_term_norms"],
-            "act_map_mean_minus_estimate": act_mean - res["estimate"],
-            "probes": FIELD_PROBES,
-            # the mean action potential at the probes at a quarter, half and all of [0, T]
-            "mean_action_potential": {f"{f:g}T": [float(x) for x in ep[:, int(round(f * (ep.shape[1] - 1)))].cpu()]
-                                      for f in (0.25, 0.5, 1.0)},
-        }
-    # per level: its solves' DOF x iterations over their host wall time (the coarser levels
-    # run concurrently, so their rates are while sharing the GPU)
-    line["levels"] = [dict(level=l, dof_iters_per_s=(runner.level_dof_iters[l] / runner.level_seconds[l]
-                                                     if runner.level_seconds[l] > 0 else None),
-                           seconds=round(runner.level_seconds[l] / max(args.steps, 1), 4),
-                           newton_per_step=round(runner.level_newton[l] / runner.level_sample_steps[l], 3),
-                           gmres_per_step=round(runner.level_inner[l] / runner.level_sample_steps[l], 2))
-                      for l in range(len(runner.levels))]
-    line["newton_guess"] = args.newton_guess
-    line["lanes_x"] = [getattr(L, "lanes_x", None) for L in runner.levels]
-    line["inner_tol"] = runner.levels[-1].desc.inner_tol
+    if args.fields:
+        line["fields"] = fields_summary(cfg, runner, res, dev)
     if breakdown:
         line["breakdown"] = breakdown
     line["kl_synthesis"] = kl_synthesis(runner, cfg, dev)
-    if prec == W.PREC_MIXED and not args.no_qoi_check and not runner.tet:
-        line["qoi_vs_fp64"] = qoi_vs_fp64(cfg, runner, res, dev, log, Ys, Yc, shifts)
     runner.log = None
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle")
-        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    if prec == W.PREC_MIXED and args.companion_steps > 0:
+        # the FP64 GPU path on the same sample plan: the same estimator to the same RMSE
+        del runner, step
+        torch.cuda.empty_cache()
+        t64 = time.perf_counter()
+        r64 = ConfigRunner(cfg, prec=W.PREC_FP64, device=dev, log=log, newton_guess=guess)
+        t64 = time.perf_counter() - t64
+        step64 = make_step(cfg, r64, args, dev)
+        el64, res64, pl64 = timed_passes(step64, r64, args.companion_steps, 1, log, "fp64 companion")
+        cmp_ = compare_runs(cfg, res, res64)
+        mixed_s, fp64_s = el / args.steps, el64 / args.companion_steps
+        line["time_to_rmse"] = dict(
+            rmse_mixed=res["rmse"] if has_rmse else None, rmse_fp64=res64["rmse"] if has_rmse else None,
+            mixed_s=round(mixed_s, 4), fp64_s=round(fp64_s, 4), fp64_over_mixed=round(fp64_s / mixed_s, 3),
+            fp64_passes=args.companion_steps, fp64_value=r64.dof_iters / el64, fp64_setup_s=round(t64, 2),
+            fp64_apply_frac=roofline_of(cfg, r64, args.config, W.PREC_FP64, pl64)["frac"],
+            **cmp_)
+        del r64, step64
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
+
+
+def fields_summary(cfg, runner, res, dev):
+    """Field quantities of interest of --fields: grid sizes, the mean action potential at the probes,
+    and on boxes the domain mean of the activation map against the scalar estimate."""
+    import torch
+    eu, ep = res["mean_u"], res["mean_probe"]
+    out = {"u_grid": list(eu.shape), "u_bytes": eu.numel() * 8,
+           "mean_action_potential": {f"{f:g}T": [float(x) for x in ep[:, int(round(f * (ep.shape[1] - 1)))].cpu()]
+                                     for f in (0.25, 0.5, 1.0)}}
+    if runner.tet:
+        out["probes"] = [list(map(float, p)) for p in field_probes(cfg, runner)]
+        return out
+    # the domain mean of the estimated activation map equals the scalar estimate (the transfer is
+    # the Q1 interpolant, which the lumped node weights integrate exactly)
+    fl = cfg["levels"][-1]
+    w1 = []
+    for a in range(cfg["dim"]):
+        h = (fl["hi"][a] - fl["lo"][a]) / (fl["n"][a] - 1)
+        v = torch.full((fl["n"][a],), h, dtype=torch.float64, device=dev)
+        v[0] = v[-1] = 0.5 * h
+        w1.append(v)
+    wts = w1[0]
+    for v in w1[1:]:
+        wts = (v[:, None] * wts[None, :]).reshape(-1)
+    act_mean = float((wts * res["mean_act_map"]).sum() / wts.sum())
+    out.update(act_map_domain_mean=act_mean, act_map_mean_minus_estimate=act_mean - res["estimate"],
+               level_term_norms_l2_h1=res["level_term_norms"], probes=FIELD_PROBES)
+    return out
 
 
 if __name__ == "__main__":

@@ -481,8 +481,14 @@ typedef struct {
   double ms[16];        /* summed kernel time per class */
   int64_t launches[16]; /* launches per class */
   double units[16];     /* node-samples processed per class */
-  double bytes[16];     /* algorithmic bytes per class (MLQ_K_APPLY only; 0 elsewhere): the
-                           operand bytes the launches must read and write at least once */
+  double bytes[16];     /* algorithmic bytes per class (MLQ_K_APPLY only; 0 elsewhere): every
+                           operand read or written once per launch -- boxes: x, y, d (or v_j) and
+                           the element's field value per node-sample, plus the basis vectors of
+                           the fused projections; tetrahedra: x, y, d per vertex-sample and the
+                           field value per tetrahedron-sample */
+  double kernel_bytes[16]; /* the bytes the kernels' own data layout reads and writes once
+                           (MLQ_K_APPLY only): e.g. assembled stiffness values in place of the
+                           field on tetrahedra */
 } mlq_timing;
 
 /* Times the kernel classes whose bit is set in kernel_mask (0 turns timing off)

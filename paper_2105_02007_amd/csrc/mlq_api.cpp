@@ -90,7 +90,7 @@ struct mlq_level {
   mlq_timing tim{};
   struct Pending {
     int cls;
-    double units, bytes, bytes_fixed;
+    double units, bytes, kbytes, kbytes_fixed;
     const int32_t* count;  // host count of active samples the per-sample figures scale with
     hipEvent_t a, b;
   };
@@ -115,10 +115,11 @@ hipEvent_t take_event(mlq_level* lv) {
 
 // Brackets one launch with events when its class is timed.  units and bytes are totals,
 // or, with count set, per active sample: the launch's figures are then resolved when the
-// count (a pinned host slot filled by an asynchronous copy) is known, at harvest.
+// count (a pinned host slot filled by an asynchronous copy) is known, at harvest.  bytes are
+// the algorithmic bytes, kbytes (+ kbytes_fixed per launch) what the kernel's own design moves.
 template <typename F>
 void timed(mlq_level* lv, int cls, double units, hipStream_t s, F&& launch, double bytes = 0.0,
-           const int32_t* count = nullptr, double bytes_fixed = 0.0) {
+           const int32_t* count = nullptr, double kbytes = 0.0, double kbytes_fixed = 0.0) {
   if (!(lv->tmask & (1u << cls))) {
     launch();
     return;
@@ -131,7 +132,7 @@ void timed(mlq_level* lv, int cls, double units, hipStream_t s, F&& launch, doub
   (void)hipEventRecord(a, s);
   launch();
   (void)hipEventRecord(b, s);
-  lv->pending.push_back({cls, units, bytes, bytes_fixed, count, a, b});
+  lv->pending.push_back({cls, units, bytes, kbytes, kbytes_fixed, count, a, b});
 }
 
 // After a stream synchronisation: fold finished event pairs into the totals.
@@ -143,7 +144,8 @@ void harvest(mlq_level* lv) {
       lv->tim.ms[p.cls] += ms;
       lv->tim.launches[p.cls] += 1;
       lv->tim.units[p.cls] += p.units * n;
-      lv->tim.bytes[p.cls] += p.bytes * n + p.bytes_fixed;
+      lv->tim.bytes[p.cls] += p.bytes * n;
+      lv->tim.kernel_bytes[p.cls] += p.kbytes * n + p.kbytes_fixed;
     }
     lv->free_events.push_back(p.a);
     lv->free_events.push_back(p.b);
@@ -792,12 +794,18 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
         // 3D boxes, j < 8: the apply kernel also forms the projections w . v_i (i <= j)
         const bool fuse = g.dim == 3 && !tet && j < 8;
         const double ti = mixed ? 4.0 : 8.0;
-        // algorithmic bytes per active sample.  Boxes: z, v_j, the element coefficients
-        // (p, q) read, w written; fused: v_0..v_{j-1} read.  Tetrahedra: per row the
-        // stiffness values of its slots, z and d read, w written; the shared pattern
-        // (columns, mass) once per launch.
+        // Algorithmic bytes per active sample, each operand once: boxes z, v_j and the
+        // element's field value theta read, w written (one element per node), v_0..v_{j-1}
+        // read for the fused projections; tetrahedra z, d read, w written per vertex and theta
+        // once per tetrahedron.  The kernel's own bytes: boxes read the element coefficient
+        // pair (p, q) instead of theta; tetrahedra read the assembled stiffness values of
+        // every slot of a row instead of theta, and the shared pattern (columns, mass) once
+        // per launch.
         const double slots = tet ? (double)td.nell / (double)td.nv : 0.0;
-        const double apply_bytes = nn * ti * (tet ? slots + 3.0 : 5.0 + (fuse ? j : 0));
+        const double apply_bytes =
+            tet ? ti * (3.0 * nn + (td.model == MLQ_DIFF_VECTOR ? 3.0 : 1.0) * (double)level->P)
+                : nn * ti * (4.0 + (fuse ? j : 0));
+        const double apply_kbytes = nn * ti * (tet ? slots + 3.0 : 5.0 + (fuse ? j : 0));
         const double apply_fixed = tet ? (double)td.nell * (4.0 + ti) : 0.0;
         timed(
             level, MLQ_K_APPLY, nn, s,
@@ -810,7 +818,7 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
               else
                 launch_apply_pk(g, w, j, 0.5 * dt, batch, mixed, s);
             },
-            apply_bytes, nin, apply_fixed);
+            apply_bytes, nin, apply_kbytes, apply_fixed);
         if (!fuse) timed(level, MLQ_K_DOTS, nn, s, [&] { launch_dots(g, w, j, batch, mixed, s); }, 0.0, nin);
         timed(level, MLQ_K_ORTH, nn, s,
               [&] { launch_orth(g, w, j, batch, mixed, s, fuse ? w.nwav : w.nred); }, 0.0, nin);

@@ -81,7 +81,7 @@ class KlDesc(C.Structure):
 
 class Timing(C.Structure):
     _fields_ = [("ms", C.c_double * 16), ("launches", C.c_int64 * 16), ("units", C.c_double * 16),
-                ("bytes", C.c_double * 16)]
+                ("bytes", C.c_double * 16), ("kernel_bytes", C.c_double * 16)]
 
 
 class EstimateOut(C.Structure):
@@ -414,7 +414,8 @@ class Level:
     def timing_read(self, reset=True):
         t = Timing()
         check(lib.mlq_timing_read(self.handle, C.byref(t), 1 if reset else 0))
-        return {c: dict(ms=t.ms[i], launches=int(t.launches[i]), units=t.units[i], bytes=t.bytes[i])
+        return {c: dict(ms=t.ms[i], launches=int(t.launches[i]), units=t.units[i], bytes=t.bytes[i],
+                        kernel_bytes=t.kernel_bytes[i])
                 for i, c in enumerate(KERNEL_CLASSES)}
 
     def apply(self, theta, x, d, y=None):
