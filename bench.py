@@ -356,6 +356,9 @@ def main():
     ap.add_argument("--fields", action="store_true",
                     help="MLMC workloads: also estimate the field quantities of interest (mean space-time "
                          "potential on the finest grid, mean activation map, mean action potential at 4 points)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch autotuner (lane layout by grid width, one GMRES launch sequence per "
+                         "iteration, whole batches)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB FP64 copy (torch.neg) before warm-up, as a counter reference")
     args = ap.parse_args()
@@ -386,7 +389,8 @@ def main():
     guess = {"previous": mlq.MLQ_GUESS_PREVIOUS, "extrapolate": mlq.MLQ_GUESS_EXTRAPOLATE,
              "reference": mlq.MLQ_GUESS_REFERENCE, "reference-local": mlq.MLQ_GUESS_REFERENCE_LOCAL}[args.newton_guess]
     t_setup = time.perf_counter()
-    runner = ConfigRunner(cfg, prec=prec, device=dev, log=log, newton_guess=guess, inner_tol=args.inner_tol)
+    runner = ConfigRunner(cfg, prec=prec, device=dev, log=log, newton_guess=guess, inner_tol=args.inner_tol,
+                          tune_launch=not args.no_tune)
     t_setup = time.perf_counter() - t_setup
     log(f"set-up done in {t_setup:.1f} s (KL rank {runner.kl_rank})")
     runner.log = log
@@ -424,6 +428,29 @@ def main():
             L.timing_enable(())
         breakdown = dict(wall_ms=round(tb * 1e3, 1), kernel_ms={c: round(v, 2) for c, v in tot.items()})
 
+    launch_tuning = None
+    if not args.no_tune:
+        # the same pass once more with every level at the untuned configuration
+        from paper_2105_02007_amd import tune
+        tuned = [dict(L.tuning) for L in runner.levels]
+        for L in runner.levels:
+            box3 = L.desc.mesh_kind == mlq.MLQ_MESH_Q1_BOX and L.desc.dim == 3
+            tune.apply_config(L, dict(lanes_x=(16 if L.desc.n[0] >= 48 else 8) if box3 else 0, gmres_block=0,
+                                      chunk=int(L.desc.max_batch)))
+        torch.cuda.synchronize()
+        tu = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        tu = time.perf_counter() - tu
+        for L, t in zip(runner.levels, tuned):
+            tune.apply_config(L, t)
+        launch_tuning = dict(
+            tuned_pass_s=round(el / args.steps, 4), untuned_pass_s=round(tu, 4),
+            levels=[dict(level=l, lanes_x=t["lanes_x"], gmres_block=t["gmres_block"], chunk=t["chunk"],
+                         cached=t.get("cached", False), trials_ms=t.get("trials_ms"))
+                    for l, t in enumerate(tuned)])
+        log(f"untuned pass {tu:.3f} s, tuned {el / args.steps:.3f} s")
+
     has_rmse = not (samp["kind"] == "combination" or (samp["kind"] in ("qmc", "mlqmc") and samp.get("n_shifts", 1) < 2))
     line = {
         "metric": METRIC, "value": dof_iters / el, "unit": "DOF·iters/s", "n_gpus": 1,
@@ -451,6 +478,8 @@ def main():
         "lanes_x": [getattr(L, "lanes_x", None) for L in runner.levels],
         "inner_tol": runner.levels[-1].desc.inner_tol,
     }
+    if launch_tuning:
+        line["launch_tuning"] = launch_tuning
     if args.fields:
         line["fields"] = fields_summary(cfg, runner, res, dev)
     if breakdown:
@@ -462,7 +491,8 @@ def main():
         del runner, step
         torch.cuda.empty_cache()
         t64 = time.perf_counter()
-        r64 = ConfigRunner(cfg, prec=W.PREC_FP64, device=dev, log=log, newton_guess=guess)
+        r64 = ConfigRunner(cfg, prec=W.PREC_FP64, device=dev, log=log, newton_guess=guess,
+                           tune_launch=not args.no_tune)
         t64 = time.perf_counter() - t64
         step64 = make_step(cfg, r64, args, dev)
         el64, res64, pl64 = timed_passes(step64, r64, args.companion_steps, 1, log, "fp64 companion")

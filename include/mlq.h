@@ -235,6 +235,17 @@ typedef struct {
  * mlq_workspace_bytes after a change.  MLQ_EINVAL for other values or levels. */
 mlq_status mlq_set_lane_layout(mlq_level* level, int32_t lanes_x);
 
+/* GMRES launch schedule of the level's solves (a tuning knob, Section 3.3's Krylov iteration):
+ * iterations = 0 launches the GMRES iterations one at a time and reads each iteration's count of
+ * still-active samples on the host (one read per iteration, one iteration behind the launches);
+ * iterations = J (1..64) runs them in blocks of J captured once into a HIP graph (per workspace,
+ * field array, batch and block) and replayed, with one count read per block, one block behind.
+ * Samples that have converged skip the work of every later iteration in either schedule, so the
+ * results are the same bit for bit; a block costs up to J - 1 iterations of launches that find no
+ * active sample.  Captured launches are not timed (mlq_timing_enable).  MLQ_EINVAL for other
+ * values. */
+mlq_status mlq_set_gmres_block(mlq_level* level, int32_t iterations);
+
 /* Reference space-time solution for the Newton guesses MLQ_GUESS_REFERENCE(_LOCAL): ref_dev
  * is (n_steps + 1) x n FP64 on the device, e.g. the u_sum of a one-sample solve of the
  * unperturbed field; the level keeps the pointer (the caller keeps the memory alive while it

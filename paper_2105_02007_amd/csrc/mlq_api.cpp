@@ -96,6 +96,16 @@ struct mlq_level {
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> free_events;
+  // GMRES iterations per captured graph (0: launched and steered one iteration at a time)
+  int gmres_block = 0;
+  struct BlockGraph {
+    const void* ws;
+    const void* theta;
+    int32_t batch, j0, jn;
+    hipGraphExec_t exec;
+  };
+  std::vector<BlockGraph> graphs;
+  hipStream_t cap_stream = nullptr;  // the level's own stream for capturing (the null stream cannot capture)
 };
 
 namespace {
@@ -151,6 +161,41 @@ void harvest(mlq_level* lv) {
     lv->free_events.push_back(p.b);
   }
   lv->pending.clear();
+}
+
+// Graph of the GMRES launches of iterations j0 .. j0 + jn - 1 for one workspace, field and
+// batch: captured from the launches once, then replayed.  The launches read no host state that
+// changes between replays (every per-step quantity of the iteration lives in the workspace).
+template <typename F>
+mlq_status block_graph(mlq_level* lv, const void* ws, const void* theta, int32_t batch, int j0, int jn, hipStream_t s,
+                       hipGraphExec_t* out, F&& launches) {
+  for (const auto& gr : lv->graphs)
+    if (gr.ws == ws && gr.theta == theta && gr.batch == batch && gr.j0 == j0 && gr.jn == jn) {
+      *out = gr.exec;
+      return MLQ_OK;
+    }
+  // capture on the level's own stream (any stream records the same launches; the caller's may be
+  // the null stream, which cannot capture); the graph is launched on the caller's stream
+  (void)s;
+  if (lv->cap_stream == nullptr) HIP_OK(hipStreamCreateWithFlags(&lv->cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  HIP_OK(hipStreamBeginCapture(lv->cap_stream, hipStreamCaptureModeRelaxed));
+  launches(lv->cap_stream);
+  hipError_t e = hipGetLastError();
+  const hipError_t ee = hipStreamEndCapture(lv->cap_stream, &graph);
+  if (e == hipSuccess) e = ee;
+  hipGraphExec_t exec = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (graph != nullptr) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(MLQ_EHIP, "capturing the GMRES block failed: %s", hipGetErrorString(e));
+  lv->graphs.push_back({ws, theta, batch, j0, jn, exec});
+  *out = exec;
+  return MLQ_OK;
+}
+
+void drop_graphs(mlq_level* lv) {
+  for (auto& gr : lv->graphs) (void)hipGraphExecDestroy(gr.exec);
+  lv->graphs.clear();
 }
 
 }  // namespace
@@ -399,6 +444,8 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   g.Hx = hx;
   g.Hy = hy;
   g.Hz = hz;
+  g.iso = desc->diffusion == MLQ_DIFF_ISO ? 1 : 0;
+  g.cfa = g.iso ? desc->sigma_t : 0.5 * (desc->sigma_l - desc->sigma_t);
   if (desc->diffusion == MLQ_DIFF_ISO) {
     g.cx0 = g.cy0 = g.cz0 = 0.0;
     g.cx1 = g.cy1 = g.cz1 = 1.0;
@@ -597,6 +644,8 @@ void mlq_destroy_level(mlq_level* level) {
   for (hipEvent_t e : level->flag_ev)
     if (e) (void)hipEventDestroy(e);
   if (level->host_flags) (void)hipHostFree(level->host_flags);
+  drop_graphs(level);
+  if (level->cap_stream) (void)hipStreamDestroy(level->cap_stream);
   delete level;
 }
 
@@ -654,6 +703,11 @@ mlq_status mlq_apply(mlq_level* level, const void* theta_dev, int32_t batch, con
     return MLQ_OK;
   }
   const bool iso = level->d.diffusion == MLQ_DIFF_ISO;
+  if (level->geo.dim == 3 && level->mixed) {  // the kernel forms the coefficients from theta
+    launch_apply_full3(level->geo, theta_dev, x_dev, d_dev, y_dev, 0.5 * level->io.dt, batch, true, s);
+    HIP_OK(hipGetLastError());
+    return MLQ_OK;
+  }
   launch_coefs(theta_dev, w.coef, level->P, batch, iso ? level->d.sigma_t : 0.5 * (level->d.sigma_l - level->d.sigma_t),
                iso, level->mixed, s);
   if (level->geo.dim == 3)
@@ -717,9 +771,10 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
 
   const bool tet = level->tet;
   const TetDev& td = level->td;
+  w.theta = theta_dev;
   if (tet)
     launch_tet_assemble(td, theta_dev, w.coef, batch, d.sigma_t, d.sigma_l - d.sigma_t, mixed, s);
-  else
+  else  // (mixed 3D boxes: for the residual and right-hand side; the Krylov apply reads theta)
     launch_coefs(theta_dev, w.coef, level->P, batch,
                  d.diffusion == MLQ_DIFF_ISO ? d.sigma_t : 0.5 * (d.sigma_l - d.sigma_t), d.diffusion == MLQ_DIFF_ISO,
                  mixed, s);
@@ -783,9 +838,18 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
       int32_t* const cnt = level->host_flags + kFlagInner;
       level->host_flags[1] = active;  // slot 0 is refilled by the next Newton check before harvest
       auto entering = [&](int j) -> const int32_t* { return j == 0 ? &level->host_flags[1] : &cnt[j - 1]; };
-      for (int j = 0; j < kmax; ++j) {
+      // The launches of GMRES iteration j (preconditioner, apply with the fused projections,
+      // projections, orthogonalisation, Givens rotation + active count); untimed while captured.
+      auto gmres_iteration = [&](int j, bool capturing, hipStream_t s) {
         const int32_t* nin = entering(j);
-        timed(level, MLQ_K_PRECOND, nn, s, [&] {
+        auto tm = [&](int cls, double units, auto&& launch, double bytes = 0.0, const int32_t* count = nullptr,
+                      double kbytes = 0.0, double kfixed = 0.0) {
+          if (capturing)
+            launch();
+          else
+            timed(level, cls, units, s, launch, bytes, count, kbytes, kfixed);
+        };
+        tm(MLQ_K_PRECOND, nn, [&] {
           if (tet)
             launch_tet_jacobi_basis(td, w, j, 0.5 * dt, batch, mixed, s);
           else
@@ -797,18 +861,19 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
         // Algorithmic bytes per active sample, each operand once: boxes z, v_j and the
         // element's field value theta read, w written (one element per node), v_0..v_{j-1}
         // read for the fused projections; tetrahedra z, d read, w written per vertex and theta
-        // once per tetrahedron.  The kernel's own bytes: boxes read the element coefficient
-        // pair (p, q) instead of theta; tetrahedra read the assembled stiffness values of
+        // once per tetrahedron.  The kernel's own bytes: FP64 and 2D boxes read the element
+        // coefficient pair (p, q) instead of theta; tetrahedra read the assembled stiffness values of
         // every slot of a row instead of theta, and the shared pattern (columns, mass) once
         // per launch.
         const double slots = tet ? (double)td.nell / (double)td.nv : 0.0;
         const double apply_bytes =
             tet ? ti * (3.0 * nn + (td.model == MLQ_DIFF_VECTOR ? 3.0 : 1.0) * (double)level->P)
                 : nn * ti * (4.0 + (fuse ? j : 0));
-        const double apply_kbytes = nn * ti * (tet ? slots + 3.0 : 5.0 + (fuse ? j : 0));
+        const double box_vals = (mixed && g.dim == 3 ? 4.0 : 5.0) + (fuse ? j : 0);  // mixed 3D: theta
+        const double apply_kbytes = nn * ti * (tet ? slots + 3.0 : box_vals);
         const double apply_fixed = tet ? (double)td.nell * (4.0 + ti) : 0.0;
-        timed(
-            level, MLQ_K_APPLY, nn, s,
+        tm(
+            MLQ_K_APPLY, nn,
             [&] {
               if (tet)  // the full Jacobian applied to z_j
                 launch_tet_apply(td, w.coef, (const char*)w.z + (size_t)j * level->nn * batch * (size_t)ti, w.d,
@@ -819,20 +884,46 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
                 launch_apply_pk(g, w, j, 0.5 * dt, batch, mixed, s);
             },
             apply_bytes, nin, apply_kbytes, apply_fixed);
-        if (!fuse) timed(level, MLQ_K_DOTS, nn, s, [&] { launch_dots(g, w, j, batch, mixed, s); }, 0.0, nin);
-        timed(level, MLQ_K_ORTH, nn, s,
-              [&] { launch_orth(g, w, j, batch, mixed, s, fuse ? w.nwav : w.nred); }, 0.0, nin);
-        timed(level, MLQ_K_SMALL, 0.0, s, [&] {
+        if (!fuse) tm(MLQ_K_DOTS, nn, [&] { launch_dots(g, w, j, batch, mixed, s); }, 0.0, nin);
+        tm(MLQ_K_ORTH, nn, [&] { launch_orth(g, w, j, batch, mixed, s, fuse ? w.nwav : w.nred); }, 0.0, nin);
+        tm(MLQ_K_SMALL, 0.0, [&] {
           launch_givens(g, w, j, batch, d.inner_tol, s, w.nred);  // counts into counter[1 + (j & 1)]
         });
-        // The count of iteration j is read while iteration j + 1 is already queued, so
-        // the GPU does not idle during the host round trip; an iteration queued after
-        // every sample has stopped finds no active sample and does nothing.
-        HIP_OK(hipMemcpyAsync(&cnt[j], w.counter + 1 + (j & 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_OK(hipEventRecord(level->flag_ev[j & 1], s));
-        if (j > 0) {
-          HIP_OK(hipEventSynchronize(level->flag_ev[(j - 1) & 1]));
-          if (cnt[j - 1] == 0) break;
+      };
+      const int J = level->gmres_block;
+      if (J <= 0) {
+        for (int j = 0; j < kmax; ++j) {
+          gmres_iteration(j, false, s);
+          // The count of iteration j is read while iteration j + 1 is already queued, so
+          // the GPU does not idle during the host round trip; an iteration queued after
+          // every sample has stopped finds no active sample and does nothing.
+          HIP_OK(hipMemcpyAsync(&cnt[j], w.counter + 1 + (j & 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+          HIP_OK(hipEventRecord(level->flag_ev[j & 1], s));
+          if (j > 0) {
+            HIP_OK(hipEventSynchronize(level->flag_ev[(j - 1) & 1]));
+            if (cnt[j - 1] == 0) break;
+          }
+        }
+      } else {
+        // Blocks of J iterations, each replayed from a graph captured once per (workspace,
+        // field, batch, block); one count read per block, one block behind the launches.
+        int prev = -1;
+        for (int j0 = 0, nb = 0; j0 < kmax; j0 += J, ++nb) {
+          const int jn = std::min(J, kmax - j0);
+          hipGraphExec_t ge = nullptr;
+          const mlq_status gs = block_graph(level, ws_dev, theta_dev, batch, j0, jn, s, &ge, [&](hipStream_t cs) {
+            for (int j = j0; j < j0 + jn; ++j) gmres_iteration(j, true, cs);
+          });
+          if (gs != MLQ_OK) return gs;
+          HIP_OK(hipGraphLaunch(ge, s));
+          const int jl = j0 + jn - 1;
+          HIP_OK(hipMemcpyAsync(&cnt[jl], w.counter + 1 + (jl & 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+          HIP_OK(hipEventRecord(level->flag_ev[nb & 1], s));
+          if (prev >= 0) {
+            HIP_OK(hipEventSynchronize(level->flag_ev[(nb - 1) & 1]));
+            if (cnt[prev] == 0) break;
+          }
+          prev = jl;
         }
       }
       timed(level, MLQ_K_UPDATE, nn * active, s, [&] {
@@ -921,6 +1012,15 @@ mlq_status mlq_set_lane_layout(mlq_level* level, int32_t lanes_x) {
   if (lanes_x != 0 && lanes_x != 8 && lanes_x != 16) return fail(MLQ_EINVAL, "lanes_x must be 0, 8 or 16");
   if (level->tet || level->geo.dim != 3) return fail(MLQ_EINVAL, "the lane layout applies to 3D box levels");
   level->geo.lx = lanes_x;
+  drop_graphs(level);
+  return MLQ_OK;
+}
+
+mlq_status mlq_set_gmres_block(mlq_level* level, int32_t iterations) {
+  if (level == nullptr) return fail(MLQ_EINVAL, "level is NULL");
+  if (iterations < 0 || iterations > kMaxInner) return fail(MLQ_EINVAL, "block of %d iterations", iterations);
+  if (iterations != level->gmres_block) drop_graphs(level);
+  level->gmres_block = iterations;
   return MLQ_OK;
 }
 

@@ -32,6 +32,10 @@ struct Geo {
   int32_t tet;         // 1: P1 tetrahedra (TetDev holds the mesh), 0: Q1 box
   int64_t nnz;         // tetrahedra: stored (padded, slot-major) entries of the vertex adjacency
   int32_t lx;          // 3D boxes: lanes along x of a wave (8 or 16), 0 = chosen by the grid width
+  // The field value behind (p, q), for kernels that form the coefficients from it: iso = 1: p =
+  // max(v, cfa), q = 0 (cfa the floor); iso = 0: p, q = cfa (cos 2t, sin 2t) (cfa = (s_l - s_t)/2).
+  int32_t iso;
+  double cfa;
 };
 
 // P1 tetrahedral level data on the device (inside the level blob).  The sparsity
@@ -97,6 +101,9 @@ struct Work {
   void* V;       // GMRES basis, (kmax + 1) vectors of [B][n]
   // per element coefficients [B][P][2] (inner precision)
   void* coef;
+  // the element field of the solve ([B][P], inner precision); mixed-precision 3D box kernels
+  // form the coefficients from it in registers instead of reading coef
+  const void* theta;
   // per-sample small arrays
   double* part;      // reduction partials (residual norms, Gram-Schmidt norms)
   double* dpart;     // Gram-Schmidt projection partials [B][kmax+1][nred]
@@ -219,6 +226,7 @@ int32_t stencil3_blocks(const Geo& g);
 // jb > 0: also accumulate the Gram-Schmidt projections w . v_i (i <= j < jb) into dpart,
 // one partial per workgroup (Work::nwav per sample)
 void launch_apply_pk3(const Geo& g, const Work& w, int j, double ck, int32_t B, bool mixed, hipStream_t s, int jb);
+// coef: the (p, q) pairs in FP64, or in mixed precision the element field itself
 void launch_apply_full3(const Geo& g, const void* coef, const void* x, const void* d, void* y, double ck, int32_t B,
                         bool mixed, hipStream_t s);
 void launch_residual3(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s);

@@ -107,7 +107,8 @@ struct Args {
   const T* vj;        // kPK: basis vector
   const double* inv_eta;
   int j, kmax;
-  const void* coef;   // [B][P][2], coefficient precision
+  const void* coef;   // CF = 0: [B][P][2] pairs (p, q), coefficient precision; else the field [B][P]
+  double cfa;         // CF > 0: (s_l - s_t)/2 for the fibre angle, the floor for the isotropic field
   T* y;               // kPK: w; kFull: y
   const double* u;   // kRes / kRhs input (FP64)
   const double* bvec; // kRes: b
@@ -147,14 +148,20 @@ struct Args {
 constexpr int kWideMinNx = 48;
 inline int wave_lx(const Geo& g) { return g.lx != 0 ? g.lx : (g.nx >= kWideMinNx ? 16 : 8); }
 constexpr int WZ = 11;  // owned node planes per wave (WZ + 1 steps)
+#ifndef MLQ_WAVE_PD_RES
+#define MLQ_WAVE_PD_RES 1
+#endif
+#ifndef MLQ_RES_WAVES
+#define MLQ_RES_WAVES 4
+#endif
 
 // steps between issuing a slab's loads and using them
-template <typename R>
+template <typename R, int MODE>
 constexpr int wave_prefetch() {
 #ifdef MLQ_WAVE_PD
   return MLQ_WAVE_PD;
 #else
-  return 2;
+  return (sizeof(R) == 8 && (MODE == kRes || MODE == kRhs)) ? MLQ_WAVE_PD_RES : 2;
 #endif
 }
 
@@ -163,8 +170,13 @@ __device__ inline R shdn(R v, int d) {
   return __shfl_down(v, d, 64);
 }
 
-template <typename R, typename TC, typename TI, int MODE, int JB, int LX>
-__global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
+// Element coefficients (CF): 0 = the pairs (p, q) read from memory; 1 = formed from the fibre
+// angle theta of the element, p, q = cfa (cos 2t, sin 2t) with the library's accurate FP32 sincos
+// (the same values the pair kernel k_coefs stores); 2 = the same with the hardware sine and cosine
+// (an approximation good to about 1e-6, used where only the Krylov operator needs it); 3 = the
+// isotropic field v, p = max(v, cfa), q = 0.  CF > 0 reads 4 bytes per element instead of 8.
+template <typename R, typename TC, typename TI, int MODE, int JB, int LX, int CF>
+__global__ __launch_bounds__(NT, (sizeof(R) == 8 && (MODE == kRes || MODE == kRhs)) ? MLQ_RES_WAVES : 1) void k_wave3(Args<R> A) {
   constexpr int LY = 64 / LX;
   constexpr int WTX = LX - 1, WTY = LY - 1;  // owned nodes per wave along x and y
   const Geo& g = A.g;
@@ -203,7 +215,8 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     const int zs = zc * WZ, ze = min(zs + WZ, g.nz);
     const int64_t plane = (int64_t)g.nx * g.ny;
     const int64_t sbase = (int64_t)sb * g.nn;
-    const TC* cf = (const TC*)A.coef + (int64_t)sb * g.P * 2;
+    constexpr int kCw = CF == 0 ? 2 : 1;  // stored values per element
+    const TC* cf = (const TC*)A.coef + (int64_t)sb * g.P * kCw;
     const int ex_n = g.nx - 1, ey_n = g.ny - 1;
     const bool elem_xy = ex >= 0 && ey >= 0 && ex < ex_n && ey < ey_n;
     const bool owner = i < WTX && j < WTY && ex + 1 < g.nx && ey + 1 < g.ny;
@@ -223,14 +236,14 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     const uint32_t lbd = (uint32_t)c00 * 8u;                      // same, FP64 node arrays
     const uint32_t ob = (uint32_t)oof * (uint32_t)sizeof(R);     // owned node, type R
     const uint32_t obd = (uint32_t)oof * 8u;                      // owned node, FP64
-    const uint32_t eb = (uint32_t)ce * 2u * (uint32_t)sizeof(TC); // element (p, q)
+    const uint32_t eb = (uint32_t)ce * (uint32_t)(kCw * sizeof(TC)); // element (p, q) or field value
     auto at = [](auto* base, uint32_t byte_off) { return *(decltype(base))((const char*)base + byte_off); };
     const int nxs = g.nx;
 
     // Per-sample base pointers (64-bit, uniform) are formed once; a plane is then a
     // 32-bit byte offset (kk * plane fits in 32 bits for every mesh the library accepts).
     const uint32_t pbR = (uint32_t)plane * (uint32_t)sizeof(R), pbD = (uint32_t)plane * 8u;
-    const uint32_t lbR = (uint32_t)layer * 2u * (uint32_t)sizeof(TC);
+    const uint32_t lbR = (uint32_t)layer * (uint32_t)(kCw * sizeof(TC));
     const R* xs = nullptr;
     const R* ds_ = nullptr;
     const double* us = nullptr;
@@ -244,14 +257,10 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
         const R v = (R)at(xs + dn, lb + po);
         vk = v;
         vm = v + (R)at(ds_ + dn, lb + po) * v;
-      } else if constexpr (MODE == kRes) {
-        const double v = at(us + dn, lbd + po);
-        vk = (R)v;
-        vm = (R)(v + A.io.dt * iion3(v, A.io));
       } else {
-        const double v = at(us + dn, lbd + po);
-        vk = (R)v;
-        vm = (R)v;
+        // kRes / kRhs: the mass input (u + dt I_ion(u), or u) is formed in step() from vk, so
+        // that the register ring of planes holds one value per corner
+        vk = (R)at(us + dn, lbd + po);
       }
     };
     struct Pl {
@@ -267,9 +276,10 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     };
     auto fetch_coef = [&](int k, R& p, R& q) {
       const uint32_t kk = (uint32_t)min(max(k, 0), g.nz - 2);
-      p = (R)at(cf, eb + kk * lbR);
-      q = (R)at(cf + 1, eb + kk * lbR);
+      p = (R)at(cf, eb + kk * lbR);  // CF > 0: the field value, converted in step()
+      q = CF == 0 ? (R)at(cf + 1, eb + kk * lbR) : (R)0;
     };
+    const float cfa32 = (float)A.cfa;
 
     const R* vjs = nullptr;
     const double* bs = nullptr;
@@ -302,6 +312,20 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     R acc_top = 0;
     auto step = [&](int k, const Pl& lo, const Pl& hi, R cp, R cq, R p0, R p1) {
       const bool slab = k >= 0 && k <= g.nz - 2;
+      if constexpr (CF == 1 || CF == 2) {
+        const float t2 = 2.0f * (float)cp;
+        float sv, cv;
+        if constexpr (CF == 1)
+          sincosf(t2, &sv, &cv);
+        else
+          __sincosf(t2, &sv, &cv);
+        cp = (R)(cfa32 * cv);
+        cq = (R)(cfa32 * sv);
+      } else if constexpr (CF == 3) {
+        const double v = (double)cp;
+        cp = (R)(TC)(v > A.cfa ? v : A.cfa);
+        cq = (R)0;
+      }
       R o[8];
       {
         const bool on = slab && elem_xy;
@@ -310,7 +334,18 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
         Elem<R>::stiff_f(xin, (CX0 + CX1 * cp) * (sc * KX), (CY0 + CY1 * cp) * (sc * KY), cq * (sc * KQ),
                          (CZ0 + CZ1 * cp) * (sc * KZ), o);
         if constexpr (kMass) {
-          R xm[8] = {lo.m[0], lo.m[1], lo.m[2], lo.m[3], hi.m[0], hi.m[1], hi.m[2], hi.m[3]};
+          R xm[8];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            if constexpr (MODE == kRes) {
+              const double v = (double)xin[c];
+              xm[c] = (R)(v + A.io.dt * iion3(v, A.io));
+            } else if constexpr (MODE == kRhs) {
+              xm[c] = xin[c];
+            } else {
+              xm[c] = c < 4 ? lo.m[c] : hi.m[c - 4];
+            }
+          }
           R om[8];
           Elem<R>::mass_f(xm, on ? (R)A.cm * KM : (R)0, om);
 #pragma unroll
@@ -372,7 +407,7 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     // s and s + 1, the coefficients and node inputs of s; the loads for step s + PD are
     // issued at step s.
     constexpr int NS = WZ + 1;
-    constexpr int PD = wave_prefetch<R>();
+    constexpr int PD = wave_prefetch<R, MODE>();
     const int k0 = zs - 1;
     Pl P[NS + 1];
     R Cp[NS], Cq[NS], Q0[NS], Q1[NS];
@@ -474,14 +509,34 @@ void wave_grid_of(const Geo& g, Args<R>& a, int32_t B, dim3& grid) {
   grid = dim3((unsigned)((int64_t)a.bps * B));
 }
 
-template <typename R, typename TC, typename TI, int MODE, int JB = 0>
-void launch_wave3(const Geo& g, Args<R>& a, int32_t B, hipStream_t s) {
+template <typename R, typename TC, typename TI, int MODE, int JB, int CF>
+void launch_wave3_cf(const Geo& g, Args<R>& a, int32_t B, hipStream_t s) {
   dim3 grid;
   wave_grid_of(g, a, B, grid);
   if (wave_lx(g) == 16)
-    hipLaunchKernelGGL((k_wave3<R, TC, TI, MODE, JB, 16>), grid, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_wave3<R, TC, TI, MODE, JB, 16, CF>), grid, dim3(NT), 0, s, a);
   else
-    hipLaunchKernelGGL((k_wave3<R, TC, TI, MODE, JB, 8>), grid, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_wave3<R, TC, TI, MODE, JB, 8, CF>), grid, dim3(NT), 0, s, a);
+}
+
+// FP64 (TC = double), and the FP64-arithmetic residual and right-hand side of mixed precision:
+// the pairs (p, q) of k_coefs (their FP64 stencils are bound by latency and registers, where the
+// accurate sine and cosine per element cost more than the 4 bytes they save).  Mixed precision
+// (TC = float) otherwise reads the field itself: the Krylov apply (kPK) with the hardware sine
+// and cosine, the public apply with the accurate ones (the values k_coefs stores).
+template <typename R, typename TC, typename TI, int MODE, int JB = 0>
+void launch_wave3(const Geo& g, Args<R>& a, int32_t B, hipStream_t s) {
+  if constexpr (sizeof(TC) == 8 || MODE == kRes || MODE == kRhs) {
+    launch_wave3_cf<R, TC, TI, MODE, JB, 0>(g, a, B, s);
+  } else {
+    a.cfa = g.cfa;
+    if (g.iso)
+      launch_wave3_cf<R, TC, TI, MODE, JB, 3>(g, a, B, s);
+    else if (MODE == kPK)
+      launch_wave3_cf<R, TC, TI, MODE, JB, 2>(g, a, B, s);
+    else
+      launch_wave3_cf<R, TC, TI, MODE, JB, 1>(g, a, B, s);
+  }
 }
 
 }  // namespace
@@ -496,7 +551,8 @@ void launch_apply_pk3(const Geo& g, const Work& w, int j, double ck, int32_t B, 
   auto fill = [&](auto& a) {
     using T = std::remove_const_t<std::remove_pointer_t<decltype(a.x)>>;
     a.g = g; a.x = (const T*)w.z + j * vs; a.vj = (const T*)w.V + j * vs; a.inv_eta = w.inv_eta;
-    a.j = j; a.kmax = w.kmax; a.coef = w.coef; a.y = (T*)w.w; a.ck = ck; a.cm = 0.0; a.active = w.inner_active;
+    a.j = j; a.kmax = w.kmax; a.coef = mixed ? w.theta : w.coef; a.y = (T*)w.w; a.ck = ck; a.cm = 0.0;
+    a.active = w.inner_active;
     a.V = (const T*)w.V; a.vs = vs; a.dpart = w.dpart;
   };
   if (mixed) {

@@ -17,7 +17,7 @@ import torch
 
 import workloads as W
 
-from . import mlq
+from . import mlq, tune
 
 EST_OF = {"mc": mlq.MLQ_EST_MC, "qmc": mlq.MLQ_EST_MLQMC, "mlmc": mlq.MLQ_EST_MLMC, "mlqmc": mlq.MLQ_EST_MLQMC}
 
@@ -27,7 +27,7 @@ class ConfigRunner:
 
     def __init__(self, cfg: dict, prec: int | None = None, device="cuda", newton_tol=None, inner_tol=None,
                  max_inner=30, kl_rank_factor=2, kl_eps=1e-2, log=None, concurrent=True,
-                 newton_guess=mlq.MLQ_GUESS_EXTRAPOLATE, tune_layout=True):
+                 newton_guess=mlq.MLQ_GUESS_EXTRAPOLATE, tune_layout=True, tune_launch=True):
         say = log if log is not None else (lambda m: None)
         self.cfg = cfg
         self.device = device
@@ -109,7 +109,17 @@ class ConfigRunner:
                            else mlq.MLQ_DIFF_FIBRE), v_mean=v_mean)
             L = mlq.Level(desc, keep, device=device)
             L._keep = None  # arrays were copied into the level blob
-            if tune_layout and not self.tet and cfg["dim"] == 3:
+            L.chunk = nb
+            if tune_launch:
+                # launch configuration (lane layout, GMRES graph blocks, batch chunk) from short
+                # trial solves of seeded samples; the finest level's launches are large and keep
+                # one launch per GMRES iteration (their apply is the kernel timed per launch)
+                draw = W.mc_uniforms if self.uniform else W.mc_normals
+                Yt = torch.as_tensor(draw(987654, l, nb, M * self.components), device=device)
+                th = self._fields(L, Yt)
+                L.tuning = tune.tune(L, th, graphs=l < top, log=say)
+                del th, Yt
+            elif tune_layout and not self.tet and cfg["dim"] == 3:
                 # the faster lane layout of the 3D kernels for this grid and batch, by timing
                 t = L.tune_lane_layout()
                 say(f"level {l}: lane layout {L.lanes_x} (apply ms: 8 lanes {t[8]:.3f}, 16 lanes {t[16]:.3f})")
@@ -151,23 +161,32 @@ class ConfigRunner:
         self.level_inner = [0.0] * n        # GMRES iterations
         self.level_sample_steps = [0.0] * n
 
-    def solve(self, l: int, Y: torch.Tensor, fields=None):
-        """QoIs (device FP64) of the samples Y (M x B, device FP64) on level l; with `fields`
-        (keyword arguments of Level.solve_fields) the field outputs are streamed as well."""
-        L = self.levels[l]
-        t0 = time.perf_counter()
+    def _fields(self, L, Y):
+        """KL synthesis of the samples Y on level L: (B, P), or (components, B, P) for the vector model."""
         if self.vector:  # Y stacks the coordinates of the components: (components x M, B)
             M = self.kd.n_modes
-            theta = torch.stack([L.sample_fields(Y[c * M:(c + 1) * M].contiguous())
-                                 for c in range(self.components)])
-        else:
-            theta = L.sample_fields(Y)
-        out = L.solve(theta) if fields is None else L.solve_fields(theta, per_sample_probes=False, **fields)
-        if out["code"] != mlq.MLQ_OK:
-            st = out["status"].cpu().numpy()
-            raise mlq.MlqError(out["code"], f"{int((st != 0).sum())} samples failed on level {l}")
-        it = out["iters"]
+            return torch.stack([L.sample_fields(Y[c * M:(c + 1) * M].contiguous()) for c in range(self.components)])
+        return L.sample_fields(Y)
+
+    def solve(self, l: int, Y: torch.Tensor, fields=None):
+        """QoIs (device FP64) of the samples Y (M x B, device FP64) on level l; with `fields`
+        (keyword arguments of Level.solve_fields) the field outputs are streamed as well.  A level
+        tuned to a smaller batch chunk solves the samples in consecutive chunks."""
+        L = self.levels[l]
+        t0 = time.perf_counter()
         B = Y.shape[1]
+        c = getattr(L, "chunk", B) if fields is None else B
+        outs = []
+        for i in range(0, B, c):
+            theta = self._fields(L, Y[:, i:i + c] if c < B else Y)
+            out = L.solve(theta) if fields is None else L.solve_fields(theta, per_sample_probes=False, **fields)
+            if out["code"] != mlq.MLQ_OK:
+                st = out["status"].cpu().numpy()
+                raise mlq.MlqError(out["code"], f"{int((st != 0).sum())} samples failed on level {l}")
+            outs.append(out)
+        if len(outs) > 1:
+            out = dict(qoi=torch.cat([o["qoi"] for o in outs]), iters=torch.cat([o["iters"] for o in outs]))
+        it = out["iters"]
         sums = it.sum(dim=0).cpu()  # waits for the solve on this stream
         newton, inner = float(sums[0]), float(sums[1])
         el = time.perf_counter() - t0

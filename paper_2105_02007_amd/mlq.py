@@ -29,7 +29,7 @@ EXPORTED = [
     "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet", "mlq_solve_batch_fields", "mlq_probe_weights",
     "mlq_transfer_add", "mlq_field_norm2", "mlq_set_reference", "mlq_tet_locate", "mlq_transfer_add_weighted",
     "mlq_set_lane_layout", "mlq_lattice_points", "mlq_solve_batch_static",
-    "mlq_kl_weights", "mlq_lattice_weights", "mlq_fibre_field",
+    "mlq_kl_weights", "mlq_lattice_weights", "mlq_fibre_field", "mlq_set_gmres_block",
 ]
 STATIC_WS_BYTES = 64 << 20
 MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE, MLQ_GUESS_REFERENCE, MLQ_GUESS_REFERENCE_LOCAL = 0, 1, 2, 3
@@ -114,6 +114,7 @@ def _load():
         "mlq_field_norm2": [VP, I32, I32, I64, VP, VP, VP, VP],
         "mlq_set_reference": [VP, VP],
         "mlq_set_lane_layout": [VP, I32],
+        "mlq_set_gmres_block": [VP, I32],
         "mlq_lattice_points": [VP, VP, I32, I64, I64, I32, I32, VP, VP],
         "mlq_tet_locate": [VP, I64, VP, I64, VP, I64, VP, VP],
         "mlq_transfer_add_weighted": [VP, VP, I32, I64, I32, VP, VP, C.c_double, VP, VP, VP],
@@ -360,6 +361,11 @@ class Level:
         """Lanes along x of the 3D box kernels' waves: 8, 16, or 0 (by grid width)."""
         check(lib.mlq_set_lane_layout(self.handle, int(lanes_x)))
         self.lanes_x = int(lanes_x)
+
+    def set_gmres_block(self, iterations):
+        """GMRES iterations per captured graph (0: one launch sequence and host read per iteration)."""
+        check(lib.mlq_set_gmres_block(self.handle, int(iterations)))
+        self.gmres_block = int(iterations)
 
     def tune_lane_layout(self, batch=None, reps=5, margin=0.05):
         """Times the operator apply of this level at `batch` samples (default: the level's
