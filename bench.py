@@ -301,13 +301,19 @@ def roofline_of(cfg, runner, config_name, prec, per_level):
 
 def level_stats(runner, steps):
     """Per level: its solves' DOF x iterations over their host wall time (the coarser levels run
-    concurrently, so their rates are while sharing the GPU), Newton and GMRES iterations per step."""
-    return [dict(level=l, dof_iters_per_s=(runner.level_dof_iters[l] / runner.level_seconds[l]
-                                           if runner.level_seconds[l] > 0 else None),
-                 seconds=round(runner.level_seconds[l] / max(steps, 1), 4),
-                 newton_per_step=round(runner.level_newton[l] / max(runner.level_sample_steps[l], 1.0), 3),
-                 gmres_per_step=round(runner.level_inner[l] / max(runner.level_sample_steps[l], 1.0), 2))
-            for l in range(len(runner.levels))]
+    concurrently, so their rates are while sharing the GPU), Newton and GMRES iterations per step
+    (per time block in the all-at-once mode)."""
+    out = []
+    for l, L in enumerate(runner.levels):
+        mb = min(runner.steps_per_block, int(L.desc.n_steps)) if runner.steps_per_block else 1
+        units = max(runner.level_sample_steps[l] / mb, 1.0)
+        out.append(dict(level=l, dof_iters_per_s=(runner.level_dof_iters[l] / runner.level_seconds[l]
+                                                  if runner.level_seconds[l] > 0 else None),
+                        seconds=round(runner.level_seconds[l] / max(steps, 1), 4),
+                        **{("newton_per_block" if mb > 1 else "newton_per_step"):
+                           round(runner.level_newton[l] / units, 3),
+                           ("gmres_per_block" if mb > 1 else "gmres_per_step"): round(runner.level_inner[l] / units, 2)}))
+    return out
 
 
 def compare_runs(cfg, a, b):
@@ -356,6 +362,11 @@ def main():
     ap.add_argument("--fields", action="store_true",
                     help="MLMC workloads: also estimate the field quantities of interest (mean space-time "
                          "potential on the finest grid, mean activation map, mean action potential at 4 points)")
+    ap.add_argument("--steps-per-block", type=int, default=0,
+                    help="all-at-once solves in time blocks of this many steps (0: time stepping)")
+    ap.add_argument("--block-guess", choices=["previous", "reference", "reference-local"], default="previous",
+                    help="Newton start of a time block: the previous block's final state (multiple time blocks), "
+                         "the reference solution (global) or its increment (local)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch autotuner (lane layout by grid width, one GMRES launch sequence per "
                          "iteration, whole batches)")
@@ -389,8 +400,13 @@ def main():
     guess = {"previous": mlq.MLQ_GUESS_PREVIOUS, "extrapolate": mlq.MLQ_GUESS_EXTRAPOLATE,
              "reference": mlq.MLQ_GUESS_REFERENCE, "reference-local": mlq.MLQ_GUESS_REFERENCE_LOCAL}[args.newton_guess]
     t_setup = time.perf_counter()
+    bguess = {"previous": mlq.MLQ_GUESS_PREVIOUS, "reference": mlq.MLQ_GUESS_REFERENCE,
+              "reference-local": mlq.MLQ_GUESS_REFERENCE_LOCAL}[args.block_guess]
+    if args.steps_per_block > 0:
+        args.no_tune = True
+        args.companion_steps = 0
     runner = ConfigRunner(cfg, prec=prec, device=dev, log=log, newton_guess=guess, inner_tol=args.inner_tol,
-                          tune_launch=not args.no_tune)
+                          tune_launch=not args.no_tune, steps_per_block=args.steps_per_block, block_guess=bguess)
     t_setup = time.perf_counter() - t_setup
     log(f"set-up done in {t_setup:.1f} s (KL rank {runner.kl_rank})")
     runner.log = log
@@ -475,6 +491,8 @@ def main():
         "apply_per_level": per_level,
         "levels": levels,
         "newton_guess": args.newton_guess,
+        "time_blocks": ({"steps_per_block": args.steps_per_block, "block_guess": args.block_guess}
+                        if args.steps_per_block > 0 else None),
         "lanes_x": [getattr(L, "lanes_x", None) for L in runner.levels],
         "inner_tol": runner.levels[-1].desc.inner_tol,
     }

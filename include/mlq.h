@@ -200,6 +200,34 @@ mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t b
                               int64_t* iters_dev, double* u_out_dev, double* act_out_dev,
                               void* hip_stream);
 
+/* All-at-once solve in time blocks (Section 3.3, the multiple-time-blocks strategy; eq. (system_C)
+ * with the reaction term of eq. (mono_disc)), 3D box levels: [0, T] is cut into K = n_steps /
+ * steps_per_block blocks of m' = steps_per_block steps, solved one after the other, each by Newton's
+ * method on all m' unknown time levels at once (the block's first level couples to the previous
+ * block's final state), every Newton system by GMRES on the whole block with the block-Jacobi
+ * preconditioner (per time level M (I + D), as in the time-stepping solve).  m' = n_steps is the
+ * direct method over the whole interval.  Newton's first iterate of a block, `guess`:
+ *   MLQ_GUESS_PREVIOUS          the previous block's final state at every time level (the
+ *                               multiple-time-blocks start);
+ *   MLQ_GUESS_REFERENCE         the reference solution r (mlq_set_reference) at the block's time
+ *                               levels (the global sample-based guess);
+ *   MLQ_GUESS_REFERENCE_LOCAL   the previous block's final state plus the reference's increment
+ *                               since the block's start (the local sample-based guess).
+ * The discrete solution is the time-stepping one (the block system is block lower triangular), so
+ * qoi_dev, status_dev and iters_dev mean what they mean for mlq_solve_batch; iters_dev[2 b] counts
+ * block Newton iterations, iters_dev[2 b + 1] block GMRES iterations (each applies the operator to
+ * m' time levels).  u_out_dev (may be NULL): the final state, batch x n.  The level's max_inner
+ * bounds the GMRES iterations per Newton step (the block-Jacobi-preconditioned block operator needs
+ * about m' more than one step does).  ws_dev >= mlq_workspace_bytes_blocks, 256-byte aligned.
+ * MLQ_EINVAL unless steps_per_block divides n_steps, the level is a 3D box and batch (m' + 1) <=
+ * 65535; MLQ_ESTATE for a reference guess without a reference.  Returns after the stream has
+ * finished. */
+mlq_status mlq_workspace_bytes_blocks(const mlq_level* level, int32_t batch, int32_t steps_per_block,
+                                      size_t* ws_bytes);
+mlq_status mlq_solve_batch_blocks(mlq_level* level, const void* theta_dev, int32_t batch, int32_t steps_per_block,
+                                  int32_t guess, void* ws_dev, size_t ws_bytes, double* qoi_dev, int32_t* status_dev,
+                                  int64_t* iters_dev, double* u_out_dev, void* hip_stream);
+
 /* Field quantities of interest (Section 2.4: the transmembrane potential u itself, the
  * activation map, the action potential u(x0, t) at a point), streamed while a batch is
  * solved.  Each output pointer may be NULL (that output is skipped).  Device arrays, FP64:

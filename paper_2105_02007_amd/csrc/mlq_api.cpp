@@ -300,13 +300,13 @@ void sizes_of(const mlq_level_desc* d, int64_t* nn, int64_t* P) {
 
 namespace mlq {
 
-Work carve_workspace(void* base, const Geo& geo, int32_t B, int kmax, bool mixed) {
+Work carve_workspace(void* base, const Geo& geo, int32_t B, int kmax, bool mixed, int res_groups) {
   Work w{};
   const int64_t nn = geo.nn, P = geo.P;
   w.kmax = kmax;
   w.nblk = (int32_t)cdiv(nn, kBlock);
   w.nred = (int32_t)cdiv(nn, kRedChunk);
-  w.nres = (geo.dim == 3 && !geo.tet) ? stencil3_blocks(geo) : w.nblk;
+  w.nres = (geo.dim == 3 && !geo.tet) ? res_groups * stencil3_blocks(geo) : w.nblk;
   w.nwav = (geo.dim == 3 && !geo.tet) ? stencil3_blocks(geo) : 0;
   const size_t ti = mixed ? sizeof(float) : sizeof(double);
   const size_t vn = (size_t)nn * B;
@@ -459,6 +459,7 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
   g.tet = tet ? 1 : 0;
   g.nnz = tet ? th.nell : 0;
   g.lx = 0;
+  g.group = 0;
   if (tet) g.nx = g.ny = g.nz = 0;
   lv->io = Ionic{desc->alpha, desc->u_rest, desc->u_th, desc->u_peak, desc->t_end / desc->n_steps};
 
@@ -963,6 +964,143 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
   const int32_t bad = level->host_flags[2];
   if (bad) return fail(MLQ_ENOCONV, "%d of %d samples did not converge", bad, batch);
   return MLQ_OK;
+}
+
+// Geometry of the all-at-once block solve: the stencil view (every time level of a block a
+// virtual sample) and the vector view (a sample's block of m' + 1 time levels one vector).
+static mlq_status block_geos(const mlq_level* level, int32_t batch, int32_t mb, Geo* gs, Geo* gv) {
+  if (level->tet || level->geo.dim != 3) return fail(MLQ_EINVAL, "time blocks are solved on 3D box levels");
+  if (mb < 1 || level->d.n_steps % mb != 0)
+    return fail(MLQ_EINVAL, "steps per block %d must divide the %d steps", mb, level->d.n_steps);
+  if (batch < 1 || batch > level->d.max_batch) return fail(MLQ_EINVAL, "batch %d outside [1, max_batch]", batch);
+  if ((int64_t)batch * (mb + 1) > 65535) return fail(MLQ_EINVAL, "batch x (steps per block + 1) exceeds 65535");
+  if ((int64_t)(mb + 1) * level->nn > (int64_t(1) << 29)) return fail(MLQ_EINVAL, "time block too large");
+  *gs = level->geo;
+  gs->group = mb + 1;
+  *gv = level->geo;
+  gv->nn = (int64_t)(mb + 1) * level->nn;
+  gv->group = 0;
+  return MLQ_OK;
+}
+
+// All-at-once solve of the space-time system in time blocks of mb steps (Section 3.3, multiple
+// time blocks; eq. (system_C) with the reaction term of eq. (mono_disc)): per block, Newton's method
+// on all its time levels at once, each linear system by GMRES on the block with the block-Jacobi
+// preconditioner (per time level M (I + D_q), the preconditioner of the time-stepping solve).
+static mlq_status solve_blocks_impl(mlq_level* level, const void* theta_dev, int32_t batch, int32_t mb, int32_t guess,
+                                    void* ws_dev, size_t ws_bytes, double* qoi_dev, int32_t* status_dev,
+                                    int64_t* iters_dev, double* u_out_dev, void* hip_stream) {
+  if (level == nullptr || theta_dev == nullptr || ws_dev == nullptr || qoi_dev == nullptr || status_dev == nullptr ||
+      iters_dev == nullptr)
+    return fail(MLQ_EINVAL, "NULL argument");
+  if (guess != MLQ_GUESS_PREVIOUS && guess != MLQ_GUESS_REFERENCE && guess != MLQ_GUESS_REFERENCE_LOCAL)
+    return fail(MLQ_EINVAL, "block guess %d: previous block, reference or local reference", guess);
+  if (guess != MLQ_GUESS_PREVIOUS && level->ref == nullptr)
+    return fail(MLQ_ESTATE, "the reference guesses need mlq_set_reference");
+  if (((uintptr_t)ws_dev & 255) != 0) return fail(MLQ_EINVAL, "workspace must be 256-byte aligned");
+  Geo gs, gv;
+  {
+    const mlq_status st = block_geos(level, batch, mb, &gs, &gv);
+    if (st != MLQ_OK) return st;
+  }
+  const int kmax = level->kmax;
+  const bool mixed = level->mixed;
+  const int G = mb + 1;
+  // residual partials of a sample: the workgroups of its G time levels
+  Work w = carve_workspace(ws_dev, gv, batch, kmax, mixed, G);
+  if (ws_bytes < w.bytes) return fail(MLQ_ESIZE, "workspace too small: %zu < %zu", ws_bytes, w.bytes);
+  const int32_t Bv = batch * G;
+  w.theta = theta_dev;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const mlq_level_desc& d = level->d;
+  const double dt = level->io.dt;
+  const int64_t n = level->nn;
+  const size_t ti = mixed ? sizeof(float) : sizeof(double);
+  const size_t vn = (size_t)gv.nn * batch;
+  launch_coefs(theta_dev, w.coef, level->P, batch,
+               d.diffusion == MLQ_DIFF_ISO ? d.sigma_t : 0.5 * (d.sigma_l - d.sigma_t), d.diffusion == MLQ_DIFF_ISO,
+               mixed, s);
+  // the unused slot 0 of every Krylov vector stays zero, so the block vectors' dot products,
+  // norms and updates see only the unknown time levels
+  HIP_OK(hipMemsetAsync(w.u, 0, sizeof(double) * vn, s));
+  HIP_OK(hipMemsetAsync(w.V, 0, ti * vn * (kmax + 1), s));
+  HIP_OK(hipMemsetAsync(w.z, 0, ti * vn * kmax, s));
+  HIP_OK(hipMemsetAsync(w.w, 0, ti * vn, s));
+  HIP_OK(hipMemsetAsync(w.d, 0, ti * vn, s));
+  launch_init(w, n, batch, d.u_th, s);  // activation flags of the [B][n] map, status, counters
+  HIP_OK(hipGetLastError());
+  const int gmode = guess == MLQ_GUESS_PREVIOUS ? 0 : guess == MLQ_GUESS_REFERENCE ? 1 : 2;
+  int32_t* const cnt = level->host_flags + kFlagInner;
+  for (int k0 = 0; k0 < d.n_steps; k0 += mb) {
+    launch_block_guess(w.u, G, n, batch, level->ref, k0, gmode, s);
+    launch_newton_reset(w, batch, s);
+    for (int it = 0;; ++it) {
+      launch_rhs3_block(gs, w.u, w.b, w.coef, level->fbox, k0, dt, d.stim_t_on, d.stim_t_off, d.stim_amp, Bv, mixed,
+                        s);
+      launch_residual3(gs, level->io, w, Bv, mixed, s);
+      launch_newton_check(gv, w, batch, d.newton_tol, s);
+      launch_count(w.newton_active, batch, w.counter, w.counter + 1, s);
+      int32_t active = 0;
+      const mlq_status st = read_counter(level, w, s, &active);
+      if (st != MLQ_OK) return st;
+      if (active == 0) break;
+      if (it >= d.max_newton) {
+        launch_mark_failed(w, batch, s);
+        break;
+      }
+      for (int j = 0; j < kmax; ++j) {
+        launch_minv_basis(gs, w, level->tri, level->nmax, j, Bv, mixed, s);
+        launch_apply_pk3(gs, w, j, 0.5 * dt, Bv, mixed, s, 0);
+        launch_coupling3(gs, (const char*)w.z + (size_t)j * vn * ti, w.w, mixed ? theta_dev : w.coef, 0.5 * dt, Bv,
+                         w.inner_active, mixed, s);
+        launch_dots(gv, w, j, batch, mixed, s);
+        launch_orth(gv, w, j, batch, mixed, s, w.nred);
+        launch_givens(gv, w, j, batch, d.inner_tol, s, w.nred);
+        HIP_OK(hipMemcpyAsync(&cnt[j], w.counter + 1 + (j & 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipEventRecord(level->flag_ev[j & 1], s));
+        if (j > 0) {
+          HIP_OK(hipEventSynchronize(level->flag_ev[(j - 1) & 1]));
+          if (cnt[j - 1] == 0) break;
+        }
+      }
+      launch_solve_y(w, batch, false, s);
+      launch_update_zbasis(gv, w, batch, mixed, s);
+    }
+    launch_block_close(w.u, G, n, batch, w.act, d.u_th, k0, dt, s);
+  }
+  // the final state (slot 0 after the last block) for the quantities of interest
+  HIP_OK(hipMemcpy2DAsync(w.uk, sizeof(double) * n, w.u, sizeof(double) * n * G, sizeof(double) * n, batch,
+                          hipMemcpyDeviceToDevice, s));
+  launch_qoi(w, level->wts, n, batch, d.qoi, (double)d.n_steps * dt, level->vol, qoi_dev, s);
+  HIP_OK(hipMemcpyAsync(status_dev, w.status, sizeof(int32_t) * batch, hipMemcpyDeviceToDevice, s));
+  HIP_OK(hipMemcpyAsync(iters_dev, w.iters, sizeof(int64_t) * 2 * batch, hipMemcpyDeviceToDevice, s));
+  if (u_out_dev)
+    HIP_OK(hipMemcpyAsync(u_out_dev, w.uk, sizeof(double) * n * batch, hipMemcpyDeviceToDevice, s));
+  launch_count(w.status, batch, w.counter + 3, nullptr, s);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipMemcpyAsync(level->host_flags + 2, w.counter + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  harvest(level);
+  const int32_t bad = level->host_flags[2];
+  if (bad) return fail(MLQ_ENOCONV, "%d of %d samples did not converge", bad, batch);
+  return MLQ_OK;
+}
+
+mlq_status mlq_workspace_bytes_blocks(const mlq_level* level, int32_t batch, int32_t steps_per_block,
+                                      size_t* ws_bytes) {
+  if (level == nullptr || ws_bytes == nullptr) return fail(MLQ_EINVAL, "NULL argument");
+  Geo gs, gv;
+  const mlq_status st = block_geos(level, batch, steps_per_block, &gs, &gv);
+  if (st != MLQ_OK) return st;
+  *ws_bytes = carve_workspace(nullptr, gv, batch, level->kmax, level->mixed, steps_per_block + 1).bytes;
+  return MLQ_OK;
+}
+
+mlq_status mlq_solve_batch_blocks(mlq_level* level, const void* theta_dev, int32_t batch, int32_t steps_per_block,
+                                  int32_t guess, void* ws_dev, size_t ws_bytes, double* qoi_dev, int32_t* status_dev,
+                                  int64_t* iters_dev, double* u_out_dev, void* hip_stream) {
+  return solve_blocks_impl(level, theta_dev, batch, steps_per_block, guess, ws_dev, ws_bytes, qoi_dev, status_dev,
+                           iters_dev, u_out_dev, hip_stream);
 }
 
 mlq_status mlq_solve_batch_ex(mlq_level* level, const void* theta_dev, int32_t batch, int32_t n_steps, void* ws_dev,

@@ -36,6 +36,11 @@ struct Geo {
   // max(v, cfa), q = 0 (cfa the floor); iso = 0: p, q = cfa (cos 2t, sin 2t) (cfa = (s_l - s_t)/2).
   int32_t iso;
   double cfa;
+  // All-at-once time blocks (3D boxes): the stencil kernels see every time level of a block as a
+  // virtual sample, group = time levels per block + 1 consecutive virtual samples per sample (slot
+  // 0 holds the block's initial state and is skipped); 0 or 1 = ordinary solves.  Per-sample data
+  // (coefficients, flags, Krylov scalars) is indexed by virtual sample / group.
+  int32_t group;
 };
 
 // P1 tetrahedral level data on the device (inside the level blob).  The sparsity
@@ -129,8 +134,9 @@ struct Work {
   size_t bytes;
 };
 
-// Carves the workspace for a batch.  With base == nullptr only computes bytes.
-Work carve_workspace(void* base, const Geo& g, int32_t batch, int kmax, bool mixed);
+// Carves the workspace for a batch.  With base == nullptr only computes bytes.  res_groups: the
+// residual kernel's workgroups per sample are res_groups times those of g (time blocks).
+Work carve_workspace(void* base, const Geo& g, int32_t batch, int kmax, bool mixed, int res_groups = 1);
 
 // ---- kernel launchers (mlq_kernels.hip) --------------------------------------
 void launch_coefs(const void* theta, void* coef, int64_t P, int32_t B, double half_dsig, bool iso, bool mixed,
@@ -239,6 +245,19 @@ void launch_rhs3(const Geo& g, const Work& w, const double* fbox, double load_co
 void launch_activation_between(const double* uold, const double* unew, double* act, int64_t nn, int32_t B,
                                double u_th, double t_k, double dt, hipStream_t s);
 void launch_cast_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+// All-at-once time blocks (g.group > 1, virtual samples as above).  Right-hand sides of every
+// time level of the block from the level before it, b_q = (M - dt/2 K) U_(q-1) + load(k0 + q) F,
+// with the stimulus rate of [t_on, t_off) at the time nodes (the step's trapezoid); U and b
+// [B][group][n].
+void launch_rhs3_block(const Geo& g, const double* U, double* b, const void* coef, const double* fbox, int k0,
+                       double dt, double t_on, double t_off, double amp, int32_t Bv, bool mixed, hipStream_t s);
+// w += (-M + dt/2 K) x_(q-1) for every time level q >= 1 of a block (the sub-diagonal block of
+// eq. (system_C)), x and w [B][group][n] in the inner precision; inactive samples skipped.
+void launch_block_guess(double* U, int G, int64_t nn, int32_t B, const double* ref, int k0, int mode, hipStream_t s);
+void launch_block_close(double* U, int G, int64_t nn, int32_t B, double* act, double u_th, int k0, double dt,
+                        hipStream_t s);
+void launch_coupling3(const Geo& g, const void* x, void* wv, const void* coef_or_theta, double ck, int32_t Bv,
+                      const int32_t* active, bool mixed, hipStream_t s);
 
 // P1 tetrahedra (mlq_tet.hip).  kval: per-sample stiffness values [B][nell] (slot-major
 // padded pattern of TetDev), inner precision.

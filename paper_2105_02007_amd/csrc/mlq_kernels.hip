@@ -712,6 +712,56 @@ void launch_activation_between(const double* uold, const double* unew, double* a
                      u_th, t_k, dt);
 }
 
+// All-at-once time blocks: U is [B][G][n] with slot 0 the block's initial state and slots 1 .. G - 1
+// its unknown time levels.  Newton's first iterate of every slot q >= 1 (Section 3.3): mode 0 the
+// initial state itself (the multiple-time-blocks start), 1 the reference solution r_(k0 + q) (global
+// guess), 2 the initial state plus the reference's increment r_(k0 + q) - r_k0 (local guess).
+__global__ void k_block_guess(double* __restrict__ U, int G, int64_t nn, int32_t B, const double* __restrict__ ref,
+                              int k0, int mode) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn * B) return;
+  const int64_t b = i / nn, x = i - b * nn;
+  double* Ub = U + b * G * nn;
+  const double u0 = Ub[x];
+  for (int q = 1; q < G; ++q) {
+    double v = u0;
+    if (mode == 1) v = ref[(int64_t)(k0 + q) * nn + x];
+    if (mode == 2) v = u0 + (ref[(int64_t)(k0 + q) * nn + x] - ref[(int64_t)k0 * nn + x]);
+    Ub[(int64_t)q * nn + x] = v;
+  }
+}
+
+void launch_block_guess(double* U, int G, int64_t nn, int32_t B, const double* ref, int k0, int mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_block_guess, dim3((unsigned)cdiv(nn * B, kBlock)), dim3(kBlock), 0, s, U, G, nn, B, ref, k0,
+                     mode);
+}
+
+// After a block: activation times of its steps (first crossing of u_th, linear in time between
+// the time nodes t_(k0 + q - 1) and t_(k0 + q)), then slot 0 := the last slot (the next block's
+// initial state).
+__global__ void k_block_close(double* __restrict__ U, int G, int64_t nn, int32_t B, double* __restrict__ act,
+                              double u_th, int k0, double dt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn * B) return;
+  const int64_t b = i / nn, x = i - b * nn;
+  double* Ub = U + b * G * nn;
+  double a = act[i];
+  double prev = Ub[x];
+  for (int q = 1; q < G; ++q) {
+    const double cur = Ub[(int64_t)q * nn + x];
+    if (a < 0.0 && prev < u_th && cur >= u_th) a = (double)(k0 + q - 1) * dt + dt * (u_th - prev) / (cur - prev);
+    prev = cur;
+  }
+  act[i] = a;
+  Ub[x] = prev;
+}
+
+void launch_block_close(double* U, int G, int64_t nn, int32_t B, double* act, double u_th, int k0, double dt,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_block_close, dim3((unsigned)cdiv(nn * B, kBlock)), dim3(kBlock), 0, s, U, G, nn, B, act, u_th,
+                     k0, dt);
+}
+
 // QoI: (1/|D|) sum_i w_i v_i with v = u (final) or the censored activation time.
 __global__ __launch_bounds__(kBlock) void k_qoi(const double* __restrict__ u, const double* __restrict__ act,
                                                 const double* __restrict__ wts, int64_t nn, int qoi, double t_stop,
@@ -1096,12 +1146,14 @@ __global__ __launch_bounds__(kBlock) void k_line_z(Geo g, const T* __restrict__ 
                                                    const double* __restrict__ inv_eta, int j, int kmax, double c6,
                                                    const T* __restrict__ iv, const int32_t* __restrict__ active) {
   const int sb = blockIdx.y;
-  if (active[sb] == 0) return;
+  // time blocks (g.group > 1): sb is a virtual sample of sample sr, slot 0 the block's initial state
+  const int grp = g.group > 1 ? g.group : 1, sr = sb / grp;
+  if ((grp > 1 && sb == sr * grp) || active[sr] == 0) return;
   const int L = blockIdx.x * kBlock + threadIdx.x;
   if (L >= g.nx * g.ny) return;
   const int64_t stride = (int64_t)g.nx * g.ny;
   const int64_t base = (int64_t)sb * g.nn + L;
-  const T s = (T)minv_scale(inv_eta, sb, j, kmax, c6);
+  const T s = (T)minv_scale(inv_eta, sr, j, kmax, c6);
   if constexpr (N > 0) {
     T v[N];
 #pragma unroll
@@ -1138,11 +1190,12 @@ __global__ __launch_bounds__(kBlock) void k_plane_xy(Geo g, const T* __restrict_
   extern __shared__ unsigned char smem_raw[];
   T* sh = reinterpret_cast<T*>(smem_raw);
   const int sb = blockIdx.y;
-  if (active[sb] == 0) return;
+  const int grp = g.group > 1 ? g.group : 1, sr = sb / grp;
+  if ((grp > 1 && sb == sr * grp) || active[sr] == 0) return;
   const int nx = N > 0 ? N : g.nx, ny = N > 0 ? N : g.ny;
   const int np = nx * ny;
   const int64_t base = (int64_t)sb * g.nn + (int64_t)blockIdx.x * np;
-  const T s = (T)minv_scale(inv_eta, sb, j, kmax, c6);
+  const T s = (T)minv_scale(inv_eta, sr, j, kmax, c6);
   const int t0 = threadIdx.x;
   // entries t0 + q kBlock of the plane, in batches of PB whose loads are all issued first
   constexpr int PB = (N > 0 && N * N <= 24 * kBlock) ? (N * N + kBlock - 1) / kBlock : 16;

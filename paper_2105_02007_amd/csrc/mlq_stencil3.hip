@@ -37,7 +37,7 @@ namespace {
 
 constexpr int NT = 256;           // threads per workgroup (four independent waves)
 
-enum { kPK = 0, kFull = 1, kRes = 2, kRhs = 3 };
+enum { kPK = 0, kFull = 1, kRes = 2, kRhs = 3, kCoup = 4 };
 
 template <typename R>
 struct Elem {
@@ -127,6 +127,10 @@ struct Args {
   double* part;       // kRes: partial norms
   double ck, cm;
   const int32_t* active;
+  // kRhs in a time block (g.group > 1): the load of time level q is dt/2 (rate(t_(k0+q)) +
+  // rate(t_(k0+q-1))), rate = amp on [t_on, t_off)
+  int k0;
+  double t_on, t_off, amp, dt_load;
   int tiles_x, tiles_y, zchunks;
   int bps;            // workgroups per sample
   // kPK with fused projections: partials of w . v_i (i <= j) per wave
@@ -148,12 +152,6 @@ struct Args {
 constexpr int kWideMinNx = 48;
 inline int wave_lx(const Geo& g) { return g.lx != 0 ? g.lx : (g.nx >= kWideMinNx ? 16 : 8); }
 constexpr int WZ = 11;  // owned node planes per wave (WZ + 1 steps)
-#ifndef MLQ_WAVE_PD_RES
-#define MLQ_WAVE_PD_RES 1
-#endif
-#ifndef MLQ_RES_WAVES
-#define MLQ_RES_WAVES 4
-#endif
 
 // steps between issuing a slab's loads and using them
 template <typename R, int MODE>
@@ -161,7 +159,7 @@ constexpr int wave_prefetch() {
 #ifdef MLQ_WAVE_PD
   return MLQ_WAVE_PD;
 #else
-  return (sizeof(R) == 8 && (MODE == kRes || MODE == kRhs)) ? MLQ_WAVE_PD_RES : 2;
+  return 2;
 #endif
 }
 
@@ -176,7 +174,7 @@ __device__ inline R shdn(R v, int d) {
 // (an approximation good to about 1e-6, used where only the Krylov operator needs it); 3 = the
 // isotropic field v, p = max(v, cfa), q = 0.  CF > 0 reads 4 bytes per element instead of 8.
 template <typename R, typename TC, typename TI, int MODE, int JB, int LX, int CF>
-__global__ __launch_bounds__(NT, (sizeof(R) == 8 && (MODE == kRes || MODE == kRhs)) ? MLQ_RES_WAVES : 1) void k_wave3(Args<R> A) {
+__global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
   constexpr int LY = 64 / LX;
   constexpr int WTX = LX - 1, WTY = LY - 1;  // owned nodes per wave along x and y
   const Geo& g = A.g;
@@ -187,7 +185,11 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 8 && (MODE == kRes || MODE == kRh
   const int q = NB >> 3, r = NB & 7, xcd = L & 7;
   const int W = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + (L >> 3);
   const int sb = W / A.bps, blk = W - sb * A.bps;
-  const bool sample_on = A.active == nullptr || A.active[sb] != 0;
+  // time blocks: sb is a virtual sample (one time level); sr the sample it belongs to, whose
+  // coefficients, flags and Krylov scalars it uses; slot 0 of a block holds its initial state
+  const int grp = g.group > 1 ? g.group : 1;
+  const int sr = sb / grp, slot = sb - sr * grp;
+  const bool sample_on = (grp == 1 || slot != 0) && (A.active == nullptr || A.active[sr] != 0);
   constexpr bool kMass = MODE != kPK;
   __shared__ double red[NT / 64][3];
   const int lane = threadIdx.x & 63;
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 8 && (MODE == kRes || MODE == kRh
     const int64_t plane = (int64_t)g.nx * g.ny;
     const int64_t sbase = (int64_t)sb * g.nn;
     constexpr int kCw = CF == 0 ? 2 : 1;  // stored values per element
-    const TC* cf = (const TC*)A.coef + (int64_t)sb * g.P * kCw;
+    const TC* cf = (const TC*)A.coef + (int64_t)sr * g.P * kCw;
     const int ex_n = g.nx - 1, ey_n = g.ny - 1;
     const bool elem_xy = ex >= 0 && ey >= 0 && ex < ex_n && ey < ey_n;
     const bool owner = i < WTX && j < WTY && ex + 1 < g.nx && ey + 1 < g.ny;
@@ -247,11 +249,11 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 8 && (MODE == kRes || MODE == kRh
     const R* xs = nullptr;
     const R* ds_ = nullptr;
     const double* us = nullptr;
-    if constexpr (MODE == kPK || MODE == kFull) xs = A.x + sbase;
+    if constexpr (MODE == kPK || MODE == kFull || MODE == kCoup) xs = A.x + sbase;
     if constexpr (MODE == kFull) ds_ = A.d + sbase;
     if constexpr (MODE == kRes || MODE == kRhs) us = A.u + sbase;
     auto in_val = [&](uint32_t po, int dn, R& vk, R& vm) {
-      if constexpr (MODE == kPK) {
+      if constexpr (MODE == kPK || MODE == kCoup) {
         vk = (R)at(xs + dn, lb + po);
       } else if constexpr (MODE == kFull) {
         const R v = (R)at(xs + dn, lb + po);
@@ -305,7 +307,16 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 8 && (MODE == kRes || MODE == kRh
     const R KM = (R)(g.Hm / 216.0);
     const R CX0 = (R)g.cx0, CX1 = (R)g.cx1, CY0 = (R)g.cy0, CY1 = (R)g.cy1, CZ0 = (R)g.cz0, CZ1 = (R)g.cz1;
     R sj = 0;
-    if constexpr (MODE == kPK) sj = (R)A.inv_eta[(int64_t)sb * (A.kmax + 1) + A.j];
+    if constexpr (MODE == kPK) sj = (R)A.inv_eta[(int64_t)sr * (A.kmax + 1) + A.j];
+    double load = A.load;
+    if constexpr (MODE == kRhs) {
+      if (grp > 1) {
+        const double ta = (double)(A.k0 + slot - 1) * A.dt_load, tb = (double)(A.k0 + slot) * A.dt_load;
+        const double ra = (A.t_on <= ta && ta < A.t_off) ? A.amp : 0.0;
+        const double rb = (A.t_on <= tb && tb < A.t_off) ? A.amp : 0.0;
+        load = 0.5 * A.dt_load * (rb + ra);
+      }
+    }
 
     // one slab: planes lo (k) and hi (k + 1), its coefficients and the node inputs of
     // plane k are resident (loaded PD steps earlier)
@@ -340,7 +351,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 8 && (MODE == kRes || MODE == kRh
             if constexpr (MODE == kRes) {
               const double v = (double)xin[c];
               xm[c] = (R)(v + A.io.dt * iion3(v, A.io));
-            } else if constexpr (MODE == kRhs) {
+            } else if constexpr (MODE == kRhs || MODE == kCoup) {
               xm[c] = xin[c];
             } else {
               xm[c] = c < 4 ? lo.m[c] : hi.m[c - 4];
@@ -376,6 +387,8 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 8 && (MODE == kRes || MODE == kRh
           }
         } else if constexpr (MODE == kFull) {
           put(A.y + sbase, ob + kk * pbR, sres);
+        } else if constexpr (MODE == kCoup) {
+          put(A.y + sbase, ob + kk * pbR, at(A.y + sbase, ob + kk * pbR) + sres);
         } else if constexpr (MODE == kRes) {
           const double G = (double)sres;
           const double bb = (double)p0;
@@ -387,7 +400,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 8 && (MODE == kRes || MODE == kRh
           n1 += G * G;
           n2 += bb * bb;
         } else {
-          put(A.bout + sbase, obd + kk * pbD, (double)sres + A.load * (double)p0);
+          put(A.bout + sbase, obd + kk * pbD, (double)sres + load * (double)p0);
           const double uk = (double)p1;
           double ustart = uk;
           if (A.uprev != nullptr) {
@@ -396,7 +409,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 8 && (MODE == kRes || MODE == kRh
             double* ap = (double*)((char*)(A.act + sbase) + obd + kk * pbD);
             if (*ap < 0.0 && um < A.u_th && uk >= A.u_th) *ap = A.t_prev + A.dt_act * (A.u_th - um) / (uk - um);
           }
-          put(A.ucopy + sbase, obd + kk * pbD, ustart);
+          if (A.ucopy != nullptr) put(A.ucopy + sbase, obd + kk * pbD, ustart);
         }
       }
       acc_top = top;
@@ -597,6 +610,34 @@ void launch_residual3(const Geo& g, const Ionic& io, const Work& w, int32_t B, b
     launch_wave3<double, float, float, kRes>(g, a, B, s);
   else
     launch_wave3<double, double, double, kRes>(g, a, B, s);
+}
+
+void launch_rhs3_block(const Geo& g, const double* U, double* b, const void* coef, const double* fbox, int k0,
+                       double dt, double t_on, double t_off, double amp, int32_t Bv, bool mixed, hipStream_t s) {
+  Args<double> a{};
+  // virtual sample v reads U at v - 1 (slot 0 of a block, its initial state, feeds slot 1)
+  a.g = g; a.u = U - g.nn; a.coef = coef; a.bout = b; a.ucopy = nullptr; a.fbox = fbox; a.load = 0.0;
+  a.ck = -0.5 * dt; a.cm = 1.0; a.active = nullptr; a.uprev = nullptr;
+  a.k0 = k0; a.t_on = t_on; a.t_off = t_off; a.amp = amp; a.dt_load = dt;
+  if (mixed)
+    launch_wave3_cf<double, float, float, kRhs, 0, 0>(g, a, Bv, s);
+  else
+    launch_wave3_cf<double, double, double, kRhs, 0, 0>(g, a, Bv, s);
+}
+
+void launch_coupling3(const Geo& g, const void* x, void* wv, const void* coef_or_theta, double ck, int32_t Bv,
+                      const int32_t* active, bool mixed, hipStream_t s) {
+  if (mixed) {
+    Args<float> a{};
+    a.g = g; a.x = (const float*)x - g.nn; a.coef = coef_or_theta; a.y = (float*)wv; a.ck = ck; a.cm = -1.0;
+    a.active = active;
+    launch_wave3<float, float, float, kCoup>(g, a, Bv, s);
+  } else {
+    Args<double> a{};
+    a.g = g; a.x = (const double*)x - g.nn; a.coef = coef_or_theta; a.y = (double*)wv; a.ck = ck; a.cm = -1.0;
+    a.active = active;
+    launch_wave3<double, double, double, kCoup>(g, a, Bv, s);
+  }
 }
 
 void launch_rhs3(const Geo& g, const Work& w, const double* fbox, double load_coef, double dt, int32_t B, bool mixed,

@@ -27,7 +27,8 @@ class ConfigRunner:
 
     def __init__(self, cfg: dict, prec: int | None = None, device="cuda", newton_tol=None, inner_tol=None,
                  max_inner=30, kl_rank_factor=2, kl_eps=1e-2, log=None, concurrent=True,
-                 newton_guess=mlq.MLQ_GUESS_EXTRAPOLATE, tune_layout=True, tune_launch=True):
+                 newton_guess=mlq.MLQ_GUESS_EXTRAPOLATE, tune_layout=True, tune_launch=True, steps_per_block=0,
+                 block_guess=mlq.MLQ_GUESS_PREVIOUS):
         say = log if log is not None else (lambda m: None)
         self.cfg = cfg
         self.device = device
@@ -64,6 +65,13 @@ class ConfigRunner:
                 raise ValueError(f"the truncation tolerance {kl_eps} needs more than {M} modes")
             say(f"stochastic dimension M = {M} (trace residual {resid:.4f})")
         self.n_modes = M
+        # all-at-once solves in time blocks of steps_per_block steps (0: time stepping); the block
+        # GMRES needs about that many more iterations than one step
+        self.steps_per_block = int(steps_per_block)
+        self.block_guess = block_guess
+        if self.steps_per_block > 0:
+            max_inner = min(64, max_inner + self.steps_per_block)
+            tune_launch = False
         self.kd = make_kd(M, kl_rank_factor * M)
         say("KL set-up")
         lam, psi, self.kl_rank, self.kl_resid = mlq.kl_modes(self.kd, device=device)
@@ -123,7 +131,8 @@ class ConfigRunner:
                 # the faster lane layout of the 3D kernels for this grid and batch, by timing
                 t = L.tune_lane_layout()
                 say(f"level {l}: lane layout {L.lanes_x} (apply ms: 8 lanes {t[8]:.3f}, 16 lanes {t[16]:.3f})")
-            if newton_guess in (mlq.MLQ_GUESS_REFERENCE, mlq.MLQ_GUESS_REFERENCE_LOCAL):
+            if newton_guess in (mlq.MLQ_GUESS_REFERENCE, mlq.MLQ_GUESS_REFERENCE_LOCAL) or (
+                    self.steps_per_block > 0 and block_guess != mlq.MLQ_GUESS_PREVIOUS):
                 # the unperturbed reference solution (all coordinates zero: theta = its mean)
                 Y0 = torch.zeros((M * self.components, 1), dtype=torch.float64, device=device)
                 if self.vector:
@@ -179,7 +188,10 @@ class ConfigRunner:
         outs = []
         for i in range(0, B, c):
             theta = self._fields(L, Y[:, i:i + c] if c < B else Y)
-            out = L.solve(theta) if fields is None else L.solve_fields(theta, per_sample_probes=False, **fields)
+            if self.steps_per_block > 0 and fields is None:
+                out = L.solve_blocks(theta, min(self.steps_per_block, int(L.desc.n_steps)), self.block_guess)
+            else:
+                out = L.solve(theta) if fields is None else L.solve_fields(theta, per_sample_probes=False, **fields)
             if out["code"] != mlq.MLQ_OK:
                 st = out["status"].cpu().numpy()
                 raise mlq.MlqError(out["code"], f"{int((st != 0).sum())} samples failed on level {l}")
@@ -190,10 +202,12 @@ class ConfigRunner:
         sums = it.sum(dim=0).cpu()  # waits for the solve on this stream
         newton, inner = float(sums[0]), float(sums[1])
         el = time.perf_counter() - t0
+        # a block GMRES iteration applies the operator to every time level of the block
+        per_it = float(L.n_nodes) * (min(self.steps_per_block, int(L.desc.n_steps)) if self.steps_per_block else 1)
         with self._lock:
-            self.dof_iters += float(L.n_nodes) * inner
+            self.dof_iters += per_it * inner
             self.st_dof += float(L.n_nodes) * float(L.desc.n_steps) * B
-            self.level_dof_iters[l] += float(L.n_nodes) * inner
+            self.level_dof_iters[l] += per_it * inner
             self.level_seconds[l] += el
             self.level_newton[l] += newton
             self.level_inner[l] += inner

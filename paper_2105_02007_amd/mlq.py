@@ -30,6 +30,7 @@ EXPORTED = [
     "mlq_transfer_add", "mlq_field_norm2", "mlq_set_reference", "mlq_tet_locate", "mlq_transfer_add_weighted",
     "mlq_set_lane_layout", "mlq_lattice_points", "mlq_solve_batch_static",
     "mlq_kl_weights", "mlq_lattice_weights", "mlq_fibre_field", "mlq_set_gmres_block",
+    "mlq_workspace_bytes_blocks", "mlq_solve_batch_blocks",
 ]
 STATIC_WS_BYTES = 64 << 20
 MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE, MLQ_GUESS_REFERENCE, MLQ_GUESS_REFERENCE_LOCAL = 0, 1, 2, 3
@@ -115,6 +116,8 @@ def _load():
         "mlq_set_reference": [VP, VP],
         "mlq_set_lane_layout": [VP, I32],
         "mlq_set_gmres_block": [VP, I32],
+        "mlq_workspace_bytes_blocks": [VP, I32, I32, C.POINTER(C.c_size_t)],
+        "mlq_solve_batch_blocks": [VP, VP, I32, I32, I32, VP, C.c_size_t, VP, VP, VP, VP, VP],
         "mlq_lattice_points": [VP, VP, I32, I64, I64, I32, I32, VP, VP],
         "mlq_tet_locate": [VP, I64, VP, I64, VP, I64, VP, VP],
         "mlq_transfer_add_weighted": [VP, VP, I32, I64, I32, VP, VP, C.c_double, VP, VP, VP],
@@ -305,6 +308,26 @@ class Level:
         if code not in (MLQ_OK, MLQ_ENOCONV):
             check(code)
         return dict(qoi=qoi, status=status, iters=iters, u=u, act=act, code=code)
+
+    def solve_blocks(self, theta, steps_per_block, guess=MLQ_GUESS_PREVIOUS, want_state=False):
+        """All-at-once solve in time blocks of steps_per_block steps (mlq_solve_batch_blocks)."""
+        import torch
+        B = theta.shape[-2]
+        nbytes = C.c_size_t()
+        check(lib.mlq_workspace_bytes_blocks(self.handle, int(B), int(steps_per_block), C.byref(nbytes)))
+        if self._ws is None or self._ws.numel() < nbytes.value:
+            self._ws = None
+            self._ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        qoi = torch.empty(B, dtype=torch.float64, device=self.device)
+        status = torch.empty(B, dtype=torch.int32, device=self.device)
+        iters = torch.empty((B, 2), dtype=torch.int64, device=self.device)
+        u = torch.empty((B, self.n_nodes), dtype=torch.float64, device=self.device) if want_state else None
+        code = lib.mlq_solve_batch_blocks(self.handle, _ptr(theta), int(B), int(steps_per_block), int(guess),
+                                          _ptr(self._ws), nbytes.value, _ptr(qoi), _ptr(status), _ptr(iters), _ptr(u),
+                                          _stream())
+        if code not in (MLQ_OK, MLQ_ENOCONV):
+            check(code)
+        return dict(qoi=qoi, status=status, iters=iters, u=u, code=code)
 
     def solve_static(self, theta):
         """mlq_solve_batch_static: the solve with the library's static device workspace (no
