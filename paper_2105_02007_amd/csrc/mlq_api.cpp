@@ -794,33 +794,40 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
   for (int32_t k = 0; k < n_steps; ++k) {
     const double t0 = (double)k * dt, t1 = (double)(k + 1) * dt;
     const double load = 0.5 * dt * (rate(t1) + rate(t0));
-    timed(level, MLQ_K_RHS, nn * batch, s, [&] {
-      if (tet)  // also the extrapolated start and the previous step's activation
-        launch_tet_rhs(td, w, level->fbox, load, dt, batch, mixed, s, k > 0 ? w.ukm1 : nullptr,
-                       d.newton_guess == MLQ_GUESS_EXTRAPOLATE, d.u_th, (double)(k - 1) * dt);
-      else if (g.dim == 3)  // the same
-        launch_rhs3(g, w, level->fbox, load, dt, batch, mixed, s, k > 0 ? w.ukm1 : nullptr,
-                    d.newton_guess == MLQ_GUESS_EXTRAPOLATE, d.u_th, (double)(k - 1) * dt);
-      else
-        launch_rhs(g, w, level->fbox, load, dt, batch, mixed, s);
-    });
+    // 3D boxes need no right-hand side: the first residual of the step forms the Newton start and
+    // the previous step's activation times (launch_residual3f)
+    const bool box3 = g.dim == 3 && !tet;
+    if (!box3)
+      timed(level, MLQ_K_RHS, nn * batch, s, [&] {
+        if (tet)  // also the extrapolated start and the previous step's activation
+          launch_tet_rhs(td, w, level->fbox, load, dt, batch, mixed, s, k > 0 ? w.ukm1 : nullptr,
+                         d.newton_guess == MLQ_GUESS_EXTRAPOLATE, d.u_th, (double)(k - 1) * dt);
+        else
+          launch_rhs(g, w, level->fbox, load, dt, batch, mixed, s);
+      });
     // the rhs kernels start Newton from u = u_k; the extrapolated guess replaces it
     const bool fused3 = g.dim == 3 || tet;  // the 3D and tetrahedral rhs kernels did the two steps below
     if (d.newton_guess == MLQ_GUESS_EXTRAPOLATE && k > 0 && !fused3) launch_extrapolate(w, level->nn, batch, s);
-    if ((d.newton_guess == MLQ_GUESS_REFERENCE || d.newton_guess == MLQ_GUESS_REFERENCE_LOCAL) &&
-        level->ref != nullptr)
+    const bool ref_guess = (d.newton_guess == MLQ_GUESS_REFERENCE || d.newton_guess == MLQ_GUESS_REFERENCE_LOCAL) &&
+                           level->ref != nullptr;
+    if (ref_guess)
       launch_guess_reference(w, level->ref + (size_t)k * level->nn, level->ref + (size_t)(k + 1) * level->nn,
                              level->nn, batch, d.newton_guess == MLQ_GUESS_REFERENCE_LOCAL, s);
     launch_newton_reset(w, batch, s);
     int32_t active = batch;
     for (int it = 0;; ++it) {
       timed(level, MLQ_K_RESIDUAL, nn * active, s, [&] {
-        if (tet)
+        if (tet) {
           launch_tet_residual(td, level->io, w, batch, mixed, s);
-        else if (g.dim == 3)
-          launch_residual3(g, level->io, w, batch, mixed, s);
-        else
+        } else if (box3) {
+          // first iteration of the step: the iterate starts at u_k, its extrapolation, or the
+          // reference guess already written to w.u
+          const int start = it > 0 || ref_guess ? 0 : (d.newton_guess == MLQ_GUESS_EXTRAPOLATE && k > 0 ? 2 : 1);
+          launch_residual3f(g, level->io, w, batch, mixed, s, start, it == 0 && k > 0 ? w.ukm1 : nullptr,
+                            level->fbox, load, d.u_th, (double)(k - 1) * dt);
+        } else {
           launch_residual(g, level->io, w, batch, mixed, s);
+        }
       });
       timed(level, MLQ_K_SMALL, 0.0, s, [&] {
         launch_newton_check(g, w, batch, d.newton_tol, s);

@@ -242,6 +242,14 @@ void launch_residual3(const Geo& g, const Ionic& io, const Work& w, int32_t B, b
 void launch_rhs3(const Geo& g, const Work& w, const double* fbox, double load_coef, double dt, int32_t B, bool mixed,
                  hipStream_t s, const double* uprev = nullptr, bool extrap = false, double u_th = 0.0,
                  double t_prev = 0.0);
+// 3D boxes: the step equation's residual without a separate right-hand side,
+//   F = M ((u - u_k) + dt I_ion(u)) + dt/2 K (u + u_k) - load F_box,
+// with -F and d = dt I_ion'(u) written and the partial norms |F|^2, |w u|^2, |w u_k + load F_box|^2
+// (w the lumped mass) per workgroup.  start: the Newton iterate is w.u (0), u_k (1) or the
+// extrapolation 2 u_k - u_(k-1) (2), written to w.u when start > 0; uprev (u_(k-1), may be NULL):
+// also records the activation times of the step from t_prev to t_prev + dt.
+void launch_residual3f(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s, int start,
+                       const double* uprev, const double* fbox, double load, double u_th, double t_prev);
 void launch_activation_between(const double* uold, const double* unew, double* act, int64_t nn, int32_t B,
                                double u_th, double t_k, double dt, hipStream_t s);
 void launch_cast_f32(const double* src, float* dst, int64_t n, hipStream_t s);

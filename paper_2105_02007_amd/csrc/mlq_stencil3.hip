@@ -37,7 +37,7 @@ namespace {
 
 constexpr int NT = 256;           // threads per workgroup (four independent waves)
 
-enum { kPK = 0, kFull = 1, kRes = 2, kRhs = 3, kCoup = 4 };
+enum { kPK = 0, kFull = 1, kRes = 2, kRhs = 3, kCoup = 4, kResF = 5 };
 
 template <typename R>
 struct Elem {
@@ -110,7 +110,8 @@ struct Args {
   const void* coef;   // CF = 0: [B][P][2] pairs (p, q), coefficient precision; else the field [B][P]
   double cfa;         // CF > 0: (s_l - s_t)/2 for the fibre angle, the floor for the isotropic field
   T* y;               // kPK: w; kFull: y
-  const double* u;   // kRes / kRhs input (FP64)
+  const double* u;   // kRes / kRhs input (FP64); kResF: the Newton iterate (start 0)
+  const double* ukp;  // kResF: u_k, the state at the start of the step
   const double* bvec; // kRes: b
   double* bout;       // kRhs: b
   double* ucopy;      // kRhs: u := u_k (or 2 u_k - u_{k-1} with extrap)
@@ -159,7 +160,9 @@ constexpr int wave_prefetch() {
 #ifdef MLQ_WAVE_PD
   return MLQ_WAVE_PD;
 #else
-  return 2;
+  // the fused residual carries two FP64 values per corner and four per owned node: one slab
+  // ahead keeps it at three waves per SIMD
+  return MODE == kResF ? 1 : 2;
 #endif
 }
 
@@ -249,9 +252,22 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     const R* xs = nullptr;
     const R* ds_ = nullptr;
     const double* us = nullptr;
+    const double* uks = nullptr;
+    const double* ups = nullptr;
     if constexpr (MODE == kPK || MODE == kFull || MODE == kCoup) xs = A.x + sbase;
     if constexpr (MODE == kFull) ds_ = A.d + sbase;
     if constexpr (MODE == kRes || MODE == kRhs) us = A.u + sbase;
+    // kResF: the JB parameter carries the start kind (0: w.u, 1: u_k, 2: 2 u_k - u_(k-1)) so that
+    // every load of the march is issued without a branch; absent optional inputs read u_k instead
+    // (cache hits), their values unused
+    constexpr int kStart = MODE == kResF ? JB : 0;
+    const double* fbs = nullptr;
+    if constexpr (MODE == kResF) {
+      uks = A.ukp + sbase;
+      us = kStart == 0 ? A.u + sbase : uks;
+      ups = A.uprev != nullptr ? A.uprev + sbase : uks;
+      fbs = A.load != 0.0 ? A.fbox : uks;
+    }
     auto in_val = [&](uint32_t po, int dn, R& vk, R& vm) {
       if constexpr (MODE == kPK || MODE == kCoup) {
         vk = (R)at(xs + dn, lb + po);
@@ -259,6 +275,15 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
         const R v = (R)at(xs + dn, lb + po);
         vk = v;
         vm = v + (R)at(ds_ + dn, lb + po) * v;
+      } else if constexpr (MODE == kResF) {
+        // from the iterate u and u_k: the stiffness input u + u_k and the mass input
+        // (u - u_k) + dt I_ion(u)
+        const double a = at(uks + dn, lbd + po);
+        double u = a;
+        if constexpr (kStart == 0) u = at(us + dn, lbd + po);
+        if constexpr (kStart == 2) u = 2.0 * a - at(ups + dn, lbd + po);
+        vk = (R)(u + a);
+        vm = (R)((u - a) + A.io.dt * iion3(u, A.io));
       } else {
         // kRes / kRhs: the mass input (u + dt I_ion(u), or u) is formed in step() from vk, so
         // that the register ring of planes holds one value per corner
@@ -270,7 +295,7 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     };
     auto fetch = [&](int k, Pl& r) {
       const uint32_t kk = (uint32_t)min(max(k, 0), g.nz - 1);
-      const uint32_t po = kk * ((MODE == kRes || MODE == kRhs) ? pbD : pbR);
+      const uint32_t po = kk * ((MODE == kRes || MODE == kRhs || MODE == kResF) ? pbD : pbR);
       in_val(po, 0, r.k[0], r.m[0]);
       in_val(po, 1, r.k[1], r.m[1]);
       in_val(po, nxs, r.k[2], r.m[2]);
@@ -287,10 +312,24 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     const double* bs = nullptr;
     if constexpr (MODE == kPK) vjs = A.vj + sbase;
     if constexpr (MODE == kRes) bs = A.bvec + sbase;
-    auto fetch_pre = [&](int k, R& p0, R& p1) {
+    auto fetch_pre = [&](int k, R& p0, R& p1, R& p2, R& p3) {
       const uint32_t kc = (uint32_t)min(max(k, 0), g.nz - 1);
       p0 = 0;
       p1 = 0;
+      p2 = 0;
+      p3 = 0;
+      if constexpr (MODE == kResF) {
+        // at the owned node: the iterate, u_k, u_(k-1) (activation) and the stimulus load
+        const double a = at(uks, obd + kc * pbD);
+        const double um = at(ups, obd + kc * pbD);
+        double u = a;
+        if constexpr (kStart == 0) u = at(us, obd + kc * pbD);
+        if constexpr (kStart == 2) u = 2.0 * a - um;
+        p0 = (R)u;
+        p1 = (R)a;
+        p2 = (R)um;
+        p3 = (R)at(fbs, obd + kc * pbD);
+      }
       if constexpr (MODE == kPK) p0 = at(vjs, ob + kc * pbR);
       if constexpr (MODE == kRes) {
         p0 = (R)at(bs, obd + kc * pbD);
@@ -321,7 +360,7 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     // one slab: planes lo (k) and hi (k + 1), its coefficients and the node inputs of
     // plane k are resident (loaded PD steps earlier)
     R acc_top = 0;
-    auto step = [&](int k, const Pl& lo, const Pl& hi, R cp, R cq, R p0, R p1) {
+    auto step = [&](int k, const Pl& lo, const Pl& hi, R cp, R cq, R p0, R p1, R p2, R p3) {
       const bool slab = k >= 0 && k <= g.nz - 2;
       if constexpr (CF == 1 || CF == 2) {
         const float t2 = 2.0f * (float)cp;
@@ -389,6 +428,28 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
           put(A.y + sbase, ob + kk * pbR, sres);
         } else if constexpr (MODE == kCoup) {
           put(A.y + sbase, ob + kk * pbR, at(A.y + sbase, ob + kk * pbR) + sres);
+        } else if constexpr (MODE == kResF) {
+          // F = M ((u - u_k) + dt I_ion(u)) + dt/2 K (u + u_k) - load F_box, the step equation's
+          // residual G(u) - b without forming G(u) and b; the stopping test's scale is the
+          // lumped mass of the two states, |w u| + |w u_k + load F_box| (w the node weight)
+          const double uo = (double)p0, uko = (double)p1, fb = load * (double)p3;
+          const double F = (double)sres - fb;
+          const uint32_t oi = (uint32_t)oof * (uint32_t)sizeof(TI) + kk * (uint32_t)plane * (uint32_t)sizeof(TI);
+          put((TI*)A.r0 + sbase, oi, (TI)(-F));
+          put((TI*)A.dout + sbase, oi, (TI)(A.io.dt * diion3(uo, A.io)));
+          if constexpr (kStart != 0) put(A.ucopy + sbase, obd + kk * pbD, uo);
+          if (A.uprev != nullptr) {  // activation in the step from t_(k-1) to t_k
+            const double um = (double)p2;
+            double* ap = (double*)((char*)(A.act + sbase) + obd + kk * pbD);
+            if (*ap < 0.0 && um < A.u_th && uko >= A.u_th)
+              *ap = A.t_prev + A.dt_act * (A.u_th - um) / (uko - um);
+          }
+          const int X = ex + 1, Y = ey + 1;
+          const double wl = g.Hx * g.Hy * g.Hz * ((X == 0 || X == g.nx - 1) ? 0.5 : 1.0) *
+                            ((Y == 0 || Y == g.ny - 1) ? 0.5 : 1.0) * ((k == 0 || k == g.nz - 1) ? 0.5 : 1.0);
+          n0 += F * F;
+          n1 += (wl * uo) * (wl * uo);
+          n2 += (wl * uko + fb) * (wl * uko + fb);
         } else if constexpr (MODE == kRes) {
           const double G = (double)sres;
           const double bb = (double)p0;
@@ -423,22 +484,22 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     constexpr int PD = wave_prefetch<R, MODE>();
     const int k0 = zs - 1;
     Pl P[NS + 1];
-    R Cp[NS], Cq[NS], Q0[NS], Q1[NS];
+    R Cp[NS], Cq[NS], Q0[NS], Q1[NS], Q2[NS], Q3[NS];
 #pragma unroll
     for (int t = 0; t <= PD; ++t) fetch(k0 + t, P[t]);
 #pragma unroll
     for (int t = 0; t < PD; ++t) {
       fetch_coef(k0 + t, Cp[t], Cq[t]);
-      fetch_pre(k0 + t, Q0[t], Q1[t]);
+      fetch_pre(k0 + t, Q0[t], Q1[t], Q2[t], Q3[t]);
     }
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
       if (t + PD + 1 <= NS) fetch(k0 + t + PD + 1, P[t + PD + 1]);
       if (t + PD < NS) {
         fetch_coef(k0 + t + PD, Cp[t + PD], Cq[t + PD]);
-        fetch_pre(k0 + t + PD, Q0[t + PD], Q1[t + PD]);
+        fetch_pre(k0 + t + PD, Q0[t + PD], Q1[t + PD], Q2[t + PD], Q3[t + PD]);
       }
-      step(k0 + t, P[t], P[t + 1], Cp[t], Cq[t], Q0[t], Q1[t]);
+      step(k0 + t, P[t], P[t + 1], Cp[t], Cq[t], Q0[t], Q1[t], Q2[t], Q3[t]);
     }
     if constexpr (MODE == kPK && JB > 0) {
       // projections w . v_i (i < j) over the wave's owned nodes, into dacc[i + 1]: all
@@ -481,7 +542,7 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
       A.dpart[((int64_t)sb * (A.kmax + 1) + i) * A.npart + blk] = v;
     }
   }
-  if constexpr (MODE == kRes) {
+  if constexpr (MODE == kRes || MODE == kResF) {
     double v[3] = {n0, n1, n2};
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -539,7 +600,7 @@ void launch_wave3_cf(const Geo& g, Args<R>& a, int32_t B, hipStream_t s) {
 // and cosine, the public apply with the accurate ones (the values k_coefs stores).
 template <typename R, typename TC, typename TI, int MODE, int JB = 0>
 void launch_wave3(const Geo& g, Args<R>& a, int32_t B, hipStream_t s) {
-  if constexpr (sizeof(TC) == 8 || MODE == kRes || MODE == kRhs) {
+  if constexpr (sizeof(TC) == 8 || MODE == kRes || MODE == kRhs || MODE == kResF) {
     launch_wave3_cf<R, TC, TI, MODE, JB, 0>(g, a, B, s);
   } else {
     a.cfa = g.cfa;
@@ -610,6 +671,29 @@ void launch_residual3(const Geo& g, const Ionic& io, const Work& w, int32_t B, b
     launch_wave3<double, float, float, kRes>(g, a, B, s);
   else
     launch_wave3<double, double, double, kRes>(g, a, B, s);
+}
+
+void launch_residual3f(const Geo& g, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s, int start,
+                       const double* uprev, const double* fbox, double load, double u_th, double t_prev) {
+  Args<double> a{};
+  a.g = g; a.io = io; a.u = w.u; a.ukp = w.uk; a.ucopy = w.u; a.uprev = uprev; a.act = w.act;
+  a.u_th = u_th; a.t_prev = t_prev; a.dt_act = io.dt; a.fbox = fbox; a.load = load;
+  a.coef = w.coef; a.r0 = w.V; a.dout = w.d; a.part = w.part; a.ck = 0.5 * io.dt; a.cm = 1.0;
+  a.active = w.newton_active;
+  // the start kind is the JB parameter of the kernel (compile time)
+  auto go = [&](auto st) {
+    constexpr int S = decltype(st)::value;
+    if (mixed)
+      launch_wave3<double, float, float, kResF, S>(g, a, B, s);
+    else
+      launch_wave3<double, double, double, kResF, S>(g, a, B, s);
+  };
+  if (start == 0)
+    go(std::integral_constant<int, 0>{});
+  else if (start == 1)
+    go(std::integral_constant<int, 1>{});
+  else
+    go(std::integral_constant<int, 2>{});
 }
 
 void launch_rhs3_block(const Geo& g, const double* U, double* b, const void* coef, const double* fbox, int k0,
