@@ -86,7 +86,7 @@ WORKLOAD_TEXT = {
     "c4i": "the paper's cube model (as c2i) with the paper's QMC rule: MLQMC with Halton points (indices 1..N_l, "
            "16 random shifts mod 1), 3D unit cube Q1 9^3..129^3 nested, 32..512 steps, 256/64/16/4/1 points, "
            "mean activation time",
-    "c5": "non-nested prolate-ellipsoidal shell, P1 tetrahedra 26k/187k/1.4M vertices, 512 steps, 256-mode KL "
+    "c5": "non-nested prolate-ellipsoidal shell, P1 tetrahedra 25k/199k/1.6M vertices, 512 steps, 256-mode KL "
           "(l = 0.1 long axis), rule-based +60/-60 deg fibres, combination estimator 16/64/256 nested MC points, "
           "mean activation time",
     "c5i": "the c5 shells with the paper's idealised-ventricle model: isotropic G = max(v, 0.1 E[V]) I, "

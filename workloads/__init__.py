@@ -70,6 +70,11 @@ def tet_mesh(level: dict) -> dict:
     return dict(xyz=xyz, tets=tets, e_circ=ec, e_long=el, theta0=th0)
 
 
+# the three non-nested shells (n_mu, n_nu, n_phi cells; vertices (n_mu + 1)(n_nu + 1) n_phi):
+# 24,960 / 198,702 / 1,602,352 vertices, the configured 25k / 200k / 1.6M, with about the same
+# cell aspect on every level
+SHELL_CELLS = [(4, 38, 128), (8, 82, 266), (16, 171, 548)]
+
 # --- the five synthetic workloads -------------------------------------------
 CONFIGS = {
     "c1": dict(
@@ -99,9 +104,9 @@ CONFIGS = {
     # combination form eq. (PimpedML): Q_0, Q_1, Q_2 with 16, 64, 256 nested Monte Carlo
     # points (prefixes of one stream) on the fine, middle and coarse shell
     "c5": dict(
-        name="c5", title="non-nested multilevel, prolate-ellipsoidal shell, P1 tetrahedra 26k/187k/1.4M "
+        name="c5", title="non-nested multilevel, prolate-ellipsoidal shell, P1 tetrahedra 25k/199k/1.6M "
                          "vertices, 512 steps, 256-mode KL, combination estimator",
-        dim=3, levels=_tet_levels([(4, 40, 128), (8, 80, 256), (16, 160, 512)], [512, 512, 512], 5),
+        dim=3, levels=_tet_levels(SHELL_CELLS, [512, 512, 512], 5),
         kl=dict(n_modes=256, corr_len=0.1 * tetshell.LONG_AXIS, std=0.3, grid_level=2),
         sampling=dict(kind="combination", n_per_level=[16, 64, 256]),
         qoi=QOI_MEAN_ACT_TIME, prec=PREC_MIXED, seed=5),
@@ -134,7 +139,7 @@ CONFIGS = {
     "c5v": dict(
         name="c5v", title="non-nested shells with the paper's heart model: random fibre vector field, "
                           "uniform coordinates, 3 x 45 modes, combination estimator",
-        dim=3, levels=_tet_levels([(4, 40, 128), (8, 80, 256), (16, 160, 512)], [512, 512, 512], 5),
+        dim=3, levels=_tet_levels(SHELL_CELLS, [512, 512, 512], 5),
         kl=dict(n_modes=45, corr_len=0.16 * (tetshell.LONG_AXIS / 1.0) ** 2, std=0.3, grid_level=2,
                 kernel="sqexp", components=3, variables="uniform"),
         model="vector",
@@ -147,7 +152,7 @@ CONFIGS = {
     "c5i": dict(
         name="c5i", title="non-nested shells with the paper's ventricle model: isotropic random diffusion, "
                           "87 uniform coordinates, combination estimator",
-        dim=3, levels=_tet_levels([(4, 40, 128), (8, 80, 256), (16, 160, 512)], [512, 512, 512], 5),
+        dim=3, levels=_tet_levels(SHELL_CELLS, [512, 512, 512], 5),
         kl=dict(n_modes=87, corr_len=0.5, std=0.3, grid_level=2,
                 kernel="sqexp", variables="uniform", mean=SIGMA_L, floor=0.1),
         model="iso",
