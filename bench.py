@@ -64,7 +64,7 @@ FIELD_PROBES = [[0.05, 0.05, 0.05], [0.5, 0.5, 0.5], [1.0, 0.5, 0.25], [1.0, 1.0
 
 def field_probes(cfg, runner):
     """Probe points of --fields: FIELD_PROBES in the unit box, or on a shell four vertices of the
-    finest mesh spread over its vertex order (from the apical opening to the base)."""
+    finest mesh spread over its vertex order (from the inner apex region outwards)."""
     import numpy as np
     if runner.tet:
         xyz = runner.meshes[-1]["xyz"]

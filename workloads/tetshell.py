@@ -75,13 +75,10 @@ def shell_mesh(cells, seed, jitter=JITTER):
     M = M + np.where(interior, off[..., 0] * (mu[1] - mu[0]), 0.0)
     N = N + np.where(interior, off[..., 1] * (nu[1] - nu[0]), 0.0)
     F = F + np.where(interior, off[..., 2] * (2.0 * np.pi / n_phi), 0.0)
-    # vertices numbered with the transmural index fastest, then around, then along the long
-    # axis: a block of consecutive rows then finds its neighbours' rows close by in every
-    # direction (the thin transmural direction first), which keeps gathers in cache
-    xyz = spheroidal_to_xyz(M, N, F).transpose(1, 2, 0, 3).reshape(-1, 3)
+    xyz = spheroidal_to_xyz(M, N, F).reshape(-1, 3)
 
     def vid(i, j, k):
-        return (j * n_phi + (k % n_phi)) * (n_mu + 1) + i
+        return (i * (n_nu + 1) + j) * n_phi + (k % n_phi)
 
     I, J, K = np.meshgrid(np.arange(n_mu), np.arange(n_nu), np.arange(n_phi), indexing="ij")
     I, J, K = I.ravel(), J.ravel(), K.ravel()
