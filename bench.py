@@ -408,7 +408,7 @@ def main():
     runner = ConfigRunner(cfg, prec=prec, device=dev, log=log, newton_guess=guess, inner_tol=args.inner_tol,
                           tune_launch=not args.no_tune, steps_per_block=args.steps_per_block, block_guess=bguess)
     t_setup = time.perf_counter() - t_setup
-    log(f"set-up done in {t_setup:.1f} s (KL rank {runner.kl_rank})")
+    log(f"set-up done in {t_setup:.1f} s (KL {runner.kl_method}, rank {runner.kl_rank})")
     runner.log = log
     samp = cfg["sampling"]
     step = make_step(cfg, runner, args, dev)
@@ -485,7 +485,8 @@ def main():
         # no error estimate: the combination form over nested point sets, or a QMC rule with one shift
         "rmse_est": res["rmse"] if has_rmse else None,
         "level_means": res["level_mean"],
-        "kl": {"rank": runner.kl_rank, "trace_resid": runner.kl_resid},
+        "kl": {"method": runner.kl_method, "rank": runner.kl_rank,
+               ("eig_resid" if runner.kl_method == "exact" else "trace_resid"): runner.kl_resid},
         "setup_s": round(t_setup, 2),
         "roofline": roofline,
         "apply_per_level": per_level,

@@ -24,7 +24,9 @@
  *     device buffer (level blob, fields, workspace, outputs) is passed in by the
  *     caller and stays owned by the caller; the one exception is the static
  *     workspace array of mlq_solve_batch_static, part of the library's code
- *     object on each GPU.  Host arrays given to mlq_create_level are
+ *     object on each GPU, and the twiddle tables hipFFT keeps while the plans
+ *     of an MLQ_KL_EXACT mlq_kl_modes call exist (created and destroyed inside
+ *     that call).  Host arrays given to mlq_create_level are
  *     copied during the call.  Each level object owns a few bytes of pinned host
  *     memory for convergence flags.
  *   Layouts: a batch of B samples on a level with n nodes and P elements stores
@@ -466,15 +468,26 @@ typedef struct {
    * MLQ_COV_SQEXP, std_dev^2 exp(-|x - x'|_2^2 / corr_len) (the paper's kernel of Section 5.1,
    * with corr_len = sigma_KL) */
   int32_t cov_kernel;
+  /* eigenpairs: MLQ_KL_CHOLESKY, the pivoted Cholesky route above (any mesh); MLQ_KL_EXACT (Q1
+   * boxes), the n_modes largest eigenpairs of eq. (algEig) itself, by subspace iteration on
+   * 2 n_modes (at least n_modes + 16) columns with Rayleigh-Ritz, the covariance applied through
+   * the FFT of its circulant embedding (2 (n_a - 1) points per axis; exact, since the covariance of
+   * a uniform grid depends on index offsets only), until every returned pair has
+   * |C M psi - lambda psi|_M <= eps lambda (eps > 0; max_rank is not used; 2 n_modes <= nodes) */
+  int32_t method;
 } mlq_kl_desc;
+typedef enum { MLQ_KL_CHOLESKY = 0, MLQ_KL_EXACT = 1 } mlq_kl_method;
 
 /* Device workspace bytes of mlq_kl_modes (dominated by two n x max_rank FP64 arrays). */
 mlq_status mlq_kl_workspace_bytes(const mlq_kl_desc* kd, size_t* ws_bytes);
 
 /* Largest n_modes eigenpairs: lambda_host (M, descending) and the M-orthonormal
  * modes psi_dev (n x M column-major FP64 device array, psi_k^T M psi_k = 1, entry of
- * largest magnitude positive).  rank_out: Cholesky rank used; resid_out:
- * trace(C - L L^T) / trace(C).  Synchronises the stream.
+ * largest magnitude positive).  rank_out: Cholesky rank used (MLQ_KL_EXACT: the subspace
+ * columns); resid_out: trace(C - L L^T) / trace(C) (MLQ_KL_EXACT: the largest relative residual
+ * of the returned pairs; MLQ_ENOCONV if it stayed above eps).  Synchronises the stream.
+ * MLQ_KL_EXACT creates hipFFT plans for the duration of the call (their work area lies in ws_dev;
+ * the FFT library keeps its own twiddle tables while a plan exists).
  * n_modes = 0: the paper's way of fixing M (Section 5.1): the factorisation runs until
  * trace(C - L L^T) <= eps trace(C) (or max_rank) and only rank_out (that rank, the stochastic
  * dimension M) and resid_out are written; lambda_host and psi_dev may be NULL. */

@@ -1569,6 +1569,7 @@ mlq_status mlq_estimate(int32_t kind, int32_t n_levels, int32_t n_shifts, const 
 mlq_status mlq_kl_workspace_bytes(const mlq_kl_desc* kd, size_t* ws_bytes) {
   if (ws_bytes == nullptr || kl_validate(kd) != MLQ_OK) return fail(MLQ_EINVAL, "invalid KL descriptor");
   *ws_bytes = kl_workspace_bytes(kd);
+  if (*ws_bytes == 0) return fail(MLQ_EHIP, "FFT plans of the exact KL route could not be created");
   return MLQ_OK;
 }
 

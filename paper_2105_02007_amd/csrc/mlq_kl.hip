@@ -12,6 +12,7 @@
 // Sign of each mode: its first entry of largest magnitude is positive (entries
 // within a relative 1e-9 of the maximum count as ties).
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <cmath>
@@ -339,6 +340,123 @@ __global__ __launch_bounds__(kT) void k_transfer(Box kb, Box lb, const double* _
   phi[p * M + k] = acc;
 }
 
+// R1 -= R2 (flat)
+__global__ __launch_bounds__(kT) void k_axpy_cols(double* __restrict__ R1, const double* __restrict__ R2, int64_t total) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i < total) R1[i] -= R2[i];
+}
+
+// ---- exact top eigenpairs on box grids (subspace iteration; C by circulant embedding) ----
+// The covariance matrix of a uniform grid is (block) Toeplitz: C_ij = k(x_i - x_j) depends on
+// the index offset only.  Embedded in a circulant of 2 (n_a - 1) points per axis (offsets d and
+// N_a - d carry the same value), its product with a vector is exact through the FFT.
+struct Emb {
+  int32_t dim;
+  int64_t n[3], N[3];  // grid and embedding sizes per axis (1 on unused axes)
+  int64_t ne, nh;      // embedding points, half-spectrum points (N0 / 2 + 1 along axis 0)
+};
+
+// First column of the embedded circulant: c[m] = k(offset(m)), offset_a = min(m_a, N_a - m_a) h_a.
+__global__ __launch_bounds__(kT) void k_circ_col(Emb e, Box b, double s2, double inv_len, int sqexp,
+                                                 double* __restrict__ c) {
+  const int64_t m = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (m >= e.ne) return;
+  int64_t r = m;
+  double d2 = 0.0;
+  for (int a = 0; a < e.dim; ++a) {
+    const int64_t ma = r % e.N[a];
+    r /= e.N[a];
+    const int64_t o = ma < e.N[a] - ma ? ma : e.N[a] - ma;
+    const double d = (double)o * b.h[a];
+    d2 += d * d;
+  }
+  c[m] = s2 * exp(-(sqexp ? d2 : sqrt(d2)) * inv_len);
+}
+
+// Columns col0 .. col0 + nc - 1 of X (n rows) zero-padded into the embedding, E[c][m].
+__global__ __launch_bounds__(kT) void k_embed(Emb e, const double* __restrict__ X, int64_t n, int64_t col0,
+                                              double* __restrict__ E) {
+  const int64_t m = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (m >= e.ne) return;
+  const int c = blockIdx.y;
+  int64_t r = m, i = 0, stride = 1;
+  bool in = true;
+  for (int a = 0; a < e.dim; ++a) {
+    const int64_t ma = r % e.N[a];
+    r /= e.N[a];
+    in = in && ma < e.n[a];
+    i += ma * stride;
+    stride *= e.n[a];
+  }
+  E[(int64_t)c * e.ne + m] = in ? X[(col0 + c) * n + i] : 0.0;
+}
+
+// Y[:, col0 + c] = the grid part of E[c] times scale.
+__global__ __launch_bounds__(kT) void k_extract(Emb e, const double* __restrict__ E, int64_t n, int64_t col0,
+                                                double scale, double* __restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  const int c = blockIdx.y;
+  int64_t r = i, m = 0, stride = 1;
+  for (int a = 0; a < e.dim; ++a) {
+    const int64_t ia = r % e.n[a];
+    r /= e.n[a];
+    m += ia * stride;
+    stride *= e.N[a];
+  }
+  Y[(col0 + c) * n + i] = E[(int64_t)c * e.ne + m] * scale;
+}
+
+// Spectrum times the circulant's eigenvalues (real: the circulant is symmetric).
+__global__ __launch_bounds__(kT) void k_cmul(hipfftDoubleComplex* __restrict__ F, const hipfftDoubleComplex* __restrict__ ch,
+                                             int64_t nh) {
+  const int64_t k = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (k >= nh) return;
+  const int c = blockIdx.y;
+  const double lam = ch[k].x;
+  hipfftDoubleComplex& f = F[(int64_t)c * nh + k];
+  f.x *= lam;
+  f.y *= lam;
+}
+
+// Seeded standard normals (counter-based: splitmix64 of the index, Box-Muller).
+__device__ inline uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ __launch_bounds__(kT) void k_randn(double* __restrict__ X, int64_t total, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= total) return;
+  const uint64_t a = mix64(seed ^ (2 * (uint64_t)i)), c = mix64(seed ^ (2 * (uint64_t)i + 1));
+  const double u1 = ((double)(a >> 11) + 0.5) * 0x1.0p-53, u2 = (double)(c >> 11) * 0x1.0p-53;
+  X[i] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+// out[:, k] = sum_j A[:, j] Z[j][k] (A column-major n x R, Z row-major R x C, out column-major n x C);
+// a thread forms 8 output columns of one row.
+constexpr int kCB = 8;
+__global__ __launch_bounds__(kT) void k_combine8(const double* __restrict__ A, int64_t n, int R,
+                                                 const double* __restrict__ Z, int C, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int k0 = blockIdx.y * kCB;
+  if (i >= n) return;
+  double acc[kCB];
+#pragma unroll
+  for (int q = 0; q < kCB; ++q) acc[q] = 0.0;
+  for (int j = 0; j < R; ++j) {
+    const double a = A[(int64_t)j * n + i];
+    const double* z = Z + (int64_t)j * C + k0;
+#pragma unroll
+    for (int q = 0; q < kCB; ++q)
+      if (k0 + q < C) acc[q] += a * z[q];
+  }
+#pragma unroll
+  for (int q = 0; q < kCB; ++q)
+    if (k0 + q < C) out[(int64_t)(k0 + q) * n + i] = acc[q];
+}
+
 // Cyclic Jacobi eigen-decomposition of a symmetric R x R matrix (row-major, in place).
 // On return A's diagonal holds the eigenvalues and V (row-major) the eigenvectors as columns.
 void jacobi_eig(std::vector<double>& A, std::vector<double>& V, int R) {
@@ -406,6 +524,322 @@ struct KlWork {
   int32_t *rowptr, *col;
   size_t bytes;
 };
+
+// ---- exact route: workspace and driver ----
+Emb make_emb(const Box& b) {
+  Emb e{};
+  e.dim = b.dim;
+  e.ne = 1;
+  for (int a = 0; a < 3; ++a) {
+    e.n[a] = a < b.dim ? b.n[a] : 1;
+    e.N[a] = a < b.dim ? 2 * (b.n[a] - 1) : 1;
+    e.ne *= e.N[a];
+  }
+  e.nh = (e.N[0] / 2 + 1) * e.N[1] * e.N[2];
+  return e;
+}
+
+// Columns of the subspace: twice the modes (at least 16 more), at most the nodes.
+int exact_block(int64_t n, int M) { return (int)std::min<int64_t>(n, std::max(2 * M, M + 16)); }
+
+// Embedded columns transformed together (bounded so that the FFT buffers stay near 4 GB).
+int exact_chunk(const Emb& e, int bcols) {
+  const double per = 8.0 * (double)e.ne + 16.0 * (double)e.nh;
+  return (int)std::max(1.0, std::min((double)bcols, 4.0e9 / per));
+}
+
+struct ExactWork {
+  double *X, *MX, *Y, *MY, *E, *part, *S, *Z, *R1, *R2, *cvec;
+  hipfftDoubleComplex *F, *ch;
+  void* fft_work;
+  size_t bytes;
+};
+
+ExactWork exact_carve(void* base, int64_t n, int bcols, int M, const Emb& e, int chunk, size_t fft_bytes) {
+  ExactWork w{};
+  char* p = (char*)base;
+  size_t o = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* r = p ? (void*)(p + o) : nullptr;
+    o = al(o + bytes);
+    return r;
+  };
+  w.X = (double*)take(sizeof(double) * n * bcols);
+  w.MX = (double*)take(sizeof(double) * n * bcols);
+  w.Y = (double*)take(sizeof(double) * n * bcols);
+  w.MY = (double*)take(sizeof(double) * n * bcols);
+  w.R1 = (double*)take(sizeof(double) * n * M);
+  w.R2 = (double*)take(sizeof(double) * n * M);
+  w.E = (double*)take(sizeof(double) * e.ne * chunk);
+  w.F = (hipfftDoubleComplex*)take(sizeof(hipfftDoubleComplex) * e.nh * chunk);
+  w.cvec = (double*)take(sizeof(double) * e.ne);
+  w.ch = (hipfftDoubleComplex*)take(sizeof(hipfftDoubleComplex) * e.nh);
+  w.part = (double*)take(sizeof(double) * cdiv(n, kGChunk) * bcols * bcols);
+  w.S = (double*)take(sizeof(double) * bcols * bcols);
+  w.Z = (double*)take(sizeof(double) * bcols * bcols);
+  w.fft_work = take(fft_bytes);
+  w.bytes = o;
+  return w;
+}
+
+// hipFFT plans of the embedding (real to complex and back, `batch` columns), with the work area
+// left to the caller's workspace; *work_bytes receives its size.
+hipfftResult exact_plans(const Emb& e, int batch, hipfftHandle* fwd, hipfftHandle* bwd, size_t* work_bytes) {
+  int dims[3];
+  const int rank = e.dim;
+  for (int a = 0; a < rank; ++a) dims[a] = (int)e.N[rank - 1 - a];  // row-major: slowest axis first
+  int inembed[3], onembed[3];
+  for (int a = 0; a < rank; ++a) inembed[a] = onembed[a] = dims[a];
+  onembed[rank - 1] = dims[rank - 1] / 2 + 1;
+  size_t w1 = 0, w2 = 0;
+  hipfftResult r = hipfftCreate(fwd);
+  if (r == HIPFFT_SUCCESS) r = hipfftCreate(bwd);
+  if (r == HIPFFT_SUCCESS) r = hipfftSetAutoAllocation(*fwd, 0);
+  if (r == HIPFFT_SUCCESS) r = hipfftSetAutoAllocation(*bwd, 0);
+  if (r == HIPFFT_SUCCESS)
+    r = hipfftMakePlanMany(*fwd, rank, dims, inembed, 1, (int)e.ne, onembed, 1, (int)e.nh, HIPFFT_D2Z, batch, &w1);
+  if (r == HIPFFT_SUCCESS)
+    r = hipfftMakePlanMany(*bwd, rank, dims, onembed, 1, (int)e.nh, inembed, 1, (int)e.ne, HIPFFT_Z2D, batch, &w2);
+  *work_bytes = std::max(w1, w2);
+  return r;
+}
+
+size_t exact_workspace_bytes(const mlq_kl_desc* kd) {
+  const Box b = make_box(kd);
+  const Emb e = make_emb(b);
+  const int bcols = exact_block(b.nn, kd->n_modes);
+  const int chunk = exact_chunk(e, bcols);
+  hipfftHandle f = 0, g = 0;
+  size_t wb = 0;
+  const hipfftResult r = exact_plans(e, chunk, &f, &g, &wb);
+  if (f) hipfftDestroy(f);
+  if (g) hipfftDestroy(g);
+  if (r != HIPFFT_SUCCESS) return 0;
+  return exact_carve(nullptr, b.nn, bcols, kd->n_modes, e, chunk, wb).bytes;
+}
+
+// Cholesky G = U^T U (upper U, row-major b x b) and its inverse in place of U; false if G is
+// not positive definite.
+bool chol_inv_upper(std::vector<double>& G, int b, std::vector<double>& Uinv) {
+  std::vector<double> U((size_t)b * b, 0.0);
+  for (int j = 0; j < b; ++j) {
+    double d = G[(size_t)j * b + j];
+    for (int k = 0; k < j; ++k) d -= U[(size_t)k * b + j] * U[(size_t)k * b + j];
+    if (!(d > 0.0)) return false;
+    const double ujj = std::sqrt(d);
+    U[(size_t)j * b + j] = ujj;
+    for (int i = j + 1; i < b; ++i) {
+      double v = G[(size_t)j * b + i];
+      for (int k = 0; k < j; ++k) v -= U[(size_t)k * b + j] * U[(size_t)k * b + i];
+      U[(size_t)j * b + i] = v / ujj;
+    }
+  }
+  Uinv.assign((size_t)b * b, 0.0);
+  for (int c = 0; c < b; ++c) {  // solve U x = e_c by back substitution
+    for (int i = c; i >= 0; --i) {
+      double v = i == c ? 1.0 : 0.0;
+      for (int k = i + 1; k <= c; ++k) v -= U[(size_t)i * b + k] * Uinv[(size_t)k * b + c];
+      Uinv[(size_t)i * b + c] = v / U[(size_t)i * b + i];
+    }
+  }
+  return true;
+}
+
+// The n_modes largest eigenpairs of eq. (algEig) on a box grid, C M psi = lambda psi with
+// psi^T M psi = 1, by subspace iteration with Rayleigh-Ritz on bcols >= 2 n_modes columns:
+//   Y = C (M X);  T = (M X)^T Y;  T W = W Theta;  X <- Y W Theta^-1 orthonormalised in the M inner
+//   product (Cholesky of its Gram matrix), until every wanted Ritz pair has
+//   |C M psi - lambda psi|_M <= eps lambda (eps = kd->eps); C is applied through the FFT of its
+//   circulant embedding.  *rank_out = bcols, *resid_out = the largest relative residual.
+mlq_status kl_modes_exact(const mlq_kl_desc* kd, void* ws, double* lambda_host, double* psi_dev, int32_t* rank_out,
+                          double* resid_out, hipStream_t s, std::string& err) {
+  const Box b = make_box(kd);
+  const Emb e = make_emb(b);
+  const int64_t n = b.nn;
+  const int M = kd->n_modes;
+  const int bc = exact_block(n, M);
+  const int chunk = exact_chunk(e, bc);
+  auto chk = [&](hipError_t x, const char* what) {
+    if (x != hipSuccess) {
+      err = std::string(what) + ": " + hipGetErrorString(x);
+      return false;
+    }
+    return true;
+  };
+  hipfftHandle pf = 0, pb = 0;
+  size_t wb = 0;
+  struct PlanGuard {
+    hipfftHandle* a;
+    hipfftHandle* b;
+    ~PlanGuard() {
+      if (*a) hipfftDestroy(*a);
+      if (*b) hipfftDestroy(*b);
+    }
+  } guard{&pf, &pb};
+  if (exact_plans(e, chunk, &pf, &pb, &wb) != HIPFFT_SUCCESS) {
+    err = "FFT plan creation failed";
+    return MLQ_EHIP;
+  }
+  ExactWork w = exact_carve(ws, n, bc, M, e, chunk, wb);
+  if (hipfftSetWorkArea(pf, w.fft_work) != HIPFFT_SUCCESS || hipfftSetWorkArea(pb, w.fft_work) != HIPFFT_SUCCESS ||
+      hipfftSetStream(pf, s) != HIPFFT_SUCCESS || hipfftSetStream(pb, s) != HIPFFT_SUCCESS) {
+    err = "FFT plan set-up failed";
+    return MLQ_EHIP;
+  }
+  const double s2 = kd->std_dev * kd->std_dev;
+  const int sq = kd->cov_kernel == MLQ_COV_SQEXP ? 1 : 0;
+  // eigenvalues of the circulant: the FFT of its first column (one column of the batch plan)
+  hipLaunchKernelGGL(k_circ_col, dim3((unsigned)cdiv(e.ne, kT)), dim3(kT), 0, s, e, b, s2, 1.0 / kd->corr_len, sq,
+                     w.E);
+  if (chunk > 1)
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)cdiv(e.ne * (chunk - 1), kT)), dim3(kT), 0, s, w.E + e.ne,
+                       e.ne * (chunk - 1), 0.0);
+  if (hipfftExecD2Z(pf, w.E, w.F) != HIPFFT_SUCCESS) {
+    err = "FFT failed";
+    return MLQ_EHIP;
+  }
+  if (!chk(hipMemcpyAsync(w.ch, w.F, sizeof(hipfftDoubleComplex) * e.nh, hipMemcpyDeviceToDevice, s), "copy")) return MLQ_EHIP;
+  const double inv_ne = 1.0 / (double)e.ne;
+  // Y[:, c] = C X[:, c] for every column
+  auto apply_c = [&](const double* X, double* Y) -> bool {
+    for (int c0 = 0; c0 < bc; c0 += chunk) {
+      const int nc = std::min(chunk, bc - c0);
+      hipLaunchKernelGGL(k_embed, dim3((unsigned)cdiv(e.ne, kT), nc), dim3(kT), 0, s, e, X, n, (int64_t)c0, w.E);
+      if (nc < chunk)
+        hipLaunchKernelGGL(k_fill, dim3((unsigned)cdiv(e.ne * (chunk - nc), kT)), dim3(kT), 0, s,
+                           w.E + (int64_t)nc * e.ne, e.ne * (chunk - nc), 0.0);
+      if (hipfftExecD2Z(pf, w.E, w.F) != HIPFFT_SUCCESS) return false;
+      hipLaunchKernelGGL(k_cmul, dim3((unsigned)cdiv(e.nh, kT), chunk), dim3(kT), 0, s, w.F, w.ch, e.nh);
+      if (hipfftExecZ2D(pb, w.F, w.E) != HIPFFT_SUCCESS) return false;
+      hipLaunchKernelGGL(k_extract, dim3((unsigned)cdiv(n, kT), nc), dim3(kT), 0, s, e, w.E, n, (int64_t)c0, inv_ne, Y);
+    }
+    return true;
+  };
+  const int nchunk = (int)cdiv(n, kGChunk);
+  // G = A^T B (bc x bc or the first cols columns), to the host
+  auto gram = [&](const double* A, const double* Bm, int cols, std::vector<double>& G) -> bool {
+    hipLaunchKernelGGL(k_gram, dim3((unsigned)cdiv(cols, kGT), (unsigned)cdiv(cols, kGT), nchunk), dim3(kGT * kGT), 0, s,
+                       A, Bm, n, cols, w.part);
+    hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)cdiv((int64_t)cols * cols, kT)), dim3(kT), 0, s, w.part, nchunk, cols,
+                       w.S);
+    G.resize((size_t)cols * cols);
+    if (!chk(hipMemcpyAsync(G.data(), w.S, sizeof(double) * cols * cols, hipMemcpyDeviceToHost, s), "copy")) return false;
+    if (!chk(hipStreamSynchronize(s), "sync")) return false;
+    for (int i = 0; i < cols; ++i)
+      for (int j = i + 1; j < cols; ++j) {
+        const double v = 0.5 * (G[(size_t)i * cols + j] + G[(size_t)j * cols + i]);
+        G[(size_t)i * cols + j] = G[(size_t)j * cols + i] = v;
+      }
+    return true;
+  };
+  auto combine = [&](const double* A, int R, const std::vector<double>& Zh, int C, double* out) -> bool {
+    if (!chk(hipMemcpyAsync(w.Z, Zh.data(), sizeof(double) * R * C, hipMemcpyHostToDevice, s), "copy")) return false;
+    hipLaunchKernelGGL(k_combine8, dim3((unsigned)cdiv(n, kT), (unsigned)cdiv(C, kCB)), dim3(kT), 0, s, A, n, R, w.Z,
+                       C, out);
+    return chk(hipStreamSynchronize(s), "sync");  // Zh is host memory of the caller's scope
+  };
+  auto mass = [&](const double* X, double* Y, int cols) {
+    hipLaunchKernelGGL(k_mass_cols, dim3((unsigned)cdiv(n, kT), cols), dim3(kT), 0, s, b, X, Y);
+  };
+  // start: seeded normals, M-orthonormalised
+  hipLaunchKernelGGL(k_randn, dim3((unsigned)cdiv(n * bc, kT)), dim3(kT), 0, s, w.Y, n * bc, (uint64_t)0x4B4C4558ull);
+  mass(w.Y, w.MY, bc);
+  std::vector<double> G, T, V, Uinv, Zh((size_t)bc * bc);
+  if (!gram(w.Y, w.MY, bc, G)) return MLQ_EHIP;
+  if (!chol_inv_upper(G, bc, Uinv)) {
+    err = "start block not of full rank";
+    return MLQ_EINVAL;
+  }
+  if (!combine(w.Y, bc, Uinv, bc, w.X) || !combine(w.MY, bc, Uinv, bc, w.MX)) return MLQ_EHIP;
+  std::vector<double> theta(bc), prev(M, 0.0);
+  double worst = 1.0;
+  const int max_it = 400;
+  for (int it = 0; it < max_it; ++it) {
+    if (!apply_c(w.MX, w.Y)) {
+      err = "FFT failed";
+      return MLQ_EHIP;
+    }
+    if (!gram(w.MX, w.Y, bc, T)) return MLQ_EHIP;  // Rayleigh quotient (M X)^T C (M X)
+    jacobi_eig(T, V, bc);
+    std::vector<int> order(bc);
+    for (int i = 0; i < bc; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return T[(size_t)x * bc + x] > T[(size_t)y * bc + y]; });
+    for (int k = 0; k < bc; ++k) theta[k] = T[(size_t)order[k] * bc + order[k]];
+    double change = 0.0;
+    for (int k = 0; k < M; ++k) change = std::max(change, std::fabs(theta[k] - prev[k]) / std::fabs(theta[k]));
+    for (int k = 0; k < M; ++k) prev[k] = theta[k];
+    // residuals of the wanted Ritz pairs, formed explicitly once the values have settled
+    if (change < 1e-12 || it == max_it - 1) {
+      std::vector<double> W1((size_t)bc * M), W2((size_t)bc * M);
+      for (int j = 0; j < bc; ++j)
+        for (int k = 0; k < M; ++k) {
+          W1[(size_t)j * M + k] = V[(size_t)j * bc + order[k]];
+          W2[(size_t)j * M + k] = V[(size_t)j * bc + order[k]] * theta[k];
+        }
+      if (!combine(w.Y, bc, W1, M, w.R1) || !combine(w.X, bc, W2, M, w.R2)) return MLQ_EHIP;
+      hipLaunchKernelGGL(k_axpy_cols, dim3((unsigned)cdiv(n * M, kT)), dim3(kT), 0, s, w.R1, w.R2, n * M);
+      mass(w.R1, w.R2, M);
+      std::vector<double> RR;
+      if (!gram(w.R1, w.R2, M, RR)) return MLQ_EHIP;
+      worst = 0.0;
+      for (int k = 0; k < M; ++k)
+        worst = std::max(worst, std::sqrt(std::max(RR[(size_t)k * M + k], 0.0)) / theta[k]);
+      if (worst <= kd->eps || it == max_it - 1) {
+        for (int k = 0; k < M; ++k) {
+          if (!(theta[k] > 0.0)) {
+            err = "non-positive KL eigenvalue among the requested modes";
+            return MLQ_EINVAL;
+          }
+          lambda_host[k] = theta[k];
+        }
+        // psi = X W (the Ritz vectors, M-orthonormal)
+        if (!combine(w.X, bc, W1, M, psi_dev)) return MLQ_EHIP;
+        hipLaunchKernelGGL(k_sign_fix, dim3(M), dim3(kT), 0, s, psi_dev, n);
+        if (!chk(hipGetLastError(), "launch") || !chk(hipStreamSynchronize(s), "sync")) return MLQ_EHIP;
+        if (rank_out) *rank_out = bc;
+        if (resid_out) *resid_out = worst;
+        if (worst > kd->eps) {
+          err = "subspace iteration did not reach the residual tolerance";
+          return MLQ_ENOCONV;
+        }
+        return MLQ_OK;
+      }
+    }
+    // next block: Y W Theta^-1 (Ritz-rotated and scaled, nearly M-orthonormal), then Cholesky
+    mass(w.Y, w.MY, bc);
+    if (!gram(w.Y, w.MY, bc, G)) return MLQ_EHIP;
+    std::vector<double> WT((size_t)bc * bc), G2((size_t)bc * bc, 0.0);
+    for (int j = 0; j < bc; ++j)
+      for (int k = 0; k < bc; ++k) WT[(size_t)j * bc + k] = V[(size_t)j * bc + order[k]] / theta[k];
+    // G2 = WT^T G WT
+    std::vector<double> GW((size_t)bc * bc, 0.0);
+    for (int i = 0; i < bc; ++i)
+      for (int j = 0; j < bc; ++j) {
+        const double g = G[(size_t)i * bc + j];
+        if (g == 0.0) continue;
+        for (int k = 0; k < bc; ++k) GW[(size_t)i * bc + k] += g * WT[(size_t)j * bc + k];
+      }
+    for (int i = 0; i < bc; ++i)
+      for (int j = 0; j < bc; ++j) {
+        const double wt = WT[(size_t)i * bc + j];
+        for (int k = 0; k < bc; ++k) G2[(size_t)j * bc + k] += wt * GW[(size_t)i * bc + k];
+      }
+    if (!chol_inv_upper(G2, bc, Uinv)) {
+      err = "subspace lost rank";
+      return MLQ_EINVAL;
+    }
+    for (int i = 0; i < bc; ++i)
+      for (int k = 0; k < bc; ++k) {
+        double v = 0.0;
+        for (int j = 0; j <= k; ++j) v += WT[(size_t)i * bc + j] * Uinv[(size_t)j * bc + k];
+        Zh[(size_t)i * bc + k] = v;
+      }
+    if (!combine(w.Y, bc, Zh, bc, w.X) || !combine(w.MY, bc, Zh, bc, w.MX)) return MLQ_EHIP;
+  }
+  err = "subspace iteration did not converge";
+  return MLQ_ENOCONV;
+}
 
 // The P1 mass matrix of a tetrahedral KL mesh (CSR on the host).
 std::string kl_tet_mass(const mlq_kl_desc* kd, TetHost& h, bool values) {
@@ -475,10 +909,15 @@ mlq_status kl_validate(const mlq_kl_desc* kd) {
   if (kd->max_rank < std::max(kd->n_modes, 1) || kd->max_rank > 4096 || kd->max_rank > n) return MLQ_EINVAL;
   if (!(kd->std_dev > 0.0) || !(kd->corr_len > 0.0) || !(kd->eps >= 0.0)) return MLQ_EINVAL;
   if (kd->cov_kernel != MLQ_COV_EXP && kd->cov_kernel != MLQ_COV_SQEXP) return MLQ_EINVAL;
+  if (kd->method != MLQ_KL_CHOLESKY && kd->method != MLQ_KL_EXACT) return MLQ_EINVAL;
+  if (kd->method == MLQ_KL_EXACT &&
+      (kd->mesh_kind != MLQ_MESH_Q1_BOX || kd->n_modes < 1 || !(kd->eps > 0.0) || 2 * (int64_t)kd->n_modes > n))
+    return MLQ_EINVAL;
   return MLQ_OK;
 }
 
 size_t kl_workspace_bytes(const mlq_kl_desc* kd) {
+  if (kd->method == MLQ_KL_EXACT) return exact_workspace_bytes(kd);
   const Box b = make_box(kd);
   if (kd->mesh_kind == MLQ_MESH_P1_TET) {
     TetHost h;
@@ -491,6 +930,7 @@ size_t kl_workspace_bytes(const mlq_kl_desc* kd) {
 // Returns MLQ_OK or MLQ_EHIP; error text in err.
 mlq_status kl_modes(const mlq_kl_desc* kd, void* ws, double* lambda_host, double* psi_dev, int32_t* rank_out,
                     double* resid_out, hipStream_t s, std::string& err) {
+  if (kd->method == MLQ_KL_EXACT) return kl_modes_exact(kd, ws, lambda_host, psi_dev, rank_out, resid_out, s, err);
   Box b = make_box(kd);
   const int64_t n = b.nn;
   const int Rmax = kd->max_rank, M = kd->n_modes;

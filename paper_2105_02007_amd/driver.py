@@ -26,7 +26,8 @@ class ConfigRunner:
     """Levels of one workload with their KL bases (Section 2.3) on one device."""
 
     def __init__(self, cfg: dict, prec: int | None = None, device="cuda", newton_tol=None, inner_tol=None,
-                 max_inner=30, kl_rank_factor=2, kl_eps=1e-2, log=None, concurrent=True,
+                 max_inner=30, kl_rank_factor=2, kl_eps=1e-2, kl_method=None, kl_tol=1e-8, log=None,
+                 concurrent=True,
                  newton_guess=mlq.MLQ_GUESS_EXTRAPOLATE, tune_layout=True, tune_launch=True, steps_per_block=0,
                  block_guess=mlq.MLQ_GUESS_PREVIOUS):
         say = log if log is not None else (lambda m: None)
@@ -47,12 +48,19 @@ class ConfigRunner:
         self.iso = cfg.get("model") == "iso"
         # the KL standard deviation is relative to sigma_l (vector model) or E[V] (isotropic)
         std = kcfg["std"] * (self.phys["sigma_l"] if self.vector else kcfg["mean"] if self.iso else 1.0)
-        def make_kd(m, max_rank):
+        # the KL route: "cholesky" (pivoted Cholesky, eq. (redEig)) or "exact" (the top M
+        # eigenpairs of eq. (algEig) to the relative residual kl_tol; Q1 boxes only)
+        method = kl_method if kl_method is not None else kcfg.get("method", "cholesky")
+        if method not in ("cholesky", "exact") or (method == "exact" and self.tet):
+            raise ValueError(f"KL method {method!r} is not available for this workload")
+        def make_kd(m, max_rank, route="cholesky"):
             if self.tet:
                 return mlq.kl_desc_tet(self.meshes[kcfg["grid_level"]], std, kcfg["corr_len"], m,
                                        max_rank=max_rank, eps=kl_eps, cov_kernel=cov)
+            exact = route == "exact"
             return mlq.kl_desc(cfg["dim"], kl_level["n"], kl_level["lo"], kl_level["hi"], std,
-                               kcfg["corr_len"], m, max_rank=max_rank, eps=kl_eps, cov_kernel=cov)
+                               kcfg["corr_len"], m, max_rank=max_rank, eps=kl_tol if exact else kl_eps,
+                               cov_kernel=cov, method=mlq.MLQ_KL_EXACT if exact else mlq.MLQ_KL_CHOLESKY)
         if self.tet:
             # tetrahedral levels: the seeded shells of the workload (non-nested), the KL on
             # the vertices of the finest one, the transfer by point location
@@ -72,8 +80,11 @@ class ConfigRunner:
         if self.steps_per_block > 0:
             max_inner = min(64, max_inner + self.steps_per_block)
             tune_launch = False
-        self.kd = make_kd(M, kl_rank_factor * M)
-        say("KL set-up")
+        self.kl_method = method
+        self.kd = make_kd(M, kl_rank_factor * M, method)
+        say(f"KL set-up ({method})")
+        # kl_resid: the trace residual of the Cholesky factor, or the largest relative
+        # eigen-residual of the exact modes
         lam, psi, self.kl_rank, self.kl_resid = mlq.kl_modes(self.kd, device=device)
         say(f"KL modes done (rank {self.kl_rank})")
         self.lam = lam

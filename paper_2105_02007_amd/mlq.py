@@ -37,6 +37,7 @@ MLQ_GUESS_PREVIOUS, MLQ_GUESS_EXTRAPOLATE, MLQ_GUESS_REFERENCE, MLQ_GUESS_REFERE
 MLQ_DIFF_FIBRE, MLQ_DIFF_ISO, MLQ_DIFF_VECTOR = 0, 1, 2
 MLQ_COV_EXP, MLQ_COV_SQEXP = 0, 1
 MLQ_MAP_NORMAL, MLQ_MAP_UNIFORM = 0, 1
+MLQ_KL_CHOLESKY, MLQ_KL_EXACT = 0, 1
 KERNEL_CLASSES = ["apply", "residual", "rhs", "precond", "dots", "orth", "small", "update", "qoi"]
 
 
@@ -76,7 +77,7 @@ class KlDesc(C.Structure):
         ("n_modes", C.c_int32), ("max_rank", C.c_int32), ("eps", C.c_double),
         ("mesh_kind", C.c_int32), ("n_vert", C.c_int64), ("n_tet", C.c_int64),
         ("xyz", C.POINTER(C.c_double)), ("tets", C.POINTER(C.c_int32)),
-        ("cov_kernel", C.c_int32),
+        ("cov_kernel", C.c_int32), ("method", C.c_int32),
     ]
 
 
@@ -591,9 +592,13 @@ def estimate(kind, f_fine, f_coarse=None, n_per_level=None, n_shifts=1):
                 level_var=list(out.level_var[:L]))
 
 
-def kl_desc(dim, n, lo, hi, std_dev, corr_len, n_modes, max_rank=None, eps=1e-2, cov_kernel=MLQ_COV_EXP):
+def kl_desc(dim, n, lo, hi, std_dev, corr_len, n_modes, max_rank=None, eps=1e-2, cov_kernel=MLQ_COV_EXP,
+            method=MLQ_KL_CHOLESKY):
+    """KL descriptor on a Q1 box; method MLQ_KL_EXACT: the exact top eigenpairs to the relative
+    residual eps (subspace iteration), else the pivoted Cholesky route (eps: trace criterion)."""
     d = KlDesc()
     d.cov_kernel = int(cov_kernel)
+    d.method = int(method)
     d.dim = int(dim)
     for a in range(3):
         d.n[a] = int(n[a]) if a < dim else 1

@@ -135,7 +135,7 @@ def test_mlmc_field_estimate_matches_oracle(env):
     M = cfg["kl"]["n_modes"]
     meshes = run.level_meshes(cfg)
     factor = meshes[-1].n_nodes // M
-    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0)
+    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0, kl_method="cholesky")
     Ys = [W.mc_uniforms(cfg["seed"], l, n, M) for l, n in enumerate(cfg["sampling"]["n_per_level"])]
     pts = np.array([[0.05, 0.05, 0.05], [0.5, 0.4, 0.65]])
     res = runner.run_mlmc_fields([torch.as_tensor(Y, device="cuda") for Y in Ys], probes=pts)

@@ -60,7 +60,7 @@ def test_c4i_pipeline_small_matches_oracle(env):
     M, S = cfg["kl"]["n_modes"], 3
     meshes = run.level_meshes(cfg)
     factor = meshes[-1].n_nodes // M
-    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0)
+    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0, kl_method="cholesky")
     shifts = [W.lattice_shifts(cfg["seed"], l, S, M) for l in range(2)]
     res = runner.run_mlqmc(shifts)
     B = run.kl_basis(cfg, meshes, max_rank=factor * M, eps=0.0)

@@ -78,7 +78,7 @@ def c4_oracle():
 def _run_c4(env, cfg, shifts, prec):
     from paper_2105_02007_amd.driver import ConfigRunner
     n = int(np.prod(NODES[-1]))
-    runner = ConfigRunner(cfg, prec=prec, kl_rank_factor=n // M, kl_eps=0.0, tune_layout=False)
+    runner = ConfigRunner(cfg, prec=prec, kl_rank_factor=n // M, kl_eps=0.0, kl_method="cholesky", tune_layout=False)
     assert runner.levels[-1].desc.n[0] >= 48
     return runner.run_mlqmc(shifts)
 
@@ -126,7 +126,7 @@ def test_c2_mlmc_fp64_matches_oracle(env):
     B = _oracle_basis(cfg)
     Ys = [W.mc_normals(cfg["seed"], l, N, M) for l, N in enumerate(cfg["sampling"]["n_per_level"])]
     n = int(np.prod(NODES[-1]))
-    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=n // M, kl_eps=0.0, tune_layout=False)
+    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=n // M, kl_eps=0.0, kl_method="cholesky", tune_layout=False)
     res = runner.run_mlmc([torch.as_tensor(Y, device="cuda") for Y in Ys])
     ff = [_oracle_qois(cfg, B, l, Ys[l]) for l in range(3)]
     fc = [None] + [_oracle_qois(cfg, B, l - 1, Ys[l]) for l in (1, 2)]

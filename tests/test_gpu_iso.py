@@ -128,7 +128,7 @@ def test_c2i_pipeline_small_matches_oracle(env):
     M = cfg["kl"]["n_modes"]
     meshes = run.level_meshes(cfg)
     factor = meshes[-1].n_nodes // M  # near-full-rank Cholesky on both sides, same rank
-    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0)
+    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0, kl_method="cholesky")
     Ys = [W.mc_uniforms(cfg["seed"], l, n, M) for l, n in enumerate(cfg["sampling"]["n_per_level"])]
     res = runner.run_mlmc([torch.as_tensor(Y, device="cuda") for Y in Ys])
     B = run.kl_basis(cfg, meshes, max_rank=factor * M, eps=0.0)

@@ -162,7 +162,7 @@ def test_c5_pipeline_small_matches_oracle(env):
     M = cfg["kl"]["n_modes"]
     n_kl = (cfg["levels"][-1]["cells"][0] + 1) * (cfg["levels"][-1]["cells"][1] + 1) * cfg["levels"][-1]["cells"][2]
     factor = n_kl // M  # near-full-rank Cholesky on both sides, same rank
-    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0)
+    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0, kl_method="cholesky")
     Y = W.mc_normals(cfg["seed"], 0, 5, M)
     res = runner.run_combination(torch.as_tensor(Y, device="cuda"))
     # oracle pipeline
@@ -273,7 +273,7 @@ def test_c5v_pipeline_small_matches_oracle(env):
     M = cfg["kl"]["n_modes"]
     n_kl = (cfg["levels"][-1]["cells"][0] + 1) * (cfg["levels"][-1]["cells"][1] + 1) * cfg["levels"][-1]["cells"][2]
     factor = n_kl // M
-    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0)
+    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0, kl_method="cholesky")
     Y = W.mc_uniforms(cfg["seed"], 0, 4, 3 * M)
     res = runner.run_combination(torch.as_tensor(Y, device="cuda"))
     ph = cfg["physics"]
@@ -344,7 +344,7 @@ def test_c5_field_combination_small_matches_oracle(env):
     meshes = [W.tet_mesh(lv) for lv in cfg["levels"]]
     n_kl = meshes[-1]["xyz"].shape[0]
     factor = n_kl // M
-    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0)
+    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0, kl_method="cholesky")
     Y = W.mc_normals(cfg["seed"], 0, 5, M)
     pts = 0.5 * (meshes[-1]["xyz"][[3, 40]] + meshes[-1]["xyz"][[4, 41]])  # midpoints of two vertex pairs
     res = runner.run_combination_fields(torch.as_tensor(Y, device="cuda"), probes=pts)
@@ -403,7 +403,7 @@ def test_c5i_pipeline_small_matches_oracle(env):
     M = cfg["kl"]["n_modes"]
     n_kl = (cfg["levels"][-1]["cells"][0] + 1) * (cfg["levels"][-1]["cells"][1] + 1) * cfg["levels"][-1]["cells"][2]
     factor = n_kl // M
-    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0)
+    runner = ConfigRunner(cfg, prec=W.PREC_FP64, kl_rank_factor=factor, kl_eps=0.0, kl_method="cholesky")
     Y = W.mc_uniforms(cfg["seed"], 0, 4, M)
     res = runner.run_combination(torch.as_tensor(Y, device="cuda"))
     ph = cfg["physics"]

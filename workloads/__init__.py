@@ -80,25 +80,25 @@ CONFIGS = {
     "c1": dict(
         name="c1", title="plain FP64 MC, 2D unit square, Q1 33x33, 64 steps, 16 samples",
         dim=2, levels=_box_levels(2, [33], [64]),
-        kl=dict(n_modes=16, corr_len=0.2, std=0.3, grid_level=0),
+        kl=dict(n_modes=16, corr_len=0.2, std=0.3, grid_level=0, method="exact"),
         sampling=dict(kind="mc", n_per_level=[16]),
         qoi=QOI_MEAN_U_FINAL, prec=PREC_FP64, seed=1),
     "c2": dict(
         name="c2", title="FP64 batched MLMC, 3D cube, Q1 9^3..65^3, 32..256 steps",
         dim=3, levels=_box_levels(3, [9, 17, 33, 65], [32, 64, 128, 256]),
-        kl=dict(n_modes=64, corr_len=0.1, std=0.3, grid_level=3),
+        kl=dict(n_modes=64, corr_len=0.1, std=0.3, grid_level=3, method="exact"),
         sampling=dict(kind="mlmc", n_per_level=[2048, 512, 128, 32]),
         qoi=QOI_MEAN_ACT_TIME, prec=PREC_FP64, seed=2),
     "c3": dict(
         name="c3", title="mixed single level, 3D cube, Q1 129^3, 512 steps, 64 lattice points",
         dim=3, levels=_box_levels(3, [129], [512]),
-        kl=dict(n_modes=128, corr_len=0.1, std=0.3, grid_level=0),
+        kl=dict(n_modes=128, corr_len=0.1, std=0.3, grid_level=0, method="exact"),
         sampling=dict(kind="qmc", n_per_level=[64], n_shifts=1),
         qoi=QOI_MEAN_ACT_TIME, prec=PREC_MIXED, seed=3),
     "c4": dict(
         name="c4", title="batched uneven MLQMC, 3D cube, Q1 9^3..129^3, 32..512 steps, 16 shifts",
         dim=3, levels=_box_levels(3, [9, 17, 33, 65, 129], [32, 64, 128, 256, 512]),
-        kl=dict(n_modes=128, corr_len=0.1, std=0.3, grid_level=4),
+        kl=dict(n_modes=128, corr_len=0.1, std=0.3, grid_level=4, method="exact"),
         sampling=dict(kind="mlqmc", n_per_level=[256, 64, 16, 4, 1], n_shifts=16),
         qoi=QOI_MEAN_ACT_TIME, prec=PREC_MIXED, seed=4),
     # combination form eq. (PimpedML): Q_0, Q_1, Q_2 with 16, 64, 256 nested Monte Carlo
