@@ -276,6 +276,20 @@ mlq_status mlq_set_lane_layout(mlq_level* level, int32_t lanes_x);
  * values. */
 mlq_status mlq_set_gmres_block(mlq_level* level, int32_t iterations);
 
+/* Persistent per-sample solves of a small 3D box level (a launch knob for the latency-bound
+ * coarse levels of a multilevel estimator; Section 3.3's time stepping with Newton-GMRES, the
+ * same method and stopping tests as the batched path).  on = 1: mlq_solve_batch and
+ * mlq_solve_batch_ex run each sample's whole time loop inside one workgroup of a single
+ * launch (workgroups walk the batch), with no host round trip: the call only enqueues work on
+ * the stream and returns MLQ_OK; per-sample failures are reported in status_dev (check with
+ * mlq_check after synchronising), and the iteration counts in iters_dev.  Applies when the
+ * level's nodal vector fits 64 KiB (n_nodes x 8 bytes in FP64, x 4 in mixed precision) and the
+ * call asks for no field outputs and no reference Newton guess; other calls keep the batched
+ * path.  Results agree with the batched path within the stopping tests (a different summation
+ * order).  on = 0: the batched path (default).  MLQ_EINVAL for a tetrahedral, 2D or too large
+ * level when on = 1. */
+mlq_status mlq_set_persistent(mlq_level* level, int32_t on);
+
 /* Reference space-time solution for the Newton guesses MLQ_GUESS_REFERENCE(_LOCAL): ref_dev
  * is (n_steps + 1) x n FP64 on the device, e.g. the u_sum of a one-sample solve of the
  * unperturbed field; the level keeps the pointer (the caller keeps the memory alive while it
@@ -526,7 +540,8 @@ enum {
   MLQ_K_SMALL = 6,    /* per-sample scalar kernels (checks, Givens, counts) */
   MLQ_K_UPDATE = 7,   /* Newton update */
   MLQ_K_QOI = 8,      /* activation tracking and QoI reductions */
-  MLQ_K_CLASSES = 9
+  MLQ_K_PERSISTENT = 9, /* persistent per-sample solves (mlq_set_persistent): the whole launch */
+  MLQ_K_CLASSES = 10
 };
 
 typedef struct {

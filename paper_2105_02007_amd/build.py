@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmlq.so")
-SOURCES = ["mlq_kernels.hip", "mlq_stencil3.hip", "mlq_kl.hip", "mlq_tet.hip", "mlq_fields.hip", "mlq_tetmesh.cpp",
+SOURCES = ["mlq_kernels.hip", "mlq_stencil3.hip", "mlq_kl.hip", "mlq_tet.hip", "mlq_fields.hip", "mlq_small.hip", "mlq_tetmesh.cpp",
            "mlq_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -98,6 +98,8 @@ struct mlq_level {
   std::vector<hipEvent_t> free_events;
   // GMRES iterations per captured graph (0: launched and steered one iteration at a time)
   int gmres_block = 0;
+  // persistent per-sample solves (small 3D box levels, mlq_set_persistent)
+  bool persistent = false;
   struct BlockGraph {
     const void* ws;
     const void* theta;
@@ -779,6 +781,41 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
     launch_coefs(theta_dev, w.coef, level->P, batch,
                  d.diffusion == MLQ_DIFF_ISO ? d.sigma_t : 0.5 * (d.sigma_l - d.sigma_t), d.diffusion == MLQ_DIFF_ISO,
                  mixed, s);
+  const bool ref_guess0 = (d.newton_guess == MLQ_GUESS_REFERENCE || d.newton_guess == MLQ_GUESS_REFERENCE_LOCAL) &&
+                          level->ref != nullptr;
+  if (level->persistent && small_solver_fits(g, mixed) && u_sum == nullptr && act_sum == nullptr && tab.n == 0 &&
+      !ref_guess0) {
+    // one launch: every sample's time loop in a workgroup of its own; enqueue only
+    SmallArgs sa{};
+    sa.g = g;
+    sa.io = level->io;
+    sa.B = batch;
+    sa.n_steps = n_steps;
+    sa.kmax = kmax;
+    sa.max_newton = d.max_newton;
+    sa.extrap = d.newton_guess == MLQ_GUESS_EXTRAPOLATE ? 1 : 0;
+    sa.qoi = d.qoi;
+    sa.newton_tol = d.newton_tol;
+    sa.inner_tol = d.inner_tol;
+    sa.t_on = d.stim_t_on;
+    sa.t_off = d.stim_t_off;
+    sa.amp = d.stim_amp;
+    sa.fbox = level->fbox;
+    sa.wts = level->wts;
+    sa.vol = level->vol;
+    sa.tri = level->tri;
+    sa.nmax = level->nmax;
+    sa.w = w;
+    sa.qoi_out = qoi_dev;
+    sa.status_out = status_dev;
+    sa.iters_out = iters_dev;
+    sa.u_out = u_out_dev;
+    sa.act_out = act_out_dev;
+    hipError_t e = hipSuccess;
+    timed(level, MLQ_K_PERSISTENT, (double)level->nn * batch * n_steps, s, [&] { e = launch_solve_small(sa, mixed, s); });
+    if (e != hipSuccess) return fail(MLQ_EHIP, "persistent solve launch failed: %s", hipGetErrorString(e));
+    return MLQ_OK;
+  }
   launch_init(w, level->nn, batch, d.u_th, s);
   HIP_OK(hipGetLastError());
   // field outputs of time level k (the state u_k sits in w.uk)
@@ -1166,6 +1203,16 @@ mlq_status mlq_set_gmres_block(mlq_level* level, int32_t iterations) {
   if (iterations < 0 || iterations > kMaxInner) return fail(MLQ_EINVAL, "block of %d iterations", iterations);
   if (iterations != level->gmres_block) drop_graphs(level);
   level->gmres_block = iterations;
+  return MLQ_OK;
+}
+
+mlq_status mlq_set_persistent(mlq_level* level, int32_t on) {
+  if (level == nullptr) return fail(MLQ_EINVAL, "level is NULL");
+  if (on != 0 && on != 1) return fail(MLQ_EINVAL, "on must be 0 or 1");
+  if (on && !small_solver_fits(level->geo, level->mixed))
+    return fail(MLQ_EINVAL, "persistent solves need a 3D box level of at most %zu bytes per vector",
+                (size_t)kSmallMaxLds);
+  level->persistent = on != 0;
   return MLQ_OK;
 }
 

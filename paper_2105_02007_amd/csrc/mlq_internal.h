@@ -267,6 +267,32 @@ void launch_block_close(double* U, int G, int64_t nn, int32_t B, double* act, do
 void launch_coupling3(const Geo& g, const void* x, void* wv, const void* coef_or_theta, double ck, int32_t Bv,
                       const int32_t* active, bool mixed, hipStream_t s);
 
+// Persistent per-sample solver of small 3D box levels (mlq_small.hip): one workgroup runs the
+// whole time loop (Newton, GMRES, preconditioner, activation, QoI) of one sample at a time,
+// the same method as the batched path.  The level's vector must fit kSmallMaxLds bytes of LDS.
+constexpr int kSmallThreads = 256;
+constexpr size_t kSmallMaxLds = 65536;
+struct SmallArgs {
+  Geo g;
+  Ionic io;
+  int32_t B, n_steps, kmax, max_newton, extrap, qoi;
+  double newton_tol, inner_tol;
+  double t_on, t_off, amp;  // stimulus rate amp on [t_on, t_off)
+  const double* fbox;       // stimulus load vector
+  const double* wts;        // node weights (M 1)
+  double vol;
+  const void* tri;          // 1 / pivots per axis, [3][nmax], inner precision
+  int32_t nmax;
+  Work w;                   // the batched workspace; w.coef holds the element coefficient pairs
+  double* qoi_out;
+  int32_t* status_out;
+  int64_t* iters_out;
+  double* u_out;            // final states and activation times (may be NULL)
+  double* act_out;
+};
+bool small_solver_fits(const Geo& g, bool mixed);
+hipError_t launch_solve_small(const SmallArgs& a, bool mixed, hipStream_t s);
+
 // P1 tetrahedra (mlq_tet.hip).  kval: per-sample stiffness values [B][nell] (slot-major
 // padded pattern of TetDev), inner precision.
 void launch_tet_assemble(const TetDev& t, const void* theta, void* kval, int32_t B, double sigma_t, double dsig,

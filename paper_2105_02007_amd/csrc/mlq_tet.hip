@@ -22,14 +22,16 @@ namespace {
 
 // XCD-aware block numbering: workgroups go to the 8 XCDs round-robin by linear id.  Give each
 // XCD one contiguous range of (row block, sample group) blocks, so that the column gathers of
-// neighbouring row blocks meet in one L2.  (bx, by) replace (blockIdx.x, blockIdx.y).
+// neighbouring row blocks meet in one L2.  Within the range the sample groups of a row block
+// are consecutive, so the shared pattern (columns, mass) of that block is fetched from HBM once
+// and read from L2 by the other groups.  (bx, by) replace (blockIdx.x, blockIdx.y).
 __device__ inline void xcd_block(int64_t& bx, int64_t& by) {
   const int64_t NB = (int64_t)gridDim.x * gridDim.y;
   const int64_t L = (int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
   const int64_t q = NB >> 3, r = NB & 7, x = L & 7;
   const int64_t W = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + (L >> 3);
-  bx = W % gridDim.x;
-  by = W / gridDim.x;
+  by = W % gridDim.y;
+  bx = W / gridDim.y;
 }
 
 __device__ inline double tet_iion(double u, const Ionic& io) {

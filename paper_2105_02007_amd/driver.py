@@ -98,10 +98,11 @@ class ConfigRunner:
                 # level j is evaluated on the points of Q_{L-j}
                 nb = samp["n_per_level"][top - l]
             else:
-                # the largest batch a level sees: its own samples and, as the coarse side, level l+1's
+                # the batch a level sees: its own samples and, as the coarse side, level l+1's,
+                # solved together (solve_all merges the jobs of one level)
                 nb = samp["n_per_level"][l] * n_shifts
                 if l + 1 < len(cfg["levels"]):
-                    nb = max(nb, samp["n_per_level"][l + 1] * n_shifts)
+                    nb += samp["n_per_level"][l + 1] * n_shifts
             theta0 = v_mean = None
             if self.tet:
                 mesh = self.meshes[l]
@@ -235,18 +236,34 @@ class ConfigRunner:
         depend on the schedule: every solve is independent and the estimators sum on the
         host in sample order."""
         levels = sorted({job[0] for job in jobs}, reverse=True)
-        if not self.concurrent or len(levels) < 3:
-            return [self.solve(*job) for job in jobs]
-        main = torch.cuda.current_stream()
         out = [None] * len(jobs)
+
+        def run_level(l):
+            # the jobs of one level without field outputs (a level's own samples and its finer
+            # neighbour's coarse side) form one batch: one solve per grid, with fuller launches
+            plain = [i for i, job in enumerate(jobs) if job[0] == l and len(job) == 2]
+            if len(plain) > 1:
+                q = self.solve(l, torch.cat([jobs[i][1] for i in plain], dim=1))
+                k = 0
+                for i in plain:
+                    n = jobs[i][1].shape[1]
+                    out[i] = q[k:k + n]
+                    k += n
+            for i, job in enumerate(jobs):
+                if job[0] == l and out[i] is None:
+                    out[i] = self.solve(*job)
+
+        if not self.concurrent or len(levels) < 3:
+            for l in levels:
+                run_level(l)
+            return out
+        main = torch.cuda.current_stream()
 
         def work(l):
             s = self.streams[l]
             s.wait_stream(main)  # the inputs were written on the caller's stream
             with torch.cuda.stream(s):
-                for i, job in enumerate(jobs):
-                    if job[0] == l:
-                        out[i] = self.solve(*job)
+                run_level(l)
                 s.synchronize()
 
         work(levels[0])

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmlq.so")
 MLQ_OK, MLQ_EINVAL, MLQ_EHIP, MLQ_ENOCONV, MLQ_ESIZE, MLQ_ESTATE = 0, -1, -2, -3, -4, -5
 MLQ_FP64, MLQ_MIXED = 0, 1
 MLQ_QOI_MEAN_U_FINAL, MLQ_QOI_MEAN_ACT_TIME = 0, 1
+MLQ_SAMPLE_OK, MLQ_SAMPLE_NOCONV, MLQ_SAMPLE_NAN = 0, 1, 2
 MLQ_EST_MC, MLQ_EST_MLMC, MLQ_EST_MLQMC, MLQ_EST_COMBINATION = 0, 1, 2, 3
 MLQ_MESH_Q1_BOX, MLQ_MESH_P1_TET = 0, 1
 
@@ -29,7 +30,7 @@ EXPORTED = [
     "mlq_kl_transfer_tet_bytes", "mlq_kl_transfer_tet", "mlq_solve_batch_fields", "mlq_probe_weights",
     "mlq_transfer_add", "mlq_field_norm2", "mlq_set_reference", "mlq_tet_locate", "mlq_transfer_add_weighted",
     "mlq_set_lane_layout", "mlq_lattice_points", "mlq_solve_batch_static",
-    "mlq_kl_weights", "mlq_lattice_weights", "mlq_fibre_field", "mlq_set_gmres_block",
+    "mlq_kl_weights", "mlq_lattice_weights", "mlq_fibre_field", "mlq_set_gmres_block", "mlq_set_persistent",
     "mlq_workspace_bytes_blocks", "mlq_solve_batch_blocks",
 ]
 STATIC_WS_BYTES = 64 << 20
@@ -38,7 +39,7 @@ MLQ_DIFF_FIBRE, MLQ_DIFF_ISO, MLQ_DIFF_VECTOR = 0, 1, 2
 MLQ_COV_EXP, MLQ_COV_SQEXP = 0, 1
 MLQ_MAP_NORMAL, MLQ_MAP_UNIFORM = 0, 1
 MLQ_KL_CHOLESKY, MLQ_KL_EXACT = 0, 1
-KERNEL_CLASSES = ["apply", "residual", "rhs", "precond", "dots", "orth", "small", "update", "qoi"]
+KERNEL_CLASSES = ["apply", "residual", "rhs", "precond", "dots", "orth", "small", "update", "qoi", "persistent"]
 
 
 class MlqError(RuntimeError):
@@ -117,6 +118,7 @@ def _load():
         "mlq_set_reference": [VP, VP],
         "mlq_set_lane_layout": [VP, I32],
         "mlq_set_gmres_block": [VP, I32],
+        "mlq_set_persistent": [VP, I32],
         "mlq_workspace_bytes_blocks": [VP, I32, I32, C.POINTER(C.c_size_t)],
         "mlq_solve_batch_blocks": [VP, VP, I32, I32, I32, VP, C.c_size_t, VP, VP, VP, VP, VP],
         "mlq_lattice_points": [VP, VP, I32, I64, I64, I32, I32, VP, VP],
@@ -154,6 +156,13 @@ def check(code):
     if code != MLQ_OK:
         raise MlqError(code, lib.mlq_last_error().decode())
     return code
+
+
+def check_status(status):
+    """mlq_check on host per-sample status words: MLQ_OK, or MLQ_ENOCONV if any sample failed."""
+    import numpy as np
+    st = np.ascontiguousarray(np.asarray(status, dtype=np.int32))
+    return lib.mlq_check(st.ctypes.data_as(C.c_void_p), int(st.size))
 
 
 def _ptr(t):
@@ -390,6 +399,12 @@ class Level:
         """GMRES iterations per captured graph (0: one launch sequence and host read per iteration)."""
         check(lib.mlq_set_gmres_block(self.handle, int(iterations)))
         self.gmres_block = int(iterations)
+
+    def set_persistent(self, on):
+        """Persistent per-sample solves (small 3D box levels): one launch per solve, enqueue only;
+        failures then show in the returned status, not in the return code."""
+        check(lib.mlq_set_persistent(self.handle, 1 if on else 0))
+        self.persistent = bool(on)
 
     def tune_lane_layout(self, batch=None, reps=5, margin=0.05):
         """Times the operator apply of this level at `batch` samples (default: the level's
