@@ -394,16 +394,11 @@ void launch_dots(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipS
 // npart projection partials (of k_dots, or of the apply kernel that fused them;
 // one wave per coefficient, fixed order):
 // h_ij = inv_eta_i sum_blk part, hc_i = h_ij inv_eta_i; block 0 stores column j of H.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_orth(int64_t nn, const T* __restrict__ w, T* __restrict__ V, size_t vs,
-                                                 int j, int kmax, const double* __restrict__ dpart,
-                                                 const double* __restrict__ inv_eta, double* __restrict__ H,
-                                                 double* __restrict__ part, const int32_t* __restrict__ active,
-                                                 int npart) {
-  const int sb = blockIdx.y;
-  if (active[sb] == 0) return;
-  __shared__ double sh[kBlock / 64];
-  __shared__ double c[kMaxInner + 1];
+// The projection coefficients of step j from the npart partials per sample (one wave per
+// coefficient, fixed order): h_ij = inv_eta_i sum_blk part, hc_i = h_ij inv_eta_i, column j of H.
+__device__ inline void sum_projections(int sb, int j, int kmax, int npart, const double* __restrict__ dpart,
+                                       const double* __restrict__ inv_eta, double* __restrict__ H, double* c,
+                                       bool store_h) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int i = wid; i <= j; i += kBlock / 64) {
     const double* pi = dpart + ((int64_t)sb * (kmax + 1) + i) * npart;
@@ -414,21 +409,72 @@ __global__ __launch_bounds__(kBlock) void k_orth(int64_t nn, const T* __restrict
       const double ie = inv_eta[(int64_t)sb * (kmax + 1) + i];
       const double h = a * ie;
       c[i] = h * ie;
-      if (blockIdx.x == 0) H[((int64_t)sb * (kmax + 1) + i) * kmax + j] = h;
+      if (store_h) H[((int64_t)sb * (kmax + 1) + i) * kmax + j] = h;
     }
+  }
+}
+
+// Projection coefficients once per sample (into hc), for launches whose orthogonalisation blocks
+// would otherwise each re-read every partial.
+__global__ __launch_bounds__(kBlock) void k_hsum(int j, int kmax, int npart, const double* __restrict__ dpart,
+                                                 const double* __restrict__ inv_eta, double* __restrict__ H,
+                                                 double* __restrict__ hc, const int32_t* __restrict__ active) {
+  const int sb = blockIdx.x;
+  if (active[sb] == 0) return;
+  sum_projections(sb, j, kmax, npart, dpart, inv_eta, H, hc + (int64_t)sb * (kmax + 1), true);
+}
+
+// npart > 0: the coefficients from the partials (each block); npart == 0: from hc (k_hsum).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_orth(int64_t nn, const T* __restrict__ w, T* __restrict__ V, size_t vs,
+                                                 int j, int kmax, const double* __restrict__ dpart,
+                                                 const double* __restrict__ inv_eta, double* __restrict__ H,
+                                                 double* __restrict__ part, const int32_t* __restrict__ active,
+                                                 int npart, const double* __restrict__ hc) {
+  const int sb = blockIdx.y;
+  if (active[sb] == 0) return;
+  __shared__ double sh[kBlock / 64];
+  __shared__ double c[kMaxInner + 1];
+  if (npart > 0) {
+    sum_projections(sb, j, kmax, npart, dpart, inv_eta, H, c, blockIdx.x == 0);
+  } else {
+    for (int i = threadIdx.x; i <= j; i += kBlock) c[i] = hc[(int64_t)sb * (kmax + 1) + i];
   }
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kRedChunk;
   const int64_t end = base + kRedChunk < nn ? base + kRedChunk : nn;
   const T* ws = w + (int64_t)sb * nn;
   T* vn = V + (size_t)(j + 1) * vs + (int64_t)sb * nn;
+  // a thread's kRedChunk / kBlock nodes side by side, so that the loads of one basis vector at
+  // all of them are in flight together (the same operations per node, in the same order)
+  constexpr int NPT = kRedChunk / kBlock;
+  double v[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const int64_t t = base + threadIdx.x + (int64_t)q * kBlock;
+    v[q] = t < end ? (double)ws[t] : 0.0;
+  }
+  for (int i = 0; i <= j; ++i) {
+    const double ci = c[i];
+    const T* vi = V + i * vs + (int64_t)sb * nn;
+    T x[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int64_t t = base + threadIdx.x + (int64_t)q * kBlock;
+      x[q] = t < end ? vi[t] : (T)0;
+    }
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) v[q] -= ci * (double)x[q];
+  }
   double acc = 0.0;
-  for (int64_t t = base + threadIdx.x; t < end; t += kBlock) {
-    double v = (double)ws[t];
-    for (int i = 0; i <= j; ++i) v -= c[i] * (double)V[i * vs + (int64_t)sb * nn + t];
-    const T vt = (T)v;
-    vn[t] = vt;
-    acc += (double)vt * (double)vt;
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const int64_t t = base + threadIdx.x + (int64_t)q * kBlock;
+    if (t < end) {
+      const T vt = (T)v[q];
+      vn[t] = vt;
+      acc += (double)vt * (double)vt;
+    }
   }
   acc = block_sum<kBlock>(acc, sh);
   if (threadIdx.x == 0) part[(int64_t)sb * gridDim.x + blockIdx.x] = acc;
@@ -437,12 +483,20 @@ __global__ __launch_bounds__(kBlock) void k_orth(int64_t nn, const T* __restrict
 void launch_orth(const Geo& g, const Work& w, int j, int32_t B, bool mixed, hipStream_t s, int32_t npart) {
   const dim3 grid((unsigned)w.nred, B);
   const size_t vs = (size_t)g.nn * B;
+  // Many blocks per sample, each re-reading (j + 1) x npart partials: sum them once per sample
+  // first (the same sums in the same order).
+  int np = npart;
+  if ((int64_t)w.nred * npart > kHsumMinReads) {
+    hipLaunchKernelGGL(k_hsum, dim3(B), dim3(kBlock), 0, s, j, w.kmax, (int)npart, w.dpart, w.inv_eta, w.H, w.hc,
+                       w.inner_active);
+    np = 0;
+  }
   if (mixed)
     hipLaunchKernelGGL((k_orth<float>), grid, dim3(kBlock), 0, s, g.nn, (const float*)w.w, (float*)w.V, vs, j,
-                       w.kmax, w.dpart, w.inv_eta, w.H, w.part, w.inner_active, (int)npart);
+                       w.kmax, w.dpart, w.inv_eta, w.H, w.part, w.inner_active, np, (const double*)w.hc);
   else
     hipLaunchKernelGGL((k_orth<double>), grid, dim3(kBlock), 0, s, g.nn, (const double*)w.w, (double*)w.V, vs, j,
-                       w.kmax, w.dpart, w.inv_eta, w.H, w.part, w.inner_active, (int)npart);
+                       w.kmax, w.dpart, w.inv_eta, w.H, w.part, w.inner_active, np, (const double*)w.hc);
 }
 
 // Norm of the new vector, Givens rotations of column j, residual estimate |g_{j+1}|.
@@ -1205,8 +1259,16 @@ __global__ __launch_bounds__(kBlock) void k_update_zbasis(int64_t nn, const T* _
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nn) return;
   const int64_t o = (int64_t)sb * nn + i;
+  // four basis vectors' loads in flight at a time; the sum in order of l
   double acc = 0.0;
-  for (int l = 0; l < k; ++l) acc += c[l] * (double)Z[l * vs + o];
+  for (int l0 = 0; l0 < k; l0 += 4) {
+    T zv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) zv[r] = l0 + r < k ? Z[(l0 + r) * vs + o] : (T)0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (l0 + r < k) acc += c[l0 + r] * (double)zv[r];
+  }
   u[o] += acc;
 }
 

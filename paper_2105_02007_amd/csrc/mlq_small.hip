@@ -58,6 +58,50 @@ __device__ inline R stiff_row3(int ix, int iy, int iz, const Geo& g, const TC* _
   return SK;
 }
 
+// Row of the mass (divided by Hm) at node (ix, iy, iz) applied to the 3^3 neighbourhood xm.
+template <typename R>
+__device__ inline R mass_row3(int ix, int iy, int iz, const Geo& g, const R (&xm)[27]) {
+  R SM = 0;
+#pragma unroll
+  for (int oz = -1; oz <= 0; ++oz)
+#pragma unroll
+    for (int oy = -1; oy <= 0; ++oy)
+#pragma unroll
+      for (int ox = -1; ox <= 0; ++ox) {
+        const int ex = ix + ox, ey = iy + oy, ez = iz + oz;
+        if (ex < 0 || ey < 0 || ez < 0 || ex >= g.nx - 1 || ey >= g.ny - 1 || ez >= g.nz - 1) continue;
+        const int ax = -ox, ay = -oy, az = -oz;
+        R sm = 0;
+#pragma unroll
+        for (int bz = 0; bz < 2; ++bz)
+#pragma unroll
+          for (int by = 0; by < 2; ++by)
+#pragma unroll
+            for (int bx = 0; bx < 2; ++bx) {
+              const int nb = (ox + bx + 1) + 3 * ((oy + by + 1) + 3 * (oz + bz + 1));
+              sm += (R)(mm(ax, bx) * mm(ay, by) * mm(az, bz)) * xm[nb];
+            }
+        SM += sm;
+      }
+  return SM;
+}
+
+// The 3^3 neighbourhood of node (ix, iy, iz) through f(node) (0 outside the grid).
+template <typename R, typename F>
+__device__ inline void load_nb(int ix, int iy, int iz, const Geo& g, F f, R (&x)[27]) {
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int jx = ix + dx, jy = iy + dy, jz = iz + dz;
+        const bool in = jx >= 0 && jy >= 0 && jz >= 0 && jx < g.nx && jy < g.ny && jz < g.nz;
+        x[(dx + 1) + 3 * ((dy + 1) + 3 * (dz + 1))] =
+            in ? f(jx + (int64_t)g.nx * (jy + (int64_t)g.ny * jz)) : (R)0;
+      }
+}
+
 // Thomas elimination of tridiag(1, 4, 1) (2 at the ends) on a strided line, iv = 1 / pivots.
 template <typename T>
 __device__ inline void thomas_line(T* a, int n, int stride, const T* __restrict__ iv) {
@@ -137,17 +181,16 @@ __global__ __launch_bounds__(NT) void k_solve_small(SmallArgs a) {
         for (int64_t i = t; i < n; i += NT) {
           int ix, iy, iz;
           node_xyz(i, g, ix, iy, iz);
-          double xm[27], xk[27];
-          load_nbhd<3, double>(
-              ix, iy, iz, g,
-              [&](int64_t j, double& m, double& s) {
-                const double uu = pu[j], u0 = pk[j];
-                m = (uu - u0) + dt * iion(uu, io);
-                s = uu + u0;
-              },
-              xm, xk);
-          double SM, SK;
-          gather3<double, TI>(ix, iy, iz, g, cf, xm, xk, SM, SK);
+          // the stiffness and the mass parts one after the other (one 27-value neighbourhood live
+          // at a time; the second reads hit the cache)
+          double xn[27];
+          load_nb<double>(ix, iy, iz, g, [&](int64_t q) { return pu[q] + pk[q]; }, xn);
+          const double SK = stiff_row3<double, TI>(ix, iy, iz, g, cf, xn);
+          load_nb<double>(ix, iy, iz, g, [&](int64_t q) {
+            const double uu = pu[q];
+            return (uu - pk[q]) + dt * iion(uu, io);
+          }, xn);
+          const double SM = mass_row3<double>(ix, iy, iz, g, xn);
           const double fb = load * a.fbox[i];
           const double F = hm * SM + ck * SK - fb;
           const double uo = pu[i];
@@ -212,14 +255,8 @@ __global__ __launch_bounds__(NT) void k_solve_small(SmallArgs a) {
           for (int64_t i = t; i < n; i += NT) {
             int ix, iy, iz;
             node_xyz(i, g, ix, iy, iz);
-            TI xm[27], xk[27];
-            load_nbhd<3, TI>(
-                ix, iy, iz, g,
-                [&](int64_t q, TI& m, TI& s) {
-                  m = 0;
-                  s = tz[q];
-                },
-                xm, xk);
+            TI xk[27];
+            load_nb<TI>(ix, iy, iz, g, [&](int64_t q) { return tz[q]; }, xk);
             const TI wi = vj[i] * iej + (TI)ck * stiff_row3<TI, TI>(ix, iy, iz, g, cf, xk);
             wv[i] = wi;
 #pragma unroll
