@@ -206,7 +206,7 @@ namespace {
 
 struct BlobLayout {
   size_t phi64, phi32, sl, th0, fbox, wts, tri;
-  size_t ucol, um, um32, lcol, lm, lm32, lidx, mdiag, mdiag32, ucptr, ucdat, geo, vmean;  // tetrahedral levels
+  size_t ecol, ediag, em, em32, mdiag, mdiag32, ecptr, ecdat, geo, vmean;  // tetrahedral levels
   size_t total;
 };
 
@@ -221,18 +221,14 @@ BlobLayout blob_layout(int64_t P, int64_t M, int64_t nn, int64_t nmax, const mlq
   L.fbox = o;  o = align256(o + sizeof(double) * nn);
   L.wts = o;   o = align256(o + sizeof(double) * nn);
   if (th != nullptr) {
-    const size_t nu = (size_t)th->wu * th->nv, nl = (size_t)th->wl * th->nv;
-    L.ucol = o;    o = align256(o + sizeof(int32_t) * nu);
-    L.um = o;      o = align256(o + sizeof(double) * nu);
-    L.um32 = o;    o = align256(o + sizeof(float) * nu);
-    L.lcol = o;    o = align256(o + sizeof(int32_t) * nl);
-    L.lm = o;      o = align256(o + sizeof(double) * nl);
-    L.lm32 = o;    o = align256(o + sizeof(float) * nl);
-    L.lidx = o;    o = align256(o + sizeof(int32_t) * nl);
+    L.ecol = o;    o = align256(o + sizeof(int32_t) * th->nell);
+    L.ediag = o;   o = align256(o + sizeof(int32_t) * th->nv);
+    L.em = o;      o = align256(o + sizeof(double) * th->nell);
+    L.em32 = o;    o = align256(o + sizeof(float) * th->nell);
     L.mdiag = o;   o = align256(o + sizeof(double) * th->nv);
     L.mdiag32 = o; o = align256(o + sizeof(float) * th->nv);
-    L.ucptr = o;   o = align256(o + sizeof(int32_t) * (nu + 1));
-    L.ucdat = o;   o = align256(o + sizeof(int32_t) * th->nc);
+    L.ecptr = o;   o = align256(o + sizeof(int32_t) * (th->nell + 1));
+    L.ecdat = o;   o = align256(o + sizeof(int32_t) * th->nc);
     L.geo = o;     o = align256(o + sizeof(double) * mlq::kTetGeo * th->nt);
     L.vmean = o;   o = align256(o + sizeof(double) * 3 * th->nt);
   }
@@ -599,39 +595,31 @@ mlq_status mlq_create_level(const mlq_level_desc* desc, void* level_mem_dev, siz
     t.nv = th.nv;
     t.nt = th.nt;
     t.nell = th.nell;
-    t.wu = th.wu;
-    t.wl = th.wl;
+    t.width = th.width;
     t.nc = th.nc;
-    t.ucol = (const int32_t*)(base + L.ucol);
-    t.um = (const double*)(base + L.um);
-    t.um32 = (const float*)(base + L.um32);
-    t.lcol = (const int32_t*)(base + L.lcol);
-    t.lm = (const double*)(base + L.lm);
-    t.lm32 = (const float*)(base + L.lm32);
-    t.lidx = (const int32_t*)(base + L.lidx);
+    t.ecol = (const int32_t*)(base + L.ecol);
+    t.ediag = (const int32_t*)(base + L.ediag);
+    t.em = (const double*)(base + L.em);
+    t.em32 = (const float*)(base + L.em32);
     t.mdiag = (const double*)(base + L.mdiag);
     t.mdiag32 = (const float*)(base + L.mdiag32);
-    t.ucptr = (const int32_t*)(base + L.ucptr);
-    t.ucdat = (const int32_t*)(base + L.ucdat);
+    t.ecptr = (const int32_t*)(base + L.ecptr);
+    t.ecdat = (const int32_t*)(base + L.ecdat);
     t.geo = (const double*)(base + L.geo);
     t.model = desc->diffusion;
     t.vmean = (const double*)(base + L.vmean);
-    std::vector<float> um32(th.um.begin(), th.um.end()), lm32(th.lm.begin(), th.lm.end());
-    std::vector<float> d32(th.mdiag.begin(), th.mdiag.end());
+    std::vector<float> m32(th.em.begin(), th.em.end()), d32(th.mdiag.begin(), th.mdiag.end());
     auto up = [&](const void* dst, const void* src, size_t bytes) {
-      if (e == hipSuccess && bytes > 0) e = hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, s);
     };
-    up(t.ucol, th.ucol.data(), sizeof(int32_t) * th.ucol.size());
-    up(t.um, th.um.data(), sizeof(double) * th.um.size());
-    up(t.um32, um32.data(), sizeof(float) * um32.size());
-    up(t.lcol, th.lcol.data(), sizeof(int32_t) * th.lcol.size());
-    up(t.lm, th.lm.data(), sizeof(double) * th.lm.size());
-    up(t.lm32, lm32.data(), sizeof(float) * lm32.size());
-    up(t.lidx, th.lidx.data(), sizeof(int32_t) * th.lidx.size());
+    up(t.ecol, th.ecol.data(), sizeof(int32_t) * th.ecol.size());
+    up(t.ediag, th.ediag.data(), sizeof(int32_t) * th.ediag.size());
+    up(t.em, th.em.data(), sizeof(double) * th.em.size());
+    up(t.em32, m32.data(), sizeof(float) * m32.size());
     up(t.mdiag, th.mdiag.data(), sizeof(double) * th.mdiag.size());
     up(t.mdiag32, d32.data(), sizeof(float) * d32.size());
-    up(t.ucptr, th.ucptr.data(), sizeof(int32_t) * th.ucptr.size());
-    up(t.ucdat, th.ucdat.data(), sizeof(int32_t) * th.ucdat.size());
+    up(t.ecptr, th.ecptr.data(), sizeof(int32_t) * th.ecptr.size());
+    up(t.ecdat, th.ecdat.data(), sizeof(int32_t) * th.ecdat.size());
     up(t.geo, th.geo.data(), sizeof(double) * th.geo.size());
     if (t.model == MLQ_DIFF_VECTOR) up(t.vmean, desc->v_mean, sizeof(double) * 3 * th.nt);
     // the host vectors must outlive the asynchronous copies
@@ -920,17 +908,15 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
         // read for the fused projections; tetrahedra z, d read, w written per vertex and theta
         // once per tetrahedron.  The kernel's own bytes: FP64 and 2D boxes read the element
         // coefficient pair (p, q) instead of theta; tetrahedra read the assembled stiffness values of
-        // the upper slots of a row (the lower ones are the same values, read again through the
-        // transposed positions) instead of theta, and the shared pattern (columns, mass,
-        // positions) once per launch.
-        const double slots = tet ? (double)td.wu : 0.0;
+        // every slot of a row instead of theta, and the shared pattern (columns, mass) once
+        // per launch.
+        const double slots = tet ? (double)td.nell / (double)td.nv : 0.0;
         const double apply_bytes =
             tet ? ti * (3.0 * nn + (td.model == MLQ_DIFF_VECTOR ? 3.0 : 1.0) * (double)level->P)
                 : nn * ti * (4.0 + (fuse ? j : 0));
         const double box_vals = (mixed && g.dim == 3 ? 4.0 : 5.0) + (fuse ? j : 0);  // mixed 3D: theta
         const double apply_kbytes = nn * ti * (tet ? slots + 3.0 : box_vals);
-        const double apply_fixed =
-            tet ? (double)td.wu * (double)td.nv * (4.0 + ti) + (double)td.wl * (double)td.nv * (8.0 + ti) : 0.0;
+        const double apply_fixed = tet ? (double)td.nell * (4.0 + ti) : 0.0;
         tm(
             MLQ_K_APPLY, nn,
             [&] {

@@ -43,41 +43,35 @@ struct Geo {
   int32_t group;
 };
 
-// P1 tetrahedral level data on the device (inside the level blob).  The sparsity of M and K
-// is the vertex adjacency.  Both are symmetric, so each row is split into its upper part (the
-// diagonal in slot 0, then the columns above it in increasing order) and its lower part (the
-// columns below it, increasing), each stored slot-major and padded to its longest row (entry
-// (s, i) at s * nv + i: consecutive rows are consecutive in memory for every slot).  The
-// per-sample stiffness values exist for the upper part only ([wu + 1][nv] per sample, slot wu all
-// zeros); a lower entry reads the value of the transposed upper entry (lidx).  Every upper
-// entry lists the element matrix entries that add into it, in increasing element order.
+// P1 tetrahedral level data on the device (inside the level blob).  The sparsity
+// of M and K is the vertex adjacency (CSR); each nonzero lists the element
+// matrix entries that add into it, in increasing element order.
 struct TetDev {
-  int64_t nv, nt, nell, nc;  // nell = (wu + 1) nv: stiffness values per sample
-  int32_t wu, wl;            // upper / lower slots per row
-  const int32_t* ucol;       // wu nv: column of upper entry (s, i) (padding: i)
-  const double* um;          // wu nv: consistent P1 mass of the upper entries (padding: 0)
-  const float* um32;
-  const int32_t* lcol;       // wl nv: column of lower entry (s, i) (padding: i)
-  const double* lm;          // wl nv: its mass (padding: 0)
-  const float* lm32;
-  const int32_t* lidx;       // wl nv: index of its stiffness value in the sample's values (padding: the zero slot)
-  const double* mdiag;       // nv: diagonal of M
-  const float* mdiag32;      // nv
-  const int32_t* ucptr;      // wu nv + 1
-  const int32_t* ucdat;      // nc: (tet << 4) | (4 a + b), a = local row vertex, b = local column vertex
-  const double* geo;         // nt x kTetGeo: grad phi_0..3 (12), e_circ (3), e_long (3), volume
-  int32_t model;             // conductivity model (MLQ_DIFF_*; vector: the field is V - vmean, 3 components)
-  const double* vmean;       // nt x 3: E[V] per element (vector model), else unused
+  int64_t nv, nt, nell, nc;
+  int32_t width;           // slots per row: the longest row of the P1 pattern
+  // the pattern stored slot-major: entry (s, i) at s * nv + i (consecutive rows are
+  // consecutive in memory for every slot); padded slots point at row i with value 0
+  const int32_t* ecol;     // nell: column
+  const int32_t* ediag;    // nv: slot of the diagonal entry of each row
+  const double* em;        // nell: consistent P1 mass
+  const float* em32;       // nell
+  const double* mdiag;     // nv: diagonal of M
+  const float* mdiag32;    // nv
+  const int32_t* ecptr;    // nell + 1
+  const int32_t* ecdat;    // nc: (tet << 4) | (4 a + b), a = local row vertex, b = local column vertex
+  const double* geo;       // nt x kTetGeo: grad phi_0..3 (12), e_circ (3), e_long (3), volume
+  int32_t model;           // conductivity model (MLQ_DIFF_*; vector: the field is V - vmean, 3 components)
+  const double* vmean;     // nt x 3: E[V] per element (vector model), else unused
 };
 constexpr int kTetGeo = 19;
 
 // Host-side preparation of a tetrahedral level (mlq_tetmesh.cpp).
 struct TetHost {
   int64_t nv = 0, nt = 0, nnz = 0, nc = 0, nell = 0;
-  int32_t wu = 0, wl = 0;
+  int32_t width = 0;
   std::vector<int32_t> rowptr, col, cptr, cdat;   // CSR (rows sorted)
-  std::vector<int32_t> ucol, ucptr, ucdat, lcol, lidx;  // the upper / lower parts (TetDev)
-  std::vector<double> mval, um, lm, mdiag, geo, wts, fload;
+  std::vector<int32_t> ecol, ecptr, ecdat, ediag; // the same, slot-major padded (TetDev)
+  std::vector<double> mval, em, mdiag, geo, wts, fload;
   double vol = 0.0;
 };
 // Validates the tetrahedral fields of desc and builds the CSR structure (and, with

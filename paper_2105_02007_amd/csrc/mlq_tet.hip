@@ -5,16 +5,15 @@
 //   K_e[a][b] = |T| ( sigma_t g_a . g_b + (sigma_l - sigma_t) (g_a . f)(g_b . f) ),
 //   f = cos(theta) e_circ + sin(theta) e_long,
 // (eq. (AdmV) with V = sigma_l f; g_a = grad phi_a).  Once per solve its values are
-// gathered per stored upper entry of the vertex-adjacency pattern (each entry sums its
+// gathered per stored entry of the vertex-adjacency pattern (each entry sums its
 // element contributions in increasing element order: deterministic, no atomics) into
-// kval[b][e]; K is symmetric, so a row's entries below the diagonal read the value stored for
-// the transposed entry (one value per pair of off-diagonal entries).  The mass M (P1,
-// |T| (1 + delta_ab) / 20) is shared by all samples.  Both parts of the pattern are stored
-// slot-major and padded (entry (s, i) at s * nv + i), so that in every operator application
-// (one thread per row and sample, or per row and group of samples in the Jacobian apply; rows
-// of one sample contiguous) a wave reads the columns, mass and upper stiffness values of slot s
-// for 64 consecutive rows in one coalesced load.  A row sums its upper slots (diagonal first,
-// then increasing column), then its lower slots (increasing column).
+// kval[b][e].  The mass M (P1, |T| (1 + delta_ab) / 20) is shared by all samples.
+// The pattern is stored slot-major and padded to the longest row (entry (s, i) at
+// s * nv + i), so that in every operator application (one thread per row and sample,
+// or per row and group of samples in the Jacobian apply; rows of one sample contiguous,
+// samples on blockIdx.y) a wave reads the columns, mass and stiffness values of slot s
+// for 64 consecutive rows in one coalesced load.  Within a row the slots follow
+// increasing column order.
 #include "mlq_internal.h"
 
 namespace mlq {
@@ -47,7 +46,7 @@ __device__ inline double tet_diion(double u, const Ionic& io) {
 // G = s_t I + (s_l - s_t) f f^T.  Isotropic model (1): G = max(theta, s_t) I, s_t the lower
 // bound.  Vector model (2): the field is V = vmean + (theta_0, theta_1, theta_2) per element,
 // component c of sample b at theta[(c B + b) P + e], and G = g I + (|V| - g) V V^T / V^T V
-// (eq. (AdmV) with g = sigma_t).  Entries of the zero slot (nz >= wu nv) are written as 0.
+// (eq. (AdmV) with g = sigma_t).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tet_assemble(TetDev t, const T* __restrict__ theta, T* __restrict__ kval,
                                                          double sigma_t, double dsig, int model, int32_t B,
@@ -58,10 +57,8 @@ __global__ __launch_bounds__(kBlock) void k_tet_assemble(TetDev t, const T* __re
   const T* th = theta + (int64_t)sb * t.nt;
   const int64_t cstride = (int64_t)B * t.nt;
   double acc = 0.0;
-  const int64_t nu = (int64_t)t.wu * t.nv;
-  const int32_t c0 = nz < nu ? t.ucptr[nz] : 0, c1 = nz < nu ? t.ucptr[nz + 1] : 0;
-  for (int32_t c = c0; c < c1; ++c) {
-    const int32_t code = t.ucdat[c];
+  for (int32_t c = t.ecptr[nz]; c < t.ecptr[nz + 1]; ++c) {
+    const int32_t code = t.ecdat[c];
     const int64_t e = code >> 4;
     const int a = (code >> 2) & 3, b = code & 3;
     const double* G = t.geo + e * kTetGeo;
@@ -91,8 +88,8 @@ __global__ __launch_bounds__(kBlock) void k_tet_assemble(TetDev t, const T* __re
 }
 
 // y = M ((1 + d) x) + ck K x.  A thread takes one row for kTetSamples samples, so that the
-// shared pattern (columns, mass, transposed positions) is read once for all of them; each
-// sample's sum runs over the slots in the same order as for one sample.
+// shared pattern (columns, mass) is read once for all of them; each sample's sum runs over
+// the slots in the same order as for one sample.
 constexpr int kTetSamples = 4;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tet_apply(TetDev t, const T* __restrict__ kval, const T* __restrict__ x,
@@ -112,87 +109,53 @@ __global__ __launch_bounds__(kBlock) void k_tet_apply(TetDev t, const T* __restr
   if (!any) return;
   const int64_t i = bx * kBlock + threadIdx.x;
   if (i >= t.nv) return;
-  const T* umv = nullptr;
-  const T* lmv = nullptr;
-  if constexpr (sizeof(T) == 4) {
-    umv = (const T*)t.um32;
-    lmv = (const T*)t.lm32;
-  } else {
-    umv = (const T*)t.um;
-    lmv = (const T*)t.lm;
-  }
+  const T* mv = nullptr;
+  if constexpr (sizeof(T) == 4) mv = (const T*)t.em32; else mv = (const T*)t.em;
   T acc[S];
 #pragma unroll
   for (int q = 0; q < S; ++q) acc[q] = 0;
   bool all = true;
 #pragma unroll
   for (int q = 0; q < S; ++q) all = all && on[q];
-  // one slot: column c, mass m, the flat position p of its stiffness value in a sample's values
-  auto slot_all = [&](int64_t c, T m, int64_t p) {
-    T dv[S], xv[S], kv[S];
-#pragma unroll
-    for (int q = 0; q < S; ++q) {
-      const int64_t j = (int64_t)(sb0 + q) * t.nv + c;
-      dv[q] = d[j];
-      xv[q] = x[j];
-      kv[q] = kval[(int64_t)(sb0 + q) * t.nell + p];
-    }
-#pragma unroll
-    for (int q = 0; q < S; ++q) acc[q] += (m * ((T)1 + dv[q]) + ck * kv[q]) * xv[q];
-  };
-  auto slot_some = [&](int64_t c, T m, int64_t p) {
-#pragma unroll
-    for (int q = 0; q < S; ++q) {
-      if (!on[q]) continue;
-      const int64_t j = (int64_t)(sb0 + q) * t.nv + c;
-      acc[q] += (m * ((T)1 + d[j]) + ck * kval[(int64_t)(sb0 + q) * t.nell + p]) * x[j];
-    }
-  };
   if (all) {
-    // Every sample of the group active (the usual case): no per-sample branch in the slot loops,
-    // so the gathers of all samples and of the next slot are in flight together.  Same
-    // arithmetic, in the same order, as the general loops below.
+    // Every sample of the group active (the usual case): no per-sample branch in the slot loop, so
+    // the gathers of all samples and of the next slot are in flight together. Same arithmetic, in
+    // the same order, as the general loop below.
 #pragma unroll 2
-    for (int32_t sl = 0; sl < t.wu; ++sl) {
+    for (int32_t sl = 0; sl < t.width; ++sl) {
       const int64_t e = (int64_t)sl * t.nv + i;
-      slot_all(t.ucol[e], umv[e], e);
-    }
-#pragma unroll 2
-    for (int32_t sl = 0; sl < t.wl; ++sl) {
-      const int64_t e = (int64_t)sl * t.nv + i;
-      slot_all(t.lcol[e], lmv[e], t.lidx[e]);
+      const int64_t c = t.ecol[e];
+      const T m = mv[e];
+      T dv[S], xv[S], kv[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        const int64_t j = (int64_t)(sb0 + q) * t.nv + c;
+        dv[q] = d[j];
+        xv[q] = x[j];
+        kv[q] = kval[(int64_t)(sb0 + q) * t.nell + e];
+      }
+#pragma unroll
+      for (int q = 0; q < S; ++q) acc[q] += (m * ((T)1 + dv[q]) + ck * kv[q]) * xv[q];
     }
 #pragma unroll
     for (int q = 0; q < S; ++q) y[(int64_t)(sb0 + q) * t.nv + i] = acc[q];
     return;
   }
-  for (int32_t sl = 0; sl < t.wu; ++sl) {
+  for (int32_t sl = 0; sl < t.width; ++sl) {
     const int64_t e = (int64_t)sl * t.nv + i;
-    slot_some(t.ucol[e], umv[e], e);
-  }
-  for (int32_t sl = 0; sl < t.wl; ++sl) {
-    const int64_t e = (int64_t)sl * t.nv + i;
-    slot_some(t.lcol[e], lmv[e], t.lidx[e]);
+    const int64_t c = t.ecol[e];
+    const T m = mv[e];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      if (!on[q]) continue;
+      const int64_t so = (int64_t)(sb0 + q) * t.nv;
+      const int64_t j = so + c;
+      acc[q] += (m * ((T)1 + d[j]) + ck * kval[(int64_t)(sb0 + q) * t.nell + e]) * x[j];
+    }
   }
 #pragma unroll
   for (int q = 0; q < S; ++q)
     if (on[q]) y[(int64_t)(sb0 + q) * t.nv + i] = acc[q];
-}
-
-// Row i of a sample in FP64: sum over the row's entries of f(column, mass, stiffness value), upper
-// slots then lower slots (the order of k_tet_apply).
-template <typename TI, typename F>
-__device__ inline void tet_row(const TetDev& t, const TI* __restrict__ kv, int64_t i, F&& f) {
-#pragma unroll 4
-  for (int32_t sl = 0; sl < t.wu; ++sl) {
-    const int64_t e = (int64_t)sl * t.nv + i;
-    f(t.ucol[e], t.um[e], (double)kv[e]);
-  }
-#pragma unroll 4
-  for (int32_t sl = 0; sl < t.wl; ++sl) {
-    const int64_t e = (int64_t)sl * t.nv + i;
-    f(t.lcol[e], t.lm[e], (double)kv[t.lidx[e]]);
-  }
 }
 
 // F = M (u + dt I_ion(u)) + dt/2 K u - b (FP64), r0 = -F, d = dt I_ion'(u), partial norms
@@ -213,10 +176,12 @@ __global__ __launch_bounds__(kBlock) void k_tet_residual(TetDev t, Ionic io, con
     const TI* kv = kval + (int64_t)sb * t.nell;
     const double ck = 0.5 * io.dt;
     double G = 0.0;
-    tet_row(t, kv, i, [&](int32_t c, double m, double k) {
-      const double uj = u[so + c];
-      G += m * (uj + io.dt * tet_iion(uj, io)) + ck * k * uj;
-    });
+#pragma unroll 4
+    for (int32_t sl = 0; sl < t.width; ++sl) {
+      const int64_t e = (int64_t)sl * t.nv + i;
+      const double uj = u[so + t.ecol[e]];
+      G += t.em[e] * (uj + io.dt * tet_iion(uj, io)) + ck * (double)kv[e] * uj;
+    }
     const double b = bv[so + i];
     const double F = G - b;
     r0[so + i] = (TI)(-F);
@@ -254,9 +219,9 @@ __global__ __launch_bounds__(kBlock) void k_tet_residual(TetDev t, Ionic io, con
 }
 
 // b = M u_k - dt/2 K u_k + load F (FP64), u = u_k
+template <typename TI>
 // Also, with uprev (u_{k-1}, may be NULL): the extrapolated Newton start 2 u_k - u_{k-1}
 // (extrap) and the activation times of the step from t_prev = t_{k-1} to t_k into act.
-template <typename TI>
 __global__ __launch_bounds__(kBlock) void k_tet_rhs(TetDev t, const TI* __restrict__ kval,
                                                     const double* __restrict__ uk, const double* __restrict__ fload,
                                                     double load, double ck, double* __restrict__ bout,
@@ -271,7 +236,12 @@ __global__ __launch_bounds__(kBlock) void k_tet_rhs(TetDev t, const TI* __restri
   const int64_t so = (int64_t)sb * t.nv;
   const TI* kv = kval + (int64_t)sb * t.nell;
   double acc = 0.0;
-  tet_row(t, kv, i, [&](int32_t c, double m, double k) { acc += (m - ck * k) * uk[so + c]; });
+#pragma unroll 4
+  for (int32_t sl = 0; sl < t.width; ++sl) {
+    const int64_t e = (int64_t)sl * t.nv + i;
+    const double uj = uk[so + t.ecol[e]];
+    acc += (t.em[e] - ck * (double)kv[e]) * uj;
+  }
   bout[so + i] = acc + load * fload[i];
   const double u0 = uk[so + i];
   double ustart = u0;
@@ -298,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_jacobi(TetDev t, const T* __rest
   const T* md = nullptr;
   if constexpr (sizeof(T) == 4) md = (const T*)t.mdiag32; else md = (const T*)t.mdiag;
   const int64_t o = (int64_t)sb * t.nv + i;
-  const T kii = kval[(int64_t)sb * t.nell + i];  // upper slot 0: the diagonal
+  const T kii = kval[(int64_t)sb * t.nell + (int64_t)t.ediag[i] * t.nv + i];
   const T s = (T)inv_eta[(int64_t)sb * (kmax + 1) + j];
   z[o] = v[o] * s / (md[i] * ((T)1 + d[o]) + ck * kii);
 }

@@ -68,19 +68,12 @@ std::string tet_build(const mlq_level_desc* d, TetHost& h, bool values) {
   }
   h.nnz = (int64_t)h.col.size();
   h.nc = 16 * nt;
-  for (int64_t v = 0; v < nv; ++v)
-    if (h.rowptr[v + 1] == h.rowptr[v]) return "a vertex belongs to no tetrahedron";
-  // upper and lower row lengths (the per-sample value count nell = (wu + 1) nv): the diagonal
-  // and the columns above it, the columns below it
-  h.wu = 0;
-  h.wl = 0;
+  h.width = 0;
   for (int64_t v = 0; v < nv; ++v) {
-    int32_t low = 0;
-    for (int32_t nz = h.rowptr[v]; nz < h.rowptr[v + 1]; ++nz) low += h.col[nz] < v;
-    h.wl = std::max(h.wl, low);
-    h.wu = std::max(h.wu, h.rowptr[v + 1] - h.rowptr[v] - low);
+    if (h.rowptr[v + 1] == h.rowptr[v]) return "a vertex belongs to no tetrahedron";
+    h.width = std::max(h.width, h.rowptr[v + 1] - h.rowptr[v]);
   }
-  h.nell = (int64_t)(h.wu + 1) * nv;
+  h.nell = (int64_t)h.width * nv;
   if (h.nell > (int64_t)INT32_MAX) return "too many padded nonzeros for 32-bit indices";
   if (!values) return "";
   // element geometry: gradients (rows of inverse edge matrix), frame, volume
@@ -145,65 +138,32 @@ std::string tet_build(const mlq_level_desc* d, TetHost& h, bool values) {
     if (pass == 0)
       for (int64_t nz = 0; nz < h.nnz; ++nz) h.cptr[nz + 1] += h.cptr[nz];
   }
-  // K and M are symmetric: the per-sample stiffness is stored once per pair of entries, as the
-  // upper part of every row (the diagonal in slot 0, then the columns above it in increasing
-  // order), slot-major and padded to the longest upper row (entry (s, v) at s * nv + v), plus one
-  // slot of zeros (s = wu).  A row's lower entries (columns below it, increasing) read the value
-  // of the transposed entry in the upper part of the column's row (lidx); a padded slot points at
-  // the row itself with zero mass and at the zero slot.  The mass values are kept for both parts.
-  h.wu = 0;
-  h.wl = 0;
-  std::vector<int32_t> dpos(nv);  // position of the diagonal within each CSR row
-  for (int64_t v = 0; v < nv; ++v) {
-    const int32_t* rb = h.col.data() + h.rowptr[v];
-    const int32_t len = h.rowptr[v + 1] - h.rowptr[v];
-    dpos[v] = (int32_t)(std::lower_bound(rb, rb + len, (int32_t)v) - rb);
-    if (dpos[v] >= len || rb[dpos[v]] != v) return "a vertex is missing from its own row";
-    h.wl = std::max(h.wl, dpos[v]);
-    h.wu = std::max(h.wu, len - dpos[v]);
+  // slot-major padded rows: entry (slot s, row v) at s * nv + v; a padded slot points at the
+  // row itself with a zero value and no contributions
+  h.ediag.assign(nv, -1);
+  for (int64_t v = 0; v < nv; ++v)
+    for (int32_t nz = h.rowptr[v]; nz < h.rowptr[v + 1]; ++nz)
+      if (h.col[nz] == v) h.ediag[v] = nz - h.rowptr[v];
+  h.ecol.assign(h.nell, 0);
+  h.em.assign(h.nell, 0.0);
+  h.ecptr.assign(h.nell + 1, 0);
+  h.ecdat.assign(h.nc, 0);
+  {
+    int64_t c = 0;
+    for (int32_t sl = 0; sl < h.width; ++sl)
+      for (int64_t v = 0; v < nv; ++v) {
+        const int64_t idx = (int64_t)sl * nv + v;
+        if (sl < h.rowptr[v + 1] - h.rowptr[v]) {
+          const int64_t nz = h.rowptr[v] + sl;
+          h.ecol[idx] = h.col[nz];
+          h.em[idx] = h.mval[nz];
+          for (int32_t q = h.cptr[nz]; q < h.cptr[nz + 1]; ++q) h.ecdat[c++] = h.cdat[q];
+        } else {
+          h.ecol[idx] = (int32_t)v;
+        }
+        h.ecptr[idx + 1] = (int32_t)c;
+      }
   }
-  h.nell = (int64_t)(h.wu + 1) * nv;
-  if (h.nell > (int64_t)INT32_MAX) return "too many padded nonzeros for 32-bit indices";
-  const int64_t nu = (int64_t)h.wu * nv, nl = (int64_t)h.wl * nv;
-  h.ucol.assign(nu, 0);
-  h.um.assign(nu, 0.0);
-  h.ucptr.assign(nu + 1, 0);
-  h.ucdat.clear();
-  h.lcol.assign(nl, 0);
-  h.lm.assign(nl, 0.0);
-  h.lidx.assign(nl, 0);
-  for (int32_t sl = 0; sl < h.wu; ++sl)
-    for (int64_t v = 0; v < nv; ++v) {
-      const int64_t idx = (int64_t)sl * nv + v;
-      const int32_t len = h.rowptr[v + 1] - h.rowptr[v];
-      if (dpos[v] + sl < len) {
-        const int64_t nz = h.rowptr[v] + dpos[v] + sl;
-        h.ucol[idx] = h.col[nz];
-        h.um[idx] = h.mval[nz];
-        for (int32_t q = h.cptr[nz]; q < h.cptr[nz + 1]; ++q) h.ucdat.push_back(h.cdat[q]);
-      } else {
-        h.ucol[idx] = (int32_t)v;
-      }
-      h.ucptr[idx + 1] = (int32_t)h.ucdat.size();
-    }
-  for (int32_t sl = 0; sl < h.wl; ++sl)
-    for (int64_t v = 0; v < nv; ++v) {
-      const int64_t idx = (int64_t)sl * nv + v;
-      if (sl < dpos[v]) {
-        const int64_t nz = h.rowptr[v] + sl;
-        const int32_t j = h.col[nz];  // j < v: entry (v, j) = entry (j, v), in row j's upper part
-        const int32_t* rb = h.col.data() + h.rowptr[j];
-        const int32_t len = h.rowptr[j + 1] - h.rowptr[j];
-        const int32_t pos = (int32_t)(std::lower_bound(rb, rb + len, (int32_t)v) - rb);
-        if (pos >= len || rb[pos] != v) return "the vertex adjacency is not symmetric";
-        h.lcol[idx] = j;
-        h.lm[idx] = h.mval[nz];
-        h.lidx[idx] = (int32_t)((int64_t)(pos - dpos[j]) * nv + j);
-      } else {
-        h.lcol[idx] = (int32_t)v;
-        h.lidx[idx] = (int32_t)(nu + v);
-      }
-    }
   h.mdiag.assign(nv, 0.0);
   h.wts.assign(nv, 0.0);
   h.fload.assign(nv, 0.0);

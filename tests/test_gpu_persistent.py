@@ -160,3 +160,35 @@ def test_persistent_refused_where_it_does_not_apply(env):
     desc, keep = mlq.make_desc(dict(dim=2, n=[9, 9], lo=[0.0] * 2, hi=[1.0] * 2, n_steps=4), W.physics(2), max_batch=2)
     with pytest.raises(mlq.MlqError):
         mlq.Level(desc, keep).set_persistent(True)
+
+
+def test_persistent_solve_captured_in_a_graph_replays_bit_identical(env):
+    """An enqueue-only solve can be captured: the whole persistent solve (field coefficients and the
+    one solver launch) recorded into a HIP graph through torch, replayed several times with eager
+    work and synchronisations in between, every replay equal to the eager solve bit for bit."""
+    torch, mlq = env
+    B = 6
+    L, theta, th, mesh, phys = _setup(env, [9, 9, 9], 16, B, W.PREC_MIXED, W.QOI_MEAN_ACT_TIME, seed=12)
+    L.set_persistent(True)
+    eager = L.solve(theta, want_state=True)  # also sizes the level's workspace outside the capture
+    torch.cuda.synchronize()
+    q0, u0 = eager["qoi"].clone(), eager["u"].clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        L.solve(theta, want_state=True)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        cap = L.solve(theta, want_state=True)
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(cap["qoi"], q0), rep
+        assert torch.equal(cap["u"], u0), rep
+        assert int(cap["status"].abs().sum()) == 0
+        # eager work between the replays
+        again = L.solve(theta)
+        torch.cuda.synchronize()
+        assert torch.equal(again["qoi"], q0)
