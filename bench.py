@@ -168,6 +168,8 @@ def cpu_baseline(name, cfg, budget_s):
                                 s_per_sample_step=round(sum(r[3] for r in res) / (len(res) * steps), 4))
             if time.perf_counter() - t_all + 5.0 * el > budget_s:  # the next level costs about 5x
                 break
+        pool.close()
+        pool.join()  # every worker has exited before the GPU is touched
     wall = sum(v["wall_s"] for v in per_level.values())
     dof_iters = sum(r[0] * r[2] for r in done)
     st_dof = sum(r[0] * r[1] for r in done)

@@ -924,7 +924,7 @@ static mlq_status solve_impl(mlq_level* level, const void* theta_dev, int32_t ba
                 launch_tet_apply(td, w.coef, (const char*)w.z + (size_t)j * level->nn * batch * (size_t)ti, w.d,
                                  w.w, 0.5 * dt, batch, w.inner_active, mixed, s);
               else if (g.dim == 3)
-                launch_apply_pk3(g, w, j, 0.5 * dt, batch, mixed, s, fuse ? (j < 4 ? 4 : 8) : 0);
+                launch_apply_pk3(g, w, j, 0.5 * dt, batch, mixed, s, fuse ? (j == 0 ? 1 : j < 4 ? 4 : 8) : 0);
               else
                 launch_apply_pk(g, w, j, 0.5 * dt, batch, mixed, s);
             },
