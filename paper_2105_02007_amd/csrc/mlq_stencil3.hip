@@ -176,8 +176,10 @@ __device__ inline R shdn(R v, int d) {
 // (the same values the pair kernel k_coefs stores); 2 = the same with the hardware sine and cosine
 // (an approximation good to about 1e-6, used where only the Krylov operator needs it); 3 = the
 // isotropic field v, p = max(v, cfa), q = 0.  CF > 0 reads 4 bytes per element instead of 8.
+// At least three waves per SIMD: the FP64 residual variants sit just above the register budget of
+// three (168 VGPRs) and would otherwise drop to two; the other variants use far fewer registers.
 template <typename R, typename TC, typename TI, int MODE, int JB, int LX, int CF>
-__global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_wave3(Args<R> A) {
   constexpr int LY = 64 / LX;
   constexpr int WTX = LX - 1, WTY = LY - 1;  // owned nodes per wave along x and y
   const Geo& g = A.g;
@@ -186,6 +188,8 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
   const double ida = A.io.dt * A.io.alpha, ir = A.io.u_rest, it_ = A.io.u_th, ip = A.io.u_peak;
   const double ic3 = ida, ic2 = -ida * (ir + it_ + ip), ic1 = ida * (ir * it_ + ir * ip + it_ * ip),
                ic0 = -ida * ir * it_ * ip;
+  // its derivative dt I_ion'(u) = (3 ic3 u + 2 ic2) u + ic1
+  const double dc2 = 3.0 * ic3, dc1 = 2.0 * ic2;
   // Workgroups go to the 8 XCDs round-robin (linear id mod 8).  Renumber them so
   // that each XCD owns one contiguous range of (sample, tile) blocks: tiles that
   // share cache lines (x/y halos, the plane above a z-chunk) then meet in one L2.
@@ -239,6 +243,9 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     const int64_t oof = (int64_t)ocy * g.nx + ocx;                      // owned node (clamped)
     const int64_t ce = (int64_t)cx0 + (int64_t)ex_n * cy0;              // clamped element in its layer
     const int64_t layer = (int64_t)ex_n * ey_n;
+    // lumped-mass weight of the owned node without its z factor (stopping-test scale)
+    const double wxy = g.Hx * g.Hy * g.Hz * ((ex + 1 == 0 || ex + 1 == g.nx - 1) ? 0.5 : 1.0) *
+                       ((ey + 1 == 0 || ey + 1 == g.ny - 1) ? 0.5 : 1.0);
 
     // Loads and stores address a wave-uniform base (sample, plane) plus a 32-bit
     // per-lane byte offset that stays fixed while the wave marches up in z.
@@ -365,7 +372,11 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
     // one slab: planes lo (k) and hi (k + 1), its coefficients and the node inputs of
     // plane k are resident (loaded PD steps earlier)
     R acc_top = 0;
-    auto step = [&](int k, const Pl& lo, const Pl& hi, R cp, R cq, R p0, R p1, R p2, R p3) {
+    // kResF: the mass term is applied per plane (its z part x_(k-1) + 4 x_k + x_(k+1) formed once per
+    // node and plane, then the element's x-y mass over it), not per slab; fm masks elements outside
+    // the grid in x-y
+    const R fm = elem_xy ? (R)A.cm * KM : (R)0;
+    auto step = [&](int k, const Pl& pv, const Pl& lo, const Pl& hi, R cp, R cq, R p0, R p1, R p2, R p3) {
       const bool slab = k >= 0 && k <= g.nz - 2;
       if constexpr (CF == 1 || CF == 2) {
         const float t2 = 2.0f * (float)cp;
@@ -388,7 +399,18 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
         R xin[8] = {lo.k[0], lo.k[1], lo.k[2], lo.k[3], hi.k[0], hi.k[1], hi.k[2], hi.k[3]};
         Elem<R>::stiff_f(xin, (CX0 + CX1 * cp) * (sc * KX), (CY0 + CY1 * cp) * (sc * KY), cq * (sc * KQ),
                          (CZ0 + CZ1 * cp) * (sc * KZ), o);
-        if constexpr (kMass) {
+        if constexpr (MODE == kResF) {
+          const R za = k > 0 ? (R)1 : (R)0, zc = k < g.nz - 1 ? (R)1 : (R)0, zb = (R)2 * (za + zc);
+          R T[4];
+#pragma unroll
+          for (int ab = 0; ab < 4; ++ab) T[ab] = za * pv.m[ab] + zb * lo.m[ab] + zc * hi.m[ab];
+          const R r0 = (R)2 * T[0] + T[1], r1 = T[0] + (R)2 * T[1];
+          const R r2 = (R)2 * T[2] + T[3], r3 = T[2] + (R)2 * T[3];
+          o[0] += fm * ((R)2 * r0 + r2);
+          o[1] += fm * ((R)2 * r1 + r3);
+          o[2] += fm * (r0 + (R)2 * r2);
+          o[3] += fm * (r1 + (R)2 * r3);
+        } else if constexpr (kMass) {
           R xm[8];
 #pragma unroll
           for (int c = 0; c < 8; ++c) {
@@ -441,7 +463,7 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
           const double F = (double)sres - fb;
           const uint32_t oi = (uint32_t)oof * (uint32_t)sizeof(TI) + kk * (uint32_t)plane * (uint32_t)sizeof(TI);
           put((TI*)A.r0 + sbase, oi, (TI)(-F));
-          put((TI*)A.dout + sbase, oi, (TI)(A.io.dt * diion3(uo, A.io)));
+          put((TI*)A.dout + sbase, oi, (TI)((dc2 * uo + dc1) * uo + ic1));
           if constexpr (kStart != 0) put(A.ucopy + sbase, obd + kk * pbD, uo);
           if (A.uprev != nullptr) {  // activation in the step from t_(k-1) to t_k
             const double um = (double)p2;
@@ -449,12 +471,11 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
             if (*ap < 0.0 && um < A.u_th && uko >= A.u_th)
               *ap = A.t_prev + A.dt_act * (A.u_th - um) / (uko - um);
           }
-          const int X = ex + 1, Y = ey + 1;
-          const double wl = g.Hx * g.Hy * g.Hz * ((X == 0 || X == g.nx - 1) ? 0.5 : 1.0) *
-                            ((Y == 0 || Y == g.ny - 1) ? 0.5 : 1.0) * ((k == 0 || k == g.nz - 1) ? 0.5 : 1.0);
+          const double wl = (k == 0 || k == g.nz - 1) ? 0.5 * wxy : wxy;
+          const double su = wl * uo, sk = wl * uko + fb;
           n0 += F * F;
-          n1 += (wl * uo) * (wl * uo);
-          n2 += (wl * uko + fb) * (wl * uko + fb);
+          n1 += su * su;
+          n2 += sk * sk;
         } else if constexpr (MODE == kRes) {
           const double G = (double)sres;
           const double bb = (double)p0;
@@ -504,7 +525,7 @@ __global__ __launch_bounds__(NT) void k_wave3(Args<R> A) {
         fetch_coef(k0 + t + PD, Cp[t + PD], Cq[t + PD]);
         fetch_pre(k0 + t + PD, Q0[t + PD], Q1[t + PD], Q2[t + PD], Q3[t + PD]);
       }
-      step(k0 + t, P[t], P[t + 1], Cp[t], Cq[t], Q0[t], Q1[t], Q2[t], Q3[t]);
+      step(k0 + t, P[t > 0 ? t - 1 : 0], P[t], P[t + 1], Cp[t], Cq[t], Q0[t], Q1[t], Q2[t], Q3[t]);
     }
     if constexpr (MODE == kPK && JB > 0) {
       // projections w . v_i (i < j) over the wave's owned nodes, into dacc[i + 1]: all
