@@ -591,7 +591,7 @@ __global__ void k_activation(const double* __restrict__ uk, const double* __rest
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
   const double a = uk[i], b = u[i];
-  if (act[i] < 0.0 && a < u_th && b >= u_th) act[i] = t_k + dt * (u_th - a) / (b - a);
+  if (a < u_th && b >= u_th && act[i] < 0.0) act[i] = t_k + dt * (u_th - a) / (b - a);
 }
 
 void launch_activation(const Work& w, int64_t nn, int32_t B, double u_th, double t_k, double dt, hipStream_t s) {

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(NT) void k_solve_small(SmallArgs a) {
         if (k > 0) {
           const double um = pkm1[i];
           if (a.extrap) s = 2.0 * u0 - um;
-          if (act[i] < 0.0 && um < io.u_th && u0 >= io.u_th)
+          if (um < io.u_th && u0 >= io.u_th && act[i] < 0.0)
             act[i] = (double)(k - 1) * dt + dt * (io.u_th - um) / (u0 - um);
         }
         pu[i] = s;
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(NT) void k_solve_small(SmallArgs a) {
     for (int64_t i = t; i < n; i += NT) {
       if (a.n_steps > 0 && status == MLQ_SAMPLE_OK) {
         const double um = pkm1[i], u0 = pk[i];
-        if (act[i] < 0.0 && um < io.u_th && u0 >= io.u_th)
+        if (um < io.u_th && u0 >= io.u_th && act[i] < 0.0)
           act[i] = (double)(a.n_steps - 1) * dt + dt * (io.u_th - um) / (u0 - um);
       }
       const double v = a.qoi == MLQ_QOI_MEAN_U_FINAL ? pk[i] : (act[i] < 0.0 ? t_stop : act[i]);

@@ -468,7 +468,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
           if (A.uprev != nullptr) {  // activation in the step from t_(k-1) to t_k
             const double um = (double)p2;
             double* ap = (double*)((char*)(A.act + sbase) + obd + kk * pbD);
-            if (*ap < 0.0 && um < A.u_th && uko >= A.u_th)
+            if (um < A.u_th && uko >= A.u_th && *ap < 0.0)  // read only where u crosses the threshold
               *ap = A.t_prev + A.dt_act * (A.u_th - um) / (uko - um);
           }
           const double wl = (k == 0 || k == g.nz - 1) ? 0.5 * wxy : wxy;
@@ -494,7 +494,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
             const double um = at(A.uprev + sbase, obd + kk * pbD);
             if (A.extrap) ustart = 2.0 * uk - um;
             double* ap = (double*)((char*)(A.act + sbase) + obd + kk * pbD);
-            if (*ap < 0.0 && um < A.u_th && uk >= A.u_th) *ap = A.t_prev + A.dt_act * (A.u_th - um) / (uk - um);
+            if (um < A.u_th && uk >= A.u_th && *ap < 0.0) *ap = A.t_prev + A.dt_act * (A.u_th - um) / (uk - um);
           }
           if (A.ucopy != nullptr) put(A.ucopy + sbase, obd + kk * pbD, ustart);
         }
