@@ -330,6 +330,10 @@ def compare_runs(cfg, a, b):
         out["estimate_diff_rel_to_T_minus_qoi"] = abs(est_a - est_b) / abs(T - est_b)
     lm = [abs(x - y) / abs(y) for x, y in zip(a["level_mean"], b["level_mean"]) if y != 0.0]
     out["level_mean_max_rel_diff"] = max(lm) if lm else 0.0
+    # the level means of the finer levels are differences F_l - F_(l-1), small against the estimate
+    la = [abs(x - y) for x, y in zip(a["level_mean"], b["level_mean"])]
+    out["level_mean_max_abs_diff"] = max(la) if la else 0.0
+    out["level_mean_max_diff_rel_to_estimate"] = (max(la) / abs(est_b)) if la and est_b != 0.0 else 0.0
     diffs, scale = [], []
     for fa, fb in [(a["f_fine"], b["f_fine"]), (a.get("f_coarse") or [], b.get("f_coarse") or [])]:
         for x, y in zip(fa, fb):
