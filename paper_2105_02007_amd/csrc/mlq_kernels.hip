@@ -1244,7 +1244,11 @@ void launch_apply_pk(const Geo& g, const Work& w, int j, double ck, int32_t B, b
 
 // Newton update, right preconditioning: u += P^-1 (sum_l y_l v_l).
 // Newton update with right preconditioning on boxes: u += sum_l y_l z_l over the
-// preconditioned basis (z_l = P^-1 v_l inv_eta_l, y_l from k_solve_y unscaled).
+// preconditioned basis (z_l = P^-1 v_l inv_eta_l, y_l from k_solve_y unscaled).  A thread takes
+// kUpdNodes nodes a block apart, side by side: the loads of four basis vectors at all of its
+// nodes (and the nodes' u) are in flight together; each node's sum runs in the order of l.
+constexpr int kUpdNodes = 4;
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_zbasis(int64_t nn, const T* __restrict__ Z, size_t vs,
                                                           const double* __restrict__ y, int kmax,
@@ -1256,24 +1260,38 @@ __global__ __launch_bounds__(kBlock) void k_update_zbasis(int64_t nn, const T* _
   const int k = inner_k[sb];
   for (int i = threadIdx.x; i < k; i += kBlock) c[i] = y[(int64_t)sb * kmax + i];
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nn) return;
-  const int64_t o = (int64_t)sb * nn + i;
-  // four basis vectors' loads in flight at a time; the sum in order of l
-  double acc = 0.0;
-  for (int l0 = 0; l0 < k; l0 += 4) {
-    T zv[4];
+  const int64_t i0 = (int64_t)blockIdx.x * (kBlock * kUpdNodes) + threadIdx.x;
+  const int64_t base = (int64_t)sb * nn;
+  double acc[kUpdNodes], uv[kUpdNodes];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) zv[r] = l0 + r < k ? Z[(l0 + r) * vs + o] : (T)0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (l0 + r < k) acc += c[l0 + r] * (double)zv[r];
+  for (int r = 0; r < kUpdNodes; ++r) {
+    const int64_t i = i0 + (int64_t)r * kBlock;
+    acc[r] = 0.0;
+    uv[r] = i < nn ? u[base + i] : 0.0;
   }
-  u[o] += acc;
+  for (int l0 = 0; l0 < k; l0 += 4) {
+    T zv[kUpdNodes][4];
+#pragma unroll
+    for (int r = 0; r < kUpdNodes; ++r) {
+      const int64_t i = i0 + (int64_t)r * kBlock;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) zv[r][q] = (l0 + q < k && i < nn) ? Z[(l0 + q) * vs + base + i] : (T)0;
+    }
+#pragma unroll
+    for (int r = 0; r < kUpdNodes; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (l0 + q < k) acc[r] += c[l0 + q] * (double)zv[r][q];
+  }
+#pragma unroll
+  for (int r = 0; r < kUpdNodes; ++r) {
+    const int64_t i = i0 + (int64_t)r * kBlock;
+    if (i < nn) u[base + i] = uv[r] + acc[r];
+  }
 }
 
 void launch_update_zbasis(const Geo& g, const Work& w, int32_t B, bool mixed, hipStream_t s) {
-  const dim3 grid((unsigned)w.nblk, B);
+  const dim3 grid((unsigned)cdiv(g.nn, (int64_t)kBlock * kUpdNodes), B);
   const size_t vs = (size_t)g.nn * B;
   if (mixed)
     hipLaunchKernelGGL((k_update_zbasis<float>), grid, dim3(kBlock), 0, s, g.nn, (const float*)w.z, vs, w.y, w.kmax,
