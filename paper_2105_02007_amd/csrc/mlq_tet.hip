@@ -256,6 +256,10 @@ __global__ __launch_bounds__(kBlock) void k_tet_rhs(TetDev t, const TI* __restri
 // GMRES preconditioner step (Jacobi on the whole Jacobian): z_j = v_j inv_eta_j / J_ii with
 // J_ii = m_ii (1 + d_i) + ck k_ii, into the preconditioned basis.  The stiffness diagonal
 // matters where the mesh is fine (near the apex dt sigma / h^2 is of order one there).
+// z_j = v_j / diag(J) per vertex-sample; a thread takes kJacRows rows a block apart, side by
+// side, with the loads of all of them in flight together.
+constexpr int kJacRows = 4;
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tet_jacobi(TetDev t, const T* __restrict__ v, const T* __restrict__ d,
                                                        const T* __restrict__ kval, T ck, T* __restrict__ z,
@@ -263,14 +267,26 @@ __global__ __launch_bounds__(kBlock) void k_tet_jacobi(TetDev t, const T* __rest
                                                        const int32_t* __restrict__ active) {
   const int sb = blockIdx.y;
   if (active[sb] == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= t.nv) return;
   const T* md = nullptr;
   if constexpr (sizeof(T) == 4) md = (const T*)t.mdiag32; else md = (const T*)t.mdiag;
-  const int64_t o = (int64_t)sb * t.nv + i;
-  const T kii = kval[(int64_t)sb * t.nell + (int64_t)t.ediag[i] * t.nv + i];
   const T s = (T)inv_eta[(int64_t)sb * (kmax + 1) + j];
-  z[o] = v[o] * s / (md[i] * ((T)1 + d[o]) + ck * kii);
+  const int64_t i0 = (int64_t)blockIdx.x * (kBlock * kJacRows) + threadIdx.x;
+  const int64_t base = (int64_t)sb * t.nv;
+  const T* ks = kval + (int64_t)sb * t.nell;
+  T vv[kJacRows], dv[kJacRows], kv[kJacRows], mv[kJacRows];
+#pragma unroll
+  for (int r = 0; r < kJacRows; ++r) {
+    const int64_t i = min(i0 + (int64_t)r * kBlock, t.nv - 1);  // clamped: rows past the end are not stored
+    vv[r] = v[base + i];
+    dv[r] = d[base + i];
+    kv[r] = ks[(int64_t)t.ediag[i] * t.nv + i];
+    mv[r] = md[i];
+  }
+#pragma unroll
+  for (int r = 0; r < kJacRows; ++r) {
+    const int64_t i = i0 + (int64_t)r * kBlock;
+    if (i < t.nv) z[base + i] = vv[r] * s / (mv[r] * ((T)1 + dv[r]) + ck * kv[r]);
+  }
 }
 
 }  // namespace
@@ -320,7 +336,7 @@ void launch_tet_rhs(const TetDev& t, const Work& w, const double* fload, double 
 
 void launch_tet_jacobi_basis(const TetDev& t, const Work& w, int j, double ck, int32_t B, bool mixed,
                              hipStream_t s) {
-  const dim3 grid((unsigned)cdiv(t.nv, kBlock), B);
+  const dim3 grid((unsigned)cdiv(t.nv, (int64_t)kBlock * kJacRows), B);
   const size_t vs = (size_t)t.nv * B;
   if (mixed)
     hipLaunchKernelGGL((k_tet_jacobi<float>), grid, dim3(kBlock), 0, s, t, (const float*)w.V + j * vs,
