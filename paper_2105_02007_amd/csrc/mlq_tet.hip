@@ -158,60 +158,97 @@ __global__ __launch_bounds__(kBlock) void k_tet_apply(TetDev t, const T* __restr
     if (on[q]) y[(int64_t)(sb0 + q) * t.nv + i] = acc[q];
 }
 
-// F = M (u + dt I_ion(u)) + dt/2 K u - b (FP64), r0 = -F, d = dt I_ion'(u), partial norms
+// F = M (u + dt I_ion(u)) + dt/2 K u - b (FP64), r0 = -F, d = dt I_ion'(u), partial norms.  A
+// thread takes one row of kTetSamples samples, as the apply does: the column and the mass value
+// of a slot are loaded once for the group, and the gathers of all samples are in flight together
+// (samples past the batch or not active read another sample's values, which are discarded).  Per
+// sample the sums run in the same order as one sample per thread would.
 template <typename TI>
 __global__ __launch_bounds__(kBlock) void k_tet_residual(TetDev t, Ionic io, const TI* __restrict__ kval,
                                                          const double* __restrict__ u, const double* __restrict__ bv,
                                                          TI* __restrict__ r0, TI* __restrict__ dout,
                                                          double* __restrict__ part,
-                                                         const int32_t* __restrict__ active) {
+                                                         const int32_t* __restrict__ active, int32_t B) {
+  constexpr int S = kTetSamples;
   int64_t bx, by;
   xcd_block(bx, by);
-  const int sb = (int)by;
-  if (active[sb] == 0) return;
+  const int sb0 = (int)by * S;
+  bool on[S];
+  int sq[S];
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    on[q] = sb0 + q < B && active[sb0 + q] != 0;
+    sq[q] = min(sb0 + q, B - 1);
+    any = any || on[q];
+  }
+  if (!any) return;
   const int64_t i = bx * kBlock + threadIdx.x;
-  double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+  double n0[S], n1[S], n2[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) n0[q] = n1[q] = n2[q] = 0.0;
   if (i < t.nv) {
-    const int64_t so = (int64_t)sb * t.nv;
-    const TI* kv = kval + (int64_t)sb * t.nell;
     const double ck = 0.5 * io.dt;
-    double G = 0.0;
-#pragma unroll 4
+    double G[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) G[q] = 0.0;
+#pragma unroll 2
     for (int32_t sl = 0; sl < t.width; ++sl) {
       const int64_t e = (int64_t)sl * t.nv + i;
-      const double uj = u[so + t.ecol[e]];
-      G += t.em[e] * (uj + io.dt * tet_iion(uj, io)) + ck * (double)kv[e] * uj;
+      const int64_t c = t.ecol[e];
+      const double m = t.em[e];
+      double uj[S];
+      TI kv[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        uj[q] = u[(int64_t)sq[q] * t.nv + c];
+        kv[q] = kval[(int64_t)sq[q] * t.nell + e];
+      }
+#pragma unroll
+      for (int q = 0; q < S; ++q) G[q] += m * (uj[q] + io.dt * tet_iion(uj[q], io)) + ck * (double)kv[q] * uj[q];
     }
-    const double b = bv[so + i];
-    const double F = G - b;
-    r0[so + i] = (TI)(-F);
-    dout[so + i] = (TI)(io.dt * tet_diion(u[so + i], io));
-    n0 = F * F;
-    n1 = G * G;
-    n2 = b * b;
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      if (!on[q]) continue;
+      const int64_t so = (int64_t)(sb0 + q) * t.nv;
+      const double b = bv[so + i];
+      const double F = G[q] - b;
+      r0[so + i] = (TI)(-F);
+      dout[so + i] = (TI)(io.dt * tet_diion(u[so + i], io));
+      n0[q] = F * F;
+      n1[q] = G[q] * G[q];
+      n2[q] = b * b;
+    }
   }
-  __shared__ double red[kBlock / 64][3];
-  double v[3] = {n0, n1, n2};
+  __shared__ double red[kBlock / 64][S][3];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int r = 0; r < 3; ++r) {
+  for (int q = 0; q < S; ++q) {
+    double v[3] = {n0[q], n1[q], n2[q]};
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[r] += __shfl_xor(v[r], off, 64);
-  }
-  if (lane == 0) {
-    red[wid][0] = v[0];
-    red[wid][1] = v[1];
-    red[wid][2] = v[2];
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v[r] += __shfl_xor(v[r], off, 64);
+    }
+    if (lane == 0) {
+      red[wid][q][0] = v[0];
+      red[wid][q][1] = v[1];
+      red[wid][q][2] = v[2];
+    }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  bool onq = false;  // on[threadIdx.x] without a runtime index into a register array
+#pragma unroll
+  for (int q = 0; q < S; ++q) onq = onq || ((int)threadIdx.x == q && on[q]);
+  if (onq) {
+    const int q = threadIdx.x;
     double s0 = 0, s1 = 0, s2 = 0;
-    for (int q = 0; q < kBlock / 64; ++q) {
-      s0 += red[q][0];
-      s1 += red[q][1];
-      s2 += red[q][2];
+    for (int w = 0; w < kBlock / 64; ++w) {
+      s0 += red[w][q][0];
+      s1 += red[w][q][1];
+      s2 += red[w][q][2];
     }
-    double* p = part + ((int64_t)sb * gridDim.x + bx) * 3;
+    double* p = part + ((int64_t)(sb0 + q) * gridDim.x + bx) * 3;
     p[0] = s0;
     p[1] = s1;
     p[2] = s2;
@@ -227,37 +264,56 @@ __global__ __launch_bounds__(kBlock) void k_tet_rhs(TetDev t, const TI* __restri
                                                     double load, double ck, double* __restrict__ bout,
                                                     double* __restrict__ ucopy, const double* __restrict__ uprev,
                                                     double* __restrict__ act, double u_th, double t_prev, double dt,
-                                                    int extrap) {
+                                                    int extrap, int32_t B) {
+  constexpr int S = kTetSamples;  // one row of kTetSamples samples per thread, as in the apply
   int64_t bx, by;
   xcd_block(bx, by);
-  const int sb = (int)by;
+  const int sb0 = (int)by * S;
   const int64_t i = bx * kBlock + threadIdx.x;
   if (i >= t.nv) return;
-  const int64_t so = (int64_t)sb * t.nv;
-  const TI* kv = kval + (int64_t)sb * t.nell;
-  double acc = 0.0;
-#pragma unroll 4
+  int sq[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) sq[q] = min(sb0 + q, B - 1);  // past the batch: read, not stored
+  double acc[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) acc[q] = 0.0;
+#pragma unroll 2
   for (int32_t sl = 0; sl < t.width; ++sl) {
     const int64_t e = (int64_t)sl * t.nv + i;
-    const double uj = uk[so + t.ecol[e]];
-    acc += (t.em[e] - ck * (double)kv[e]) * uj;
+    const int64_t c = t.ecol[e];
+    const double m = t.em[e];
+    double uj[S];
+    TI kv[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      uj[q] = uk[(int64_t)sq[q] * t.nv + c];
+      kv[q] = kval[(int64_t)sq[q] * t.nell + e];
+    }
+#pragma unroll
+    for (int q = 0; q < S; ++q) acc[q] += (m - ck * (double)kv[q]) * uj[q];
   }
-  bout[so + i] = acc + load * fload[i];
-  const double u0 = uk[so + i];
-  double ustart = u0;
-  if (uprev != nullptr) {
-    const double um = uprev[so + i];
-    if (extrap) ustart = 2.0 * u0 - um;
-    if (act[so + i] < 0.0 && um < u_th && u0 >= u_th) act[so + i] = t_prev + dt * (u_th - um) / (u0 - um);
+  const double fl = load * fload[i];
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    if (sb0 + q >= B) break;
+    const int64_t so = (int64_t)(sb0 + q) * t.nv;
+    bout[so + i] = acc[q] + fl;
+    const double u0 = uk[so + i];
+    double ustart = u0;
+    if (uprev != nullptr) {
+      const double um = uprev[so + i];
+      if (extrap) ustart = 2.0 * u0 - um;
+      // the activation time is read only where u crosses the threshold
+      if (um < u_th && u0 >= u_th && act[so + i] < 0.0) act[so + i] = t_prev + dt * (u_th - um) / (u0 - um);
+    }
+    ucopy[so + i] = ustart;
   }
-  ucopy[so + i] = ustart;
 }
 
 // GMRES preconditioner step (Jacobi on the whole Jacobian): z_j = v_j inv_eta_j / J_ii with
 // J_ii = m_ii (1 + d_i) + ck k_ii, into the preconditioned basis.  The stiffness diagonal
-// matters where the mesh is fine (near the apex dt sigma / h^2 is of order one there).
-// z_j = v_j / diag(J) per vertex-sample; a thread takes kJacRows rows a block apart, side by
-// side, with the loads of all of them in flight together.
+// matters where the mesh is fine (near the apex dt sigma / h^2 is of order one there).  A thread
+// takes kJacRows rows a block apart, side by side, with the loads of all of them in flight.
 constexpr int kJacRows = 4;
 
 template <typename T>
@@ -314,24 +370,25 @@ void launch_tet_apply(const TetDev& t, const void* kval, const void* x, const vo
 }
 
 void launch_tet_residual(const TetDev& t, const Ionic& io, const Work& w, int32_t B, bool mixed, hipStream_t s) {
-  const dim3 grid((unsigned)cdiv(t.nv, kBlock), B);  // = w.nres blocks per sample
+  // gridDim.x = w.nres blocks per sample; kTetSamples samples per block row
+  const dim3 grid((unsigned)cdiv(t.nv, kBlock), (unsigned)cdiv(B, kTetSamples));
   if (mixed)
     hipLaunchKernelGGL((k_tet_residual<float>), grid, dim3(kBlock), 0, s, t, io, (const float*)w.coef, w.u, w.b,
-                       (float*)w.V, (float*)w.d, w.part, w.newton_active);
+                       (float*)w.V, (float*)w.d, w.part, w.newton_active, B);
   else
     hipLaunchKernelGGL((k_tet_residual<double>), grid, dim3(kBlock), 0, s, t, io, (const double*)w.coef, w.u, w.b,
-                       (double*)w.V, (double*)w.d, w.part, w.newton_active);
+                       (double*)w.V, (double*)w.d, w.part, w.newton_active, B);
 }
 
 void launch_tet_rhs(const TetDev& t, const Work& w, const double* fload, double load, double dt, int32_t B,
                     bool mixed, hipStream_t s, const double* uprev, bool extrap, double u_th, double t_prev) {
-  const dim3 grid((unsigned)cdiv(t.nv, kBlock), B);
+  const dim3 grid((unsigned)cdiv(t.nv, kBlock), (unsigned)cdiv(B, kTetSamples));
   if (mixed)
     hipLaunchKernelGGL((k_tet_rhs<float>), grid, dim3(kBlock), 0, s, t, (const float*)w.coef, w.uk, fload, load,
-                       0.5 * dt, w.b, w.u, uprev, w.act, u_th, t_prev, dt, extrap ? 1 : 0);
+                       0.5 * dt, w.b, w.u, uprev, w.act, u_th, t_prev, dt, extrap ? 1 : 0, B);
   else
     hipLaunchKernelGGL((k_tet_rhs<double>), grid, dim3(kBlock), 0, s, t, (const double*)w.coef, w.uk, fload, load,
-                       0.5 * dt, w.b, w.u, uprev, w.act, u_th, t_prev, dt, extrap ? 1 : 0);
+                       0.5 * dt, w.b, w.u, uprev, w.act, u_th, t_prev, dt, extrap ? 1 : 0, B);
 }
 
 void launch_tet_jacobi_basis(const TetDev& t, const Work& w, int j, double ck, int32_t B, bool mixed,
