@@ -90,8 +90,10 @@ def _tet_solve_pair(env, cells, steps, B, prec, stop=None):
     return out, refs
 
 
-def test_tet_solve_fp64_matches_oracle(env):
-    out, refs = _tet_solve_pair(env, (2, 6, 12), 32, 3, W.PREC_FP64)
+# B = 3: one partial group of the four-sample kernels; B = 6: a full group and a partial one
+@pytest.mark.parametrize("B", [3, 6])
+def test_tet_solve_fp64_matches_oracle(env, B):
+    out, refs = _tet_solve_pair(env, (2, 6, 12), 32, B, W.PREC_FP64)
     assert int(out["status"].abs().sum()) == 0
     q = out["qoi"].cpu().numpy()
     u = out["u"].cpu().numpy()
