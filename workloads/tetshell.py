@@ -75,12 +75,15 @@ def shell_mesh(cells, seed, jitter=JITTER):
     M = M + np.where(interior, off[..., 0] * (mu[1] - mu[0]), 0.0)
     N = N + np.where(interior, off[..., 1] * (nu[1] - nu[0]), 0.0)
     F = F + np.where(interior, off[..., 2] * (2.0 * np.pi / n_phi), 0.0)
-    xyz = spheroidal_to_xyz(M, N, F).reshape(-1, 3)
+    # vertices numbered longitudinal index slowest, then transmural, circumferential fastest: the
+    # rows of a wave are consecutive around a ring (their slot gathers coalesce), and a row's
+    # transmural neighbours are one ring (n_phi rows) away, its longitudinal ones one ring of rings
+    xyz = np.transpose(spheroidal_to_xyz(M, N, F), (1, 0, 2, 3)).reshape(-1, 3)
 
     def vid(i, j, k):
-        return (i * (n_nu + 1) + j) * n_phi + (k % n_phi)
+        return (j * (n_mu + 1) + i) * n_phi + (k % n_phi)
 
-    I, J, K = np.meshgrid(np.arange(n_mu), np.arange(n_nu), np.arange(n_phi), indexing="ij")
+    J, I, K = np.meshgrid(np.arange(n_nu), np.arange(n_mu), np.arange(n_phi), indexing="ij")
     I, J, K = I.ravel(), J.ravel(), K.ravel()
     tets = np.concatenate([np.stack([vid(I + a[0], J + a[1], K + a[2]) for a in t], axis=1) for t in _KUHN])
     # positive orientation
